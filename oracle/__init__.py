@@ -1,0 +1,565 @@
+"""Oracle: plain float64 CPU implementation of entropic-OT domain decomposition
+with flow updates (Medina & Schmitzer, "Flow updates for domain decomposition of
+entropic optimal transport").  TEST INFRASTRUCTURE ONLY: tests, the smoke check
+and the benchmark's CPU-baseline leg may use it; the GPU product path never does.
+
+It follows the paper's algorithms step by step in their notation:
+  * cell problem and Sinkhorn: Sec. 2.2 eq. (entropic-transport), Prop. "Optimal
+    entropic transport couplings", Sec. 2.3 Alg. "DomDecIter" (reference measure
+    mu_J (x) nu), dense non-separable log-domain Sinkhorn in oracle.c;
+  * basic-cell Y-marginals as the state: Sec. 2.3 eq. (basic-cell-Y-marginal);
+  * partitions: Def. "Basic and composite partitions", App. A.2.1 (2x2 groups of
+    s x s basic cells, B staggered by one basic cell; B boundary cells truncated);
+  * balancing and truncation: App. A Alg. "DomDecIterGPU" (Balance, Truncate),
+    truncation threshold 1e-15 (App. A.2.1);
+  * flow update with product gluing candidates: Sec. 3.2 Def. "Flow update",
+    eq. (edge-cost), eq. (flow-update-cell-marginals), Remark "eps-gamma";
+    min-cost flow (MinCostFlow) by successive shortest paths in oracle.c;
+  * evaluation: E, D and the primal-dual gap of App. A.2.2 "Solution quality".
+
+Sparse storage: each basic-cell Y-marginal nu_i is a sorted index array plus a
+value array on the flattened N*N Y grid.  Readings of points where the paper is
+silent are listed in the project's design notes and restated at each function.
+
+Pinned by tests/test_oracle_*.py against closed forms, invariants and brute force.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+from dataclasses import dataclass
+from typing import Dict, List, Optional, Tuple
+
+import numpy as np
+
+from . import build as _build
+
+_LIB = None
+
+
+def lib():
+    global _LIB
+    if _LIB is None:
+        path = _build.ensure_built()
+        L = ctypes.CDLL(path)
+        d = ctypes.POINTER(ctypes.c_double)
+        i64 = ctypes.POINTER(ctypes.c_int64)
+        i32 = ctypes.POINTER(ctypes.c_int32)
+        ip = ctypes.POINTER(ctypes.c_int)
+        L.orc_sinkhorn_cells.restype = ctypes.c_int
+        L.orc_sinkhorn_cells.argtypes = [ctypes.c_int, i64, d, d, i64, d, d, d, ctypes.c_double,
+                                         ctypes.c_double, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                         d, d, ip, d, ctypes.c_int]
+        L.orc_cell_plan.restype = None
+        L.orc_cell_plan.argtypes = [ctypes.c_int, d, d, d, ctypes.c_int, d, d, d, ctypes.c_double, d]
+        L.orc_mcf_ssp.restype = ctypes.c_int
+        L.orc_mcf_ssp.argtypes = [ctypes.c_int, ctypes.c_int, i32, i32, i64, i64, i64, i64, i64]
+        _LIB = L
+    return _LIB
+
+
+def _p(a, ct):
+    return a.ctypes.data_as(ctypes.POINTER(ct))
+
+
+# ---------------------------------------------------------------------------
+# C entry points
+# ---------------------------------------------------------------------------
+
+def sinkhorn_cells(xoff, xc, mu, yoff, yc, nuJ, nuref, eps, tol=1e-5, max_iter=10000,
+                   fixed_iters=0, rule=0, alpha=None, nthreads=0):
+    """Batch cell Sinkhorn (see oracle.c).  Returns (alpha, beta, iters, err, n_iter)."""
+    xoff = np.ascontiguousarray(xoff, dtype=np.int64)
+    yoff = np.ascontiguousarray(yoff, dtype=np.int64)
+    xc = np.ascontiguousarray(xc, dtype=np.float64)
+    yc = np.ascontiguousarray(yc, dtype=np.float64)
+    mu = np.ascontiguousarray(mu, dtype=np.float64)
+    nuJ = np.ascontiguousarray(nuJ, dtype=np.float64)
+    nuref = np.ascontiguousarray(nuref, dtype=np.float64)
+    nc = len(xoff) - 1
+    a = np.zeros(int(xoff[-1]), dtype=np.float64) if alpha is None else np.array(alpha, dtype=np.float64)
+    b = np.zeros(int(yoff[-1]), dtype=np.float64)
+    iters = np.zeros(nc, dtype=np.int32)
+    err = np.zeros(nc, dtype=np.float64)
+    n = lib().orc_sinkhorn_cells(nc, _p(xoff, ctypes.c_int64), _p(xc, ctypes.c_double),
+                                 _p(mu, ctypes.c_double), _p(yoff, ctypes.c_int64),
+                                 _p(yc, ctypes.c_double), _p(nuJ, ctypes.c_double),
+                                 _p(nuref, ctypes.c_double), float(eps), float(tol), int(max_iter),
+                                 int(fixed_iters), int(rule), _p(a, ctypes.c_double),
+                                 _p(b, ctypes.c_double), _p(iters, ctypes.c_int),
+                                 _p(err, ctypes.c_double), int(nthreads))
+    return a, b, iters, err, n
+
+
+def cell_plan(xc, mu, alpha, yc, nuref, beta, eps):
+    """Dense pi(x,y) = exp((alpha+beta-c)/eps) mu nu for one cell (nx x ny)."""
+    xc = np.ascontiguousarray(xc, dtype=np.float64)
+    yc = np.ascontiguousarray(yc, dtype=np.float64)
+    mu = np.ascontiguousarray(mu, dtype=np.float64)
+    nuref = np.ascontiguousarray(nuref, dtype=np.float64)
+    alpha = np.ascontiguousarray(alpha, dtype=np.float64)
+    beta = np.ascontiguousarray(beta, dtype=np.float64)
+    nx, ny = len(mu), len(nuref)
+    out = np.empty((nx, ny), dtype=np.float64)
+    lib().orc_cell_plan(nx, _p(xc, ctypes.c_double), _p(mu, ctypes.c_double),
+                        _p(alpha, ctypes.c_double), ny, _p(yc, ctypes.c_double),
+                        _p(nuref, ctypes.c_double), _p(beta, ctypes.c_double), float(eps),
+                        _p(out, ctypes.c_double))
+    return out
+
+
+def mcf_ssp(n, tail, head, cost, sup, dem):
+    """Integer bipartite min-cost flow (see oracle.c).  Returns (flow, potentials, status)."""
+    tail = np.ascontiguousarray(tail, dtype=np.int32)
+    head = np.ascontiguousarray(head, dtype=np.int32)
+    cost = np.ascontiguousarray(cost, dtype=np.int64)
+    sup = np.ascontiguousarray(sup, dtype=np.int64)
+    dem = np.ascontiguousarray(dem, dtype=np.int64)
+    m = len(tail)
+    flow = np.zeros(m, dtype=np.int64)
+    pot = np.zeros(2 * n, dtype=np.int64)
+    st = lib().orc_mcf_ssp(int(n), int(m), _p(tail, ctypes.c_int32), _p(head, ctypes.c_int32),
+                           _p(cost, ctypes.c_int64), _p(sup, ctypes.c_int64), _p(dem, ctypes.c_int64),
+                           _p(flow, ctypes.c_int64), _p(pot, ctypes.c_int64))
+    return flow, pot, st
+
+
+# ---------------------------------------------------------------------------
+# Grid, partitions
+# ---------------------------------------------------------------------------
+
+def pixel_coords(N: int) -> np.ndarray:
+    """(N*N, 2) pixel-centre coordinates ((k1+1/2)/N, (k2+1/2)/N), row-major."""
+    t = (np.arange(N, dtype=np.float64) + 0.5) / N
+    X1, X2 = np.meshgrid(t, t, indexing="ij")
+    return np.stack([X1.reshape(-1), X2.reshape(-1)], axis=1)
+
+
+def basic_cell_pixels(N: int, s: int) -> List[np.ndarray]:
+    """Pixels of basic cell i = r*n + c (n = N/s): the s x s block at rows r*s.., cols c*s.."""
+    n = N // s
+    out = []
+    for r in range(n):
+        for c in range(n):
+            k1 = np.arange(r * s, (r + 1) * s)
+            k2 = np.arange(c * s, (c + 1) * s)
+            out.append((k1[:, None] * N + k2[None, :]).reshape(-1).astype(np.int64))
+    return out
+
+
+def composite_partition(n: int, which: str) -> List[List[int]]:
+    """Composite cells as ascending lists of basic-cell ids.
+
+    A: 2x2 groups starting at the origin.  B: 2x2 groups shifted by one basic
+    cell in both axes, cells at the boundary keep only their in-range members.
+    """
+    cells = []
+    if which == "A":
+        for R in range(n // 2):
+            for C in range(n // 2):
+                cells.append([(2 * R + dr) * n + (2 * C + dc) for dr in (0, 1) for dc in (0, 1)])
+    elif which == "B":
+        for R in range(n // 2 + 1):
+            for C in range(n // 2 + 1):
+                ids = []
+                for dr in (0, 1):
+                    for dc in (0, 1):
+                        r, c = 2 * R - 1 + dr, 2 * C - 1 + dc
+                        if 0 <= r < n and 0 <= c < n:
+                            ids.append(r * n + c)
+                cells.append(ids)
+    else:
+        raise ValueError(which)
+    return cells
+
+
+def neighbourhood(n: int) -> Tuple[np.ndarray, np.ndarray]:
+    """4-neighbourhood plus self loops on the n x n basic-cell grid (Def. neighbourhood set).
+
+    Arcs are listed per tail node in ascending head order: (r-1,c), (r,c-1), (r,c), (r,c+1), (r+1,c).
+    """
+    tails, heads = [], []
+    for r in range(n):
+        for c in range(n):
+            i = r * n + c
+            for dr, dc in ((-1, 0), (0, -1), (0, 0), (0, 1), (1, 0)):
+                rr, cc = r + dr, c + dc
+                if 0 <= rr < n and 0 <= cc < n:
+                    tails.append(i)
+                    heads.append(rr * n + cc)
+    return np.array(tails, dtype=np.int32), np.array(heads, dtype=np.int32)
+
+
+# ---------------------------------------------------------------------------
+# Sparse helpers
+# ---------------------------------------------------------------------------
+
+def sparse_sum(parts: List[Tuple[np.ndarray, np.ndarray]]) -> Tuple[np.ndarray, np.ndarray]:
+    """Sum of sparse vectors (idx, val) -> sorted union support."""
+    if not parts:
+        return np.zeros(0, np.int64), np.zeros(0)
+    idx = np.concatenate([p[0] for p in parts])
+    val = np.concatenate([p[1] for p in parts])
+    u, inv = np.unique(idx, return_inverse=True)
+    out = np.zeros(len(u))
+    np.add.at(out, inv, val)
+    return u, out
+
+
+def largest_remainder(m: np.ndarray, total: int) -> np.ndarray:
+    """Integers b_i >= 0 with sum b_i == total, b_i = floor(total * m_i / sum m) + 1 for the
+    largest remainders (ties by index)."""
+    q = m / m.sum() * total
+    b = np.floor(q).astype(np.int64)
+    rem = int(total - b.sum())
+    if rem > 0:
+        frac = q - b
+        order = np.lexsort((np.arange(len(m)), -frac))
+        b[order[:rem]] += 1
+    return b
+
+
+# ---------------------------------------------------------------------------
+# Domain decomposition state
+# ---------------------------------------------------------------------------
+
+@dataclass
+class CellSolve:
+    """What one DD iteration keeps of a composite cell: geometry and potentials."""
+    basic: List[int]
+    xpix: np.ndarray  # X pixels (flat), basic cells concatenated in `basic` order
+    xcount: List[int]  # pixels per basic cell
+    ysup: np.ndarray  # support of nu_J (flat Y pixels)
+    nuJ: np.ndarray
+    alpha: np.ndarray
+    beta: np.ndarray
+
+
+class DomDec:
+    """Oracle domain-decomposition state: basic-cell Y-marginals nu_i (sparse, float64).
+
+    mu, nu: (N, N) float64 probability arrays; s: basic cell size; init: None for
+    the product coupling nu_i = m_i nu, else a sparse (x, y, mass) list.
+    """
+
+    TRUNC = 1e-15
+
+    def __init__(self, mu: np.ndarray, nu: np.ndarray, s: int, init=None, trunc: float = 1e-15):
+        N = mu.shape[0]
+        assert mu.shape == (N, N) and nu.shape == (N, N) and N % (2 * s) == 0
+        self.N, self.s, self.n = N, s, N // s
+        self.h = 1.0 / N
+        self.mu = mu.reshape(-1).astype(np.float64)
+        self.nu = nu.reshape(-1).astype(np.float64)
+        self.coords = pixel_coords(N)
+        self.cells = basic_cell_pixels(N, s)
+        self.m = np.array([self.mu[p].sum() for p in self.cells])
+        if np.any(self.m <= 0):
+            raise ValueError("every basic cell needs positive mass")
+        self.trunc = trunc
+        self.nu_i: List[Tuple[np.ndarray, np.ndarray]] = []
+        if init is None:
+            sup = np.nonzero(self.nu > 0)[0].astype(np.int64)
+            for mi in self.m:
+                self.nu_i.append((sup.copy(), mi * self.nu[sup]))
+        else:
+            x, y, w = init
+            cell_of_pix = np.empty(N * N, dtype=np.int64)
+            for i, p in enumerate(self.cells):
+                cell_of_pix[p] = i
+            ci = cell_of_pix[np.asarray(x)]
+            key = ci * (N * N) + np.asarray(y, dtype=np.int64)
+            u, inv = np.unique(key, return_inverse=True)
+            acc = np.zeros(len(u))
+            np.add.at(acc, inv, np.asarray(w, dtype=np.float64))
+            cid = u // (N * N)
+            yy = u % (N * N)
+            starts = np.searchsorted(cid, np.arange(len(self.cells) + 1))
+            for i in range(len(self.cells)):
+                self.nu_i.append((yy[starts[i]:starts[i + 1]].copy(), acc[starts[i]:starts[i + 1]].copy()))
+        self.parts = {w: composite_partition(self.n, w) for w in ("A", "B")}
+        self.alpha: Dict[str, List[Optional[np.ndarray]]] = {
+            w: [None] * len(self.parts[w]) for w in ("A", "B")}
+        self.last: Dict[str, List[CellSolve]] = {}
+        self.last_eps: Dict[str, float] = {}
+        self.last_which: Optional[str] = None
+
+    # -- DomDecIter -----------------------------------------------------------
+    def iterate(self, which: str, eps: float, tol: float = 1e-5, max_iter: int = 10000,
+                fixed_iters: int = 0, rule: int = 0, nthreads: int = 0, balance: bool = True,
+                truncate: bool = True) -> dict:
+        """One DomDecIter on partition `which` (Alg. "DomDecIter"; App. A Alg. "DomDecIterGPU").
+
+        For each composite cell J: mu_J = mu on X_J, nu_J = sum of its basic nu_i,
+        solve the cell problem by Sinkhorn (warm start: the alpha of the previous
+        visit of this partition, zero on the first visit), set nu_i(y) =
+        sum_{x in X_i} pi_J(x, y), then balance the basic masses inside J and
+        truncate entries below 1e-15.
+        """
+        parts = self.parts[which]
+        xoffs, yoffs = [0], [0]
+        xcs, mus, ycs, nuJs, nurefs, als, geo = [], [], [], [], [], [], []
+        for J, basic in enumerate(parts):
+            xpix = np.concatenate([self.cells[i] for i in basic])
+            ysup, nuJ = sparse_sum([self.nu_i[i] for i in basic])
+            keep = nuJ > 0
+            ysup, nuJ = ysup[keep], nuJ[keep]
+            a0 = self.alpha[which][J]
+            if a0 is None:
+                a0 = np.zeros(len(xpix))
+            xcs.append(self.coords[xpix])
+            mus.append(self.mu[xpix])
+            ycs.append(self.coords[ysup])
+            nuJs.append(nuJ)
+            nurefs.append(self.nu[ysup])
+            als.append(a0)
+            xoffs.append(xoffs[-1] + len(xpix))
+            yoffs.append(yoffs[-1] + len(ysup))
+            geo.append((basic, xpix, [len(self.cells[i]) for i in basic], ysup, nuJ))
+        a, b, iters, err, nit = sinkhorn_cells(
+            np.array(xoffs), np.concatenate(xcs), np.concatenate(mus), np.array(yoffs),
+            np.concatenate(ycs), np.concatenate(nuJs), np.concatenate(nurefs), eps, tol, max_iter,
+            fixed_iters, rule, np.concatenate(als), nthreads)
+        solves = []
+        for J, (basic, xpix, xcount, ysup, nuJ) in enumerate(geo):
+            aJ = a[xoffs[J]:xoffs[J + 1]].copy()
+            bJ = b[yoffs[J]:yoffs[J + 1]].copy()
+            self.alpha[which][J] = aJ
+            solves.append(CellSolve(basic, xpix, xcount, ysup, nuJ, aJ, bJ))
+            plan = cell_plan(self.coords[xpix], self.mu[xpix], aJ, self.coords[ysup], self.nu[ysup],
+                             bJ, eps)
+            row = 0
+            new = []
+            for k, i in enumerate(basic):
+                new.append(plan[row:row + xcount[k]].sum(axis=0))
+                row += xcount[k]
+            if balance:
+                self._balance(basic, new)
+            for k, i in enumerate(basic):
+                v = new[k]
+                if truncate:
+                    keep = v >= self.trunc
+                    self.nu_i[i] = (ysup[keep].copy(), v[keep].copy())
+                else:
+                    self.nu_i[i] = (ysup.copy(), v.copy())
+        self.last[which] = solves
+        self.last_eps[which] = eps
+        self.last_which = which
+        return {"iters": iters, "err": err, "n_iter": nit,
+                "err_total": float(err.sum()), "mass": float(np.concatenate(mus).sum())}
+
+    def _balance(self, basic: List[int], new: List[np.ndarray]) -> None:
+        """Restore sum_y nu_i = m_i inside one composite cell, keeping sum_i nu_i fixed.
+
+        Reading (the balancing routine is deferred to another paper): basic cells with
+        excess e_i = sum nu_i - m_i > 0 and with deficit e_k < 0 are paired in
+        ascending order; t = min(e_i, -e_k) moves from i to k pointwise in proportion
+        to nu_i: moved = (t / M_i) nu_i, nu_k += moved, nu_i -= moved.  Each step zeroes
+        one excess or deficit, so at most |J|-1 transfers occur; entries stay >= 0.
+        """
+        M = [float(v.sum()) for v in new]
+        e = [M[k] - self.m[i] for k, i in enumerate(basic)]
+        while True:
+            src = next((k for k in range(len(basic)) if e[k] > 0), None)
+            dst = next((k for k in range(len(basic)) if e[k] < 0), None)
+            if src is None or dst is None:
+                break
+            t = min(e[src], -e[dst])
+            f = t / M[src]
+            moved = f * new[src]
+            new[dst] = new[dst] + moved
+            new[src] = new[src] - moved
+            M[src] -= t
+            M[dst] += t
+            if e[src] <= -e[dst]:
+                e[dst] += e[src]
+                e[src] = 0.0
+            else:
+                e[src] += e[dst]
+                e[dst] = 0.0
+
+    # -- ε rescaling is implicit: alpha is kept in energy units across eps changes.
+
+    # -- evaluation -----------------------------------------------------------
+    def y_marginal_error(self) -> float:
+        """L1 error of sum_i nu_i against nu."""
+        tot = np.zeros(self.N * self.N)
+        for idx, val in self.nu_i:
+            np.add.at(tot, idx, val)
+        return float(np.abs(tot - self.nu).sum())
+
+    def basic_mass_error(self) -> float:
+        """max_i |sum_y nu_i - m_i| (balancing target)."""
+        return float(max(abs(v.sum() - mi) for (_, v), mi in zip(self.nu_i, self.m)))
+
+    def cell_plans(self, which: Optional[str] = None):
+        """Dense composite plans of the last iteration on `which`: list of (xpix, ysup, plan)."""
+        which = which or self.last_which
+        eps = self.last_eps[which]
+        out = []
+        for cs in self.last[which]:
+            plan = cell_plan(self.coords[cs.xpix], self.mu[cs.xpix], cs.alpha,
+                             self.coords[cs.ysup], self.nu[cs.ysup], cs.beta, eps)
+            out.append((cs.xpix, cs.ysup, plan))
+        return out
+
+    def x_marginal_error(self, which: Optional[str] = None) -> float:
+        """L1 error of the X-marginal of the composite plans of the last iteration."""
+        e = 0.0
+        for xpix, _, plan in self.cell_plans(which):
+            e += float(np.abs(plan.sum(axis=1) - self.mu[xpix]).sum())
+        return e
+
+    def primal(self, eps: float, which: Optional[str] = None) -> float:
+        """E(pi) = <c, pi> + eps KL(pi | mu (x) nu) of the composite plans (eq. KL, eq.
+        entropic-transport): KL = sum_{pi>0} [pi log(pi/(mu nu)) - pi] + sum_{x,y} mu(x) nu(y)."""
+        E = 0.0
+        for xpix, ysup, plan in self.cell_plans(which):
+            d = self.coords[xpix][:, None, :] - self.coords[ysup][None, :, :]
+            c = (d ** 2).sum(axis=2)
+            ref = self.mu[xpix][:, None] * self.nu[ysup][None, :]
+            pos = plan > 0
+            E += float((c * plan).sum())
+            E += eps * float((plan[pos] * np.log(plan[pos] / ref[pos]) - plan[pos]).sum())
+        return E + eps * float(self.mu.sum() * self.nu.sum())
+
+    def transport_cost(self, which: Optional[str] = None) -> float:
+        """<c, pi> of the composite plans."""
+        E = 0.0
+        for xpix, ysup, plan in self.cell_plans(which):
+            d = self.coords[xpix][:, None, :] - self.coords[ysup][None, :, :]
+            E += float((((d ** 2).sum(axis=2)) * plan).sum())
+        return E
+
+    def dense_plan_from_state(self) -> np.ndarray:
+        """For s == 1 only: the plan sum_i delta_{x_i} (x) nu_i as an (N^2, N^2) array."""
+        assert self.s == 1
+        P = np.zeros((self.N * self.N, self.N * self.N))
+        for i, (idx, val) in enumerate(self.nu_i):
+            P[self.cells[i][0], idx] = val
+        return P
+
+    # -- flow update ------------------------------------------------------------
+    def flow_update(self, mass_bits: int = 40, cost_bits: int = 30, truncate: bool = True) -> dict:
+        """Flow update with product gluing candidates (Def. "Flow update", Remark "eps-gamma").
+
+        pi_i is the restriction to X_i x Y of the composite plan of the immediately
+        preceding DD iteration (instantiated from its potentials).  For every arc (i, j)
+        of the 4-neighbourhood plus self loops,
+            cbar_ij = <c, mu_j/m_j (x) nu_i/m_i> - <c, pi_i>/m_i   (i != j),  cbar_ii = 0,
+        summed by brute force over X_j x supp(nu_i) and X_i x supp(pi_i).
+        The min-cost flow is solved on integers: masses b_i by largest remainder with
+        sum 2^mass_bits, costs round(cbar * 2^cost_bits / max|cbar|); the flow is mapped
+        back as w_ij = flow_ij * m_i / b_i.  New marginals nu_hat_j = sum_i w_ij nu_i / m_i
+        (eq. flow-update-cell-marginals), then truncated at 1e-15.
+        """
+        which = self.last_which
+        eps = self.last_eps[which]
+        n, N = self.n, self.N
+        # instantiate pi_i from the last composite solve
+        ctotal = np.zeros(len(self.cells))
+        for cs in self.last[which]:
+            plan = cell_plan(self.coords[cs.xpix], self.mu[cs.xpix], cs.alpha,
+                             self.coords[cs.ysup], self.nu[cs.ysup], cs.beta, eps)
+            d = self.coords[cs.xpix][:, None, :] - self.coords[cs.ysup][None, :, :]
+            cp = ((d ** 2).sum(axis=2)) * plan
+            row = 0
+            for k, i in enumerate(cs.basic):
+                ctotal[i] = float(cp[row:row + cs.xcount[k]].sum())
+                row += cs.xcount[k]
+        tail, head = neighbourhood(n)
+        cbar = np.zeros(len(tail))
+        for a in range(len(tail)):
+            i, j = int(tail[a]), int(head[a])
+            if i == j:
+                continue
+            idx, val = self.nu_i[i]
+            xj = self.coords[self.cells[j]]
+            d = xj[:, None, :] - self.coords[idx][None, :, :]
+            c = (d ** 2).sum(axis=2)
+            w = (self.mu[self.cells[j]] / self.m[j])[:, None] * (val / self.m[i])[None, :]
+            cbar[a] = float((c * w).sum()) - ctotal[i] / self.m[i]
+        res = self.solve_flow(tail, head, cbar, mass_bits, cost_bits)
+        self.apply_flow(tail, head, res["w"], truncate=truncate)
+        res["cbar"] = cbar
+        return res
+
+    def solve_flow(self, tail, head, cbar, mass_bits=40, cost_bits=30) -> dict:
+        nI = len(self.cells)
+        b = largest_remainder(self.m, 1 << mass_bits)
+        cmax = float(np.abs(cbar).max()) if len(cbar) else 0.0
+        scale = (float(1 << cost_bits) / cmax) if cmax > 0 else 0.0
+        icost = np.rint(cbar * scale).astype(np.int64)
+        flow, pot, st = mcf_ssp(nI, tail, head, icost, b, b)
+        if st != 0:
+            raise RuntimeError("min-cost flow failed")
+        w = flow.astype(np.float64) * (self.m[tail] / b[tail].astype(np.float64))
+        return {"w": w, "flow": flow, "icost": icost, "b": b, "pot": pot,
+                "int_value": int((flow * icost).sum()), "value": float((w * cbar).sum())}
+
+    def apply_flow(self, tail, head, w, truncate: bool = True) -> None:
+        """nu_hat_j = sum_{i in N(j)} w_ij nu_i / m_i (eq. flow-update-cell-marginals)."""
+        parts: List[List[Tuple[np.ndarray, np.ndarray]]] = [[] for _ in self.cells]
+        for a in range(len(tail)):
+            i, j = int(tail[a]), int(head[a])
+            if w[a] == 0.0:
+                continue
+            idx, val = self.nu_i[i]
+            parts[j].append((idx, (w[a] / self.m[i]) * val))
+        new = []
+        for j in range(len(self.cells)):
+            idx, val = sparse_sum(parts[j])
+            if truncate:
+                keep = val >= self.trunc
+                idx, val = idx[keep], val[keep]
+            new.append((idx, val))
+        self.nu_i = new
+
+
+# ---------------------------------------------------------------------------
+# Global problems (tiny grids)
+# ---------------------------------------------------------------------------
+
+def global_sinkhorn(mu: np.ndarray, nu: np.ndarray, eps: float, tol: float = 1e-13,
+                    max_iter: int = 200000):
+    """Entropic OT on the whole grid with the oracle's cell solver (one cell = X, Y = supp nu).
+
+    Returns (alpha, beta) on all pixels (beta = nan off the support), and the dense plan."""
+    N = mu.shape[0]
+    C = pixel_coords(N)
+    m = mu.reshape(-1)
+    v = nu.reshape(-1)
+    ys = np.nonzero(v > 0)[0]
+    a, b, it, err, nit = sinkhorn_cells(np.array([0, N * N]), C, m, np.array([0, len(ys)]), C[ys],
+                                        v[ys], v[ys], eps, tol=tol, max_iter=max_iter, rule=0)
+    plan = np.zeros((N * N, N * N))
+    plan[:, ys] = cell_plan(C, m, a, C[ys], v[ys], b, eps)
+    beta = np.full(N * N, np.nan)
+    beta[ys] = b
+    return a, beta, plan, nit
+
+
+def dual_value(mu: np.ndarray, nu: np.ndarray, alpha: np.ndarray, beta: np.ndarray, eps: float) -> float:
+    """D(alpha, beta) = <alpha, mu> + <beta, nu> + eps <1 - exp((alpha+beta-c)/eps), mu (x) nu>."""
+    N = mu.shape[0]
+    C = pixel_coords(N)
+    m, v = mu.reshape(-1), nu.reshape(-1)
+    sup = v > 0
+    b = np.where(sup, beta, 0.0)
+    c = ((C[:, None, :] - C[None, :, :]) ** 2).sum(axis=2)
+    K = np.exp((alpha[:, None] + b[None, :] - c) / eps) * (m[:, None] * v[None, :])
+    K[:, ~sup] = 0.0
+    return float((alpha * m).sum() + (b * v).sum() + eps * (m.sum() * v.sum() - K.sum()))
+
+
+def primal_dense(mu: np.ndarray, nu: np.ndarray, plan: np.ndarray, eps: float) -> float:
+    """E(pi) for a dense (N^2, N^2) plan, straight from eq. (KL) and eq. (entropic-transport)."""
+    N = mu.shape[0]
+    C = pixel_coords(N)
+    m, v = mu.reshape(-1), nu.reshape(-1)
+    c = ((C[:, None, :] - C[None, :, :]) ** 2).sum(axis=2)
+    ref = m[:, None] * v[None, :]
+    pos = plan > 0
+    kl = float((plan[pos] * np.log(plan[pos] / ref[pos]) - plan[pos]).sum()) + float(ref.sum())
+    return float((c * plan).sum()) + eps * kl
