@@ -1,0 +1,294 @@
+/*
+ * domdec.h -- C ABI of the MI355X (gfx950) domain-decomposition library for
+ * entropic optimal transport with flow updates (Medina & Schmitzer, "Flow
+ * updates for domain decomposition of entropic optimal transport").
+ *
+ * Problem (Sec. 2.2, eq. entropic-transport): mu, nu are probability measures
+ * on the same regular N x N pixel grid of [0,1]^2 (pixel (k1,k2) has centre
+ * ((k1+1/2)h, (k2+1/2)h), h = 1/N, row-major, k1 slow), cost c(x,y) = |x-y|^2,
+ * regularisation eps > 0.  The library keeps a feasible coupling as its basic
+ * cell Y-marginals nu_i (Sec. 2.3 eq. basic-cell-Y-marginal) in per-cell
+ * bounding boxes (App. A.1 "Bounding box representation") on the device, and
+ * updates it by domain-decomposition iterations (Alg. "DomDecIter", App. A
+ * Alg. "DomDecIterGPU") and flow updates (Sec. 3.2 Def. "Flow update").
+ *
+ * Conventions for every entry point:
+ *   - No function aborts or exits.  A status is returned; every status other
+ *     than DD_OK / DD_NOTCONV leaves a message readable by domdec_strerror.
+ *   - DD_NOTCONV is a warning: max_iter was reached before the tolerance.
+ *   - Pointers marked (host) are host memory, (dev) device memory of the
+ *     current HIP device.  The caller owns every pointer it passes in; the
+ *     library copies what it keeps.  A dd_ctx owns its device memory and
+ *     releases it in domdec_free.
+ *   - Streams are hipStream_t passed as void*; NULL means the null stream.
+ *     Entry points that return statistics synchronise that stream.
+ *   - One dd_ctx must not be used by two host threads at once.
+ */
+#ifndef DOMDEC_H
+#define DOMDEC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    DD_OK = 0,
+    DD_NOTCONV = 1,    /* warning: iteration limit hit before the tolerance        */
+    DD_EINVAL = -1,    /* invalid argument (shape, value, NaN, unsupported option) */
+    DD_ENOMEM = -2,    /* device or host allocation failed                         */
+    DD_EDEVICE = -3,   /* a HIP call failed                                        */
+    DD_ESTATE = -4,    /* call out of order (e.g. flow_update before a B iteration)*/
+    DD_ENUMERIC = -5   /* a non-finite value appeared in a reduction               */
+} dd_status;
+
+enum { DD_PREC_F32 = 0, DD_PREC_F64 = 1 };      /* arithmetic of the cell log-sum-exp */
+enum { DD_STOP_BATCH = 0, DD_STOP_CELL = 1 };   /* Sinkhorn stopping rule             */
+enum { DD_INIT_ZERO = 0, DD_INIT_PREV = 1 };    /* X-potential initialisation         */
+enum { DD_PART_A = 0, DD_PART_B = 1 };          /* composite partition                */
+
+/* Sinkhorn options (App. A.2.1 "Stopping criterion and measure truncation").
+ * One iteration = Y-update, X-marginal L1 error, then (unless stopped) the
+ * X-update; a solve always ends on a Y-update, so the Y-marginal is exact.
+ *   DD_STOP_BATCH: stop once sum_J err_J <= tol * sum_J mu(X_J) (the paper's rule).
+ *   DD_STOP_CELL : cell J stops once err_J <= tol * mu(X_J); this implies the batch
+ *                  rule, so it never loosens the tolerance.
+ *   fixed_iters > 0: exactly fixed_iters Y-updates per cell, tol ignored.          */
+typedef struct {
+    double tol;           /* Err, e.g. 1e-5                                        */
+    int32_t max_iter;     /* iteration cap (>= 1)                                  */
+    int32_t fixed_iters;  /* 0 = use tol                                           */
+    int32_t stop_rule;    /* DD_STOP_BATCH | DD_STOP_CELL                          */
+    int32_t check_every;  /* batch rule: test the error every k-th iteration (>=1) */
+    int32_t init;         /* DD_INIT_ZERO | DD_INIT_PREV (domdec_iterate only)     */
+    int32_t reserved;     /* must be 0                                             */
+} dd_sinkhorn_opts;
+
+/* Statistics of one batched cell solve. */
+typedef struct {
+    int32_t ncells;
+    int32_t iters_max;         /* iterations of the batch (max over cells)             */
+    int32_t iters_min;
+    int32_t converged;         /* 1 if the stopping rule was met                       */
+    int64_t cell_iters;        /* sum over cells of iterations run                     */
+    double err;                /* final sum over cells of X-marginal L1 errors         */
+    double mass;               /* sum over cells of mu(X_J)                            */
+    double lse_terms;          /* log-sum-exp terms evaluated (exponentials)           */
+    double alg_bytes;          /* algorithmic bytes: 12 (|X_J| + W1 W2) per cell-iter  */
+    double time_ms;            /* device time of the whole solve (HIP events)          */
+    double main_ms;            /* device time of the main (float32 or float64) loop    */
+    int32_t finish_iters_max;  /* float64-finish iterations (sinkhorn_batch, tol mode)  */
+    int32_t reserved;
+} dd_batch_stats;
+
+/*
+ * sinkhorn_batch / sinkhorn_batch_f64 -- batched log-domain cell Sinkhorn
+ * (App. A.1 "Custom CUDA Sinkhorn": batched, log-domain, online cost,
+ * separable for the squared cost; the cell problem of Alg. "DomDecIter").
+ *
+ * Cell c has an X block of xside x xside pixels (local index i = (i1,i2),
+ * row-major) and a Y box of W1 x W2 pixels (local j = (j1,j2), row-major).
+ * With an integer gauge shift E = (E1,E2) per cell and kappa = eps / h^2 > 0
+ * the local cost is
+ *     C(i,j) = ((i1 - j1 + E1)^2 + (i2 - j2 + E2)^2) / kappa.
+ * For an X block at pixel origin pX and a Y box at pixel origin pY the true
+ * cost |x - y|^2 / eps equals |pX - pY + i - j|^2 / kappa, which differs from
+ * C by f(i) + g(j); such terms leave the optimal plan unchanged (they move
+ * into the potentials), so the plan solved here is the paper's cell plan for
+ * any choice of E.  A shift near the mean displacement keeps the potentials
+ * small, which is what lets float32 reach tol = 1e-5.
+ *
+ * Potentials f = alpha/eps (X) and g = beta/eps (Y) are taken with reference measure
+ * mu_J (x) nu_J, which differs from the paper's mu_J (x) nu by a constant (Sec. 2.3):
+ *     pi(i,j) = mu(i) nu_J(j) exp(f(i) + g(j) - C(i,j))
+ *     g(j) = -LSE_i [f(i) + log mu(i) - C(i,j)]                   (Y-update)
+ *     err  = sum_i mu(i) |exp(f(i) + LSE_j[g(j) + log nu_J(j) - C(i,j)]) - 1|
+ *     f(i) = -LSE_j [g(j) + log nu_J(j) - C(i,j)]                 (X-update)
+ * Each LSE runs as two 1D passes, one per axis (the cost is separable).
+ * Arguments (all arrays (dev), cells packed in order c = 0..ncells-1):
+ *   xside         X block side (2..16); each cell's X block has xside^2 entries.
+ *   dims          int32 [ncells][2]: W1, W2 >= 1.
+ *   base          int64 [ncells]: offset of cell c's Y box in lognu and b.
+ *   shift         int32 [ncells][2]: E1, E2.
+ *   logmu         [ncells][xside^2]: log mu; entries <= -1e30 mark zero mass.
+ *   lognu         packed Y boxes: log nu_J; entries <= -1e30 mark zero mass.
+ *   a             [ncells][xside^2] in: initial f; out: final f.
+ *   b             packed Y boxes, out: final g (g of the last Y-update).
+ *   kappa         eps / h^2.
+ *   max_w1/max_w2 upper bounds of W1, W2 over the batch (size the on-chip tiles).
+ *   opts          (host) options; init and reserved are ignored here.
+ *   cell_iters    int32 [ncells] out, may be NULL: iterations per cell.
+ *   cell_err      double [ncells] out, may be NULL: final error per cell.
+ *   stream        hipStream_t; the call synchronises it before returning.
+ *   stats         (host) out, may be NULL.
+ * Errors: DD_EINVAL for ncells < 0, xside outside [2,16], kappa <= 0, a cell
+ * whose W1/W2 exceed max_w1/max_w2 or is < 1, or bad opts; DD_ENUMERIC if an
+ * error sum is not finite; DD_NOTCONV when max_iter stopped the solve.
+ * Inputs, potentials and outputs are float64 in both entry points.  sinkhorn_batch
+ * evaluates the log-sum-exp terms in float32, each 1D pass on values shifted by a
+ * float64 maximum of its input line (so every float32 term is O(1)), with float64
+ * line offsets, potentials, errors and masses.  When it stops on a tolerance, the
+ * same rule then continues in float64 from the float32 state until the float64
+ * error meets the tolerance (usually one Y-update), so the tolerance holds in
+ * float64.  sinkhorn_batch_f64 is float64 throughout.  Y boxes too large for one
+ * workgroup's LDS run from global memory (L2-resident) instead.
+ */
+dd_status sinkhorn_batch(int32_t ncells, int32_t xside, const int32_t* dims, const int64_t* base,
+                         const int32_t* shift, const double* logmu, const double* lognu,
+                         double* a, double* b, double kappa, int32_t max_w1, int32_t max_w2,
+                         const dd_sinkhorn_opts* opts, int32_t* cell_iters, double* cell_err,
+                         void* stream, dd_batch_stats* stats);
+
+dd_status sinkhorn_batch_f64(int32_t ncells, int32_t xside, const int32_t* dims,
+                             const int64_t* base, const int32_t* shift, const double* logmu,
+                             const double* lognu, double* a, double* b, double kappa,
+                             int32_t max_w1, int32_t max_w2, const dd_sinkhorn_opts* opts,
+                             int32_t* cell_iters, double* cell_err, void* stream,
+                             dd_batch_stats* stats);
+
+/* ------------------------------------------------------------------------- */
+/* Domain-decomposition context                                              */
+/* ------------------------------------------------------------------------- */
+
+typedef struct dd_ctx dd_ctx;
+
+typedef struct {
+    int32_t n;         /* grid side N                                              */
+    int32_t s;         /* basic cell side; N % (2 s) == 0, 1 <= s <= 8              */
+    double trunc;      /* truncation threshold for nu_i entries (e.g. 1e-15)       */
+    int32_t prec;      /* DD_PREC_F32 | DD_PREC_F64                                */
+    int32_t reserved;  /* must be 0                                                */
+} dd_params;
+
+/*
+ * domdec_init -- set up partitions and the initial coupling (Def. "Basic and
+ * composite partitions"; Alg. "DomDec" input pi_init; App. A.2.1 "Basic and
+ * composite partitions").
+ *   Basic cells are the s x s pixel blocks, i = r * (N/s) + c.  Partition A
+ *   groups 2x2 basic cells from the origin; partition B groups 2x2 basic cells
+ *   shifted by one basic cell, boundary cells keep their in-range members (on
+ *   the device they are padded to 2s x 2s with zero mass, which leaves every
+ *   plan unchanged).
+ *   mu, nu     (host) float64 [N*N], >= 0, each summing to 1 within 1e-12;
+ *              every basic cell needs m_i = mu(X_i) > 0.
+ *   n_init     0 for the product coupling nu_i = m_i nu; else the number of
+ *              entries of a sparse initial coupling given by
+ *   init_x, init_y (host) int64 [n_init] flat pixel indices and
+ *   init_m     (host) float64 [n_init] masses; the coupling must have marginals
+ *              mu and nu within 1e-12 (checked).
+ *   stream     hipStream_t for all later work of this context.
+ *   out        receives the context (NULL on failure).
+ * Errors: DD_EINVAL (shapes, negative/NaN masses, sums, m_i == 0, marginals),
+ * DD_ENOMEM, DD_EDEVICE.
+ */
+dd_status domdec_init(const dd_params* params, const double* mu, const double* nu, int64_t n_init,
+                      const int64_t* init_x, const int64_t* init_y, const double* init_m,
+                      void* stream, dd_ctx** out);
+
+/* Statistics of one domain-decomposition iteration. */
+typedef struct {
+    dd_batch_stats sk;        /* the cell solve                                       */
+    int32_t partition;
+    int32_t max_w1, max_w2;   /* largest composite Y box                              */
+    int32_t reserved;
+    int64_t nu_entries;       /* stored nu_i entries after truncation                 */
+    int64_t comp_entries;     /* composite Y-box entries solved                       */
+    double t_b2c_ms;          /* BasicToComposite                                     */
+    double t_sinkhorn_ms;     /* cell solve                                           */
+    double t_c2b_ms;          /* CompositeToBasic + balancing + truncation            */
+    double t_total_ms;        /* whole iteration (device)                             */
+} dd_iter_stats;
+
+/*
+ * domdec_iterate -- one domain-decomposition iteration on partition A or B
+ * (Alg. "DomDecIter"; App. A Alg. "DomDecIterGPU" without the batch loop: all
+ * composite cells run in one launch):
+ *   BasicToComposite (eq. get-composite-cell-marginal), batched cell Sinkhorn
+ *   at regularisation eps, CompositeToBasic (App. A.1 "Online reduction for
+ *   basic cell marginals"), balancing, truncation below params.trunc.
+ *   X-potentials persist per partition: opts.init = DD_INIT_PREV warm-starts
+ *   from the previous visit of this partition (alpha kept in energy units across
+ *   eps changes), DD_INIT_ZERO starts from zero.
+ *   stats (host) may be NULL.  Synchronises the context stream.
+ * Errors: DD_EINVAL (partition, eps <= 0, opts), DD_ENOMEM (a box outgrew the
+ * on-chip limit or memory), DD_ENUMERIC, DD_NOTCONV (warning).
+ */
+dd_status domdec_iterate(dd_ctx* ctx, int32_t partition, double eps,
+                         const dd_sinkhorn_opts* opts, dd_iter_stats* stats);
+
+/* Flow update statistics. */
+typedef struct {
+    int32_t n_nodes, n_arcs;
+    int64_t int_value;         /* optimal value of the integer min-cost flow          */
+    double value;              /* sum_ij w_ij cbar_ij in float64 (<= 0)               */
+    double moved_mass;         /* sum_{i != j} w_ij                                   */
+    int32_t n_active_arcs;     /* arcs i != j with w_ij > 0                           */
+    int32_t reserved;
+    double t_costs_ms, t_mcf_ms, t_assemble_ms;
+} dd_flow_stats;
+
+/*
+ * flow_update -- flow update with product gluing candidates (Sec. 3.2
+ * Def. "Flow update", Def. "Gluing edge candidate", Remark "eps-gamma";
+ * implementation steps of Sec. 5.1).  Must follow a B iteration: pi_i is the
+ * restriction to X_i x Y of that iteration's composite plans.
+ *   Edge costs cbar_ij = <c, mu_j/m_j (x) nu_i/m_i> - <c, pi_i>/m_i over the
+ *   4-neighbourhood (cbar_ii = 0), computed on the device in float64 from cell
+ *   moments; min-cost flow (MinCostFlow) on the host, integerised with masses
+ *   b_i (largest remainder, sum 2^40) and costs round(cbar 2^30 / max|cbar|),
+ *   w_ij = flow_ij m_i / b_i; new marginals nu_hat_j = sum_i w_ij nu_i / m_i
+ *   (eq. flow-update-cell-marginals) assembled on the device, then truncated.
+ *   stats (host) may be NULL.  Synchronises the context stream.
+ * Errors: DD_ESTATE if the last iteration was not on partition B.
+ */
+dd_status flow_update(dd_ctx* ctx, dd_flow_stats* stats);
+
+/* Host view of the basic-cell Y-marginals (two-call protocol). */
+typedef struct {
+    int64_t n_cells;     /* out: |I|                                                   */
+    int64_t n_entries;   /* out: total stored entries                                  */
+    int32_t* offsets;    /* (host) [|I|][2] Y-box origin (k1, k2), or NULL             */
+    int32_t* dims;       /* (host) [|I|][2] Y-box dims (w1, w2), or NULL               */
+    int64_t* base;       /* (host) [|I|+1] offsets into data, or NULL                  */
+    double* data;        /* (host) [n_entries] row-major box entries, or NULL          */
+} dd_plan_view;
+
+/*
+ * extract_plan -- copy the coupling out as basic-cell Y-marginals (Sec. 2.3
+ * eq. basic-cell-Y-marginal) in bounding-box form (App. A.1).  First call with
+ * all pointers NULL to read n_cells and n_entries, then with caller buffers of
+ * those sizes.  Synchronises the context stream.
+ */
+dd_status extract_plan(dd_ctx* ctx, dd_plan_view* view);
+
+/* Quality measures (App. A.2.2 "Solution quality"). */
+typedef struct {
+    double y_marginal_l1;   /* sum_y |sum_i nu_i(y) - nu(y)| of the stored state      */
+    double x_marginal_l1;   /* X-marginal L1 error of the last composite plans        */
+    double primal;          /* E(pi) of the last composite plans                       */
+    double transport;       /* <c, pi> of the last composite plans                     */
+    double basic_mass_err;  /* max_i |sum_y nu_i - m_i|                                */
+    double total_mass;      /* sum of all stored nu_i entries                          */
+} dd_eval;
+
+/*
+ * domdec_evaluate -- float64 reductions of the current state (App. A.2.2):
+ * marginal errors and the primal objective E(pi) = <c,pi> + eps KL(pi|mu (x) nu)
+ * of the composite plans pi_J of the last iteration, evaluated from their
+ * potentials in float64.  Synchronises the context stream.
+ */
+dd_status domdec_evaluate(dd_ctx* ctx, dd_eval* out);
+
+void domdec_free(dd_ctx* ctx);
+
+/* Message of the last error on ctx (or of the last context-free call when ctx is
+ * NULL); never NULL. */
+const char* domdec_strerror(const dd_ctx* ctx, dd_status status);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DOMDEC_H */

@@ -1,0 +1,286 @@
+"""ctypes binding of libdomdec.so (include/domdec.h).  Marshalling only."""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(HERE, "libdomdec.so")
+_LIB = None
+
+DD_OK, DD_NOTCONV, DD_EINVAL, DD_ENOMEM, DD_EDEVICE, DD_ESTATE, DD_ENUMERIC = 0, 1, -1, -2, -3, -4, -5
+DD_PREC_F32, DD_PREC_F64 = 0, 1
+DD_STOP_BATCH, DD_STOP_CELL = 0, 1
+DD_INIT_ZERO, DD_INIT_PREV = 0, 1
+DD_PART_A, DD_PART_B = 0, 1
+
+_NAMES = {0: "DD_OK", 1: "DD_NOTCONV", -1: "DD_EINVAL", -2: "DD_ENOMEM", -3: "DD_EDEVICE",
+          -4: "DD_ESTATE", -5: "DD_ENUMERIC"}
+
+# every function include/domdec.h declares
+SYMBOLS = ("sinkhorn_batch", "sinkhorn_batch_f64", "domdec_init", "domdec_iterate", "flow_update",
+           "extract_plan", "domdec_evaluate", "domdec_free", "domdec_strerror")
+
+
+class DomDecError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+class SinkhornOpts(ctypes.Structure):
+    _fields_ = [("tol", ctypes.c_double), ("max_iter", ctypes.c_int32), ("fixed_iters", ctypes.c_int32),
+                ("stop_rule", ctypes.c_int32), ("check_every", ctypes.c_int32), ("init", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
+
+
+class BatchStats(ctypes.Structure):
+    _fields_ = [("ncells", ctypes.c_int32), ("iters_max", ctypes.c_int32), ("iters_min", ctypes.c_int32),
+                ("converged", ctypes.c_int32), ("cell_iters", ctypes.c_int64), ("err", ctypes.c_double),
+                ("mass", ctypes.c_double), ("lse_terms", ctypes.c_double), ("alg_bytes", ctypes.c_double),
+                ("time_ms", ctypes.c_double), ("main_ms", ctypes.c_double),
+                ("finish_iters_max", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+class Params(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32), ("s", ctypes.c_int32), ("trunc", ctypes.c_double),
+                ("prec", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+class IterStats(ctypes.Structure):
+    _fields_ = [("sk", BatchStats), ("partition", ctypes.c_int32), ("max_w1", ctypes.c_int32),
+                ("max_w2", ctypes.c_int32), ("reserved", ctypes.c_int32), ("nu_entries", ctypes.c_int64),
+                ("comp_entries", ctypes.c_int64), ("t_b2c_ms", ctypes.c_double),
+                ("t_sinkhorn_ms", ctypes.c_double), ("t_c2b_ms", ctypes.c_double),
+                ("t_total_ms", ctypes.c_double)]
+
+
+class FlowStats(ctypes.Structure):
+    _fields_ = [("n_nodes", ctypes.c_int32), ("n_arcs", ctypes.c_int32), ("int_value", ctypes.c_int64),
+                ("value", ctypes.c_double), ("moved_mass", ctypes.c_double),
+                ("n_active_arcs", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("t_costs_ms", ctypes.c_double), ("t_mcf_ms", ctypes.c_double),
+                ("t_assemble_ms", ctypes.c_double)]
+
+
+class PlanView(ctypes.Structure):
+    _fields_ = [("n_cells", ctypes.c_int64), ("n_entries", ctypes.c_int64),
+                ("offsets", ctypes.POINTER(ctypes.c_int32)), ("dims", ctypes.POINTER(ctypes.c_int32)),
+                ("base", ctypes.POINTER(ctypes.c_int64)), ("data", ctypes.POINTER(ctypes.c_double))]
+
+
+class Eval(ctypes.Structure):
+    _fields_ = [("y_marginal_l1", ctypes.c_double), ("x_marginal_l1", ctypes.c_double),
+                ("primal", ctypes.c_double), ("transport", ctypes.c_double),
+                ("basic_mass_err", ctypes.c_double), ("total_mass", ctypes.c_double)]
+
+
+def _struct_dict(s) -> dict:
+    out = {}
+    for name, _ in s._fields_:
+        v = getattr(s, name)
+        out[name] = _struct_dict(v) if isinstance(v, ctypes.Structure) else v
+    return out
+
+
+def lib_path() -> str:
+    return _LIB_PATH
+
+
+def lib():
+    """Load libdomdec.so; raises if it has not been built (no fallback)."""
+    global _LIB
+    if _LIB is not None:
+        return _LIB
+    if not os.path.exists(_LIB_PATH):
+        raise RuntimeError(f"{_LIB_PATH} is missing: build it with `python -m paper_2405_09400_amd.build` "
+                           "(the HIP library is required; there is no CPU path)")
+    L = ctypes.CDLL(_LIB_PATH)
+    vp, i32p, i64p = ctypes.c_void_p, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int64)
+    dp = ctypes.POINTER(ctypes.c_double)
+    for name in ("sinkhorn_batch", "sinkhorn_batch_f64"):
+        f = getattr(L, name)
+        f.restype = ctypes.c_int
+        f.argtypes = [ctypes.c_int32, ctypes.c_int32, vp, vp, vp, vp, vp, vp, vp, ctypes.c_double,
+                      ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(SinkhornOpts), vp, vp, vp,
+                      ctypes.POINTER(BatchStats)]
+    L.domdec_init.restype = ctypes.c_int
+    L.domdec_init.argtypes = [ctypes.POINTER(Params), dp, dp, ctypes.c_int64, i64p, i64p, dp, vp,
+                              ctypes.POINTER(vp)]
+    L.domdec_iterate.restype = ctypes.c_int
+    L.domdec_iterate.argtypes = [vp, ctypes.c_int32, ctypes.c_double, ctypes.POINTER(SinkhornOpts),
+                                 ctypes.POINTER(IterStats)]
+    L.flow_update.restype = ctypes.c_int
+    L.flow_update.argtypes = [vp, ctypes.POINTER(FlowStats)]
+    L.extract_plan.restype = ctypes.c_int
+    L.extract_plan.argtypes = [vp, ctypes.POINTER(PlanView)]
+    L.domdec_evaluate.restype = ctypes.c_int
+    L.domdec_evaluate.argtypes = [vp, ctypes.POINTER(Eval)]
+    L.domdec_free.restype = None
+    L.domdec_free.argtypes = [vp]
+    L.domdec_strerror.restype = ctypes.c_char_p
+    L.domdec_strerror.argtypes = [vp, ctypes.c_int]
+    _LIB = L
+    return L
+
+
+def exported_symbols():
+    """Names from include/domdec.h that the loaded library exports."""
+    L = lib()
+    return [n for n in SYMBOLS if hasattr(L, n)]
+
+
+def _check(st: int, ctx=None, warn_ok=True):
+    if st == DD_OK or (warn_ok and st == DD_NOTCONV):
+        return st
+    msg = lib().domdec_strerror(ctx, st)
+    raise DomDecError(st, msg.decode() if msg else "")
+
+
+def _ptr(t) -> Optional[int]:
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _opts(tol, max_iter, fixed_iters, stop_rule, check_every, init=DD_INIT_PREV) -> SinkhornOpts:
+    return SinkhornOpts(float(tol), int(max_iter), int(fixed_iters), int(stop_rule), int(check_every),
+                        int(init), 0)
+
+
+def _stream_ptr(stream):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def sinkhorn_batch(dims, base, shift, logmu, lognu, a, b, kappa, max_w1, max_w2, *, prec=DD_PREC_F32,
+                   tol=1e-5, max_iter=10000, fixed_iters=0, stop_rule=DD_STOP_BATCH, check_every=8,
+                   cell_iters=None, cell_err=None, stream=None, raise_on_error=True):
+    """Batched cell Sinkhorn on device tensors (see sinkhorn_batch in include/domdec.h).
+
+    dims int32 [n,2], base int64 [n], shift int32 [n,2], float64 logmu [n, xside^2], lognu packed,
+    a [n, xside^2] (f, in/out), b packed (g, out).  prec DD_PREC_F32 -> sinkhorn_batch
+    (float32 log-sum-exp terms), DD_PREC_F64 -> sinkhorn_batch_f64.  Returns (status, stats)."""
+    import torch
+    n = int(dims.shape[0])
+    xside = int(round(logmu.shape[1] ** 0.5)) if n else 2
+    for t, dt in ((dims, torch.int32), (base, torch.int64), (shift, torch.int32)):
+        assert t.dtype == dt and t.is_cuda and t.is_contiguous()
+    for t in (logmu, lognu, a, b):
+        assert t.dtype == torch.float64 and t.is_cuda and t.is_contiguous()
+    # host-side shape checks: the kernels trust base/dims to stay inside the packed buffers
+    if n:
+        hd = dims.cpu().numpy().astype(np.int64)
+        hb = base.cpu().numpy()
+        if logmu.dim() != 2 or logmu.shape[1] != xside * xside or tuple(a.shape) != tuple(logmu.shape) \
+                or logmu.shape[0] != n or tuple(shift.shape) != (n, 2) or tuple(dims.shape) != (n, 2):
+            raise ValueError("sinkhorn_batch: logmu/a must be [n, xside^2], dims/shift [n, 2]")
+        if np.any(hd < 1) or np.any(hb < 0) or np.any(hb + hd[:, 0] * hd[:, 1] > lognu.numel()) \
+                or b.numel() != lognu.numel():
+            raise ValueError("sinkhorn_batch: a Y box lies outside lognu/b")
+    f = lib().sinkhorn_batch if prec == DD_PREC_F32 else lib().sinkhorn_batch_f64
+    st = BatchStats()
+    o = _opts(tol, max_iter, fixed_iters, stop_rule, check_every)
+    status = f(n, xside, _ptr(dims), _ptr(base), _ptr(shift), _ptr(logmu), _ptr(lognu), _ptr(a), _ptr(b),
+               float(kappa), int(max_w1), int(max_w2), ctypes.byref(o), _ptr(cell_iters), _ptr(cell_err),
+               _stream_ptr(stream), ctypes.byref(st))
+    if raise_on_error:
+        _check(status)
+    return status, _struct_dict(st)
+
+
+class DomDec:
+    """A device-resident domain-decomposition state (dd_ctx) on the current HIP device."""
+
+    def __init__(self, mu: np.ndarray, nu: np.ndarray, s: int, init=None, trunc: float = 1e-15,
+                 prec: int = DD_PREC_F32, stream=None):
+        import torch
+        self.N = int(mu.shape[0])
+        self.s = int(s)
+        self._stream = stream if stream is not None else torch.cuda.current_stream()
+        mu64 = np.ascontiguousarray(mu.reshape(-1), dtype=np.float64)
+        nu64 = np.ascontiguousarray(nu.reshape(-1), dtype=np.float64)
+        p = Params(self.N, self.s, float(trunc), int(prec), 0)
+        ctx = ctypes.c_void_p()
+        dp = ctypes.POINTER(ctypes.c_double)
+        i64p = ctypes.POINTER(ctypes.c_int64)
+        if init is None:
+            n_init, xp, yp, mp = 0, None, None, None
+        else:
+            x, y, m = init
+            self._ix = np.ascontiguousarray(x, dtype=np.int64)
+            self._iy = np.ascontiguousarray(y, dtype=np.int64)
+            self._im = np.ascontiguousarray(m, dtype=np.float64)
+            n_init = len(self._ix)
+            xp, yp, mp = (self._ix.ctypes.data_as(i64p), self._iy.ctypes.data_as(i64p),
+                          self._im.ctypes.data_as(dp))
+        st = lib().domdec_init(ctypes.byref(p), mu64.ctypes.data_as(dp), nu64.ctypes.data_as(dp), n_init,
+                               xp, yp, mp, _stream_ptr(self._stream), ctypes.byref(ctx))
+        _check(st, None)
+        self._ctx = ctx
+
+    def close(self):
+        if getattr(self, "_ctx", None):
+            lib().domdec_free(self._ctx)
+            self._ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def iterate(self, partition: str, eps: float, *, tol=1e-5, max_iter=10000, fixed_iters=0,
+                stop_rule=DD_STOP_BATCH, check_every=8, init=DD_INIT_PREV) -> dict:
+        st = IterStats()
+        o = _opts(tol, max_iter, fixed_iters, stop_rule, check_every, init)
+        part = {"A": DD_PART_A, "B": DD_PART_B}[partition] if isinstance(partition, str) else int(partition)
+        status = lib().domdec_iterate(self._ctx, part, float(eps), ctypes.byref(o), ctypes.byref(st))
+        _check(status, self._ctx)
+        d = _struct_dict(st)
+        d["status"] = status
+        return d
+
+    def flow_update(self) -> dict:
+        st = FlowStats()
+        _check(lib().flow_update(self._ctx, ctypes.byref(st)), self._ctx)
+        return _struct_dict(st)
+
+    def evaluate(self) -> dict:
+        ev = Eval()
+        _check(lib().domdec_evaluate(self._ctx, ctypes.byref(ev)), self._ctx)
+        return _struct_dict(ev)
+
+    def extract_plan(self):
+        """Basic-cell Y-marginals: (offsets [I,2], dims [I,2], base [I+1], data) host arrays."""
+        v = PlanView()
+        _check(lib().extract_plan(self._ctx, ctypes.byref(v)), self._ctx)
+        nI, nE = int(v.n_cells), int(v.n_entries)
+        off = np.zeros((nI, 2), np.int32)
+        dims = np.zeros((nI, 2), np.int32)
+        base = np.zeros(nI + 1, np.int64)
+        data = np.zeros(max(nE, 1), np.float64)
+        v.offsets = off.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+        v.dims = dims.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+        v.base = base.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))
+        v.data = data.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        _check(lib().extract_plan(self._ctx, ctypes.byref(v)), self._ctx)
+        return off, dims, base, data[:nE]
+
+    def nu_i_sparse(self):
+        """The stored basic-cell Y-marginals as (flat indices, values) lists (host)."""
+        off, dims, base, data = self.extract_plan()
+        out = []
+        for i in range(len(dims)):
+            o1, o2 = off[i]
+            w1, w2 = dims[i]
+            vals = data[base[i]:base[i + 1]].reshape(w1, w2)
+            k1 = (o1 + np.arange(w1))[:, None]
+            k2 = (o2 + np.arange(w2))[None, :]
+            idx = (k1 * self.N + k2).reshape(-1)
+            v = vals.reshape(-1)
+            keep = v > 0
+            out.append((idx[keep].astype(np.int64), v[keep]))
+        return out

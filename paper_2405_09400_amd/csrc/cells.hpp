@@ -1,0 +1,60 @@
+// Basic/composite cell-marginal kernels of one domain-decomposition iteration (declarations).
+#pragma once
+
+#include "common.hpp"
+
+namespace dd {
+
+// Static geometry of a composite partition on the device.
+struct PartDev {
+    int ncell = 0;
+    int32_t* members = nullptr;  // [ncell][4] basic ids, -1 if absent; slot k = (dr, dc) = (k>>1, k&1)
+    int32_t* xorig = nullptr;    // [ncell][2] X block origin pixel (may be -s for B)
+};
+
+// Current basic-cell Y-marginals nu_i in bounding-box form.
+struct BoxSet {
+    int32_t* box = nullptr;   // [nI][4] o1, o2, w1, w2
+    int64_t* base = nullptr;  // [nI + 1]
+    double* data = nullptr;   // packed row-major boxes
+    size_t cap = 0;           // entries allocated in data
+};
+
+// Composite-cell work arrays of one iteration.
+struct CompDev {
+    int32_t* dims = nullptr;   // [ncell][2] W1, W2
+    int32_t* orig = nullptr;   // [ncell][2] Y box origin pixel
+    int32_t* shift = nullptr;  // [ncell][2] gauge E
+    int32_t* gofs = nullptr;   // [ncell][2] G = pX - pY - E of this solve
+    int64_t* size = nullptr;   // [ncell] W1*W2
+    int64_t* base = nullptr;   // [ncell + 1]
+    int32_t* info = nullptr;   // [8] totals read back by the host
+};
+
+void launch_fill_i32(int32_t* p, int n, int32_t v, hipStream_t st);
+void launch_comp_boxes(const PartDev& P, const BoxSet& S, int xside, CompDev& C, hipStream_t st);
+void launch_scan(const int64_t* in, int64_t* out, int n, hipStream_t st);
+void launch_comp_max(const CompDev& C, int ncell, hipStream_t st);
+
+void launch_b2c(const PartDev& P, const BoxSet& S, const CompDev& C, double* nuJ, double* lognu,
+                hipStream_t st);
+
+void launch_warm_start(const PartDev& P, const CompDev& C, int xside, double* a, int32_t* g_stored,
+                       double kappa_old, double kappa_new, int use_prev, hipStream_t st);
+
+// c2b needs an upper bound maxw2 of the box widths (sizes its LDS tiles).
+void launch_c2b(const PartDev& P, const CompDev& C, int xside, int s, int maxw2, const double* a,
+                const double* logmu, const double* nuJ, double kappa, double h, double* tmp,
+                double* py2, hipStream_t st);
+
+void launch_balance(const PartDev& P, const CompDev& C, const double* m, double* tmp,
+                    hipStream_t st);
+
+void launch_trunc_boxes(const PartDev& P, const CompDev& C, const double* tmp, double trunc,
+                        int nI, int32_t* nbox, int64_t* nsize, int32_t* flags, hipStream_t st);
+
+void launch_compact(const PartDev& P, const CompDev& C, const double* tmp, double trunc,
+                    const int32_t* nbox, const int64_t* nbase, const int32_t* flags,
+                    double* ndata, hipStream_t st);
+
+}  // namespace dd

@@ -1,0 +1,542 @@
+// Domain-decomposition context: setup, one DD iteration, plan extraction and evaluation.
+//
+// Alg. "DomDecIter" as App. A Alg. "DomDecIterGPU" lays it out, with all composite cells of
+// a partition in one batch (no CreateBatches / CombineBatches loop):
+//   BasicToComposite -> warm start -> batched cell Sinkhorn -> CompositeToBasic ->
+//   balancing -> truncation and repacking.
+// The state is the set of basic-cell Y-marginals nu_i in per-cell bounding boxes on the
+// device (float64).  The host only reads back a few sizes per iteration (to size buffers
+// and the solver's LDS tiles) and the statistics.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <numeric>
+#include <vector>
+
+#include "cells.hpp"
+#include "ctx.hpp"
+#include "eval.hpp"
+#include "sinkhorn.hpp"
+
+using namespace dd;
+
+namespace {
+
+template <typename P>
+Status grow(P*& p, size_t& cap, size_t need, Status& st, double slack = 1.25) {
+    if (need <= cap && p) return st;
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    const size_t n = std::max<size_t>((size_t)(need * slack) + 16, 64);
+    DD_HIP(hipMalloc(&p, n * sizeof(P)), st);
+    cap = n;
+    return st;
+}
+
+template <typename P>
+Status alloc(P*& p, size_t n, Status& st) {
+    DD_HIP(hipMalloc(&p, std::max<size_t>(n, 1) * sizeof(P)), st);
+    return st;
+}
+
+template <typename P>
+Status upload(P*& p, const std::vector<P>& v, hipStream_t s, Status& st) {
+    if (alloc(p, v.size(), st).code) return st;
+    if (!v.empty()) {
+        // the host vector may be a temporary: finish the copy before returning
+        DD_HIP(hipMemcpyAsync(p, v.data(), v.size() * sizeof(P), hipMemcpyHostToDevice, s), st);
+        DD_HIP(hipStreamSynchronize(s), st);
+    }
+    return st;
+}
+
+dd_status fail(dd_ctx* c, dd_status code, const std::string& m) {
+    if (c) c->err = m;
+    set_global_error(m);
+    return code;
+}
+
+dd_status fail(dd_ctx* c, const Status& s) { return fail(c, s.code, s.msg); }
+
+}  // namespace
+
+void dd_ctx_release(dd_ctx* c) {
+    auto F = [](auto& p) {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+    };
+    F(c->d_mu);
+    F(c->d_nu);
+    F(c->d_lognu_glob);
+    F(c->d_m);
+    for (int q = 0; q < 2; ++q) {
+        F(c->part[q].members);
+        F(c->part[q].xorig);
+        F(c->d_logmu[q]);
+        F(c->d_a[q]);
+        F(c->d_gst[q]);
+    }
+    for (BoxSet* S : {&c->S, &c->S2}) {
+        F(S->box);
+        F(S->base);
+        F(S->data);
+    }
+    F(c->C.dims);
+    F(c->C.orig);
+    F(c->C.shift);
+    F(c->C.gofs);
+    F(c->C.size);
+    F(c->C.base);
+    F(c->C.info);
+    F(c->d_nuJ);
+    F(c->d_lognu);
+    F(c->d_b);
+    F(c->d_tmp);
+    F(c->d_py2);
+    F(c->d_nsize);
+    F(c->d_flags);
+    F(c->d_iters);
+    F(c->d_cerr);
+    F(c->d_scratch);
+    F(c->d_cell_out);
+    F(c->d_basic_out);
+    F(c->d_eval);
+    for (auto& e : c->ev)
+        if (e) (void)hipEventDestroy(e);
+    sk_work_release(c->skw);
+    flow_release(c);
+}
+
+extern "C" dd_status domdec_init(const dd_params* prm, const double* mu, const double* nu,
+                                 int64_t n_init, const int64_t* init_x, const int64_t* init_y,
+                                 const double* init_m, void* stream, dd_ctx** out) {
+    if (out) *out = nullptr;
+    if (!prm || !mu || !nu || !out) return fail(nullptr, DD_EINVAL, "domdec_init: null argument");
+    const int N = prm->n, s = prm->s;
+    if (N < 2 || s < 1 || s > 8 || N % (2 * s) != 0 || prm->reserved != 0 ||
+        (prm->prec != DD_PREC_F32 && prm->prec != DD_PREC_F64) || !(prm->trunc >= 0.0))
+        return fail(nullptr, DD_EINVAL,
+                    "domdec_init: need N % (2s) == 0, 1 <= s <= 8, prec F32|F64, trunc >= 0");
+    if (n_init < 0 || (n_init > 0 && (!init_x || !init_y || !init_m)))
+        return fail(nullptr, DD_EINVAL, "domdec_init: bad initial coupling arrays");
+    const int64_t NN = (int64_t)N * N;
+    double smu = 0, snu = 0;
+    for (int64_t k = 0; k < NN; ++k) {
+        if (!(mu[k] >= 0.0) || !(nu[k] >= 0.0) || !std::isfinite(mu[k]) || !std::isfinite(nu[k]))
+            return fail(nullptr, DD_EINVAL, "domdec_init: masses must be finite and >= 0");
+        smu += mu[k];
+        snu += nu[k];
+    }
+    if (std::fabs(smu - 1.0) > 1e-12 || std::fabs(snu - 1.0) > 1e-12)
+        return fail(nullptr, DD_EINVAL, "domdec_init: mu and nu must each sum to 1 (within 1e-12)");
+
+    dd_ctx* c = new dd_ctx();
+    c->N = N;
+    c->s = s;
+    c->n = N / s;
+    c->nI = c->n * c->n;
+    c->AS = 2 * s;
+    c->h = 1.0 / N;
+    c->trunc = prm->trunc;
+    c->prec = prm->prec;
+    c->st = reinterpret_cast<hipStream_t>(stream);
+    Status st;
+    const hipStream_t hs = c->st;
+    auto bail = [&](const Status& e) {
+        dd_ctx_release(c);
+        delete c;
+        return fail(nullptr, e);
+    };
+    for (auto& e : c->ev)
+        if (hipEventCreate(&e) != hipSuccess) {
+            st.code = DD_EDEVICE;
+            st.msg = "domdec_init: hipEventCreate failed";
+            return bail(st);
+        }
+    const int n = c->n, AS = c->AS;
+    // basic cell masses (pixel order inside the block, row-major)
+    c->m.assign(c->nI, 0.0);
+    for (int r = 0; r < n; ++r)
+        for (int q = 0; q < n; ++q) {
+            double t = 0.0;
+            for (int a = 0; a < s; ++a)
+                for (int b = 0; b < s; ++b) t += mu[(int64_t)(r * s + a) * N + (q * s + b)];
+            c->m[r * n + q] = t;
+            if (!(t > 0.0)) {
+                st.code = DD_EINVAL;
+                st.msg = "domdec_init: every basic cell needs positive mass";
+                return bail(st);
+            }
+        }
+    // partitions
+    for (int q = 0; q < 2; ++q) {
+        const int nc = q == 0 ? n / 2 : n / 2 + 1;
+        const int off = q == 0 ? 0 : -1;
+        std::vector<int32_t> mem, xo;
+        std::vector<double> lm;
+        for (int R = 0; R < nc; ++R)
+            for (int Cc = 0; Cc < nc; ++Cc) {
+                for (int dr = 0; dr < 2; ++dr)
+                    for (int dc = 0; dc < 2; ++dc) {
+                        const int r = 2 * R + off + dr, cc = 2 * Cc + off + dc;
+                        mem.push_back((r >= 0 && r < n && cc >= 0 && cc < n) ? r * n + cc : -1);
+                    }
+                const int p1 = (2 * R + off) * s, p2 = (2 * Cc + off) * s;
+                xo.push_back(p1);
+                xo.push_back(p2);
+                for (int i1 = 0; i1 < AS; ++i1)
+                    for (int i2 = 0; i2 < AS; ++i2) {
+                        const int k1 = p1 + i1, k2 = p2 + i2;
+                        double v = kNegD;
+                        if (k1 >= 0 && k1 < N && k2 >= 0 && k2 < N && mu[(int64_t)k1 * N + k2] > 0)
+                            v = std::log(mu[(int64_t)k1 * N + k2]);
+                        lm.push_back(v);
+                    }
+            }
+        c->part[q].ncell = nc * nc;
+        c->pmembers[q] = mem;
+        c->pxorig[q] = xo;
+        if (upload(c->part[q].members, mem, hs, st).code) return bail(st);
+        if (upload(c->part[q].xorig, xo, hs, st).code) return bail(st);
+        double* plm = nullptr;
+        if (upload(plm, lm, hs, st).code) return bail(st);
+        c->d_logmu[q] = plm;
+        double* pa = nullptr;
+        if (upload(pa, std::vector<double>(lm.size(), 0.0), hs, st).code) return bail(st);
+        c->d_a[q] = pa;
+        if (upload(c->d_gst[q], std::vector<int32_t>(2 * (size_t)nc * nc, 0), hs, st).code)
+            return bail(st);
+    }
+    // initial basic-cell Y-marginals in bounding-box form
+    std::vector<int32_t> box(4 * (size_t)c->nI);
+    std::vector<int64_t> base(c->nI + 1, 0);
+    std::vector<double> data;
+    if (n_init == 0) {
+        int lo1 = N, lo2 = N, hi1 = -1, hi2 = -1;
+        for (int k1 = 0; k1 < N; ++k1)
+            for (int k2 = 0; k2 < N; ++k2)
+                if (nu[(int64_t)k1 * N + k2] > 0) {
+                    lo1 = std::min(lo1, k1);
+                    hi1 = std::max(hi1, k1);
+                    lo2 = std::min(lo2, k2);
+                    hi2 = std::max(hi2, k2);
+                }
+        const int64_t w1 = hi1 - lo1 + 1, w2 = hi2 - lo2 + 1;
+        if ((double)w1 * w2 * c->nI > 4.0e8) {
+            st.code = DD_ENOMEM;
+            st.msg = "domdec_init: the product coupling is too large here; pass a sparse init";
+            return bail(st);
+        }
+        data.resize((size_t)(w1 * w2 * c->nI));
+        for (int i = 0; i < c->nI; ++i) {
+            box[4 * i] = lo1;
+            box[4 * i + 1] = lo2;
+            box[4 * i + 2] = (int32_t)w1;
+            box[4 * i + 3] = (int32_t)w2;
+            base[i + 1] = base[i] + w1 * w2;
+            for (int64_t r = 0; r < w1; ++r)
+                for (int64_t q = 0; q < w2; ++q)
+                    data[base[i] + r * w2 + q] = c->m[i] * nu[(lo1 + r) * N + (lo2 + q)];
+        }
+    } else {
+        std::vector<double> px(NN, 0.0), py(NN, 0.0);
+        std::vector<int32_t> cell(n_init);
+        std::vector<int64_t> cnt(c->nI + 1, 0);
+        for (int64_t e = 0; e < n_init; ++e) {
+            const int64_t x = init_x[e], y = init_y[e];
+            if (x < 0 || x >= NN || y < 0 || y >= NN || !(init_m[e] >= 0.0)) {
+                st.code = DD_EINVAL;
+                st.msg = "domdec_init: initial coupling entry out of range or negative";
+                return bail(st);
+            }
+            px[x] += init_m[e];
+            py[y] += init_m[e];
+            const int k1 = (int)(x / N), k2 = (int)(x % N);
+            cell[e] = (k1 / s) * n + (k2 / s);
+            cnt[cell[e] + 1]++;
+        }
+        for (int64_t k = 0; k < NN; ++k)
+            if (std::fabs(px[k] - mu[k]) > 1e-12 || std::fabs(py[k] - nu[k]) > 1e-12) {
+                st.code = DD_EINVAL;
+                st.msg = "domdec_init: the initial coupling's marginals differ from mu, nu";
+                return bail(st);
+            }
+        for (int i = 0; i < c->nI; ++i) cnt[i + 1] += cnt[i];
+        std::vector<int64_t> order(n_init), fill(cnt.begin(), cnt.end() - 1);
+        for (int64_t e = 0; e < n_init; ++e) order[fill[cell[e]]++] = e;
+        for (int i = 0; i < c->nI; ++i) {
+            int lo1 = N, lo2 = N, hi1 = -1, hi2 = -1;
+            for (int64_t q = cnt[i]; q < cnt[i + 1]; ++q) {
+                const int64_t y = init_y[order[q]];
+                const int y1 = (int)(y / N), y2 = (int)(y % N);
+                lo1 = std::min(lo1, y1);
+                hi1 = std::max(hi1, y1);
+                lo2 = std::min(lo2, y2);
+                hi2 = std::max(hi2, y2);
+            }
+            if (hi1 < 0) {
+                st.code = DD_EINVAL;
+                st.msg = "domdec_init: a basic cell has no mass in the initial coupling";
+                return bail(st);
+            }
+            const int w1 = hi1 - lo1 + 1, w2 = hi2 - lo2 + 1;
+            box[4 * i] = lo1;
+            box[4 * i + 1] = lo2;
+            box[4 * i + 2] = w1;
+            box[4 * i + 3] = w2;
+            base[i + 1] = base[i] + (int64_t)w1 * w2;
+        }
+        data.assign((size_t)base[c->nI], 0.0);
+        for (int i = 0; i < c->nI; ++i)
+            for (int64_t q = cnt[i]; q < cnt[i + 1]; ++q) {
+                const int64_t e = order[q];
+                const int y1 = (int)(init_y[e] / N), y2 = (int)(init_y[e] % N);
+                data[base[i] + (int64_t)(y1 - box[4 * i]) * box[4 * i + 3] + (y2 - box[4 * i + 1])] +=
+                    init_m[e];
+            }
+    }
+    std::vector<double> vmu(mu, mu + NN), vnu(nu, nu + NN), lnu(NN);
+    for (int64_t k = 0; k < NN; ++k) lnu[k] = nu[k] > 0 ? std::log(nu[k]) : -INFINITY;
+    if (upload(c->d_mu, vmu, hs, st).code || upload(c->d_nu, vnu, hs, st).code ||
+        upload(c->d_lognu_glob, lnu, hs, st).code || upload(c->d_m, c->m, hs, st).code ||
+        upload(c->S.box, box, hs, st).code || upload(c->S.base, base, hs, st).code ||
+        upload(c->S.data, data, hs, st).code)
+        return bail(st);
+    c->S.cap = std::max<size_t>(data.size(), 1);
+    const int mc = std::max(c->part[0].ncell, c->part[1].ncell);
+    if (alloc(c->S2.box, 4 * (size_t)c->nI, st).code || alloc(c->S2.base, c->nI + 1, st).code ||
+        alloc(c->C.dims, 2 * (size_t)mc, st).code || alloc(c->C.orig, 2 * (size_t)mc, st).code ||
+        alloc(c->C.shift, 2 * (size_t)mc, st).code || alloc(c->C.gofs, 2 * (size_t)mc, st).code ||
+        alloc(c->C.size, mc, st).code || alloc(c->C.base, mc + 1, st).code ||
+        alloc(c->C.info, 8, st).code || alloc(c->d_py2, c->nI, st).code ||
+        alloc(c->d_nsize, c->nI, st).code || alloc(c->d_flags, c->nI + 1, st).code ||
+        alloc(c->d_iters, mc, st).code || alloc(c->d_cerr, mc, st).code ||
+        alloc(c->d_scratch, std::max<int64_t>(NN, c->nI), st).code ||
+        alloc(c->d_cell_out, 4 * (size_t)mc, st).code ||
+        alloc(c->d_basic_out, 3 * (size_t)c->nI, st).code || alloc(c->d_eval, 8, st).code)
+        return bail(st);
+    if (hipStreamSynchronize(hs) != hipSuccess) {
+        st.code = DD_EDEVICE;
+        st.msg = "domdec_init: stream synchronisation failed";
+        return bail(st);
+    }
+    *out = c;
+    return DD_OK;
+}
+
+static dd_status iterate_impl(dd_ctx* c, int p, double eps, const dd_sinkhorn_opts& o,
+                              dd_iter_stats* out) {
+    Status st;
+    const hipStream_t hs = c->st;
+    PartDev& P = c->part[p];
+    const int nc = P.ncell;
+    const double kappa = eps / (c->h * c->h);
+    (void)hipEventRecord(c->ev[0], hs);
+    launch_comp_boxes(P, c->S, c->AS, c->C, hs);
+    launch_scan(c->C.size, c->C.base, nc, hs);
+    launch_comp_max(c->C, nc, hs);
+    int32_t info[2];
+    int64_t total = 0;
+    if (hipMemcpyAsync(info, c->C.info, sizeof info, hipMemcpyDeviceToHost, hs) != hipSuccess ||
+        hipMemcpyAsync(&total, c->C.base + nc, sizeof total, hipMemcpyDeviceToHost, hs) !=
+            hipSuccess ||
+        hipStreamSynchronize(hs) != hipSuccess)
+        return fail(c, DD_EDEVICE, "domdec_iterate: reading composite sizes failed");
+    const int mw1 = info[0], mw2 = info[1];
+    if (!sk_lds_bytes(c->AS, mw1, mw2, c->prec))
+        return fail(c, DD_ENOMEM,
+                    "domdec_iterate: a composite Y box (" + std::to_string(mw1) + "x" +
+                        std::to_string(mw2) + ") exceeds one workgroup's LDS");
+    if (grow(c->d_nuJ, c->nuJ_cap, (size_t)total, st).code ||
+        grow(c->d_lognu, c->lognu_cap, (size_t)total, st).code ||
+        grow(c->d_b, c->b_cap, (size_t)total, st).code ||
+        grow(c->d_tmp, c->tmp_cap, 4 * (size_t)total, st).code)
+        return fail(c, st);
+    double* lognu = c->d_lognu;
+    double* bpot = c->d_b;
+    double* apot = c->d_a[p];
+    const double* logmu = c->d_logmu[p];
+    launch_b2c(P, c->S, c->C, c->d_nuJ, lognu, hs);
+    (void)hipEventRecord(c->ev[1], hs);
+    const int use_prev = (o.init == DD_INIT_PREV && c->visited[p]) ? 1 : 0;
+    launch_warm_start(P, c->C, c->AS, apot, c->d_gst[p], c->kappa_a[p], kappa, use_prev, hs);
+    SkBatch B;
+    B.ncells = nc;
+    B.xside = c->AS;
+    B.dims = c->C.dims;
+    B.base = c->C.base;
+    B.shift = c->C.shift;
+    B.logmu = logmu;
+    B.lognu = lognu;
+    B.a = apot;
+    B.b = bpot;
+    B.kappa = kappa;
+    B.max_w1 = mw1;
+    B.max_w2 = mw2;
+    B.prec = c->prec;
+    dd_batch_stats bs{};
+    const Status ss = sk_solve(B, o, hs, c->skw, &bs, c->d_iters, c->d_cerr);
+    if (ss.code != DD_OK && ss.code != DD_NOTCONV) return fail(c, ss);
+    c->visited[p] = true;
+    c->kappa_a[p] = kappa;
+    (void)hipEventRecord(c->ev[2], hs);
+    launch_c2b(P, c->C, c->AS, c->s, mw2, apot, logmu, c->d_nuJ, kappa, c->h, c->d_tmp, c->d_py2,
+               hs);
+    launch_balance(P, c->C, c->d_m, c->d_tmp, hs);
+    launch_fill_i32(c->d_flags, c->nI + 1, 0, hs);
+    launch_trunc_boxes(P, c->C, c->d_tmp, c->trunc, c->nI, c->S2.box, c->d_nsize, c->d_flags, hs);
+    launch_scan(c->d_nsize, c->S2.base, c->nI, hs);
+    int64_t ntot = 0;
+    int32_t kept = 0;
+    if (hipMemcpyAsync(&ntot, c->S2.base + c->nI, sizeof ntot, hipMemcpyDeviceToHost, hs) !=
+            hipSuccess ||
+        hipMemcpyAsync(&kept, c->d_flags + c->nI, sizeof kept, hipMemcpyDeviceToHost, hs) !=
+            hipSuccess ||
+        hipStreamSynchronize(hs) != hipSuccess)
+        return fail(c, DD_EDEVICE, "domdec_iterate: reading truncated sizes failed");
+    if (grow(c->S2.data, c->S2.cap, (size_t)ntot, st).code) return fail(c, st);
+    launch_compact(P, c->C, c->d_tmp, c->trunc, c->S2.box, c->S2.base, c->d_flags, c->S2.data, hs);
+    std::swap(c->S, c->S2);
+    (void)hipEventRecord(c->ev[3], hs);
+    if (hipStreamSynchronize(hs) != hipSuccess || hipGetLastError() != hipSuccess)
+        return fail(c, DD_EDEVICE, "domdec_iterate: a kernel failed");
+    c->last_part = p;
+    c->last_eps = eps;
+    c->last_mw1 = mw1;
+    c->last_mw2 = mw2;
+    c->untruncated_cells = kept;
+    if (out) {
+        dd_iter_stats s{};
+        s.sk = bs;
+        s.partition = p;
+        s.max_w1 = mw1;
+        s.max_w2 = mw2;
+        s.nu_entries = ntot;
+        s.comp_entries = total;
+        float t = 0.f;
+        (void)hipEventElapsedTime(&t, c->ev[0], c->ev[1]);
+        s.t_b2c_ms = t;
+        s.t_sinkhorn_ms = bs.time_ms;
+        (void)hipEventElapsedTime(&t, c->ev[2], c->ev[3]);
+        s.t_c2b_ms = t;
+        (void)hipEventElapsedTime(&t, c->ev[0], c->ev[3]);
+        s.t_total_ms = t;
+        *out = s;
+    }
+    if (ss.code == DD_NOTCONV) {
+        c->err = ss.msg;
+        return DD_NOTCONV;
+    }
+    return DD_OK;
+}
+
+extern "C" dd_status domdec_iterate(dd_ctx* c, int32_t partition, double eps,
+                                    const dd_sinkhorn_opts* o, dd_iter_stats* out) {
+    if (!c || !o) return fail(c, DD_EINVAL, "domdec_iterate: null argument");
+    if (partition != DD_PART_A && partition != DD_PART_B)
+        return fail(c, DD_EINVAL, "domdec_iterate: partition must be DD_PART_A or DD_PART_B");
+    if (!(eps > 0.0) || !std::isfinite(eps))
+        return fail(c, DD_EINVAL, "domdec_iterate: eps must be positive and finite");
+    if (o->init != DD_INIT_ZERO && o->init != DD_INIT_PREV)
+        return fail(c, DD_EINVAL, "domdec_iterate: init must be DD_INIT_ZERO or DD_INIT_PREV");
+    return iterate_impl(c, partition, eps, *o, out);
+}
+
+extern "C" dd_status extract_plan(dd_ctx* c, dd_plan_view* v) {
+    if (!c || !v) return fail(c, DD_EINVAL, "extract_plan: null argument");
+    int64_t total = 0;
+    if (hipMemcpyAsync(&total, c->S.base + c->nI, sizeof total, hipMemcpyDeviceToHost, c->st) !=
+            hipSuccess ||
+        hipStreamSynchronize(c->st) != hipSuccess)
+        return fail(c, DD_EDEVICE, "extract_plan: copy failed");
+    v->n_cells = c->nI;
+    v->n_entries = total;
+    if (!v->offsets && !v->dims && !v->base && !v->data) return DD_OK;
+    std::vector<int32_t> box(4 * (size_t)c->nI);
+    if (hipMemcpyAsync(box.data(), c->S.box, box.size() * 4, hipMemcpyDeviceToHost, c->st) !=
+            hipSuccess ||
+        (v->base && hipMemcpyAsync(v->base, c->S.base, (c->nI + 1) * sizeof(int64_t),
+                                   hipMemcpyDeviceToHost, c->st) != hipSuccess) ||
+        (v->data && total > 0 &&
+         hipMemcpyAsync(v->data, c->S.data, total * sizeof(double), hipMemcpyDeviceToHost, c->st) !=
+             hipSuccess) ||
+        hipStreamSynchronize(c->st) != hipSuccess)
+        return fail(c, DD_EDEVICE, "extract_plan: copy failed");
+    for (int i = 0; i < c->nI; ++i) {
+        if (v->offsets) {
+            v->offsets[2 * i] = box[4 * i];
+            v->offsets[2 * i + 1] = box[4 * i + 1];
+        }
+        if (v->dims) {
+            v->dims[2 * i] = box[4 * i + 2];
+            v->dims[2 * i + 1] = box[4 * i + 3];
+        }
+    }
+    return DD_OK;
+}
+
+void dd_eval_cells(dd_ctx* c) {
+    const int p = c->last_part;
+    EvalArgs e;
+    e.ncell = c->part[p].ncell;
+    e.xside = c->AS;
+    e.s = c->s;
+    e.maxw1 = c->last_mw1;
+    e.maxw2 = c->last_mw2;
+    e.N = c->N;
+    e.members = c->part[p].members;
+    e.xorig = c->part[p].xorig;
+    e.cdims = c->C.dims;
+    e.corig = c->C.orig;
+    e.cshift = c->C.shift;
+    e.gofs = c->C.gofs;
+    e.cbase = c->C.base;
+    e.logmu = c->d_logmu[p];
+    e.a = c->d_a[p];
+    e.b = c->d_b;
+    e.lognuJ = c->d_lognu;
+    e.nuJ = c->d_nuJ;
+    e.lognu_glob = c->d_lognu_glob;
+    e.kappa = c->last_eps / (c->h * c->h);
+    e.cell_out = c->d_cell_out;
+    e.basic_out = c->d_basic_out;
+    e.totals = c->d_eval + 4;
+    launch_cell_eval(e, c->st);
+}
+
+extern "C" dd_status domdec_evaluate(dd_ctx* c, dd_eval* out) {
+    if (!c || !out) return fail(c, DD_EINVAL, "domdec_evaluate: null argument");
+    dd_eval r{};
+    launch_ymarg(c->nI, c->S.box, c->S.base, c->S.data, c->N, c->d_scratch, c->d_nu, c->d_eval,
+                 c->st);
+    launch_basic_mass(c->nI, c->S.base, c->S.data, c->d_m, c->d_scratch, c->d_eval + 1, c->st);
+    if (c->last_part >= 0) dd_eval_cells(c);
+    double h[8] = {0};
+    if (hipMemcpyAsync(h, c->d_eval, sizeof h, hipMemcpyDeviceToHost, c->st) != hipSuccess ||
+        hipStreamSynchronize(c->st) != hipSuccess)
+        return fail(c, DD_EDEVICE, "domdec_evaluate: reduction failed");
+    r.y_marginal_l1 = h[0];
+    r.total_mass = h[1];
+    r.basic_mass_err = h[2];
+    if (c->last_part >= 0) {
+        const double eps = c->last_eps;
+        r.primal = eps * h[4] + eps * 1.0;  // + eps * (sum mu)(sum nu), the KL reference mass
+        r.transport = h[5] * c->h * c->h;
+        r.x_marginal_l1 = h[6];
+    } else {
+        r.primal = r.transport = r.x_marginal_l1 = NAN;
+    }
+    *out = r;
+    return DD_OK;
+}
+
+extern "C" void domdec_free(dd_ctx* c) {
+    if (!c) return;
+    (void)hipStreamSynchronize(c->st);
+    dd_ctx_release(c);
+    delete c;
+}
+
+extern "C" const char* domdec_strerror(const dd_ctx* c, dd_status) {
+    return c ? c->err.c_str() : global_error();
+}

@@ -1,0 +1,63 @@
+// The domain-decomposition context (opaque dd_ctx of the C ABI).
+#pragma once
+
+#include <string>
+#include <vector>
+
+#include "cells.hpp"
+#include "sinkhorn.hpp"
+
+struct FlowState;
+
+struct dd_ctx {
+    // problem
+    int N = 0, s = 0, n = 0, nI = 0, AS = 0, prec = DD_PREC_F32;
+    double h = 0.0, trunc = 1e-15;
+    hipStream_t st = nullptr;
+    std::string err;
+    std::vector<double> m;  // basic cell masses (host copy)
+    std::vector<int32_t> pmembers[2], pxorig[2];
+    double* d_mu = nullptr;
+    double* d_nu = nullptr;
+    double* d_lognu_glob = nullptr;
+    double* d_m = nullptr;
+    // partitions and their persistent X potentials (warm start)
+    dd::PartDev part[2];
+    double* d_logmu[2] = {nullptr, nullptr};
+    double* d_a[2] = {nullptr, nullptr};
+    int32_t* d_gst[2] = {nullptr, nullptr};
+    bool visited[2] = {false, false};
+    double kappa_a[2] = {1.0, 1.0};
+    // state
+    dd::BoxSet S, S2;
+    // composite work of the current / last iteration
+    dd::CompDev C;
+    double* d_nuJ = nullptr;
+    size_t nuJ_cap = 0;
+    double* d_lognu = nullptr;
+    size_t lognu_cap = 0;
+    double* d_b = nullptr;
+    size_t b_cap = 0;
+    double* d_tmp = nullptr;
+    size_t tmp_cap = 0;
+    double* d_py2 = nullptr;
+    int64_t* d_nsize = nullptr;
+    int32_t* d_flags = nullptr;
+    int32_t* d_iters = nullptr;
+    double* d_cerr = nullptr;
+    double* d_scratch = nullptr;
+    double* d_cell_out = nullptr;
+    double* d_basic_out = nullptr;
+    double* d_eval = nullptr;
+    dd::SkWork skw;
+    hipEvent_t ev[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+    int last_part = -1;
+    double last_eps = 0.0;
+    int last_mw1 = 0, last_mw2 = 0;
+    int untruncated_cells = 0;
+    FlowState* flow = nullptr;
+};
+
+void dd_ctx_release(dd_ctx* c);
+void dd_eval_cells(dd_ctx* c);
+void flow_release(dd_ctx* c);

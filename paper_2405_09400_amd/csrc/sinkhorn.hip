@@ -1,0 +1,861 @@
+// Batched separable log-domain cell Sinkhorn for gfx950.
+//
+// The cell problem and its Sinkhorn iteration are those of Alg. "DomDecIter",
+// solved in the log domain with the cost evaluated online and split into one 1D
+// log-sum-exp pass per axis (App. A.1 "Custom CUDA Sinkhorn").  Potentials are
+// f = alpha/eps and g = beta/eps with reference measure mu_J (x) nu_J (equal to the
+// paper's mu_J (x) nu up to a constant, Sec. 2.3): pi = mu nu_J exp(f + g - C).
+//
+// Precision: the log-sum-exp terms run in T (float32 for sinkhorn_batch, float64
+// for sinkhorn_batch_f64).  Every 1D pass works on values shifted by a float64
+// maximum of their input line, so each float32 term is O(1) no matter how large
+// log mu, log nu_J or the potentials are; the line offsets, the potentials f and g,
+// the marginal error and the masses are float64.  This is what lets float32 reach a
+// marginal tolerance of 1e-5 (the paper saw plain float32 stall, App. A.2.1).
+//
+// Mapping to the hardware: one workgroup (4 wave64s) owns one cell at a time with
+// the whole cell -- f, log mu, the Y box of log nu_J and g, the shifted per-axis
+// intermediates -- resident in LDS (up to 160 KB per workgroup on gfx950).  Each
+// 1D pass gives one output per lane and walks its short reduction line from LDS
+// (max pass, then exp-sum pass).  Row maxima and the float64 error / mass sums are
+// wave64 shuffle reductions.
+//
+// Two drivers:
+//   * per-cell stopping or a fixed iteration count: a persistent kernel pulls
+//     cells from an atomic work queue (in the given order, largest box first when
+//     the caller sorts) and iterates each to its own stop inside LDS -- no HBM
+//     traffic and no grid-wide synchronisation between iterations;
+//   * the paper's batch rule (App. A.2.1): one launch per iteration that reads f
+//     from one buffer and writes the next f into the other, and ends with a
+//     last-workgroup float64 reduction of the per-cell errors in fixed cell order
+//     that sets a device-side stop flag; later launches exit at once.  The host
+//     polls the flag every `check_every` launches, which changes only how many
+//     no-op launches trail the stop, never the result.
+#include "sinkhorn.hpp"
+
+#include <algorithm>
+#include <cmath>
+#include <vector>
+
+namespace dd {
+
+namespace {
+thread_local std::string g_err;
+}
+void set_global_error(const std::string& m) { g_err = m; }
+const char* global_error() { return g_err.c_str(); }
+
+constexpr int kThreads = 256;
+
+namespace {
+
+// LSE_{k<K} ( in[k*stride] - (k - q + e)^2 * invk ), max-shifted, two passes.
+template <typename T>
+__device__ __forceinline__ T lse_line(const T* __restrict__ in, int stride, int K, int q, int e,
+                                      T invk) {
+    T d = T(e - q);
+    T m = in[0] - d * d * invk;
+    for (int k = 1; k < K; ++k) {
+        d = T(k - q + e);
+        const T v = in[k * stride] - d * d * invk;
+        m = v > m ? v : m;
+    }
+    T s = T(0);
+    for (int k = 0; k < K; ++k) {
+        d = T(k - q + e);
+        s += fexp(in[k * stride] - d * d * invk - m);
+    }
+    return m + flog(s);
+}
+
+// Same with an additive per-k shift sh[k] (the float offsets of the input lines).
+template <typename T>
+__device__ __forceinline__ T lse_line_sh(const T* __restrict__ in, int stride, int K, int q,
+                                         int e, T invk, const T* __restrict__ sh) {
+    T d = T(e - q);
+    T m = in[0] + sh[0] - d * d * invk;
+    for (int k = 1; k < K; ++k) {
+        d = T(k - q + e);
+        const T v = in[k * stride] + sh[k] - d * d * invk;
+        m = v > m ? v : m;
+    }
+    T s = T(0);
+    for (int k = 0; k < K; ++k) {
+        d = T(k - q + e);
+        s += fexp(in[k * stride] + sh[k] - d * d * invk - m);
+    }
+    return m + flog(s);
+}
+
+__device__ __forceinline__ double wave_max_d(double v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
+    return v;
+}
+
+template <typename T>
+struct Lds {
+    double* f;    // [N2]          X potential f
+    double* lm;   // [N2]          log mu
+    double* s;    // [N2]          LSE_j (g + log nu_J - C)
+    double* ry;   // [AS]          row maxima of f + log mu
+    double* qx;   // [mw1]         row maxima of g + log nu_J (full offsets)
+    double* ln;   // [mw1][W2p]    log nu_J
+    double* red;  // [16]          reductions; [8] = R, [9] = Q
+    T* wq;        // [N2]          f + log mu - ry(row)
+    T* rhoy;      // [AS]          ry - R
+    T* t1;        // [AS][W2p]     Y-half intermediate, relative to ry
+    T* gq;        // [mw1][W2p]    g + R (g = gq - R)
+    T* zq;        // [mw1][W2p]    g + log nu_J - qx(row)
+    T* kq;        // [mw1]         qx - Q
+    T* u;         // [mw1][ASp]    X-half intermediate, relative to qx
+    int W2p, ASp;
+    int ys;       // row stride of ln / gq / zq (W2p in LDS, W2 in global memory)
+};
+
+__host__ __device__ inline size_t lds_layout_bytes(int AS, int mw1, int mw2, size_t elem) {
+    const size_t W2p = (size_t)mw2 + 1, ASp = (size_t)AS + 1, N2 = (size_t)AS * AS;
+    const size_t nd = 3 * N2 + AS + mw1 + (size_t)mw1 * W2p + 16;
+    const size_t nt = N2 + AS + AS * W2p + 2 * (size_t)mw1 * W2p + mw1 + (size_t)mw1 * ASp;
+    return 8 * nd + elem * nt + 16;
+}
+
+template <typename T>
+__device__ __forceinline__ Lds<T> carve(char* base, int AS, int mw1, int mw2) {
+    Lds<T> L;
+    L.W2p = mw2 + 1;
+    L.ASp = AS + 1;
+    const int N2 = AS * AS;
+    double* d = reinterpret_cast<double*>(base);
+    L.red = d;
+    d += 16;
+    L.f = d;
+    d += N2;
+    L.lm = d;
+    d += N2;
+    L.s = d;
+    d += N2;
+    L.ry = d;
+    d += AS;
+    L.qx = d;
+    d += mw1;
+    L.ln = d;
+    d += (size_t)mw1 * L.W2p;
+    T* t = reinterpret_cast<T*>(d);
+    L.wq = t;
+    t += N2;
+    L.rhoy = t;
+    t += AS;
+    L.t1 = t;
+    t += AS * L.W2p;
+    L.gq = t;
+    t += mw1 * L.W2p;
+    L.zq = t;
+    t += mw1 * L.W2p;
+    L.kq = t;
+    t += mw1;
+    L.u = t;
+    return L;
+}
+
+// Large-box mode keeps ln, gq and zq of the current cell in global memory (read through
+// L1/L2) and only the per-line arrays in LDS.  The layout code below is shared.
+template <bool BIG>
+__host__ __device__ inline size_t lds_bytes_mode(int AS, int mw1, int mw2, size_t elem) {
+    if (!BIG) return lds_layout_bytes(AS, mw1, mw2, elem);
+    const size_t W2p = (size_t)mw2 + 1, ASp = (size_t)AS + 1, N2 = (size_t)AS * AS;
+    const size_t nd = 3 * N2 + AS + mw1 + 16;
+    const size_t nt = N2 + AS + AS * W2p + mw1 + (size_t)mw1 * ASp;
+    return 8 * nd + elem * nt + 16;
+}
+
+template <typename T, bool BIG>
+__device__ __forceinline__ Lds<T> carve_mode(char* base, int AS, int mw1, int mw2) {
+    if (!BIG) {
+        Lds<T> L = carve<T>(base, AS, mw1, mw2);
+        L.ys = L.W2p;
+        return L;
+    }
+    Lds<T> L;
+    L.W2p = mw2 + 1;
+    L.ASp = AS + 1;
+    const int N2 = AS * AS;
+    double* d = reinterpret_cast<double*>(base);
+    L.red = d;
+    d += 16;
+    L.f = d;
+    d += N2;
+    L.lm = d;
+    d += N2;
+    L.s = d;
+    d += N2;
+    L.ry = d;
+    d += AS;
+    L.qx = d;
+    d += mw1;
+    L.ln = nullptr;
+    T* t = reinterpret_cast<T*>(d);
+    L.wq = t;
+    t += N2;
+    L.rhoy = t;
+    t += AS;
+    L.t1 = t;
+    t += AS * L.W2p;
+    L.gq = nullptr;
+    L.zq = nullptr;
+    L.kq = t;
+    t += mw1;
+    L.u = t;
+    L.ys = 0;
+    return L;
+}
+
+// Y-update g(j) = -LSE_i [f(i) + log mu(i) - C(i,j)], as two 1D passes over shifted values.
+// Leaves gq (g = gq - R, R in red[8]).
+template <typename T>
+__device__ __forceinline__ void y_half(const Lds<T>& L, int AS, int W1, int W2, int E1, int E2,
+                                       T invk) {
+    const int N2 = AS * AS;
+    if (threadIdx.x < AS) {
+        const int i1 = threadIdx.x;
+        double r = L.f[i1 * AS] + L.lm[i1 * AS];
+        for (int i2 = 1; i2 < AS; ++i2) r = fmax(r, L.f[i1 * AS + i2] + L.lm[i1 * AS + i2]);
+        L.ry[i1] = r;
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < N2; i += blockDim.x) L.wq[i] = (T)(L.f[i] + L.lm[i] - L.ry[i / AS]);
+    if (threadIdx.x == 0) {
+        double R = L.ry[0];
+        for (int i1 = 1; i1 < AS; ++i1) R = fmax(R, L.ry[i1]);
+        L.red[8] = R;
+        for (int i1 = 0; i1 < AS; ++i1) L.rhoy[i1] = (T)(L.ry[i1] - R);
+    }
+    __syncthreads();
+    for (int o = threadIdx.x; o < AS * W2; o += blockDim.x) {
+        const int i1 = o / W2, j2 = o - i1 * W2;
+        L.t1[i1 * L.W2p + j2] = lse_line(L.wq + i1 * AS, 1, AS, j2, E2, invk);
+    }
+    __syncthreads();
+    for (int o = threadIdx.x; o < W1 * W2; o += blockDim.x) {
+        const int j1 = o / W2, j2 = o - j1 * W2;
+        L.gq[j1 * L.ys + j2] = -lse_line_sh(L.t1 + j2, L.W2p, AS, j1, E1, invk, L.rhoy);
+    }
+    __syncthreads();
+}
+
+// s(i) = LSE_j [g(j) + log nu_J(j) - C(i,j)] (float64 result), as two 1D passes over shifted
+// values (cost (i - j + E)^2 = (j - i - E)^2).
+template <typename T>
+__device__ __forceinline__ void x_half(const Lds<T>& L, int AS, int W1, int W2, int E1, int E2,
+                                       T invk) {
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    const double goff = -L.red[8];
+    for (int j1 = wid; j1 < W1; j1 += nw) {
+        double m = -1e300;
+        for (int j2 = lane; j2 < W2; j2 += 64)
+            m = fmax(m, (double)L.gq[j1 * L.ys + j2] + L.ln[j1 * L.ys + j2]);
+        m = wave_max_d(m);
+        for (int j2 = lane; j2 < W2; j2 += 64)
+            L.zq[j1 * L.ys + j2] = (T)((double)L.gq[j1 * L.ys + j2] + L.ln[j1 * L.ys + j2] - m);
+        if (lane == 0) L.qx[j1] = m + goff;
+    }
+    __syncthreads();
+    if (wid == 0) {
+        double Q = -1e300;
+        for (int j1 = lane; j1 < W1; j1 += 64) Q = fmax(Q, L.qx[j1]);
+        Q = wave_max_d(Q);
+        for (int j1 = lane; j1 < W1; j1 += 64) L.kq[j1] = (T)(L.qx[j1] - Q);
+        if (lane == 0) L.red[9] = Q;
+    }
+    for (int o = threadIdx.x; o < W1 * AS; o += blockDim.x) {
+        const int j1 = o / AS, i2 = o - j1 * AS;
+        L.u[j1 * L.ASp + i2] = lse_line(L.zq + j1 * L.ys, 1, W2, i2, -E2, invk);
+    }
+    __syncthreads();
+    const double Q = L.red[9];
+    for (int o = threadIdx.x; o < AS * AS; o += blockDim.x) {
+        const int i1 = o / AS, i2 = o - i1 * AS;
+        L.s[o] = Q + (double)lse_line_sh(L.u + i2, L.ASp, W1, i1, -E1, invk, L.kq);
+    }
+    __syncthreads();
+}
+
+// X-marginal L1 error sum_i mu |exp(f + s) - 1| and mass sum_i mu, float64.
+template <typename T>
+__device__ __forceinline__ void err_mass(const Lds<T>& L, int AS, double& err, double& mass) {
+    double e = 0.0, m = 0.0;
+    for (int i = threadIdx.x; i < AS * AS; i += blockDim.x) {
+        const double lm = L.lm[i];
+        if (lm > kZeroMassLog) {
+            const double mu = exp(lm);
+            e += mu * fabs(expm1(L.f[i] + L.s[i]));
+            m += mu;
+        }
+    }
+    err = block_sum(e, L.red);
+    mass = block_sum(m, L.red);
+}
+
+// Load one cell: f and log mu into LDS; log nu_J into LDS (or bind it in global memory in
+// large-box mode, where gq / zq live in a per-cell global scratch at the cell's Y offset).
+template <typename T, bool BIG>
+__device__ __forceinline__ void load_cell(const SkBatch& p, Lds<T>& L, const double* f_src,
+                                          int c, int W1, int W2, int64_t base, T* big_scratch) {
+    const int N2 = p.xside * p.xside;
+    // zero-mass points carry the log-domain sentinel in log mu / log nu_J, which removes
+    // them from every sum whatever their potential
+    for (int i = threadIdx.x; i < N2; i += blockDim.x) {
+        L.lm[i] = p.logmu[(int64_t)c * N2 + i];
+        L.f[i] = f_src[(int64_t)c * N2 + i];
+    }
+    if (BIG) {
+        L.ln = const_cast<double*>(p.lognu) + base;
+        L.gq = big_scratch + 2 * base;
+        L.zq = big_scratch + 2 * base + (int64_t)W1 * W2;
+        L.ys = W2;
+    } else {
+        for (int o = threadIdx.x; o < W1 * W2; o += blockDim.x) {
+            const int j1 = o / W2, j2 = o - j1 * W2;
+            L.ln[j1 * L.ys + j2] = p.lognu[base + o];
+        }
+    }
+    __syncthreads();
+}
+
+template <typename T>
+__device__ __forceinline__ void store_g(const SkBatch& p, const Lds<T>& L, int W1, int W2,
+                                        int64_t base) {
+    const double goff = -L.red[8];
+    for (int o = threadIdx.x; o < W1 * W2; o += blockDim.x) {
+        const int j1 = o / W2, j2 = o - j1 * W2;
+        p.b[base + o] = (double)L.gq[j1 * L.ys + j2] + goff;
+    }
+}
+
+// ctrl words: [0] work queue, [1] ticket, [2] done iteration, [3] bad-dims flag, [4] converged
+__global__ void zero_ints(int* p, int n) {
+    for (int i = threadIdx.x; i < n; i += blockDim.x) p[i] = 0;
+}
+
+template <typename T, bool BIG>
+__global__ void __launch_bounds__(kThreads)
+    sk_cell_kernel(SkBatch p, double tol, int limit, int fixed, int* ctrl, int32_t* iters_out,
+                   double* err_out, double* mass_out, T* big_scratch) {
+    extern __shared__ __align__(16) char smem[];
+    __shared__ int s_cell;
+    const int AS = p.xside, N2 = AS * AS;
+    Lds<T> L = carve_mode<T, BIG>(smem, AS, p.max_w1, p.max_w2);
+    const T invk = T(1.0 / p.kappa);
+    for (;;) {
+        __syncthreads();
+        if (threadIdx.x == 0) s_cell = atomicAdd(&ctrl[0], 1);
+        __syncthreads();
+        const int q = s_cell;
+        if (q >= p.ncells) break;
+        const int c = p.order ? p.order[q] : q;
+        const int W1 = p.dims[2 * c], W2 = p.dims[2 * c + 1];
+        if (W1 < 1 || W2 < 1 || W1 > p.max_w1 || W2 > p.max_w2) {
+            if (threadIdx.x == 0) {
+                atomicOr(&ctrl[3], 1);
+                iters_out[c] = 0;
+                err_out[c] = 0.0;
+                mass_out[c] = 0.0;
+            }
+            continue;
+        }
+        const int64_t base = p.base[c];
+        const int E1 = p.shift[2 * c], E2 = p.shift[2 * c + 1];
+        load_cell<T, BIG>(p, L, p.a, c, W1, W2, base, big_scratch);
+        double err = 0.0, mass = 0.0;
+        int it = 1;
+        for (;; ++it) {
+            y_half(L, AS, W1, W2, E1, E2, invk);
+            x_half(L, AS, W1, W2, E1, E2, invk);
+            err_mass(L, AS, err, mass);
+            const bool stop = (it >= limit) || (!fixed && err <= tol * mass);
+            if (stop) break;
+            for (int i = threadIdx.x; i < N2; i += blockDim.x) L.f[i] = -L.s[i];
+            __syncthreads();
+        }
+        for (int i = threadIdx.x; i < N2; i += blockDim.x) p.a[(int64_t)c * N2 + i] = L.f[i];
+        store_g(p, L, W1, W2, base);
+        if (threadIdx.x == 0) {
+            iters_out[c] = it;
+            err_out[c] = err;
+            mass_out[c] = mass;
+        }
+    }
+}
+
+template <typename T, bool BIG>
+__global__ void __launch_bounds__(kThreads)
+    sk_iter_kernel(SkBatch p, const double* f_in, double* f_out, int it, int limit, double tol,
+                   int* ctrl, double* cell_err, double* cell_mass, double* dtot, T* big_scratch) {
+    if (__atomic_load_n(&ctrl[2], __ATOMIC_RELAXED) != 0) return;
+    extern __shared__ __align__(16) char smem[];
+    __shared__ int s_last;
+    const int AS = p.xside, N2 = AS * AS;
+    Lds<T> L = carve_mode<T, BIG>(smem, AS, p.max_w1, p.max_w2);
+    const T invk = T(1.0 / p.kappa);
+    for (int q = blockIdx.x; q < p.ncells; q += gridDim.x) {
+        const int c = p.order ? p.order[q] : q;
+        const int W1 = p.dims[2 * c], W2 = p.dims[2 * c + 1];
+        if (W1 < 1 || W2 < 1 || W1 > p.max_w1 || W2 > p.max_w2) {
+            if (threadIdx.x == 0) {
+                atomicOr(&ctrl[3], 1);
+                cell_err[c] = 0.0;
+                cell_mass[c] = 0.0;
+            }
+            continue;
+        }
+        const int64_t base = p.base[c];
+        const int E1 = p.shift[2 * c], E2 = p.shift[2 * c + 1];
+        load_cell<T, BIG>(p, L, f_in, c, W1, W2, base, big_scratch);
+        y_half(L, AS, W1, W2, E1, E2, invk);
+        x_half(L, AS, W1, W2, E1, E2, invk);
+        double err, mass;
+        err_mass(L, AS, err, mass);
+        if (threadIdx.x == 0) {
+            cell_err[c] = err;
+            cell_mass[c] = mass;
+        }
+        for (int i = threadIdx.x; i < N2; i += blockDim.x) f_out[(int64_t)c * N2 + i] = -L.s[i];
+        __syncthreads();
+    }
+    // last workgroup to finish reduces the per-cell errors in fixed order
+    __threadfence();
+    if (threadIdx.x == 0) s_last = (atomicAdd(&ctrl[1], 1) == (int)gridDim.x - 1);
+    __syncthreads();
+    if (!s_last) return;
+    __threadfence();
+    double e = 0.0, m = 0.0;
+    for (int c = threadIdx.x; c < p.ncells; c += blockDim.x) {
+        e += cell_err[c];
+        m += cell_mass[c];
+    }
+    e = block_sum(e, L.red);
+    m = block_sum(m, L.red);
+    if (threadIdx.x == 0) {
+        dtot[0] = e;
+        dtot[1] = m;
+        const bool conv = e <= tol * m;
+        if (conv) ctrl[4] = 1;
+        if (conv || it >= limit || !(e == e)) __atomic_store_n(&ctrl[2], it, __ATOMIC_RELAXED);
+        ctrl[1] = 0;
+    }
+}
+
+// g from the final f (one Y-update), for the batch-rule driver.
+template <typename T, bool BIG>
+__global__ void __launch_bounds__(kThreads) sk_final_kernel(SkBatch p, const int* ctrl,
+                                                           int32_t* iters_out, T* big_scratch) {
+    extern __shared__ __align__(16) char smem[];
+    const int AS = p.xside;
+    Lds<T> L = carve_mode<T, BIG>(smem, AS, p.max_w1, p.max_w2);
+    const T invk = T(1.0 / p.kappa);
+    const int done = ctrl[2];
+    for (int q = blockIdx.x; q < p.ncells; q += gridDim.x) {
+        const int c = p.order ? p.order[q] : q;
+        const int W1 = p.dims[2 * c], W2 = p.dims[2 * c + 1];
+        if (W1 < 1 || W2 < 1 || W1 > p.max_w1 || W2 > p.max_w2) continue;
+        const int64_t base = p.base[c];
+        load_cell<T, BIG>(p, L, p.a, c, W1, W2, base, big_scratch);
+        y_half(L, AS, W1, W2, p.shift[2 * c], p.shift[2 * c + 1], invk);
+        store_g(p, L, W1, W2, base);
+        if (threadIdx.x == 0) iters_out[c] = done;
+        __syncthreads();
+    }
+}
+
+// Batch statistics: sums of err, mass, iterations, terms and algorithmic bytes; min/max
+// iterations; whether every cell met its per-cell tolerance.  One workgroup.
+__global__ void __launch_bounds__(kThreads)
+    sk_stats_kernel(int ncells, const int32_t* iters, const int32_t* iters64, const double* err,
+                    const double* mass, double tol, const int32_t* dims, int xside, double* dtot,
+                    int* ictl) {
+    __shared__ double red[8];
+    __shared__ int smin[kThreads / 64], smax[kThreads / 64], sconv[kThreads / 64],
+        spol[kThreads / 64];
+    double e = 0.0, m = 0.0, work = 0.0, bytes = 0.0, terms = 0.0;
+    int imin = 0x7fffffff, imax = 0, allconv = 1, pmax = 0;
+    for (int c = threadIdx.x; c < ncells; c += blockDim.x) {
+        const int it = iters[c];
+        if (iters64) pmax = max(pmax, iters64[c]);
+        e += err[c];
+        m += mass[c];
+        work += it;
+        const double W1 = dims[2 * c], W2 = dims[2 * c + 1];
+        const double A = xside;
+        terms += it * (A * W2 * (A + W1) + A * W1 * (W2 + A));
+        bytes += it * 12.0 * (A * A + W1 * W2);
+        imin = min(imin, it);
+        imax = max(imax, it);
+        if (!(err[c] <= tol * mass[c])) allconv = 0;
+    }
+    e = block_sum(e, red);
+    m = block_sum(m, red);
+    work = block_sum(work, red);
+    terms = block_sum(terms, red);
+    bytes = block_sum(bytes, red);
+    const int w = threadIdx.x >> 6, nw = (int)(blockDim.x >> 6);
+    imin = wave_min_i(imin);
+    imax = wave_max_i(imax);
+    allconv = wave_min_i(allconv);
+    pmax = wave_max_i(pmax);
+    if ((threadIdx.x & 63) == 0) {
+        smin[w] = imin;
+        smax[w] = imax;
+        sconv[w] = allconv;
+        spol[w] = pmax;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int k = 0; k < nw; ++k) {
+            imin = min(imin, smin[k]);
+            imax = max(imax, smax[k]);
+            allconv = min(allconv, sconv[k]);
+            pmax = max(pmax, spol[k]);
+        }
+        ictl[8] = pmax;
+        dtot[0] = e;
+        dtot[1] = m;
+        dtot[2] = work;
+        dtot[3] = terms;
+        dtot[4] = bytes;
+        ictl[5] = ncells > 0 ? imin : 0;
+        ictl[6] = imax;
+        ictl[7] = allconv;
+    }
+}
+
+// max over cells of base + W1*W2 (the packed Y extent), for sizing large-box scratch
+__global__ void maxend_kernel(int ncells, const int64_t* base, const int32_t* dims, int64_t* out) {
+    __shared__ int64_t sm[kThreads];
+    int64_t m = 0;
+    for (int c = threadIdx.x; c < ncells; c += blockDim.x)
+        m = max(m, base[c] + (int64_t)max(dims[2 * c], 0) * max(dims[2 * c + 1], 0));
+    sm[threadIdx.x] = m;
+    __syncthreads();
+    for (int off = blockDim.x / 2; off > 0; off >>= 1) {
+        if ((int)threadIdx.x < off) sm[threadIdx.x] = max(sm[threadIdx.x], sm[threadIdx.x + off]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[0] = sm[0];
+}
+
+}  // namespace
+
+size_t sk_lds_bytes(int xside, int max_w1, int max_w2, int prec) {
+    const size_t e = prec == DD_PREC_F64 ? sizeof(double) : sizeof(float);
+    const size_t need = lds_bytes_mode<false>(xside, max_w1, max_w2, e);
+    if (need <= 160 * 1024) return need;
+    const size_t big = lds_bytes_mode<true>(xside, max_w1, max_w2, e);
+    return big <= 160 * 1024 ? big : 0;
+}
+
+static bool sk_needs_big(int xside, int max_w1, int max_w2, size_t e) {
+    return lds_bytes_mode<false>(xside, max_w1, max_w2, e) > 160 * 1024;
+}
+
+Status sk_work_reserve(SkWork& w, int ncells, size_t a_n) {
+    Status st;
+    if (!w.ctrl) {
+        DD_HIP(hipMalloc(&w.ctrl, 16 * sizeof(int)), st);
+        DD_HIP(hipMalloc(&w.dtot, 8 * sizeof(double)), st);
+        DD_HIP(hipEventCreate(&w.ev0), st);
+        DD_HIP(hipEventCreate(&w.ev1), st);
+        DD_HIP(hipEventCreate(&w.ev2), st);
+    }
+    if (ncells > w.cap) {
+        if (w.cell_err) (void)hipFree(w.cell_err);
+        if (w.cell_mass) (void)hipFree(w.cell_mass);
+        if (w.cell_iters) (void)hipFree(w.cell_iters);
+        w.cell_err = nullptr;
+        w.cell_mass = nullptr;
+        w.cell_iters = nullptr;
+        const int cap = std::max(ncells, 1024);
+        DD_HIP(hipMalloc(&w.cell_err, cap * sizeof(double)), st);
+        DD_HIP(hipMalloc(&w.cell_mass, cap * sizeof(double)), st);
+        DD_HIP(hipMalloc(&w.cell_iters, cap * sizeof(int32_t)), st);
+        if (w.iters64) (void)hipFree(w.iters64);
+        w.iters64 = nullptr;
+        DD_HIP(hipMalloc(&w.iters64, cap * sizeof(int32_t)), st);
+        w.cap = cap;
+    }
+    if (a_n > w.a_alt_n) {
+        if (w.a_alt) (void)hipFree(w.a_alt);
+        w.a_alt = nullptr;
+        DD_HIP(hipMalloc(&w.a_alt, a_n * sizeof(double)), st);
+        w.a_alt_n = a_n;
+    }
+    return st;
+}
+
+void sk_work_release(SkWork& w) {
+    if (w.big) (void)hipFree(w.big);
+    if (w.iters64) (void)hipFree(w.iters64);
+    if (w.a_alt) (void)hipFree(w.a_alt);
+    if (w.cell_err) (void)hipFree(w.cell_err);
+    if (w.cell_mass) (void)hipFree(w.cell_mass);
+    if (w.cell_iters) (void)hipFree(w.cell_iters);
+    if (w.ctrl) (void)hipFree(w.ctrl);
+    if (w.dtot) (void)hipFree(w.dtot);
+    if (w.ev0) (void)hipEventDestroy(w.ev0);
+    if (w.ev1) (void)hipEventDestroy(w.ev1);
+    if (w.ev2) (void)hipEventDestroy(w.ev2);
+    w = SkWork{};
+}
+
+namespace {
+int g_num_cus = 0;
+int num_cus() {
+    if (!g_num_cus) {
+        int dev = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&g_num_cus, hipDeviceAttributeMultiprocessorCount, dev) !=
+                hipSuccess)
+            g_num_cus = 256;
+    }
+    return g_num_cus;
+}
+
+template <typename K>
+Status set_lds_attr(K kernel, size_t bytes, Status& st) {
+    DD_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(kernel),
+                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes),
+           st);
+    return st;
+}
+
+template <typename K>
+int grid_for(K kernel, size_t lds, int ncells) {
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(kernel),
+                                                     kThreads, lds) != hipSuccess ||
+        per_cu < 1)
+        per_cu = 1;
+    const long g = (long)per_cu * num_cus();
+    return (int)std::max(1L, std::min<long>(g, ncells));
+}
+
+template <typename T, bool BIG>
+Status run_solver(const SkBatch& p, const dd_sinkhorn_opts& o, hipStream_t st, SkWork& w,
+                  size_t lds, int32_t* iters, double* errs) {
+    Status S;
+    T* big = reinterpret_cast<T*>(w.big);
+    const bool fixed = o.fixed_iters > 0;
+    zero_ints<<<1, 64, 0, st>>>(w.ctrl, 5);
+    if (fixed || o.stop_rule == DD_STOP_CELL) {
+        auto kern = sk_cell_kernel<T, BIG>;
+        if (set_lds_attr(kern, lds, S).code) return S;
+        const int grid = grid_for(kern, lds, p.ncells);
+        const int limit = fixed ? o.fixed_iters : o.max_iter;
+        kern<<<grid, kThreads, lds, st>>>(p, o.tol, limit, fixed ? 1 : 0, w.ctrl, iters, errs,
+                                          w.cell_mass, big);
+        DD_HIP(hipGetLastError(), S);
+        return S;
+    }
+    auto kern = sk_iter_kernel<T, BIG>;
+    auto fin = sk_final_kernel<T, BIG>;
+    if (set_lds_attr(kern, lds, S).code) return S;
+    if (set_lds_attr(fin, lds, S).code) return S;
+    const int grid = grid_for(kern, lds, p.ncells);
+    double* bufs[2] = {p.a, w.a_alt};
+    const size_t a_bytes = (size_t)p.ncells * p.xside * p.xside * sizeof(double);
+    const int chunk = o.check_every > 0 ? o.check_every : 8;
+    int done = 0, it = 1;
+    while (it <= o.max_iter && !done) {
+        const int end = std::min(o.max_iter, it + chunk - 1);
+        for (; it <= end; ++it)
+            kern<<<grid, kThreads, lds, st>>>(p, bufs[(it - 1) & 1], bufs[it & 1], it, o.max_iter,
+                                              o.tol, w.ctrl, errs, w.cell_mass, w.dtot, big);
+        DD_HIP(hipGetLastError(), S);
+        DD_HIP(hipMemcpyAsync(&done, w.ctrl + 2, sizeof(int), hipMemcpyDeviceToHost, st), S);
+        DD_HIP(hipStreamSynchronize(st), S);
+    }
+    if (done < 1) done = o.max_iter;  // unreachable: the kernel sets done at max_iter
+    if (((done - 1) & 1) == 1)
+        DD_HIP(hipMemcpyAsync(p.a, bufs[1], a_bytes, hipMemcpyDeviceToDevice, st), S);
+    fin<<<grid, kThreads, lds, st>>>(p, w.ctrl, iters, big);
+    DD_HIP(hipGetLastError(), S);
+    return S;
+}
+
+template <typename T>
+Status run_any(const SkBatch& p, const dd_sinkhorn_opts& o, hipStream_t st, SkWork& w,
+               int32_t* iters, double* errs) {
+    Status S;
+    const bool big = sk_needs_big(p.xside, p.max_w1, p.max_w2, sizeof(T));
+    const size_t lds = lds_bytes_mode<false>(p.xside, p.max_w1, p.max_w2, sizeof(T));
+    const size_t ldsb = lds_bytes_mode<true>(p.xside, p.max_w1, p.max_w2, sizeof(T));
+    if (big) {
+        // per-cell global scratch for gq and zq at twice the cell's packed Y offset
+        int64_t* d_end = reinterpret_cast<int64_t*>(w.dtot + 6);
+        maxend_kernel<<<1, kThreads, 0, st>>>(p.ncells, p.base, p.dims, d_end);
+        int64_t ext = 0;
+        DD_HIP(hipMemcpyAsync(&ext, d_end, sizeof ext, hipMemcpyDeviceToHost, st), S);
+        DD_HIP(hipStreamSynchronize(st), S);
+        const size_t need = 2 * (size_t)ext * sizeof(T) + 64;
+        if (need > w.big_bytes) {
+            if (w.big) (void)hipFree(w.big);
+            w.big = nullptr;
+            DD_HIP(hipMalloc(&w.big, need), S);
+            w.big_bytes = need;
+        }
+        return run_solver<T, true>(p, o, st, w, ldsb, iters, errs);
+    }
+    return run_solver<T, false>(p, o, st, w, lds, iters, errs);
+}
+}  // namespace
+
+Status sk_solve(const SkBatch& p, const dd_sinkhorn_opts& o, hipStream_t st, SkWork& w,
+                dd_batch_stats* stats, int32_t* cell_iters_out, double* cell_err_out) {
+    Status S;
+    if (p.ncells < 0 || p.xside < 2 || p.xside > 16 || !(p.kappa > 0.0) || p.max_w1 < 1 ||
+        p.max_w2 < 1 || (p.prec != DD_PREC_F32 && p.prec != DD_PREC_F64)) {
+        S.code = DD_EINVAL;
+        S.msg = "sinkhorn: bad batch (ncells, xside in [2,16], kappa > 0, max_w >= 1)";
+        return S;
+    }
+    if (o.max_iter < 1 || o.fixed_iters < 0 ||
+        (o.stop_rule != DD_STOP_BATCH && o.stop_rule != DD_STOP_CELL) || !(o.tol >= 0.0) ||
+        o.check_every < 0) {
+        S.code = DD_EINVAL;
+        S.msg = "sinkhorn: bad options (max_iter >= 1, fixed_iters >= 0, stop_rule, tol >= 0)";
+        return S;
+    }
+    const size_t lds = sk_lds_bytes(p.xside, p.max_w1, p.max_w2, p.prec);
+    if (!lds) {
+        S.code = DD_EINVAL;
+        S.msg = "sinkhorn: Y box bound too large for one workgroup's LDS";
+        return S;
+    }
+    S = sk_work_reserve(w, p.ncells, (size_t)p.ncells * p.xside * p.xside);
+    if (S.code) return S;
+    int32_t* iters = cell_iters_out ? cell_iters_out : w.cell_iters;
+    double* errs = cell_err_out ? cell_err_out : w.cell_err;
+    if (p.ncells == 0) {
+        if (stats) {
+            *stats = dd_batch_stats{};
+            stats->converged = 1;
+        }
+        return S;
+    }
+    DD_HIP(hipEventRecord(w.ev0, st), S);
+    zero_ints<<<1, 64, 0, st>>>(w.ctrl, 16);
+    S = p.prec == DD_PREC_F32 ? run_any<float>(p, o, st, w, iters, errs)
+                              : run_any<double>(p, o, st, w, iters, errs);
+    if (S.code) return S;
+    DD_HIP(hipEventRecord(w.ev2, st), S);
+    const bool finish = p.prec == DD_PREC_F32 && o.fixed_iters == 0;
+    if (finish) {
+        // float64 finish: continue the same stopping rule in float64 from the float32 state;
+        // the tolerance is then certified by a float64 error (usually after one Y-update)
+        S = run_any<double>(p, o, st, w, w.iters64, errs);
+        if (S.code) return S;
+    }
+    sk_stats_kernel<<<1, kThreads, 0, st>>>(p.ncells, iters, finish ? w.iters64 : nullptr, errs,
+                                            w.cell_mass, o.tol, p.dims, p.xside, w.dtot, w.ctrl);
+    DD_HIP(hipEventRecord(w.ev1, st), S);
+    int hctl[16];
+    double htot[8];
+    DD_HIP(hipMemcpyAsync(hctl, w.ctrl, sizeof hctl, hipMemcpyDeviceToHost, st), S);
+    DD_HIP(hipMemcpyAsync(htot, w.dtot, sizeof htot, hipMemcpyDeviceToHost, st), S);
+    DD_HIP(hipStreamSynchronize(st), S);
+    float ms = 0.f, ms_main = 0.f;
+    DD_HIP(hipEventElapsedTime(&ms, w.ev0, w.ev1), S);
+    DD_HIP(hipEventElapsedTime(&ms_main, w.ev0, w.ev2), S);
+    if (hctl[3]) {
+        S.code = DD_EINVAL;
+        S.msg = "sinkhorn: a cell's Y box is empty or exceeds max_w1/max_w2";
+        return S;
+    }
+    dd_batch_stats bs{};
+    bs.ncells = p.ncells;
+    bs.iters_min = hctl[5];
+    bs.iters_max = hctl[6];
+    bs.err = htot[0];
+    bs.mass = htot[1];
+    bs.cell_iters = (int64_t)htot[2];
+    bs.lse_terms = htot[3];
+    bs.alg_bytes = htot[4];
+    bs.time_ms = ms;
+    bs.main_ms = ms_main;
+    bs.finish_iters_max = finish ? hctl[8] : 0;
+    if (o.fixed_iters > 0)
+        bs.converged = 1;
+    else if (o.stop_rule == DD_STOP_CELL)
+        bs.converged = hctl[7];
+    else
+        bs.converged = hctl[4];
+    if (stats) *stats = bs;
+    if (!std::isfinite(bs.err)) {
+        S.code = DD_ENUMERIC;
+        S.msg = "sinkhorn: non-finite marginal error";
+        return S;
+    }
+    if (!bs.converged) {
+        S.code = DD_NOTCONV;
+        S.msg = "sinkhorn: iteration limit reached before the tolerance";
+    }
+    return S;
+}
+
+}  // namespace dd
+
+// ---------------------------------------------------------------------------
+// C ABI
+// ---------------------------------------------------------------------------
+namespace {
+dd_status batch_entry(int prec, int32_t ncells, int32_t xside, const int32_t* dims,
+                      const int64_t* base, const int32_t* shift, const double* logmu,
+                      const double* lognu, double* a, double* b, double kappa, int32_t max_w1,
+                      int32_t max_w2, const dd_sinkhorn_opts* opts, int32_t* cell_iters,
+                      double* cell_err, void* stream, dd_batch_stats* stats) {
+    if (!opts || (ncells > 0 && (!dims || !base || !shift || !logmu || !lognu || !a || !b))) {
+        dd::set_global_error("sinkhorn_batch: null argument");
+        return DD_EINVAL;
+    }
+    dd::SkBatch p;
+    p.ncells = ncells;
+    p.xside = xside;
+    p.dims = dims;
+    p.base = base;
+    p.shift = shift;
+    p.logmu = logmu;
+    p.lognu = lognu;
+    p.a = a;
+    p.b = b;
+    p.kappa = kappa;
+    p.max_w1 = max_w1;
+    p.max_w2 = max_w2;
+    p.prec = prec;
+    dd::SkWork w;
+    const hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    dd::Status s = dd::sk_solve(p, *opts, st, w, stats, cell_iters, cell_err);
+    (void)hipStreamSynchronize(st);
+    dd::sk_work_release(w);
+    if (s.code != DD_OK) dd::set_global_error(s.msg);
+    return s.code;
+}
+}  // namespace
+
+extern "C" dd_status sinkhorn_batch(int32_t ncells, int32_t xside, const int32_t* dims,
+                                    const int64_t* base, const int32_t* shift, const double* logmu,
+                                    const double* lognu, double* a, double* b, double kappa,
+                                    int32_t max_w1, int32_t max_w2, const dd_sinkhorn_opts* opts,
+                                    int32_t* cell_iters, double* cell_err, void* stream,
+                                    dd_batch_stats* stats) {
+    return batch_entry(DD_PREC_F32, ncells, xside, dims, base, shift, logmu, lognu, a, b, kappa,
+                       max_w1, max_w2, opts, cell_iters, cell_err, stream, stats);
+}
+
+extern "C" dd_status sinkhorn_batch_f64(int32_t ncells, int32_t xside, const int32_t* dims,
+                                        const int64_t* base, const int32_t* shift,
+                                        const double* logmu, const double* lognu, double* a,
+                                        double* b, double kappa, int32_t max_w1, int32_t max_w2,
+                                        const dd_sinkhorn_opts* opts, int32_t* cell_iters,
+                                        double* cell_err, void* stream, dd_batch_stats* stats) {
+    return batch_entry(DD_PREC_F64, ncells, xside, dims, base, shift, logmu, lognu, a, b, kappa,
+                       max_w1, max_w2, opts, cell_iters, cell_err, stream, stats);
+}

@@ -1,0 +1,56 @@
+// Batched separable log-domain cell Sinkhorn on gfx950 (declarations).
+#pragma once
+
+#include "common.hpp"
+
+namespace dd {
+
+// Device-side description of a batch of cell problems (see sinkhorn_batch in domdec.h).
+// Inputs and potentials are float64; `prec` selects the arithmetic of the log-sum-exp terms.
+struct SkBatch {
+    int ncells = 0;
+    int xside = 0;                   // X block side (2s)
+    const int32_t* dims = nullptr;   // [ncells][2] W1, W2
+    const int64_t* base = nullptr;   // [ncells] packed Y offset
+    const int32_t* shift = nullptr;  // [ncells][2] E1, E2
+    const double* logmu = nullptr;   // [ncells][xside^2]
+    const double* lognu = nullptr;   // packed Y boxes
+    double* a = nullptr;             // [ncells][xside^2] f, in/out
+    double* b = nullptr;             // packed Y boxes, g out
+    const int32_t* order = nullptr;  // optional processing order (largest first), may be null
+    double kappa = 1.0;
+    int max_w1 = 0, max_w2 = 0;
+    int prec = DD_PREC_F32;
+};
+
+// Scratch owned by the caller (reused across solves).
+struct SkWork {
+    double* a_alt = nullptr;    // second X-potential buffer for the batch rule
+    size_t a_alt_n = 0;
+    double* cell_err = nullptr; // [cap]
+    double* cell_mass = nullptr;
+    int32_t* cell_iters = nullptr;
+    int32_t* iters64 = nullptr; // [cap] float64-finish iterations
+    int* ctrl = nullptr;        // [16] device control words (queue, ticket, done, flags)
+    double* dtot = nullptr;     // [8] device totals
+    void* big = nullptr;        // large-box scratch (gq, zq in global memory)
+    size_t big_bytes = 0;
+    int cap = 0;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr, ev2 = nullptr;
+};
+
+Status sk_work_reserve(SkWork& w, int ncells, size_t a_n);
+void sk_work_release(SkWork& w);
+
+// LDS bytes one workgroup needs for the given bounds, or 0 when it does not fit.
+size_t sk_lds_bytes(int xside, int max_w1, int max_w2, int prec);
+
+Status sk_solve(const SkBatch& p, const dd_sinkhorn_opts& o, hipStream_t st, SkWork& w,
+                dd_batch_stats* stats, int32_t* cell_iters_out, double* cell_err_out);
+
+// Algorithmic work of one iteration of one cell (for the statistics).
+inline double sk_cell_terms(int a, int W1, int W2) {
+    return (double)a * W2 * (a + W1) + (double)a * W1 * (W2 + a);
+}
+
+}  // namespace dd
