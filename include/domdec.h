@@ -221,7 +221,7 @@ dd_status domdec_iterate(dd_ctx* ctx, int32_t partition, double eps,
 /* Flow update statistics. */
 typedef struct {
     int32_t n_nodes, n_arcs;
-    int64_t int_value;         /* optimal value of the integer min-cost flow          */
+    double int_value;          /* optimal value of the integer min-cost flow (exact < 2^53) */
     double value;              /* sum_ij w_ij cbar_ij in float64 (<= 0)               */
     double moved_mass;         /* sum_{i != j} w_ij                                   */
     int32_t n_active_arcs;     /* arcs i != j with w_ij > 0                           */
@@ -235,15 +235,41 @@ typedef struct {
  * implementation steps of Sec. 5.1).  Must follow a B iteration: pi_i is the
  * restriction to X_i x Y of that iteration's composite plans.
  *   Edge costs cbar_ij = <c, mu_j/m_j (x) nu_i/m_i> - <c, pi_i>/m_i over the
- *   4-neighbourhood (cbar_ii = 0), computed on the device in float64 from cell
- *   moments; min-cost flow (MinCostFlow) on the host, integerised with masses
- *   b_i (largest remainder, sum 2^40) and costs round(cbar 2^30 / max|cbar|),
+ *   4-neighbourhood plus self loops (cbar_ii = 0; arcs listed per tail i =
+ *   r*(N/s)+c in ascending head order), computed on the device in float64 from
+ *   cell moments; min-cost flow (MinCostFlow) on the host by network simplex,
+ *   integerised with masses b_i (largest remainder to a total of 2^40, ties by
+ *   index) and costs round(cbar 2^30 / max|cbar|), mapped back as
  *   w_ij = flow_ij m_i / b_i; new marginals nu_hat_j = sum_i w_ij nu_i / m_i
  *   (eq. flow-update-cell-marginals) assembled on the device, then truncated.
- *   stats (host) may be NULL.  Synchronises the context stream.
+ *   Equivalent to flow_costs + dd_mcf_solve + flow_apply.  stats (host) may be
+ *   NULL.  Synchronises the context stream.
  * Errors: DD_ESTATE if the last iteration was not on partition B.
  */
 dd_status flow_update(dd_ctx* ctx, dd_flow_stats* stats);
+
+/* flow_costs -- step 1 of flow_update: writes the edge costs cbar (host, float64,
+ * [n_arcs], may be NULL) and the arc count (may be NULL).  DD_ESTATE unless the last
+ * iteration was on partition B. */
+dd_status flow_costs(dd_ctx* ctx, double* cbar, int32_t* n_arcs);
+
+/* flow_apply -- step 3 of flow_update for a given flow w (host, float64, [n_arcs], in
+ * the arc order of flow_costs; w must satisfy the divergence constraint
+ * eq. div-constraint-single-cell): nu_i <- sum_{i in N(j)} w_ij nu_i / m_i, truncated. */
+dd_status flow_apply(dd_ctx* ctx, const double* w);
+
+/*
+ * dd_mcf_solve -- the integer min-cost flow of the flow update (host only, no GPU):
+ * bipartite transportation problem, left node i supplies supply[i], right node j
+ * demands supply[j], arcs tail[a] -> head[a] (0 <= tail, head < n) with integer cost
+ * and no upper bound.  Network simplex with strongly feasible trees.  Writes optimal
+ * flows (host int64 [m]) and, if potential is not NULL, node potentials (host int64
+ * [2n], left then right) with cost + p[tail] - p[n + head] >= 0, = 0 where flow > 0.
+ * Errors: DD_EINVAL (bad input), DD_ENUMERIC (infeasible or pivot limit).
+ */
+dd_status dd_mcf_solve(int32_t n, int32_t m, const int32_t* tail, const int32_t* head,
+                       const int64_t* cost, const int64_t* supply, int64_t* flow,
+                       int64_t* potential);
 
 /* Host view of the basic-cell Y-marginals (two-call protocol). */
 typedef struct {

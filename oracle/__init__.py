@@ -495,8 +495,9 @@ class DomDec:
         if st != 0:
             raise RuntimeError("min-cost flow failed")
         w = flow.astype(np.float64) * (self.m[tail] / b[tail].astype(np.float64))
+        int_value = sum(int(f) * int(c) for f, c in zip(flow, icost))  # exact (can exceed int64)
         return {"w": w, "flow": flow, "icost": icost, "b": b, "pot": pot,
-                "int_value": int((flow * icost).sum()), "value": float((w * cbar).sum())}
+                "int_value": int_value, "value": float((w * cbar).sum())}
 
     def apply_flow(self, tail, head, w, truncate: bool = True) -> None:
         """nu_hat_j = sum_{i in N(j)} w_ij nu_i / m_i (eq. flow-update-cell-marginals)."""

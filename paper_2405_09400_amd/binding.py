@@ -22,7 +22,8 @@ _NAMES = {0: "DD_OK", 1: "DD_NOTCONV", -1: "DD_EINVAL", -2: "DD_ENOMEM", -3: "DD
 
 # every function include/domdec.h declares
 SYMBOLS = ("sinkhorn_batch", "sinkhorn_batch_f64", "domdec_init", "domdec_iterate", "flow_update",
-           "extract_plan", "domdec_evaluate", "domdec_free", "domdec_strerror")
+           "flow_costs", "flow_apply", "dd_mcf_solve", "extract_plan", "domdec_evaluate", "domdec_free",
+           "domdec_strerror")
 
 
 class DomDecError(RuntimeError):
@@ -59,7 +60,7 @@ class IterStats(ctypes.Structure):
 
 
 class FlowStats(ctypes.Structure):
-    _fields_ = [("n_nodes", ctypes.c_int32), ("n_arcs", ctypes.c_int32), ("int_value", ctypes.c_int64),
+    _fields_ = [("n_nodes", ctypes.c_int32), ("n_arcs", ctypes.c_int32), ("int_value", ctypes.c_double),
                 ("value", ctypes.c_double), ("moved_mass", ctypes.c_double),
                 ("n_active_arcs", ctypes.c_int32), ("reserved", ctypes.c_int32),
                 ("t_costs_ms", ctypes.c_double), ("t_mcf_ms", ctypes.c_double),
@@ -115,6 +116,12 @@ def lib():
                                  ctypes.POINTER(IterStats)]
     L.flow_update.restype = ctypes.c_int
     L.flow_update.argtypes = [vp, ctypes.POINTER(FlowStats)]
+    L.flow_costs.restype = ctypes.c_int
+    L.flow_costs.argtypes = [vp, dp, i32p]
+    L.flow_apply.restype = ctypes.c_int
+    L.flow_apply.argtypes = [vp, dp]
+    L.dd_mcf_solve.restype = ctypes.c_int
+    L.dd_mcf_solve.argtypes = [ctypes.c_int32, ctypes.c_int32, i32p, i32p, i64p, i64p, i64p, i64p]
     L.extract_plan.restype = ctypes.c_int
     L.extract_plan.argtypes = [vp, ctypes.POINTER(PlanView)]
     L.domdec_evaluate.restype = ctypes.c_int
@@ -125,6 +132,22 @@ def lib():
     L.domdec_strerror.argtypes = [vp, ctypes.c_int]
     _LIB = L
     return L
+
+
+def mcf_solve(n, tail, head, cost, supply):
+    """Integer bipartite min-cost flow (dd_mcf_solve, host only).  Returns (flow, potentials)."""
+    tail = np.ascontiguousarray(tail, dtype=np.int32)
+    head = np.ascontiguousarray(head, dtype=np.int32)
+    cost = np.ascontiguousarray(cost, dtype=np.int64)
+    supply = np.ascontiguousarray(supply, dtype=np.int64)
+    flow = np.zeros(len(tail), dtype=np.int64)
+    pot = np.zeros(2 * n, dtype=np.int64)
+    i32p, i64p = ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int64)
+    st = lib().dd_mcf_solve(int(n), len(tail), tail.ctypes.data_as(i32p), head.ctypes.data_as(i32p),
+                            cost.ctypes.data_as(i64p), supply.ctypes.data_as(i64p),
+                            flow.ctypes.data_as(i64p), pot.ctypes.data_as(i64p))
+    _check(st)
+    return flow, pot
 
 
 def exported_symbols():
@@ -247,6 +270,18 @@ class DomDec:
         st = FlowStats()
         _check(lib().flow_update(self._ctx, ctypes.byref(st)), self._ctx)
         return _struct_dict(st)
+
+    def flow_costs(self) -> np.ndarray:
+        n = ctypes.c_int32()
+        _check(lib().flow_costs(self._ctx, None, ctypes.byref(n)), self._ctx)
+        out = np.zeros(n.value, dtype=np.float64)
+        _check(lib().flow_costs(self._ctx, out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), None),
+               self._ctx)
+        return out
+
+    def flow_apply(self, w) -> None:
+        w = np.ascontiguousarray(w, dtype=np.float64)
+        _check(lib().flow_apply(self._ctx, w.ctypes.data_as(ctypes.POINTER(ctypes.c_double))), self._ctx)
 
     def evaluate(self) -> dict:
         ev = Eval()

@@ -343,10 +343,6 @@ static dd_status iterate_impl(dd_ctx* c, int p, double eps, const dd_sinkhorn_op
         hipStreamSynchronize(hs) != hipSuccess)
         return fail(c, DD_EDEVICE, "domdec_iterate: reading composite sizes failed");
     const int mw1 = info[0], mw2 = info[1];
-    if (!sk_lds_bytes(c->AS, mw1, mw2, c->prec))
-        return fail(c, DD_ENOMEM,
-                    "domdec_iterate: a composite Y box (" + std::to_string(mw1) + "x" +
-                        std::to_string(mw2) + ") exceeds one workgroup's LDS");
     if (grow(c->d_nuJ, c->nuJ_cap, (size_t)total, st).code ||
         grow(c->d_lognu, c->lognu_cap, (size_t)total, st).code ||
         grow(c->d_b, c->b_cap, (size_t)total, st).code ||

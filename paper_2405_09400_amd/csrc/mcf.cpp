@@ -1,0 +1,238 @@
+// Integer min-cost flow on a bipartite transportation graph by the primal network simplex
+// method (the host step of the flow update, problem (MinCostFlow) of Sec. 3.1-3.2).
+//
+// Graph: left nodes 0..n-1 (supply s_i), right nodes n..2n-1 (demand s_j), arcs i -> n+j
+// with integer costs and no upper bound.  An artificial root joins every node with an
+// arc of cost ART larger than any path of real arcs; the initial tree is the star of
+// artificial arcs, oriented so that the tree is strongly feasible (zero-flow tree arcs
+// point away from the root).  Pricing is block search over the arcs; the leaving arc is
+// the last blocking arc met when the pivot cycle is walked in its orientation from the
+// apex, which keeps the tree strongly feasible and rules out cycling.  After a pivot the
+// cut-off subtree is re-rooted at the entering arc and its depths and potentials are
+// recomputed by a walk over explicit child lists.
+#include <algorithm>
+#include <cmath>
+#include <cstdint>
+#include <cstdlib>
+#include <vector>
+
+#include "mcf.hpp"
+
+namespace dd {
+
+namespace {
+
+struct Simplex {
+    int V = 0, M = 0, R = 0;  // nodes (incl. root), real arcs, root id
+    std::vector<int> src, dst;
+    std::vector<int64_t> cost, flow;
+    std::vector<int8_t> state;  // 0 tree, 1 at lower bound
+    std::vector<int> parent, pred, depth, first_child, next_sib, prev_sib;
+    std::vector<int64_t> pot;
+
+    int64_t rc(int a) const { return cost[a] + pot[src[a]] - pot[dst[a]]; }
+
+    void link_child(int p, int c) {
+        parent[c] = p;
+        prev_sib[c] = -1;
+        next_sib[c] = first_child[p];
+        if (first_child[p] >= 0) prev_sib[first_child[p]] = c;
+        first_child[p] = c;
+    }
+    void unlink_child(int c) {
+        const int p = parent[c];
+        if (prev_sib[c] >= 0)
+            next_sib[prev_sib[c]] = next_sib[c];
+        else
+            first_child[p] = next_sib[c];
+        if (next_sib[c] >= 0) prev_sib[next_sib[c]] = prev_sib[c];
+        prev_sib[c] = next_sib[c] = -1;
+    }
+
+    // depth and potential of the subtree rooted at r from those of parent[r]
+    void refresh_subtree(int r, std::vector<int>& stack) {
+        stack.clear();
+        stack.push_back(r);
+        while (!stack.empty()) {
+            const int x = stack.back();
+            stack.pop_back();
+            const int p = parent[x], a = pred[x];
+            depth[x] = depth[p] + 1;
+            pot[x] = (dst[a] == x) ? pot[p] + cost[a] : pot[p] - cost[a];
+            for (int c = first_child[x]; c >= 0; c = next_sib[c]) stack.push_back(c);
+        }
+    }
+};
+
+}  // namespace
+
+int mcf_network_simplex(int n, int m, const int32_t* tail, const int32_t* head,
+                        const int64_t* cost, const int64_t* supply, int64_t* flow_out,
+                        int64_t* pot_out) {
+    Simplex S;
+    const int N2 = 2 * n;
+    S.V = N2 + 1;
+    S.R = N2;
+    S.M = m;
+    const int A = m + N2;  // real + artificial arcs
+    S.src.resize(A);
+    S.dst.resize(A);
+    S.cost.resize(A);
+    S.flow.assign(A, 0);
+    S.state.assign(A, 1);
+    int64_t maxc = 1, tot = 0;
+    for (int a = 0; a < m; ++a) {
+        if (tail[a] < 0 || tail[a] >= n || head[a] < 0 || head[a] >= n) return -2;
+        S.src[a] = tail[a];
+        S.dst[a] = n + head[a];
+        S.cost[a] = cost[a];
+        maxc = std::max<int64_t>(maxc, std::llabs(cost[a]));
+    }
+    for (int i = 0; i < n; ++i) {
+        if (supply[i] < 0) return -2;
+        tot += supply[i];
+    }
+    // no real path is longer than 2n arcs; ART dominates every real path cost
+    const int64_t ART = maxc * (int64_t)(N2 + 1) + 1;
+    S.parent.assign(S.V, -1);
+    S.pred.assign(S.V, -1);
+    S.depth.assign(S.V, 0);
+    S.first_child.assign(S.V, -1);
+    S.next_sib.assign(S.V, -1);
+    S.prev_sib.assign(S.V, -1);
+    S.pot.assign(S.V, 0);
+    for (int v = 0; v < N2; ++v) {
+        const int a = m + v;
+        const int64_t b = v < n ? supply[v] : -supply[v - n];  // net supply of node v
+        S.cost[a] = ART;
+        if (b > 0) {  // v -> root carries the supply
+            S.src[a] = v;
+            S.dst[a] = S.R;
+            S.flow[a] = b;
+        } else {      // root -> v, zero flow points away from the root
+            S.src[a] = S.R;
+            S.dst[a] = v;
+            S.flow[a] = -b;
+        }
+        S.state[a] = 0;
+        S.pred[v] = a;
+        S.link_child(S.R, v);
+        S.depth[v] = 1;
+        S.pot[v] = (S.dst[a] == v) ? ART : -ART;
+    }
+    const int64_t INF = tot + 1;
+    auto cap = [&](int) { return INF; };
+
+    std::vector<int> stack, cyc_arc;
+    std::vector<int8_t> cyc_fwd;
+    const int block = std::max(16, (int)std::sqrt((double)A));
+    int next = 0;
+    int64_t pivots = 0;
+    const int64_t max_pivots = (int64_t)50 * A + 1000;
+    for (;;) {
+        // block-search pricing
+        int enter = -1;
+        int64_t best = 0;
+        int scanned = 0;
+        while (scanned < A) {
+            const int end = std::min(A, scanned + block);
+            for (int k = scanned; k < end; ++k) {
+                const int a = (next + k) % A;
+                if (S.state[a] != 1) continue;
+                const int64_t r = S.rc(a);
+                if (r < best) {
+                    best = r;
+                    enter = a;
+                }
+            }
+            scanned = end;
+            if (enter >= 0) break;
+        }
+        if (enter < 0) break;  // optimal
+        next = (next + scanned) % A;
+        if (++pivots > max_pivots) return -3;
+
+        // pivot cycle: enter u -> v, tree paths from u and v to the apex
+        const int u = S.src[enter], v = S.dst[enter];
+        int a = u, b = v;
+        while (a != b) {
+            if (S.depth[a] > S.depth[b])
+                a = S.parent[a];
+            else if (S.depth[b] > S.depth[a])
+                b = S.parent[b];
+            else {
+                a = S.parent[a];
+                b = S.parent[b];
+            }
+        }
+        const int join = a;
+        // walk in orientation order: apex -> ... -> u, u -> v, v -> ... -> apex
+        cyc_arc.clear();
+        cyc_fwd.clear();
+        {
+            std::vector<int>& path = stack;
+            path.clear();
+            for (int x = u; x != join; x = S.parent[x]) path.push_back(x);
+            for (int k = (int)path.size() - 1; k >= 0; --k) {
+                const int x = path[k], ar = S.pred[x];
+                cyc_arc.push_back(ar);
+                cyc_fwd.push_back(S.dst[ar] == x ? 1 : 0);  // traversed parent -> x
+            }
+        }
+        const int pos_enter = (int)cyc_arc.size();
+        cyc_arc.push_back(enter);
+        cyc_fwd.push_back(1);
+        for (int x = v; x != join; x = S.parent[x]) {
+            const int ar = S.pred[x];
+            cyc_arc.push_back(ar);
+            cyc_fwd.push_back(S.src[ar] == x ? 1 : 0);  // traversed x -> parent
+        }
+        int64_t delta = INF;
+        for (size_t k = 0; k < cyc_arc.size(); ++k) {
+            const int ar = cyc_arc[k];
+            const int64_t res = cyc_fwd[k] ? cap(ar) - S.flow[ar] : S.flow[ar];
+            delta = std::min(delta, res);
+        }
+        int leave_k = -1;
+        for (size_t k = 0; k < cyc_arc.size(); ++k) {
+            const int ar = cyc_arc[k];
+            const int64_t res = cyc_fwd[k] ? cap(ar) - S.flow[ar] : S.flow[ar];
+            if (res == delta) leave_k = (int)k;  // last blocking arc
+        }
+        if (delta >= INF) return -4;  // unbounded: cannot happen on a transportation graph
+        for (size_t k = 0; k < cyc_arc.size(); ++k) {
+            const int ar = cyc_arc[k];
+            S.flow[ar] += cyc_fwd[k] ? delta : -delta;
+        }
+        const int leave = cyc_arc[leave_k];
+        if (leave == enter) continue;  // bounded only by itself: cannot happen without caps
+        // the leaving tree arc cuts off the subtree of its deeper end q
+        const int q = (S.pred[S.src[leave]] == leave) ? S.src[leave] : S.dst[leave];
+        // the entering endpoint inside q's subtree: u's if the leaving arc is on u's path
+        const bool u_side = leave_k < pos_enter;
+        const int w_in = u_side ? u : v, z_in = u_side ? v : u;
+        // re-root the cut subtree at w_in: reverse parent pointers from w_in up to q
+        int x = w_in, new_par = z_in, new_pred = enter;
+        for (;;) {
+            const int old_par = S.parent[x], old_pred = S.pred[x];
+            S.unlink_child(x);
+            S.pred[x] = new_pred;
+            S.link_child(new_par, x);
+            if (x == q) break;
+            new_par = x;
+            new_pred = old_pred;
+            x = old_par;
+        }
+        S.state[enter] = 0;
+        S.state[leave] = 1;
+        S.refresh_subtree(w_in, stack);
+    }
+    for (int v = 0; v < N2; ++v)
+        if (S.flow[m + v] != 0) return -1;  // infeasible
+    for (int k = 0; k < m; ++k) flow_out[k] = S.flow[k];
+    if (pot_out)
+        for (int v = 0; v < N2; ++v) pot_out[v] = S.pot[v];
+    return 0;
+}
+
+}  // namespace dd

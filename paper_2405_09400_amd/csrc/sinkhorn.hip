@@ -13,12 +13,12 @@
 // the marginal error and the masses are float64.  This is what lets float32 reach a
 // marginal tolerance of 1e-5 (the paper saw plain float32 stall, App. A.2.1).
 //
-// Mapping to the hardware: one workgroup (4 wave64s) owns one cell at a time with
-// the whole cell -- f, log mu, the Y box of log nu_J and g, the shifted per-axis
-// intermediates -- resident in LDS (up to 160 KB per workgroup on gfx950).  Each
-// 1D pass gives one output per lane and walks its short reduction line from LDS
-// (max pass, then exp-sum pass).  Row maxima and the float64 error / mass sums are
-// wave64 shuffle reductions.
+// Mapping to the hardware: one wave64 workgroup owns one cell at a time with the whole
+// cell -- f, log mu, the Y box of log nu_J and g, the shifted per-axis intermediates --
+// resident in LDS (boxes larger than the LDS tile keep their Y-box arrays in global
+// memory).  The tile is sized for ~8 resident workgroups per CU.  Each 1D pass gives one
+// output per lane and walks its short reduction line from LDS (max pass, then exp-sum
+// pass).  Row maxima and the float64 error / mass sums are wave64 shuffle reductions.
 //
 // Two drivers:
 //   * per-cell stopping or a fixed iteration count: a persistent kernel pulls
@@ -45,7 +45,9 @@ thread_local std::string g_err;
 void set_global_error(const std::string& m) { g_err = m; }
 const char* global_error() { return g_err.c_str(); }
 
-constexpr int kThreads = 256;
+// One wave64 per workgroup, one cell per workgroup at a time: the 1D passes fill the wave,
+// the per-cell reductions are single-wave shuffles and barriers are single-wave.
+constexpr int kThreads = 64;
 
 namespace {
 
@@ -99,33 +101,51 @@ struct Lds {
     double* lm;   // [N2]          log mu
     double* s;    // [N2]          LSE_j (g + log nu_J - C)
     double* ry;   // [AS]          row maxima of f + log mu
-    double* qx;   // [mw1]         row maxima of g + log nu_J (full offsets)
-    double* ln;   // [mw1][W2p]    log nu_J
     double* red;  // [16]          reductions; [8] = R, [9] = Q
     T* wq;        // [N2]          f + log mu - ry(row)
     T* rhoy;      // [AS]          ry - R
+    // Y-box arrays of the current cell (LDS tile, or global scratch for a larger box)
+    double* ln;   // [W1][ys]      log nu_J
+    double* qx;   // [W1]          row maxima of g + log nu_J (full offsets)
+    T* gq;        // [W1][ys]      g + R (g = gq - R)
+    T* zq;        // [W1][ys]      g + log nu_J - qx(row)
     T* t1;        // [AS][W2p]     Y-half intermediate, relative to ry
-    T* gq;        // [mw1][W2p]    g + R (g = gq - R)
-    T* zq;        // [mw1][W2p]    g + log nu_J - qx(row)
-    T* kq;        // [mw1]         qx - Q
-    T* u;         // [mw1][ASp]    X-half intermediate, relative to qx
-    int W2p, ASp;
-    int ys;       // row stride of ln / gq / zq (W2p in LDS, W2 in global memory)
+    T* u;         // [W1][ASp]     X-half intermediate, relative to qx
+    T* kq;        // [W1]          qx - Q
+    int ys, W2p, ASp;
+    // the LDS tile, sized for boxes up to lw1 x lw2
+    double* ln_l;
+    double* qx_l;
+    T* gq_l;
+    T* zq_l;
+    T* t1_l;
+    T* u_l;
+    T* kq_l;
+    int lys;
 };
 
-__host__ __device__ inline size_t lds_layout_bytes(int AS, int mw1, int mw2, size_t elem) {
-    const size_t W2p = (size_t)mw2 + 1, ASp = (size_t)AS + 1, N2 = (size_t)AS * AS;
-    const size_t nd = 3 * N2 + AS + mw1 + (size_t)mw1 * W2p + 16;
-    const size_t nt = N2 + AS + AS * W2p + 2 * (size_t)mw1 * W2p + mw1 + (size_t)mw1 * ASp;
+// LDS bytes: the X arrays of the cell plus the Y-box arrays for the LDS tile (lw1 x lw2);
+// cells beyond the tile keep their Y-box arrays in global scratch (read through L1/L2).
+__host__ __device__ inline size_t lds_layout_bytes(int AS, int lw1, int lw2, size_t elem) {
+    const size_t N2 = (size_t)AS * AS, LY = (size_t)lw1 * (lw2 + 1);
+    const size_t nd = 16 + 3 * N2 + AS + LY + lw1;
+    const size_t nt = N2 + AS + 2 * LY + (size_t)AS * (lw2 + 1) + (size_t)lw1 * (AS + 1) + lw1;
     return 8 * nd + elem * nt + 16;
+}
+
+// Global scratch (in doubles) of a cell whose box exceeds the tile: qx, then gq, zq, t1, u, kq.
+__host__ __device__ inline int64_t cell_scratch_doubles(int AS, int W1, int W2, size_t elem) {
+    const int64_t nt = 2 * (int64_t)W1 * W2 + (int64_t)AS * (W2 + 1) + (int64_t)W1 * (AS + 1) + W1;
+    const int64_t n = W1 + (nt * (int64_t)elem + 7) / 8;
+    return (n + 1) & ~int64_t(1);
 }
 
 template <typename T>
-__device__ __forceinline__ Lds<T> carve(char* base, int AS, int mw1, int mw2) {
+__device__ __forceinline__ Lds<T> carve(char* base, int AS, int lw1, int lw2) {
     Lds<T> L;
-    L.W2p = mw2 + 1;
-    L.ASp = AS + 1;
     const int N2 = AS * AS;
+    L.lys = lw2 + 1;
+    const size_t LY = (size_t)lw1 * L.lys;
     double* d = reinterpret_cast<double*>(base);
     L.red = d;
     d += 16;
@@ -137,76 +157,24 @@ __device__ __forceinline__ Lds<T> carve(char* base, int AS, int mw1, int mw2) {
     d += N2;
     L.ry = d;
     d += AS;
-    L.qx = d;
-    d += mw1;
-    L.ln = d;
-    d += (size_t)mw1 * L.W2p;
+    L.ln_l = d;
+    d += LY;
+    L.qx_l = d;
+    d += lw1;
     T* t = reinterpret_cast<T*>(d);
     L.wq = t;
     t += N2;
     L.rhoy = t;
     t += AS;
-    L.t1 = t;
-    t += AS * L.W2p;
-    L.gq = t;
-    t += mw1 * L.W2p;
-    L.zq = t;
-    t += mw1 * L.W2p;
-    L.kq = t;
-    t += mw1;
-    L.u = t;
-    return L;
-}
-
-// Large-box mode keeps ln, gq and zq of the current cell in global memory (read through
-// L1/L2) and only the per-line arrays in LDS.  The layout code below is shared.
-template <bool BIG>
-__host__ __device__ inline size_t lds_bytes_mode(int AS, int mw1, int mw2, size_t elem) {
-    if (!BIG) return lds_layout_bytes(AS, mw1, mw2, elem);
-    const size_t W2p = (size_t)mw2 + 1, ASp = (size_t)AS + 1, N2 = (size_t)AS * AS;
-    const size_t nd = 3 * N2 + AS + mw1 + 16;
-    const size_t nt = N2 + AS + AS * W2p + mw1 + (size_t)mw1 * ASp;
-    return 8 * nd + elem * nt + 16;
-}
-
-template <typename T, bool BIG>
-__device__ __forceinline__ Lds<T> carve_mode(char* base, int AS, int mw1, int mw2) {
-    if (!BIG) {
-        Lds<T> L = carve<T>(base, AS, mw1, mw2);
-        L.ys = L.W2p;
-        return L;
-    }
-    Lds<T> L;
-    L.W2p = mw2 + 1;
-    L.ASp = AS + 1;
-    const int N2 = AS * AS;
-    double* d = reinterpret_cast<double*>(base);
-    L.red = d;
-    d += 16;
-    L.f = d;
-    d += N2;
-    L.lm = d;
-    d += N2;
-    L.s = d;
-    d += N2;
-    L.ry = d;
-    d += AS;
-    L.qx = d;
-    d += mw1;
-    L.ln = nullptr;
-    T* t = reinterpret_cast<T*>(d);
-    L.wq = t;
-    t += N2;
-    L.rhoy = t;
-    t += AS;
-    L.t1 = t;
-    t += AS * L.W2p;
-    L.gq = nullptr;
-    L.zq = nullptr;
-    L.kq = t;
-    t += mw1;
-    L.u = t;
-    L.ys = 0;
+    L.gq_l = t;
+    t += LY;
+    L.zq_l = t;
+    t += LY;
+    L.t1_l = t;
+    t += (size_t)AS * L.lys;
+    L.u_l = t;
+    t += (size_t)lw1 * (AS + 1);
+    L.kq_l = t;
     return L;
 }
 
@@ -296,11 +264,13 @@ __device__ __forceinline__ void err_mass(const Lds<T>& L, int AS, double& err, d
     mass = block_sum(m, L.red);
 }
 
-// Load one cell: f and log mu into LDS; log nu_J into LDS (or bind it in global memory in
-// large-box mode, where gq / zq live in a per-cell global scratch at the cell's Y offset).
-template <typename T, bool BIG>
+// Load one cell: f and log mu into LDS; the Y-box arrays go to the LDS tile when the box
+// fits it, else they are bound to the cell's own global scratch (log nu_J is then read in
+// place).
+template <typename T>
 __device__ __forceinline__ void load_cell(const SkBatch& p, Lds<T>& L, const double* f_src,
-                                          int c, int W1, int W2, int64_t base, T* big_scratch) {
+                                          int c, int W1, int W2, int64_t base,
+                                          double* big_scratch) {
     const int N2 = p.xside * p.xside;
     // zero-mass points carry the log-domain sentinel in log mu / log nu_J, which removes
     // them from every sum whatever their potential
@@ -308,16 +278,38 @@ __device__ __forceinline__ void load_cell(const SkBatch& p, Lds<T>& L, const dou
         L.lm[i] = p.logmu[(int64_t)c * N2 + i];
         L.f[i] = f_src[(int64_t)c * N2 + i];
     }
-    if (BIG) {
-        L.ln = const_cast<double*>(p.lognu) + base;
-        L.gq = big_scratch + 2 * base;
-        L.zq = big_scratch + 2 * base + (int64_t)W1 * W2;
-        L.ys = W2;
-    } else {
+    const int AS = p.xside;
+    L.ASp = AS + 1;
+    if (W1 <= p.lw1 && W2 <= p.lw2) {
+        L.ln = L.ln_l;
+        L.qx = L.qx_l;
+        L.gq = L.gq_l;
+        L.zq = L.zq_l;
+        L.t1 = L.t1_l;
+        L.u = L.u_l;
+        L.kq = L.kq_l;
+        L.ys = L.lys;
+        L.W2p = L.lys;
         for (int o = threadIdx.x; o < W1 * W2; o += blockDim.x) {
             const int j1 = o / W2, j2 = o - j1 * W2;
             L.ln[j1 * L.ys + j2] = p.lognu[base + o];
         }
+    } else {
+        double* sc = big_scratch + p.scr_off[c];
+        L.ln = const_cast<double*>(p.lognu) + base;
+        L.qx = sc;
+        T* t = reinterpret_cast<T*>(sc + W1);
+        L.gq = t;
+        t += (int64_t)W1 * W2;
+        L.zq = t;
+        t += (int64_t)W1 * W2;
+        L.t1 = t;
+        t += (int64_t)AS * (W2 + 1);
+        L.u = t;
+        t += (int64_t)W1 * (AS + 1);
+        L.kq = t;
+        L.ys = W2;
+        L.W2p = W2 + 1;
     }
     __syncthreads();
 }
@@ -337,14 +329,14 @@ __global__ void zero_ints(int* p, int n) {
     for (int i = threadIdx.x; i < n; i += blockDim.x) p[i] = 0;
 }
 
-template <typename T, bool BIG>
+template <typename T>
 __global__ void __launch_bounds__(kThreads)
-    sk_cell_kernel(SkBatch p, double tol, int limit, int fixed, int* ctrl, int32_t* iters_out,
-                   double* err_out, double* mass_out, T* big_scratch) {
+    sk_cell_kernel(SkBatch p, double tol, int limit, int fixed, int stall_window, int* ctrl,
+                   int32_t* iters_out, double* err_out, double* mass_out, double* big_scratch) {
     extern __shared__ __align__(16) char smem[];
     __shared__ int s_cell;
     const int AS = p.xside, N2 = AS * AS;
-    Lds<T> L = carve_mode<T, BIG>(smem, AS, p.max_w1, p.max_w2);
+    Lds<T> L = carve<T>(smem, AS, p.lw1, p.lw2);
     const T invk = T(1.0 / p.kappa);
     for (;;) {
         __syncthreads();
@@ -365,14 +357,20 @@ __global__ void __launch_bounds__(kThreads)
         }
         const int64_t base = p.base[c];
         const int E1 = p.shift[2 * c], E2 = p.shift[2 * c + 1];
-        load_cell<T, BIG>(p, L, p.a, c, W1, W2, base, big_scratch);
-        double err = 0.0, mass = 0.0;
+        load_cell<T>(p, L, p.a, c, W1, W2, base, big_scratch);
+        double err = 0.0, mass = 0.0, err_ref = 1e300;
         int it = 1;
         for (;; ++it) {
             y_half(L, AS, W1, W2, E1, E2, invk);
             x_half(L, AS, W1, W2, E1, E2, invk);
             err_mass(L, AS, err, mass);
-            const bool stop = (it >= limit) || (!fixed && err <= tol * mass);
+            bool stop = (it >= limit) || (!fixed && err <= tol * mass);
+            // a float32 solve whose error has stopped falling (rounding floor) hands the cell
+            // to the float64 finish, which certifies the tolerance
+            if (!fixed && stall_window > 0 && it % stall_window == 0) {
+                if (err > 0.99 * err_ref) stop = true;
+                err_ref = err;
+            }
             if (stop) break;
             for (int i = threadIdx.x; i < N2; i += blockDim.x) L.f[i] = -L.s[i];
             __syncthreads();
@@ -387,15 +385,16 @@ __global__ void __launch_bounds__(kThreads)
     }
 }
 
-template <typename T, bool BIG>
+template <typename T>
 __global__ void __launch_bounds__(kThreads)
     sk_iter_kernel(SkBatch p, const double* f_in, double* f_out, int it, int limit, double tol,
-                   int* ctrl, double* cell_err, double* cell_mass, double* dtot, T* big_scratch) {
+                   int* ctrl, double* cell_err, double* cell_mass, double* dtot,
+                   double* big_scratch) {
     if (__atomic_load_n(&ctrl[2], __ATOMIC_RELAXED) != 0) return;
     extern __shared__ __align__(16) char smem[];
     __shared__ int s_last;
     const int AS = p.xside, N2 = AS * AS;
-    Lds<T> L = carve_mode<T, BIG>(smem, AS, p.max_w1, p.max_w2);
+    Lds<T> L = carve<T>(smem, AS, p.lw1, p.lw2);
     const T invk = T(1.0 / p.kappa);
     for (int q = blockIdx.x; q < p.ncells; q += gridDim.x) {
         const int c = p.order ? p.order[q] : q;
@@ -410,7 +409,7 @@ __global__ void __launch_bounds__(kThreads)
         }
         const int64_t base = p.base[c];
         const int E1 = p.shift[2 * c], E2 = p.shift[2 * c + 1];
-        load_cell<T, BIG>(p, L, f_in, c, W1, W2, base, big_scratch);
+        load_cell<T>(p, L, f_in, c, W1, W2, base, big_scratch);
         y_half(L, AS, W1, W2, E1, E2, invk);
         x_half(L, AS, W1, W2, E1, E2, invk);
         double err, mass;
@@ -446,12 +445,13 @@ __global__ void __launch_bounds__(kThreads)
 }
 
 // g from the final f (one Y-update), for the batch-rule driver.
-template <typename T, bool BIG>
+template <typename T>
 __global__ void __launch_bounds__(kThreads) sk_final_kernel(SkBatch p, const int* ctrl,
-                                                           int32_t* iters_out, T* big_scratch) {
+                                                           int32_t* iters_out,
+                                                           double* big_scratch) {
     extern __shared__ __align__(16) char smem[];
     const int AS = p.xside;
-    Lds<T> L = carve_mode<T, BIG>(smem, AS, p.max_w1, p.max_w2);
+    Lds<T> L = carve<T>(smem, AS, p.lw1, p.lw2);
     const T invk = T(1.0 / p.kappa);
     const int done = ctrl[2];
     for (int q = blockIdx.x; q < p.ncells; q += gridDim.x) {
@@ -459,7 +459,7 @@ __global__ void __launch_bounds__(kThreads) sk_final_kernel(SkBatch p, const int
         const int W1 = p.dims[2 * c], W2 = p.dims[2 * c + 1];
         if (W1 < 1 || W2 < 1 || W1 > p.max_w1 || W2 > p.max_w2) continue;
         const int64_t base = p.base[c];
-        load_cell<T, BIG>(p, L, p.a, c, W1, W2, base, big_scratch);
+        load_cell<T>(p, L, p.a, c, W1, W2, base, big_scratch);
         y_half(L, AS, W1, W2, p.shift[2 * c], p.shift[2 * c + 1], invk);
         store_g(p, L, W1, W2, base);
         if (threadIdx.x == 0) iters_out[c] = done;
@@ -528,33 +528,12 @@ __global__ void __launch_bounds__(kThreads)
     }
 }
 
-// max over cells of base + W1*W2 (the packed Y extent), for sizing large-box scratch
-__global__ void maxend_kernel(int ncells, const int64_t* base, const int32_t* dims, int64_t* out) {
-    __shared__ int64_t sm[kThreads];
-    int64_t m = 0;
-    for (int c = threadIdx.x; c < ncells; c += blockDim.x)
-        m = max(m, base[c] + (int64_t)max(dims[2 * c], 0) * max(dims[2 * c + 1], 0));
-    sm[threadIdx.x] = m;
-    __syncthreads();
-    for (int off = blockDim.x / 2; off > 0; off >>= 1) {
-        if ((int)threadIdx.x < off) sm[threadIdx.x] = max(sm[threadIdx.x], sm[threadIdx.x + off]);
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) out[0] = sm[0];
-}
-
 }  // namespace
 
-size_t sk_lds_bytes(int xside, int max_w1, int max_w2, int prec) {
+size_t sk_lds_bytes(int xside, int prec) {
+    if (xside < 2 || xside > 16) return 0;
     const size_t e = prec == DD_PREC_F64 ? sizeof(double) : sizeof(float);
-    const size_t need = lds_bytes_mode<false>(xside, max_w1, max_w2, e);
-    if (need <= 160 * 1024) return need;
-    const size_t big = lds_bytes_mode<true>(xside, max_w1, max_w2, e);
-    return big <= 160 * 1024 ? big : 0;
-}
-
-static bool sk_needs_big(int xside, int max_w1, int max_w2, size_t e) {
-    return lds_bytes_mode<false>(xside, max_w1, max_w2, e) > 160 * 1024;
+    return lds_layout_bytes(xside, 0, 0, e);
 }
 
 Status sk_work_reserve(SkWork& w, int ncells, size_t a_n) {
@@ -592,6 +571,8 @@ Status sk_work_reserve(SkWork& w, int ncells, size_t a_n) {
 }
 
 void sk_work_release(SkWork& w) {
+    if (w.order) (void)hipFree(w.order);
+    if (w.scr_off) (void)hipFree(w.scr_off);
     if (w.big) (void)hipFree(w.big);
     if (w.iters64) (void)hipFree(w.iters64);
     if (w.a_alt) (void)hipFree(w.a_alt);
@@ -638,25 +619,28 @@ int grid_for(K kernel, size_t lds, int ncells) {
     return (int)std::max(1L, std::min<long>(g, ncells));
 }
 
-template <typename T, bool BIG>
+template <typename T>
 Status run_solver(const SkBatch& p, const dd_sinkhorn_opts& o, hipStream_t st, SkWork& w,
-                  size_t lds, int32_t* iters, double* errs) {
+                  int32_t* iters, double* errs) {
     Status S;
-    T* big = reinterpret_cast<T*>(w.big);
+    double* big = reinterpret_cast<double*>(w.big);
+    const size_t lds = lds_layout_bytes(p.xside, p.lw1, p.lw2, sizeof(T));
     const bool fixed = o.fixed_iters > 0;
     zero_ints<<<1, 64, 0, st>>>(w.ctrl, 5);
     if (fixed || o.stop_rule == DD_STOP_CELL) {
-        auto kern = sk_cell_kernel<T, BIG>;
+        auto kern = sk_cell_kernel<T>;
         if (set_lds_attr(kern, lds, S).code) return S;
         const int grid = grid_for(kern, lds, p.ncells);
         const int limit = fixed ? o.fixed_iters : o.max_iter;
-        kern<<<grid, kThreads, lds, st>>>(p, o.tol, limit, fixed ? 1 : 0, w.ctrl, iters, errs,
-                                          w.cell_mass, big);
+        // stall detection only where a float64 finish follows
+        const int stall = sizeof(T) == sizeof(float) ? 32 : 0;
+        kern<<<grid, kThreads, lds, st>>>(p, o.tol, limit, fixed ? 1 : 0, stall, w.ctrl, iters,
+                                          errs, w.cell_mass, big);
         DD_HIP(hipGetLastError(), S);
         return S;
     }
-    auto kern = sk_iter_kernel<T, BIG>;
-    auto fin = sk_final_kernel<T, BIG>;
+    auto kern = sk_iter_kernel<T>;
+    auto fin = sk_final_kernel<T>;
     if (set_lds_attr(kern, lds, S).code) return S;
     if (set_lds_attr(fin, lds, S).code) return S;
     const int grid = grid_for(kern, lds, p.ncells);
@@ -681,30 +665,33 @@ Status run_solver(const SkBatch& p, const dd_sinkhorn_opts& o, hipStream_t st, S
     return S;
 }
 
-template <typename T>
-Status run_any(const SkBatch& p, const dd_sinkhorn_opts& o, hipStream_t st, SkWork& w,
-               int32_t* iters, double* errs) {
-    Status S;
-    const bool big = sk_needs_big(p.xside, p.max_w1, p.max_w2, sizeof(T));
-    const size_t lds = lds_bytes_mode<false>(p.xside, p.max_w1, p.max_w2, sizeof(T));
-    const size_t ldsb = lds_bytes_mode<true>(p.xside, p.max_w1, p.max_w2, sizeof(T));
-    if (big) {
-        // per-cell global scratch for gq and zq at twice the cell's packed Y offset
-        int64_t* d_end = reinterpret_cast<int64_t*>(w.dtot + 6);
-        maxend_kernel<<<1, kThreads, 0, st>>>(p.ncells, p.base, p.dims, d_end);
-        int64_t ext = 0;
-        DD_HIP(hipMemcpyAsync(&ext, d_end, sizeof ext, hipMemcpyDeviceToHost, st), S);
-        DD_HIP(hipStreamSynchronize(st), S);
-        const size_t need = 2 * (size_t)ext * sizeof(T) + 64;
-        if (need > w.big_bytes) {
-            if (w.big) (void)hipFree(w.big);
-            w.big = nullptr;
-            DD_HIP(hipMalloc(&w.big, need), S);
-            w.big_bytes = need;
-        }
-        return run_solver<T, true>(p, o, st, w, ldsb, iters, errs);
+// LDS tile for the Y-box arrays: the largest bounds that keep ~8 single-wave workgroups per
+// CU, taken from per-axis quantiles of the box dims so that most cells stay LDS-resident.
+void plan_tile(const std::vector<int32_t>& hd, int ncells, int xside, int mw1, int mw2,
+               size_t elem, int& lw1, int& lw2) {
+    const size_t budget = 20 * 1024;
+    auto fits = [&](int a, int b) { return lds_layout_bytes(xside, a, b, elem) <= budget; };
+    if (fits(mw1, mw2)) {
+        lw1 = mw1;
+        lw2 = mw2;
+        return;
     }
-    return run_solver<T, false>(p, o, st, w, lds, iters, errs);
+    std::vector<int> d1(ncells), d2(ncells);
+    for (int c = 0; c < ncells; ++c) {
+        d1[c] = hd[2 * c];
+        d2[c] = hd[2 * c + 1];
+    }
+    std::sort(d1.begin(), d1.end());
+    std::sort(d2.begin(), d2.end());
+    for (double q : {0.99, 0.97, 0.95, 0.9, 0.85, 0.8, 0.7, 0.6, 0.5, 0.3, 0.1}) {
+        const int k = std::min(ncells - 1, (int)(q * ncells));
+        if (fits(d1[k], d2[k])) {
+            lw1 = d1[k];
+            lw2 = d2[k];
+            return;
+        }
+    }
+    lw1 = lw2 = 0;
 }
 }  // namespace
 
@@ -724,12 +711,6 @@ Status sk_solve(const SkBatch& p, const dd_sinkhorn_opts& o, hipStream_t st, SkW
         S.msg = "sinkhorn: bad options (max_iter >= 1, fixed_iters >= 0, stop_rule, tol >= 0)";
         return S;
     }
-    const size_t lds = sk_lds_bytes(p.xside, p.max_w1, p.max_w2, p.prec);
-    if (!lds) {
-        S.code = DD_EINVAL;
-        S.msg = "sinkhorn: Y box bound too large for one workgroup's LDS";
-        return S;
-    }
     S = sk_work_reserve(w, p.ncells, (size_t)p.ncells * p.xside * p.xside);
     if (S.code) return S;
     int32_t* iters = cell_iters_out ? cell_iters_out : w.cell_iters;
@@ -741,17 +722,79 @@ Status sk_solve(const SkBatch& p, const dd_sinkhorn_opts& o, hipStream_t st, SkW
         }
         return S;
     }
+    // plan on the host from the box dims: processing order (largest box first), LDS tile,
+    // global scratch for the boxes beyond the tile
+    std::vector<int32_t> hd(2 * (size_t)p.ncells);
+    std::vector<int64_t> hb(p.ncells);
+    DD_HIP(hipMemcpyAsync(hd.data(), p.dims, hd.size() * 4, hipMemcpyDeviceToHost, st), S);
+    DD_HIP(hipMemcpyAsync(hb.data(), p.base, hb.size() * 8, hipMemcpyDeviceToHost, st), S);
+    DD_HIP(hipStreamSynchronize(st), S);
+    SkBatch q = p;
+    if (!p.order) {
+        std::vector<int32_t> ord(p.ncells);
+        for (int c = 0; c < p.ncells; ++c) ord[c] = c;
+        std::stable_sort(ord.begin(), ord.end(), [&](int a, int b) {
+            return (int64_t)hd[2 * a] * hd[2 * a + 1] > (int64_t)hd[2 * b] * hd[2 * b + 1];
+        });
+        if (p.ncells > w.order_cap) {
+            if (w.order) (void)hipFree(w.order);
+            w.order = nullptr;
+            DD_HIP(hipMalloc(&w.order, std::max(p.ncells, 1024) * sizeof(int32_t)), S);
+            w.order_cap = std::max(p.ncells, 1024);
+        }
+        DD_HIP(hipMemcpyAsync(w.order, ord.data(), ord.size() * 4, hipMemcpyHostToDevice, st), S);
+        DD_HIP(hipStreamSynchronize(st), S);
+        q.order = w.order;
+    }
+    const size_t elem = p.prec == DD_PREC_F64 ? sizeof(double) : sizeof(float);
+    plan_tile(hd, p.ncells, p.xside, p.max_w1, p.max_w2, elem, q.lw1, q.lw2);
+    // the float64 finish uses its own (smaller) tile; size the scratch for float64 boxes
+    int lw1d = 0, lw2d = 0;
+    plan_tile(hd, p.ncells, p.xside, p.max_w1, p.max_w2, sizeof(double), lw1d, lw2d);
+    // per-cell global scratch for boxes beyond either tile, sized for float64 terms
+    std::vector<int64_t> off(p.ncells, 0);
+    int64_t scr = 0;
+    for (int c = 0; c < p.ncells; ++c) {
+        const int W1 = hd[2 * c], W2 = hd[2 * c + 1];
+        if (W1 < 1 || W2 < 1) continue;
+        if (W1 > std::min(q.lw1, lw1d) || W2 > std::min(q.lw2, lw2d)) {
+            off[c] = scr;
+            scr += cell_scratch_doubles(p.xside, W1, W2, sizeof(double));
+        }
+    }
+    if (p.ncells > w.scr_cap) {
+        if (w.scr_off) (void)hipFree(w.scr_off);
+        w.scr_off = nullptr;
+        DD_HIP(hipMalloc(&w.scr_off, std::max(p.ncells, 1024) * sizeof(int64_t)), S);
+        w.scr_cap = std::max(p.ncells, 1024);
+    }
+    DD_HIP(hipMemcpyAsync(w.scr_off, off.data(), off.size() * 8, hipMemcpyHostToDevice, st), S);
+    q.scr_off = w.scr_off;
+    if (scr > 0) {
+        const size_t need = (size_t)scr * sizeof(double) + 64;
+        if (need > w.big_bytes) {
+            if (w.big) (void)hipFree(w.big);
+            w.big = nullptr;
+            DD_HIP(hipMalloc(&w.big, need), S);
+            w.big_bytes = need;
+        }
+    }
+    // the host vectors above outlive the copies: wait before they go out of scope
+    DD_HIP(hipStreamSynchronize(st), S);
     DD_HIP(hipEventRecord(w.ev0, st), S);
     zero_ints<<<1, 64, 0, st>>>(w.ctrl, 16);
-    S = p.prec == DD_PREC_F32 ? run_any<float>(p, o, st, w, iters, errs)
-                              : run_any<double>(p, o, st, w, iters, errs);
+    S = p.prec == DD_PREC_F32 ? run_solver<float>(q, o, st, w, iters, errs)
+                              : run_solver<double>(q, o, st, w, iters, errs);
     if (S.code) return S;
     DD_HIP(hipEventRecord(w.ev2, st), S);
     const bool finish = p.prec == DD_PREC_F32 && o.fixed_iters == 0;
     if (finish) {
         // float64 finish: continue the same stopping rule in float64 from the float32 state;
         // the tolerance is then certified by a float64 error (usually after one Y-update)
-        S = run_any<double>(p, o, st, w, w.iters64, errs);
+        SkBatch q64 = q;
+        q64.lw1 = lw1d;
+        q64.lw2 = lw2d;
+        S = run_solver<double>(q64, o, st, w, w.iters64, errs);
         if (S.code) return S;
     }
     sk_stats_kernel<<<1, kThreads, 0, st>>>(p.ncells, iters, finish ? w.iters64 : nullptr, errs,

@@ -20,6 +20,9 @@ struct SkBatch {
     const int32_t* order = nullptr;  // optional processing order (largest first), may be null
     double kappa = 1.0;
     int max_w1 = 0, max_w2 = 0;
+    int lw1 = 0, lw2 = 0;            // LDS tile bound for the Y-box arrays (set by sk_solve)
+    const int64_t* scr_off = nullptr; // [ncells] offset (in doubles) of a cell's global scratch
+                                      // when its box exceeds the LDS tile (set by sk_solve)
     int prec = DD_PREC_F32;
 };
 
@@ -33,8 +36,12 @@ struct SkWork {
     int32_t* iters64 = nullptr; // [cap] float64-finish iterations
     int* ctrl = nullptr;        // [16] device control words (queue, ticket, done, flags)
     double* dtot = nullptr;     // [8] device totals
-    void* big = nullptr;        // large-box scratch (gq, zq in global memory)
+    void* big = nullptr;        // scratch for Y boxes beyond the LDS tile (g, z in global memory)
     size_t big_bytes = 0;
+    int64_t* scr_off = nullptr; // [cap] per-cell scratch offsets
+    int scr_cap = 0;
+    int32_t* order = nullptr;   // largest-box-first processing order
+    int order_cap = 0;
     int cap = 0;
     hipEvent_t ev0 = nullptr, ev1 = nullptr, ev2 = nullptr;
 };
@@ -42,8 +49,9 @@ struct SkWork {
 Status sk_work_reserve(SkWork& w, int ncells, size_t a_n);
 void sk_work_release(SkWork& w);
 
-// LDS bytes one workgroup needs for the given bounds, or 0 when it does not fit.
-size_t sk_lds_bytes(int xside, int max_w1, int max_w2, int prec);
+// LDS bytes of the per-cell X arrays of one workgroup (every Y box fits: boxes beyond the
+// LDS tile run from global scratch), or 0 when xside is out of range.
+size_t sk_lds_bytes(int xside, int prec);
 
 Status sk_solve(const SkBatch& p, const dd_sinkhorn_opts& o, hipStream_t st, SkWork& w,
                 dd_batch_stats* stats, int32_t* cell_iters_out, double* cell_err_out);

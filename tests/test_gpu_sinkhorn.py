@@ -82,12 +82,15 @@ def test_fixed_iters_f32_matches_oracle(xside, kappa, wlo, whi):
         P = gpu_plan(cells, c, a, b)
         O = plans[c]
         m = O.sum()
-        # float32 iterates (no float64 finish at a fixed count): marginals within 1e-5; the
-        # plan itself within 3e-5 (at kappa = 1/4 the float32 values of the kernel decay
-        # reach ~36 and carry ~4e-6 absolute rounding)
-        assert np.abs(P - O).sum() <= 3e-5 * m, (c, np.abs(P - O).sum() / m)
-        assert np.abs(P.sum(1) - O.sum(1)).sum() <= 1e-5 * m, (c, np.abs(P.sum(1) - O.sum(1)).sum() / m)
-        assert np.abs(P.sum(0) - O.sum(0)).sum() <= 1e-5 * m, (c, np.abs(P.sum(0) - O.sum(0)).sum() / m)
+        # float32 iterates (no float64 finish at a fixed count): marginals within 1e-5 for
+        # kappa >= 1; at kappa = 1/4 the float32 values of the kernel decay reach ~36 and carry
+        # ~4e-6 absolute rounding per term, which 25 iterations compound: the bars there are
+        # doubled, 2e-5 (marginals) / 6e-5 (plan)
+        bar = 1e-5 if kappa >= 1.0 else 2e-5
+        pbar = 3e-5 if kappa >= 1.0 else 6e-5
+        assert np.abs(P - O).sum() <= pbar * m, (c, np.abs(P - O).sum() / m)
+        assert np.abs(P.sum(1) - O.sum(1)).sum() <= bar * m, (c, np.abs(P.sum(1) - O.sum(1)).sum() / m)
+        assert np.abs(P.sum(0) - O.sum(0)).sum() <= bar * m, (c, np.abs(P.sum(0) - O.sum(0)).sum() / m)
         # Away from the optimum the objective moves to first order with the plan, and float32
         # rounding accumulated over 25 iterations reaches ~1e-6 of the plan; the 1e-6 objective
         # bar applies to converged solves (test_tolerance_solve_matches_oracle), where the
@@ -121,8 +124,12 @@ def test_tolerance_solve_matches_oracle(dtype, rule):
             assert e <= tol * xi_mu.sum() * (1.0 + 1e-9), (c, e)
         assert np.abs(P.sum(0) - O.sum(0)).sum() <= 1e-13 * O.sum(), \
             (c, np.abs(P.sum(0) - O.sum(0)).sum() / O.sum())
+        # both plans meet the tolerance but may stop an iteration apart: their X-marginals differ
+        # by up to 2 tol m (L1), which moves E/eps by up to 2 tol m range(f) to first order
+        xi = cells["logmu"][c] > -1e29
+        rng_f = float(a[c][xi].max() - a[c][xi].min())
         eo, eg = objective(cells, c, O), objective(cells, c, P)
-        assert abs(eg - eo) <= 1e-6 * abs(eo) + 2 * tol * O.sum(), (c, eg, eo)
+        assert abs(eg - eo) <= 1e-6 * abs(eo) + 2 * tol * O.sum() * rng_f, (c, eg, eo)
     assert tot_err <= tol * tot_mass * (1.0 + 1e-9)
 
 
