@@ -72,6 +72,54 @@ def run_steps(ctx, w, n, k0, args, rule, init=None):
     return out
 
 
+def load_net(path):
+    import paper_2405_09400_amd as dd
+    if not path or not os.path.exists(path):
+        return None
+    with np.load(path, allow_pickle=False) as z:
+        return dd.WarmStartNet(z["params"])
+
+
+def time_to_tol(ctx, w, k0, args, rule):
+    """Replay: from each of R consecutive states of the plain trajectory, solve the same
+    half-iteration to the same tolerance with the zero start, the previous-iterate start and
+    the learned start (time = start + Sinkhorn, device clock), then continue the trajectory
+    with the previous-iterate step."""
+    import paper_2405_09400_amd as dd
+    net = load_net(args.net_weights)
+    if net is not None:
+        ctx.set_net(net)
+    eps = w.kappas[-1] / w.N ** 2
+    kinds = [("zero", dd.DD_INIT_ZERO)] + ([("learned_net", dd.DD_INIT_NET)] if net else []) + \
+        [("prev_iterate", dd.DD_INIT_PREV)]
+    rec = {name: {"ms": [], "iters": [], "sinkhorn_ms": [], "init_ms": []} for name, _ in kinds}
+    for r in range(args.replay):
+        ctx.save()
+        for j, (name, init) in enumerate(kinds):
+            if j:
+                ctx.restore()
+            st = ctx.iterate("AB"[(k0 + r) % 2], eps, tol=args.tol, stop_rule=rule,
+                             max_iter=args.max_iter, init=init)
+            d = rec[name]
+            d["sinkhorn_ms"].append(round(st["t_sinkhorn_ms"], 3))
+            d["init_ms"].append(round(st["t_init_ms"], 3))
+            d["ms"].append(round(st["t_sinkhorn_ms"] + st["t_init_ms"], 3))
+            d["iters"].append(st["sk"]["iters_max"])
+    out = {"tol": args.tol, "states": args.replay, "_steps": args.replay}
+    for name, _ in kinds:
+        out[name] = rec[name]
+    if not net:
+        out["learned_net"] = None
+    tot = {name: sum(rec[name]["ms"]) for name, _ in kinds}
+    out["speedup_prev_vs_zero"] = tot["zero"] / tot["prev_iterate"]
+    if net:
+        out["speedup_net_vs_zero"] = tot["zero"] / tot["learned_net"]
+        out["speedup_net_vs_prev"] = tot["prev_iterate"] / tot["learned_net"]
+        ctx.set_net(None)
+        net.close()
+    return out
+
+
 def cpu_baseline(args, w):
     """Oracle dense cell Sinkhorn on a bounded sample: the first composite cells of partition A
     on the workload's initial coupling at kappa = 1, a fixed number of iterations."""
@@ -129,6 +177,9 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-compare", action="store_true")
+    ap.add_argument("--replay", type=int, default=4)
+    ap.add_argument("--net-weights", default=os.path.join(ROOT, "paper_2405_09400_amd", "weights",
+                                                          "warmstart_s4_k1.npz"))
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
@@ -166,19 +217,8 @@ def main():
 
     compare = None
     if not args.no_compare:
-        # time-to-tolerance from the same kind of state: previous-iterate vs zero initialisation
-        prev = run_steps(ctx, w, 2, k, args, rule)
-        k += 2
-        zero = run_steps(ctx, w, 2, k, args, rule, init=dd.DD_INIT_ZERO)
-        k += 2
-        compare = {
-            "tol": args.tol,
-            "prev_iterate": {"sinkhorn_ms": [round(s["t_sinkhorn_ms"], 3) for s in prev],
-                             "iters": [s["sk"]["iters_max"] for s in prev]},
-            "zero": {"sinkhorn_ms": [round(s["t_sinkhorn_ms"], 3) for s in zero],
-                     "iters": [s["sk"]["iters_max"] for s in zero]},
-            "learned_net": None,
-        }
+        compare = time_to_tol(ctx, w, k, args, rule)
+        k += compare.pop("_steps")
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -213,6 +253,8 @@ def main():
         "time_to_tol": compare,
         "detail": {
             "sinkhorn_iters": sk_iters,
+            "finish_f64_iters": [s["sk"]["finish_iters_max"] for s in stats],
+            "main_ms_per_step": sum(s["sk"]["main_ms"] for s in stats) / len(stats),
             "sinkhorn_ms_per_step": sk_ms / len(stats),
             "b2c_ms_per_step": sum(s["t_b2c_ms"] for s in stats) / len(stats),
             "c2b_ms_per_step": sum(s["t_c2b_ms"] for s in stats) / len(stats),

@@ -46,7 +46,7 @@ typedef enum {
 
 enum { DD_PREC_F32 = 0, DD_PREC_F64 = 1 };      /* arithmetic of the cell log-sum-exp */
 enum { DD_STOP_BATCH = 0, DD_STOP_CELL = 1 };   /* Sinkhorn stopping rule             */
-enum { DD_INIT_ZERO = 0, DD_INIT_PREV = 1 };    /* X-potential initialisation         */
+enum { DD_INIT_ZERO = 0, DD_INIT_PREV = 1, DD_INIT_NET = 2 }; /* X-potential start        */
 enum { DD_PART_A = 0, DD_PART_B = 1 };          /* composite partition                */
 
 /* Sinkhorn options (App. A.2.1 "Stopping criterion and measure truncation").
@@ -62,7 +62,7 @@ typedef struct {
     int32_t fixed_iters;  /* 0 = use tol                                           */
     int32_t stop_rule;    /* DD_STOP_BATCH | DD_STOP_CELL                          */
     int32_t check_every;  /* batch rule: test the error every k-th iteration (>=1) */
-    int32_t init;         /* DD_INIT_ZERO | DD_INIT_PREV (domdec_iterate only)     */
+    int32_t init;         /* DD_INIT_ZERO | PREV | NET (domdec_iterate only)      */
     int32_t reserved;     /* must be 0                                             */
 } dd_sinkhorn_opts;
 
@@ -199,6 +199,8 @@ typedef struct {
     double t_sinkhorn_ms;     /* cell solve                                           */
     double t_c2b_ms;          /* CompositeToBasic + balancing + truncation            */
     double t_total_ms;        /* whole iteration (device)                             */
+    double t_init_ms;         /* X-potential start (warm start, or the net's features,
+                                 inference and X-update) before the Sinkhorn solve     */
 } dd_iter_stats;
 
 /*
@@ -312,6 +314,65 @@ void domdec_free(dd_ctx* ctx);
 /* Message of the last error on ctx (or of the last context-free call when ctx is
  * NULL); never NULL. */
 const char* domdec_strerror(const dd_ctx* ctx, dd_status status);
+
+/* Save a copy of the mutable state inside the context -- the basic-cell Y-marginals
+ * and, for both partitions, the X potentials, their gauge offsets and visit flags --
+ * replacing any earlier copy; domdec_restore brings it back (for replaying iterations
+ * from one state, or checkpointing).  After a restore, flow_update / domdec_evaluate
+ * need a new domdec_iterate.  Errors: DD_ENOMEM, DD_EDEVICE, DD_ESTATE (restore with
+ * nothing saved). */
+dd_status domdec_save(dd_ctx* ctx);
+dd_status domdec_restore(dd_ctx* ctx);
+
+/* ------------------------------------------------------------------------------
+ * Learned warm start (not part of the paper's method: an initialisation of the
+ * cell problem's alpha, the input the paper's GPU Sinkhorn already takes, App. A.1).
+ *
+ * A 5-layer convolutional net (3x3 kernels, 32 channels, BF16 weights, FP32
+ * accumulation) maps a 32x32 window of a cell, centred on its X block in the
+ * box-local coordinates of the cell problem, to a predicted Y potential g on the
+ * window; the starting X potential is one exact X-update of it,
+ *   f(i) = -LSE_w [ g(w) + log nu_J(w) - |o + i - w|^2 / kappa ],  o = (32 - 2s)/2.
+ * The stopping rule is untouched: the net changes only where Sinkhorn starts.
+ * Window features (6 channels): nu_J feature max(log(nu_J/m_J) + 16, 0)/4 and its
+ * support, the same for mu on the X block, and the two window coordinates.
+ * ------------------------------------------------------------------------------ */
+typedef struct dd_net dd_net;
+
+/* Number of float parameters: per layer the weights [cout][cin][3][3], then bias [cout]. */
+int64_t dd_net_param_count(void);
+
+/* Create a net from host FP32 parameters (copied; the kernels use their BF16 rounding).
+ * Errors: DD_EINVAL (null, non-finite), DD_ENOMEM, DD_EDEVICE. */
+dd_status dd_net_create(const float* params, dd_net** out);
+
+/* Copy the FP32 master parameters to host memory (dd_net_param_count() floats). */
+dd_status dd_net_params(dd_net* net, float* params_out);
+
+/* Inference on n samples: x (device) [n][6][32][32] float32 -> y (device) [n][32][32]. */
+dd_status dd_net_forward(dd_net* net, int32_t n, const float* x, float* y, void* stream);
+
+/* One Adam step (lr; betas 0.9, 0.999) on the gauge-invariant weighted squared error
+ *   loss_b = sum_w weight (y - target - c)^2,  c = sum_w weight (y - target) / sum_w weight,
+ * averaged over the n samples (device arrays, layouts as dd_net_forward; target and
+ * weight [n][32][32]).  *loss (host, may be null) receives the batch mean before the step. */
+dd_status dd_net_train_step(dd_net* net, int32_t n, const float* x, const float* target,
+                            const float* weight, float lr, void* stream, double* loss);
+
+void dd_net_free(dd_net* net);
+const char* dd_net_strerror(const dd_net* net);
+
+/* Attach a net (borrowed; NULL detaches) for opts.init = DD_INIT_NET. */
+dd_status domdec_set_net(dd_ctx* ctx, dd_net* net);
+
+/* Training samples from the last domdec_iterate: for each composite cell of that
+ * partition, its window features x [n][6][32][32], the solved Y potential on the
+ * window made mean-free under the weights (target [n][32][32]) and the weights
+ * nu_J/m_J (weight [n][32][32]); device float32 buffers of the caller.  Two-call:
+ * with all three buffers NULL only *n is set.  Errors: DD_ESTATE (no iteration
+ * since init or flow_apply), DD_EINVAL (cap < n). */
+dd_status domdec_net_samples(dd_ctx* ctx, float* x, float* target, float* weight,
+                             int32_t cap, int32_t* n);
 
 #ifdef __cplusplus
 }

@@ -14,7 +14,7 @@ _LIB = None
 DD_OK, DD_NOTCONV, DD_EINVAL, DD_ENOMEM, DD_EDEVICE, DD_ESTATE, DD_ENUMERIC = 0, 1, -1, -2, -3, -4, -5
 DD_PREC_F32, DD_PREC_F64 = 0, 1
 DD_STOP_BATCH, DD_STOP_CELL = 0, 1
-DD_INIT_ZERO, DD_INIT_PREV = 0, 1
+DD_INIT_ZERO, DD_INIT_PREV, DD_INIT_NET = 0, 1, 2
 DD_PART_A, DD_PART_B = 0, 1
 
 _NAMES = {0: "DD_OK", 1: "DD_NOTCONV", -1: "DD_EINVAL", -2: "DD_ENOMEM", -3: "DD_EDEVICE",
@@ -23,7 +23,8 @@ _NAMES = {0: "DD_OK", 1: "DD_NOTCONV", -1: "DD_EINVAL", -2: "DD_ENOMEM", -3: "DD
 # every function include/domdec.h declares
 SYMBOLS = ("sinkhorn_batch", "sinkhorn_batch_f64", "domdec_init", "domdec_iterate", "flow_update",
            "flow_costs", "flow_apply", "dd_mcf_solve", "extract_plan", "domdec_evaluate", "domdec_free",
-           "domdec_strerror")
+           "domdec_strerror", "dd_net_param_count", "dd_net_create", "dd_net_params", "dd_net_forward",
+           "dd_net_train_step", "dd_net_free", "dd_net_strerror", "domdec_set_net", "domdec_net_samples", "domdec_save", "domdec_restore")
 
 
 class DomDecError(RuntimeError):
@@ -56,7 +57,7 @@ class IterStats(ctypes.Structure):
                 ("max_w2", ctypes.c_int32), ("reserved", ctypes.c_int32), ("nu_entries", ctypes.c_int64),
                 ("comp_entries", ctypes.c_int64), ("t_b2c_ms", ctypes.c_double),
                 ("t_sinkhorn_ms", ctypes.c_double), ("t_c2b_ms", ctypes.c_double),
-                ("t_total_ms", ctypes.c_double)]
+                ("t_total_ms", ctypes.c_double), ("t_init_ms", ctypes.c_double)]
 
 
 class FlowStats(ctypes.Structure):
@@ -130,6 +131,28 @@ def lib():
     L.domdec_free.argtypes = [vp]
     L.domdec_strerror.restype = ctypes.c_char_p
     L.domdec_strerror.argtypes = [vp, ctypes.c_int]
+    L.dd_net_param_count.restype = ctypes.c_int64
+    L.dd_net_param_count.argtypes = []
+    fp = ctypes.POINTER(ctypes.c_float)
+    L.dd_net_create.restype = ctypes.c_int
+    L.dd_net_create.argtypes = [fp, ctypes.POINTER(vp)]
+    L.dd_net_params.restype = ctypes.c_int
+    L.dd_net_params.argtypes = [vp, fp]
+    L.dd_net_forward.restype = ctypes.c_int
+    L.dd_net_forward.argtypes = [vp, ctypes.c_int32, vp, vp, vp]
+    L.dd_net_train_step.restype = ctypes.c_int
+    L.dd_net_train_step.argtypes = [vp, ctypes.c_int32, vp, vp, vp, ctypes.c_float, vp, dp]
+    L.dd_net_free.restype = None
+    L.dd_net_free.argtypes = [vp]
+    L.dd_net_strerror.restype = ctypes.c_char_p
+    L.dd_net_strerror.argtypes = [vp]
+    L.domdec_set_net.restype = ctypes.c_int
+    L.domdec_set_net.argtypes = [vp, vp]
+    for name in ("domdec_save", "domdec_restore"):
+        getattr(L, name).restype = ctypes.c_int
+        getattr(L, name).argtypes = [vp]
+    L.domdec_net_samples.restype = ctypes.c_int
+    L.domdec_net_samples.argtypes = [vp, vp, vp, vp, ctypes.c_int32, i32p]
     _LIB = L
     return L
 
@@ -266,6 +289,35 @@ class DomDec:
         d["status"] = status
         return d
 
+    def save(self) -> None:
+        """Keep a copy of the mutable state (domdec_save)."""
+        _check(lib().domdec_save(self._ctx), self._ctx)
+
+    def restore(self) -> None:
+        """Return to the saved state (domdec_restore)."""
+        _check(lib().domdec_restore(self._ctx), self._ctx)
+
+    def set_net(self, net: Optional["WarmStartNet"]) -> None:
+        """Attach a warm-start net for init=DD_INIT_NET (the object must outlive its use)."""
+        self._net = net
+        _check(lib().domdec_set_net(self._ctx, net._net if net is not None else None), self._ctx)
+
+    def net_samples(self):
+        """(x [n,6,32,32], target [n,32,32], weight [n,32,32]) float32 device tensors of the
+        cells of the last iteration (features, solved Y potential, weights)."""
+        import torch
+        n = ctypes.c_int32(0)
+        _check(lib().domdec_net_samples(self._ctx, None, None, None, 0, ctypes.byref(n)), self._ctx)
+        k = int(n.value)
+        dev = torch.device("cuda", torch.cuda.current_device())
+        x = torch.empty((k, 6, 32, 32), dtype=torch.float32, device=dev)
+        t = torch.empty((k, 32, 32), dtype=torch.float32, device=dev)
+        w = torch.empty((k, 32, 32), dtype=torch.float32, device=dev)
+        self._stream.synchronize()
+        _check(lib().domdec_net_samples(self._ctx, _ptr(x), _ptr(t), _ptr(w), k, ctypes.byref(n)),
+               self._ctx)
+        return x, t, w
+
     def flow_update(self) -> dict:
         st = FlowStats()
         _check(lib().flow_update(self._ctx, ctypes.byref(st)), self._ctx)
@@ -319,3 +371,70 @@ class DomDec:
             keep = v > 0
             out.append((idx[keep].astype(np.int64), v[keep]))
         return out
+
+
+def net_param_count() -> int:
+    return int(lib().dd_net_param_count())
+
+
+class WarmStartNet:
+    """The learned warm-start conv net (dd_net): BF16 weights, FP32 accumulation, trained with
+    Adam by hand-written kernels.  `params` is the flat FP32 parameter vector."""
+
+    def __init__(self, params: np.ndarray):
+        p = np.ascontiguousarray(params, dtype=np.float32).reshape(-1)
+        if p.size != net_param_count():
+            raise ValueError(f"expected {net_param_count()} parameters, got {p.size}")
+        h = ctypes.c_void_p()
+        st = lib().dd_net_create(p.ctypes.data_as(ctypes.POINTER(ctypes.c_float)), ctypes.byref(h))
+        if st != DD_OK:
+            raise DomDecError(st, lib().dd_net_strerror(None).decode())
+        self._net = h
+
+    def _check(self, st):
+        if st != DD_OK:
+            raise DomDecError(st, lib().dd_net_strerror(self._net).decode())
+
+    def params(self) -> np.ndarray:
+        out = np.zeros(net_param_count(), np.float32)
+        self._check(lib().dd_net_params(self._net, out.ctypes.data_as(ctypes.POINTER(ctypes.c_float))))
+        return out
+
+    def forward(self, x, stream=None):
+        import torch
+        n = int(x.shape[0])
+        y = torch.empty((n, 32, 32), dtype=torch.float32, device=x.device)
+        s = stream if stream is not None else torch.cuda.current_stream()
+        self._check(lib().dd_net_forward(self._net, n, _ptr(x.contiguous()), _ptr(y), _stream_ptr(s)))
+        return y
+
+    def train_step(self, x, target, weight, lr: float, stream=None) -> float:
+        import torch
+        s = stream if stream is not None else torch.cuda.current_stream()
+        loss = ctypes.c_double(0.0)
+        self._check(lib().dd_net_train_step(self._net, int(x.shape[0]), _ptr(x), _ptr(target), _ptr(weight),
+                                            float(lr), _stream_ptr(s), ctypes.byref(loss)))
+        return float(loss.value)
+
+    def close(self):
+        if getattr(self, "_net", None):
+            lib().dd_net_free(self._net)
+            self._net = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def net_init_params(seed: int = 0) -> np.ndarray:
+    """He-normal weights, zero biases, in the dd_net parameter layout (seeded)."""
+    rng = np.random.default_rng(seed)
+    layers = [(6, 32), (32, 32), (32, 32), (32, 32), (32, 4)]
+    out = []
+    for l, (cin, cout) in enumerate(layers):
+        std = np.sqrt(2.0 / (cin * 9)) if l < len(layers) - 1 else np.sqrt(1.0 / (cin * 9))
+        out.append(rng.normal(0.0, std, cout * cin * 9))
+        out.append(np.zeros(cout))
+    return np.concatenate(out).astype(np.float32)

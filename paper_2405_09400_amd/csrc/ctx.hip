@@ -16,6 +16,7 @@
 #include "cells.hpp"
 #include "ctx.hpp"
 #include "eval.hpp"
+#include "net.hpp"
 #include "sinkhorn.hpp"
 
 using namespace dd;
@@ -91,6 +92,15 @@ void dd_ctx_release(dd_ctx* c) {
     F(c->d_nuJ);
     F(c->d_lognu);
     F(c->d_b);
+    F(c->d_nx);
+    F(c->d_ng);
+    F(c->snap.box);
+    F(c->snap.base);
+    F(c->snap.data);
+    for (int q = 0; q < 2; ++q) {
+        F(c->snap.a[q]);
+        F(c->snap.gst[q]);
+    }
     F(c->d_tmp);
     F(c->d_py2);
     F(c->d_nsize);
@@ -354,8 +364,22 @@ static dd_status iterate_impl(dd_ctx* c, int p, double eps, const dd_sinkhorn_op
     const double* logmu = c->d_logmu[p];
     launch_b2c(P, c->S, c->C, c->d_nuJ, lognu, hs);
     (void)hipEventRecord(c->ev[1], hs);
-    const int use_prev = (o.init == DD_INIT_PREV && c->visited[p]) ? 1 : 0;
-    launch_warm_start(P, c->C, c->AS, apot, c->d_gst[p], c->kappa_a[p], kappa, use_prev, hs);
+    if (o.init == DD_INIT_NET) {
+        // learned start: features -> net -> one X-update of the predicted Y potential
+        if (grow(c->d_nx, c->nx_cap, (size_t)nc * kNetCin * kNetWin * kNetWin, st).code ||
+            grow(c->d_ng, c->ng_cap, (size_t)nc * kNetWin * kNetWin, st).code)
+            return fail(c, st);
+        launch_net_features(nc, c->AS, c->C.dims, c->C.shift, c->C.base, logmu, lognu, nullptr,
+                            c->d_nx, nullptr, nullptr, hs);
+        const Status ns = net_forward(c->net, nc, c->d_nx, c->d_ng, hs);
+        if (ns.code) return fail(c, ns);
+        launch_net_finit(nc, c->AS, c->C.dims, c->C.shift, c->C.base, lognu, c->C.gofs, c->d_ng,
+                         kappa, apot, c->d_gst[p], hs);
+    } else {
+        const int use_prev = (o.init == DD_INIT_PREV && c->visited[p]) ? 1 : 0;
+        launch_warm_start(P, c->C, c->AS, apot, c->d_gst[p], c->kappa_a[p], kappa, use_prev, hs);
+    }
+    (void)hipEventRecord(c->ev[4], hs);
     SkBatch B;
     B.ncells = nc;
     B.xside = c->AS;
@@ -417,6 +441,8 @@ static dd_status iterate_impl(dd_ctx* c, int p, double eps, const dd_sinkhorn_op
         s.t_c2b_ms = t;
         (void)hipEventElapsedTime(&t, c->ev[0], c->ev[3]);
         s.t_total_ms = t;
+        (void)hipEventElapsedTime(&t, c->ev[1], c->ev[4]);
+        s.t_init_ms = t;
         *out = s;
     }
     if (ss.code == DD_NOTCONV) {
@@ -433,8 +459,11 @@ extern "C" dd_status domdec_iterate(dd_ctx* c, int32_t partition, double eps,
         return fail(c, DD_EINVAL, "domdec_iterate: partition must be DD_PART_A or DD_PART_B");
     if (!(eps > 0.0) || !std::isfinite(eps))
         return fail(c, DD_EINVAL, "domdec_iterate: eps must be positive and finite");
-    if (o->init != DD_INIT_ZERO && o->init != DD_INIT_PREV)
-        return fail(c, DD_EINVAL, "domdec_iterate: init must be DD_INIT_ZERO or DD_INIT_PREV");
+    if (o->init != DD_INIT_ZERO && o->init != DD_INIT_PREV && o->init != DD_INIT_NET)
+        return fail(c, DD_EINVAL,
+                    "domdec_iterate: init must be DD_INIT_ZERO, DD_INIT_PREV or DD_INIT_NET");
+    if (o->init == DD_INIT_NET && !c->net)
+        return fail(c, DD_ESTATE, "domdec_iterate: DD_INIT_NET needs a net (domdec_set_net)");
     return iterate_impl(c, partition, eps, *o, out);
 }
 
@@ -535,4 +564,96 @@ extern "C" void domdec_free(dd_ctx* c) {
 
 extern "C" const char* domdec_strerror(const dd_ctx* c, dd_status) {
     return c ? c->err.c_str() : global_error();
+}
+
+extern "C" dd_status domdec_set_net(dd_ctx* c, dd_net* net) {
+    if (!c) return fail(c, DD_EINVAL, "domdec_set_net: null context");
+    c->net = net;
+    return DD_OK;
+}
+
+extern "C" dd_status domdec_net_samples(dd_ctx* c, float* x, float* target, float* weight,
+                                        int32_t cap, int32_t* n) {
+    if (!c || !n) return fail(c, DD_EINVAL, "domdec_net_samples: null argument");
+    if (c->last_part < 0)
+        return fail(c, DD_ESTATE, "domdec_net_samples: needs a preceding domdec_iterate");
+    const int p = c->last_part;
+    const int nc = c->part[p].ncell;
+    *n = nc;
+    if (!x && !target && !weight) return DD_OK;
+    if (!x || !target || !weight || cap < nc)
+        return fail(c, DD_EINVAL, "domdec_net_samples: buffers missing or cap < cells");
+    launch_net_features(nc, c->AS, c->C.dims, c->C.shift, c->C.base, c->d_logmu[p], c->d_lognu,
+                        c->d_b, x, target, weight, c->st);
+    if (hipStreamSynchronize(c->st) != hipSuccess || hipGetLastError() != hipSuccess)
+        return fail(c, DD_EDEVICE, "domdec_net_samples: kernel failed");
+    return DD_OK;
+}
+
+namespace {
+hipError_t d2d(void* dst, const void* src, size_t bytes, hipStream_t st) {
+    return bytes ? hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToDevice, st) : hipSuccess;
+}
+}  // namespace
+
+extern "C" dd_status domdec_save(dd_ctx* c) {
+    if (!c) return fail(c, DD_EINVAL, "domdec_save: null context");
+    Status st;
+    auto& S = c->snap;
+    const hipStream_t hs = c->st;
+    int64_t ntot = 0;
+    if (hipMemcpyAsync(&ntot, c->S.base + c->nI, sizeof ntot, hipMemcpyDeviceToHost, hs) !=
+            hipSuccess ||
+        hipStreamSynchronize(hs) != hipSuccess)
+        return fail(c, DD_EDEVICE, "domdec_save: copy failed");
+    if ((!S.box && alloc(S.box, 4 * (size_t)c->nI, st).code) ||
+        (!S.base && alloc(S.base, (size_t)c->nI + 1, st).code) ||
+        grow(S.data, S.data_cap, (size_t)std::max<int64_t>(ntot, 1), st).code)
+        return fail(c, st);
+    for (int q = 0; q < 2; ++q) {
+        const size_t nc = c->part[q].ncell;
+        if ((!S.a[q] && alloc(S.a[q], nc * c->AS * c->AS, st).code) ||
+            (!S.gst[q] && alloc(S.gst[q], 2 * nc, st).code))
+            return fail(c, st);
+    }
+    bool ok = d2d(S.box, c->S.box, 4 * (size_t)c->nI * sizeof(int32_t), hs) == hipSuccess &&
+              d2d(S.base, c->S.base, ((size_t)c->nI + 1) * sizeof(int64_t), hs) == hipSuccess &&
+              d2d(S.data, c->S.data, (size_t)ntot * sizeof(double), hs) == hipSuccess;
+    for (int q = 0; q < 2 && ok; ++q) {
+        const size_t nc = c->part[q].ncell;
+        ok = d2d(S.a[q], c->d_a[q], nc * c->AS * c->AS * sizeof(double), hs) == hipSuccess &&
+             d2d(S.gst[q], c->d_gst[q], 2 * nc * sizeof(int32_t), hs) == hipSuccess;
+        S.visited[q] = c->visited[q];
+        S.kappa_a[q] = c->kappa_a[q];
+    }
+    if (!ok || hipStreamSynchronize(hs) != hipSuccess)
+        return fail(c, DD_EDEVICE, "domdec_save: copy failed");
+    S.ntot = ntot;
+    S.valid = true;
+    return DD_OK;
+}
+
+extern "C" dd_status domdec_restore(dd_ctx* c) {
+    if (!c) return fail(c, DD_EINVAL, "domdec_restore: null context");
+    auto& S = c->snap;
+    if (!S.valid) return fail(c, DD_ESTATE, "domdec_restore: nothing saved");
+    Status st;
+    const hipStream_t hs = c->st;
+    if (grow(c->S.data, c->S.cap, (size_t)std::max<int64_t>(S.ntot, 1), st).code)
+        return fail(c, st);
+    bool ok = d2d(c->S.box, S.box, 4 * (size_t)c->nI * sizeof(int32_t), hs) == hipSuccess &&
+              d2d(c->S.base, S.base, ((size_t)c->nI + 1) * sizeof(int64_t), hs) == hipSuccess &&
+              d2d(c->S.data, S.data, (size_t)S.ntot * sizeof(double), hs) == hipSuccess;
+    for (int q = 0; q < 2 && ok; ++q) {
+        const size_t nc = c->part[q].ncell;
+        ok = d2d(c->d_a[q], S.a[q], nc * c->AS * c->AS * sizeof(double), hs) == hipSuccess &&
+             d2d(c->d_gst[q], S.gst[q], 2 * nc * sizeof(int32_t), hs) == hipSuccess;
+        c->visited[q] = S.visited[q];
+        c->kappa_a[q] = S.kappa_a[q];
+    }
+    if (!ok || hipStreamSynchronize(hs) != hipSuccess)
+        return fail(c, DD_EDEVICE, "domdec_restore: copy failed");
+    // the last iteration's composite data no longer belongs to the state
+    c->last_part = -1;
+    return DD_OK;
 }

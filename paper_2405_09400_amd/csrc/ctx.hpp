@@ -8,6 +8,7 @@
 #include "sinkhorn.hpp"
 
 struct FlowState;
+struct dd_net;
 
 struct dd_ctx {
     // problem
@@ -56,6 +57,25 @@ struct dd_ctx {
     int last_mw1 = 0, last_mw2 = 0;
     int untruncated_cells = 0;
     FlowState* flow = nullptr;
+    // learned warm start (borrowed net) and its per-cell buffers
+    dd_net* net = nullptr;
+    float* d_nx = nullptr;  // [cells][6][32][32] features
+    size_t nx_cap = 0;
+    float* d_ng = nullptr;  // [cells][32][32] predicted Y potentials
+    size_t ng_cap = 0;
+    // one saved copy of the mutable state (domdec_save / domdec_restore)
+    struct Snap {
+        bool valid = false;
+        int32_t* box = nullptr;
+        int64_t* base = nullptr;
+        double* data = nullptr;
+        size_t data_cap = 0;
+        int64_t ntot = 0;
+        double* a[2] = {nullptr, nullptr};
+        int32_t* gst[2] = {nullptr, nullptr};
+        bool visited[2] = {false, false};
+        double kappa_a[2] = {1.0, 1.0};
+    } snap;
 };
 
 void dd_ctx_release(dd_ctx* c);

@@ -1,0 +1,663 @@
+// Learned warm start: conv-net inference and training kernels, cell features and the
+// X-update that turns a predicted Y potential into the initial X potential.
+//
+// All kernels are direct 3x3 convolutions on the vector ALUs: one workgroup of 256 lanes
+// per sample, one output pixel per lane (every layer has a 16x16 output), the sample's
+// input and the layer's weights staged in LDS (weights converted from BF16 once per
+// workgroup, laid out [ci][tap][co] so that each lane reads them as broadcasts), FP32
+// accumulation.  Training keeps FP32 master weights with Adam and refreshes the BF16
+// copy after every step.  The weight gradients are reduced over the batch in a fixed
+// order (per-workgroup partials, then one reduction), so training is deterministic.
+#include "net.hpp"
+
+#include <algorithm>
+#include <cmath>
+#include <vector>
+
+namespace dd {
+
+namespace {
+
+constexpr int kT = 256;   // lanes per workgroup == output pixels per layer (16 x 16)
+constexpr int kPix = 256;
+
+ConvDesc make_layers_table(ConvDesc* L) {
+    const int cin[kNetLayers] = {kNetCin, kNetCh, kNetCh, kNetCh, kNetCh};
+    const int cout[kNetLayers] = {kNetCh, kNetCh, kNetCh, kNetCh, 4};
+    const int hin[kNetLayers] = {kNetWin, 16, 16, 16, 16};
+    const int stride[kNetLayers] = {2, 1, 1, 1, 1};
+    const int dil[kNetLayers] = {1, 1, 2, 4, 1};
+    int64_t off = 0;
+    for (int l = 0; l < kNetLayers; ++l) {
+        ConvDesc& d = L[l];
+        d.cin = cin[l];
+        d.cout = cout[l];
+        d.hin = d.win = hin[l];
+        d.hout = d.wout = 16;
+        d.stride = stride[l];
+        d.dil = dil[l];
+        d.pad = dil[l];
+        d.relu = l < kNetLayers - 1;
+        d.woff = off;
+        off += (int64_t)d.cout * d.cin * 9;
+        d.boff = off;
+        off += d.cout;
+    }
+    return L[0];
+}
+
+struct Table {
+    ConvDesc L[kNetLayers];
+    int64_t n;
+    Table() {
+        make_layers_table(L);
+        n = L[kNetLayers - 1].boff + L[kNetLayers - 1].cout;
+    }
+};
+const Table& table() {
+    static const Table t;
+    return t;
+}
+
+__device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
+
+// float -> bfloat16, round to nearest even (finite inputs)
+__device__ __forceinline__ uint16_t f2bf(float f) {
+    uint32_t u = __float_as_uint(f);
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+
+// y = act(conv(x) + b); for the last layer the 4 output channels are pixel-shuffled into
+// the 32x32 output: y[2*oy + a][2*ox + c] = channel 2a + c.
+template <int CO>
+__global__ void __launch_bounds__(kT)
+    conv_fwd_kernel(ConvDesc d, int n, const float* __restrict__ x,
+                    const uint16_t* __restrict__ wbf, const float* __restrict__ params,
+                    float* __restrict__ y, int shuffle) {
+    extern __shared__ float sm[];
+    const int xin = d.cin * d.hin * d.win;
+    float* xs = sm;
+    float* ws = sm + xin;  // [ci][tap][co]
+    for (int k = threadIdx.x; k < d.cin * 9 * CO; k += blockDim.x) {
+        const int co = k % CO, t = (k / CO) % 9, ci = k / (9 * CO);
+        ws[k] = bf2f(wbf[d.woff + ((int64_t)co * d.cin + ci) * 9 + t]);
+    }
+    const int p = threadIdx.x;
+    const int oy = p / d.wout, ox = p % d.wout;
+    float bias[CO];
+#pragma unroll
+    for (int co = 0; co < CO; ++co) bias[co] = params[d.boff + co];
+    for (int b = blockIdx.x; b < n; b += gridDim.x) {
+        __syncthreads();
+        for (int k = threadIdx.x; k < xin; k += blockDim.x) xs[k] = x[(int64_t)b * xin + k];
+        __syncthreads();
+        float acc[CO];
+#pragma unroll
+        for (int co = 0; co < CO; ++co) acc[co] = bias[co];
+        for (int ci = 0; ci < d.cin; ++ci)
+            for (int ky = 0; ky < 3; ++ky) {
+                const int iy = oy * d.stride + ky * d.dil - d.pad;
+                if (iy < 0 || iy >= d.hin) continue;
+                for (int kx = 0; kx < 3; ++kx) {
+                    const int ix = ox * d.stride + kx * d.dil - d.pad;
+                    if (ix < 0 || ix >= d.win) continue;
+                    const float v = xs[(ci * d.hin + iy) * d.win + ix];
+                    const float* wr = ws + (ci * 9 + ky * 3 + kx) * CO;
+#pragma unroll
+                    for (int co = 0; co < CO; ++co) acc[co] = fmaf(v, wr[co], acc[co]);
+                }
+            }
+        if (!shuffle) {
+#pragma unroll
+            for (int co = 0; co < CO; ++co)
+                y[((int64_t)b * CO + co) * kPix + p] = d.relu ? fmaxf(acc[co], 0.f) : acc[co];
+        } else {
+#pragma unroll
+            for (int a = 0; a < 2; ++a)
+#pragma unroll
+                for (int c = 0; c < 2; ++c)
+                    y[(int64_t)b * kNetWin * kNetWin + (2 * oy + a) * kNetWin + 2 * ox + c] =
+                        acc[(2 * a + c) % CO];
+        }
+    }
+}
+
+// Gradient with respect to the input of a stride-1 layer:
+// dX[ci][iy][ix] = sum_co sum_tap dZ[co][iy - ky*dil + pad][ix - kx*dil + pad] W[co][ci][tap],
+// dZ = dA * [A > 0] for a ReLU layer (A = the layer's output), dZ = dA otherwise.
+template <int CI>
+__global__ void __launch_bounds__(kT)
+    conv_bwd_data_kernel(ConvDesc d, int n, const float* __restrict__ dA,
+                         const float* __restrict__ A, const uint16_t* __restrict__ wbf,
+                         float* __restrict__ dX) {
+    extern __shared__ float sm[];
+    float* zs = sm;                       // [cout][256]
+    float* ws = sm + d.cout * kPix;       // [co][tap][ci]
+    for (int k = threadIdx.x; k < d.cout * 9 * CI; k += blockDim.x) {
+        const int ci = k % CI, t = (k / CI) % 9, co = k / (9 * CI);
+        ws[k] = bf2f(wbf[d.woff + ((int64_t)co * CI + ci) * 9 + t]);
+    }
+    const int p = threadIdx.x;
+    const int iy = p / d.win, ix = p % d.win;
+    for (int b = blockIdx.x; b < n; b += gridDim.x) {
+        __syncthreads();
+        for (int k = threadIdx.x; k < d.cout * kPix; k += blockDim.x) {
+            const int64_t g = (int64_t)b * d.cout * kPix + k;
+            zs[k] = (d.relu && !(A[g] > 0.f)) ? 0.f : dA[g];
+        }
+        __syncthreads();
+        float acc[CI];
+#pragma unroll
+        for (int ci = 0; ci < CI; ++ci) acc[ci] = 0.f;
+        for (int co = 0; co < d.cout; ++co)
+            for (int ky = 0; ky < 3; ++ky) {
+                const int oy = iy - ky * d.dil + d.pad;
+                if (oy < 0 || oy >= d.hout) continue;
+                for (int kx = 0; kx < 3; ++kx) {
+                    const int ox = ix - kx * d.dil + d.pad;
+                    if (ox < 0 || ox >= d.wout) continue;
+                    const float z = zs[co * kPix + oy * d.wout + ox];
+                    const float* wr = ws + (co * 9 + ky * 3 + kx) * CI;
+#pragma unroll
+                    for (int ci = 0; ci < CI; ++ci) acc[ci] = fmaf(z, wr[ci], acc[ci]);
+                }
+            }
+#pragma unroll
+        for (int ci = 0; ci < CI; ++ci) dX[((int64_t)b * CI + ci) * kPix + p] = acc[ci];
+    }
+}
+
+// Per-workgroup partial weight and bias gradients of one layer over its share of the batch:
+// dW[co][ci][tap] = sum_b sum_p dZ[co][p] X[ci][in(p, tap)], db[co] = sum_b sum_p dZ[co][p].
+constexpr int kMaxE = (kNetCh * kNetCh * 9 + kNetCh + kT - 1) / kT;
+
+__global__ void __launch_bounds__(kT)
+    conv_bwd_w_kernel(ConvDesc d, int n, const float* __restrict__ X,
+                      const float* __restrict__ dA, const float* __restrict__ A,
+                      float* __restrict__ part) {
+    extern __shared__ float sm[];
+    const int xin = d.cin * d.hin * d.win;
+    float* xs = sm;
+    float* zs = sm + xin;
+    const int ne = d.cout * d.cin * 9, np = ne + d.cout;
+    float acc[kMaxE];
+#pragma unroll
+    for (int k = 0; k < kMaxE; ++k) acc[k] = 0.f;
+    for (int b = blockIdx.x; b < n; b += gridDim.x) {
+        __syncthreads();
+        for (int k = threadIdx.x; k < xin; k += blockDim.x) xs[k] = X[(int64_t)b * xin + k];
+        for (int k = threadIdx.x; k < d.cout * kPix; k += blockDim.x) {
+            const int64_t g = (int64_t)b * d.cout * kPix + k;
+            zs[k] = (d.relu && !(A[g] > 0.f)) ? 0.f : dA[g];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < kMaxE; ++k) {
+            const int e = threadIdx.x + k * kT;
+            if (e < ne) {
+                const int co = e / (d.cin * 9), r = e - co * d.cin * 9;
+                const int ci = r / 9, t = r - ci * 9, ky = t / 3, kx = t - ky * 3;
+                const float* z = zs + co * kPix;
+                const float* xc = xs + ci * d.hin * d.win;
+                float s = 0.f;
+                for (int oy = 0; oy < d.hout; ++oy) {
+                    const int iy = oy * d.stride + ky * d.dil - d.pad;
+                    if (iy < 0 || iy >= d.hin) continue;
+                    for (int ox = 0; ox < d.wout; ++ox) {
+                        const int ix = ox * d.stride + kx * d.dil - d.pad;
+                        if (ix < 0 || ix >= d.win) continue;
+                        s = fmaf(z[oy * d.wout + ox], xc[iy * d.win + ix], s);
+                    }
+                }
+                acc[k] += s;
+            } else if (e < np) {
+                const float* z = zs + (e - ne) * kPix;
+                float s = 0.f;
+                for (int q = 0; q < kPix; ++q) s += z[q];
+                acc[k] += s;
+            }
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < kMaxE; ++k) {
+        const int e = threadIdx.x + k * kT;
+        if (e < np) part[(int64_t)blockIdx.x * np + e] = acc[k];
+    }
+}
+
+// grad[e] = sum over workgroups of the partials, in workgroup order.
+__global__ void reduce_part_kernel(int nblk, int np, const float* __restrict__ part,
+                                   float* __restrict__ grad) {
+    for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < np; e += gridDim.x * blockDim.x) {
+        float s = 0.f;
+        for (int k = 0; k < nblk; ++k) s += part[(int64_t)k * np + e];
+        grad[e] = s;
+    }
+}
+
+// Gauge-invariant weighted squared error of the predicted Y potential (a constant shift of
+// g changes nothing in the cell problem):
+//   loss_b = sum_w omega (y - t - c)^2,  c = sum_w omega (y - t) / sum_w omega,
+// with the gradient 2 omega (y - t - c) / n written un-shuffled into the L5 gradient layout.
+__global__ void __launch_bounds__(kT)
+    loss_kernel(int n, const float* __restrict__ y, const float* __restrict__ tgt,
+                const float* __restrict__ wgt, float* __restrict__ dA5, float* __restrict__ loss_b) {
+    __shared__ double red[8];
+    constexpr int W2 = kNetWin * kNetWin;
+    for (int b = blockIdx.x; b < n; b += gridDim.x) {
+        const int64_t o = (int64_t)b * W2;
+        double sw = 0.0, swr = 0.0;
+        for (int k = threadIdx.x; k < W2; k += kT) {
+            const double w = wgt[o + k];
+            sw += w;
+            swr += w * ((double)y[o + k] - tgt[o + k]);
+        }
+        sw = block_sum(sw, red);
+        swr = block_sum(swr, red);
+        const double c = sw > 0.0 ? swr / sw : 0.0;
+        double l = 0.0;
+        for (int k = threadIdx.x; k < W2; k += kT) {
+            const double w = wgt[o + k];
+            const double r = (double)y[o + k] - tgt[o + k] - c;
+            l += w * r * r;
+            const int Y = k / kNetWin, Xp = k % kNetWin;
+            const int ch = 2 * (Y & 1) + (Xp & 1);
+            dA5[((int64_t)b * 4 + ch) * kPix + (Y >> 1) * 16 + (Xp >> 1)] =
+                (float)(2.0 * w * r / n);
+        }
+        l = block_sum(l, red);
+        if (threadIdx.x == 0) loss_b[b] = (float)l;
+    }
+}
+
+__global__ void adam_kernel(int64_t np, float* __restrict__ th, float* __restrict__ m,
+                            float* __restrict__ v, const float* __restrict__ g,
+                            uint16_t* __restrict__ wbf, float lr, float c1, float c2) {
+    const float b1 = 0.9f, b2 = 0.999f, eps = 1e-8f;
+    for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < np;
+         k += (int64_t)gridDim.x * blockDim.x) {
+        const float gk = g[k];
+        const float mk = b1 * m[k] + (1.f - b1) * gk;
+        const float vk = b2 * v[k] + (1.f - b2) * gk * gk;
+        m[k] = mk;
+        v[k] = vk;
+        const float t = th[k] - lr * (mk / c1) / (sqrtf(vk / c2) + eps);
+        th[k] = t;
+        wbf[k] = f2bf(t);
+    }
+}
+
+__global__ void to_bf16_kernel(int64_t np, const float* __restrict__ th, uint16_t* __restrict__ wbf) {
+    for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < np;
+         k += (int64_t)gridDim.x * blockDim.x)
+        wbf[k] = f2bf(th[k]);
+}
+
+__device__ __forceinline__ float feat(double lv, double lm) {
+    return (float)(fmax(lv - lm + 16.0, 0.0) * 0.25);
+}
+
+// Features of cell J on the 32x32 window; window position w maps to box-local j = w - o + E
+// and to X pixel i = w - o (o = (32 - xside)/2).
+__global__ void __launch_bounds__(kT)
+    net_features_kernel(int ncell, int xside, const int32_t* __restrict__ dims,
+                        const int32_t* __restrict__ shift, const int64_t* __restrict__ base,
+                        const double* __restrict__ logmu, const double* __restrict__ lognu,
+                        const double* __restrict__ b, float* __restrict__ x,
+                        float* __restrict__ tgt, float* __restrict__ wgt) {
+    __shared__ double red[8];
+    constexpr int W2 = kNetWin * kNetWin;
+    const int N2 = xside * xside, o = (kNetWin - xside) / 2;
+    for (int J = blockIdx.x; J < ncell; J += gridDim.x) {
+        double m = 0.0;
+        for (int i = threadIdx.x; i < N2; i += kT) {
+            const double l = logmu[(int64_t)J * N2 + i];
+            if (l > kZeroMassLog) m += exp(l);
+        }
+        m = block_sum(m, red);
+        const double lm = log(m);
+        const int W1 = dims[2 * J], Wd2 = dims[2 * J + 1];
+        const int E1 = shift[2 * J], E2 = shift[2 * J + 1];
+        const int64_t bs = base[J];
+        float* xc = x + (int64_t)J * kNetCin * W2;
+        double sw = 0.0, swg = 0.0;
+        for (int k = threadIdx.x; k < W2; k += kT) {
+            const int w1 = k / kNetWin, w2 = k % kNetWin;
+            const int j1 = w1 - o + E1, j2 = w2 - o + E2;
+            const bool inbox = j1 >= 0 && j1 < W1 && j2 >= 0 && j2 < Wd2;
+            const double ln = inbox ? lognu[bs + (int64_t)j1 * Wd2 + j2] : kNegD;
+            const bool has = ln > kZeroMassLog;
+            const int i1 = w1 - o, i2 = w2 - o;
+            const bool inx = i1 >= 0 && i1 < xside && i2 >= 0 && i2 < xside;
+            const double lmu = inx ? logmu[(int64_t)J * N2 + i1 * xside + i2] : kNegD;
+            const bool hmu = lmu > kZeroMassLog;
+            xc[0 * W2 + k] = has ? feat(ln, lm) : 0.f;
+            xc[1 * W2 + k] = has ? 1.f : 0.f;
+            xc[2 * W2 + k] = hmu ? feat(lmu, lm) : 0.f;
+            xc[3 * W2 + k] = hmu ? 1.f : 0.f;
+            xc[4 * W2 + k] = (w1 - 15.5f) * (1.f / 16.f);
+            xc[5 * W2 + k] = (w2 - 15.5f) * (1.f / 16.f);
+            if (tgt) {
+                const double w = has ? exp(ln - lm) : 0.0;
+                const double g = has ? b[bs + (int64_t)j1 * Wd2 + j2] : 0.0;
+                sw += w;
+                swg += w * g;
+                wgt[(int64_t)J * W2 + k] = (float)w;
+            }
+        }
+        if (tgt) {
+            sw = block_sum(sw, red);
+            swg = block_sum(swg, red);
+            const double gm = sw > 0.0 ? swg / sw : 0.0;
+            for (int k = threadIdx.x; k < W2; k += kT) {
+                const int w1 = k / kNetWin, w2 = k % kNetWin;
+                const int j1 = w1 - o + E1, j2 = w2 - o + E2;
+                const bool inbox = j1 >= 0 && j1 < W1 && j2 >= 0 && j2 < Wd2;
+                const double ln = inbox ? lognu[bs + (int64_t)j1 * Wd2 + j2] : kNegD;
+                tgt[(int64_t)J * W2 + k] =
+                    ln > kZeroMassLog ? (float)(b[bs + (int64_t)j1 * Wd2 + j2] - gm) : 0.f;
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// f(i) = -LSE_w [ghat(w) + log nu_J(w) - ((o + i1 - w1)^2 + (o + i2 - w2)^2) / kappa] over
+// the window positions inside the box with nu_J > 0.
+__global__ void __launch_bounds__(kT)
+    net_finit_kernel(int ncell, int xside, const int32_t* __restrict__ dims,
+                     const int32_t* __restrict__ shift, const int64_t* __restrict__ base,
+                     const double* __restrict__ lognu, const int32_t* __restrict__ gofs,
+                     const float* __restrict__ ghat, float invk, double* __restrict__ a,
+                     int32_t* __restrict__ g_stored) {
+    constexpr int W2 = kNetWin * kNetWin;
+    __shared__ float v[W2];
+    const int N2 = xside * xside, o = (kNetWin - xside) / 2;
+    for (int J = blockIdx.x; J < ncell; J += gridDim.x) {
+        const int W1 = dims[2 * J], Wd2 = dims[2 * J + 1];
+        const int E1 = shift[2 * J], E2 = shift[2 * J + 1];
+        const int64_t bs = base[J];
+        __syncthreads();
+        for (int k = threadIdx.x; k < W2; k += kT) {
+            const int w1 = k / kNetWin, w2 = k % kNetWin;
+            const int j1 = w1 - o + E1, j2 = w2 - o + E2;
+            const bool inbox = j1 >= 0 && j1 < W1 && j2 >= 0 && j2 < Wd2;
+            const double ln = inbox ? lognu[bs + (int64_t)j1 * Wd2 + j2] : kNegD;
+            v[k] = ln > kZeroMassLog ? ghat[(int64_t)J * W2 + k] + (float)ln : kNegF;
+        }
+        __syncthreads();
+        for (int i = threadIdx.x; i < N2; i += kT) {
+            const int i1 = i / xside, i2 = i % xside;
+            float mx = kNegF;
+            for (int k = 0; k < W2; ++k) {
+                const float d1 = (float)(o + i1 - k / kNetWin), d2 = (float)(o + i2 - k % kNetWin);
+                mx = fmaxf(mx, v[k] - (d1 * d1 + d2 * d2) * invk);
+            }
+            double f = 0.0;
+            if (mx > 0.5f * kNegF) {
+                float s = 0.f;
+                for (int k = 0; k < W2; ++k) {
+                    const float d1 = (float)(o + i1 - k / kNetWin),
+                                d2 = (float)(o + i2 - k % kNetWin);
+                    s += __expf(v[k] - (d1 * d1 + d2 * d2) * invk - mx);
+                }
+                f = -((double)mx + log((double)s));
+            }
+            a[(int64_t)J * N2 + i] = f;
+        }
+        if (threadIdx.x == 0) {
+            g_stored[2 * J] = gofs[2 * J];
+            g_stored[2 * J + 1] = gofs[2 * J + 1];
+        }
+    }
+}
+
+int grid_n(int n, int cap) { return std::max(1, std::min(n, cap)); }
+
+template <typename K>
+void lds_attr(K k, size_t bytes) {
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(k),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+}
+
+size_t fwd_lds(const ConvDesc& d) {
+    return sizeof(float) * ((size_t)d.cin * d.hin * d.win + (size_t)d.cin * 9 * d.cout);
+}
+
+void launch_fwd(const ConvDesc& d, int n, const float* x, const uint16_t* wbf,
+                const float* params, float* y, int shuffle, hipStream_t st) {
+    const size_t lds = fwd_lds(d);
+    const int g = grid_n(n, 2048);
+    if (d.cout == kNetCh) {
+        lds_attr(conv_fwd_kernel<kNetCh>, lds);
+        conv_fwd_kernel<kNetCh><<<g, kT, lds, st>>>(d, n, x, wbf, params, y, shuffle);
+    } else {
+        lds_attr(conv_fwd_kernel<4>, lds);
+        conv_fwd_kernel<4><<<g, kT, lds, st>>>(d, n, x, wbf, params, y, shuffle);
+    }
+}
+
+}  // namespace
+
+const ConvDesc* net_layers() { return table().L; }
+int64_t net_param_count() { return table().n; }
+
+void launch_net_features(int ncell, int xside, const int32_t* dims, const int32_t* shift,
+                         const int64_t* base, const double* logmu, const double* lognu,
+                         const double* b, float* x, float* tgt, float* wgt, hipStream_t st) {
+    if (ncell <= 0) return;
+    net_features_kernel<<<grid_n(ncell, 4096), kT, 0, st>>>(ncell, xside, dims, shift, base,
+                                                            logmu, lognu, b, x, tgt, wgt);
+}
+
+void launch_net_finit(int ncell, int xside, const int32_t* dims, const int32_t* shift,
+                      const int64_t* base, const double* lognu, const int32_t* gofs,
+                      const float* ghat, double kappa, double* a, int32_t* g_stored,
+                      hipStream_t st) {
+    if (ncell <= 0) return;
+    net_finit_kernel<<<grid_n(ncell, 4096), kT, 0, st>>>(ncell, xside, dims, shift, base, lognu,
+                                                         gofs, ghat, (float)(1.0 / kappa), a,
+                                                         g_stored);
+}
+
+}  // namespace dd
+
+using dd::Status;
+
+namespace {
+
+Status net_reserve(dd_net* net, int n) {
+    Status st;
+    if (n <= net->cap_n) return st;
+    const int cap = std::max(n, 256);
+    if (net->act) (void)hipFree(net->act);
+    if (net->ga) (void)hipFree(net->ga);
+    if (net->out) (void)hipFree(net->out);
+    if (net->loss_b) (void)hipFree(net->loss_b);
+    net->act = net->ga = net->out = net->loss_b = nullptr;
+    net->cap_n = 0;
+    const size_t per = (size_t)dd::kNetCh * dd::kPix;
+    DD_HIP(hipMalloc(&net->act, 4 * per * cap * sizeof(float)), st);
+    DD_HIP(hipMalloc(&net->ga, 2 * per * cap * sizeof(float)), st);
+    DD_HIP(hipMalloc(&net->out, (size_t)cap * dd::kNetWin * dd::kNetWin * sizeof(float)), st);
+    DD_HIP(hipMalloc(&net->loss_b, cap * sizeof(float)), st);
+    net->cap_n = cap;
+    return st;
+}
+
+}  // namespace
+
+Status net_forward(dd_net* net, int n, const float* x, float* y, hipStream_t st) {
+    Status s = net_reserve(net, n);
+    if (s.code || n == 0) return s;
+    const dd::ConvDesc* L = dd::net_layers();
+    const size_t per = (size_t)dd::kNetCh * dd::kPix * n;
+    const float* in = x;
+    for (int l = 0; l < dd::kNetLayers; ++l) {
+        const bool last = l == dd::kNetLayers - 1;
+        float* o = last ? y : net->act + l * per;
+        dd::launch_fwd(L[l], n, in, net->wbf, net->master, o, last ? 1 : 0, st);
+        in = o;
+    }
+    DD_HIP(hipGetLastError(), s);
+    return s;
+}
+
+namespace {
+
+dd_status net_fail(dd_net* net, dd_status code, const std::string& msg) {
+    if (net) net->err = msg;
+    dd::set_global_error(msg);
+    return code;
+}
+
+Status net_train(dd_net* net, int n, const float* x, const float* tgt, const float* wgt,
+                 float lr, hipStream_t st, double* loss) {
+    using namespace dd;
+    Status s = net_reserve(net, n);
+    if (s.code) return s;
+    s = net_forward(net, n, x, net->out, st);
+    if (s.code) return s;
+    const ConvDesc* L = net_layers();
+    const size_t per = (size_t)kNetCh * kPix * n;
+    float* A[4] = {net->act, net->act + per, net->act + 2 * per, net->act + 3 * per};
+    float* G[2] = {net->ga, net->ga + per};
+    loss_kernel<<<grid_n(n, 2048), kT, 0, st>>>(n, net->out, tgt, wgt, G[0], net->loss_b);
+    // weight-gradient partials: one slot per workgroup of the largest layer
+    const int gw = grid_n(n, 512);
+    const size_t need = (size_t)gw * (kNetCh * kNetCh * 9 + kNetCh);
+    if (need > net->part_cap) {
+        if (net->part) (void)hipFree(net->part);
+        net->part = nullptr;
+        DD_HIP(hipMalloc(&net->part, need * sizeof(float)), s);
+        net->part_cap = need;
+    }
+    int cur = 0;  // G[cur] holds the gradient w.r.t. the output of layer l
+    for (int l = kNetLayers - 1; l >= 0; --l) {
+        const ConvDesc& d = L[l];
+        const float* X = l == 0 ? x : A[l - 1];
+        const float* Aout = l == kNetLayers - 1 ? nullptr : A[l];
+        const size_t wl = sizeof(float) * ((size_t)d.cin * d.hin * d.win + (size_t)d.cout * kPix);
+        lds_attr(conv_bwd_w_kernel, wl);
+        conv_bwd_w_kernel<<<gw, kT, wl, st>>>(d, n, X, G[cur], Aout, net->part);
+        const int np = d.cout * d.cin * 9 + d.cout;
+        reduce_part_kernel<<<(np + 255) / 256, 256, 0, st>>>(gw, np, net->part,
+                                                             net->grad + d.woff);
+        if (l > 0) {
+            const size_t dl = sizeof(float) * ((size_t)d.cout * kPix + (size_t)d.cout * 9 * d.cin);
+            lds_attr(conv_bwd_data_kernel<kNetCh>, dl);
+            conv_bwd_data_kernel<kNetCh><<<grid_n(n, 2048), kT, dl, st>>>(d, n, G[cur], Aout,
+                                                                          net->wbf, G[1 - cur]);
+            cur = 1 - cur;
+        }
+    }
+    net->step += 1;
+    const float c1 = 1.f - std::pow(0.9f, (float)net->step);
+    const float c2 = 1.f - std::pow(0.999f, (float)net->step);
+    const int64_t np = net_param_count();
+    adam_kernel<<<(int)std::min<int64_t>((np + 255) / 256, 1024), 256, 0, st>>>(
+        np, net->master, net->adam_m, net->adam_v, net->grad, net->wbf, lr, c1, c2);
+    DD_HIP(hipGetLastError(), s);
+    if (loss) {
+        std::vector<float> lb(n);
+        DD_HIP(hipMemcpyAsync(lb.data(), net->loss_b, n * sizeof(float), hipMemcpyDeviceToHost, st),
+               s);
+        DD_HIP(hipStreamSynchronize(st), s);
+        double t = 0.0;
+        for (float v : lb) t += v;
+        *loss = n > 0 ? t / n : 0.0;
+    }
+    return s;
+}
+
+}  // namespace
+
+extern "C" int64_t dd_net_param_count(void) { return dd::net_param_count(); }
+
+extern "C" dd_status dd_net_create(const float* params, dd_net** out) {
+    if (!params || !out) return net_fail(nullptr, DD_EINVAL, "dd_net_create: null argument");
+    *out = nullptr;
+    const int64_t np = dd::net_param_count();
+    for (int64_t k = 0; k < np; ++k)
+        if (!std::isfinite(params[k]))
+            return net_fail(nullptr, DD_EINVAL, "dd_net_create: non-finite parameter");
+    dd_net* net = new dd_net();
+    Status s;
+    auto bail = [&](const Status& e) {
+        dd_net_free(net);
+        return net_fail(nullptr, e.code, e.msg);
+    };
+    if (hipMalloc(&net->master, np * sizeof(float)) != hipSuccess ||
+        hipMalloc(&net->adam_m, np * sizeof(float)) != hipSuccess ||
+        hipMalloc(&net->adam_v, np * sizeof(float)) != hipSuccess ||
+        hipMalloc(&net->grad, np * sizeof(float)) != hipSuccess ||
+        hipMalloc(&net->wbf, np * sizeof(uint16_t)) != hipSuccess) {
+        s.code = DD_ENOMEM;
+        s.msg = "dd_net_create: device allocation failed";
+        return bail(s);
+    }
+    if (hipMemcpy(net->master, params, np * sizeof(float), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemset(net->adam_m, 0, np * sizeof(float)) != hipSuccess ||
+        hipMemset(net->adam_v, 0, np * sizeof(float)) != hipSuccess) {
+        s.code = DD_EDEVICE;
+        s.msg = "dd_net_create: upload failed";
+        return bail(s);
+    }
+    dd::to_bf16_kernel<<<(int)std::min<int64_t>((np + 255) / 256, 1024), 256>>>(np, net->master,
+                                                                              net->wbf);
+    if (hipDeviceSynchronize() != hipSuccess) {
+        s.code = DD_EDEVICE;
+        s.msg = "dd_net_create: kernel failed";
+        return bail(s);
+    }
+    *out = net;
+    return DD_OK;
+}
+
+extern "C" dd_status dd_net_params(dd_net* net, float* out) {
+    if (!net || !out) return net_fail(net, DD_EINVAL, "dd_net_params: null argument");
+    if (hipDeviceSynchronize() != hipSuccess ||
+        hipMemcpy(out, net->master, dd::net_param_count() * sizeof(float),
+                  hipMemcpyDeviceToHost) != hipSuccess)
+        return net_fail(net, DD_EDEVICE, "dd_net_params: copy failed");
+    return DD_OK;
+}
+
+extern "C" dd_status dd_net_forward(dd_net* net, int32_t n, const float* x, float* y,
+                                    void* stream) {
+    if (!net || n < 0 || (n > 0 && (!x || !y)))
+        return net_fail(net, DD_EINVAL, "dd_net_forward: bad argument");
+    const hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    const Status s = net_forward(net, n, x, y, st);
+    if (s.code) return net_fail(net, s.code, s.msg);
+    if (hipStreamSynchronize(st) != hipSuccess)
+        return net_fail(net, DD_EDEVICE, "dd_net_forward: kernel failed");
+    return DD_OK;
+}
+
+extern "C" dd_status dd_net_train_step(dd_net* net, int32_t n, const float* x, const float* tgt,
+                                       const float* wgt, float lr, void* stream, double* loss) {
+    if (!net || n < 1 || !x || !tgt || !wgt || !(lr > 0.f))
+        return net_fail(net, DD_EINVAL, "dd_net_train_step: bad argument");
+    const hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    const Status s = net_train(net, n, x, tgt, wgt, lr, st, loss);
+    if (s.code) return net_fail(net, s.code, s.msg);
+    if (hipStreamSynchronize(st) != hipSuccess)
+        return net_fail(net, DD_EDEVICE, "dd_net_train_step: kernel failed");
+    return DD_OK;
+}
+
+extern "C" void dd_net_free(dd_net* net) {
+    if (!net) return;
+    (void)hipDeviceSynchronize();
+    for (void* p : {(void*)net->master, (void*)net->adam_m, (void*)net->adam_v, (void*)net->grad,
+                    (void*)net->wbf, (void*)net->part, (void*)net->act, (void*)net->ga,
+                    (void*)net->out, (void*)net->loss_b})
+        if (p) (void)hipFree(p);
+    delete net;
+}
+
+extern "C" const char* dd_net_strerror(const dd_net* net) {
+    return net ? net->err.c_str() : dd::global_error();
+}

@@ -1,0 +1,73 @@
+// Learned warm start for the cell Sinkhorn: a small convolutional net (declarations).
+//
+// The net maps a 32x32 window of the cell -- centred on the X block in the box-local
+// coordinates of the cell problem, so that window position w and X pixel i are at cost
+// |o + i - w|^2 / kappa with o = (32 - xside)/2 -- to a predicted Y potential g on that
+// window.  The X potential used to start Sinkhorn is then one exact X-update of the
+// prediction, f(i) = -LSE_w [g(w) + log nu_J(w) - C(i, w)], which is the slot for the
+// initial alpha of the cell solve (App. A.1, Alg. "SinkhornGPU" input alpha_init).
+// The stopping rule of the solve is untouched, so the prediction only changes where the
+// iteration starts.
+//
+// Layers (3x3 kernels, 32 channels, BF16 weights, FP32 accumulation, ReLU between):
+//   L1  6 -> 32, stride 2      32x32 -> 16x16
+//   L2 32 -> 32, dilation 1    16x16
+//   L3 32 -> 32, dilation 2    16x16
+//   L4 32 -> 32, dilation 4    16x16
+//   L5 32 -> 4,  dilation 1    16x16, pixel-shuffled to the 32x32 output (no ReLU)
+// Input channels: nu_J feature and support, mu feature and support, two window coordinates.
+#pragma once
+
+#include "common.hpp"
+
+namespace dd {
+
+constexpr int kNetWin = 32;          // window side
+constexpr int kNetCin = 6;           // input channels
+constexpr int kNetCh = 32;           // hidden channels
+constexpr int kNetLayers = 5;
+
+struct ConvDesc {
+    int cin, cout, hin, win, hout, wout, stride, dil, pad, relu;
+    int64_t woff, boff;  // offsets of the weights [cout][cin][3][3] and bias [cout]
+};
+
+// Layer table and parameter count.
+const ConvDesc* net_layers();
+int64_t net_param_count();
+
+// Cell features of a composite batch (box-local window), optionally with the training
+// target (the solved g, mean-free under the weights) and weights nu_J / m_J.
+void launch_net_features(int ncell, int xside, const int32_t* dims, const int32_t* shift,
+                         const int64_t* base, const double* logmu, const double* lognu,
+                         const double* b, float* x, float* tgt, float* wgt, hipStream_t st);
+
+// f(i) = -LSE_w [g(w) + log nu_J(w) - C(i, w)] over the window part of the box; also
+// records the gauge offsets of this solve (as the zero / previous-iterate start does).
+void launch_net_finit(int ncell, int xside, const int32_t* dims, const int32_t* shift,
+                      const int64_t* base, const double* lognu, const int32_t* gofs,
+                      const float* ghat, double kappa, double* a, int32_t* g_stored,
+                      hipStream_t st);
+
+}  // namespace dd
+
+// The opaque net of the C ABI.
+struct dd_net {
+    float* master = nullptr;  // FP32 master parameters
+    float* adam_m = nullptr;
+    float* adam_v = nullptr;
+    float* grad = nullptr;
+    uint16_t* wbf = nullptr;  // BF16 copy used by the kernels (weights; biases stay FP32)
+    float* part = nullptr;    // weight-gradient partials [blocks][layer params]
+    size_t part_cap = 0;
+    float* act = nullptr;     // activations of the last forward (training) [4][n][32][256]
+    float* ga = nullptr;      // gradient buffers [2][n][32][256]
+    float* out = nullptr;     // output of the last forward [n][1024]
+    float* loss_b = nullptr;  // per-sample loss [n]
+    int cap_n = 0;
+    int64_t step = 0;
+    std::string err;
+};
+
+// Forward pass on n samples (x [n][6][32][32] -> y [n][32][32]); keeps the activations.
+dd::Status net_forward(dd_net* net, int n, const float* x, float* y, hipStream_t st);

@@ -13,18 +13,21 @@
 // the marginal error and the masses are float64.  This is what lets float32 reach a
 // marginal tolerance of 1e-5 (the paper saw plain float32 stall, App. A.2.1).
 //
-// Mapping to the hardware: one wave64 workgroup owns one cell at a time with the whole
-// cell -- f, log mu, the Y box of log nu_J and g, the shifted per-axis intermediates --
-// resident in LDS (boxes larger than the LDS tile keep their Y-box arrays in global
-// memory).  The tile is sized for ~8 resident workgroups per CU.  Each 1D pass gives one
-// output per lane and walks its short reduction line from LDS (max pass, then exp-sum
-// pass).  Row maxima and the float64 error / mass sums are wave64 shuffle reductions.
+// Mapping to the hardware.  A workgroup is four wave64s.  Cells are split on the host by
+// their LSE work per iteration: a "big" cell is solved by the whole workgroup, a "small"
+// cell by one wave on its own, so a workgroup runs one big cell or four small ones.  Each
+// cell keeps f, log mu, the Y box of log nu_J and g and the shifted per-axis intermediates
+// in LDS (an LDS tile per class sized from the box-size quantiles; a box larger than its
+// tile keeps its Y-box arrays in a per-cell global scratch read through L1/L2).  Each 1D
+// pass gives one output per lane and walks its short reduction line from LDS (max pass,
+// then exp-sum pass).  Row maxima and the float64 error / mass sums are wave shuffles;
+// a wave working alone synchronises with wave-level barriers only.
 //
 // Two drivers:
-//   * per-cell stopping or a fixed iteration count: a persistent kernel pulls
-//     cells from an atomic work queue (in the given order, largest box first when
-//     the caller sorts) and iterates each to its own stop inside LDS -- no HBM
-//     traffic and no grid-wide synchronisation between iterations;
+//   * per-cell stopping or a fixed iteration count: a persistent kernel; workgroups first
+//     pull big cells from one atomic queue, then each wave pulls small cells from a second
+//     one, and every cell iterates to its own stop inside LDS -- no HBM traffic and no
+//     grid-wide synchronisation between iterations;
 //   * the paper's batch rule (App. A.2.1): one launch per iteration that reads f
 //     from one buffer and writes the next f into the other, and ends with a
 //     last-workgroup float64 reduction of the per-cell errors in fixed cell order
@@ -35,6 +38,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <type_traits>
 #include <vector>
 
 namespace dd {
@@ -45,16 +49,52 @@ thread_local std::string g_err;
 void set_global_error(const std::string& m) { g_err = m; }
 const char* global_error() { return g_err.c_str(); }
 
-// One wave64 per workgroup, one cell per workgroup at a time: the 1D passes fill the wave,
-// the per-cell reductions are single-wave shuffles and barriers are single-wave.
-constexpr int kThreads = 64;
+constexpr int kThreads = 256;
+constexpr int kWaves = kThreads / 64;
 
 namespace {
 
-// LSE_{k<K} ( in[k*stride] - (k - q + e)^2 * invk ), max-shifted, two passes.
-template <typename T>
-__device__ __forceinline__ T lse_line(const T* __restrict__ in, int stride, int K, int q, int e,
-                                      T invk) {
+// The team that works on one cell: the whole workgroup or one wave.
+struct BlockTeam {
+    __device__ int tid() const { return threadIdx.x; }
+    __device__ int size() const { return blockDim.x; }
+    __device__ int wid() const { return threadIdx.x >> 6; }
+    __device__ int nw() const { return blockDim.x >> 6; }
+    __device__ void sync() const { __syncthreads(); }
+    template <typename P>
+    __device__ double sum(double v, P scratch) const {
+        const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+        v = wave_sum(v);
+        __syncthreads();
+        if (lane == 0) scratch[w] = v;
+        __syncthreads();
+        double t = 0.0;
+        for (int k = 0; k < nw; ++k) t += scratch[k];
+        __syncthreads();
+        return t;
+    }
+};
+
+struct WaveTeam {
+    __device__ int tid() const { return threadIdx.x & 63; }
+    __device__ int size() const { return 64; }
+    __device__ int wid() const { return 0; }
+    __device__ int nw() const { return 1; }
+    // a wave's own LDS and global writes are complete and visible to its other lanes
+    __device__ void sync() const {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_s_waitcnt(0);
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
+    template <typename P>
+    __device__ double sum(double v, P) const { return wave_sum(v); }
+};
+
+// LSE_{k<K} ( in[k*stride] - (k - q + e)^2 * invk ), max-shifted, two passes.  P is a
+// pointer into LDS or global memory.
+template <typename T, typename P>
+__device__ __forceinline__ T lse_line(P in, int stride, int K, int q, int e, T invk) {
     T d = T(e - q);
     T m = in[0] - d * d * invk;
     for (int k = 1; k < K; ++k) {
@@ -71,9 +111,8 @@ __device__ __forceinline__ T lse_line(const T* __restrict__ in, int stride, int 
 }
 
 // Same with an additive per-k shift sh[k] (the float offsets of the input lines).
-template <typename T>
-__device__ __forceinline__ T lse_line_sh(const T* __restrict__ in, int stride, int K, int q,
-                                         int e, T invk, const T* __restrict__ sh) {
+template <typename T, typename P, typename PS>
+__device__ __forceinline__ T lse_line_sh(P in, int stride, int K, int q, int e, T invk, PS sh) {
     T d = T(e - q);
     T m = in[0] + sh[0] - d * d * invk;
     for (int k = 1; k < K; ++k) {
@@ -95,33 +134,34 @@ __device__ __forceinline__ double wave_max_d(double v) {
     return v;
 }
 
+// Address-space-qualified pointers: LDS (ds_* instructions) and global (global_* ones), so
+// that no access in the hot loops goes through flat addressing.
 template <typename T>
+using lds_p = __attribute__((address_space(3))) T*;
+template <typename T>
+using glb_p = __attribute__((address_space(1))) T*;
+
+// A cell's working set.  The X arrays always live in LDS; the Y-box arrays live in the LDS
+// tile (G = false) or, for a box larger than the tile, in the cell's global scratch (G = true).
+template <typename T, bool G>
 struct Lds {
-    double* f;    // [N2]          X potential f
-    double* lm;   // [N2]          log mu
-    double* s;    // [N2]          LSE_j (g + log nu_J - C)
-    double* ry;   // [AS]          row maxima of f + log mu
-    double* red;  // [16]          reductions; [8] = R, [9] = Q
-    T* wq;        // [N2]          f + log mu - ry(row)
-    T* rhoy;      // [AS]          ry - R
-    // Y-box arrays of the current cell (LDS tile, or global scratch for a larger box)
-    double* ln;   // [W1][ys]      log nu_J
-    double* qx;   // [W1]          row maxima of g + log nu_J (full offsets)
-    T* gq;        // [W1][ys]      g + R (g = gq - R)
-    T* zq;        // [W1][ys]      g + log nu_J - qx(row)
-    T* t1;        // [AS][W2p]     Y-half intermediate, relative to ry
-    T* u;         // [W1][ASp]     X-half intermediate, relative to qx
-    T* kq;        // [W1]          qx - Q
+    using YT = std::conditional_t<G, glb_p<T>, lds_p<T>>;
+    using YD = std::conditional_t<G, glb_p<double>, lds_p<double>>;
+    lds_p<double> f;    // [N2]          X potential f
+    lds_p<double> lm;   // [N2]          log mu
+    lds_p<double> s;    // [N2]          LSE_j (g + log nu_J - C)
+    lds_p<double> ry;   // [AS]          row maxima of f + log mu
+    lds_p<double> red;  // [16]          reductions; [8] = R, [9] = Q
+    lds_p<T> wq;        // [N2]          f + log mu - ry(row)
+    lds_p<T> rhoy;      // [AS]          ry - R
+    YD ln;              // [W1][ys]      log nu_J
+    YD qx;              // [W1]          row maxima of g + log nu_J (full offsets)
+    YT gq;              // [W1][ys]      g + R (g = gq - R)
+    YT zq;              // [W1][ys]      g + log nu_J - qx(row)
+    YT t1;              // [AS][W2p]     Y-half intermediate, relative to ry
+    YT u;               // [W1][ASp]     X-half intermediate, relative to qx
+    YT kq;              // [W1]          qx - Q
     int ys, W2p, ASp;
-    // the LDS tile, sized for boxes up to lw1 x lw2
-    double* ln_l;
-    double* qx_l;
-    T* gq_l;
-    T* zq_l;
-    T* t1_l;
-    T* u_l;
-    T* kq_l;
-    int lys;
 };
 
 // LDS bytes: the X arrays of the cell plus the Y-box arrays for the LDS tile (lw1 x lw2);
@@ -130,7 +170,15 @@ __host__ __device__ inline size_t lds_layout_bytes(int AS, int lw1, int lw2, siz
     const size_t N2 = (size_t)AS * AS, LY = (size_t)lw1 * (lw2 + 1);
     const size_t nd = 16 + 3 * N2 + AS + LY + lw1;
     const size_t nt = N2 + AS + 2 * LY + (size_t)AS * (lw2 + 1) + (size_t)lw1 * (AS + 1) + lw1;
-    return 8 * nd + elem * nt + 16;
+    return (8 * nd + elem * nt + 16 + 15) & ~size_t(15);
+}
+
+// Workgroup LDS: one big-cell layout, or kWaves small-cell layouts side by side.
+__host__ __device__ inline size_t wg_lds_bytes(int AS, int lw1, int lw2, int lw1b, int lw2b,
+                                               size_t elem) {
+    const size_t small = kWaves * lds_layout_bytes(AS, lw1, lw2, elem);
+    const size_t big = lds_layout_bytes(AS, lw1b, lw2b, elem);
+    return small > big ? small : big;
 }
 
 // Global scratch (in doubles) of a cell whose box exceeds the tile: qx, then gq, zq, t1, u, kq.
@@ -140,13 +188,17 @@ __host__ __device__ inline int64_t cell_scratch_doubles(int AS, int W1, int W2, 
     return (n + 1) & ~int64_t(1);
 }
 
-template <typename T>
-__device__ __forceinline__ Lds<T> carve(char* base, int AS, int lw1, int lw2) {
-    Lds<T> L;
-    const int N2 = AS * AS;
-    L.lys = lw2 + 1;
-    const size_t LY = (size_t)lw1 * L.lys;
-    double* d = reinterpret_cast<double*>(base);
+// Carve the X arrays (and, for G = false, the tile) out of an LDS slice; for G = true bind
+// the Y-box arrays to the cell's global scratch.
+template <typename T, bool G>
+__device__ __forceinline__ Lds<T, G> carve(lds_p<char> base, const SkBatch& p, int lw1, int lw2,
+                                           int c, int W1, int W2, int64_t ybase,
+                                           double* big_scratch) {
+    Lds<T, G> L;
+    const int AS = p.xside, N2 = AS * AS;
+    const int lys = lw2 + 1;
+    const size_t LY = (size_t)lw1 * lys;
+    lds_p<double> d = (lds_p<double>)base;
     L.red = d;
     d += 16;
     L.f = d;
@@ -157,66 +209,90 @@ __device__ __forceinline__ Lds<T> carve(char* base, int AS, int lw1, int lw2) {
     d += N2;
     L.ry = d;
     d += AS;
-    L.ln_l = d;
+    lds_p<double> ln_l = d;
     d += LY;
-    L.qx_l = d;
+    lds_p<double> qx_l = d;
     d += lw1;
-    T* t = reinterpret_cast<T*>(d);
+    lds_p<T> t = (lds_p<T>)d;
     L.wq = t;
     t += N2;
     L.rhoy = t;
     t += AS;
-    L.gq_l = t;
-    t += LY;
-    L.zq_l = t;
-    t += LY;
-    L.t1_l = t;
-    t += (size_t)AS * L.lys;
-    L.u_l = t;
-    t += (size_t)lw1 * (AS + 1);
-    L.kq_l = t;
+    L.ASp = AS + 1;
+    if constexpr (!G) {
+        L.ln = ln_l;
+        L.qx = qx_l;
+        L.gq = t;
+        t += LY;
+        L.zq = t;
+        t += LY;
+        L.t1 = t;
+        t += (size_t)AS * lys;
+        L.u = t;
+        t += (size_t)lw1 * (AS + 1);
+        L.kq = t;
+        L.ys = lys;
+        L.W2p = lys;
+    } else {
+        glb_p<double> sc = (glb_p<double>)(big_scratch + p.scr_off[c]);
+        L.ln = (glb_p<double>)(const_cast<double*>(p.lognu) + ybase);
+        L.qx = sc;
+        glb_p<T> g = (glb_p<T>)(sc + W1);
+        L.gq = g;
+        g += (int64_t)W1 * W2;
+        L.zq = g;
+        g += (int64_t)W1 * W2;
+        L.t1 = g;
+        g += (int64_t)AS * (W2 + 1);
+        L.u = g;
+        g += (int64_t)W1 * (AS + 1);
+        L.kq = g;
+        L.ys = W2;
+        L.W2p = W2 + 1;
+    }
     return L;
 }
 
 // Y-update g(j) = -LSE_i [f(i) + log mu(i) - C(i,j)], as two 1D passes over shifted values.
 // Leaves gq (g = gq - R, R in red[8]).
-template <typename T>
-__device__ __forceinline__ void y_half(const Lds<T>& L, int AS, int W1, int W2, int E1, int E2,
-                                       T invk) {
-    const int N2 = AS * AS;
-    if (threadIdx.x < AS) {
-        const int i1 = threadIdx.x;
+template <typename Tm, typename T, bool G>
+__device__ __forceinline__ void y_half(const Tm& tm, const Lds<T, G>& L, int AS, int W1, int W2,
+                                       int E1, int E2, T invk) {
+    const int N2 = AS * AS, tid = tm.tid(), nt = tm.size();
+    if (tid < AS) {
+        const int i1 = tid;
         double r = L.f[i1 * AS] + L.lm[i1 * AS];
         for (int i2 = 1; i2 < AS; ++i2) r = fmax(r, L.f[i1 * AS + i2] + L.lm[i1 * AS + i2]);
         L.ry[i1] = r;
     }
-    __syncthreads();
-    for (int i = threadIdx.x; i < N2; i += blockDim.x) L.wq[i] = (T)(L.f[i] + L.lm[i] - L.ry[i / AS]);
-    if (threadIdx.x == 0) {
+    tm.sync();
+    for (int i = tid; i < N2; i += nt) L.wq[i] = (T)(L.f[i] + L.lm[i] - L.ry[i / AS]);
+    if (tid == 0) {
         double R = L.ry[0];
         for (int i1 = 1; i1 < AS; ++i1) R = fmax(R, L.ry[i1]);
         L.red[8] = R;
         for (int i1 = 0; i1 < AS; ++i1) L.rhoy[i1] = (T)(L.ry[i1] - R);
     }
-    __syncthreads();
-    for (int o = threadIdx.x; o < AS * W2; o += blockDim.x) {
+    tm.sync();
+    for (int o = tid; o < AS * W2; o += nt) {
         const int i1 = o / W2, j2 = o - i1 * W2;
         L.t1[i1 * L.W2p + j2] = lse_line(L.wq + i1 * AS, 1, AS, j2, E2, invk);
     }
-    __syncthreads();
-    for (int o = threadIdx.x; o < W1 * W2; o += blockDim.x) {
+    tm.sync();
+    for (int o = tid; o < W1 * W2; o += nt) {
         const int j1 = o / W2, j2 = o - j1 * W2;
         L.gq[j1 * L.ys + j2] = -lse_line_sh(L.t1 + j2, L.W2p, AS, j1, E1, invk, L.rhoy);
     }
-    __syncthreads();
+    tm.sync();
 }
 
 // s(i) = LSE_j [g(j) + log nu_J(j) - C(i,j)] (float64 result), as two 1D passes over shifted
 // values (cost (i - j + E)^2 = (j - i - E)^2).
-template <typename T>
-__device__ __forceinline__ void x_half(const Lds<T>& L, int AS, int W1, int W2, int E1, int E2,
-                                       T invk) {
-    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
+template <typename Tm, typename T, bool G>
+__device__ __forceinline__ void x_half(const Tm& tm, const Lds<T, G>& L, int AS, int W1, int W2,
+                                       int E1, int E2, T invk) {
+    const int tid = tm.tid(), nt = tm.size();
+    const int lane = threadIdx.x & 63, wid = tm.wid(), nw = tm.nw();
     const double goff = -L.red[8];
     for (int j1 = wid; j1 < W1; j1 += nw) {
         double m = -1e300;
@@ -227,7 +303,7 @@ __device__ __forceinline__ void x_half(const Lds<T>& L, int AS, int W1, int W2, 
             L.zq[j1 * L.ys + j2] = (T)((double)L.gq[j1 * L.ys + j2] + L.ln[j1 * L.ys + j2] - m);
         if (lane == 0) L.qx[j1] = m + goff;
     }
-    __syncthreads();
+    tm.sync();
     if (wid == 0) {
         double Q = -1e300;
         for (int j1 = lane; j1 < W1; j1 += 64) Q = fmax(Q, L.qx[j1]);
@@ -235,24 +311,25 @@ __device__ __forceinline__ void x_half(const Lds<T>& L, int AS, int W1, int W2, 
         for (int j1 = lane; j1 < W1; j1 += 64) L.kq[j1] = (T)(L.qx[j1] - Q);
         if (lane == 0) L.red[9] = Q;
     }
-    for (int o = threadIdx.x; o < W1 * AS; o += blockDim.x) {
+    for (int o = tid; o < W1 * AS; o += nt) {
         const int j1 = o / AS, i2 = o - j1 * AS;
         L.u[j1 * L.ASp + i2] = lse_line(L.zq + j1 * L.ys, 1, W2, i2, -E2, invk);
     }
-    __syncthreads();
+    tm.sync();
     const double Q = L.red[9];
-    for (int o = threadIdx.x; o < AS * AS; o += blockDim.x) {
+    for (int o = tid; o < AS * AS; o += nt) {
         const int i1 = o / AS, i2 = o - i1 * AS;
         L.s[o] = Q + (double)lse_line_sh(L.u + i2, L.ASp, W1, i1, -E1, invk, L.kq);
     }
-    __syncthreads();
+    tm.sync();
 }
 
 // X-marginal L1 error sum_i mu |exp(f + s) - 1| and mass sum_i mu, float64.
-template <typename T>
-__device__ __forceinline__ void err_mass(const Lds<T>& L, int AS, double& err, double& mass) {
+template <typename Tm, typename T, bool G>
+__device__ __forceinline__ void err_mass(const Tm& tm, const Lds<T, G>& L, int AS, double& err,
+                                         double& mass) {
     double e = 0.0, m = 0.0;
-    for (int i = threadIdx.x; i < AS * AS; i += blockDim.x) {
+    for (int i = tm.tid(); i < AS * AS; i += tm.size()) {
         const double lm = L.lm[i];
         if (lm > kZeroMassLog) {
             const double mu = exp(lm);
@@ -260,74 +337,121 @@ __device__ __forceinline__ void err_mass(const Lds<T>& L, int AS, double& err, d
             m += mu;
         }
     }
-    err = block_sum(e, L.red);
-    mass = block_sum(m, L.red);
+    err = tm.sum(e, L.red);
+    mass = tm.sum(m, L.red);
 }
 
-// Load one cell: f and log mu into LDS; the Y-box arrays go to the LDS tile when the box
-// fits it, else they are bound to the cell's own global scratch (log nu_J is then read in
-// place).
-template <typename T>
-__device__ __forceinline__ void load_cell(const SkBatch& p, Lds<T>& L, const double* f_src,
-                                          int c, int W1, int W2, int64_t base,
-                                          double* big_scratch) {
-    const int N2 = p.xside * p.xside;
+// Load one cell: f and log mu into LDS, log nu_J into the tile (G = false).
+template <typename Tm, typename T, bool G>
+__device__ __forceinline__ void load_cell(const Tm& tm, const SkBatch& p, const Lds<T, G>& L,
+                                          const double* f_src, int c, int W1, int W2,
+                                          int64_t base) {
+    const int N2 = p.xside * p.xside, tid = tm.tid(), nt = tm.size();
     // zero-mass points carry the log-domain sentinel in log mu / log nu_J, which removes
     // them from every sum whatever their potential
-    for (int i = threadIdx.x; i < N2; i += blockDim.x) {
+    for (int i = tid; i < N2; i += nt) {
         L.lm[i] = p.logmu[(int64_t)c * N2 + i];
         L.f[i] = f_src[(int64_t)c * N2 + i];
     }
-    const int AS = p.xside;
-    L.ASp = AS + 1;
-    if (W1 <= p.lw1 && W2 <= p.lw2) {
-        L.ln = L.ln_l;
-        L.qx = L.qx_l;
-        L.gq = L.gq_l;
-        L.zq = L.zq_l;
-        L.t1 = L.t1_l;
-        L.u = L.u_l;
-        L.kq = L.kq_l;
-        L.ys = L.lys;
-        L.W2p = L.lys;
-        for (int o = threadIdx.x; o < W1 * W2; o += blockDim.x) {
+    if constexpr (!G)
+        for (int o = tid; o < W1 * W2; o += nt) {
             const int j1 = o / W2, j2 = o - j1 * W2;
             L.ln[j1 * L.ys + j2] = p.lognu[base + o];
         }
-    } else {
-        double* sc = big_scratch + p.scr_off[c];
-        L.ln = const_cast<double*>(p.lognu) + base;
-        L.qx = sc;
-        T* t = reinterpret_cast<T*>(sc + W1);
-        L.gq = t;
-        t += (int64_t)W1 * W2;
-        L.zq = t;
-        t += (int64_t)W1 * W2;
-        L.t1 = t;
-        t += (int64_t)AS * (W2 + 1);
-        L.u = t;
-        t += (int64_t)W1 * (AS + 1);
-        L.kq = t;
-        L.ys = W2;
-        L.W2p = W2 + 1;
-    }
-    __syncthreads();
+    tm.sync();
 }
 
-template <typename T>
-__device__ __forceinline__ void store_g(const SkBatch& p, const Lds<T>& L, int W1, int W2,
-                                        int64_t base) {
+template <typename Tm, typename T, bool G>
+__device__ __forceinline__ void store_g(const Tm& tm, const SkBatch& p, const Lds<T, G>& L, int W1,
+                                        int W2, int64_t base) {
     const double goff = -L.red[8];
-    for (int o = threadIdx.x; o < W1 * W2; o += blockDim.x) {
+    for (int o = tm.tid(); o < W1 * W2; o += tm.size()) {
         const int j1 = o / W2, j2 = o - j1 * W2;
         p.b[base + o] = (double)L.gq[j1 * L.ys + j2] + goff;
     }
 }
 
-// ctrl words: [0] work queue, [1] ticket, [2] done iteration, [3] bad-dims flag, [4] converged
+// ctrl words: [0] big-cell queue, [1] ticket, [2] done iteration, [3] bad-dims flag,
+// [4] converged, [9] small-cell queue; [5..8] batch statistics
 __global__ void zero_ints(int* p, int n) {
     for (int i = threadIdx.x; i < n; i += blockDim.x) p[i] = 0;
 }
+
+// Bind cell c to an LDS slice -- its Y-box arrays in the slice's tile when the box fits,
+// else (AllowG) in its global scratch -- and run `body` on the view.  A box that fits
+// neither sets the bad-dims flag and is skipped.
+template <typename T, bool AllowG, typename Tm, typename F>
+__device__ __forceinline__ void with_cell(const Tm& tm, const SkBatch& p, lds_p<char> slice,
+                                          int lw1, int lw2, int c, double* big_scratch,
+                                          int* ctrl, F&& body) {
+    const int W1 = p.dims[2 * c], W2 = p.dims[2 * c + 1];
+    const bool bad = W1 < 1 || W2 < 1 || W1 > p.max_w1 || W2 > p.max_w2;
+    const bool fits = W1 <= lw1 && W2 <= lw2;
+    if (bad || (!AllowG && !fits)) {
+        if (tm.tid() == 0) atomicOr(&ctrl[3], 1);
+        body.skip(c);
+        return;
+    }
+    const int64_t base = p.base[c];
+    if (fits) {
+        const Lds<T, false> L = carve<T, false>(slice, p, lw1, lw2, c, W1, W2, base, big_scratch);
+        body(L, c, W1, W2, base);
+    } else if constexpr (AllowG) {
+        const Lds<T, true> L = carve<T, true>(slice, p, lw1, lw2, c, W1, W2, base, big_scratch);
+        body(L, c, W1, W2, base);
+    }
+}
+
+// Per-cell rule / fixed count: iterate the cell to its own stop, then store f and g.
+template <typename Tm, typename T>
+struct SolveCell {
+    const Tm& tm;
+    const SkBatch& p;
+    double tol;
+    int limit, fixed, stall_window;
+    int32_t* iters_out;
+    double* err_out;
+    double* mass_out;
+    __device__ void skip(int c) const {
+        if (tm.tid() == 0) {
+            iters_out[c] = 0;
+            err_out[c] = 0.0;
+            mass_out[c] = 0.0;
+        }
+    }
+    template <bool G>
+    __device__ void operator()(const Lds<T, G>& L, int c, int W1, int W2, int64_t base) const {
+        const int AS = p.xside, N2 = AS * AS, tid = tm.tid(), nt = tm.size();
+        const T invk = T(1.0 / p.kappa);
+        const int E1 = p.shift[2 * c], E2 = p.shift[2 * c + 1];
+        load_cell(tm, p, L, p.a, c, W1, W2, base);
+        double err = 0.0, mass = 0.0, err_ref = 1e300;
+        int it = 1;
+        for (;; ++it) {
+            y_half(tm, L, AS, W1, W2, E1, E2, invk);
+            x_half(tm, L, AS, W1, W2, E1, E2, invk);
+            err_mass(tm, L, AS, err, mass);
+            bool stop = (it >= limit) || (!fixed && err <= tol * mass);
+            // a float32 solve whose error has stopped falling (rounding floor) hands the
+            // cell to the float64 finish, which certifies the tolerance
+            if (!fixed && stall_window > 0 && it % stall_window == 0) {
+                if (err > 0.99 * err_ref) stop = true;
+                err_ref = err;
+            }
+            if (stop) break;
+            for (int i = tid; i < N2; i += nt) L.f[i] = -L.s[i];
+            tm.sync();
+        }
+        for (int i = tid; i < N2; i += nt) p.a[(int64_t)c * N2 + i] = L.f[i];
+        store_g(tm, p, L, W1, W2, base);
+        if (tid == 0) {
+            iters_out[c] = it;
+            err_out[c] = err;
+            mass_out[c] = mass;
+        }
+        tm.sync();
+    }
+};
 
 template <typename T>
 __global__ void __launch_bounds__(kThreads)
@@ -335,53 +459,119 @@ __global__ void __launch_bounds__(kThreads)
                    int32_t* iters_out, double* err_out, double* mass_out, double* big_scratch) {
     extern __shared__ __align__(16) char smem[];
     __shared__ int s_cell;
-    const int AS = p.xside, N2 = AS * AS;
-    Lds<T> L = carve<T>(smem, AS, p.lw1, p.lw2);
-    const T invk = T(1.0 / p.kappa);
-    for (;;) {
-        __syncthreads();
-        if (threadIdx.x == 0) s_cell = atomicAdd(&ctrl[0], 1);
-        __syncthreads();
-        const int q = s_cell;
-        if (q >= p.ncells) break;
-        const int c = p.order ? p.order[q] : q;
-        const int W1 = p.dims[2 * c], W2 = p.dims[2 * c + 1];
-        if (W1 < 1 || W2 < 1 || W1 > p.max_w1 || W2 > p.max_w2) {
-            if (threadIdx.x == 0) {
-                atomicOr(&ctrl[3], 1);
-                iters_out[c] = 0;
-                err_out[c] = 0.0;
-                mass_out[c] = 0.0;
-            }
-            continue;
-        }
-        const int64_t base = p.base[c];
-        const int E1 = p.shift[2 * c], E2 = p.shift[2 * c + 1];
-        load_cell<T>(p, L, p.a, c, W1, W2, base, big_scratch);
-        double err = 0.0, mass = 0.0, err_ref = 1e300;
-        int it = 1;
-        for (;; ++it) {
-            y_half(L, AS, W1, W2, E1, E2, invk);
-            x_half(L, AS, W1, W2, E1, E2, invk);
-            err_mass(L, AS, err, mass);
-            bool stop = (it >= limit) || (!fixed && err <= tol * mass);
-            // a float32 solve whose error has stopped falling (rounding floor) hands the cell
-            // to the float64 finish, which certifies the tolerance
-            if (!fixed && stall_window > 0 && it % stall_window == 0) {
-                if (err > 0.99 * err_ref) stop = true;
-                err_ref = err;
-            }
-            if (stop) break;
-            for (int i = threadIdx.x; i < N2; i += blockDim.x) L.f[i] = -L.s[i];
+    const lds_p<char> base = (lds_p<char>)smem;
+    const int nsmall = p.ncells - p.nbig;
+    // big cells: the whole workgroup on one cell
+    {
+        const BlockTeam tm;
+        const SolveCell<BlockTeam, T> body{tm, p, tol, limit, fixed, stall_window,
+                                           iters_out, err_out, mass_out};
+        for (;;) {
             __syncthreads();
+            if (threadIdx.x == 0) s_cell = atomicAdd(&ctrl[0], 1);
+            __syncthreads();
+            const int q = s_cell;
+            if (q >= p.nbig) break;
+            with_cell<T, true>(tm, p, base, p.lw1b, p.lw2b, p.order[q], big_scratch, ctrl, body);
         }
-        for (int i = threadIdx.x; i < N2; i += blockDim.x) p.a[(int64_t)c * N2 + i] = L.f[i];
-        store_g(p, L, W1, W2, base);
-        if (threadIdx.x == 0) {
-            iters_out[c] = it;
-            err_out[c] = err;
-            mass_out[c] = mass;
+    }
+    __syncthreads();
+    // small cells: each wave on its own cell, in its own LDS slice
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
+    const lds_p<char> slice = base + w * lds_layout_bytes(p.xside, p.lw1, p.lw2, sizeof(T));
+    const WaveTeam tm;
+    const SolveCell<WaveTeam, T> body{tm, p, tol, limit, fixed, stall_window,
+                                      iters_out, err_out, mass_out};
+    for (;;) {
+        int q = 0;
+        if (lane == 0) q = atomicAdd(&ctrl[9], 1);
+        q = __builtin_amdgcn_readfirstlane(__shfl(q, 0, 64));
+        if (q >= nsmall) break;
+        with_cell<T, false>(tm, p, slice, p.lw1, p.lw2, p.order[p.nbig + q], big_scratch, ctrl,
+                            body);
+    }
+}
+
+// One batch-rule iteration of a cell: f_in -> f_out, per-cell error and mass.
+template <typename Tm, typename T>
+struct IterCell {
+    const Tm& tm;
+    const SkBatch& p;
+    const double* f_in;
+    double* f_out;
+    double* cell_err;
+    double* cell_mass;
+    __device__ void skip(int c) const {
+        if (tm.tid() == 0) {
+            cell_err[c] = 0.0;
+            cell_mass[c] = 0.0;
         }
+    }
+    template <bool G>
+    __device__ void operator()(const Lds<T, G>& L, int c, int W1, int W2, int64_t base) const {
+        const int AS = p.xside, N2 = AS * AS, tid = tm.tid(), nt = tm.size();
+        const T invk = T(1.0 / p.kappa);
+        const int E1 = p.shift[2 * c], E2 = p.shift[2 * c + 1];
+        load_cell(tm, p, L, f_in, c, W1, W2, base);
+        y_half(tm, L, AS, W1, W2, E1, E2, invk);
+        x_half(tm, L, AS, W1, W2, E1, E2, invk);
+        double err, mass;
+        err_mass(tm, L, AS, err, mass);
+        if (tid == 0) {
+            cell_err[c] = err;
+            cell_mass[c] = mass;
+        }
+        for (int i = tid; i < N2; i += nt) f_out[(int64_t)c * N2 + i] = -L.s[i];
+        tm.sync();
+    }
+};
+
+// g from the final f (one Y-update) of a cell, for the batch-rule driver.
+template <typename Tm, typename T>
+struct FinalCell {
+    const Tm& tm;
+    const SkBatch& p;
+    int done;
+    int32_t* iters_out;
+    __device__ void skip(int) const {}
+    template <bool G>
+    __device__ void operator()(const Lds<T, G>& L, int c, int W1, int W2, int64_t base) const {
+        const T invk = T(1.0 / p.kappa);
+        load_cell(tm, p, L, p.a, c, W1, W2, base);
+        y_half(tm, L, p.xside, W1, W2, p.shift[2 * c], p.shift[2 * c + 1], invk);
+        store_g(tm, p, L, W1, W2, base);
+        if (tm.tid() == 0) iters_out[c] = done;
+        tm.sync();
+    }
+};
+
+// Work items of a batch-rule launch: the big cells one per item, then the small cells four
+// per item (one per wave).
+__host__ __device__ inline int batch_items(int ncells, int nbig) {
+    return nbig + (ncells - nbig + kWaves - 1) / kWaves;
+}
+
+// Run `make(team)` over the batch-rule items assigned to this workgroup.
+template <typename T, typename Make>
+__device__ __forceinline__ void for_items(const SkBatch& p, lds_p<char> base, double* big_scratch,
+                                          int* ctrl, Make&& make) {
+    const int nitems = batch_items(p.ncells, p.nbig);
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const lds_p<char> slice = base + w * lds_layout_bytes(p.xside, p.lw1, p.lw2, sizeof(T));
+    for (int q = blockIdx.x; q < nitems; q += gridDim.x) {
+        if (q < p.nbig) {
+            const BlockTeam tm;
+            with_cell<T, true>(tm, p, base, p.lw1b, p.lw2b, p.order[q], big_scratch, ctrl,
+                               make(tm));
+        } else {
+            const int k = p.nbig + (q - p.nbig) * kWaves + w;
+            if (k < p.ncells) {
+                const WaveTeam tm;
+                with_cell<T, false>(tm, p, slice, p.lw1, p.lw2, p.order[k], big_scratch, ctrl,
+                                    make(tm));
+            }
+        }
+        __syncthreads();
     }
 }
 
@@ -393,34 +583,11 @@ __global__ void __launch_bounds__(kThreads)
     if (__atomic_load_n(&ctrl[2], __ATOMIC_RELAXED) != 0) return;
     extern __shared__ __align__(16) char smem[];
     __shared__ int s_last;
-    const int AS = p.xside, N2 = AS * AS;
-    Lds<T> L = carve<T>(smem, AS, p.lw1, p.lw2);
-    const T invk = T(1.0 / p.kappa);
-    for (int q = blockIdx.x; q < p.ncells; q += gridDim.x) {
-        const int c = p.order ? p.order[q] : q;
-        const int W1 = p.dims[2 * c], W2 = p.dims[2 * c + 1];
-        if (W1 < 1 || W2 < 1 || W1 > p.max_w1 || W2 > p.max_w2) {
-            if (threadIdx.x == 0) {
-                atomicOr(&ctrl[3], 1);
-                cell_err[c] = 0.0;
-                cell_mass[c] = 0.0;
-            }
-            continue;
-        }
-        const int64_t base = p.base[c];
-        const int E1 = p.shift[2 * c], E2 = p.shift[2 * c + 1];
-        load_cell<T>(p, L, f_in, c, W1, W2, base, big_scratch);
-        y_half(L, AS, W1, W2, E1, E2, invk);
-        x_half(L, AS, W1, W2, E1, E2, invk);
-        double err, mass;
-        err_mass(L, AS, err, mass);
-        if (threadIdx.x == 0) {
-            cell_err[c] = err;
-            cell_mass[c] = mass;
-        }
-        for (int i = threadIdx.x; i < N2; i += blockDim.x) f_out[(int64_t)c * N2 + i] = -L.s[i];
-        __syncthreads();
-    }
+    __shared__ double s_red[16];
+    for_items<T>(p, (lds_p<char>)smem, big_scratch, ctrl, [&](const auto& tm) {
+        using Tm = std::decay_t<decltype(tm)>;
+        return IterCell<Tm, T>{tm, p, f_in, f_out, cell_err, cell_mass};
+    });
     // last workgroup to finish reduces the per-cell errors in fixed order
     __threadfence();
     if (threadIdx.x == 0) s_last = (atomicAdd(&ctrl[1], 1) == (int)gridDim.x - 1);
@@ -432,8 +599,8 @@ __global__ void __launch_bounds__(kThreads)
         e += cell_err[c];
         m += cell_mass[c];
     }
-    e = block_sum(e, L.red);
-    m = block_sum(m, L.red);
+    e = block_sum(e, s_red);
+    m = block_sum(m, s_red);
     if (threadIdx.x == 0) {
         dtot[0] = e;
         dtot[1] = m;
@@ -444,27 +611,16 @@ __global__ void __launch_bounds__(kThreads)
     }
 }
 
-// g from the final f (one Y-update), for the batch-rule driver.
 template <typename T>
-__global__ void __launch_bounds__(kThreads) sk_final_kernel(SkBatch p, const int* ctrl,
+__global__ void __launch_bounds__(kThreads) sk_final_kernel(SkBatch p, int* ctrl,
                                                            int32_t* iters_out,
                                                            double* big_scratch) {
     extern __shared__ __align__(16) char smem[];
-    const int AS = p.xside;
-    Lds<T> L = carve<T>(smem, AS, p.lw1, p.lw2);
-    const T invk = T(1.0 / p.kappa);
     const int done = ctrl[2];
-    for (int q = blockIdx.x; q < p.ncells; q += gridDim.x) {
-        const int c = p.order ? p.order[q] : q;
-        const int W1 = p.dims[2 * c], W2 = p.dims[2 * c + 1];
-        if (W1 < 1 || W2 < 1 || W1 > p.max_w1 || W2 > p.max_w2) continue;
-        const int64_t base = p.base[c];
-        load_cell<T>(p, L, p.a, c, W1, W2, base, big_scratch);
-        y_half(L, AS, W1, W2, p.shift[2 * c], p.shift[2 * c + 1], invk);
-        store_g(p, L, W1, W2, base);
-        if (threadIdx.x == 0) iters_out[c] = done;
-        __syncthreads();
-    }
+    for_items<T>(p, (lds_p<char>)smem, big_scratch, ctrl, [&](const auto& tm) {
+        using Tm = std::decay_t<decltype(tm)>;
+        return FinalCell<Tm, T>{tm, p, done, iters_out};
+    });
 }
 
 // Batch statistics: sums of err, mass, iterations, terms and algorithmic bytes; min/max
@@ -474,8 +630,7 @@ __global__ void __launch_bounds__(kThreads)
                     const double* mass, double tol, const int32_t* dims, int xside, double* dtot,
                     int* ictl) {
     __shared__ double red[8];
-    __shared__ int smin[kThreads / 64], smax[kThreads / 64], sconv[kThreads / 64],
-        spol[kThreads / 64];
+    __shared__ int smin[kWaves], smax[kWaves], sconv[kWaves], spol[kWaves];
     double e = 0.0, m = 0.0, work = 0.0, bytes = 0.0, terms = 0.0;
     int imin = 0x7fffffff, imax = 0, allconv = 1, pmax = 0;
     for (int c = threadIdx.x; c < ncells; c += blockDim.x) {
@@ -533,7 +688,7 @@ __global__ void __launch_bounds__(kThreads)
 size_t sk_lds_bytes(int xside, int prec) {
     if (xside < 2 || xside > 16) return 0;
     const size_t e = prec == DD_PREC_F64 ? sizeof(double) : sizeof(float);
-    return lds_layout_bytes(xside, 0, 0, e);
+    return wg_lds_bytes(xside, 0, 0, 0, 0, e);
 }
 
 Status sk_work_reserve(SkWork& w, int ncells, size_t a_n) {
@@ -609,14 +764,14 @@ Status set_lds_attr(K kernel, size_t bytes, Status& st) {
 }
 
 template <typename K>
-int grid_for(K kernel, size_t lds, int ncells) {
+int grid_for(K kernel, size_t lds, int items) {
     int per_cu = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(kernel),
                                                      kThreads, lds) != hipSuccess ||
         per_cu < 1)
         per_cu = 1;
     const long g = (long)per_cu * num_cus();
-    return (int)std::max(1L, std::min<long>(g, ncells));
+    return (int)std::max(1L, std::min<long>(g, items));
 }
 
 template <typename T>
@@ -624,13 +779,13 @@ Status run_solver(const SkBatch& p, const dd_sinkhorn_opts& o, hipStream_t st, S
                   int32_t* iters, double* errs) {
     Status S;
     double* big = reinterpret_cast<double*>(w.big);
-    const size_t lds = lds_layout_bytes(p.xside, p.lw1, p.lw2, sizeof(T));
+    const size_t lds = wg_lds_bytes(p.xside, p.lw1, p.lw2, p.lw1b, p.lw2b, sizeof(T));
     const bool fixed = o.fixed_iters > 0;
-    zero_ints<<<1, 64, 0, st>>>(w.ctrl, 5);
+    zero_ints<<<1, 64, 0, st>>>(w.ctrl, 10);
     if (fixed || o.stop_rule == DD_STOP_CELL) {
         auto kern = sk_cell_kernel<T>;
         if (set_lds_attr(kern, lds, S).code) return S;
-        const int grid = grid_for(kern, lds, p.ncells);
+        const int grid = grid_for(kern, lds, batch_items(p.ncells, p.nbig));
         const int limit = fixed ? o.fixed_iters : o.max_iter;
         // stall detection only where a float64 finish follows
         const int stall = sizeof(T) == sizeof(float) ? 32 : 0;
@@ -643,7 +798,7 @@ Status run_solver(const SkBatch& p, const dd_sinkhorn_opts& o, hipStream_t st, S
     auto fin = sk_final_kernel<T>;
     if (set_lds_attr(kern, lds, S).code) return S;
     if (set_lds_attr(fin, lds, S).code) return S;
-    const int grid = grid_for(kern, lds, p.ncells);
+    const int grid = grid_for(kern, lds, batch_items(p.ncells, p.nbig));
     double* bufs[2] = {p.a, w.a_alt};
     const size_t a_bytes = (size_t)p.ncells * p.xside * p.xside * sizeof(double);
     const int chunk = o.check_every > 0 ? o.check_every : 8;
@@ -665,33 +820,35 @@ Status run_solver(const SkBatch& p, const dd_sinkhorn_opts& o, hipStream_t st, S
     return S;
 }
 
-// LDS tile for the Y-box arrays: the largest bounds that keep ~8 single-wave workgroups per
-// CU, taken from per-axis quantiles of the box dims so that most cells stay LDS-resident.
-void plan_tile(const std::vector<int32_t>& hd, int ncells, int xside, int mw1, int mw2,
-               size_t elem, int& lw1, int& lw2) {
-    const size_t budget = 20 * 1024;
+// LDS tile for the Y-box arrays of one class of cells: the largest bounds within the byte
+// budget, taken from per-axis quantiles of the class's box dims so that most of its cells
+// stay LDS-resident.
+void plan_tile(const std::vector<int32_t>& hd, const std::vector<int32_t>& cells, int xside,
+               size_t elem, size_t budget, int& lw1, int& lw2) {
+    lw1 = lw2 = 0;
+    const int n = (int)cells.size();
+    if (n == 0) return;
     auto fits = [&](int a, int b) { return lds_layout_bytes(xside, a, b, elem) <= budget; };
-    if (fits(mw1, mw2)) {
-        lw1 = mw1;
-        lw2 = mw2;
-        return;
-    }
-    std::vector<int> d1(ncells), d2(ncells);
-    for (int c = 0; c < ncells; ++c) {
-        d1[c] = hd[2 * c];
-        d2[c] = hd[2 * c + 1];
+    std::vector<int> d1(n), d2(n);
+    for (int k = 0; k < n; ++k) {
+        d1[k] = hd[2 * cells[k]];
+        d2[k] = hd[2 * cells[k] + 1];
     }
     std::sort(d1.begin(), d1.end());
     std::sort(d2.begin(), d2.end());
+    if (fits(d1[n - 1], d2[n - 1])) {
+        lw1 = d1[n - 1];
+        lw2 = d2[n - 1];
+        return;
+    }
     for (double q : {0.99, 0.97, 0.95, 0.9, 0.85, 0.8, 0.7, 0.6, 0.5, 0.3, 0.1}) {
-        const int k = std::min(ncells - 1, (int)(q * ncells));
+        const int k = std::min(n - 1, (int)(q * n));
         if (fits(d1[k], d2[k])) {
             lw1 = d1[k];
             lw2 = d2[k];
             return;
         }
     }
-    lw1 = lw2 = 0;
 }
 }  // namespace
 
@@ -722,44 +879,68 @@ Status sk_solve(const SkBatch& p, const dd_sinkhorn_opts& o, hipStream_t st, SkW
         }
         return S;
     }
-    // plan on the host from the box dims: processing order (largest box first), LDS tile,
-    // global scratch for the boxes beyond the tile
+    // plan on the host from the box dims: processing order (most LSE work first), the split
+    // into big (workgroup) and small (wave) cells, an LDS tile per class, and global scratch
+    // for the boxes beyond their tile
     std::vector<int32_t> hd(2 * (size_t)p.ncells);
     std::vector<int64_t> hb(p.ncells);
     DD_HIP(hipMemcpyAsync(hd.data(), p.dims, hd.size() * 4, hipMemcpyDeviceToHost, st), S);
     DD_HIP(hipMemcpyAsync(hb.data(), p.base, hb.size() * 8, hipMemcpyDeviceToHost, st), S);
     DD_HIP(hipStreamSynchronize(st), S);
-    SkBatch q = p;
-    if (!p.order) {
-        std::vector<int32_t> ord(p.ncells);
-        for (int c = 0; c < p.ncells; ++c) ord[c] = c;
-        std::stable_sort(ord.begin(), ord.end(), [&](int a, int b) {
-            return (int64_t)hd[2 * a] * hd[2 * a + 1] > (int64_t)hd[2 * b] * hd[2 * b + 1];
-        });
-        if (p.ncells > w.order_cap) {
-            if (w.order) (void)hipFree(w.order);
-            w.order = nullptr;
-            DD_HIP(hipMalloc(&w.order, std::max(p.ncells, 1024) * sizeof(int32_t)), S);
-            w.order_cap = std::max(p.ncells, 1024);
-        }
-        DD_HIP(hipMemcpyAsync(w.order, ord.data(), ord.size() * 4, hipMemcpyHostToDevice, st), S);
-        DD_HIP(hipStreamSynchronize(st), S);
-        q.order = w.order;
-    }
+    const int AS = p.xside;
+    auto work = [&](int c) {
+        return sk_cell_terms(AS, std::max(hd[2 * c], 0), std::max(hd[2 * c + 1], 0));
+    };
+    std::vector<int32_t> ord(p.ncells);
+    for (int c = 0; c < p.ncells; ++c) ord[c] = c;
+    std::stable_sort(ord.begin(), ord.end(), [&](int a, int b) { return work(a) > work(b); });
+    // LDS budget per workgroup: ~2 workgroups (8 waves) per CU
+    const size_t wg_budget = 78 * 1024;
     const size_t elem = p.prec == DD_PREC_F64 ? sizeof(double) : sizeof(float);
-    plan_tile(hd, p.ncells, p.xside, p.max_w1, p.max_w2, elem, q.lw1, q.lw2);
-    // the float64 finish uses its own (smaller) tile; size the scratch for float64 boxes
-    int lw1d = 0, lw2d = 0;
-    plan_tile(hd, p.ncells, p.xside, p.max_w1, p.max_w2, sizeof(double), lw1d, lw2d);
-    // per-cell global scratch for boxes beyond either tile, sized for float64 terms
+    // a cell whose LSE work per iteration is several times a typical cell's runs on the whole
+    // workgroup; the others run one per wave from the LDS tile planned over them, and a cell
+    // that does not fit that tile (in either precision) also goes to a workgroup
+    const double big_terms = 64.0 * 1024.0;
+    std::vector<int32_t> cand;
+    for (int c : ord)
+        if (work(c) < big_terms) cand.push_back(c);
+    SkBatch q = p;
+    SkBatch q64 = p;
+    plan_tile(hd, cand, AS, elem, wg_budget / kWaves, q.lw1, q.lw2);
+    plan_tile(hd, cand, AS, sizeof(double), wg_budget / kWaves, q64.lw1, q64.lw2);
+    const int sw1 = std::min(q.lw1, q64.lw1), sw2 = std::min(q.lw2, q64.lw2);
+    std::vector<int32_t> big_cells, small_cells;
+    for (int c : ord) {
+        if (work(c) < big_terms && hd[2 * c] <= sw1 && hd[2 * c + 1] <= sw2)
+            small_cells.push_back(c);
+        else
+            big_cells.push_back(c);
+    }
+    const int nbig = (int)big_cells.size();
+    plan_tile(hd, big_cells, AS, elem, wg_budget, q.lw1b, q.lw2b);
+    plan_tile(hd, big_cells, AS, sizeof(double), wg_budget, q64.lw1b, q64.lw2b);
+    ord = big_cells;
+    ord.insert(ord.end(), small_cells.begin(), small_cells.end());
+    q.nbig = q64.nbig = nbig;
+    if (p.ncells > w.order_cap) {
+        if (w.order) (void)hipFree(w.order);
+        w.order = nullptr;
+        DD_HIP(hipMalloc(&w.order, std::max(p.ncells, 1024) * sizeof(int32_t)), S);
+        w.order_cap = std::max(p.ncells, 1024);
+    }
+    DD_HIP(hipMemcpyAsync(w.order, ord.data(), ord.size() * 4, hipMemcpyHostToDevice, st), S);
+    q.order = q64.order = w.order;
+    // per-cell global scratch for the big boxes beyond their tile in either precision, sized
+    // for float64 terms
     std::vector<int64_t> off(p.ncells, 0);
     int64_t scr = 0;
-    for (int c = 0; c < p.ncells; ++c) {
+    const int bw1 = std::min(q.lw1b, q64.lw1b), bw2 = std::min(q.lw2b, q64.lw2b);
+    for (int c : big_cells) {
         const int W1 = hd[2 * c], W2 = hd[2 * c + 1];
         if (W1 < 1 || W2 < 1) continue;
-        if (W1 > std::min(q.lw1, lw1d) || W2 > std::min(q.lw2, lw2d)) {
+        if (W1 > bw1 || W2 > bw2) {
             off[c] = scr;
-            scr += cell_scratch_doubles(p.xside, W1, W2, sizeof(double));
+            scr += cell_scratch_doubles(AS, W1, W2, sizeof(double));
         }
     }
     if (p.ncells > w.scr_cap) {
@@ -769,7 +950,7 @@ Status sk_solve(const SkBatch& p, const dd_sinkhorn_opts& o, hipStream_t st, SkW
         w.scr_cap = std::max(p.ncells, 1024);
     }
     DD_HIP(hipMemcpyAsync(w.scr_off, off.data(), off.size() * 8, hipMemcpyHostToDevice, st), S);
-    q.scr_off = w.scr_off;
+    q.scr_off = q64.scr_off = w.scr_off;
     if (scr > 0) {
         const size_t need = (size_t)scr * sizeof(double) + 64;
         if (need > w.big_bytes) {
@@ -791,9 +972,6 @@ Status sk_solve(const SkBatch& p, const dd_sinkhorn_opts& o, hipStream_t st, SkW
     if (finish) {
         // float64 finish: continue the same stopping rule in float64 from the float32 state;
         // the tolerance is then certified by a float64 error (usually after one Y-update)
-        SkBatch q64 = q;
-        q64.lw1 = lw1d;
-        q64.lw2 = lw2d;
         S = run_solver<double>(q64, o, st, w, w.iters64, errs);
         if (S.code) return S;
     }

@@ -17,10 +17,14 @@ struct SkBatch {
     const double* lognu = nullptr;   // packed Y boxes
     double* a = nullptr;             // [ncells][xside^2] f, in/out
     double* b = nullptr;             // packed Y boxes, g out
-    const int32_t* order = nullptr;  // optional processing order (largest first), may be null
+    const int32_t* order = nullptr;  // processing order, most work first (set by sk_solve)
     double kappa = 1.0;
     int max_w1 = 0, max_w2 = 0;
-    int lw1 = 0, lw2 = 0;            // LDS tile bound for the Y-box arrays (set by sk_solve)
+    // set by sk_solve: the cells order[0..nbig) run one per workgroup, the rest one per wave;
+    // LDS tile bounds for the Y-box arrays of the small (lw1, lw2) and big (lw1b, lw2b) cells
+    int nbig = 0;
+    int lw1 = 0, lw2 = 0;
+    int lw1b = 0, lw2b = 0;
     const int64_t* scr_off = nullptr; // [ncells] offset (in doubles) of a cell's global scratch
                                       // when its box exceeds the LDS tile (set by sk_solve)
     int prec = DD_PREC_F32;

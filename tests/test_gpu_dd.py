@@ -124,3 +124,28 @@ def test_init_rejects_bad_inputs():
     x, y, m = synth.kr_coupling(w.mu, w.nu)
     with pytest.raises(dd.DomDecError):
         dd.DomDec(w.mu, w.nu, w.s, (x, y, m * 1.01))  # wrong marginals
+
+
+def test_save_restore_replays_bit_exactly():
+    """domdec_save / domdec_restore: an iteration replayed from the saved state gives the
+    same plan, bit for bit (the solve is deterministic)."""
+    import paper_2405_09400_amd as dd
+    _need_gpu()
+    print("save/restore mix256 N=64", flush=True)
+    w = synth.workload("mix256", N=64)
+    g = dd.DomDec(w.mu, w.nu, w.s, w.init)
+    h = 1.0 / w.N
+    for part in "ABA":
+        g.iterate(part, 4 * h * h, tol=1e-5)
+    g.save()
+    s1 = g.iterate("B", h * h, tol=1e-5)
+    p1 = g.extract_plan()
+    g.restore()
+    with pytest.raises(dd.DomDecError):
+        g.flow_update()  # the last iteration's data is gone after a restore
+    s2 = g.iterate("B", h * h, tol=1e-5)
+    p2 = g.extract_plan()
+    assert s1["sk"]["iters_max"] == s2["sk"]["iters_max"]
+    for a, b in zip(p1, p2):
+        assert np.array_equal(a, b)
+    g.close()

@@ -1,0 +1,176 @@
+"""The learned warm-start net (dd_net): inference and one training step of the hand-written
+kernels against a plain PyTorch fp32 reference of the same net on the CPU, and its use as
+the start of the cell solves (the stopping rule must stay untouched).
+
+The net is not part of the paper's method; its outputs have no paper value to match
+("parity unpinned" for the predictions).  What is pinned here is that the kernels compute
+the stated net and its gradients, and that a solve started from the prediction still meets
+the tolerance."""
+import numpy as np
+import pytest
+
+import synth
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+LAYERS = [(6, 32, 2, 1), (32, 32, 1, 1), (32, 32, 1, 2), (32, 32, 1, 4), (32, 4, 1, 1)]
+
+
+def _need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def _unpack(params):
+    out, k = [], 0
+    for cin, cout, _, _ in LAYERS:
+        w = params[k:k + cout * cin * 9].reshape(cout, cin, 3, 3)
+        k += cout * cin * 9
+        b = params[k:k + cout]
+        k += cout
+        out.append((w, b))
+    return out
+
+
+def _ref_forward(params, x):
+    """fp32 CPU forward with the kernels' BF16 rounding of the weights (biases FP32)."""
+    F = torch.nn.functional
+    h = x
+    for l, ((w, b), (_, _, stride, dil)) in enumerate(zip(_unpack(params), LAYERS)):
+        wb = w.to(torch.bfloat16).to(torch.float32)
+        h = F.conv2d(h, wb, b, stride=stride, padding=dil, dilation=dil)
+        if l < len(LAYERS) - 1:
+            h = torch.relu(h)
+    return F.pixel_shuffle(h, 2)[:, 0]
+
+
+def _ref_loss(y, t, w):
+    sw = w.sum(dim=(1, 2), keepdim=True)
+    c = (w * (y - t)).sum(dim=(1, 2), keepdim=True) / sw
+    return (w * (y - t - c) ** 2).sum(dim=(1, 2)).mean()
+
+
+def _inputs(n, seed):
+    rng = np.random.default_rng(seed)
+    x = rng.normal(0.0, 1.0, (n, 6, 32, 32)).astype(np.float32)
+    t = rng.normal(0.0, 3.0, (n, 32, 32)).astype(np.float32)
+    w = rng.uniform(0.0, 1.0, (n, 32, 32)).astype(np.float32)
+    w[:, :4, :] = 0.0  # empty rows, as outside a box
+    w /= w.sum(axis=(1, 2), keepdims=True)
+    return x, t, w
+
+
+def _params(seed):
+    import paper_2405_09400_amd as dd
+    p = dd.net_init_params(seed)
+    rng = np.random.default_rng(seed + 7)
+    # non-zero biases so that they are exercised
+    k = 0
+    for cin, cout, _, _ in LAYERS:
+        k += cout * cin * 9
+        p[k:k + cout] = rng.normal(0.0, 0.1, cout)
+        k += cout
+    return p
+
+
+@pytest.mark.parametrize("n", [1, 5, 300])
+def test_forward_matches_torch(n):
+    import paper_2405_09400_amd as dd
+    _need_gpu()
+    print(f"net forward n={n}", flush=True)
+    p = _params(3)
+    x, _, _ = _inputs(n, 11)
+    net = dd.WarmStartNet(p)
+    y = net.forward(torch.from_numpy(x).cuda()).cpu()
+    ref = _ref_forward(torch.from_numpy(p), torch.from_numpy(x))
+    err = (y - ref).abs().max().item()
+    assert err <= 2e-5 * ref.abs().max().item() + 1e-6, err
+    net.close()
+
+
+def test_train_step_matches_torch():
+    """One Adam step: the loss before the step, and the update direction of every parameter
+    whose reference gradient is clearly non-zero (Adam's first step is -lr * g / (|g| + eps))."""
+    import paper_2405_09400_amd as dd
+    _need_gpu()
+    print("net train step", flush=True)
+    n, lr = 64, 1e-3
+    p = _params(5)
+    x, t, w = _inputs(n, 13)
+    net = dd.WarmStartNet(p)
+    loss = net.train_step(torch.from_numpy(x).cuda(), torch.from_numpy(t).cuda(),
+                          torch.from_numpy(w).cuda(), lr)
+    p1 = net.params()
+    # reference: gradient with respect to the BF16-rounded weights (straight through)
+    pt = torch.from_numpy(p.copy()).requires_grad_(True)
+    ref_loss = _ref_loss(_ref_forward(pt, torch.from_numpy(x)), torch.from_numpy(t),
+                         torch.from_numpy(w))
+    ref_loss.backward()
+    g = pt.grad.numpy()
+    assert abs(loss - ref_loss.item()) <= 1e-5 * abs(ref_loss.item()), (loss, ref_loss.item())
+    step = p1 - p
+    big = np.abs(g) > 1e-3 * np.abs(g).max()
+    assert big.sum() > 0.5 * g.size
+    assert np.all(np.sign(step[big]) == -np.sign(g[big]))
+    assert np.allclose(np.abs(step[big]), lr, rtol=1e-3)
+    # parameters with zero gradient do not move
+    assert np.all(np.abs(step) <= lr * 1.001)
+    net.close()
+
+
+def test_training_reduces_loss():
+    import paper_2405_09400_amd as dd
+    _need_gpu()
+    print("net training", flush=True)
+    p = _params(9)
+    x, t, w = _inputs(128, 17)
+    xs, ts, ws = (torch.from_numpy(a).cuda() for a in (x, t, w))
+    net = dd.WarmStartNet(p)
+    losses = [net.train_step(xs, ts, ws, 3e-3) for _ in range(40)]
+    assert losses[-1] < 0.7 * losses[0], losses
+    net.close()
+
+
+def test_samples_and_net_start_keep_tolerance():
+    """Samples of a DD iteration are consistent, and a solve started by the net meets the
+    same tolerance as one started from zero (the stopping rule is unchanged)."""
+    import paper_2405_09400_amd as dd
+    _need_gpu()
+    print("net start N=32", flush=True)
+    wl = synth.workload("mix256", N=32)
+    g = dd.DomDec(wl.mu, wl.nu, wl.s, wl.init)
+    h = 1.0 / wl.N
+    for part in "ABAB":
+        g.iterate(part, 4 * h * h, tol=1e-5)
+    x, t, w = g.net_samples()
+    assert x.shape[1:] == (6, 32, 32) and t.shape[1:] == (32, 32)
+    wsum = w.sum(dim=(1, 2))
+    assert torch.all(wsum <= 1.0 + 1e-5) and torch.all(wsum > 0.5)
+    assert torch.all(((w * t).sum(dim=(1, 2))).abs() <= 1e-3 * (w * t.abs()).sum(dim=(1, 2)) + 1e-6)
+    # indicator channels are 0/1, the mu block sits in the window centre
+    assert set(torch.unique(x[:, 1]).tolist()) <= {0.0, 1.0}
+    assert torch.all(x[:, 3, 12:20, 12:20].sum(dim=(1, 2)) > 0)
+    assert torch.all(x[:, 3, :12].sum(dim=(1, 2)) == 0)
+    net = dd.WarmStartNet(dd.net_init_params(0))
+    g.set_net(net)
+    for part in "AB":
+        st = g.iterate(part, h * h, tol=1e-5, init=dd.DD_INIT_NET)
+        assert st["status"] == dd.DD_OK
+        assert st["sk"]["err"] <= 1e-5 * st["sk"]["mass"]
+    ev = g.evaluate()
+    assert ev["y_marginal_l1"] < 1e-8
+    g.set_net(None)
+    g.close()
+    net.close()
+
+
+def test_net_start_requires_net():
+    import paper_2405_09400_amd as dd
+    _need_gpu()
+    wl = synth.workload("small32", N=16)
+    g = dd.DomDec(wl.mu, wl.nu, wl.s)
+    with pytest.raises(dd.DomDecError) as e:
+        g.iterate("A", 1.0 / 256, tol=1e-5, init=dd.DD_INIT_NET)
+    assert e.value.status == dd.DD_ESTATE
+    g.close()
