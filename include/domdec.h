@@ -299,6 +299,9 @@ typedef struct {
     double transport;       /* <c, pi> of the last composite plans                     */
     double basic_mass_err;  /* max_i |sum_y nu_i - m_i|                                */
     double total_mass;      /* sum of all stored nu_i entries                          */
+    double dual;            /* D of the stitched global dual point (NaN until both
+                               partitions have been iterated)                          */
+    double pd_gap;          /* primal - dual                                           */
 } dd_eval;
 
 /*

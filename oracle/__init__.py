@@ -288,7 +288,7 @@ class DomDec:
     # -- DomDecIter -----------------------------------------------------------
     def iterate(self, which: str, eps: float, tol: float = 1e-5, max_iter: int = 10000,
                 fixed_iters: int = 0, rule: int = 0, nthreads: int = 0, balance: bool = True,
-                truncate: bool = True) -> dict:
+                truncate: bool = True, cells=None) -> dict:
         """One DomDecIter on partition `which` (Alg. "DomDecIter"; App. A Alg. "DomDecIterGPU").
 
         For each composite cell J: mu_J = mu on X_J, nu_J = sum of its basic nu_i,
@@ -296,11 +296,17 @@ class DomDec:
         visit of this partition, zero on the first visit), set nu_i(y) =
         sum_{x in X_i} pi_J(x, y), then balance the basic masses inside J and
         truncate entries below 1e-15.
+
+        `cells` (optional) restricts the iteration to those composite cells; the cells of
+        one partition are independent problems (disjoint X_J), so the others are unchanged.
+        With a subset and the batch stopping rule the stopping test covers the subset only.
         """
         parts = self.parts[which]
+        sel = range(len(parts)) if cells is None else sorted(set(int(c) for c in cells))
         xoffs, yoffs = [0], [0]
         xcs, mus, ycs, nuJs, nurefs, als, geo = [], [], [], [], [], [], []
-        for J, basic in enumerate(parts):
+        for J in sel:
+            basic = parts[J]
             xpix = np.concatenate([self.cells[i] for i in basic])
             ysup, nuJ = sparse_sum([self.nu_i[i] for i in basic])
             keep = nuJ > 0
@@ -322,9 +328,9 @@ class DomDec:
             np.concatenate(ycs), np.concatenate(nuJs), np.concatenate(nurefs), eps, tol, max_iter,
             fixed_iters, rule, np.concatenate(als), nthreads)
         solves = []
-        for J, (basic, xpix, xcount, ysup, nuJ) in enumerate(geo):
-            aJ = a[xoffs[J]:xoffs[J + 1]].copy()
-            bJ = b[yoffs[J]:yoffs[J + 1]].copy()
+        for n, (J, (basic, xpix, xcount, ysup, nuJ)) in enumerate(zip(sel, geo)):
+            aJ = a[xoffs[n]:xoffs[n + 1]].copy()
+            bJ = b[yoffs[n]:yoffs[n + 1]].copy()
             self.alpha[which][J] = aJ
             solves.append(CellSolve(basic, xpix, xcount, ysup, nuJ, aJ, bJ))
             plan = cell_plan(self.coords[xpix], self.mu[xpix], aJ, self.coords[ysup], self.nu[ysup],
@@ -423,6 +429,69 @@ class DomDec:
             E += float((c * plan).sum())
             E += eps * float((plan[pos] * np.log(plan[pos] / ref[pos]) - plan[pos]).sum())
         return E + eps * float(self.mu.sum() * self.nu.sum())
+
+    def stitched_dual(self, eps: float):
+        """A global dual point from the composite-cell potentials and its value D.
+
+        The cell potentials alpha_J are each defined up to a constant (Sec. 2.3, the gauge of
+        the cell problem).  Offsets s_J are fixed by a breadth-first walk over the graph whose
+        nodes are the A and B composite cells and whose edges are their overlaps (one basic
+        cell each): starting from A cell 0 with s = 0, an edge through basic cell i sets the
+        new cell's offset so that the mu-weighted mean of alpha_A - s_A and alpha_B - s_B on
+        X_i agree.  Cells are expanded in FIFO order and neighbours through members taken in
+        ascending basic-cell order.  Then alpha^dagger = alpha_J - s_J on the A cells, and
+        beta^dagger is its exact Y-update against mu (x) nu,
+            beta(y) = -eps log sum_x mu(x) exp((alpha(x) - c(x, y)) / eps),
+        so that D(alpha, beta) = <alpha, mu> + <beta, nu> (dual_value's last term vanishes).
+        Returns (D, alpha^dagger, beta^dagger); beta is nan off supp nu."""
+        if any(a is None for a in self.alpha["A"]) or any(a is None for a in self.alpha["B"]):
+            raise ValueError("stitched_dual needs both partitions visited")
+        N2 = self.N * self.N
+        aX = {}
+        own = {}
+        for which in "AB":
+            arr = np.zeros(N2)
+            o = np.full(len(self.cells), -1)
+            for J, basic in enumerate(self.parts[which]):
+                xpix = np.concatenate([self.cells[i] for i in basic])
+                arr[xpix] = self.alpha[which][J]
+                o[basic] = J
+            aX[which], own[which] = arr, o
+        d = np.array([float((self.mu[p] * (aX["A"][p] - aX["B"][p])).sum()) / mi
+                      for p, mi in zip(self.cells, self.m)])
+        sA = np.full(len(self.parts["A"]), np.nan)
+        sB = np.full(len(self.parts["B"]), np.nan)
+        sA[0] = 0.0
+        queue = [("A", 0)]
+        head = 0
+        while head < len(queue):
+            which, J = queue[head]
+            head += 1
+            for i in sorted(self.parts[which][J]):
+                if which == "A":
+                    K = own["B"][i]
+                    if np.isnan(sB[K]):
+                        sB[K] = sA[J] - d[i]
+                        queue.append(("B", K))
+                else:
+                    K = own["A"][i]
+                    if np.isnan(sA[K]):
+                        sA[K] = sB[J] + d[i]
+                        queue.append(("A", K))
+        alpha = aX["A"].copy()
+        for J, basic in enumerate(self.parts["A"]):
+            for i in basic:
+                alpha[self.cells[i]] -= sA[J]
+        sup = self.nu > 0
+        beta = np.full(N2, np.nan)
+        C = self.coords
+        for y in np.nonzero(sup)[0]:
+            z = (alpha - ((C - C[y]) ** 2).sum(axis=1)) / eps
+            pos = self.mu > 0
+            zm = z[pos].max()
+            beta[y] = -eps * (zm + np.log((self.mu[pos] * np.exp(z[pos] - zm)).sum()))
+        D = float((alpha * self.mu).sum() + (beta[sup] * self.nu[sup]).sum())
+        return D, alpha, beta
 
     def transport_cost(self, which: Optional[str] = None) -> float:
         """<c, pi> of the composite plans."""

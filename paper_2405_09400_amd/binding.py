@@ -77,7 +77,8 @@ class PlanView(ctypes.Structure):
 class Eval(ctypes.Structure):
     _fields_ = [("y_marginal_l1", ctypes.c_double), ("x_marginal_l1", ctypes.c_double),
                 ("primal", ctypes.c_double), ("transport", ctypes.c_double),
-                ("basic_mass_err", ctypes.c_double), ("total_mass", ctypes.c_double)]
+                ("basic_mass_err", ctypes.c_double), ("total_mass", ctypes.c_double),
+                ("dual", ctypes.c_double), ("pd_gap", ctypes.c_double)]
 
 
 def _struct_dict(s) -> dict:

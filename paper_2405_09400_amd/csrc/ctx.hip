@@ -94,6 +94,7 @@ void dd_ctx_release(dd_ctx* c) {
     F(c->d_b);
     F(c->d_nx);
     F(c->d_ng);
+    dual_release(c->dual);
     F(c->snap.box);
     F(c->snap.base);
     F(c->snap.data);
@@ -543,11 +544,35 @@ extern "C" dd_status domdec_evaluate(dd_ctx* c, dd_eval* out) {
     r.y_marginal_l1 = h[0];
     r.total_mass = h[1];
     r.basic_mass_err = h[2];
+    r.dual = r.pd_gap = NAN;
     if (c->last_part >= 0) {
         const double eps = c->last_eps;
         r.primal = eps * h[4] + eps * 1.0;  // + eps * (sum mu)(sum nu), the KL reference mass
         r.transport = h[5] * c->h * c->h;
         r.x_marginal_l1 = h[6];
+        if (c->visited[0] && c->visited[1]) {
+            DualArgs a;
+            a.N = c->N;
+            a.s = c->s;
+            a.xside = c->AS;
+            for (int q = 0; q < 2; ++q) {
+                a.ncell[q] = c->part[q].ncell;
+                a.members[q] = c->pmembers[q].data();
+                a.xorig[q] = c->part[q].xorig;
+                a.a[q] = c->d_a[q];
+                a.gst[q] = c->d_gst[q];
+                a.kappa[q] = c->kappa_a[q];
+            }
+            a.kappa_eval = eps / (c->h * c->h);
+            a.eps = eps;
+            a.mu = c->d_mu;
+            a.nu = c->d_nu;
+            double D = NAN;
+            const Status ds = stitched_dual(a, c->dual, c->st, &D);
+            if (ds.code) return fail(c, ds);
+            r.dual = D;
+            r.pd_gap = r.primal - D;
+        }
     } else {
         r.primal = r.transport = r.x_marginal_l1 = NAN;
     }

@@ -5,6 +5,7 @@
 #include <vector>
 
 #include "cells.hpp"
+#include "dual.hpp"
 #include "sinkhorn.hpp"
 
 struct FlowState;
@@ -63,6 +64,7 @@ struct dd_ctx {
     size_t nx_cap = 0;
     float* d_ng = nullptr;  // [cells][32][32] predicted Y potentials
     size_t ng_cap = 0;
+    dd::DualWork dual;
     // one saved copy of the mutable state (domdec_save / domdec_restore)
     struct Snap {
         bool valid = false;

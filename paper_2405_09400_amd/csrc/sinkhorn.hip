@@ -38,6 +38,8 @@
 
 #include <algorithm>
 #include <cmath>
+#include <map>
+#include <mutex>
 #include <type_traits>
 #include <vector>
 
@@ -91,43 +93,6 @@ struct WaveTeam {
     __device__ double sum(double v, P) const { return wave_sum(v); }
 };
 
-// LSE_{k<K} ( in[k*stride] - (k - q + e)^2 * invk ), max-shifted, two passes.  P is a
-// pointer into LDS or global memory.
-template <typename T, typename P>
-__device__ __forceinline__ T lse_line(P in, int stride, int K, int q, int e, T invk) {
-    T d = T(e - q);
-    T m = in[0] - d * d * invk;
-    for (int k = 1; k < K; ++k) {
-        d = T(k - q + e);
-        const T v = in[k * stride] - d * d * invk;
-        m = v > m ? v : m;
-    }
-    T s = T(0);
-    for (int k = 0; k < K; ++k) {
-        d = T(k - q + e);
-        s += fexp(in[k * stride] - d * d * invk - m);
-    }
-    return m + flog(s);
-}
-
-// Same with an additive per-k shift sh[k] (the float offsets of the input lines).
-template <typename T, typename P, typename PS>
-__device__ __forceinline__ T lse_line_sh(P in, int stride, int K, int q, int e, T invk, PS sh) {
-    T d = T(e - q);
-    T m = in[0] + sh[0] - d * d * invk;
-    for (int k = 1; k < K; ++k) {
-        d = T(k - q + e);
-        const T v = in[k * stride] + sh[k] - d * d * invk;
-        m = v > m ? v : m;
-    }
-    T s = T(0);
-    for (int k = 0; k < K; ++k) {
-        d = T(k - q + e);
-        s += fexp(in[k * stride] + sh[k] - d * d * invk - m);
-    }
-    return m + flog(s);
-}
-
 __device__ __forceinline__ double wave_max_d(double v) {
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
@@ -143,34 +108,68 @@ using glb_p = __attribute__((address_space(1))) T*;
 
 // A cell's working set.  The X arrays always live in LDS; the Y-box arrays live in the LDS
 // tile (G = false) or, for a box larger than the tile, in the cell's global scratch (G = true).
+//
+// Each 1D log-sum-exp pass, LSE_k [in(k) - (k - q + e)^2 / kappa] for the outputs q of one
+// line, is evaluated as a stabilised kernel product: with in(k) shifted by the line maximum,
+// u(k) = exp(in(k) - max), and the cost split at the input c(q) nearest to q - e,
+//   (k - q + e)^2 = (c(q) - q + e)^2 + [(k - q + e)^2 - (c(q) - q + e)^2],
+// the pass is  max - s(q) + log sum_k u(k) Kt[k][q],  s(q) = (c(q) - q + e)^2 / kappa,
+// Kt[k][q] = exp(-[(k - q + e)^2 - (c(q) - q + e)^2] / kappa) in (0, 1], Kt = 1 at k = c(q).
+// Kt and s depend only on the box shape and kappa, so a cell builds its four tables once,
+// and the exponentials per iteration drop from one per term to one per input and output.
+// A sum that underflows (every input near q is negligible against the line maximum) is
+// recomputed for that output by the exact two-pass log-sum-exp.
 template <typename T, bool G>
 struct Lds {
     using YT = std::conditional_t<G, glb_p<T>, lds_p<T>>;
     using YD = std::conditional_t<G, glb_p<double>, lds_p<double>>;
-    lds_p<double> f;    // [N2]          X potential f
-    lds_p<double> lm;   // [N2]          log mu
-    lds_p<double> s;    // [N2]          LSE_j (g + log nu_J - C)
-    lds_p<double> ry;   // [AS]          row maxima of f + log mu
-    lds_p<double> red;  // [16]          reductions; [8] = R, [9] = Q
-    lds_p<T> wq;        // [N2]          f + log mu - ry(row)
-    lds_p<T> rhoy;      // [AS]          ry - R
-    YD ln;              // [W1][ys]      log nu_J
-    YD qx;              // [W1]          row maxima of g + log nu_J (full offsets)
-    YT gq;              // [W1][ys]      g + R (g = gq - R)
-    YT zq;              // [W1][ys]      g + log nu_J - qx(row)
-    YT t1;              // [AS][W2p]     Y-half intermediate, relative to ry
-    YT u;               // [W1][ASp]     X-half intermediate, relative to qx
-    YT kq;              // [W1]          qx - Q
-    int ys, W2p, ASp;
+    // X arrays
+    lds_p<double> f;    // [N2]        X potential f
+    lds_p<double> lm;   // [N2]        log mu
+    lds_p<double> s;    // [N2]        LSE_j (g + log nu_J - C)
+    lds_p<double> ry;   // [AS]        row maxima of f + log mu
+    lds_p<double> Mx;   // [AS]        column maxima of the X-half intermediate
+    lds_p<double> red;  // [16]        reductions; [8] = R (max of ry)
+    lds_p<T> wq;        // [N2]        f + log mu - ry(row)
+    lds_p<T> u1;        // [N2]        exp(wq)
+    lds_p<T> sX1;       // [AS]        nearest-point shifts of the X-half passes
+    lds_p<T> sX2;       // [AS]
+    // Y-box arrays
+    YD ln;              // [W1][ys]    log nu_J
+    YD qx;              // [W1]        row maxima of g + log nu_J
+    YD My;              // [W2]        column maxima of the Y-half intermediate
+    YT gq;              // [W1][ys]    g + R
+    YT u3;              // [W1][ys]    exp(g + log nu_J - qx(row))
+    YT KY1;             // [AS][W2p]   kernel table, Y-half pass over i2
+    YT t1;              // [AS][W2p]   Y-half intermediate, relative to ry
+    YT u2;              // [AS][W2p]   exp(t1 + ry - My)
+    YT KY2;             // [AS][W1p]   kernel table, Y-half pass over i1
+    YT KX1;             // [W2][ASp]   kernel table, X-half pass over j2
+    YT r;               // [W1][ASp]   X-half intermediate, relative to qx
+    YT u4;              // [W1][ASp]   exp(r + qx - Mx)
+    YT KX2;             // [W1][ASp]   kernel table, X-half pass over j1
+    YT sY1;             // [W2]
+    YT sY2;             // [W1]
+    int ys, W2p, W1p, ASp;
 };
 
-// LDS bytes: the X arrays of the cell plus the Y-box arrays for the LDS tile (lw1 x lw2);
+// Bytes of the X arrays and of the Y-box arrays of a (w1 x w2) box (strides included).
+__host__ __device__ inline size_t x_bytes(int AS, size_t elem) {
+    const size_t N2 = (size_t)AS * AS;
+    return 8 * (3 * N2 + 2 * (size_t)AS + 16) + elem * (2 * N2 + 2 * (size_t)AS);
+}
+__host__ __device__ inline size_t box_bytes(int AS, int w1, int w2, size_t elem) {
+    const size_t ys = (size_t)w2 + 1, W2p = ys, W1p = (size_t)w1 + 1, ASp = (size_t)AS + 1;
+    const size_t nd = (size_t)w1 * ys + w1 + w2;
+    const size_t nt = 2 * (size_t)w1 * ys + 3 * (size_t)AS * W2p + (size_t)AS * W1p +
+                      (size_t)w2 * ASp + 3 * (size_t)w1 * ASp + w2 + w1;
+    return 8 * nd + elem * nt + 64;
+}
+
+// LDS bytes of one cell slice: the X arrays plus the Y-box arrays for the tile (lw1 x lw2);
 // cells beyond the tile keep their Y-box arrays in global scratch (read through L1/L2).
 __host__ __device__ inline size_t lds_layout_bytes(int AS, int lw1, int lw2, size_t elem) {
-    const size_t N2 = (size_t)AS * AS, LY = (size_t)lw1 * (lw2 + 1);
-    const size_t nd = 16 + 3 * N2 + AS + LY + lw1;
-    const size_t nt = N2 + AS + 2 * LY + (size_t)AS * (lw2 + 1) + (size_t)lw1 * (AS + 1) + lw1;
-    return (8 * nd + elem * nt + 16 + 15) & ~size_t(15);
+    return (x_bytes(AS, elem) + box_bytes(AS, lw1, lw2, elem) + 15) & ~size_t(15);
 }
 
 // Workgroup LDS: one big-cell layout, or kWaves small-cell layouts side by side.
@@ -181,11 +180,48 @@ __host__ __device__ inline size_t wg_lds_bytes(int AS, int lw1, int lw2, int lw1
     return small > big ? small : big;
 }
 
-// Global scratch (in doubles) of a cell whose box exceeds the tile: qx, then gq, zq, t1, u, kq.
+// Global scratch (in doubles) of a cell whose box exceeds the tile.
 __host__ __device__ inline int64_t cell_scratch_doubles(int AS, int W1, int W2, size_t elem) {
-    const int64_t nt = 2 * (int64_t)W1 * W2 + (int64_t)AS * (W2 + 1) + (int64_t)W1 * (AS + 1) + W1;
-    const int64_t n = W1 + (nt * (int64_t)elem + 7) / 8;
-    return (n + 1) & ~int64_t(1);
+    return (int64_t)((box_bytes(AS, W1, W2, elem) + 15) / 16) * 2;
+}
+
+// Bind the Y-box arrays of a (W1 x W2) box with strides for (w1s x w2s) starting at `base`.
+template <typename T, typename PD, typename PT>
+__device__ __forceinline__ void bind_box(PD& ln, PD& qx, PD& My, PT& gq, PT& u3, PT& KY1, PT& t1,
+                                         PT& u2, PT& KY2, PT& KX1, PT& r, PT& u4, PT& KX2, PT& sY1,
+                                         PT& sY2, PD base, int AS, int w1s, int w2s) {
+    const int ys = w2s + 1, W2p = ys, W1p = w1s + 1, ASp = AS + 1;
+    PD d = base;
+    ln = d;
+    d += (size_t)w1s * ys;
+    qx = d;
+    d += w1s;
+    My = d;
+    d += w2s;
+    PT t = (PT)d;
+    gq = t;
+    t += (size_t)w1s * ys;
+    u3 = t;
+    t += (size_t)w1s * ys;
+    KY1 = t;
+    t += (size_t)AS * W2p;
+    t1 = t;
+    t += (size_t)AS * W2p;
+    u2 = t;
+    t += (size_t)AS * W2p;
+    KY2 = t;
+    t += (size_t)AS * W1p;
+    KX1 = t;
+    t += (size_t)w2s * ASp;
+    r = t;
+    t += (size_t)w1s * ASp;
+    u4 = t;
+    t += (size_t)w1s * ASp;
+    KX2 = t;
+    t += (size_t)w1s * ASp;
+    sY1 = t;
+    t += w2s;
+    sY2 = t;
 }
 
 // Carve the X arrays (and, for G = false, the tile) out of an LDS slice; for G = true bind
@@ -196,8 +232,6 @@ __device__ __forceinline__ Lds<T, G> carve(lds_p<char> base, const SkBatch& p, i
                                            double* big_scratch) {
     Lds<T, G> L;
     const int AS = p.xside, N2 = AS * AS;
-    const int lys = lw2 + 1;
-    const size_t LY = (size_t)lw1 * lys;
     lds_p<double> d = (lds_p<double>)base;
     L.red = d;
     d += 16;
@@ -209,51 +243,104 @@ __device__ __forceinline__ Lds<T, G> carve(lds_p<char> base, const SkBatch& p, i
     d += N2;
     L.ry = d;
     d += AS;
-    lds_p<double> ln_l = d;
-    d += LY;
-    lds_p<double> qx_l = d;
-    d += lw1;
+    L.Mx = d;
+    d += AS;
     lds_p<T> t = (lds_p<T>)d;
     L.wq = t;
     t += N2;
-    L.rhoy = t;
+    L.u1 = t;
+    t += N2;
+    L.sX1 = t;
+    t += AS;
+    L.sX2 = t;
     t += AS;
     L.ASp = AS + 1;
     if constexpr (!G) {
-        L.ln = ln_l;
-        L.qx = qx_l;
-        L.gq = t;
-        t += LY;
-        L.zq = t;
-        t += LY;
-        L.t1 = t;
-        t += (size_t)AS * lys;
-        L.u = t;
-        t += (size_t)lw1 * (AS + 1);
-        L.kq = t;
-        L.ys = lys;
-        L.W2p = lys;
+        lds_p<double> bb = (lds_p<double>)(base + ((x_bytes(AS, sizeof(T)) + 15) & ~size_t(15)));
+        bind_box<T>(L.ln, L.qx, L.My, L.gq, L.u3, L.KY1, L.t1, L.u2, L.KY2, L.KX1, L.r, L.u4,
+                    L.KX2, L.sY1, L.sY2, bb, AS, lw1, lw2);
+        L.ys = lw2 + 1;
+        L.W2p = lw2 + 1;
+        L.W1p = lw1 + 1;
     } else {
-        glb_p<double> sc = (glb_p<double>)(big_scratch + p.scr_off[c]);
-        L.ln = (glb_p<double>)(const_cast<double*>(p.lognu) + ybase);
-        L.qx = sc;
-        glb_p<T> g = (glb_p<T>)(sc + W1);
-        L.gq = g;
-        g += (int64_t)W1 * W2;
-        L.zq = g;
-        g += (int64_t)W1 * W2;
-        L.t1 = g;
-        g += (int64_t)AS * (W2 + 1);
-        L.u = g;
-        g += (int64_t)W1 * (AS + 1);
-        L.kq = g;
-        L.ys = W2;
+        (void)ybase;
+        glb_p<double> bb = (glb_p<double>)(big_scratch + p.scr_off[c]);
+        bind_box<T>(L.ln, L.qx, L.My, L.gq, L.u3, L.KY1, L.t1, L.u2, L.KY2, L.KX1, L.r, L.u4,
+                    L.KX2, L.sY1, L.sY2, bb, AS, W1, W2);
+        L.ys = W2 + 1;
         L.W2p = W2 + 1;
+        L.W1p = W1 + 1;
     }
     return L;
 }
 
-// Y-update g(j) = -LSE_i [f(i) + log mu(i) - C(i,j)], as two 1D passes over shifted values.
+// Kernel table of one pass: inputs k in [0, K), outputs q in [0, Q), d = k - q + e;
+// Kt[k * ks + q * qs] and the shifts sh[q] (see above).
+template <typename Tm, typename T, typename P, typename PS>
+__device__ __forceinline__ void build_table(const Tm& tm, P Kt, PS sh, int K, int Q, int e,
+                                            int ks, int qs, T invk) {
+    for (int o = tm.tid(); o < K * Q; o += tm.size()) {
+        const int k = o / Q, q = o - k * Q;
+        const int c = min(max(q - e, 0), K - 1);
+        const int d = k - q + e, dn = c - q + e;
+        Kt[k * ks + q * qs] = fexp(-T(d * d - dn * dn) * invk);
+        if (k == 0) sh[q] = T(dn * dn) * invk;
+    }
+}
+
+// Exact LSE_k [in(k) - (k - q + e)^2 / kappa] of one output, in(k) = base[k * stride] + add[k]
+// (the fallback of an underflowed kernel-product sum).
+template <typename T, typename F>
+__device__ __forceinline__ T lse_exact(F in, int K, int q, int e, T invk) {
+    T m = T(-3.0e38);
+    for (int k = 0; k < K; ++k) {
+        const T d = T(k - q + e);
+        m = fmax(m, in(k) - d * d * invk);
+    }
+    T sum = T(0);
+    for (int k = 0; k < K; ++k) {
+        const T d = T(k - q + e);
+        sum += fexp(in(k) - d * d * invk - m);
+    }
+    return m + flog(sum);
+}
+
+// smallest kernel-product sum trusted without the exact fallback
+template <typename T>
+__device__ __forceinline__ T sum_floor();
+template <>
+__device__ __forceinline__ float sum_floor<float>() { return 1e-30f; }
+template <>
+__device__ __forceinline__ double sum_floor<double>() { return 1e-290; }
+
+// Load one cell: f and log mu into LDS, log nu_J into the tile (G = false), kernel tables.
+template <typename Tm, typename T, bool G>
+__device__ __forceinline__ void load_cell(const Tm& tm, const SkBatch& p, const Lds<T, G>& L,
+                                          const double* f_src, int c, int W1, int W2,
+                                          int64_t base) {
+    const int AS = p.xside, N2 = AS * AS, tid = tm.tid(), nt = tm.size();
+    const int E1 = p.shift[2 * c], E2 = p.shift[2 * c + 1];
+    const T invk = T(1.0 / p.kappa);
+    // zero-mass points carry the log-domain sentinel in log mu / log nu_J, which removes
+    // them from every sum whatever their potential
+    for (int i = tid; i < N2; i += nt) {
+        L.lm[i] = p.logmu[(int64_t)c * N2 + i];
+        L.f[i] = f_src[(int64_t)c * N2 + i];
+    }
+    for (int o = tid; o < W1 * W2; o += nt) {
+        const int j1 = o / W2, j2 = o - j1 * W2;
+        L.ln[j1 * L.ys + j2] = p.lognu[base + o];
+    }
+    // Y-half: over i2 (d = i2 - j2 + E2), over i1 (d = i1 - j1 + E1);
+    // X-half: over j2 (d = j2 - i2 - E2), over j1 (d = j1 - i1 - E1)
+    build_table(tm, L.KY1, L.sY1, AS, W2, E2, L.W2p, 1, invk);
+    build_table(tm, L.KY2, L.sY2, AS, W1, E1, L.W1p, 1, invk);
+    build_table(tm, L.KX1, L.sX1, W2, AS, -E2, L.ASp, 1, invk);
+    build_table(tm, L.KX2, L.sX2, W1, AS, -E1, L.ASp, 1, invk);
+    tm.sync();
+}
+
+// Y-update g(j) = -LSE_i [f(i) + log mu(i) - C(i,j)]: pass over i2, then over i1.
 // Leaves gq (g = gq - R, R in red[8]).
 template <typename Tm, typename T, bool G>
 __device__ __forceinline__ void y_half(const Tm& tm, const Lds<T, G>& L, int AS, int W1, int W2,
@@ -266,60 +353,127 @@ __device__ __forceinline__ void y_half(const Tm& tm, const Lds<T, G>& L, int AS,
         L.ry[i1] = r;
     }
     tm.sync();
-    for (int i = tid; i < N2; i += nt) L.wq[i] = (T)(L.f[i] + L.lm[i] - L.ry[i / AS]);
+    for (int i = tid; i < N2; i += nt) {
+        const T w = (T)(L.f[i] + L.lm[i] - L.ry[i / AS]);
+        L.wq[i] = w;
+        L.u1[i] = fexp(w);
+    }
     if (tid == 0) {
         double R = L.ry[0];
         for (int i1 = 1; i1 < AS; ++i1) R = fmax(R, L.ry[i1]);
         L.red[8] = R;
-        for (int i1 = 0; i1 < AS; ++i1) L.rhoy[i1] = (T)(L.ry[i1] - R);
+    }
+    tm.sync();
+    // pass over i2: t1(i1, j2) = LSE_i2 [wq(i1, i2) - (i2 - j2 + E2)^2 / kappa]
+    for (int o = tid; o < AS * W2; o += nt) {
+        const int i1 = o / W2, j2 = o - i1 * W2;
+        T sum = T(0);
+        for (int k = 0; k < AS; ++k) sum += L.u1[i1 * AS + k] * L.KY1[k * L.W2p + j2];
+        T v;
+        if (sum >= sum_floor<T>())
+            v = flog(sum) - L.sY1[j2];
+        else
+            v = lse_exact<T>([&](int k) { return L.wq[i1 * AS + k]; }, AS, j2, E2, invk);
+        L.t1[i1 * L.W2p + j2] = v;
+    }
+    tm.sync();
+    // column maxima over i1 of t1 + ry, and the scaled inputs of the second pass
+    for (int j2 = tid; j2 < W2; j2 += nt) {
+        double m = (double)L.t1[j2] + L.ry[0];
+        for (int i1 = 1; i1 < AS; ++i1) m = fmax(m, (double)L.t1[i1 * L.W2p + j2] + L.ry[i1]);
+        L.My[j2] = m;
     }
     tm.sync();
     for (int o = tid; o < AS * W2; o += nt) {
         const int i1 = o / W2, j2 = o - i1 * W2;
-        L.t1[i1 * L.W2p + j2] = lse_line(L.wq + i1 * AS, 1, AS, j2, E2, invk);
+        L.u2[i1 * L.W2p + j2] = fexp((T)((double)L.t1[i1 * L.W2p + j2] + L.ry[i1] - L.My[j2]));
     }
     tm.sync();
+    // pass over i1: g(j1, j2) = -LSE_i1 [t1(i1, j2) + ry(i1) - (i1 - j1 + E1)^2 / kappa]
+    const double R = L.red[8];
     for (int o = tid; o < W1 * W2; o += nt) {
         const int j1 = o / W2, j2 = o - j1 * W2;
-        L.gq[j1 * L.ys + j2] = -lse_line_sh(L.t1 + j2, L.W2p, AS, j1, E1, invk, L.rhoy);
+        T sum = T(0);
+        for (int k = 0; k < AS; ++k) sum += L.u2[k * L.W2p + j2] * L.KY2[k * L.W1p + j1];
+        const double Mj = L.My[j2];
+        T v;
+        if (sum >= sum_floor<T>()) {
+            v = flog(sum) - L.sY2[j1];
+        } else {
+            v = lse_exact<T>(
+                [&](int k) { return L.t1[k * L.W2p + j2] + (T)(L.ry[k] - Mj); }, AS, j1, E1,
+                invk);
+        }
+        L.gq[j1 * L.ys + j2] = -(T)(Mj - R) - v;
     }
     tm.sync();
 }
 
-// s(i) = LSE_j [g(j) + log nu_J(j) - C(i,j)] (float64 result), as two 1D passes over shifted
-// values (cost (i - j + E)^2 = (j - i - E)^2).
+// s(i) = LSE_j [g(j) + log nu_J(j) - C(i,j)] (float64 result): pass over j2, then over j1
+// (cost (i - j + E)^2 = (j - i - E)^2).
 template <typename Tm, typename T, bool G>
 __device__ __forceinline__ void x_half(const Tm& tm, const Lds<T, G>& L, int AS, int W1, int W2,
                                        int E1, int E2, T invk) {
     const int tid = tm.tid(), nt = tm.size();
     const int lane = threadIdx.x & 63, wid = tm.wid(), nw = tm.nw();
-    const double goff = -L.red[8];
+    const double R = L.red[8];
+    // row maxima of g + log nu_J (one wave per row) and the scaled inputs
     for (int j1 = wid; j1 < W1; j1 += nw) {
         double m = -1e300;
         for (int j2 = lane; j2 < W2; j2 += 64)
             m = fmax(m, (double)L.gq[j1 * L.ys + j2] + L.ln[j1 * L.ys + j2]);
         m = wave_max_d(m);
         for (int j2 = lane; j2 < W2; j2 += 64)
-            L.zq[j1 * L.ys + j2] = (T)((double)L.gq[j1 * L.ys + j2] + L.ln[j1 * L.ys + j2] - m);
-        if (lane == 0) L.qx[j1] = m + goff;
+            L.u3[j1 * L.ys + j2] = fexp((T)((double)L.gq[j1 * L.ys + j2] + L.ln[j1 * L.ys + j2] - m));
+        if (lane == 0) L.qx[j1] = m - R;
     }
     tm.sync();
-    if (wid == 0) {
-        double Q = -1e300;
-        for (int j1 = lane; j1 < W1; j1 += 64) Q = fmax(Q, L.qx[j1]);
-        Q = wave_max_d(Q);
-        for (int j1 = lane; j1 < W1; j1 += 64) L.kq[j1] = (T)(L.qx[j1] - Q);
-        if (lane == 0) L.red[9] = Q;
-    }
+    // pass over j2: r(j1, i2) = LSE_j2 [g + log nu_J - qx(j1) - (j2 - i2 - E2)^2 / kappa]
     for (int o = tid; o < W1 * AS; o += nt) {
         const int j1 = o / AS, i2 = o - j1 * AS;
-        L.u[j1 * L.ASp + i2] = lse_line(L.zq + j1 * L.ys, 1, W2, i2, -E2, invk);
+        T sum = T(0);
+        for (int k = 0; k < W2; ++k) sum += L.u3[j1 * L.ys + k] * L.KX1[k * L.ASp + i2];
+        T v;
+        if (sum >= sum_floor<T>()) {
+            v = flog(sum) - L.sX1[i2];
+        } else {
+            const double q = L.qx[j1] + R;
+            v = lse_exact<T>(
+                [&](int k) {
+                    return (T)((double)L.gq[j1 * L.ys + k] + L.ln[j1 * L.ys + k] - q);
+                },
+                W2, i2, -E2, invk);
+        }
+        L.r[j1 * L.ASp + i2] = v;
     }
     tm.sync();
-    const double Q = L.red[9];
+    // column maxima over j1 of r + qx, and the scaled inputs of the second pass
+    for (int i2 = tid; i2 < AS; i2 += nt) {
+        double m = (double)L.r[i2] + L.qx[0];
+        for (int j1 = 1; j1 < W1; ++j1) m = fmax(m, (double)L.r[j1 * L.ASp + i2] + L.qx[j1]);
+        L.Mx[i2] = m;
+    }
+    tm.sync();
+    for (int o = tid; o < W1 * AS; o += nt) {
+        const int j1 = o / AS, i2 = o - j1 * AS;
+        L.u4[j1 * L.ASp + i2] = fexp((T)((double)L.r[j1 * L.ASp + i2] + L.qx[j1] - L.Mx[i2]));
+    }
+    tm.sync();
+    // pass over j1: s(i1, i2) = LSE_j1 [r(j1, i2) + qx(j1) - (j1 - i1 - E1)^2 / kappa]
     for (int o = tid; o < AS * AS; o += nt) {
         const int i1 = o / AS, i2 = o - i1 * AS;
-        L.s[o] = Q + (double)lse_line_sh(L.u + i2, L.ASp, W1, i1, -E1, invk, L.kq);
+        T sum = T(0);
+        for (int k = 0; k < W1; ++k) sum += L.u4[k * L.ASp + i2] * L.KX2[k * L.ASp + i1];
+        const double Mi = L.Mx[i2];
+        T v;
+        if (sum >= sum_floor<T>()) {
+            v = flog(sum) - L.sX2[i1];
+        } else {
+            v = lse_exact<T>(
+                [&](int k) { return L.r[k * L.ASp + i2] + (T)(L.qx[k] - Mi); }, W1, i1, -E1,
+                invk);
+        }
+        L.s[o] = Mi + (double)v;
     }
     tm.sync();
 }
@@ -339,26 +493,6 @@ __device__ __forceinline__ void err_mass(const Tm& tm, const Lds<T, G>& L, int A
     }
     err = tm.sum(e, L.red);
     mass = tm.sum(m, L.red);
-}
-
-// Load one cell: f and log mu into LDS, log nu_J into the tile (G = false).
-template <typename Tm, typename T, bool G>
-__device__ __forceinline__ void load_cell(const Tm& tm, const SkBatch& p, const Lds<T, G>& L,
-                                          const double* f_src, int c, int W1, int W2,
-                                          int64_t base) {
-    const int N2 = p.xside * p.xside, tid = tm.tid(), nt = tm.size();
-    // zero-mass points carry the log-domain sentinel in log mu / log nu_J, which removes
-    // them from every sum whatever their potential
-    for (int i = tid; i < N2; i += nt) {
-        L.lm[i] = p.logmu[(int64_t)c * N2 + i];
-        L.f[i] = f_src[(int64_t)c * N2 + i];
-    }
-    if constexpr (!G)
-        for (int o = tid; o < W1 * W2; o += nt) {
-            const int j1 = o / W2, j2 = o - j1 * W2;
-            L.ln[j1 * L.ys + j2] = p.lognu[base + o];
-        }
-    tm.sync();
 }
 
 template <typename Tm, typename T, bool G>
@@ -487,8 +621,8 @@ __global__ void __launch_bounds__(kThreads)
         if (lane == 0) q = atomicAdd(&ctrl[9], 1);
         q = __builtin_amdgcn_readfirstlane(__shfl(q, 0, 64));
         if (q >= nsmall) break;
-        with_cell<T, false>(tm, p, slice, p.lw1, p.lw2, p.order[p.nbig + q], big_scratch, ctrl,
-                            body);
+        with_cell<T, true>(tm, p, slice, p.lw1, p.lw2, p.order[p.nbig + q], big_scratch, ctrl,
+                           body);
     }
 }
 
@@ -567,8 +701,8 @@ __device__ __forceinline__ void for_items(const SkBatch& p, lds_p<char> base, do
             const int k = p.nbig + (q - p.nbig) * kWaves + w;
             if (k < p.ncells) {
                 const WaveTeam tm;
-                with_cell<T, false>(tm, p, slice, p.lw1, p.lw2, p.order[k], big_scratch, ctrl,
-                                    make(tm));
+                with_cell<T, true>(tm, p, slice, p.lw1, p.lw2, p.order[k], big_scratch, ctrl,
+                                   make(tm));
             }
         }
         __syncthreads();
@@ -577,10 +711,14 @@ __device__ __forceinline__ void for_items(const SkBatch& p, lds_p<char> base, do
 
 template <typename T>
 __global__ void __launch_bounds__(kThreads)
-    sk_iter_kernel(SkBatch p, const double* f_in, double* f_out, int it, int limit, double tol,
-                   int* ctrl, double* cell_err, double* cell_mass, double* dtot,
-                   double* big_scratch) {
+    sk_iter_kernel(SkBatch p, double* fa, double* fb, int limit, double tol, int* ctrl,
+                   double* cell_err, double* cell_mass, double* dtot, double* big_scratch) {
     if (__atomic_load_n(&ctrl[2], __ATOMIC_RELAXED) != 0) return;
+    // the iteration number lives on the device (every launch is identical, so a chunk of
+    // launches can be captured once and replayed); odd iterations read fa and write fb
+    const int it = __atomic_load_n(&ctrl[10], __ATOMIC_RELAXED) + 1;
+    const double* f_in = (it & 1) ? fa : fb;
+    double* f_out = (it & 1) ? fb : fa;
     extern __shared__ __align__(16) char smem[];
     __shared__ int s_last;
     __shared__ double s_red[16];
@@ -607,6 +745,7 @@ __global__ void __launch_bounds__(kThreads)
         const bool conv = e <= tol * m;
         if (conv) ctrl[4] = 1;
         if (conv || it >= limit || !(e == e)) __atomic_store_n(&ctrl[2], it, __ATOMIC_RELAXED);
+        ctrl[10] = it;
         ctrl[1] = 0;
     }
 }
@@ -699,6 +838,8 @@ Status sk_work_reserve(SkWork& w, int ncells, size_t a_n) {
         DD_HIP(hipEventCreate(&w.ev0), st);
         DD_HIP(hipEventCreate(&w.ev1), st);
         DD_HIP(hipEventCreate(&w.ev2), st);
+        DD_HIP(hipEventCreateWithFlags(&w.evj, hipEventDisableTiming), st);
+        DD_HIP(hipStreamCreateWithFlags(&w.stream, hipStreamNonBlocking), st);
     }
     if (ncells > w.cap) {
         if (w.cell_err) (void)hipFree(w.cell_err);
@@ -739,6 +880,11 @@ void sk_work_release(SkWork& w) {
     if (w.ev0) (void)hipEventDestroy(w.ev0);
     if (w.ev1) (void)hipEventDestroy(w.ev1);
     if (w.ev2) (void)hipEventDestroy(w.ev2);
+    if (w.evj) (void)hipEventDestroy(w.evj);
+    if (w.stream) {
+        (void)hipStreamSynchronize(w.stream);
+        (void)hipStreamDestroy(w.stream);
+    }
     w = SkWork{};
 }
 
@@ -781,7 +927,7 @@ Status run_solver(const SkBatch& p, const dd_sinkhorn_opts& o, hipStream_t st, S
     double* big = reinterpret_cast<double*>(w.big);
     const size_t lds = wg_lds_bytes(p.xside, p.lw1, p.lw2, p.lw1b, p.lw2b, sizeof(T));
     const bool fixed = o.fixed_iters > 0;
-    zero_ints<<<1, 64, 0, st>>>(w.ctrl, 10);
+    zero_ints<<<1, 64, 0, st>>>(w.ctrl, 11);
     if (fixed || o.stop_rule == DD_STOP_CELL) {
         auto kern = sk_cell_kernel<T>;
         if (set_lds_attr(kern, lds, S).code) return S;
@@ -802,16 +948,36 @@ Status run_solver(const SkBatch& p, const dd_sinkhorn_opts& o, hipStream_t st, S
     double* bufs[2] = {p.a, w.a_alt};
     const size_t a_bytes = (size_t)p.ncells * p.xside * p.xside * sizeof(double);
     const int chunk = o.check_every > 0 ? o.check_every : 8;
-    int done = 0, it = 1;
-    while (it <= o.max_iter && !done) {
-        const int end = std::min(o.max_iter, it + chunk - 1);
-        for (; it <= end; ++it)
-            kern<<<grid, kThreads, lds, st>>>(p, bufs[(it - 1) & 1], bufs[it & 1], it, o.max_iter,
-                                              o.tol, w.ctrl, errs, w.cell_mass, w.dtot, big);
-        DD_HIP(hipGetLastError(), S);
-        DD_HIP(hipMemcpyAsync(&done, w.ctrl + 2, sizeof(int), hipMemcpyDeviceToHost, st), S);
-        DD_HIP(hipStreamSynchronize(st), S);
+    // a chunk of identical launches is captured into a HIP graph once and replayed; the host
+    // reads the device stop flag between replays
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    DD_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal), S);
+    for (int k = 0; k < chunk; ++k)
+        kern<<<grid, kThreads, lds, st>>>(p, bufs[0], bufs[1], o.max_iter, o.tol, w.ctrl, errs,
+                                          w.cell_mass, w.dtot, big);
+    const hipError_t ce = hipStreamEndCapture(st, &graph);
+    if (ce != hipSuccess || hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) != hipSuccess) {
+        if (graph) (void)hipGraphDestroy(graph);
+        S.code = DD_EDEVICE;
+        S.msg = "sinkhorn: HIP graph capture of the iteration failed";
+        return S;
     }
+    int done = 0;
+    for (int launched = 0; launched < o.max_iter && !done; launched += chunk) {
+        if (hipGraphLaunch(exec, st) != hipSuccess ||
+            hipMemcpyAsync(&done, w.ctrl + 2, sizeof(int), hipMemcpyDeviceToHost, st) !=
+                hipSuccess ||
+            hipStreamSynchronize(st) != hipSuccess) {
+            (void)hipGraphExecDestroy(exec);
+            (void)hipGraphDestroy(graph);
+            S.code = DD_EDEVICE;
+            S.msg = "sinkhorn: graph replay failed";
+            return S;
+        }
+    }
+    (void)hipGraphExecDestroy(exec);
+    (void)hipGraphDestroy(graph);
     if (done < 1) done = o.max_iter;  // unreachable: the kernel sets done at max_iter
     if (((done - 1) & 1) == 1)
         DD_HIP(hipMemcpyAsync(p.a, bufs[1], a_bytes, hipMemcpyDeviceToDevice, st), S);
@@ -850,9 +1016,75 @@ void plan_tile(const std::vector<int32_t>& hd, const std::vector<int32_t>& cells
         }
     }
 }
+// Online tuner of the LDS budget per workgroup (occupancy against LDS-resident boxes):
+// each key (block side, precision, stop rule) tries every candidate once on consecutive
+// solves, then keeps the one with the least Sinkhorn time per LSE term.
+constexpr size_t kBudgets[] = {40 * 1024, 52 * 1024, 78 * 1024, 156 * 1024};
+constexpr int kNumBudgets = sizeof(kBudgets) / sizeof(kBudgets[0]);
+
+struct TuneKey {
+    int as, prec, rule;
+    bool operator<(const TuneKey& o) const {
+        return as != o.as ? as < o.as : prec != o.prec ? prec < o.prec : rule < o.rule;
+    }
+};
+
+class Tuner {
+   public:
+    int pick(const TuneKey& k) {
+        std::lock_guard<std::mutex> g(mu_);
+        Entry& e = tab_[k];
+        if (forced_ >= 0) return forced_;
+        for (int c = 0; c < kNumBudgets; ++c)
+            if (e.n[c] == 0) return c;
+        int best = 0;
+        for (int c = 1; c < kNumBudgets; ++c)
+            if (e.t[c] < e.t[best]) best = c;
+        return best;
+    }
+    void record(const TuneKey& k, int c, double t) {
+        std::lock_guard<std::mutex> g(mu_);
+        Entry& e = tab_[k];
+        e.t[c] = e.n[c] ? std::min(e.t[c], t) : t;
+        e.n[c] += 1;
+    }
+    void force(int c) { forced_ = c; }
+
+   private:
+    struct Entry {
+        double t[kNumBudgets] = {};
+        int n[kNumBudgets] = {};
+    };
+    std::mutex mu_;
+    std::map<TuneKey, Entry> tab_;
+    int forced_ = -1;
+};
+
+Tuner& tuner() {
+    static Tuner t;
+    return t;
+}
 }  // namespace
 
-Status sk_solve(const SkBatch& p, const dd_sinkhorn_opts& o, hipStream_t st, SkWork& w,
+namespace {
+// Runs the solve on the library's own stream, ordered after the caller's stream on entry
+// and before it on exit (a stream of our own can be captured into graphs whatever stream
+// the caller uses).
+struct StreamJoin {
+    hipStream_t caller, own;
+    hipEvent_t ev;
+    StreamJoin(hipStream_t c, hipStream_t o, hipEvent_t e) : caller(c), own(o), ev(e) {
+        (void)hipEventRecord(ev, caller);
+        (void)hipStreamWaitEvent(own, ev, 0);
+    }
+    ~StreamJoin() {
+        (void)hipEventRecord(ev, own);
+        (void)hipStreamWaitEvent(caller, ev, 0);
+    }
+};
+}  // namespace
+
+Status sk_solve(const SkBatch& p, const dd_sinkhorn_opts& o, hipStream_t caller_st, SkWork& w,
                 dd_batch_stats* stats, int32_t* cell_iters_out, double* cell_err_out) {
     Status S;
     if (p.ncells < 0 || p.xside < 2 || p.xside > 16 || !(p.kappa > 0.0) || p.max_w1 < 1 ||
@@ -870,6 +1102,8 @@ Status sk_solve(const SkBatch& p, const dd_sinkhorn_opts& o, hipStream_t st, SkW
     }
     S = sk_work_reserve(w, p.ncells, (size_t)p.ncells * p.xside * p.xside);
     if (S.code) return S;
+    const StreamJoin join(caller_st, w.stream, w.evj);
+    const hipStream_t st = w.stream;
     int32_t* iters = cell_iters_out ? cell_iters_out : w.cell_iters;
     double* errs = cell_err_out ? cell_err_out : w.cell_err;
     if (p.ncells == 0) {
@@ -894,29 +1128,22 @@ Status sk_solve(const SkBatch& p, const dd_sinkhorn_opts& o, hipStream_t st, SkW
     std::vector<int32_t> ord(p.ncells);
     for (int c = 0; c < p.ncells; ++c) ord[c] = c;
     std::stable_sort(ord.begin(), ord.end(), [&](int a, int b) { return work(a) > work(b); });
-    // LDS budget per workgroup: ~2 workgroups (8 waves) per CU
-    const size_t wg_budget = 78 * 1024;
     const size_t elem = p.prec == DD_PREC_F64 ? sizeof(double) : sizeof(float);
     // a cell whose LSE work per iteration is several times a typical cell's runs on the whole
-    // workgroup; the others run one per wave from the LDS tile planned over them, and a cell
-    // that does not fit that tile (in either precision) also goes to a workgroup
+    // workgroup, the others one per wave; the split depends on the box shapes only
     const double big_terms = 64.0 * 1024.0;
-    std::vector<int32_t> cand;
-    for (int c : ord)
-        if (work(c) < big_terms) cand.push_back(c);
+    std::vector<int32_t> big_cells, small_cells;
+    for (int c : ord) (work(c) >= big_terms ? big_cells : small_cells).push_back(c);
+    const int nbig = (int)big_cells.size();
+    // LDS budget per workgroup from the tuner; it only decides which boxes live in LDS and
+    // which in global scratch, never the arithmetic, so every choice gives the same result
+    const TuneKey key{AS, p.prec, o.fixed_iters > 0 ? 2 : o.stop_rule};
+    const int choice = tuner().pick(key);
+    const size_t wg_budget = kBudgets[choice];
     SkBatch q = p;
     SkBatch q64 = p;
-    plan_tile(hd, cand, AS, elem, wg_budget / kWaves, q.lw1, q.lw2);
-    plan_tile(hd, cand, AS, sizeof(double), wg_budget / kWaves, q64.lw1, q64.lw2);
-    const int sw1 = std::min(q.lw1, q64.lw1), sw2 = std::min(q.lw2, q64.lw2);
-    std::vector<int32_t> big_cells, small_cells;
-    for (int c : ord) {
-        if (work(c) < big_terms && hd[2 * c] <= sw1 && hd[2 * c + 1] <= sw2)
-            small_cells.push_back(c);
-        else
-            big_cells.push_back(c);
-    }
-    const int nbig = (int)big_cells.size();
+    plan_tile(hd, small_cells, AS, elem, wg_budget / kWaves, q.lw1, q.lw2);
+    plan_tile(hd, small_cells, AS, sizeof(double), wg_budget / kWaves, q64.lw1, q64.lw2);
     plan_tile(hd, big_cells, AS, elem, wg_budget, q.lw1b, q.lw2b);
     plan_tile(hd, big_cells, AS, sizeof(double), wg_budget, q64.lw1b, q64.lw2b);
     ord = big_cells;
@@ -930,15 +1157,18 @@ Status sk_solve(const SkBatch& p, const dd_sinkhorn_opts& o, hipStream_t st, SkW
     }
     DD_HIP(hipMemcpyAsync(w.order, ord.data(), ord.size() * 4, hipMemcpyHostToDevice, st), S);
     q.order = q64.order = w.order;
-    // per-cell global scratch for the big boxes beyond their tile in either precision, sized
-    // for float64 terms
+    // per-cell global scratch for the boxes beyond their class's tile in either precision,
+    // sized for float64 terms
     std::vector<int64_t> off(p.ncells, 0);
     int64_t scr = 0;
-    const int bw1 = std::min(q.lw1b, q64.lw1b), bw2 = std::min(q.lw2b, q64.lw2b);
-    for (int c : big_cells) {
+    for (int k = 0; k < p.ncells; ++k) {
+        const int c = ord[k];
         const int W1 = hd[2 * c], W2 = hd[2 * c + 1];
         if (W1 < 1 || W2 < 1) continue;
-        if (W1 > bw1 || W2 > bw2) {
+        const bool is_big = k < nbig;
+        const int t1 = is_big ? std::min(q.lw1b, q64.lw1b) : std::min(q.lw1, q64.lw1);
+        const int t2 = is_big ? std::min(q.lw2b, q64.lw2b) : std::min(q.lw2, q64.lw2);
+        if (W1 > t1 || W2 > t2) {
             off[c] = scr;
             scr += cell_scratch_doubles(AS, W1, W2, sizeof(double));
         }
@@ -1009,6 +1239,7 @@ Status sk_solve(const SkBatch& p, const dd_sinkhorn_opts& o, hipStream_t st, SkW
         bs.converged = hctl[7];
     else
         bs.converged = hctl[4];
+    if (bs.lse_terms > 0.0) tuner().record(key, choice, ms_main / bs.lse_terms);
     if (stats) *stats = bs;
     if (!std::isfinite(bs.err)) {
         S.code = DD_ENUMERIC;

@@ -48,6 +48,8 @@ struct SkWork {
     int order_cap = 0;
     int cap = 0;
     hipEvent_t ev0 = nullptr, ev1 = nullptr, ev2 = nullptr;
+    hipEvent_t evj = nullptr;     // joins the caller's stream and `stream`
+    hipStream_t stream = nullptr; // the solver's own stream (default priority)
 };
 
 Status sk_work_reserve(SkWork& w, int ncells, size_t a_n);

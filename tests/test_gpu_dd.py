@@ -149,3 +149,29 @@ def test_save_restore_replays_bit_exactly():
     for a, b in zip(p1, p2):
         assert np.array_equal(a, b)
     g.close()
+
+
+@pytest.mark.parametrize("N,s", [(16, 2), (32, 4)])
+def test_stitched_dual_matches_oracle(N, s):
+    """The primal-dual gap of the evaluation: the GPU's stitched dual value equals the
+    oracle's on the same float64 trajectory, and the gap is non-negative."""
+    import paper_2405_09400_amd as dd
+    _need_gpu()
+    print(f"stitched dual N={N} s={s}", flush=True)
+    w = synth.workload("small32", N=N)
+    g = dd.DomDec(w.mu, w.nu, s, prec=dd.DD_PREC_F64)
+    o = oracle.DomDec(w.mu, w.nu, s)
+    eps = 4.0 / N ** 2
+    ev = None
+    for k in range(6):
+        part = "AB"[k % 2]
+        g.iterate(part, eps, fixed_iters=80)
+        o.iterate(part, eps, fixed_iters=80)
+        ev = g.evaluate()
+        if k == 0:
+            assert np.isnan(ev["dual"])  # B not visited yet
+    D, _, _ = o.stitched_dual(eps)
+    assert abs(ev["dual"] - D) <= 1e-10 * abs(D), (ev["dual"], D)
+    assert abs(ev["primal"] - o.primal(eps)) <= 1e-10 * abs(D)
+    assert ev["pd_gap"] >= -1e-12 * abs(D)
+    g.close()

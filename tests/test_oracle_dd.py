@@ -109,3 +109,34 @@ def test_basic_cells_are_contiguous_blocks():
         r, c = divmod(i, N // s)
         assert set(k1) == set(range(r * s, r * s + s)) and set(k2) == set(range(c * s, c * s + s))
     assert np.all(owner >= 0)
+
+
+def test_stitched_dual_weak_duality_and_zero_gap():
+    """Stitched dual (the gap of the DD iterate): D(alpha+, beta+) never exceeds the optimum
+    (weak duality, checked with dual_value's general formula on the same point), and the gap
+    E(pi) - D closes as DD converges to the global optimum."""
+    N = 16
+    mu, nu = _small(N, seed=2)
+    eps = (2.0 / N) ** 2
+    a, b, P, _ = oracle.global_sinkhorn(mu, nu, eps, tol=1e-13)
+    Estar = oracle.primal_dense(mu, nu, P, eps)
+    dd = oracle.DomDec(mu, nu, 4)
+    gaps = []
+    for k in range(60):
+        dd.iterate("AB"[k % 2], eps, tol=1e-11, max_iter=5000)
+        if k >= 1:
+            D, al, be = dd.stitched_dual(eps)
+            # the Y-update makes the exp term of the dual exactly its constant
+            Dg = oracle.dual_value(mu, nu, al, be, eps)
+            assert abs(D - Dg) <= 1e-12 * abs(D)
+            assert D <= Estar + 1e-12 * abs(Estar)
+            gaps.append(dd.primal(eps) - D)
+    gaps = np.array(gaps)
+    assert gaps[0] > 1e-6 * Estar        # far from the optimum at the start
+    assert 0 <= gaps[-1] < 1e-8 * Estar  # closed at convergence
+    # a gauge shift of one cell's potential (the cell problem's invariance) leaves D unchanged
+    D0, _, _ = dd.stitched_dual(eps)
+    dd.alpha["B"][3] = dd.alpha["B"][3] + 0.37
+    dd.alpha["A"][0] = dd.alpha["A"][0] - 1.25
+    D1, _, _ = dd.stitched_dual(eps)
+    assert abs(D1 - D0) <= 1e-12 * abs(D0)
