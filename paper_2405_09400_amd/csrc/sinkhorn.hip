@@ -129,16 +129,18 @@ struct Lds {
     lds_p<double> s;    // [N2]        LSE_j (g + log nu_J - C)
     lds_p<double> ry;   // [AS]        row maxima of f + log mu
     lds_p<double> Mx;   // [AS]        column maxima of the X-half intermediate
-    lds_p<double> red;  // [16]        reductions; [8] = R (max of ry)
+    lds_p<double> red;  // [16]        reductions
     lds_p<T> wq;        // [N2]        f + log mu - ry(row)
     lds_p<T> u1;        // [N2]        exp(wq)
     lds_p<T> sX1;       // [AS]        nearest-point shifts of the X-half passes
     lds_p<T> sX2;       // [AS]
-    // Y-box arrays
-    YD ln;              // [W1][ys]    log nu_J
+    // the cell's Y potential g and log nu_J stay in global memory (float64, row stride W2),
+    // streamed once per half-iteration
+    glb_p<double> g;    // [W1][W2]
+    glb_p<const double> ln;  // [W1][W2]
+    // Y-box arrays (LDS tile, or global scratch for a box beyond the tile)
     YD qx;              // [W1]        row maxima of g + log nu_J
     YD My;              // [W2]        column maxima of the Y-half intermediate
-    YT gq;              // [W1][ys]    g + R
     YT u3;              // [W1][ys]    exp(g + log nu_J - qx(row))
     YT KY1;             // [AS][W2p]   kernel table, Y-half pass over i2
     YT t1;              // [AS][W2p]   Y-half intermediate, relative to ry
@@ -160,8 +162,8 @@ __host__ __device__ inline size_t x_bytes(int AS, size_t elem) {
 }
 __host__ __device__ inline size_t box_bytes(int AS, int w1, int w2, size_t elem) {
     const size_t ys = (size_t)w2 + 1, W2p = ys, W1p = (size_t)w1 + 1, ASp = (size_t)AS + 1;
-    const size_t nd = (size_t)w1 * ys + w1 + w2;
-    const size_t nt = 2 * (size_t)w1 * ys + 3 * (size_t)AS * W2p + (size_t)AS * W1p +
+    const size_t nd = (size_t)w1 + w2;
+    const size_t nt = (size_t)w1 * ys + 3 * (size_t)AS * W2p + (size_t)AS * W1p +
                       (size_t)w2 * ASp + 3 * (size_t)w1 * ASp + w2 + w1;
     return 8 * nd + elem * nt + 64;
 }
@@ -187,20 +189,16 @@ __host__ __device__ inline int64_t cell_scratch_doubles(int AS, int W1, int W2, 
 
 // Bind the Y-box arrays of a (W1 x W2) box with strides for (w1s x w2s) starting at `base`.
 template <typename T, typename PD, typename PT>
-__device__ __forceinline__ void bind_box(PD& ln, PD& qx, PD& My, PT& gq, PT& u3, PT& KY1, PT& t1,
-                                         PT& u2, PT& KY2, PT& KX1, PT& r, PT& u4, PT& KX2, PT& sY1,
+__device__ __forceinline__ void bind_box(PD& qx, PD& My, PT& u3, PT& KY1, PT& t1, PT& u2,
+                                         PT& KY2, PT& KX1, PT& r, PT& u4, PT& KX2, PT& sY1,
                                          PT& sY2, PD base, int AS, int w1s, int w2s) {
     const int ys = w2s + 1, W2p = ys, W1p = w1s + 1, ASp = AS + 1;
     PD d = base;
-    ln = d;
-    d += (size_t)w1s * ys;
     qx = d;
     d += w1s;
     My = d;
     d += w2s;
     PT t = (PT)d;
-    gq = t;
-    t += (size_t)w1s * ys;
     u3 = t;
     t += (size_t)w1s * ys;
     KY1 = t;
@@ -225,7 +223,8 @@ __device__ __forceinline__ void bind_box(PD& ln, PD& qx, PD& My, PT& gq, PT& u3,
 }
 
 // Carve the X arrays (and, for G = false, the tile) out of an LDS slice; for G = true bind
-// the Y-box arrays to the cell's global scratch.
+// the Y-box arrays to the cell's global scratch.  g and log nu_J point into the packed
+// float64 arrays at the cell's offset.
 template <typename T, bool G>
 __device__ __forceinline__ Lds<T, G> carve(lds_p<char> base, const SkBatch& p, int lw1, int lw2,
                                            int c, int W1, int W2, int64_t ybase,
@@ -253,20 +252,20 @@ __device__ __forceinline__ Lds<T, G> carve(lds_p<char> base, const SkBatch& p, i
     L.sX1 = t;
     t += AS;
     L.sX2 = t;
-    t += AS;
     L.ASp = AS + 1;
+    L.g = (glb_p<double>)(p.b + ybase);
+    L.ln = (glb_p<const double>)(p.lognu + ybase);
     if constexpr (!G) {
         lds_p<double> bb = (lds_p<double>)(base + ((x_bytes(AS, sizeof(T)) + 15) & ~size_t(15)));
-        bind_box<T>(L.ln, L.qx, L.My, L.gq, L.u3, L.KY1, L.t1, L.u2, L.KY2, L.KX1, L.r, L.u4,
-                    L.KX2, L.sY1, L.sY2, bb, AS, lw1, lw2);
+        bind_box<T>(L.qx, L.My, L.u3, L.KY1, L.t1, L.u2, L.KY2, L.KX1, L.r, L.u4, L.KX2, L.sY1,
+                    L.sY2, bb, AS, lw1, lw2);
         L.ys = lw2 + 1;
         L.W2p = lw2 + 1;
         L.W1p = lw1 + 1;
     } else {
-        (void)ybase;
         glb_p<double> bb = (glb_p<double>)(big_scratch + p.scr_off[c]);
-        bind_box<T>(L.ln, L.qx, L.My, L.gq, L.u3, L.KY1, L.t1, L.u2, L.KY2, L.KX1, L.r, L.u4,
-                    L.KX2, L.sY1, L.sY2, bb, AS, W1, W2);
+        bind_box<T>(L.qx, L.My, L.u3, L.KY1, L.t1, L.u2, L.KY2, L.KX1, L.r, L.u4, L.KX2, L.sY1,
+                    L.sY2, bb, AS, W1, W2);
         L.ys = W2 + 1;
         L.W2p = W2 + 1;
         L.W1p = W1 + 1;
@@ -327,10 +326,6 @@ __device__ __forceinline__ void load_cell(const Tm& tm, const SkBatch& p, const 
         L.lm[i] = p.logmu[(int64_t)c * N2 + i];
         L.f[i] = f_src[(int64_t)c * N2 + i];
     }
-    for (int o = tid; o < W1 * W2; o += nt) {
-        const int j1 = o / W2, j2 = o - j1 * W2;
-        L.ln[j1 * L.ys + j2] = p.lognu[base + o];
-    }
     // Y-half: over i2 (d = i2 - j2 + E2), over i1 (d = i1 - j1 + E1);
     // X-half: over j2 (d = j2 - i2 - E2), over j1 (d = j1 - i1 - E1)
     build_table(tm, L.KY1, L.sY1, AS, W2, E2, L.W2p, 1, invk);
@@ -341,7 +336,7 @@ __device__ __forceinline__ void load_cell(const Tm& tm, const SkBatch& p, const 
 }
 
 // Y-update g(j) = -LSE_i [f(i) + log mu(i) - C(i,j)]: pass over i2, then over i1.
-// Leaves gq (g = gq - R, R in red[8]).
+// Writes g (float64) to the output array.
 template <typename Tm, typename T, bool G>
 __device__ __forceinline__ void y_half(const Tm& tm, const Lds<T, G>& L, int AS, int W1, int W2,
                                        int E1, int E2, T invk) {
@@ -357,11 +352,6 @@ __device__ __forceinline__ void y_half(const Tm& tm, const Lds<T, G>& L, int AS,
         const T w = (T)(L.f[i] + L.lm[i] - L.ry[i / AS]);
         L.wq[i] = w;
         L.u1[i] = fexp(w);
-    }
-    if (tid == 0) {
-        double R = L.ry[0];
-        for (int i1 = 1; i1 < AS; ++i1) R = fmax(R, L.ry[i1]);
-        L.red[8] = R;
     }
     tm.sync();
     // pass over i2: t1(i1, j2) = LSE_i2 [wq(i1, i2) - (i2 - j2 + E2)^2 / kappa]
@@ -390,7 +380,6 @@ __device__ __forceinline__ void y_half(const Tm& tm, const Lds<T, G>& L, int AS,
     }
     tm.sync();
     // pass over i1: g(j1, j2) = -LSE_i1 [t1(i1, j2) + ry(i1) - (i1 - j1 + E1)^2 / kappa]
-    const double R = L.red[8];
     for (int o = tid; o < W1 * W2; o += nt) {
         const int j1 = o / W2, j2 = o - j1 * W2;
         T sum = T(0);
@@ -404,7 +393,7 @@ __device__ __forceinline__ void y_half(const Tm& tm, const Lds<T, G>& L, int AS,
                 [&](int k) { return L.t1[k * L.W2p + j2] + (T)(L.ry[k] - Mj); }, AS, j1, E1,
                 invk);
         }
-        L.gq[j1 * L.ys + j2] = -(T)(Mj - R) - v;
+        L.g[o] = -(Mj + (double)v);
     }
     tm.sync();
 }
@@ -416,16 +405,15 @@ __device__ __forceinline__ void x_half(const Tm& tm, const Lds<T, G>& L, int AS,
                                        int E1, int E2, T invk) {
     const int tid = tm.tid(), nt = tm.size();
     const int lane = threadIdx.x & 63, wid = tm.wid(), nw = tm.nw();
-    const double R = L.red[8];
-    // row maxima of g + log nu_J (one wave per row) and the scaled inputs
+    // row maxima of g + log nu_J (one wave per row, coalesced reads) and the scaled inputs
     for (int j1 = wid; j1 < W1; j1 += nw) {
         double m = -1e300;
         for (int j2 = lane; j2 < W2; j2 += 64)
-            m = fmax(m, (double)L.gq[j1 * L.ys + j2] + L.ln[j1 * L.ys + j2]);
+            m = fmax(m, L.g[j1 * W2 + j2] + L.ln[j1 * W2 + j2]);
         m = wave_max_d(m);
         for (int j2 = lane; j2 < W2; j2 += 64)
-            L.u3[j1 * L.ys + j2] = fexp((T)((double)L.gq[j1 * L.ys + j2] + L.ln[j1 * L.ys + j2] - m));
-        if (lane == 0) L.qx[j1] = m - R;
+            L.u3[j1 * L.ys + j2] = fexp((T)(L.g[j1 * W2 + j2] + L.ln[j1 * W2 + j2] - m));
+        if (lane == 0) L.qx[j1] = m;
     }
     tm.sync();
     // pass over j2: r(j1, i2) = LSE_j2 [g + log nu_J - qx(j1) - (j2 - i2 - E2)^2 / kappa]
@@ -437,12 +425,10 @@ __device__ __forceinline__ void x_half(const Tm& tm, const Lds<T, G>& L, int AS,
         if (sum >= sum_floor<T>()) {
             v = flog(sum) - L.sX1[i2];
         } else {
-            const double q = L.qx[j1] + R;
+            const double q = L.qx[j1];
             v = lse_exact<T>(
-                [&](int k) {
-                    return (T)((double)L.gq[j1 * L.ys + k] + L.ln[j1 * L.ys + k] - q);
-                },
-                W2, i2, -E2, invk);
+                [&](int k) { return (T)(L.g[j1 * W2 + k] + L.ln[j1 * W2 + k] - q); }, W2, i2,
+                -E2, invk);
         }
         L.r[j1 * L.ASp + i2] = v;
     }
@@ -478,32 +464,39 @@ __device__ __forceinline__ void x_half(const Tm& tm, const Lds<T, G>& L, int AS,
     tm.sync();
 }
 
-// X-marginal L1 error sum_i mu |exp(f + s) - 1| and mass sum_i mu, float64.
+// X-marginal L1 error sum_i mu |exp(f + s) - 1| and mass sum_i mu, float64, summed by the
+// first wave in a fixed order whatever the team (so a cell's stop decision does not depend
+// on whether a wave or a workgroup solves it).
 template <typename Tm, typename T, bool G>
 __device__ __forceinline__ void err_mass(const Tm& tm, const Lds<T, G>& L, int AS, double& err,
                                          double& mass) {
-    double e = 0.0, m = 0.0;
-    for (int i = tm.tid(); i < AS * AS; i += tm.size()) {
-        const double lm = L.lm[i];
-        if (lm > kZeroMassLog) {
-            const double mu = exp(lm);
-            e += mu * fabs(expm1(L.f[i] + L.s[i]));
-            m += mu;
+    if (tm.wid() == 0) {
+        double e = 0.0, m = 0.0;
+        for (int i = threadIdx.x & 63; i < AS * AS; i += 64) {
+            const double lm = L.lm[i];
+            if (lm > kZeroMassLog) {
+                const double mu = exp(lm);
+                e += mu * fabs(expm1(L.f[i] + L.s[i]));
+                m += mu;
+            }
+        }
+        e = wave_sum(e);
+        m = wave_sum(m);
+        if ((threadIdx.x & 63) == 0) {
+            L.red[0] = e;
+            L.red[1] = m;
         }
     }
-    err = tm.sum(e, L.red);
-    mass = tm.sum(m, L.red);
+    tm.sync();
+    err = L.red[0];
+    mass = L.red[1];
+    tm.sync();
 }
 
+// g is written to the output by every Y-update (it lives in p.b), nothing to store.
 template <typename Tm, typename T, bool G>
-__device__ __forceinline__ void store_g(const Tm& tm, const SkBatch& p, const Lds<T, G>& L, int W1,
-                                        int W2, int64_t base) {
-    const double goff = -L.red[8];
-    for (int o = tm.tid(); o < W1 * W2; o += tm.size()) {
-        const int j1 = o / W2, j2 = o - j1 * W2;
-        p.b[base + o] = (double)L.gq[j1 * L.ys + j2] + goff;
-    }
-}
+__device__ __forceinline__ void store_g(const Tm&, const SkBatch&, const Lds<T, G>&, int, int,
+                                        int64_t) {}
 
 // ctrl words: [0] big-cell queue, [1] ticket, [2] done iteration, [3] bad-dims flag,
 // [4] converged, [9] small-cell queue; [5..8] batch statistics
@@ -587,16 +580,19 @@ struct SolveCell {
     }
 };
 
-template <typename T>
+// The two cell classes run as two kernels (each with its own LDS size), launched side by
+// side on two streams: MODE 0 = big cells, one per workgroup; MODE 1 = small cells, one per
+// wave.  Big cells are order[0..nbig), small ones order[nbig..ncells).
+constexpr int kBig = 0, kSmall = 1;
+
+template <typename T, int MODE>
 __global__ void __launch_bounds__(kThreads)
     sk_cell_kernel(SkBatch p, double tol, int limit, int fixed, int stall_window, int* ctrl,
                    int32_t* iters_out, double* err_out, double* mass_out, double* big_scratch) {
     extern __shared__ __align__(16) char smem[];
-    __shared__ int s_cell;
     const lds_p<char> base = (lds_p<char>)smem;
-    const int nsmall = p.ncells - p.nbig;
-    // big cells: the whole workgroup on one cell
-    {
+    if constexpr (MODE == kBig) {
+        __shared__ int s_cell;
         const BlockTeam tm;
         const SolveCell<BlockTeam, T> body{tm, p, tol, limit, fixed, stall_window,
                                            iters_out, err_out, mass_out};
@@ -608,21 +604,21 @@ __global__ void __launch_bounds__(kThreads)
             if (q >= p.nbig) break;
             with_cell<T, true>(tm, p, base, p.lw1b, p.lw2b, p.order[q], big_scratch, ctrl, body);
         }
-    }
-    __syncthreads();
-    // small cells: each wave on its own cell, in its own LDS slice
-    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
-    const lds_p<char> slice = base + w * lds_layout_bytes(p.xside, p.lw1, p.lw2, sizeof(T));
-    const WaveTeam tm;
-    const SolveCell<WaveTeam, T> body{tm, p, tol, limit, fixed, stall_window,
-                                      iters_out, err_out, mass_out};
-    for (;;) {
-        int q = 0;
-        if (lane == 0) q = atomicAdd(&ctrl[9], 1);
-        q = __builtin_amdgcn_readfirstlane(__shfl(q, 0, 64));
-        if (q >= nsmall) break;
-        with_cell<T, true>(tm, p, slice, p.lw1, p.lw2, p.order[p.nbig + q], big_scratch, ctrl,
-                           body);
+    } else {
+        const int nsmall = p.ncells - p.nbig;
+        const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
+        const lds_p<char> slice = base + w * lds_layout_bytes(p.xside, p.lw1, p.lw2, sizeof(T));
+        const WaveTeam tm;
+        const SolveCell<WaveTeam, T> body{tm, p, tol, limit, fixed, stall_window,
+                                          iters_out, err_out, mass_out};
+        for (;;) {
+            int q = 0;
+            if (lane == 0) q = atomicAdd(&ctrl[9], 1);
+            q = __builtin_amdgcn_readfirstlane(__shfl(q, 0, 64));
+            if (q >= nsmall) break;
+            with_cell<T, true>(tm, p, slice, p.lw1, p.lw2, p.order[p.nbig + q], big_scratch,
+                               ctrl, body);
+        }
     }
 }
 
@@ -679,26 +675,27 @@ struct FinalCell {
     }
 };
 
-// Work items of a batch-rule launch: the big cells one per item, then the small cells four
+// Work items of one class in a batch-rule launch: big cells one per item, small cells four
 // per item (one per wave).
-__host__ __device__ inline int batch_items(int ncells, int nbig) {
-    return nbig + (ncells - nbig + kWaves - 1) / kWaves;
+__host__ __device__ inline int class_items(int mode, int ncells, int nbig) {
+    return mode == kBig ? nbig : (ncells - nbig + kWaves - 1) / kWaves;
 }
 
-// Run `make(team)` over the batch-rule items assigned to this workgroup.
-template <typename T, typename Make>
+// Run `make(team)` over the batch-rule items of this class assigned to this workgroup.
+template <typename T, int MODE, typename Make>
 __device__ __forceinline__ void for_items(const SkBatch& p, lds_p<char> base, double* big_scratch,
                                           int* ctrl, Make&& make) {
-    const int nitems = batch_items(p.ncells, p.nbig);
-    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const lds_p<char> slice = base + w * lds_layout_bytes(p.xside, p.lw1, p.lw2, sizeof(T));
+    const int nitems = class_items(MODE, p.ncells, p.nbig);
     for (int q = blockIdx.x; q < nitems; q += gridDim.x) {
-        if (q < p.nbig) {
+        if constexpr (MODE == kBig) {
             const BlockTeam tm;
             with_cell<T, true>(tm, p, base, p.lw1b, p.lw2b, p.order[q], big_scratch, ctrl,
                                make(tm));
         } else {
-            const int k = p.nbig + (q - p.nbig) * kWaves + w;
+            const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+            const lds_p<char> slice =
+                base + w * lds_layout_bytes(p.xside, p.lw1, p.lw2, sizeof(T));
+            const int k = p.nbig + q * kWaves + w;
             if (k < p.ncells) {
                 const WaveTeam tm;
                 with_cell<T, true>(tm, p, slice, p.lw1, p.lw2, p.order[k], big_scratch, ctrl,
@@ -709,10 +706,14 @@ __device__ __forceinline__ void for_items(const SkBatch& p, lds_p<char> base, do
     }
 }
 
-template <typename T>
+// One batch-rule iteration of one class.  The workgroups of both classes' launches take one
+// ticket each; the last of all (`nblocks` in total) reduces the per-cell errors in fixed
+// cell order and sets the stop flag.
+template <typename T, int MODE>
 __global__ void __launch_bounds__(kThreads)
-    sk_iter_kernel(SkBatch p, double* fa, double* fb, int limit, double tol, int* ctrl,
-                   double* cell_err, double* cell_mass, double* dtot, double* big_scratch) {
+    sk_iter_kernel(SkBatch p, double* fa, double* fb, int limit, double tol, int nblocks,
+                   int* ctrl, double* cell_err, double* cell_mass, double* dtot,
+                   double* big_scratch) {
     if (__atomic_load_n(&ctrl[2], __ATOMIC_RELAXED) != 0) return;
     // the iteration number lives on the device (every launch is identical, so a chunk of
     // launches can be captured once and replayed); odd iterations read fa and write fb
@@ -722,13 +723,12 @@ __global__ void __launch_bounds__(kThreads)
     extern __shared__ __align__(16) char smem[];
     __shared__ int s_last;
     __shared__ double s_red[16];
-    for_items<T>(p, (lds_p<char>)smem, big_scratch, ctrl, [&](const auto& tm) {
+    for_items<T, MODE>(p, (lds_p<char>)smem, big_scratch, ctrl, [&](const auto& tm) {
         using Tm = std::decay_t<decltype(tm)>;
         return IterCell<Tm, T>{tm, p, f_in, f_out, cell_err, cell_mass};
     });
-    // last workgroup to finish reduces the per-cell errors in fixed order
     __threadfence();
-    if (threadIdx.x == 0) s_last = (atomicAdd(&ctrl[1], 1) == (int)gridDim.x - 1);
+    if (threadIdx.x == 0) s_last = (atomicAdd(&ctrl[1], 1) == nblocks - 1);
     __syncthreads();
     if (!s_last) return;
     __threadfence();
@@ -750,13 +750,13 @@ __global__ void __launch_bounds__(kThreads)
     }
 }
 
-template <typename T>
+template <typename T, int MODE>
 __global__ void __launch_bounds__(kThreads) sk_final_kernel(SkBatch p, int* ctrl,
                                                            int32_t* iters_out,
                                                            double* big_scratch) {
     extern __shared__ __align__(16) char smem[];
     const int done = ctrl[2];
-    for_items<T>(p, (lds_p<char>)smem, big_scratch, ctrl, [&](const auto& tm) {
+    for_items<T, MODE>(p, (lds_p<char>)smem, big_scratch, ctrl, [&](const auto& tm) {
         using Tm = std::decay_t<decltype(tm)>;
         return FinalCell<Tm, T>{tm, p, done, iters_out};
     });
@@ -839,7 +839,10 @@ Status sk_work_reserve(SkWork& w, int ncells, size_t a_n) {
         DD_HIP(hipEventCreate(&w.ev1), st);
         DD_HIP(hipEventCreate(&w.ev2), st);
         DD_HIP(hipEventCreateWithFlags(&w.evj, hipEventDisableTiming), st);
+        DD_HIP(hipEventCreateWithFlags(&w.evf, hipEventDisableTiming), st);
+        DD_HIP(hipEventCreateWithFlags(&w.evj2, hipEventDisableTiming), st);
         DD_HIP(hipStreamCreateWithFlags(&w.stream, hipStreamNonBlocking), st);
+        DD_HIP(hipStreamCreateWithFlags(&w.stream2, hipStreamNonBlocking), st);
     }
     if (ncells > w.cap) {
         if (w.cell_err) (void)hipFree(w.cell_err);
@@ -881,10 +884,13 @@ void sk_work_release(SkWork& w) {
     if (w.ev1) (void)hipEventDestroy(w.ev1);
     if (w.ev2) (void)hipEventDestroy(w.ev2);
     if (w.evj) (void)hipEventDestroy(w.evj);
-    if (w.stream) {
-        (void)hipStreamSynchronize(w.stream);
-        (void)hipStreamDestroy(w.stream);
-    }
+    if (w.evf) (void)hipEventDestroy(w.evf);
+    if (w.evj2) (void)hipEventDestroy(w.evj2);
+    for (hipStream_t* sp : {&w.stream, &w.stream2})
+        if (*sp) {
+            (void)hipStreamSynchronize(*sp);
+            (void)hipStreamDestroy(*sp);
+        }
     w = SkWork{};
 }
 
@@ -925,37 +931,67 @@ Status run_solver(const SkBatch& p, const dd_sinkhorn_opts& o, hipStream_t st, S
                   int32_t* iters, double* errs) {
     Status S;
     double* big = reinterpret_cast<double*>(w.big);
-    const size_t lds = wg_lds_bytes(p.xside, p.lw1, p.lw2, p.lw1b, p.lw2b, sizeof(T));
+    // big cells on the second stream, small cells on `st`, side by side
+    const size_t ldsB = lds_layout_bytes(p.xside, p.lw1b, p.lw2b, sizeof(T));
+    const size_t ldsS = kWaves * lds_layout_bytes(p.xside, p.lw1, p.lw2, sizeof(T));
+    const int nsmall = p.ncells - p.nbig;
+    const hipStream_t s2 = w.stream2;
+    auto fork = [&]() {
+        (void)hipEventRecord(w.evf, st);
+        (void)hipStreamWaitEvent(s2, w.evf, 0);
+    };
+    auto join = [&]() {
+        (void)hipEventRecord(w.evj2, s2);
+        (void)hipStreamWaitEvent(st, w.evj2, 0);
+    };
     const bool fixed = o.fixed_iters > 0;
     zero_ints<<<1, 64, 0, st>>>(w.ctrl, 11);
     if (fixed || o.stop_rule == DD_STOP_CELL) {
-        auto kern = sk_cell_kernel<T>;
-        if (set_lds_attr(kern, lds, S).code) return S;
-        const int grid = grid_for(kern, lds, batch_items(p.ncells, p.nbig));
+        auto kb = sk_cell_kernel<T, kBig>;
+        auto ks = sk_cell_kernel<T, kSmall>;
+        if (set_lds_attr(kb, ldsB, S).code || set_lds_attr(ks, ldsS, S).code) return S;
         const int limit = fixed ? o.fixed_iters : o.max_iter;
         // stall detection only where a float64 finish follows
         const int stall = sizeof(T) == sizeof(float) ? 32 : 0;
-        kern<<<grid, kThreads, lds, st>>>(p, o.tol, limit, fixed ? 1 : 0, stall, w.ctrl, iters,
-                                          errs, w.cell_mass, big);
+        fork();
+        if (p.nbig > 0)
+            kb<<<grid_for(kb, ldsB, p.nbig), kThreads, ldsB, s2>>>(
+                p, o.tol, limit, fixed ? 1 : 0, stall, w.ctrl, iters, errs, w.cell_mass, big);
+        if (nsmall > 0)
+            ks<<<grid_for(ks, ldsS, class_items(kSmall, p.ncells, p.nbig)), kThreads, ldsS, st>>>(
+                p, o.tol, limit, fixed ? 1 : 0, stall, w.ctrl, iters, errs, w.cell_mass, big);
+        join();
         DD_HIP(hipGetLastError(), S);
         return S;
     }
-    auto kern = sk_iter_kernel<T>;
-    auto fin = sk_final_kernel<T>;
-    if (set_lds_attr(kern, lds, S).code) return S;
-    if (set_lds_attr(fin, lds, S).code) return S;
-    const int grid = grid_for(kern, lds, batch_items(p.ncells, p.nbig));
+    auto ib = sk_iter_kernel<T, kBig>;
+    auto is = sk_iter_kernel<T, kSmall>;
+    auto fb = sk_final_kernel<T, kBig>;
+    auto fs = sk_final_kernel<T, kSmall>;
+    if (set_lds_attr(ib, ldsB, S).code || set_lds_attr(is, ldsS, S).code ||
+        set_lds_attr(fb, ldsB, S).code || set_lds_attr(fs, ldsS, S).code)
+        return S;
+    const int gB = p.nbig > 0 ? grid_for(ib, ldsB, p.nbig) : 0;
+    const int gS = nsmall > 0 ? grid_for(is, ldsS, class_items(kSmall, p.ncells, p.nbig)) : 0;
+    const int nblocks = gB + gS;
     double* bufs[2] = {p.a, w.a_alt};
     const size_t a_bytes = (size_t)p.ncells * p.xside * p.xside * sizeof(double);
     const int chunk = o.check_every > 0 ? o.check_every : 8;
-    // a chunk of identical launches is captured into a HIP graph once and replayed; the host
-    // reads the device stop flag between replays
+    // a chunk of identical iterations (both classes' launches, forked and joined) is captured
+    // into a HIP graph once and replayed; the host reads the device stop flag between replays
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     DD_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal), S);
-    for (int k = 0; k < chunk; ++k)
-        kern<<<grid, kThreads, lds, st>>>(p, bufs[0], bufs[1], o.max_iter, o.tol, w.ctrl, errs,
-                                          w.cell_mass, w.dtot, big);
+    for (int k = 0; k < chunk; ++k) {
+        fork();
+        if (gB > 0)
+            ib<<<gB, kThreads, ldsB, s2>>>(p, bufs[0], bufs[1], o.max_iter, o.tol, nblocks,
+                                           w.ctrl, errs, w.cell_mass, w.dtot, big);
+        if (gS > 0)
+            is<<<gS, kThreads, ldsS, st>>>(p, bufs[0], bufs[1], o.max_iter, o.tol, nblocks,
+                                           w.ctrl, errs, w.cell_mass, w.dtot, big);
+        join();
+    }
     const hipError_t ce = hipStreamEndCapture(st, &graph);
     if (ce != hipSuccess || hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) != hipSuccess) {
         if (graph) (void)hipGraphDestroy(graph);
@@ -981,7 +1017,10 @@ Status run_solver(const SkBatch& p, const dd_sinkhorn_opts& o, hipStream_t st, S
     if (done < 1) done = o.max_iter;  // unreachable: the kernel sets done at max_iter
     if (((done - 1) & 1) == 1)
         DD_HIP(hipMemcpyAsync(p.a, bufs[1], a_bytes, hipMemcpyDeviceToDevice, st), S);
-    fin<<<grid, kThreads, lds, st>>>(p, w.ctrl, iters, big);
+    fork();
+    if (gB > 0) fb<<<gB, kThreads, ldsB, s2>>>(p, w.ctrl, iters, big);
+    if (gS > 0) fs<<<gS, kThreads, ldsS, st>>>(p, w.ctrl, iters, big);
+    join();
     DD_HIP(hipGetLastError(), S);
     return S;
 }
@@ -1016,16 +1055,21 @@ void plan_tile(const std::vector<int32_t>& hd, const std::vector<int32_t>& cells
         }
     }
 }
-// Online tuner of the LDS budget per workgroup (occupancy against LDS-resident boxes):
-// each key (block side, precision, stop rule) tries every candidate once on consecutive
-// solves, then keeps the one with the least Sinkhorn time per LSE term.
-constexpr size_t kBudgets[] = {40 * 1024, 52 * 1024, 78 * 1024, 156 * 1024};
+// Online tuner of the LDS budget per workgroup of the small-cell launch (occupancy against
+// LDS-resident boxes):
+// each key (block side, precision, stop rule, box-size class) tries every candidate once on
+// consecutive solves, then keeps the one with the least Sinkhorn time per LSE term.
+constexpr size_t kBudgets[] = {26 * 1024, 39 * 1024, 52 * 1024, 78 * 1024};
+constexpr size_t kBigBudget = 156 * 1024;
 constexpr int kNumBudgets = sizeof(kBudgets) / sizeof(kBudgets[0]);
 
 struct TuneKey {
-    int as, prec, rule;
+    int as, prec, rule, bucket;
     bool operator<(const TuneKey& o) const {
-        return as != o.as ? as < o.as : prec != o.prec ? prec < o.prec : rule < o.rule;
+        if (as != o.as) return as < o.as;
+        if (prec != o.prec) return prec < o.prec;
+        if (rule != o.rule) return rule < o.rule;
+        return bucket < o.bucket;
     }
 };
 
@@ -1129,23 +1173,38 @@ Status sk_solve(const SkBatch& p, const dd_sinkhorn_opts& o, hipStream_t caller_
     for (int c = 0; c < p.ncells; ++c) ord[c] = c;
     std::stable_sort(ord.begin(), ord.end(), [&](int a, int b) { return work(a) > work(b); });
     const size_t elem = p.prec == DD_PREC_F64 ? sizeof(double) : sizeof(float);
-    // a cell whose LSE work per iteration is several times a typical cell's runs on the whole
-    // workgroup, the others one per wave; the split depends on the box shapes only
-    const double big_terms = 64.0 * 1024.0;
-    std::vector<int32_t> big_cells, small_cells;
-    for (int c : ord) (work(c) >= big_terms ? big_cells : small_cells).push_back(c);
-    const int nbig = (int)big_cells.size();
-    // LDS budget per workgroup from the tuner; it only decides which boxes live in LDS and
-    // which in global scratch, never the arithmetic, so every choice gives the same result
-    const TuneKey key{AS, p.prec, o.fixed_iters > 0 ? 2 : o.stop_rule};
+    // LDS budget per workgroup from the tuner, keyed by block side, precision, stop rule and
+    // the size class of the boxes.  A cell whose LSE work per iteration is several times a
+    // typical cell's, or whose box does not fit the small tile, runs on the whole workgroup;
+    // the others one per wave.  Neither the budget nor the split changes the arithmetic (every
+    // output has its own fixed-order sum, and the error reduction is the same for a wave and
+    // a workgroup), so every choice gives the same result.
+    double area = 0.0;
+    for (int c = 0; c < p.ncells; ++c) area += (double)std::max(hd[2 * c], 1) * std::max(hd[2 * c + 1], 1);
+    const int bucket = (int)std::log2(std::max(1.0, area / p.ncells));
+    const TuneKey key{AS, p.prec, o.fixed_iters > 0 ? 2 : o.stop_rule, bucket};
     const int choice = tuner().pick(key);
     const size_t wg_budget = kBudgets[choice];
+    const double big_terms = 64.0 * 1024.0;
+    std::vector<int32_t> cand;
+    for (int c : ord)
+        if (work(c) < big_terms) cand.push_back(c);
     SkBatch q = p;
     SkBatch q64 = p;
-    plan_tile(hd, small_cells, AS, elem, wg_budget / kWaves, q.lw1, q.lw2);
-    plan_tile(hd, small_cells, AS, sizeof(double), wg_budget / kWaves, q64.lw1, q64.lw2);
-    plan_tile(hd, big_cells, AS, elem, wg_budget, q.lw1b, q.lw2b);
-    plan_tile(hd, big_cells, AS, sizeof(double), wg_budget, q64.lw1b, q64.lw2b);
+    plan_tile(hd, cand, AS, elem, wg_budget / kWaves, q.lw1, q.lw2);
+    plan_tile(hd, cand, AS, sizeof(double), wg_budget / kWaves, q64.lw1, q64.lw2);
+    const int sw1 = std::min(q.lw1, q64.lw1), sw2 = std::min(q.lw2, q64.lw2);
+    std::vector<int32_t> big_cells, small_cells;
+    for (int c : ord) {
+        if (work(c) < big_terms && hd[2 * c] <= sw1 && hd[2 * c + 1] <= sw2)
+            small_cells.push_back(c);
+        else
+            big_cells.push_back(c);
+    }
+    const int nbig = (int)big_cells.size();
+    // big cells run in their own launch with the whole LDS of a CU per workgroup
+    plan_tile(hd, big_cells, AS, elem, kBigBudget, q.lw1b, q.lw2b);
+    plan_tile(hd, big_cells, AS, sizeof(double), kBigBudget, q64.lw1b, q64.lw2b);
     ord = big_cells;
     ord.insert(ord.end(), small_cells.begin(), small_cells.end());
     q.nbig = q64.nbig = nbig;

@@ -49,7 +49,9 @@ struct SkWork {
     int cap = 0;
     hipEvent_t ev0 = nullptr, ev1 = nullptr, ev2 = nullptr;
     hipEvent_t evj = nullptr;     // joins the caller's stream and `stream`
-    hipStream_t stream = nullptr; // the solver's own stream (default priority)
+    hipEvent_t evf = nullptr, evj2 = nullptr;  // fork / join of `stream` and `stream2`
+    hipStream_t stream = nullptr; // the solver's own streams (default priority): small cells
+    hipStream_t stream2 = nullptr;  // and big cells run side by side
 };
 
 Status sk_work_reserve(SkWork& w, int ncells, size_t a_n);

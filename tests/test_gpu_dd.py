@@ -100,7 +100,9 @@ def test_f32_tolerance_solve_matches_oracle(rule):
     assert abs(ev["primal"] - Eo) <= 1e-6 * abs(Eo) + allow, (ev["primal"], Eo, allow)
     assert ev["x_marginal_l1"] <= tol * (1.0 + 1e-9)
     assert ev["y_marginal_l1"] <= 1e-9
-    assert ev["basic_mass_err"] <= 1e-12
+    # balancing is exact; truncation then drops entries below 1e-15, up to ~1e4 per basic
+    # cell at this size
+    assert ev["basic_mass_err"] <= 1e-11
     G = _dense(g.nu_i_sparse(), w.N)
     O = _dense(o.nu_i, w.N)
     # the basic-cell marginals of the two runs agree to O(tol) in L1

@@ -124,11 +124,15 @@ def test_training_reduces_loss():
     _need_gpu()
     print("net training", flush=True)
     p = _params(9)
-    x, t, w = _inputs(128, 17)
+    x, _, w = _inputs(128, 17)
+    # a learnable target: a smooth function of the first input channel
+    k = np.ones((5, 5)) / 25.0
+    from scipy.signal import convolve2d
+    t = np.stack([3.0 * convolve2d(xi[0], k, mode="same") for xi in x]).astype(np.float32)
     xs, ts, ws = (torch.from_numpy(a).cuda() for a in (x, t, w))
     net = dd.WarmStartNet(p)
-    losses = [net.train_step(xs, ts, ws, 3e-3) for _ in range(40)]
-    assert losses[-1] < 0.7 * losses[0], losses
+    losses = [net.train_step(xs, ts, ws, 3e-3) for _ in range(150)]
+    assert losses[-1] < 0.5 * losses[0], losses[::10]
     net.close()
 
 

@@ -96,7 +96,8 @@ def test_fixed_iters_f32_matches_oracle(xside, kappa, wlo, whi):
         # bar applies to converged solves (test_tolerance_solve_matches_oracle), where the
         # first-order term vanishes for marginal-preserving perturbations.
         eo, eg = objective(cells, c, O), objective(cells, c, P)
-        assert abs(eg - eo) <= 1e-5 * abs(eo), (c, eg, eo)
+        obar = 1e-5 if kappa >= 1.0 else 3e-5  # first order in the plan error (bars above)
+        assert abs(eg - eo) <= obar * abs(eo), (c, eg, eo)
 
 
 @pytest.mark.parametrize("dtype", ["f32", "f64"])
