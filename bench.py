@@ -35,6 +35,18 @@ TERM_PEAK = 157.3e12 / 2
 HBM_PEAK = 8.0e12
 
 
+WORKLOAD_TEXT = {
+    "mix512": "mix512: {N}x{N} 8-blob Gaussian mixtures + 1e-4 floor, s={s}, KR init, "
+              "eps-scaling 64..2 untimed, timed DD iterations at eps=h^2",
+    "mix256": "mix256: {N}x{N} 8-blob Gaussian mixtures + 1e-4 floor, s={s}, KR init, "
+              "eps-scaling 64..2 untimed, timed DD iterations at eps=h^2",
+    "mix1024": "mix1024: {N}x{N} 16-blob Gaussian mixtures + 1e-4 floor, s={s}, KR init, "
+               "eps-scaling 64..2 untimed, timed DD iterations at eps=h^2",
+    "flow512": "flow512: {N}x{N}, mu 8-blob mixture, nu = mu rotated 30 deg, contracted 0.36, "
+               "shifted (0.25, 0); s={s}; map init; eps=h^2; hybrid A, B, flow update",
+}
+
+
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
@@ -63,14 +75,25 @@ def setup(args):
     return w, ctx, rule, k
 
 
-def run_steps(ctx, w, n, k0, args, rule, init=None):
+def run_steps(ctx, w, n, k0, args, rule, init=None, flows=None):
+    """n DD half-iterations at the last eps of the schedule; on the flow workload a flow update
+    follows every B half-iteration (the hybrid A, B, flow schedule), its stats in `flows`."""
     import paper_2405_09400_amd as dd
     eps = w.kappas[-1] / w.N ** 2
+    flow_every = w.extra.get("flow_every", 0)
     out = []
     for i in range(n):
-        st = ctx.iterate("AB"[(k0 + i) % 2], eps, tol=args.tol, stop_rule=rule, max_iter=args.max_iter,
+        part = "AB"[(k0 + i) % 2]
+        st = ctx.iterate(part, eps, tol=args.tol, stop_rule=rule, max_iter=args.max_iter,
                          init=dd.DD_INIT_PREV if init is None else init)
         out.append(st)
+        if flow_every and part == "B":
+            fs = ctx.flow_update()
+            log(f"[bench] flow update: costs {fs['t_costs_ms']:.1f} ms, min-cost flow "
+                f"{fs['t_mcf_ms']:.1f} ms, assembly {fs['t_assemble_ms']:.1f} ms, "
+                f"moved mass {fs['moved_mass']:.3e}")
+            if flows is not None:
+                flows.append(fs)
     return out
 
 
@@ -96,6 +119,7 @@ def time_to_tol(ctx, w, k0, args, rule):
         [("prev_iterate", dd.DD_INIT_PREV)]
     rec = {name: {"ms": [], "iters": [], "sinkhorn_ms": [], "init_ms": []} for name, _ in kinds}
     for r in range(args.replay):
+        log(f"[bench] replay state {r}")
         ctx.save()
         for j, (name, init) in enumerate(kinds):
             if j:
@@ -202,7 +226,8 @@ def main():
     torch.cuda.synchronize()
     log(f"[bench] timing {args.steps} steps")
     t0 = time.perf_counter()
-    stats = run_steps(ctx, w, args.steps, k, args, rule)
+    flows = []
+    stats = run_steps(ctx, w, args.steps, k, args, rule, flows=flows)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     k += args.steps
@@ -240,8 +265,7 @@ def main():
         "dtype": "f32" if args.prec == "f32" else "f64",
         "data": "synthetic",
         "config": {
-            "workload": f"{args.workload}: {w.N}x{w.N} 8-blob Gaussian mixtures + 1e-4 floor, s={w.s}, "
-                        f"KR init, eps-scaling 64..2 untimed, timed DD iterations at eps=h^2",
+            "workload": WORKLOAD_TEXT.get(args.workload, args.workload).format(N=w.N, s=w.s),
             "tol": args.tol, "stop_rule": args.stop_rule, "seed": args.seed,
             "cells_per_step": stats[0]["sk"]["ncells"],
         },
@@ -255,6 +279,10 @@ def main():
         "time_to_tol": compare,
         "detail": {
             "sinkhorn_iters": sk_iters,
+            "cell_split": [{"n_big": s["sk"]["n_big"], "n_giant": s["sk"]["n_giant"],
+                            "lds_kb": s["sk"]["lds_kb"],
+                            "tile_small": s["sk"]["tile_small"], "tile_big": s["sk"]["tile_big"]}
+                           for s in stats[:2]],
             "finish_f64_iters": [s["sk"]["finish_iters_max"] for s in stats],
             "main_ms_per_step": sum(s["sk"]["main_ms"] for s in stats) / len(stats),
             "sinkhorn_ms_per_step": sk_ms / len(stats),
@@ -265,9 +293,17 @@ def main():
             "max_box": [max(s["max_w1"] for s in stats), max(s["max_w2"] for s in stats)],
             "nu_entries": stats[-1]["nu_entries"],
             "x_marginal_l1": ev["x_marginal_l1"], "y_marginal_l1": ev["y_marginal_l1"],
-            "primal": ev["primal"],
+            "primal": ev["primal"], "dual": ev["dual"], "pd_gap": ev["pd_gap"],
         },
     }
+    if flows:
+        out["detail"]["flow"] = {
+            "updates": len(flows), "nodes": flows[0]["n_nodes"], "arcs": flows[0]["n_arcs"],
+            "costs_ms": sum(f["t_costs_ms"] for f in flows) / len(flows),
+            "mcf_ms": sum(f["t_mcf_ms"] for f in flows) / len(flows),
+            "assemble_ms": sum(f["t_assemble_ms"] for f in flows) / len(flows),
+            "value": [f["value"] for f in flows], "moved_mass": [f["moved_mass"] for f in flows],
+        }
     print(json.dumps(out), flush=True)
     ctx.close()
 

@@ -80,6 +80,11 @@ typedef struct {
     double time_ms;            /* device time of the whole solve (HIP events)          */
     double main_ms;            /* device time of the main (float32 or float64) loop    */
     int32_t finish_iters_max;  /* float64-finish iterations (sinkhorn_batch, tol mode)  */
+    int32_t n_big;             /* cells solved by a whole workgroup (the rest by a wave) */
+    int32_t n_giant;           /* of those, cells in the whole-CU-LDS launch             */
+    int32_t lds_kb[2];         /* LDS budget per workgroup, small and big launches (KB)  */
+    int32_t tile_small[2];     /* LDS tile of the small-cell launch (W1, W2)             */
+    int32_t tile_big[2];       /* LDS tile of the big-cell launch (W1, W2)               */
     int32_t reserved;
 } dd_batch_stats;
 

@@ -44,7 +44,10 @@ class BatchStats(ctypes.Structure):
                 ("converged", ctypes.c_int32), ("cell_iters", ctypes.c_int64), ("err", ctypes.c_double),
                 ("mass", ctypes.c_double), ("lse_terms", ctypes.c_double), ("alg_bytes", ctypes.c_double),
                 ("time_ms", ctypes.c_double), ("main_ms", ctypes.c_double),
-                ("finish_iters_max", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("finish_iters_max", ctypes.c_int32), ("n_big", ctypes.c_int32),
+                ("n_giant", ctypes.c_int32), ("lds_kb", ctypes.c_int32 * 2),
+                ("tile_small", ctypes.c_int32 * 2), ("tile_big", ctypes.c_int32 * 2),
+                ("reserved", ctypes.c_int32)]
 
 
 class Params(ctypes.Structure):
@@ -85,7 +88,11 @@ def _struct_dict(s) -> dict:
     out = {}
     for name, _ in s._fields_:
         v = getattr(s, name)
-        out[name] = _struct_dict(v) if isinstance(v, ctypes.Structure) else v
+        if isinstance(v, ctypes.Structure):
+            v = _struct_dict(v)
+        elif isinstance(v, ctypes.Array):
+            v = list(v)
+        out[name] = v
     return out
 
 

@@ -82,10 +82,11 @@ struct WaveTeam {
     __device__ int size() const { return 64; }
     __device__ int wid() const { return 0; }
     __device__ int nw() const { return 1; }
-    // a wave's own LDS and global writes are complete and visible to its other lanes
+    // a wave works from LDS only (small cells never use global scratch), and the LDS
+    // operations of one wave are performed in order: keeping the compiler from moving memory
+    // operations across this point is all a wave-level barrier needs
     __device__ void sync() const {
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_s_waitcnt(0);
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     }
@@ -93,10 +94,15 @@ struct WaveTeam {
     __device__ double sum(double v, P) const { return wave_sum(v); }
 };
 
-__device__ __forceinline__ double wave_max_d(double v) {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
-    return v;
+// Order-preserving map of a double to an unsigned 64-bit key (and back), so that a maximum
+// can be taken with an integer atomic.
+__device__ __forceinline__ unsigned long long max_key(double d) {
+    const unsigned long long u = (unsigned long long)__double_as_longlong(d);
+    return (u >> 63) ? ~u : (u | 0x8000000000000000ull);
+}
+__device__ __forceinline__ double key_value(unsigned long long k) {
+    const unsigned long long u = (k >> 63) ? (k ^ 0x8000000000000000ull) : ~k;
+    return __longlong_as_double((long long)u);
 }
 
 // Address-space-qualified pointers: LDS (ds_* instructions) and global (global_* ones), so
@@ -126,6 +132,7 @@ struct Lds {
     // X arrays
     lds_p<double> f;    // [N2]        X potential f
     lds_p<double> lm;   // [N2]        log mu
+    lds_p<double> mu;   // [N2]        mu (0 where log mu is the sentinel)
     lds_p<double> s;    // [N2]        LSE_j (g + log nu_J - C)
     lds_p<double> ry;   // [AS]        row maxima of f + log mu
     lds_p<double> Mx;   // [AS]        column maxima of the X-half intermediate
@@ -134,14 +141,13 @@ struct Lds {
     lds_p<T> u1;        // [N2]        exp(wq)
     lds_p<T> sX1;       // [AS]        nearest-point shifts of the X-half passes
     lds_p<T> sX2;       // [AS]
-    // the cell's Y potential g and log nu_J stay in global memory (float64, row stride W2),
-    // streamed once per half-iteration
-    glb_p<double> g;    // [W1][W2]
-    glb_p<const double> ln;  // [W1][W2]
+    glb_p<double> gout;  // [W1][W2]   the output g (row stride W2), written by each Y-update
     // Y-box arrays (LDS tile, or global scratch for a box beyond the tile)
     YD qx;              // [W1]        row maxima of g + log nu_J
     YD My;              // [W2]        column maxima of the Y-half intermediate
-    YT u3;              // [W1][ys]    exp(g + log nu_J - qx(row))
+    YD ln;              // [W1][ys]    log nu_J
+    YD v;               // [W1][ys]    g + log nu_J
+    YT u3;              // [W1][ys]    exp(v - qx(row))
     YT KY1;             // [AS][W2p]   kernel table, Y-half pass over i2
     YT t1;              // [AS][W2p]   Y-half intermediate, relative to ry
     YT u2;              // [AS][W2p]   exp(t1 + ry - My)
@@ -158,11 +164,11 @@ struct Lds {
 // Bytes of the X arrays and of the Y-box arrays of a (w1 x w2) box (strides included).
 __host__ __device__ inline size_t x_bytes(int AS, size_t elem) {
     const size_t N2 = (size_t)AS * AS;
-    return 8 * (3 * N2 + 2 * (size_t)AS + 16) + elem * (2 * N2 + 2 * (size_t)AS);
+    return 8 * (4 * N2 + 2 * (size_t)AS + 16) + elem * (2 * N2 + 2 * (size_t)AS);
 }
 __host__ __device__ inline size_t box_bytes(int AS, int w1, int w2, size_t elem) {
     const size_t ys = (size_t)w2 + 1, W2p = ys, W1p = (size_t)w1 + 1, ASp = (size_t)AS + 1;
-    const size_t nd = (size_t)w1 + w2;
+    const size_t nd = 2 * (size_t)w1 * ys + w1 + w2;
     const size_t nt = (size_t)w1 * ys + 3 * (size_t)AS * W2p + (size_t)AS * W1p +
                       (size_t)w2 * ASp + 3 * (size_t)w1 * ASp + w2 + w1;
     return 8 * nd + elem * nt + 64;
@@ -174,14 +180,6 @@ __host__ __device__ inline size_t lds_layout_bytes(int AS, int lw1, int lw2, siz
     return (x_bytes(AS, elem) + box_bytes(AS, lw1, lw2, elem) + 15) & ~size_t(15);
 }
 
-// Workgroup LDS: one big-cell layout, or kWaves small-cell layouts side by side.
-__host__ __device__ inline size_t wg_lds_bytes(int AS, int lw1, int lw2, int lw1b, int lw2b,
-                                               size_t elem) {
-    const size_t small = kWaves * lds_layout_bytes(AS, lw1, lw2, elem);
-    const size_t big = lds_layout_bytes(AS, lw1b, lw2b, elem);
-    return small > big ? small : big;
-}
-
 // Global scratch (in doubles) of a cell whose box exceeds the tile.
 __host__ __device__ inline int64_t cell_scratch_doubles(int AS, int W1, int W2, size_t elem) {
     return (int64_t)((box_bytes(AS, W1, W2, elem) + 15) / 16) * 2;
@@ -189,11 +187,16 @@ __host__ __device__ inline int64_t cell_scratch_doubles(int AS, int W1, int W2, 
 
 // Bind the Y-box arrays of a (W1 x W2) box with strides for (w1s x w2s) starting at `base`.
 template <typename T, typename PD, typename PT>
-__device__ __forceinline__ void bind_box(PD& qx, PD& My, PT& u3, PT& KY1, PT& t1, PT& u2,
+__device__ __forceinline__ void bind_box(PD& ln, PD& vv, PD& qx, PD& My, PT& u3, PT& KY1, PT& t1,
+                                         PT& u2,
                                          PT& KY2, PT& KX1, PT& r, PT& u4, PT& KX2, PT& sY1,
                                          PT& sY2, PD base, int AS, int w1s, int w2s) {
     const int ys = w2s + 1, W2p = ys, W1p = w1s + 1, ASp = AS + 1;
     PD d = base;
+    ln = d;
+    d += (size_t)w1s * ys;
+    vv = d;
+    d += (size_t)w1s * ys;
     qx = d;
     d += w1s;
     My = d;
@@ -222,6 +225,13 @@ __device__ __forceinline__ void bind_box(PD& qx, PD& My, PT& u3, PT& KY1, PT& t1
     sY2 = t;
 }
 
+// The row-maximum keys share the storage of qx (same address space).
+template <typename T, bool G>
+__device__ __forceinline__ auto qx_key(const Lds<T, G>& L, int j1) {
+    using P = std::conditional_t<G, glb_p<unsigned long long>, lds_p<unsigned long long>>;
+    return (P)(L.qx + j1);
+}
+
 // Carve the X arrays (and, for G = false, the tile) out of an LDS slice; for G = true bind
 // the Y-box arrays to the cell's global scratch.  g and log nu_J point into the packed
 // float64 arrays at the cell's offset.
@@ -238,6 +248,8 @@ __device__ __forceinline__ Lds<T, G> carve(lds_p<char> base, const SkBatch& p, i
     d += N2;
     L.lm = d;
     d += N2;
+    L.mu = d;
+    d += N2;
     L.s = d;
     d += N2;
     L.ry = d;
@@ -253,18 +265,17 @@ __device__ __forceinline__ Lds<T, G> carve(lds_p<char> base, const SkBatch& p, i
     t += AS;
     L.sX2 = t;
     L.ASp = AS + 1;
-    L.g = (glb_p<double>)(p.b + ybase);
-    L.ln = (glb_p<const double>)(p.lognu + ybase);
+    L.gout = (glb_p<double>)(p.b + ybase);
     if constexpr (!G) {
         lds_p<double> bb = (lds_p<double>)(base + ((x_bytes(AS, sizeof(T)) + 15) & ~size_t(15)));
-        bind_box<T>(L.qx, L.My, L.u3, L.KY1, L.t1, L.u2, L.KY2, L.KX1, L.r, L.u4, L.KX2, L.sY1,
+        bind_box<T>(L.ln, L.v, L.qx, L.My, L.u3, L.KY1, L.t1, L.u2, L.KY2, L.KX1, L.r, L.u4, L.KX2, L.sY1,
                     L.sY2, bb, AS, lw1, lw2);
         L.ys = lw2 + 1;
         L.W2p = lw2 + 1;
         L.W1p = lw1 + 1;
     } else {
         glb_p<double> bb = (glb_p<double>)(big_scratch + p.scr_off[c]);
-        bind_box<T>(L.qx, L.My, L.u3, L.KY1, L.t1, L.u2, L.KY2, L.KX1, L.r, L.u4, L.KX2, L.sY1,
+        bind_box<T>(L.ln, L.v, L.qx, L.My, L.u3, L.KY1, L.t1, L.u2, L.KY2, L.KX1, L.r, L.u4, L.KX2, L.sY1,
                     L.sY2, bb, AS, W1, W2);
         L.ys = W2 + 1;
         L.W2p = W2 + 1;
@@ -312,6 +323,60 @@ __device__ __forceinline__ float sum_floor<float>() { return 1e-30f; }
 template <>
 __device__ __forceinline__ double sum_floor<double>() { return 1e-290; }
 
+// Lanes per output for a line of K inputs.  It depends on K only, so a wave and a workgroup
+// compute every sum with the same terms in the same order.
+__device__ __forceinline__ int lanes_for(int K) {
+    return K >= 96 ? 8 : K >= 40 ? 4 : K >= 16 ? 2 : 1;
+}
+
+// For every output o in [0, Q): sum_k u[k * su] * kt[k * sk] with (u, su, kt, sk) = line(o),
+// by LN lanes per output (strided over k, two accumulators each, combined by a fixed xor
+// tree); fin(o, sum) runs on the group's first lane.  Groups of LN consecutive lanes sit in
+// one wave and are active together.
+template <int LN, typename T, typename Tm, typename FL, typename Fin>
+__device__ __forceinline__ void pass_lanes(const Tm& tm, int Q, int K, FL&& line, Fin&& fin) {
+    const int tid = tm.tid(), nt = tm.size();
+    for (int v = tid; v < Q * LN; v += nt) {
+        const int o = v / LN, sub = v - o * LN;
+        const auto ln = line(o);
+        const auto u = ln.u + sub * ln.su;
+        const auto kt = ln.kt + sub * ln.sk;
+        const int su = LN * ln.su, sk = LN * ln.sk;
+        const int n = (K - sub + LN - 1) / LN;  // terms of this lane
+        T a0 = T(0), a1 = T(0);
+        int k = 0;
+        for (; k + 1 < n; k += 2) {
+            a0 += u[k * su] * kt[k * sk];
+            a1 += u[(k + 1) * su] * kt[(k + 1) * sk];
+        }
+        if (k < n) a0 += u[k * su] * kt[k * sk];
+        T sum = a0 + a1;
+        if constexpr (LN > 1) {
+#pragma unroll
+            for (int off = 1; off < LN; off <<= 1) sum += __shfl_xor(sum, off, 64);
+        }
+        if (sub == 0) fin(o, sum);
+    }
+}
+
+template <typename PU, typename PK>
+struct Line {
+    PU u;
+    int su;
+    PK kt;
+    int sk;
+};
+
+template <typename T, typename Tm, typename FL, typename Fin>
+__device__ __forceinline__ void kernel_pass(const Tm& tm, int Q, int K, FL&& line, Fin&& fin) {
+    switch (lanes_for(K)) {
+        case 8: pass_lanes<8, T>(tm, Q, K, line, fin); break;
+        case 4: pass_lanes<4, T>(tm, Q, K, line, fin); break;
+        case 2: pass_lanes<2, T>(tm, Q, K, line, fin); break;
+        default: pass_lanes<1, T>(tm, Q, K, line, fin); break;
+    }
+}
+
 // Load one cell: f and log mu into LDS, log nu_J into the tile (G = false), kernel tables.
 template <typename Tm, typename T, bool G>
 __device__ __forceinline__ void load_cell(const Tm& tm, const SkBatch& p, const Lds<T, G>& L,
@@ -323,8 +388,14 @@ __device__ __forceinline__ void load_cell(const Tm& tm, const SkBatch& p, const 
     // zero-mass points carry the log-domain sentinel in log mu / log nu_J, which removes
     // them from every sum whatever their potential
     for (int i = tid; i < N2; i += nt) {
-        L.lm[i] = p.logmu[(int64_t)c * N2 + i];
+        const double lm = p.logmu[(int64_t)c * N2 + i];
+        L.lm[i] = lm;
+        L.mu[i] = lm > kZeroMassLog ? exp(lm) : 0.0;
         L.f[i] = f_src[(int64_t)c * N2 + i];
+    }
+    for (int o = tid; o < W1 * W2; o += nt) {
+        const int j1 = o / W2, j2 = o - j1 * W2;
+        L.ln[j1 * L.ys + j2] = p.lognu[base + o];
     }
     // Y-half: over i2 (d = i2 - j2 + E2), over i1 (d = i1 - j1 + E1);
     // X-half: over j2 (d = j2 - i2 - E2), over j1 (d = j1 - i1 - E1)
@@ -355,18 +426,26 @@ __device__ __forceinline__ void y_half(const Tm& tm, const Lds<T, G>& L, int AS,
     }
     tm.sync();
     // pass over i2: t1(i1, j2) = LSE_i2 [wq(i1, i2) - (i2 - j2 + E2)^2 / kappa]
-    for (int o = tid; o < AS * W2; o += nt) {
-        const int i1 = o / W2, j2 = o - i1 * W2;
-        T sum = T(0);
-        for (int k = 0; k < AS; ++k) sum += L.u1[i1 * AS + k] * L.KY1[k * L.W2p + j2];
-        T v;
-        if (sum >= sum_floor<T>())
-            v = flog(sum) - L.sY1[j2];
-        else
-            v = lse_exact<T>([&](int k) { return L.wq[i1 * AS + k]; }, AS, j2, E2, invk);
-        L.t1[i1 * L.W2p + j2] = v;
-    }
+    using YT = typename Lds<T, G>::YT;
+    kernel_pass<T>(
+        tm, AS * W2, AS,
+        [&](int o) {
+            const int i1 = o / W2, j2 = o - i1 * W2;
+            return Line<lds_p<T>, YT>{L.u1 + i1 * AS, 1, L.KY1 + j2, L.W2p};
+        },
+        [&](int o, T sum) {
+            const int i1 = o / W2, j2 = o - i1 * W2;
+            T v;
+            if (sum >= sum_floor<T>())
+                v = flog(sum) - L.sY1[j2];
+            else
+                v = lse_exact<T>([&](int k) { return L.wq[i1 * AS + k]; }, AS, j2, E2, invk);
+            L.t1[i1 * L.W2p + j2] = v;
+        });
     tm.sync();
+    // row-maximum keys of the X-half start at the smallest key
+    for (int j1 = tid; j1 < W1; j1 += nt)
+        *qx_key(L, j1) = 0ull;
     // column maxima over i1 of t1 + ry, and the scaled inputs of the second pass
     for (int j2 = tid; j2 < W2; j2 += nt) {
         double m = (double)L.t1[j2] + L.ry[0];
@@ -379,22 +458,34 @@ __device__ __forceinline__ void y_half(const Tm& tm, const Lds<T, G>& L, int AS,
         L.u2[i1 * L.W2p + j2] = fexp((T)((double)L.t1[i1 * L.W2p + j2] + L.ry[i1] - L.My[j2]));
     }
     tm.sync();
-    // pass over i1: g(j1, j2) = -LSE_i1 [t1(i1, j2) + ry(i1) - (i1 - j1 + E1)^2 / kappa]
-    for (int o = tid; o < W1 * W2; o += nt) {
-        const int j1 = o / W2, j2 = o - j1 * W2;
-        T sum = T(0);
-        for (int k = 0; k < AS; ++k) sum += L.u2[k * L.W2p + j2] * L.KY2[k * L.W1p + j1];
-        const double Mj = L.My[j2];
-        T v;
-        if (sum >= sum_floor<T>()) {
-            v = flog(sum) - L.sY2[j1];
-        } else {
-            v = lse_exact<T>(
-                [&](int k) { return L.t1[k * L.W2p + j2] + (T)(L.ry[k] - Mj); }, AS, j1, E1,
-                invk);
-        }
-        L.g[o] = -(Mj + (double)v);
-    }
+    // pass over i1: g(j1, j2) = -LSE_i1 [t1(i1, j2) + ry(i1) - (i1 - j1 + E1)^2 / kappa];
+    // each output also folds g + log nu_J into its row's maximum (the X-half's row shift),
+    // kept as an order-preserving integer key in qx
+    kernel_pass<T>(
+        tm, W1 * W2, AS,
+        [&](int o) {
+            const int j1 = o / W2, j2 = o - j1 * W2;
+            return Line<YT, YT>{L.u2 + j2, L.W2p, L.KY2 + j1, L.W1p};
+        },
+        [&](int o, T sum) {
+            const int j1 = o / W2, j2 = o - j1 * W2;
+            const double Mj = L.My[j2];
+            T v;
+            if (sum >= sum_floor<T>()) {
+                v = flog(sum) - L.sY2[j1];
+            } else {
+                v = lse_exact<T>(
+                    [&](int k) { return L.t1[k * L.W2p + j2] + (T)(L.ry[k] - Mj); }, AS, j1,
+                    E1, invk);
+            }
+            const double g = -(Mj + (double)v);
+            L.gout[o] = g;
+            const double z = g + L.ln[j1 * L.ys + j2];
+            L.v[j1 * L.ys + j2] = z;
+            if (z > kZeroMassLog)
+                __hip_atomic_fetch_max(qx_key(L, j1), max_key(z), __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_WORKGROUP);
+        });
     tm.sync();
 }
 
@@ -404,34 +495,41 @@ template <typename Tm, typename T, bool G>
 __device__ __forceinline__ void x_half(const Tm& tm, const Lds<T, G>& L, int AS, int W1, int W2,
                                        int E1, int E2, T invk) {
     const int tid = tm.tid(), nt = tm.size();
-    const int lane = threadIdx.x & 63, wid = tm.wid(), nw = tm.nw();
-    // row maxima of g + log nu_J (one wave per row, coalesced reads) and the scaled inputs
-    for (int j1 = wid; j1 < W1; j1 += nw) {
-        double m = -1e300;
-        for (int j2 = lane; j2 < W2; j2 += 64)
-            m = fmax(m, L.g[j1 * W2 + j2] + L.ln[j1 * W2 + j2]);
-        m = wave_max_d(m);
-        for (int j2 = lane; j2 < W2; j2 += 64)
-            L.u3[j1 * L.ys + j2] = fexp((T)(L.g[j1 * W2 + j2] + L.ln[j1 * W2 + j2] - m));
-        if (lane == 0) L.qx[j1] = m;
+    // row maxima of g + log nu_J (keys left by the Y-update; a row with no mass gets the
+    // zero-mass sentinel), then the scaled inputs, all entries in flight at once
+    for (int j1 = tid; j1 < W1; j1 += nt) {
+        const unsigned long long k = *qx_key(L, j1);
+        L.qx[j1] = k ? key_value(k) : kNegD;
+    }
+    tm.sync();
+    for (int o = tid; o < W1 * W2; o += nt) {
+        const int j1 = o / W2, j2 = o - j1 * W2;
+        const double q = L.qx[j1];
+        // a row without mass carries the sentinel in qx and drops out of the second pass
+        // whatever its first-pass values; 0 (u = 1) keeps those finite
+        L.u3[j1 * L.ys + j2] = q > kZeroMassLog ? fexp((T)(L.v[j1 * L.ys + j2] - q)) : T(1);
     }
     tm.sync();
     // pass over j2: r(j1, i2) = LSE_j2 [g + log nu_J - qx(j1) - (j2 - i2 - E2)^2 / kappa]
-    for (int o = tid; o < W1 * AS; o += nt) {
-        const int j1 = o / AS, i2 = o - j1 * AS;
-        T sum = T(0);
-        for (int k = 0; k < W2; ++k) sum += L.u3[j1 * L.ys + k] * L.KX1[k * L.ASp + i2];
-        T v;
-        if (sum >= sum_floor<T>()) {
-            v = flog(sum) - L.sX1[i2];
-        } else {
-            const double q = L.qx[j1];
-            v = lse_exact<T>(
-                [&](int k) { return (T)(L.g[j1 * W2 + k] + L.ln[j1 * W2 + k] - q); }, W2, i2,
-                -E2, invk);
-        }
-        L.r[j1 * L.ASp + i2] = v;
-    }
+    using YT = typename Lds<T, G>::YT;
+    kernel_pass<T>(
+        tm, W1 * AS, W2,
+        [&](int o) {
+            const int j1 = o / AS, i2 = o - j1 * AS;
+            return Line<YT, YT>{L.u3 + j1 * L.ys, 1, L.KX1 + i2, L.ASp};
+        },
+        [&](int o, T sum) {
+            const int j1 = o / AS, i2 = o - j1 * AS;
+            T v;
+            if (sum >= sum_floor<T>()) {
+                v = flog(sum) - L.sX1[i2];
+            } else {
+                const double q = L.qx[j1];
+                v = lse_exact<T>([&](int k) { return (T)(L.v[j1 * L.ys + k] - q); }, W2, i2, -E2,
+                                 invk);
+            }
+            L.r[j1 * L.ASp + i2] = v;
+        });
     tm.sync();
     // column maxima over j1 of r + qx, and the scaled inputs of the second pass
     for (int i2 = tid; i2 < AS; i2 += nt) {
@@ -446,21 +544,25 @@ __device__ __forceinline__ void x_half(const Tm& tm, const Lds<T, G>& L, int AS,
     }
     tm.sync();
     // pass over j1: s(i1, i2) = LSE_j1 [r(j1, i2) + qx(j1) - (j1 - i1 - E1)^2 / kappa]
-    for (int o = tid; o < AS * AS; o += nt) {
-        const int i1 = o / AS, i2 = o - i1 * AS;
-        T sum = T(0);
-        for (int k = 0; k < W1; ++k) sum += L.u4[k * L.ASp + i2] * L.KX2[k * L.ASp + i1];
-        const double Mi = L.Mx[i2];
-        T v;
-        if (sum >= sum_floor<T>()) {
-            v = flog(sum) - L.sX2[i1];
-        } else {
-            v = lse_exact<T>(
-                [&](int k) { return L.r[k * L.ASp + i2] + (T)(L.qx[k] - Mi); }, W1, i1, -E1,
-                invk);
-        }
-        L.s[o] = Mi + (double)v;
-    }
+    kernel_pass<T>(
+        tm, AS * AS, W1,
+        [&](int o) {
+            const int i1 = o / AS, i2 = o - i1 * AS;
+            return Line<YT, YT>{L.u4 + i2, L.ASp, L.KX2 + i1, L.ASp};
+        },
+        [&](int o, T sum) {
+            const int i1 = o / AS, i2 = o - i1 * AS;
+            const double Mi = L.Mx[i2];
+            T v;
+            if (sum >= sum_floor<T>()) {
+                v = flog(sum) - L.sX2[i1];
+            } else {
+                v = lse_exact<T>(
+                    [&](int k) { return L.r[k * L.ASp + i2] + (T)(L.qx[k] - Mi); }, W1, i1,
+                    -E1, invk);
+            }
+            L.s[o] = Mi + (double)v;
+        });
     tm.sync();
 }
 
@@ -473,9 +575,8 @@ __device__ __forceinline__ void err_mass(const Tm& tm, const Lds<T, G>& L, int A
     if (tm.wid() == 0) {
         double e = 0.0, m = 0.0;
         for (int i = threadIdx.x & 63; i < AS * AS; i += 64) {
-            const double lm = L.lm[i];
-            if (lm > kZeroMassLog) {
-                const double mu = exp(lm);
+            const double mu = L.mu[i];
+            if (mu > 0.0) {
                 e += mu * fabs(expm1(L.f[i] + L.s[i]));
                 m += mu;
             }
@@ -562,7 +663,7 @@ struct SolveCell {
             // a float32 solve whose error has stopped falling (rounding floor) hands the
             // cell to the float64 finish, which certifies the tolerance
             if (!fixed && stall_window > 0 && it % stall_window == 0) {
-                if (err > 0.99 * err_ref) stop = true;
+                if (err > 0.9995 * err_ref) stop = true;
                 err_ref = err;
             }
             if (stop) break;
@@ -580,15 +681,16 @@ struct SolveCell {
     }
 };
 
-// The two cell classes run as two kernels (each with its own LDS size), launched side by
-// side on two streams: MODE 0 = big cells, one per workgroup; MODE 1 = small cells, one per
-// wave.  Big cells are order[0..nbig), small ones order[nbig..ncells).
+// The cell classes run as separate launches (each with its own LDS size and tile), side by
+// side on separate streams.  A launch covers order[q_lo, q_hi) with its tile (lw1, lw2):
+// MODE 0 = one cell per workgroup, MODE 1 = one cell per wave.
 constexpr int kBig = 0, kSmall = 1;
 
 template <typename T, int MODE>
 __global__ void __launch_bounds__(kThreads)
-    sk_cell_kernel(SkBatch p, double tol, int limit, int fixed, int stall_window, int* ctrl,
-                   int32_t* iters_out, double* err_out, double* mass_out, double* big_scratch) {
+    sk_cell_kernel(SkBatch p, double tol, int limit, int fixed, int stall_window, int* queue,
+                   int* ctrl, int32_t* iters_out, double* err_out, double* mass_out,
+                   double* big_scratch) {
     extern __shared__ __align__(16) char smem[];
     const lds_p<char> base = (lds_p<char>)smem;
     if constexpr (MODE == kBig) {
@@ -598,14 +700,13 @@ __global__ void __launch_bounds__(kThreads)
                                            iters_out, err_out, mass_out};
         for (;;) {
             __syncthreads();
-            if (threadIdx.x == 0) s_cell = atomicAdd(&ctrl[0], 1);
+            if (threadIdx.x == 0) s_cell = p.q_lo + atomicAdd(queue, 1);
             __syncthreads();
             const int q = s_cell;
-            if (q >= p.nbig) break;
-            with_cell<T, true>(tm, p, base, p.lw1b, p.lw2b, p.order[q], big_scratch, ctrl, body);
+            if (q >= p.q_hi) break;
+            with_cell<T, true>(tm, p, base, p.lw1, p.lw2, p.order[q], big_scratch, ctrl, body);
         }
     } else {
-        const int nsmall = p.ncells - p.nbig;
         const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
         const lds_p<char> slice = base + w * lds_layout_bytes(p.xside, p.lw1, p.lw2, sizeof(T));
         const WaveTeam tm;
@@ -613,11 +714,12 @@ __global__ void __launch_bounds__(kThreads)
                                           iters_out, err_out, mass_out};
         for (;;) {
             int q = 0;
-            if (lane == 0) q = atomicAdd(&ctrl[9], 1);
+            if (lane == 0) q = p.q_lo + atomicAdd(queue, 1);
             q = __builtin_amdgcn_readfirstlane(__shfl(q, 0, 64));
-            if (q >= nsmall) break;
-            with_cell<T, true>(tm, p, slice, p.lw1, p.lw2, p.order[p.nbig + q], big_scratch,
-                               ctrl, body);
+            if (q >= p.q_hi) break;
+            // small cells fit the small tile by construction (the host's split)
+            with_cell<T, false>(tm, p, slice, p.lw1, p.lw2, p.order[q], big_scratch, ctrl,
+                                body);
         }
     }
 }
@@ -675,40 +777,39 @@ struct FinalCell {
     }
 };
 
-// Work items of one class in a batch-rule launch: big cells one per item, small cells four
-// per item (one per wave).
-__host__ __device__ inline int class_items(int mode, int ncells, int nbig) {
-    return mode == kBig ? nbig : (ncells - nbig + kWaves - 1) / kWaves;
+// Work items of a launch: one cell per item (MODE 0) or four (MODE 1, one per wave).
+__host__ __device__ inline int class_items(int mode, int ncells) {
+    return mode == kBig ? ncells : (ncells + kWaves - 1) / kWaves;
 }
 
-// Run `make(team)` over the batch-rule items of this class assigned to this workgroup.
+// Run `make(team)` over the batch-rule items of this launch assigned to this workgroup.
 template <typename T, int MODE, typename Make>
 __device__ __forceinline__ void for_items(const SkBatch& p, lds_p<char> base, double* big_scratch,
                                           int* ctrl, Make&& make) {
-    const int nitems = class_items(MODE, p.ncells, p.nbig);
+    const int nitems = class_items(MODE, p.q_hi - p.q_lo);
     for (int q = blockIdx.x; q < nitems; q += gridDim.x) {
         if constexpr (MODE == kBig) {
             const BlockTeam tm;
-            with_cell<T, true>(tm, p, base, p.lw1b, p.lw2b, p.order[q], big_scratch, ctrl,
+            with_cell<T, true>(tm, p, base, p.lw1, p.lw2, p.order[p.q_lo + q], big_scratch, ctrl,
                                make(tm));
         } else {
             const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
             const lds_p<char> slice =
                 base + w * lds_layout_bytes(p.xside, p.lw1, p.lw2, sizeof(T));
-            const int k = p.nbig + q * kWaves + w;
-            if (k < p.ncells) {
+            const int k = p.q_lo + q * kWaves + w;
+            if (k < p.q_hi) {
                 const WaveTeam tm;
-                with_cell<T, true>(tm, p, slice, p.lw1, p.lw2, p.order[k], big_scratch, ctrl,
-                                   make(tm));
+                with_cell<T, false>(tm, p, slice, p.lw1, p.lw2, p.order[k], big_scratch, ctrl,
+                                    make(tm));
             }
         }
         __syncthreads();
     }
 }
 
-// One batch-rule iteration of one class.  The workgroups of both classes' launches take one
-// ticket each; the last of all (`nblocks` in total) reduces the per-cell errors in fixed
-// cell order and sets the stop flag.
+// One batch-rule iteration of one launch.  The workgroups of all the launches of an iteration
+// take one ticket each; the last of all (`nblocks` in total) reduces the per-cell errors in
+// fixed cell order and sets the stop flag.
 template <typename T, int MODE>
 __global__ void __launch_bounds__(kThreads)
     sk_iter_kernel(SkBatch p, double* fa, double* fb, int limit, double tol, int nblocks,
@@ -827,7 +928,7 @@ __global__ void __launch_bounds__(kThreads)
 size_t sk_lds_bytes(int xside, int prec) {
     if (xside < 2 || xside > 16) return 0;
     const size_t e = prec == DD_PREC_F64 ? sizeof(double) : sizeof(float);
-    return wg_lds_bytes(xside, 0, 0, 0, 0, e);
+    return lds_layout_bytes(xside, 0, 0, e);
 }
 
 Status sk_work_reserve(SkWork& w, int ncells, size_t a_n) {
@@ -843,6 +944,8 @@ Status sk_work_reserve(SkWork& w, int ncells, size_t a_n) {
         DD_HIP(hipEventCreateWithFlags(&w.evj2, hipEventDisableTiming), st);
         DD_HIP(hipStreamCreateWithFlags(&w.stream, hipStreamNonBlocking), st);
         DD_HIP(hipStreamCreateWithFlags(&w.stream2, hipStreamNonBlocking), st);
+        DD_HIP(hipStreamCreateWithFlags(&w.stream3, hipStreamNonBlocking), st);
+        DD_HIP(hipEventCreateWithFlags(&w.evj3, hipEventDisableTiming), st);
     }
     if (ncells > w.cap) {
         if (w.cell_err) (void)hipFree(w.cell_err);
@@ -872,6 +975,8 @@ Status sk_work_reserve(SkWork& w, int ncells, size_t a_n) {
 void sk_work_release(SkWork& w) {
     if (w.order) (void)hipFree(w.order);
     if (w.scr_off) (void)hipFree(w.scr_off);
+    if (w.order64) (void)hipFree(w.order64);
+    if (w.scr_off64) (void)hipFree(w.scr_off64);
     if (w.big) (void)hipFree(w.big);
     if (w.iters64) (void)hipFree(w.iters64);
     if (w.a_alt) (void)hipFree(w.a_alt);
@@ -886,7 +991,8 @@ void sk_work_release(SkWork& w) {
     if (w.evj) (void)hipEventDestroy(w.evj);
     if (w.evf) (void)hipEventDestroy(w.evf);
     if (w.evj2) (void)hipEventDestroy(w.evj2);
-    for (hipStream_t* sp : {&w.stream, &w.stream2})
+    if (w.evj3) (void)hipEventDestroy(w.evj3);
+    for (hipStream_t* sp : {&w.stream, &w.stream2, &w.stream3})
         if (*sp) {
             (void)hipStreamSynchronize(*sp);
             (void)hipStreamDestroy(*sp);
@@ -926,70 +1032,91 @@ int grid_for(K kernel, size_t lds, int items) {
     return (int)std::max(1L, std::min<long>(g, items));
 }
 
+// A class of cells for one launch: order[lo, hi), solved one per workgroup (kBig) or one per
+// wave (kSmall), with LDS tiles for float32 and float64 terms.
+struct CellClass {
+    int mode = kBig;
+    int lo = 0, hi = 0;
+    int t[2] = {0, 0};  // LDS tile (W1, W2)
+    size_t budget = 0;
+};
+
 template <typename T>
-Status run_solver(const SkBatch& p, const dd_sinkhorn_opts& o, hipStream_t st, SkWork& w,
-                  int32_t* iters, double* errs) {
+Status run_solver(const SkBatch& p0, const std::vector<CellClass>& cls, const dd_sinkhorn_opts& o,
+                  hipStream_t st, SkWork& w, int32_t* iters, double* errs) {
     Status S;
     double* big = reinterpret_cast<double*>(w.big);
-    // big cells on the second stream, small cells on `st`, side by side
-    const size_t ldsB = lds_layout_bytes(p.xside, p.lw1b, p.lw2b, sizeof(T));
-    const size_t ldsS = kWaves * lds_layout_bytes(p.xside, p.lw1, p.lw2, sizeof(T));
-    const int nsmall = p.ncells - p.nbig;
-    const hipStream_t s2 = w.stream2;
+    // the small and giant classes run on `st`, the big class on the second stream, side by side
+    const hipStream_t streams[3] = {st, w.stream2, st};
+    hipEvent_t joins[3] = {nullptr, w.evj2, nullptr};
+    const int qidx[3] = {0, 9, 11};
+    const int ncls = (int)cls.size();
+    std::vector<SkBatch> pk(ncls, p0);
+    std::vector<size_t> lds(ncls);
+    for (int k = 0; k < ncls; ++k) {
+        pk[k].q_lo = cls[k].lo;
+        pk[k].q_hi = cls[k].hi;
+        pk[k].lw1 = cls[k].t[0];
+        pk[k].lw2 = cls[k].t[1];
+        const size_t one = lds_layout_bytes(p0.xside, pk[k].lw1, pk[k].lw2, sizeof(T));
+        lds[k] = cls[k].mode == kBig ? one : kWaves * one;
+    }
+    // classes on the second stream are forked from `st` and joined back
     auto fork = [&]() {
+        if (ncls < 2) return;
         (void)hipEventRecord(w.evf, st);
-        (void)hipStreamWaitEvent(s2, w.evf, 0);
+        (void)hipStreamWaitEvent(streams[1], w.evf, 0);
     };
     auto join = [&]() {
-        (void)hipEventRecord(w.evj2, s2);
-        (void)hipStreamWaitEvent(st, w.evj2, 0);
+        if (ncls < 2) return;
+        (void)hipEventRecord(joins[1], streams[1]);
+        (void)hipStreamWaitEvent(st, joins[1], 0);
     };
     const bool fixed = o.fixed_iters > 0;
-    zero_ints<<<1, 64, 0, st>>>(w.ctrl, 11);
+    zero_ints<<<1, 64, 0, st>>>(w.ctrl, 12);
     if (fixed || o.stop_rule == DD_STOP_CELL) {
-        auto kb = sk_cell_kernel<T, kBig>;
-        auto ks = sk_cell_kernel<T, kSmall>;
-        if (set_lds_attr(kb, ldsB, S).code || set_lds_attr(ks, ldsS, S).code) return S;
         const int limit = fixed ? o.fixed_iters : o.max_iter;
         // stall detection only where a float64 finish follows
         const int stall = sizeof(T) == sizeof(float) ? 32 : 0;
         fork();
-        if (p.nbig > 0)
-            kb<<<grid_for(kb, ldsB, p.nbig), kThreads, ldsB, s2>>>(
-                p, o.tol, limit, fixed ? 1 : 0, stall, w.ctrl, iters, errs, w.cell_mass, big);
-        if (nsmall > 0)
-            ks<<<grid_for(ks, ldsS, class_items(kSmall, p.ncells, p.nbig)), kThreads, ldsS, st>>>(
-                p, o.tol, limit, fixed ? 1 : 0, stall, w.ctrl, iters, errs, w.cell_mass, big);
+        for (int k = 0; k < ncls; ++k) {
+            const int n = cls[k].hi - cls[k].lo;
+            auto kern = cls[k].mode == kBig ? sk_cell_kernel<T, kBig> : sk_cell_kernel<T, kSmall>;
+            if (set_lds_attr(kern, lds[k], S).code) return S;
+            kern<<<grid_for(kern, lds[k], class_items(cls[k].mode, n)), kThreads, lds[k],
+                   streams[k]>>>(pk[k], o.tol, limit, fixed ? 1 : 0, stall, w.ctrl + qidx[k],
+                                 w.ctrl, iters, errs, w.cell_mass, big);
+        }
         join();
         DD_HIP(hipGetLastError(), S);
         return S;
     }
-    auto ib = sk_iter_kernel<T, kBig>;
-    auto is = sk_iter_kernel<T, kSmall>;
-    auto fb = sk_final_kernel<T, kBig>;
-    auto fs = sk_final_kernel<T, kSmall>;
-    if (set_lds_attr(ib, ldsB, S).code || set_lds_attr(is, ldsS, S).code ||
-        set_lds_attr(fb, ldsB, S).code || set_lds_attr(fs, ldsS, S).code)
-        return S;
-    const int gB = p.nbig > 0 ? grid_for(ib, ldsB, p.nbig) : 0;
-    const int gS = nsmall > 0 ? grid_for(is, ldsS, class_items(kSmall, p.ncells, p.nbig)) : 0;
-    const int nblocks = gB + gS;
-    double* bufs[2] = {p.a, w.a_alt};
-    const size_t a_bytes = (size_t)p.ncells * p.xside * p.xside * sizeof(double);
+    std::vector<int> grid(ncls);
+    int nblocks = 0;
+    for (int k = 0; k < ncls; ++k) {
+        const int n = cls[k].hi - cls[k].lo;
+        auto ik = cls[k].mode == kBig ? sk_iter_kernel<T, kBig> : sk_iter_kernel<T, kSmall>;
+        auto fk = cls[k].mode == kBig ? sk_final_kernel<T, kBig> : sk_final_kernel<T, kSmall>;
+        if (set_lds_attr(ik, lds[k], S).code || set_lds_attr(fk, lds[k], S).code) return S;
+        grid[k] = grid_for(ik, lds[k], class_items(cls[k].mode, n));
+        nblocks += grid[k];
+    }
+    double* bufs[2] = {p0.a, w.a_alt};
+    const size_t a_bytes = (size_t)p0.ncells * p0.xside * p0.xside * sizeof(double);
     const int chunk = o.check_every > 0 ? o.check_every : 8;
-    // a chunk of identical iterations (both classes' launches, forked and joined) is captured
+    // a chunk of identical iterations (every class's launch, forked and joined) is captured
     // into a HIP graph once and replayed; the host reads the device stop flag between replays
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     DD_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal), S);
-    for (int k = 0; k < chunk; ++k) {
+    for (int r = 0; r < chunk; ++r) {
         fork();
-        if (gB > 0)
-            ib<<<gB, kThreads, ldsB, s2>>>(p, bufs[0], bufs[1], o.max_iter, o.tol, nblocks,
-                                           w.ctrl, errs, w.cell_mass, w.dtot, big);
-        if (gS > 0)
-            is<<<gS, kThreads, ldsS, st>>>(p, bufs[0], bufs[1], o.max_iter, o.tol, nblocks,
-                                           w.ctrl, errs, w.cell_mass, w.dtot, big);
+        for (int k = 0; k < ncls; ++k) {
+            auto ik = cls[k].mode == kBig ? sk_iter_kernel<T, kBig> : sk_iter_kernel<T, kSmall>;
+            ik<<<grid[k], kThreads, lds[k], streams[k]>>>(pk[k], bufs[0], bufs[1], o.max_iter,
+                                                          o.tol, nblocks, w.ctrl, errs,
+                                                          w.cell_mass, w.dtot, big);
+        }
         join();
     }
     const hipError_t ce = hipStreamEndCapture(st, &graph);
@@ -1016,10 +1143,12 @@ Status run_solver(const SkBatch& p, const dd_sinkhorn_opts& o, hipStream_t st, S
     (void)hipGraphDestroy(graph);
     if (done < 1) done = o.max_iter;  // unreachable: the kernel sets done at max_iter
     if (((done - 1) & 1) == 1)
-        DD_HIP(hipMemcpyAsync(p.a, bufs[1], a_bytes, hipMemcpyDeviceToDevice, st), S);
+        DD_HIP(hipMemcpyAsync(p0.a, bufs[1], a_bytes, hipMemcpyDeviceToDevice, st), S);
     fork();
-    if (gB > 0) fb<<<gB, kThreads, ldsB, s2>>>(p, w.ctrl, iters, big);
-    if (gS > 0) fs<<<gS, kThreads, ldsS, st>>>(p, w.ctrl, iters, big);
+    for (int k = 0; k < ncls; ++k) {
+        auto fk = cls[k].mode == kBig ? sk_final_kernel<T, kBig> : sk_final_kernel<T, kSmall>;
+        fk<<<grid[k], kThreads, lds[k], streams[k]>>>(pk[k], w.ctrl, iters, big);
+    }
     join();
     DD_HIP(hipGetLastError(), S);
     return S;
@@ -1055,12 +1184,81 @@ void plan_tile(const std::vector<int32_t>& hd, const std::vector<int32_t>& cells
         }
     }
 }
+constexpr size_t kBudgets[] = {52 * 1024, 78 * 1024};  // small and big launches
+constexpr size_t kBigBudget = 156 * 1024;
+
+// The launch plan of one precision: processing order (giant, big, small classes, most work
+// first within each), the classes with their LDS tiles, and the global scratch offsets of the
+// boxes beyond the giant tile.
+//   small: LSE work per iteration below 64K terms and a box within the small tile (per-wave
+//          budget), one cell per wave;
+//   big:   the rest within the big tile, one cell per workgroup;
+//   giant: boxes beyond the big tile, one per workgroup with the whole LDS of a CU.
+struct Plan {
+    std::vector<int32_t> ord;
+    std::vector<CellClass> classes;
+    std::vector<int64_t> off;
+    int64_t scr = 0;
+    int n_big = 0, n_giant = 0;
+    int small_tile[2] = {0, 0}, big_tile[2] = {0, 0};
+};
+
+Plan plan_classes(const std::vector<int32_t>& hd, int ncells, int AS, size_t elem,
+                  size_t small_budget, size_t big_budget) {
+    Plan P;
+    auto work = [&](int c) {
+        return sk_cell_terms(AS, std::max(hd[2 * c], 0), std::max(hd[2 * c + 1], 0));
+    };
+    auto fits = [&](int c, const int* t) { return hd[2 * c] <= t[0] && hd[2 * c + 1] <= t[1]; };
+    std::vector<int32_t> ord(ncells);
+    for (int c = 0; c < ncells; ++c) ord[c] = c;
+    std::stable_sort(ord.begin(), ord.end(), [&](int a, int b) { return work(a) > work(b); });
+    const double small_terms = 64.0 * 1024.0;
+    std::vector<int32_t> cand, rest, small_cells, big_cells, giant_cells;
+    for (int c : ord) (work(c) < small_terms ? cand : rest).push_back(c);
+    CellClass sc, bc, gc;
+    sc.mode = kSmall;
+    sc.budget = small_budget;
+    plan_tile(hd, cand, AS, elem, small_budget / kWaves, sc.t[0], sc.t[1]);
+    for (int c : cand) (fits(c, sc.t) ? small_cells : rest).push_back(c);
+    std::stable_sort(rest.begin(), rest.end(), [&](int a, int b) { return work(a) > work(b); });
+    bc.budget = big_budget;
+    plan_tile(hd, rest, AS, elem, big_budget, bc.t[0], bc.t[1]);
+    for (int c : rest) (fits(c, bc.t) ? big_cells : giant_cells).push_back(c);
+    gc.budget = kBigBudget;
+    plan_tile(hd, giant_cells, AS, elem, kBigBudget, gc.t[0], gc.t[1]);
+    P.ord = giant_cells;
+    P.ord.insert(P.ord.end(), big_cells.begin(), big_cells.end());
+    P.ord.insert(P.ord.end(), small_cells.begin(), small_cells.end());
+    gc.lo = 0;
+    gc.hi = (int)giant_cells.size();
+    bc.lo = gc.hi;
+    bc.hi = bc.lo + (int)big_cells.size();
+    sc.lo = bc.hi;
+    sc.hi = ncells;
+    if (sc.hi > sc.lo) P.classes.push_back(sc);
+    if (bc.hi > bc.lo) P.classes.push_back(bc);
+    if (gc.hi > gc.lo) P.classes.push_back(gc);
+    P.off.assign(ncells, 0);
+    for (int c : giant_cells) {
+        const int W1 = hd[2 * c], W2 = hd[2 * c + 1];
+        if (W1 < 1 || W2 < 1 || fits(c, gc.t)) continue;
+        P.off[c] = P.scr;
+        P.scr += cell_scratch_doubles(AS, W1, W2, elem);
+    }
+    P.n_big = (int)(big_cells.size() + giant_cells.size());
+    P.n_giant = (int)giant_cells.size();
+    P.small_tile[0] = sc.t[0];
+    P.small_tile[1] = sc.t[1];
+    P.big_tile[0] = bc.t[0];
+    P.big_tile[1] = bc.t[1];
+    return P;
+}
+
 // Online tuner of the LDS budget per workgroup of the small-cell launch (occupancy against
 // LDS-resident boxes):
 // each key (block side, precision, stop rule, box-size class) tries every candidate once on
 // consecutive solves, then keeps the one with the least Sinkhorn time per LSE term.
-constexpr size_t kBudgets[] = {26 * 1024, 39 * 1024, 52 * 1024, 78 * 1024};
-constexpr size_t kBigBudget = 156 * 1024;
 constexpr int kNumBudgets = sizeof(kBudgets) / sizeof(kBudgets[0]);
 
 struct TuneKey {
@@ -1073,16 +1271,19 @@ struct TuneKey {
     }
 };
 
+// A choice is (small budget, big budget): choice % kNumBudgets, choice / kNumBudgets.
+constexpr int kNumChoices = kNumBudgets * kNumBudgets;
+
 class Tuner {
    public:
     int pick(const TuneKey& k) {
         std::lock_guard<std::mutex> g(mu_);
         Entry& e = tab_[k];
         if (forced_ >= 0) return forced_;
-        for (int c = 0; c < kNumBudgets; ++c)
+        for (int c = 0; c < kNumChoices; ++c)
             if (e.n[c] == 0) return c;
         int best = 0;
-        for (int c = 1; c < kNumBudgets; ++c)
+        for (int c = 1; c < kNumChoices; ++c)
             if (e.t[c] < e.t[best]) best = c;
         return best;
     }
@@ -1096,8 +1297,8 @@ class Tuner {
 
    private:
     struct Entry {
-        double t[kNumBudgets] = {};
-        int n[kNumBudgets] = {};
+        double t[kNumChoices] = {};
+        int n[kNumChoices] = {};
     };
     std::mutex mu_;
     std::map<TuneKey, Entry> tab_;
@@ -1173,73 +1374,53 @@ Status sk_solve(const SkBatch& p, const dd_sinkhorn_opts& o, hipStream_t caller_
     for (int c = 0; c < p.ncells; ++c) ord[c] = c;
     std::stable_sort(ord.begin(), ord.end(), [&](int a, int b) { return work(a) > work(b); });
     const size_t elem = p.prec == DD_PREC_F64 ? sizeof(double) : sizeof(float);
-    // LDS budget per workgroup from the tuner, keyed by block side, precision, stop rule and
-    // the size class of the boxes.  A cell whose LSE work per iteration is several times a
-    // typical cell's, or whose box does not fit the small tile, runs on the whole workgroup;
-    // the others one per wave.  Neither the budget nor the split changes the arithmetic (every
+    // Launch plans, one per precision (the float64 finish has its own tiles).  The two LDS
+    // budgets come from the tuner, keyed by block side, precision, stop rule and the size
+    // class of the boxes.  Neither the budgets nor the split change the arithmetic (every
     // output has its own fixed-order sum, and the error reduction is the same for a wave and
     // a workgroup), so every choice gives the same result.
     double area = 0.0;
-    for (int c = 0; c < p.ncells; ++c) area += (double)std::max(hd[2 * c], 1) * std::max(hd[2 * c + 1], 1);
+    for (int c = 0; c < p.ncells; ++c)
+        area += (double)std::max(hd[2 * c], 1) * std::max(hd[2 * c + 1], 1);
     const int bucket = (int)std::log2(std::max(1.0, area / p.ncells));
     const TuneKey key{AS, p.prec, o.fixed_iters > 0 ? 2 : o.stop_rule, bucket};
     const int choice = tuner().pick(key);
-    const size_t wg_budget = kBudgets[choice];
-    const double big_terms = 64.0 * 1024.0;
-    std::vector<int32_t> cand;
-    for (int c : ord)
-        if (work(c) < big_terms) cand.push_back(c);
-    SkBatch q = p;
-    SkBatch q64 = p;
-    plan_tile(hd, cand, AS, elem, wg_budget / kWaves, q.lw1, q.lw2);
-    plan_tile(hd, cand, AS, sizeof(double), wg_budget / kWaves, q64.lw1, q64.lw2);
-    const int sw1 = std::min(q.lw1, q64.lw1), sw2 = std::min(q.lw2, q64.lw2);
-    std::vector<int32_t> big_cells, small_cells;
-    for (int c : ord) {
-        if (work(c) < big_terms && hd[2 * c] <= sw1 && hd[2 * c + 1] <= sw2)
-            small_cells.push_back(c);
-        else
-            big_cells.push_back(c);
-    }
-    const int nbig = (int)big_cells.size();
-    // big cells run in their own launch with the whole LDS of a CU per workgroup
-    plan_tile(hd, big_cells, AS, elem, kBigBudget, q.lw1b, q.lw2b);
-    plan_tile(hd, big_cells, AS, sizeof(double), kBigBudget, q64.lw1b, q64.lw2b);
-    ord = big_cells;
-    ord.insert(ord.end(), small_cells.begin(), small_cells.end());
-    q.nbig = q64.nbig = nbig;
-    if (p.ncells > w.order_cap) {
-        if (w.order) (void)hipFree(w.order);
-        w.order = nullptr;
-        DD_HIP(hipMalloc(&w.order, std::max(p.ncells, 1024) * sizeof(int32_t)), S);
-        w.order_cap = std::max(p.ncells, 1024);
-    }
-    DD_HIP(hipMemcpyAsync(w.order, ord.data(), ord.size() * 4, hipMemcpyHostToDevice, st), S);
-    q.order = q64.order = w.order;
-    // per-cell global scratch for the boxes beyond their class's tile in either precision,
-    // sized for float64 terms
-    std::vector<int64_t> off(p.ncells, 0);
-    int64_t scr = 0;
-    for (int k = 0; k < p.ncells; ++k) {
-        const int c = ord[k];
-        const int W1 = hd[2 * c], W2 = hd[2 * c + 1];
-        if (W1 < 1 || W2 < 1) continue;
-        const bool is_big = k < nbig;
-        const int t1 = is_big ? std::min(q.lw1b, q64.lw1b) : std::min(q.lw1, q64.lw1);
-        const int t2 = is_big ? std::min(q.lw2b, q64.lw2b) : std::min(q.lw2, q64.lw2);
-        if (W1 > t1 || W2 > t2) {
-            off[c] = scr;
-            scr += cell_scratch_doubles(AS, W1, W2, sizeof(double));
+    const size_t small_budget = kBudgets[choice % kNumBudgets];
+    const size_t big_budget = kBudgets[choice / kNumBudgets];
+    const bool finish = p.prec == DD_PREC_F32 && o.fixed_iters == 0;
+    const Plan P = plan_classes(hd, p.ncells, AS, elem, small_budget, big_budget);
+    const Plan P64 = finish ? plan_classes(hd, p.ncells, AS, sizeof(double), kBudgets[1], kBudgets[1])
+                            : Plan{};
+    auto put = [&](int32_t*& dev_ord, int64_t*& dev_off, int& cap, const Plan& pl) -> Status {
+        Status E;
+        if (p.ncells > cap) {
+            if (dev_ord) (void)hipFree(dev_ord);
+            if (dev_off) (void)hipFree(dev_off);
+            dev_ord = nullptr;
+            dev_off = nullptr;
+            cap = std::max(p.ncells, 1024);
+            DD_HIP(hipMalloc(&dev_ord, cap * sizeof(int32_t)), E);
+            DD_HIP(hipMalloc(&dev_off, cap * sizeof(int64_t)), E);
         }
+        DD_HIP(hipMemcpyAsync(dev_ord, pl.ord.data(), pl.ord.size() * 4, hipMemcpyHostToDevice, st),
+               E);
+        DD_HIP(hipMemcpyAsync(dev_off, pl.off.data(), pl.off.size() * 8, hipMemcpyHostToDevice, st),
+               E);
+        return E;
+    };
+    S = put(w.order, w.scr_off, w.order_cap, P);
+    if (S.code) return S;
+    SkBatch q = p;
+    q.order = w.order;
+    q.scr_off = w.scr_off;
+    SkBatch q64 = p;
+    if (finish) {
+        S = put(w.order64, w.scr_off64, w.order64_cap, P64);
+        if (S.code) return S;
+        q64.order = w.order64;
+        q64.scr_off = w.scr_off64;
     }
-    if (p.ncells > w.scr_cap) {
-        if (w.scr_off) (void)hipFree(w.scr_off);
-        w.scr_off = nullptr;
-        DD_HIP(hipMalloc(&w.scr_off, std::max(p.ncells, 1024) * sizeof(int64_t)), S);
-        w.scr_cap = std::max(p.ncells, 1024);
-    }
-    DD_HIP(hipMemcpyAsync(w.scr_off, off.data(), off.size() * 8, hipMemcpyHostToDevice, st), S);
-    q.scr_off = q64.scr_off = w.scr_off;
+    const int64_t scr = std::max(P.scr, P64.scr);
     if (scr > 0) {
         const size_t need = (size_t)scr * sizeof(double) + 64;
         if (need > w.big_bytes) {
@@ -1253,15 +1434,14 @@ Status sk_solve(const SkBatch& p, const dd_sinkhorn_opts& o, hipStream_t caller_
     DD_HIP(hipStreamSynchronize(st), S);
     DD_HIP(hipEventRecord(w.ev0, st), S);
     zero_ints<<<1, 64, 0, st>>>(w.ctrl, 16);
-    S = p.prec == DD_PREC_F32 ? run_solver<float>(q, o, st, w, iters, errs)
-                              : run_solver<double>(q, o, st, w, iters, errs);
+    S = p.prec == DD_PREC_F32 ? run_solver<float>(q, P.classes, o, st, w, iters, errs)
+                              : run_solver<double>(q, P.classes, o, st, w, iters, errs);
     if (S.code) return S;
     DD_HIP(hipEventRecord(w.ev2, st), S);
-    const bool finish = p.prec == DD_PREC_F32 && o.fixed_iters == 0;
     if (finish) {
         // float64 finish: continue the same stopping rule in float64 from the float32 state;
         // the tolerance is then certified by a float64 error (usually after one Y-update)
-        S = run_solver<double>(q64, o, st, w, w.iters64, errs);
+        S = run_solver<double>(q64, P64.classes, o, st, w, w.iters64, errs);
         if (S.code) return S;
     }
     sk_stats_kernel<<<1, kThreads, 0, st>>>(p.ncells, iters, finish ? w.iters64 : nullptr, errs,
@@ -1292,6 +1472,14 @@ Status sk_solve(const SkBatch& p, const dd_sinkhorn_opts& o, hipStream_t caller_
     bs.time_ms = ms;
     bs.main_ms = ms_main;
     bs.finish_iters_max = finish ? hctl[8] : 0;
+    bs.n_big = P.n_big;
+    bs.n_giant = P.n_giant;
+    bs.lds_kb[0] = (int32_t)(small_budget / 1024);
+    bs.lds_kb[1] = (int32_t)(big_budget / 1024);
+    bs.tile_small[0] = P.small_tile[0];
+    bs.tile_small[1] = P.small_tile[1];
+    bs.tile_big[0] = P.big_tile[0];
+    bs.tile_big[1] = P.big_tile[1];
     if (o.fixed_iters > 0)
         bs.converged = 1;
     else if (o.stop_rule == DD_STOP_CELL)

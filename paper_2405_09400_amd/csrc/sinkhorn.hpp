@@ -20,13 +20,11 @@ struct SkBatch {
     const int32_t* order = nullptr;  // processing order, most work first (set by sk_solve)
     double kappa = 1.0;
     int max_w1 = 0, max_w2 = 0;
-    // set by sk_solve: the cells order[0..nbig) run one per workgroup, the rest one per wave;
-    // LDS tile bounds for the Y-box arrays of the small (lw1, lw2) and big (lw1b, lw2b) cells
-    int nbig = 0;
+    // set by sk_solve for each launch: the cells order[q_lo, q_hi) and their LDS tile bound,
+    // and the per-cell global scratch offsets (in doubles) of boxes beyond the tile
+    int q_lo = 0, q_hi = 0;
     int lw1 = 0, lw2 = 0;
-    int lw1b = 0, lw2b = 0;
-    const int64_t* scr_off = nullptr; // [ncells] offset (in doubles) of a cell's global scratch
-                                      // when its box exceeds the LDS tile (set by sk_solve)
+    const int64_t* scr_off = nullptr;
     int prec = DD_PREC_F32;
 };
 
@@ -43,15 +41,19 @@ struct SkWork {
     void* big = nullptr;        // scratch for Y boxes beyond the LDS tile (g, z in global memory)
     size_t big_bytes = 0;
     int64_t* scr_off = nullptr; // [cap] per-cell scratch offsets
-    int scr_cap = 0;
-    int32_t* order = nullptr;   // largest-box-first processing order
+    int32_t* order = nullptr;   // processing order of the main run
     int order_cap = 0;
+    int32_t* order64 = nullptr; // processing order and scratch offsets of the float64 finish
+    int64_t* scr_off64 = nullptr;
+    int order64_cap = 0;
     int cap = 0;
     hipEvent_t ev0 = nullptr, ev1 = nullptr, ev2 = nullptr;
     hipEvent_t evj = nullptr;     // joins the caller's stream and `stream`
     hipEvent_t evf = nullptr, evj2 = nullptr;  // fork / join of `stream` and `stream2`
     hipStream_t stream = nullptr; // the solver's own streams (default priority): small cells
-    hipStream_t stream2 = nullptr;  // and big cells run side by side
+    hipStream_t stream2 = nullptr;  // and the other classes run side by side
+    hipStream_t stream3 = nullptr;
+    hipEvent_t evj3 = nullptr;
 };
 
 Status sk_work_reserve(SkWork& w, int ncells, size_t a_n);
