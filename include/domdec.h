@@ -61,7 +61,9 @@ typedef struct {
     int32_t max_iter;     /* iteration cap (>= 1)                                  */
     int32_t fixed_iters;  /* 0 = use tol                                           */
     int32_t stop_rule;    /* DD_STOP_BATCH | DD_STOP_CELL                          */
-    int32_t check_every;  /* batch rule: test the error every k-th iteration (>=1) */
+    int32_t check_every;  /* batch rule: the float32 register-blocked path tests the
+                             error every k-th iteration (0 = 8); the other kernels test
+                             every iteration and poll the flag every k launches        */
     int32_t init;         /* DD_INIT_ZERO | PREV | NET (domdec_iterate only)      */
     int32_t reserved;     /* must be 0                                             */
 } dd_sinkhorn_opts;
@@ -85,7 +87,12 @@ typedef struct {
     int32_t lds_kb[2];         /* LDS budget per workgroup, small and big launches (KB)  */
     int32_t tile_small[2];     /* LDS tile of the small-cell launch (W1, W2)             */
     int32_t tile_big[2];       /* LDS tile of the big-cell launch (W1, W2)               */
-    int32_t reserved;
+    int32_t path;              /* 0: general kernels; 1: register-blocked float32 path for
+                                  8 x 8 blocks (n_big = cells per workgroup, the rest one
+                                  per wave; lds_kb = LDS per workgroup of each launch;
+                                  exact-fallback counts: tile_small = X-update first
+                                  pass (rows), second pass (outputs); tile_big = Y-update
+                                  second pass (rows), first pass (outputs))                 */
 } dd_batch_stats;
 
 /*

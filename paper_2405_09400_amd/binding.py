@@ -47,7 +47,7 @@ class BatchStats(ctypes.Structure):
                 ("finish_iters_max", ctypes.c_int32), ("n_big", ctypes.c_int32),
                 ("n_giant", ctypes.c_int32), ("lds_kb", ctypes.c_int32 * 2),
                 ("tile_small", ctypes.c_int32 * 2), ("tile_big", ctypes.c_int32 * 2),
-                ("reserved", ctypes.c_int32)]
+                ("path", ctypes.c_int32)]
 
 
 class Params(ctypes.Structure):

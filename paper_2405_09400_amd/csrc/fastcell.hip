@@ -1,0 +1,1099 @@
+// Register-blocked float32 cell Sinkhorn for 8 x 8 X blocks on gfx950.
+//
+// The iteration, the potentials (f = alpha/eps, g = beta/eps, reference measure
+// mu_J (x) nu_J) and the precision split (float32 terms, float64 line offsets, potentials,
+// errors and masses) are those of the general kernels: the cell problem of Alg.
+// "DomDecIter" in the log domain, with the separable cost of App. A.1 evaluated as two 1D
+// log-sum-exp passes per half-iteration, each as a stabilised kernel product (input shifted
+// by its line maximum, the cost split at the input nearest to each output, so that the
+// per-term work is one multiply-add against a kernel table built once per cell).
+//
+// What is specific to the common block side 2s = 8 is the mapping to the hardware:
+//   * the 64 lanes of a wave form an 8 x 8 grid (r, c).  The lane (r, c) of the first wave
+//     owns X point (r, c) (f, log mu, mu in registers); in the Y box it owns the rows
+//     j1 = r + 8 (wave + waves * t) and the columns j2 = c + 8 u (+ 32 per column block);
+//   * the Y-update of a box row is fused with the first pass of the X-update of that row:
+//     g, g + log nu_J, the row maximum and exp(g + log nu_J - max) never leave registers.
+//     The 8-wide kernel rows (Y-update over i1, X-update over i2) are vectors read once per
+//     row or column as 128-bit LDS broadcasts, so a box entry costs 16 multiply-adds, one
+//     log and one exp, and no LDS traffic of its own;
+//   * row maxima and the reductions of the X-update over the 8 lanes of a row are DPP lane
+//     permutations; the second X pass reduces across the rows through shuffles;
+//   * a cell's box is transposed on load when it is wider than tall, so the long side is the
+//     one split across lanes and waves;
+//   * a box whose long side is at most 32 is solved by one wave (four cells per workgroup,
+//     log nu_J in registers); larger boxes by a workgroup of four waves (log nu_J read from
+//     global memory, L2-resident while the cell runs);
+//   * an underflowed kernel-product sum (every input near the output negligible against the
+//     line maximum) is recomputed for that output by an exact log-sum-exp in float64.
+// The batch rule runs `check_every` iterations per launch and reduces the per-cell errors
+// once per launch (last-workgroup ticket, fixed cell order); launches are replayed from a
+// captured HIP graph.
+#include "fastcell.hpp"
+
+#include <algorithm>
+#include <cmath>
+#include <cstdlib>
+
+namespace dd {
+namespace {
+
+constexpr int kA = 8;  // X block side
+constexpr int kBlock = 256;
+// Smallest kernel-product sum trusted without the exact fallback.  Every factor is at most 1,
+// so the terms lost to float underflow (each below 1.2e-38, at most 512 of them) stay below
+// 1e-9 of any sum above the floor.
+constexpr float kFloorF = 1e-28f;
+constexpr int kSolve = 0, kBatch = 1, kFinal = 2;
+
+template <typename T>
+using lds_p = __attribute__((address_space(3))) T*;
+typedef float v4f __attribute__((ext_vector_type(4)));
+
+// ---------------------------------------------------------------------------------------
+// Lane permutations (all 64 lanes active).
+// ---------------------------------------------------------------------------------------
+constexpr int kDppXor1 = 0xB1;     // quad_perm [1,0,3,2]
+constexpr int kDppXor2 = 0x4E;     // quad_perm [2,3,0,1]
+constexpr int kDppMirror8 = 0x141;  // row_half_mirror: lane i <-> 7 - i within 8
+constexpr int kDppRor8 = 0x128;     // row_ror:8 within 16 lanes: lane i <-> i ^ 8
+
+template <int CTRL>
+__device__ __forceinline__ float dppf(float v) {
+    return __builtin_bit_cast(
+        float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), CTRL, 0xF, 0xF, false));
+}
+template <int CTRL>
+__device__ __forceinline__ double dppd(double v) {
+    const unsigned long long u = __builtin_bit_cast(unsigned long long, v);
+    const unsigned lo = (unsigned)__builtin_amdgcn_mov_dpp((int)(unsigned)u, CTRL, 0xF, 0xF, false);
+    const unsigned hi =
+        (unsigned)__builtin_amdgcn_mov_dpp((int)(unsigned)(u >> 32), CTRL, 0xF, 0xF, false);
+    return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
+}
+// maximum over the aligned group of 8 lanes (same r); every lane gets the same result
+__device__ __forceinline__ double max8(double v) {
+    v = fmax(v, dppd<kDppXor1>(v));
+    v = fmax(v, dppd<kDppXor2>(v));
+    return fmax(v, dppd<kDppMirror8>(v));
+}
+// maximum over the 8 lanes with the same c (lane bits 3..5)
+__device__ __forceinline__ double maxr(double v) {
+    v = fmax(v, dppd<kDppRor8>(v));
+    v = fmax(v, __shfl_xor(v, 16, 64));
+    return fmax(v, __shfl_xor(v, 32, 64));
+}
+__device__ __forceinline__ double wsum(double v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+__device__ __forceinline__ double wmax(double v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
+    return v;
+}
+// Reduce-scatter of a[0..7] over the 8 lanes with the same r: lane c gets the sum over those
+// lanes of a[c] (recursive halving with partners 7 - c, c ^ 2, c ^ 1).
+__device__ __forceinline__ float rs8(const float (&a)[8], int c) {
+    const bool b2 = (c & 4) != 0, b1 = (c & 2) != 0, b0 = (c & 1) != 0;
+    float h[4], e[2];
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+        h[q] = (b2 ? a[4 + q] : a[q]) + dppf<kDppMirror8>(b2 ? a[q] : a[4 + q]);
+#pragma unroll
+    for (int q = 0; q < 2; ++q)
+        e[q] = (b1 ? h[2 + q] : h[q]) + dppf<kDppXor2>(b1 ? h[q] : h[2 + q]);
+    return (b0 ? e[1] : e[0]) + dppf<kDppXor1>(b0 ? e[0] : e[1]);
+}
+// The same over the 8 lanes with the same c: lane (r, c) gets the sum of a[r] (partners
+// lane ^ 32, ^ 16, ^ 8).
+__device__ __forceinline__ float rsr(const float (&a)[8], int r) {
+    const bool b2 = (r & 4) != 0, b1 = (r & 2) != 0, b0 = (r & 1) != 0;
+    float h[4], e[2];
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+        h[q] = (b2 ? a[4 + q] : a[q]) + __shfl_xor(b2 ? a[q] : a[4 + q], 32, 64);
+#pragma unroll
+    for (int q = 0; q < 2; ++q)
+        e[q] = (b1 ? h[2 + q] : h[q]) + __shfl_xor(b1 ? h[q] : h[2 + q], 16, 64);
+    return (b0 ? e[1] : e[0]) + dppf<kDppRor8>(b0 ? e[0] : e[1]);
+}
+
+template <int NW>
+struct Team {
+    __device__ static int wave() { return NW == 1 ? 0 : (int)(threadIdx.x >> 6); }
+    // a wave alone works from LDS only and its LDS operations complete in order: keeping the
+    // compiler from moving memory operations across this point is all it needs
+    __device__ static void sync() {
+        if constexpr (NW == 1) {
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        } else {
+            __syncthreads();
+        }
+    }
+};
+
+__device__ __forceinline__ double uni(double v) {
+    const unsigned long long u = __builtin_bit_cast(unsigned long long, v);
+    const unsigned lo = __builtin_amdgcn_readfirstlane((unsigned)u);
+    const unsigned hi = __builtin_amdgcn_readfirstlane((unsigned)(u >> 32));
+    return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
+}
+
+// ---------------------------------------------------------------------------------------
+// LDS slice of one cell (kernel frame: W1 >= W2 after the optional transposition).
+//   fixed part: U1 [64] f32 = exp(WQ), WQ [64] f32 = f + log mu - phi(i2) - ry(i1),
+//               ry [8] f64 (row maxima of f + log mu - phi), red [8] f64 (shared scalars),
+//               phi [8], psi [8] f64 (profiles absorbed into the Y-update kernels), and for
+//               a workgroup team the per-wave partials xd [NW][8] f64, xs [NW][64] f32;
+//   row records (box row j1, 144 B): KY2 [8] (Y-update pass over i1, inputs i1), KX2 [8]
+//               (X-update pass over j1, outputs i1), R [8] f64 (first X pass, minus
+//               dx1(j1)^2 / kappa), sY2 f64
+//               (shift of output j1 of the Y-update's second pass);
+//   column records (box column j2, 192 B): KY1 [8] (Y-update pass over i2, inputs i2),
+//               KX1 [8] (X-update pass over j2, outputs i2), U2 [8] = exp(V - My) over i1,
+//               My f64 (column maximum of V), sY1 f64 (shift of output j2 of the Y-update's
+//               first pass), V [8] f64 = ry + t1 (kept for the exact fallback),
+//               Myx f64 = My + dx2(j2)^2 / kappa.
+// Kernel entries.  The potential f varies across the block by far more than float exp covers
+// at small kappa, and g grows quadratically away from it, so each pass absorbs the bulk of
+// its input's variation into its kernel (the stabilised-kernel idea, here once per launch):
+//   * Y-update, pass over i2: the column profile phi(i2) = max_i1 (f + log mu) taken at the
+//     cell's load, KY1[j2][i2] = exp(phi(i2) - (i2 - j2 + E2)^2 / kappa - tau1(j2)) with
+//     tau1(j2) the maximum over i2 of the exponent, sY1 = -tau1;
+//   * Y-update, pass over i1: the row profile psi(i1) = max_i2 (f + log mu - phi) at load,
+//     KY2[j1][i1] = exp(psi(i1) - (i1 - j1 + E1)^2 / kappa - tau2(j1)), sY2 = -tau2, and the
+//     pass's input is V - psi with V = LSE_i2 [f + log mu - cost] the first pass's result;
+//   * X-update passes (box inputs, X outputs): each input is normalised at the X output
+//     nearest to it, dn = dx(j) the distance of box line j to the block's range, whose
+//     square / kappa is taken out of that input instead (the quadratic growth of g).
+// Any profile gives the same sums; a good one keeps the scaled inputs within float range, so
+// the exact fallbacks stay rare.
+// ---------------------------------------------------------------------------------------
+constexpr int kRowB = 144, kColB = 192;  // 16-byte multiples
+constexpr int kOffU1 = 0, kOffWQ = 256, kOffRy = 512, kOffRed = 576, kOffPhi = 640,
+              kOffPsi = 704, kOffXd = 768;
+// row record fields
+constexpr int kRKY2 = 0, kRKX2 = 32, kRR = 64, kRSY2 = 128;
+// column record fields
+constexpr int kCKY1 = 0, kCKX1 = 32, kCU2 = 64, kCMy = 96, kCSY1 = 104, kCV = 112, kCMyx = 176;
+constexpr double kNeedExact = 1e300;  // R marker: recompute this output exactly
+__device__ __forceinline__ double klog(float x) { return (double)__logf(x); }
+
+__host__ __device__ constexpr int fixed_bytes(int NW) {
+    return NW > 1 ? kOffXd + 64 * NW + 256 * NW : kOffXd;
+}
+
+__host__ __device__ inline size_t slice_bytes(int NW, int W1m, int W2m) {
+    return (size_t)fixed_bytes(NW) + (size_t)kRowB * W1m + (size_t)kColB * W2m;
+}
+
+__device__ __forceinline__ void ld8(lds_p<float> p, float (&v)[8]) {
+    const v4f a = *(lds_p<v4f>)p;
+    const v4f b = *(lds_p<v4f>)(p + 4);
+    v[0] = a.x;
+    v[1] = a.y;
+    v[2] = a.z;
+    v[3] = a.w;
+    v[4] = b.x;
+    v[5] = b.y;
+    v[6] = b.z;
+    v[7] = b.w;
+}
+
+// signed distance of box line j to the block's range [e, e + 8) along one axis
+__device__ __forceinline__ int dx_block(int j, int e) { return j - min(max(j, e), e + kA - 1); }
+
+struct FastArgs {
+    SkBatch p;
+    const int32_t* cells;  // the cells of this launch, most work first
+    int n;
+    int W1m, W2m;          // slice bounds (kernel frame)
+    int mode;
+    int limit, fixed, stall;  // kSolve
+    int chunk, max_iter;      // kBatch
+    double tol;
+    int nblocks;              // kBatch: workgroups of all the launches of one round
+    int* ctrl;
+    int qidx;                 // this launch's queue word
+    int32_t* iters;
+    double* err;
+    double* mass;
+    double* dtot;
+    double* f_keep;           // kBatch / kFinal: f at the start of each cell's last iteration
+};
+
+// Exact log-sum-exp fallbacks, reached only when a kernel-product sum underflows (an output
+// whose nearest inputs with mass are all negligible against the line maximum).
+// LSE_k [in(k) - (k - q + e)^2 / kappa] over the 8 inputs of an X line.
+template <typename F>
+__device__ __forceinline__ double exact8(F in, int q, int e, double invk) {
+    double m = -1e300;
+#pragma unroll
+    for (int k = 0; k < kA; ++k) {
+        const double d = k - q + e;
+        m = fmax(m, in(k) - d * d * invk);
+    }
+    float s = 0.f;
+#pragma unroll
+    for (int k = 0; k < kA; ++k) {
+        const double d = k - q + e;
+        s += __expf((float)(in(k) - d * d * invk - m));
+    }
+    return m + (double)__logf(s);
+}
+// Y-update, first pass, output (i1, j2), relative to ry: LSE_i2 [WQ(i1, i2) + phi(i2) - cost].
+__device__ __noinline__ double exact_y1(lds_p<float> wq, lds_p<double> phi, int j2, int E2,
+                                        double invk) {
+    return exact8([&](int k) { return (double)wq[k] + phi[k]; }, j2, E2, invk);
+}
+// Y-update, second pass, entry (j1, j2): LSE_i1 [V(i1, j2) - (i1 - j1 + E1)^2 / kappa].
+__device__ __forceinline__ double exact_y2(lds_p<char> col, int j1, int E1, double invk) {
+    const lds_p<double> V = (lds_p<double>)(col + kCV);
+    return exact8([&](int k) { return V[k]; }, j1, E1, invk);
+}
+__device__ __noinline__ double exact_y2_call(lds_p<char> col, int j1, int E1, double invk) {
+    return exact_y2(col, j1, E1, invk);
+}
+// X-update, second pass, output (i1, i2): LSE_j1 [R(j1, i2) - (j1 - i1 - E1)^2 / kappa], R
+// the first pass's result (stored minus dx1(j1)^2 / kappa).
+__device__ __noinline__ double exact_x2(lds_p<char> rows, int i1, int i2, int W1, int E1,
+                                        double invk) {
+    auto term = [&](int j1) {
+        const double d = j1 - i1 - E1, e = dx_block(j1, E1);
+        return *((lds_p<double>)(rows + j1 * kRowB + kRR) + i2) + (e * e - d * d) * invk;
+    };
+    double m = -1e300;
+    for (int j1 = 0; j1 < W1; ++j1) m = fmax(m, term(j1));
+    float s = 0.f;
+    for (int j1 = 0; j1 < W1; ++j1) s += __expf((float)(term(j1) - m));
+    return m + (double)__logf(s);
+}
+
+// One cell: load, iterate, store.  NW waves per cell, RPL box rows per lane at most, RC rows
+// per lane processed together; LNREG: log nu_J held in registers (NW == 1, box within
+// 32 x 32).
+template <int NW, int RPL, bool LNREG, int RC>
+__device__ __forceinline__ void run_cell(const FastArgs& g, int cell, lds_p<char> sb, int K) {
+    using Tm = Team<NW>;
+    const SkBatch& p = g.p;
+    const int lane = threadIdx.x & 63, w = Tm::wave(), tl = w * 64 + lane;
+    const int r = lane >> 3, c = lane & 7;
+    const int W1o = p.dims[2 * cell], W2o = p.dims[2 * cell + 1];
+    const bool T = W2o > W1o;
+    const int W1 = T ? W2o : W1o, W2 = T ? W1o : W2o;
+    if (W1o < 1 || W2o < 1 || W1o > p.max_w1 || W2o > p.max_w2 || W1 > g.W1m || W2 > g.W2m) {
+        if (tl == 0) {
+            atomicOr(&g.ctrl[3], 1);
+            g.err[cell] = 0.0;
+            g.mass[cell] = 0.0;
+            if (g.mode != kBatch) g.iters[cell] = 0;
+        }
+        return;
+    }
+    const int E1 = p.shift[2 * cell + (T ? 1 : 0)], E2 = p.shift[2 * cell + (T ? 0 : 1)];
+    const int64_t bse = p.base[cell];
+    const int s1 = T ? 1 : W2o, s2 = T ? W2o : 1;  // kernel-frame (j1, j2) -> packed offset
+    const int xo = T ? c * kA + r : r * kA + c;    // this lane's X point (i1 = r, i2 = c)
+    const double invk = 1.0 / p.kappa;
+    const float invkf = (float)invk;
+    const lds_p<float> U1 = (lds_p<float>)(sb + kOffU1);
+    const lds_p<float> WQ = (lds_p<float>)(sb + kOffWQ);
+    const lds_p<double> ry = (lds_p<double>)(sb + kOffRy);
+    const lds_p<double> red = (lds_p<double>)(sb + kOffRed);
+    const lds_p<int> ired = (lds_p<int>)(sb + kOffRed + 32);  // [8] shared ints
+    const lds_p<double> phi = (lds_p<double>)(sb + kOffPhi);
+    const lds_p<double> psi = (lds_p<double>)(sb + kOffPsi);
+    const lds_p<double> xd = (lds_p<double>)(sb + kOffXd);
+    const lds_p<float> xs = (lds_p<float>)(sb + kOffXd + 64 * NW);
+    const lds_p<char> rows = sb + fixed_bytes(NW);
+    const lds_p<char> cols = rows + kRowB * g.W1m;
+    auto rowp = [&](int j) { return rows + j * kRowB; };
+    auto colp = [&](int j) { return cols + j * kColB; };
+    auto KY2 = [&](int j) { return (lds_p<float>)(rowp(j) + kRKY2); };
+    auto KX2 = [&](int j) { return (lds_p<float>)(rowp(j) + kRKX2); };
+    auto Rr = [&](int j) { return (lds_p<double>)(rowp(j) + kRR); };
+    auto SY2 = [&](int j) { return (lds_p<double>)(rowp(j) + kRSY2); };
+    auto KY1 = [&](int j) { return (lds_p<float>)(colp(j) + kCKY1); };
+    auto KX1 = [&](int j) { return (lds_p<float>)(colp(j) + kCKX1); };
+    auto U2 = [&](int j) { return (lds_p<float>)(colp(j) + kCU2); };
+    auto My = [&](int j) { return (lds_p<double>)(colp(j) + kCMy); };
+    auto SY1 = [&](int j) { return (lds_p<double>)(colp(j) + kCSY1); };
+    auto Vc = [&](int j) { return (lds_p<double>)(colp(j) + kCV); };
+    auto Myx = [&](int j) { return (lds_p<double>)(colp(j) + kCMyx); };
+
+    // ---- load: X state (first wave), log nu_J, which X rows and columns carry mass --------
+    const double* fsrc = g.mode == kFinal ? g.f_keep : p.a;
+    double f = 0.0, lm = kNegD, mu = 0.0;
+    if (w == 0) {
+        f = fsrc[(int64_t)cell * 64 + xo];
+        lm = p.logmu[(int64_t)cell * 64 + xo];
+        mu = lm > kZeroMassLog ? exp(lm) : 0.0;
+    }
+    if (tl == 0) ired[1] = 0;  // underflow flag of the first X pass
+    Tm::sync();
+    float lnr[LNREG ? RPL : 1][4];
+    double lnref = 0.0;
+    if constexpr (LNREG) {
+        double m = kNegD;
+#pragma unroll
+        for (int t = 0; t < RPL; ++t)
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int j1 = r + 8 * t, j2 = c + 8 * u;
+                const double v = (j1 < W1 && j2 < W2)
+                                     ? p.lognu[bse + (int64_t)j1 * s1 + (int64_t)j2 * s2]
+                                     : kNegD;
+                if (v > kZeroMassLog) m = fmax(m, v);
+            }
+        lnref = uni(wmax(m));
+        if (!(lnref > kZeroMassLog)) lnref = 0.0;
+#pragma unroll
+        for (int t = 0; t < RPL; ++t)
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int j1 = r + 8 * t, j2 = c + 8 * u;
+                const double v = (j1 < W1 && j2 < W2)
+                                     ? p.lognu[bse + (int64_t)j1 * s1 + (int64_t)j2 * s2]
+                                     : kNegD;
+                lnr[t][u] = v > kZeroMassLog ? (float)(v - lnref) : kNegF;
+            }
+    }
+    // X rows / columns with mass (kernel frame), and the cell's mass
+    unsigned xrow = 0, xcol = 0;
+    double mass_all = 0.0;
+    if (w == 0) {
+        const unsigned long long bm = __ballot(mu > 0.0);
+        for (int k = 0; k < kA; ++k) {
+            if ((bm >> (8 * k)) & 0xFFull) xrow |= 1u << k;
+            if ((bm >> k) & 0x0101010101010101ull) xcol |= 1u << k;
+        }
+        mass_all = wsum(mu);
+        if constexpr (NW > 1) {
+            if (tl == 0) {
+                ired[2] = (int)xrow;
+                ired[3] = (int)xcol;
+                red[1] = mass_all;
+            }
+        }
+    }
+    Tm::sync();
+    if constexpr (NW > 1) {
+        xrow = (unsigned)ired[2];
+        xcol = (unsigned)ired[3];
+        mass_all = red[1];
+    }
+    xrow = __builtin_amdgcn_readfirstlane(xrow);
+    xcol = __builtin_amdgcn_readfirstlane(xcol);
+    mass_all = uni(mass_all);
+    // X-update kernel tables (fixed for the cell)
+    for (int o = tl; o < W2 * 8; o += 64 * NW) {
+        const int j2 = o >> 3, k = o & 7;
+        const int dx = j2 - k - E2, dnx = dx_block(j2, E2);
+        KX1(j2)[k] = __expf(-(float)(dx * dx - dnx * dnx) * invkf);
+    }
+    for (int o = tl; o < W1 * 8; o += 64 * NW) {
+        const int j1 = o >> 3, k = o & 7;
+        const int dx = j1 - k - E1, dnx = dx_block(j1, E1);
+        KX2(j1)[k] = __expf(-(float)(dx * dx - dnx * dnx) * invkf);
+    }
+    // Y-update kernel tables with the profiles of f + log mu absorbed (from f = fc)
+    auto build_y = [&](double fc) {
+        if (w == 0) {
+            const bool has = mu > 0.0;
+            const double w0 = has ? fc + lm : kNegD;
+            const double ph = maxr(w0);  // over the rows, per column c
+            const double ps = max8(has ? w0 - ph : kNegD);  // over the columns, per row r
+            if (r == 0) phi[c] = ph;
+            if (c == 0) psi[r] = ps;
+        }
+        Tm::sync();
+        for (int o = tl; o < W2 * 8; o += 64 * NW) {
+            const int j2 = o >> 3, k = o & 7;
+            double tau = -1e300;
+#pragma unroll
+            for (int q = 0; q < kA; ++q) {
+                const double d = q - j2 + E2;
+                if ((xcol >> q) & 1u) tau = fmax(tau, phi[q] - d * d * invk);
+            }
+            if (!(tau > -1e299)) tau = 0.0;
+            const double d = k - j2 + E2;
+            const bool on = (xcol >> k) & 1u;
+            KY1(j2)[k] = on ? __expf((float)(phi[k] - d * d * invk - tau)) : 0.f;
+            if (k == 0) *SY1(j2) = -tau;
+        }
+        for (int o = tl; o < W1 * 8; o += 64 * NW) {
+            const int j1 = o >> 3, k = o & 7;
+            double tau = -1e300;
+#pragma unroll
+            for (int q = 0; q < kA; ++q) {
+                const double d = q - j1 + E1;
+                if ((xrow >> q) & 1u) tau = fmax(tau, psi[q] - d * d * invk);
+            }
+            if (!(tau > -1e299)) tau = 0.0;
+            const double d = k - j1 + E1;
+            const bool on = (xrow >> k) & 1u;
+            KY2(j1)[k] = on ? __expf((float)(psi[k] - d * d * invk - tau)) : 0.f;
+            if (k == 0) *SY2(j1) = -tau;
+        }
+        Tm::sync();
+    };
+    build_y(f);
+
+    // number of rows t of this wave inside the box; column blocks of 32
+    const int ntw = W1 > 8 * w ? min(RPL, (W1 - 8 * w + 8 * NW - 1) / (8 * NW)) : 0;
+    const int nb = (W2 + 31) >> 5;
+
+    // ---- Y-update, first part: U1, WQ, ry (first wave), then per column j2:
+    //      t1 = LSE_i2 [WQ - cost] (relative to ry), V = ry + t1, My = max_i1 V, U2 = exp(V - My)
+    auto y_first = [&](double fc) {
+        if (w == 0) {
+            const bool has = mu > 0.0;
+            const double wv = has ? fc + lm - phi[c] : kNegD;
+            const double ryv = max8(wv);
+            const float wq = has ? (float)(wv - ryv) : kNegF;
+            WQ[lane] = wq;
+            U1[lane] = __expf(wq);
+            if (c == 0) ry[r] = ryv;
+        }
+        Tm::sync();
+        for (int j2 = tl >> 1; j2 < W2; j2 += 32 * NW) {  // lanes 2k, 2k + 1 share a column
+            const int h = tl & 1;
+            float k1[8];
+            ld8(KY1(j2), k1);
+            const double sy = *SY1(j2);
+            double v[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int i1 = 4 * h + q;
+                float a[8];
+                ld8(U1 + i1 * 8, a);
+                float sm = a[0] * k1[0];
+#pragma unroll
+                for (int k = 1; k < 8; ++k) sm = fmaf(a[k], k1[k], sm);
+                double t1 = klog(sm) - sy;
+                const bool row_has = (xrow >> i1) & 1u;
+                if (__builtin_expect(row_has && !(sm >= kFloorF), 0)) {
+                    t1 = exact_y1(WQ + i1 * kA, phi, j2, E2, invk);
+                    atomicAdd(&g.ctrl[15], 1);
+                }
+                v[q] = row_has ? ry[i1] + t1 : kNegD;
+            }
+            {
+                const lds_p<double> V = Vc(j2) + 4 * h;
+                V[0] = v[0];
+                V[1] = v[1];
+                V[2] = v[2];
+                V[3] = v[3];
+            }
+            // input of the pass over i1: V - psi (rows without mass drop out)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int i1 = 4 * h + q;
+                v[q] = ((xrow >> i1) & 1u) ? v[q] - psi[i1] : kNegD;
+            }
+            double my = fmax(fmax(v[0], v[1]), fmax(v[2], v[3]));
+            my = fmax(my, dppd<kDppXor1>(my));
+            v4f o;
+            o.x = __expf((float)(v[0] - my));
+            o.y = __expf((float)(v[1] - my));
+            o.z = __expf((float)(v[2] - my));
+            o.w = __expf((float)(v[3] - my));
+            *(lds_p<v4f>)(U2(j2) + 4 * h) = o;
+            if (h == 0) {
+                const int e = dx_block(j2, E2);
+                *My(j2) = my;
+                *Myx(j2) = my + (double)(e * e) * invk;
+            }
+        }
+        Tm::sync();
+    };
+
+    // ---- fused Y-update (second part) and first X pass for the RC rows of one chunk:
+    //      Zx = g + log nu_J - lnref - dx2(j2)^2 / kappa (float64), online row maximum over
+    //      column blocks, acc(i2) = sum_j2 exp(Zx - max) KX1(j2, i2),
+    //      R - dx1(j1)^2 / kappa = max + log acc - dx1(j1)^2 / kappa
+    auto chunk = [&](int ch) {
+        int j1[RC];
+        bool rv[RC];
+        float ky[RC][8], acc[RC][8];
+        double sy2[RC], m[RC];
+#pragma unroll
+        for (int t = 0; t < RC; ++t) {
+            j1[t] = r + 8 * (w + NW * (RC * ch + t));
+            rv[t] = j1[t] < W1;
+            const int jr = min(j1[t], W1 - 1);
+            ld8(KY2(jr), ky[t]);
+            sy2[t] = *SY2(jr);
+            m[t] = kNegD;
+#pragma unroll
+            for (int k = 0; k < 8; ++k) acc[t][k] = 0.f;
+        }
+        for (int b = 0; b < nb; ++b) {
+            double Z[RC][4];
+            unsigned badm = 0;  // entries whose Y-update sum underflowed
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int j2 = c + 8 * u + 32 * b;
+                const bool cv = j2 < W2;
+                const int jc = min(j2, W2 - 1);
+                float u2[8];
+                ld8(U2(jc), u2);
+                const double myv = *Myx(jc);
+#pragma unroll
+                for (int t = 0; t < RC; ++t) {
+                    float y = ky[t][0] * u2[0];
+#pragma unroll
+                    for (int k = 1; k < 8; ++k) y = fmaf(ky[t][k], u2[k], y);
+                    double lnv;
+                    if constexpr (LNREG) {
+                        lnv = (double)lnr[RC * ch + t][u];
+                    } else {
+                        const double v = p.lognu[bse + (int64_t)min(j1[t], W1 - 1) * s1 +
+                                                 (int64_t)jc * s2];
+                        lnv = v > kZeroMassLog ? v - lnref : kNegD;
+                    }
+                    const bool valid = rv[t] && cv && lnv > kZeroMassLog;
+                    const bool under = !(y >= kFloorF);
+                    badm |= (unsigned)(valid && under) << (t * 4 + u);
+                    const double z = lnv - myv - (klog(y) - sy2[t]);
+                    Z[t][u] = (valid && !under) ? z : kNegD;
+                }
+            }
+            if (__builtin_expect(badm != 0, 0)) {
+                // those entries exactly (log nu_J re-read from global memory)
+#pragma unroll 1
+                for (int q = 0; q < RC * 4; ++q) {
+                    if (!((badm >> q) & 1u)) continue;
+                    const int jq = r + 8 * (w + NW * (RC * ch + (q >> 2)));
+                    const int kq = c + 8 * (q & 3) + 32 * b, e = dx_block(kq, E2);
+                    const double ln = p.lognu[bse + (int64_t)jq * s1 + (int64_t)kq * s2];
+                    const double z = ln - lnref - (double)(e * e) * invk -
+                                     exact_y2(colp(kq), jq, E1, invk);
+#pragma unroll
+                    for (int pq = 0; pq < RC * 4; ++pq)
+                        if (pq == q) Z[pq >> 2][pq & 3] = z;
+                }
+                if (c == 0 && r == 0) atomicAdd(&g.ctrl[14], 1);
+            }
+#pragma unroll
+            for (int t = 0; t < RC; ++t) {
+                double mb = fmax(fmax(Z[t][0], Z[t][1]), fmax(Z[t][2], Z[t][3]));
+                mb = max8(mb);
+                const double mn = fmax(m[t], mb);
+                const float sc = __expf((float)(m[t] - mn));
+#pragma unroll
+                for (int k = 0; k < 8; ++k) acc[t][k] *= sc;
+                m[t] = mn;
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int jc = min(c + 8 * u + 32 * b, W2 - 1);
+                float kx[8];
+                ld8(KX1(jc), kx);
+#pragma unroll
+                for (int t = 0; t < RC; ++t) {
+                    const float e0 = __expf((float)(Z[t][u] - m[t]));
+                    const float e = Z[t][u] > kZeroMassLog ? e0 : 0.f;
+#pragma unroll
+                    for (int k = 0; k < 8; ++k) acc[t][k] = fmaf(e, kx[k], acc[t][k]);
+                }
+            }
+        }
+#pragma unroll
+        for (int t = 0; t < RC; ++t) {
+            const float a = rs8(acc[t], c);
+            const int e1 = dx_block(j1[t], E1);
+            double R = m[t] + klog(a) - (double)(e1 * e1) * invk;
+            const bool live = rv[t] && m[t] > kZeroMassLog;
+            if (__builtin_expect(live && !(a >= kFloorF), 0)) {
+                R = kNeedExact;
+                ired[1] = 1;
+                if (c == 0) atomicAdd(&g.ctrl[12], 1);
+            }
+            if (rv[t]) Rr(j1[t])[c] = live ? R : kNegD;
+        }
+    };
+
+    // ---- exact first X pass of the rows marked by `chunk`: the 8 lanes of a row split its
+    //      columns, keep a running maximum and sum per output, then combine
+    auto fix_rows = [&]() {
+        for (int t = 0; t < ntw; ++t) {
+            const int j1 = r + 8 * (w + NW * t), jr = min(j1, W1 - 1);
+            const bool need = j1 < W1 && Rr(jr)[c] == kNeedExact;
+            const unsigned long long bm = __ballot(need);
+            if (!bm) continue;  // wave-uniform
+            const bool rowneed = ((bm >> (8 * r)) & 0xFFull) != 0;
+            float ky[8];
+            ld8(KY2(jr), ky);
+            const double sy2 = *SY2(jr);
+            double mo[8], so[8];
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+                mo[k] = -1e300;
+                so[k] = 0.0;
+            }
+            if (rowneed) {
+                for (int j2 = c; j2 < W2; j2 += 8) {
+                    const double ln = p.lognu[bse + (int64_t)jr * s1 + (int64_t)j2 * s2];
+                    if (!(ln > kZeroMassLog)) continue;
+                    float u2[8];
+                    ld8(U2(j2), u2);
+                    float y = ky[0] * u2[0];
+#pragma unroll
+                    for (int k = 1; k < 8; ++k) y = fmaf(ky[k], u2[k], y);
+                    const double z = y >= kFloorF
+                                         ? ln - lnref - *My(j2) - (klog(y) - sy2)
+                                         : ln - lnref - exact_y2(colp(j2), jr, E1, invk);
+#pragma unroll
+                    for (int k = 0; k < 8; ++k) {
+                        const double d = j2 - k - E2;
+                        const double v = z - d * d * invk;
+                        if (v > mo[k]) {
+                            so[k] = so[k] * (double)__expf((float)(mo[k] - v)) + 1.0;
+                            mo[k] = v;
+                        } else {
+                            so[k] += (double)__expf((float)(v - mo[k]));
+                        }
+                    }
+                }
+            }
+            // combine the 8 lanes of the row: common maximum, rescaled sums
+            float sf[8];
+            double M[8];
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+                M[k] = max8(mo[k]);
+                sf[k] = (float)(so[k] * (double)__expf((float)(mo[k] - M[k])));
+            }
+            const float ssum = rs8(sf, c);
+            double Mc = M[0];
+#pragma unroll
+            for (int k = 1; k < 8; ++k) Mc = c == k ? M[k] : Mc;
+            const int e1 = dx_block(jr, E1);
+            if (need)
+                Rr(jr)[c] = ssum > 0.f ? Mc + (double)__logf(ssum) - (double)(e1 * e1) * invk
+                                       : kNegD;
+        }
+        Tm::sync();
+    };
+
+    // ---- rest of one iteration from f = fc: returns s (first wave) and err ----------------
+    auto iterate = [&](double fc, bool want_err, double& s_out, double& err_out) {
+        if constexpr (LNREG) {
+#pragma unroll
+            for (int ch = 0; ch < RPL / RC; ++ch)
+                if (RC * ch < ntw) chunk(ch);
+        } else {
+            for (int ch = 0; RC * ch < ntw; ++ch) chunk(ch);
+        }
+        Tm::sync();
+        if (__builtin_expect(ired[1] != 0, 0)) {
+            fix_rows();
+            if (tl == 0) ired[1] = 0;
+        }
+        // second X pass: Mx(i2) = max_j1 R, S(i1, i2) = sum_j1 KX2(j1, i1) exp(R - Mx)
+        double mx = kNegD;
+        for (int t = 0; t < ntw; ++t) {
+            const int j1 = r + 8 * (w + NW * t);
+            const double v = Rr(min(j1, W1 - 1))[c];
+            mx = j1 < W1 ? fmax(mx, v) : mx;
+        }
+        mx = maxr(mx);
+        if constexpr (NW > 1) {
+            if (r == 0) xd[w * 8 + c] = mx;
+            Tm::sync();
+            mx = xd[c];
+#pragma unroll
+            for (int q = 1; q < NW; ++q) mx = fmax(mx, xd[q * 8 + c]);
+        }
+        float a2[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) a2[k] = 0.f;
+        for (int t = 0; t < ntw; ++t) {
+            const int j1 = r + 8 * (w + NW * t), jc = min(j1, W1 - 1);
+            const double Rv = Rr(jc)[c];
+            const float u0 = __expf((float)(Rv - mx));
+            const float u4 = (j1 < W1 && Rv > kZeroMassLog) ? u0 : 0.f;
+            float kx[8];
+            ld8(KX2(jc), kx);
+#pragma unroll
+            for (int k = 0; k < 8; ++k) a2[k] = fmaf(kx[k], u4, a2[k]);
+        }
+        float Sv = rsr(a2, r);
+        if constexpr (NW > 1) {
+            xs[w * 64 + lane] = Sv;
+            Tm::sync();
+            if (w == 0) {
+                Sv = xs[lane];
+#pragma unroll
+                for (int q = 1; q < NW; ++q) Sv += xs[q * 64 + lane];
+            }
+        }
+        if (w == 0) {
+            double sr = lnref + mx + klog(Sv);
+            if (__builtin_expect(!(Sv >= kFloorF && mx > kZeroMassLog), 0)) {
+                sr = lnref + exact_x2(rows, r, c, W1, E1, invk);
+                atomicAdd(&g.ctrl[13], 1);
+            }
+            s_out = sr;
+            if (want_err) err_out = wsum(mu > 0.0 ? mu * fabs(expm1(fc + sr)) : 0.0);
+        }
+    };
+
+    // ---- g = -LSE_i [f + log mu - C] over the box, written to p.b -------------------------
+    auto write_g = [&]() {
+        for (int t = 0; t < ntw; ++t) {
+            const int j1 = r + 8 * (w + NW * t);
+            if (j1 >= W1) continue;
+            float ky[8];
+            ld8(KY2(j1), ky);
+            const double sy2 = *SY2(j1);
+            for (int j2 = c; j2 < W2; j2 += 8) {
+                float u2[8];
+                ld8(U2(j2), u2);
+                float y = ky[0] * u2[0];
+#pragma unroll
+                for (int k = 1; k < 8; ++k) y = fmaf(ky[k], u2[k], y);
+                double gv = -(*My(j2) + klog(y) - sy2);
+                if (__builtin_expect(!(y >= kFloorF), 0)) gv = -exact_y2_call(colp(j2), j1, E1, invk);
+                p.b[bse + (int64_t)j1 * s1 + (int64_t)j2 * s2] = gv;
+            }
+        }
+    };
+
+    // One loop for the three modes.  Every pass starts with the first part of the Y-update
+    // from fc; it then either completes an iteration or, as the last pass, writes g.  At a
+    // stop f stays at the start of the last iteration: (f, g) is the pair whose X-marginal
+    // error was measured.
+    double fc = f, err = 0.0, eref = 1e300, s = 0.0;
+    int it = 0;
+    bool gpass = g.mode == kFinal;
+    for (;;) {
+        // a long solve refreshes the absorbed profiles as f moves
+        if (g.mode == kSolve && it > 0 && (it & 15) == 0) build_y(fc);
+        y_first(fc);
+        if (gpass) {
+            write_g();
+            break;
+        }
+        ++it;
+        iterate(fc, g.mode == kSolve || it == K, s, err);
+        if (g.mode == kBatch) {
+            if (it >= K) {
+                if (w == 0) g.f_keep[(int64_t)cell * 64 + xo] = fc;
+                fc = -s;
+                break;
+            }
+            fc = -s;
+            continue;
+        }
+        // the first wave's error, known to every thread (same stop decision everywhere)
+        if constexpr (NW > 1) {
+            if (tl == 0) red[0] = err;
+            Tm::sync();
+            err = red[0];
+        }
+        err = uni(err);
+        bool stop = it >= g.limit || (!g.fixed && err <= g.tol * mass_all);
+        if (!g.fixed && g.stall > 0 && it % g.stall == 0) {
+            if (err > 0.9995 * eref) stop = true;
+            eref = err;
+        }
+        if (stop)
+            gpass = true;
+        else
+            fc = -s;
+    }
+    if (w == 0) p.a[(int64_t)cell * 64 + xo] = fc;
+    if (tl == 0) {
+        if (g.mode == kFinal) {
+            g.iters[cell] = g.ctrl[2];
+        } else {
+            if (g.mode == kSolve) g.iters[cell] = it;
+            g.err[cell] = err;
+            g.mass[cell] = mass_all;
+        }
+    }
+    Tm::sync();
+}
+
+template <int NW, int RPL, bool LNREG, int RC>
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) fast_kernel(FastArgs g) {
+    extern __shared__ __align__(16) char smem[];
+    __shared__ int s_q, s_last;
+    __shared__ double s_red[kBlock / 64];
+    int K = 0;
+    if (g.mode == kBatch) {
+        if (__atomic_load_n(&g.ctrl[2], __ATOMIC_RELAXED) != 0) return;
+        K = min(g.chunk, g.max_iter - __atomic_load_n(&g.ctrl[10], __ATOMIC_RELAXED));
+    }
+    int* queue = &g.ctrl[g.qidx];
+    if constexpr (NW == 1) {
+        const int lane = threadIdx.x & 63;
+        const int slot = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+        const lds_p<char> base = (lds_p<char>)smem + slot * (int)slice_bytes(1, g.W1m, g.W2m);
+        for (;;) {
+            int q = 0;
+            if (lane == 0) q = atomicAdd(queue, 1);
+            q = __builtin_amdgcn_readfirstlane(__shfl(q, 0, 64));
+            if (q >= g.n) break;
+            run_cell<NW, RPL, LNREG, RC>(g, g.cells[q], base, K);
+        }
+    } else {
+        const lds_p<char> base = (lds_p<char>)smem;
+        for (;;) {
+            __syncthreads();
+            if (threadIdx.x == 0) s_q = atomicAdd(queue, 1);
+            __syncthreads();
+            const int q = s_q;
+            if (q >= g.n) break;
+            run_cell<NW, RPL, LNREG, RC>(g, g.cells[q], base, K);
+        }
+    }
+    if (g.mode != kBatch) return;
+    // last workgroup of the round: reduce the per-cell errors in fixed cell order
+    __syncthreads();
+    __threadfence();
+    if (threadIdx.x == 0) s_last = (atomicAdd(&g.ctrl[1], 1) == g.nblocks - 1);
+    __syncthreads();
+    if (!s_last) return;
+    __threadfence();
+    double e = 0.0, m = 0.0;
+    for (int c = threadIdx.x; c < g.p.ncells; c += kBlock) {
+        e += g.err[c];
+        m += g.mass[c];
+    }
+    e = block_sum(e, s_red);
+    m = block_sum(m, s_red);
+    if (threadIdx.x == 0) {
+        const int it = g.ctrl[10] + K;
+        g.dtot[0] = e;
+        g.dtot[1] = m;
+        const bool conv = e <= g.tol * m;
+        if (conv) g.ctrl[4] = 1;
+        g.ctrl[10] = it;
+        if (conv || it >= g.max_iter || !(e == e)) __atomic_store_n(&g.ctrl[2], it, __ATOMIC_RELAXED);
+        g.ctrl[0] = 0;
+        g.ctrl[9] = 0;
+        g.ctrl[1] = 0;
+    }
+}
+
+__global__ void fill_ints(int* p, int n) {
+    for (int i = threadIdx.x; i < n; i += blockDim.x) p[i] = 0;
+}
+
+// one wave per cell: box long side <= 32 (4 rows per lane, one column block)
+#ifndef FAST_WAVE_RC
+#define FAST_WAVE_RC 2
+#endif
+#ifndef FAST_GROUP_RC
+#define FAST_GROUP_RC 2
+#endif
+constexpr int kWaveSide = 32;
+#define FAST_WAVE fast_kernel<1, 4, true, FAST_WAVE_RC>
+#define FAST_GROUP fast_kernel<4, 16, false, FAST_GROUP_RC>
+
+int cus() {
+    static int n = 0;
+    if (!n) {
+        int dev = 0;
+        (void)hipGetDevice(&dev);
+        if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+            n < 1)
+            n = 1;
+    }
+    return n;
+}
+
+template <typename Kern>
+Status prep(Kern k, size_t lds, int items, int& grid) {
+    Status S;
+    DD_HIP(hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize,
+                               (int)lds),
+           S);
+    int per = 0;
+    DD_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k, kBlock, lds), S);
+    grid = std::max(1, std::min(items, std::max(per, 1) * cus()));
+    return S;
+}
+
+}  // namespace
+
+bool fast_eligible(const SkBatch& p, const std::vector<int32_t>& hd) {
+    static const bool off = [] {
+        const char* e = std::getenv("DD_FAST");
+        return e && e[0] == '0';
+    }();
+    if (off || p.prec != DD_PREC_F32 || p.xside != kA) return false;
+    for (int c = 0; c < p.ncells; ++c)
+        if (std::max(hd[2 * c], hd[2 * c + 1]) > kFastMaxSide) return false;
+    return true;
+}
+
+Status fast_solve(const SkBatch& p, const dd_sinkhorn_opts& o, hipStream_t st, SkWork& w,
+                  const std::vector<int32_t>& hd, int32_t* iters, double* errs, FastInfo* info) {
+    Status S;
+    const int n = p.ncells;
+    // classes (kernel frame: long side first), most work first within each
+    std::vector<int32_t> wave_cells, group_cells;
+    int w1w = 1, w2w = 1, w1g = 1, w2g = 1;
+    for (int c = 0; c < n; ++c) {
+        const int a = std::max(std::max(hd[2 * c], hd[2 * c + 1]), 1);
+        const int b = std::max(std::min(hd[2 * c], hd[2 * c + 1]), 1);
+        if (a <= kWaveSide) {
+            wave_cells.push_back(c);
+            w1w = std::max(w1w, a);
+            w2w = std::max(w2w, b);
+        } else {
+            group_cells.push_back(c);
+            w1g = std::max(w1g, a);
+            w2g = std::max(w2g, b);
+        }
+    }
+    auto work = [&](int c) { return (double)std::max(hd[2 * c], 1) * std::max(hd[2 * c + 1], 1); };
+    auto by_work = [&](int a, int b) { return work(a) > work(b); };
+    std::stable_sort(wave_cells.begin(), wave_cells.end(), by_work);
+    std::stable_sort(group_cells.begin(), group_cells.end(), by_work);
+    std::vector<int32_t> ord(group_cells);
+    ord.insert(ord.end(), wave_cells.begin(), wave_cells.end());
+    if (n > w.order_cap) {
+        if (w.order) (void)hipFree(w.order);
+        if (w.scr_off) (void)hipFree(w.scr_off);
+        w.order = nullptr;
+        w.scr_off = nullptr;
+        w.order_cap = std::max(n, 1024);
+        DD_HIP(hipMalloc(&w.order, w.order_cap * sizeof(int32_t)), S);
+        DD_HIP(hipMalloc(&w.scr_off, w.order_cap * sizeof(int64_t)), S);
+    }
+    if (n > 0) {
+        DD_HIP(hipMemcpyAsync(w.order, ord.data(), n * sizeof(int32_t), hipMemcpyHostToDevice, st),
+               S);
+        DD_HIP(hipStreamSynchronize(st), S);  // `ord` goes out of scope with this function
+    }
+    const int ng = (int)group_cells.size(), nw = (int)wave_cells.size();
+    const size_t lds_w = kBlock / 64 * slice_bytes(1, w1w, w2w);
+    const size_t lds_g = slice_bytes(4, w1g, w2g);
+    if (info) {
+        info->n_wave = nw;
+        info->n_group = ng;
+        info->lds_wave = (int)slice_bytes(1, w1w, w2w);
+        info->lds_group = (int)lds_g;
+    }
+    FastArgs ga{}, wa{};
+    ga.p = p;
+    ga.cells = w.order;
+    ga.n = ng;
+    ga.W1m = w1g;
+    ga.W2m = w2g;
+    ga.qidx = 0;
+    wa = ga;
+    wa.cells = w.order + ng;
+    wa.n = nw;
+    wa.W1m = w1w;
+    wa.W2m = w2w;
+    wa.qidx = 9;
+    for (FastArgs* a : {&ga, &wa}) {
+        a->ctrl = w.ctrl;
+        a->iters = iters;
+        a->err = errs;
+        a->mass = w.cell_mass;
+        a->dtot = w.dtot;
+        a->f_keep = w.a_alt;
+        a->tol = o.tol;
+        a->max_iter = o.max_iter;
+    }
+    int grid_g = 0, grid_w = 0;
+    if (ng) {
+        S = prep(FAST_GROUP, lds_g, ng, grid_g);
+        if (S.code) return S;
+    }
+    if (nw) {
+        S = prep(FAST_WAVE, lds_w, (nw + 3) / 4, grid_w);
+        if (S.code) return S;
+    }
+    // the workgroup class runs on the second stream, forked from `st` and joined back
+    const bool two = ng && nw;
+    auto fork = [&]() {
+        if (!two) return;
+        (void)hipEventRecord(w.evf, st);
+        (void)hipStreamWaitEvent(w.stream2, w.evf, 0);
+    };
+    auto join = [&]() {
+        if (!two) return;
+        (void)hipEventRecord(w.evj2, w.stream2);
+        (void)hipStreamWaitEvent(st, w.evj2, 0);
+    };
+    auto launch = [&](const FastArgs& a, int mode) {
+        auto with = [&](FastArgs x) {
+            x.mode = mode;
+            x.limit = a.limit;
+            x.fixed = a.fixed;
+            x.stall = a.stall;
+            x.chunk = a.chunk;
+            x.nblocks = a.nblocks;
+            return x;
+        };
+        if (ng) FAST_GROUP<<<grid_g, kBlock, lds_g, two ? w.stream2 : st>>>(with(ga));
+        if (nw) FAST_WAVE<<<grid_w, kBlock, lds_w, st>>>(with(wa));
+    };
+    fill_ints<<<1, 64, 0, st>>>(w.ctrl, 16);
+    const bool fixed = o.fixed_iters > 0;
+    FastArgs a{};
+    if (fixed || o.stop_rule == DD_STOP_CELL) {
+        a.limit = fixed ? o.fixed_iters : o.max_iter;
+        a.fixed = fixed ? 1 : 0;
+        a.stall = fixed ? 0 : 32;  // a float64 finish follows
+        fork();
+        launch(a, kSolve);
+        join();
+        DD_HIP(hipGetLastError(), S);
+        return S;
+    }
+    a.chunk = std::max(1, o.check_every > 0 ? o.check_every : 8);
+    a.nblocks = (ng ? grid_g : 0) + (nw ? grid_w : 0);
+    // rounds of `chunk` iterations, captured once into a graph of `reps` rounds and replayed;
+    // the host reads the device stop flag between replays
+    const int reps = 4;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    DD_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal), S);
+    for (int k = 0; k < reps; ++k) {
+        fork();
+        launch(a, kBatch);
+        join();
+    }
+    const hipError_t ce = hipStreamEndCapture(st, &graph);
+    if (ce != hipSuccess || hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) != hipSuccess) {
+        if (graph) (void)hipGraphDestroy(graph);
+        S.code = DD_EDEVICE;
+        S.msg = "sinkhorn: HIP graph capture of the iteration failed";
+        return S;
+    }
+    int done = 0;
+    for (int launched = 0; launched < o.max_iter && !done; launched += reps * a.chunk) {
+        if (hipGraphLaunch(exec, st) != hipSuccess ||
+            hipMemcpyAsync(&done, w.ctrl + 2, sizeof(int), hipMemcpyDeviceToHost, st) !=
+                hipSuccess ||
+            hipStreamSynchronize(st) != hipSuccess) {
+            (void)hipGraphExecDestroy(exec);
+            (void)hipGraphDestroy(graph);
+            S.code = DD_EDEVICE;
+            S.msg = "sinkhorn: graph replay failed";
+            return S;
+        }
+    }
+    (void)hipGraphExecDestroy(exec);
+    (void)hipGraphDestroy(graph);
+    fork();
+    launch(a, kFinal);
+    join();
+    DD_HIP(hipGetLastError(), S);
+    return S;
+}
+
+}  // namespace dd

@@ -36,6 +36,8 @@
 //     no-op launches trail the stop, never the result.
 #include "sinkhorn.hpp"
 
+#include "fastcell.hpp"
+
 #include <algorithm>
 #include <cmath>
 #include <map>
@@ -1367,6 +1369,14 @@ Status sk_solve(const SkBatch& p, const dd_sinkhorn_opts& o, hipStream_t caller_
     DD_HIP(hipMemcpyAsync(hb.data(), p.base, hb.size() * 8, hipMemcpyDeviceToHost, st), S);
     DD_HIP(hipStreamSynchronize(st), S);
     const int AS = p.xside;
+    // a box outside [1, max_w] is rejected before any launch (a and b untouched)
+    for (int c = 0; c < p.ncells; ++c)
+        if (hd[2 * c] < 1 || hd[2 * c + 1] < 1 || hd[2 * c] > p.max_w1 ||
+            hd[2 * c + 1] > p.max_w2) {
+            S.code = DD_EINVAL;
+            S.msg = "sinkhorn: a cell's Y box is empty or exceeds max_w1/max_w2";
+            return S;
+        }
     auto work = [&](int c) {
         return sk_cell_terms(AS, std::max(hd[2 * c], 0), std::max(hd[2 * c + 1], 0));
     };
@@ -1408,8 +1418,12 @@ Status sk_solve(const SkBatch& p, const dd_sinkhorn_opts& o, hipStream_t caller_
                E);
         return E;
     };
-    S = put(w.order, w.scr_off, w.order_cap, P);
-    if (S.code) return S;
+    // 8 x 8 blocks in float32 take the register-blocked path (same iteration and rules)
+    const bool fast = fast_eligible(p, hd);
+    if (!fast) {
+        S = put(w.order, w.scr_off, w.order_cap, P);
+        if (S.code) return S;
+    }
     SkBatch q = p;
     q.order = w.order;
     q.scr_off = w.scr_off;
@@ -1434,8 +1448,12 @@ Status sk_solve(const SkBatch& p, const dd_sinkhorn_opts& o, hipStream_t caller_
     DD_HIP(hipStreamSynchronize(st), S);
     DD_HIP(hipEventRecord(w.ev0, st), S);
     zero_ints<<<1, 64, 0, st>>>(w.ctrl, 16);
-    S = p.prec == DD_PREC_F32 ? run_solver<float>(q, P.classes, o, st, w, iters, errs)
-                              : run_solver<double>(q, P.classes, o, st, w, iters, errs);
+    FastInfo fi;
+    if (fast)
+        S = fast_solve(p, o, st, w, hd, iters, errs, &fi);
+    else
+        S = p.prec == DD_PREC_F32 ? run_solver<float>(q, P.classes, o, st, w, iters, errs)
+                                  : run_solver<double>(q, P.classes, o, st, w, iters, errs);
     if (S.code) return S;
     DD_HIP(hipEventRecord(w.ev2, st), S);
     if (finish) {
@@ -1472,21 +1490,34 @@ Status sk_solve(const SkBatch& p, const dd_sinkhorn_opts& o, hipStream_t caller_
     bs.time_ms = ms;
     bs.main_ms = ms_main;
     bs.finish_iters_max = finish ? hctl[8] : 0;
-    bs.n_big = P.n_big;
-    bs.n_giant = P.n_giant;
-    bs.lds_kb[0] = (int32_t)(small_budget / 1024);
-    bs.lds_kb[1] = (int32_t)(big_budget / 1024);
-    bs.tile_small[0] = P.small_tile[0];
-    bs.tile_small[1] = P.small_tile[1];
-    bs.tile_big[0] = P.big_tile[0];
-    bs.tile_big[1] = P.big_tile[1];
+    if (fast) {
+        bs.path = 1;
+        // exact fallbacks: first X pass (rows), second X pass (outputs), Y-update second pass
+        // (rows), Y-update first pass (outputs)
+        bs.tile_small[0] = hctl[12];
+        bs.tile_small[1] = hctl[13];
+        bs.tile_big[0] = hctl[14];
+        bs.tile_big[1] = hctl[15];
+        bs.n_big = fi.n_group;
+        bs.lds_kb[0] = (fi.lds_wave * 4 + 1023) / 1024;
+        bs.lds_kb[1] = (fi.lds_group + 1023) / 1024;
+    } else {
+        bs.n_big = P.n_big;
+        bs.n_giant = P.n_giant;
+        bs.lds_kb[0] = (int32_t)(small_budget / 1024);
+        bs.lds_kb[1] = (int32_t)(big_budget / 1024);
+        bs.tile_small[0] = P.small_tile[0];
+        bs.tile_small[1] = P.small_tile[1];
+        bs.tile_big[0] = P.big_tile[0];
+        bs.tile_big[1] = P.big_tile[1];
+    }
     if (o.fixed_iters > 0)
         bs.converged = 1;
     else if (o.stop_rule == DD_STOP_CELL)
         bs.converged = hctl[7];
     else
         bs.converged = hctl[4];
-    if (bs.lse_terms > 0.0) tuner().record(key, choice, ms_main / bs.lse_terms);
+    if (!fast && bs.lse_terms > 0.0) tuner().record(key, choice, ms_main / bs.lse_terms);
     if (stats) *stats = bs;
     if (!std::isfinite(bs.err)) {
         S.code = DD_ENUMERIC;

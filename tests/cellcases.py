@@ -12,8 +12,13 @@ import oracle
 NEG = -1.0e30
 
 
-def random_cells(rng, ncells, xside, wlo, whi, kappa, zero_x_rows=True, zero_frac=0.1):
+def random_cells(rng, ncells, xside, wlo, whi, kappa, zero_x_rows=True, zero_frac=0.1,
+                 w2=None):
+    """Random cell problems; box sides uniform in [wlo, whi] (the second side in w2 = (lo, hi)
+    when given)."""
     dims = rng.integers(wlo, whi + 1, size=(ncells, 2)).astype(np.int32)
+    if w2 is not None:
+        dims[:, 1] = rng.integers(w2[0], w2[1] + 1, size=ncells)
     sizes = dims[:, 0].astype(np.int64) * dims[:, 1]
     base = np.concatenate([[0], np.cumsum(sizes)[:-1]]).astype(np.int64)
     shift = np.zeros((ncells, 2), np.int32)

@@ -100,6 +100,32 @@ def test_fixed_iters_f32_matches_oracle(xside, kappa, wlo, whi):
         assert abs(eg - eo) <= obar * abs(eo), (c, eg, eo)
 
 
+@pytest.mark.parametrize("shape", ["large", "thin", "tall"])
+def test_register_blocked_path_box_shapes(shape):
+    """The float32 path for 8 x 8 blocks (path 1): boxes up to 300 a side (a workgroup per
+    cell, several column blocks, up to ten rows per lane), and thin boxes of either
+    orientation (transposed on load), against the oracle at a fixed count."""
+    rng = np.random.default_rng({"large": 41, "thin": 42, "tall": 43}[shape])
+    if shape == "large":
+        cells = random_cells(rng, 6, 8, 60, 300, 2.0)
+    elif shape == "thin":
+        cells = random_cells(rng, 9, 8, 1, 3, 1.0, w2=(30, 200))
+    else:
+        cells = random_cells(rng, 9, 8, 30, 200, 1.0, w2=(1, 3))
+    a0 = _a0(rng, cells)
+    a, b, it, er, st, _ = _run(cells, torch.float32, a0=a0, fixed_iters=25)
+    assert st["path"] == 1
+    assert np.all(it == 25)
+    plans, _, _, _ = oracle_solve(cells, a0=a0, fixed_iters=25)
+    for c in range(len(plans)):
+        P = gpu_plan(cells, c, a, b)
+        O = plans[c]
+        m = O.sum()
+        assert np.abs(P - O).sum() <= 3e-5 * m, (c, np.abs(P - O).sum() / m)
+        assert np.abs(P.sum(1) - O.sum(1)).sum() <= 1e-5 * m
+        assert np.abs(P.sum(0) - O.sum(0)).sum() <= 1e-5 * m
+
+
 @pytest.mark.parametrize("dtype", ["f32", "f64"])
 @pytest.mark.parametrize("rule", [0, 1])
 def test_tolerance_solve_matches_oracle(dtype, rule):
