@@ -90,9 +90,10 @@ typedef struct {
     int32_t path;              /* 0: general kernels; 1: register-blocked float32 path for
                                   8 x 8 blocks (n_big = cells per workgroup, the rest one
                                   per wave; lds_kb = LDS per workgroup of each launch;
-                                  exact-fallback counts: tile_small = X-update first
-                                  pass (rows), second pass (outputs); tile_big = Y-update
-                                  second pass (rows), first pass (outputs))                 */
+                                  fallback counts: tile_small = first-X-pass outputs
+                                  held as upper bounds, exact second-X-pass outputs;
+                                  tile_big = second-X-pass repeats after exact first-pass
+                                  outputs, wave blocks with exact Y-update entries)          */
 } dd_batch_stats;
 
 /*

@@ -106,18 +106,18 @@ __device__ __forceinline__ float rs8(const float (&a)[8], int c) {
         e[q] = (b1 ? h[2 + q] : h[q]) + dppf<kDppXor2>(b1 ? h[q] : h[2 + q]);
     return (b0 ? e[1] : e[0]) + dppf<kDppXor1>(b0 ? e[0] : e[1]);
 }
-// The same over the 8 lanes with the same c: lane (r, c) gets the sum of a[r] (partners
-// lane ^ 32, ^ 16, ^ 8).
-__device__ __forceinline__ float rsr(const float (&a)[8], int r) {
+// The same over the 8 lanes with the same c (float64): lane (r, c) gets the sum of a[r]
+// (partners lane ^ 32, ^ 16, ^ 8).
+__device__ __forceinline__ double rsrd(const double (&a)[8], int r) {
     const bool b2 = (r & 4) != 0, b1 = (r & 2) != 0, b0 = (r & 1) != 0;
-    float h[4], e[2];
+    double h[4], e[2];
 #pragma unroll
     for (int q = 0; q < 4; ++q)
         h[q] = (b2 ? a[4 + q] : a[q]) + __shfl_xor(b2 ? a[q] : a[4 + q], 32, 64);
 #pragma unroll
     for (int q = 0; q < 2; ++q)
         e[q] = (b1 ? h[2 + q] : h[q]) + __shfl_xor(b1 ? h[q] : h[2 + q], 16, 64);
-    return (b0 ? e[1] : e[0]) + dppf<kDppRor8>(b0 ? e[0] : e[1]);
+    return (b0 ? e[1] : e[0]) + dppd<kDppRor8>(b0 ? e[0] : e[1]);
 }
 
 template <int NW>
@@ -145,18 +145,18 @@ __device__ __forceinline__ double uni(double v) {
 
 // ---------------------------------------------------------------------------------------
 // LDS slice of one cell (kernel frame: W1 >= W2 after the optional transposition).
-//   fixed part: U1 [64] f32 = exp(WQ), WQ [64] f32 = f + log mu - phi(i2) - ry(i1),
-//               ry [8] f64 (row maxima of f + log mu - phi), red [8] f64 (shared scalars),
-//               phi [8], psi [8] f64 (profiles absorbed into the Y-update kernels), and for
-//               a workgroup team the per-wave partials xd [NW][8] f64, xs [NW][64] f32;
-//   row records (box row j1, 144 B): KY2 [8] (Y-update pass over i1, inputs i1), KX2 [8]
-//               (X-update pass over j1, outputs i1), R [8] f64 (first X pass, minus
-//               dx1(j1)^2 / kappa), sY2 f64
-//               (shift of output j1 of the Y-update's second pass);
-//   column records (box column j2, 192 B): KY1 [8] (Y-update pass over i2, inputs i2),
-//               KX1 [8] (X-update pass over j2, outputs i2), U2 [8] = exp(V - My) over i1,
-//               My f64 (column maximum of V), sY1 f64 (shift of output j2 of the Y-update's
-//               first pass), V [8] f64 = ry + t1 (kept for the exact fallback),
+//   fixed part: U1 [64] f64 = exp(f + log mu - phi(i2) - ry(i1)), ry [8] f64 (row maxima of
+//               f + log mu - phi), red [8] f64 (shared scalars), phi [8], psi [8] f64
+//               (profiles absorbed into the Y-update kernels), and for a workgroup team the
+//               per-wave partials xd [NW][8] f64, xs [2][NW][64] f64;
+//   row records (box row j1, 176 B): KY2 [8] f32 (Y-update pass over i1, inputs i1),
+//               KX2 [8] f64 (X-update pass over j1, outputs i1), R [8] f64 (first X pass,
+//               minus dx1(j1)^2 / kappa), sY2 f64 (shift of output j1 of the Y-update's
+//               second pass), unc [8] u8 (R is only an upper bound, see below);
+//   column records (box column j2, 224 B): KY1 [8] f64 (Y-update pass over i2, inputs i2),
+//               KX1 [8] f32 (X-update pass over j2, outputs i2), U2 [8] f32 = exp(V - psi
+//               - My) over i1, My f64, sY1 f64 (shift of output j2 of the Y-update's first
+//               pass), V [8] f64 = LSE_i2 [f + log mu - cost] (for the exact fallback),
 //               Myx f64 = My + dx2(j2)^2 / kappa.
 // Kernel entries.  The potential f varies across the block by far more than float exp covers
 // at small kappa, and g grows quadratically away from it, so each pass absorbs the bulk of
@@ -166,25 +166,42 @@ __device__ __forceinline__ double uni(double v) {
 //     tau1(j2) the maximum over i2 of the exponent, sY1 = -tau1;
 //   * Y-update, pass over i1: the row profile psi(i1) = max_i2 (f + log mu - phi) at load,
 //     KY2[j1][i1] = exp(psi(i1) - (i1 - j1 + E1)^2 / kappa - tau2(j1)), sY2 = -tau2, and the
-//     pass's input is V - psi with V = LSE_i2 [f + log mu - cost] the first pass's result;
+//     pass's input is V - psi;
 //   * X-update passes (box inputs, X outputs): each input is normalised at the X output
 //     nearest to it, dn = dx(j) the distance of box line j to the block's range, whose
 //     square / kappa is taken out of that input instead (the quadratic growth of g).
-// Any profile gives the same sums; a good one keeps the scaled inputs within float range, so
-// the exact fallbacks stay rare.
+// Any profile gives the same sums.  The two passes over the X block's 8-wide lines (the first
+// Y pass, the second X pass) run in float64 with a float exp split into an exponent and a
+// fraction, so they cannot underflow; the two float32 passes over box lines fall back to
+// exact sums when one underflows (rare with the profiles above), and the first X pass's
+// underflowed outputs are first replaced by an upper bound that is kept whenever it cannot
+// move the second pass's sums.
 // ---------------------------------------------------------------------------------------
-constexpr int kRowB = 144, kColB = 192;  // 16-byte multiples
-constexpr int kOffU1 = 0, kOffWQ = 256, kOffRy = 512, kOffRed = 576, kOffPhi = 640,
-              kOffPsi = 704, kOffXd = 768;
+constexpr int kRowB = 176, kColB = 224;  // 16-byte multiples
+constexpr int kOffU1 = 0, kOffRy = 512, kOffRed = 576, kOffPhi = 640, kOffPsi = 704,
+              kOffXd = 768;
 // row record fields
-constexpr int kRKY2 = 0, kRKX2 = 32, kRR = 64, kRSY2 = 128;
+constexpr int kRKY2 = 0, kRKX2 = 32, kRR = 96, kRSY2 = 160, kRUnc = 168;
 // column record fields
-constexpr int kCKY1 = 0, kCKX1 = 32, kCU2 = 64, kCMy = 96, kCSY1 = 104, kCV = 112, kCMyx = 176;
-constexpr double kNeedExact = 1e300;  // R marker: recompute this output exactly
+constexpr int kCKY1 = 0, kCKX1 = 64, kCU2 = 96, kCMy = 128, kCSY1 = 136, kCV = 144,
+              kCMyx = 208;
 __device__ __forceinline__ double klog(float x) { return (double)__logf(x); }
+// exp of a float64 argument to float accuracy over the whole float64 range: 2^(x log2 e)
+// split into an integer power and a fraction
+__device__ __forceinline__ double exp_wide(double x) {
+    const double t = x * 1.4426950408889634;
+    const double k = fmin(fmax(floor(t), -2000.0), 1000.0);
+    return ldexp((double)exp2f((float)(t - k)), (int)k);
+}
+// log of a positive float64 to float accuracy: mantissa and exponent separately
+__device__ __forceinline__ double log_wide(double x) {
+    int e;
+    const double m = frexp(x, &e);
+    return (double)__logf((float)m) + e * 0.6931471805599453;
+}
 
 __host__ __device__ constexpr int fixed_bytes(int NW) {
-    return NW > 1 ? kOffXd + 64 * NW + 256 * NW : kOffXd;
+    return NW > 1 ? kOffXd + 64 * NW + 1024 * NW : kOffXd;
 }
 
 __host__ __device__ inline size_t slice_bytes(int NW, int W1m, int W2m) {
@@ -206,6 +223,16 @@ __device__ __forceinline__ void ld8(lds_p<float> p, float (&v)[8]) {
 
 // signed distance of box line j to the block's range [e, e + 8) along one axis
 __device__ __forceinline__ int dx_block(int j, int e) { return j - min(max(j, e), e + kA - 1); }
+
+typedef double v2d __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ void ld8d(lds_p<double> p, double (&v)[8]) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const v2d a = *(lds_p<v2d>)(p + 2 * q);
+        v[2 * q] = a.x;
+        v[2 * q + 1] = a.y;
+    }
+}
 
 struct FastArgs {
     SkBatch p;
@@ -245,11 +272,6 @@ __device__ __forceinline__ double exact8(F in, int q, int e, double invk) {
     }
     return m + (double)__logf(s);
 }
-// Y-update, first pass, output (i1, j2), relative to ry: LSE_i2 [WQ(i1, i2) + phi(i2) - cost].
-__device__ __noinline__ double exact_y1(lds_p<float> wq, lds_p<double> phi, int j2, int E2,
-                                        double invk) {
-    return exact8([&](int k) { return (double)wq[k] + phi[k]; }, j2, E2, invk);
-}
 // Y-update, second pass, entry (j1, j2): LSE_i1 [V(i1, j2) - (i1 - j1 + E1)^2 / kappa].
 __device__ __forceinline__ double exact_y2(lds_p<char> col, int j1, int E1, double invk) {
     const lds_p<double> V = (lds_p<double>)(col + kCV);
@@ -262,6 +284,7 @@ __device__ __noinline__ double exact_y2_call(lds_p<char> col, int j1, int E1, do
 // the first pass's result (stored minus dx1(j1)^2 / kappa).
 __device__ __noinline__ double exact_x2(lds_p<char> rows, int i1, int i2, int W1, int E1,
                                         double invk) {
+    // (reached only when every term of the float64 pass is zero)
     auto term = [&](int j1) {
         const double d = j1 - i1 - E1, e = dx_block(j1, E1);
         return *((lds_p<double>)(rows + j1 * kRowB + kRR) + i2) + (e * e - d * d) * invk;
@@ -300,24 +323,24 @@ __device__ __forceinline__ void run_cell(const FastArgs& g, int cell, lds_p<char
     const int xo = T ? c * kA + r : r * kA + c;    // this lane's X point (i1 = r, i2 = c)
     const double invk = 1.0 / p.kappa;
     const float invkf = (float)invk;
-    const lds_p<float> U1 = (lds_p<float>)(sb + kOffU1);
-    const lds_p<float> WQ = (lds_p<float>)(sb + kOffWQ);
+    const lds_p<double> U1 = (lds_p<double>)(sb + kOffU1);
     const lds_p<double> ry = (lds_p<double>)(sb + kOffRy);
     const lds_p<double> red = (lds_p<double>)(sb + kOffRed);
     const lds_p<int> ired = (lds_p<int>)(sb + kOffRed + 32);  // [8] shared ints
     const lds_p<double> phi = (lds_p<double>)(sb + kOffPhi);
     const lds_p<double> psi = (lds_p<double>)(sb + kOffPsi);
     const lds_p<double> xd = (lds_p<double>)(sb + kOffXd);
-    const lds_p<float> xs = (lds_p<float>)(sb + kOffXd + 64 * NW);
+    const lds_p<double> xs = (lds_p<double>)(sb + kOffXd + 64 * NW);  // [2][NW][64]
     const lds_p<char> rows = sb + fixed_bytes(NW);
     const lds_p<char> cols = rows + kRowB * g.W1m;
     auto rowp = [&](int j) { return rows + j * kRowB; };
     auto colp = [&](int j) { return cols + j * kColB; };
     auto KY2 = [&](int j) { return (lds_p<float>)(rowp(j) + kRKY2); };
-    auto KX2 = [&](int j) { return (lds_p<float>)(rowp(j) + kRKX2); };
+    auto KX2 = [&](int j) { return (lds_p<double>)(rowp(j) + kRKX2); };
+    auto UNC = [&](int j) { return (lds_p<unsigned char>)(rowp(j) + kRUnc); };
     auto Rr = [&](int j) { return (lds_p<double>)(rowp(j) + kRR); };
     auto SY2 = [&](int j) { return (lds_p<double>)(rowp(j) + kRSY2); };
-    auto KY1 = [&](int j) { return (lds_p<float>)(colp(j) + kCKY1); };
+    auto KY1 = [&](int j) { return (lds_p<double>)(colp(j) + kCKY1); };
     auto KX1 = [&](int j) { return (lds_p<float>)(colp(j) + kCKX1); };
     auto U2 = [&](int j) { return (lds_p<float>)(colp(j) + kCU2); };
     auto My = [&](int j) { return (lds_p<double>)(colp(j) + kCMy); };
@@ -398,7 +421,7 @@ __device__ __forceinline__ void run_cell(const FastArgs& g, int cell, lds_p<char
     for (int o = tl; o < W1 * 8; o += 64 * NW) {
         const int j1 = o >> 3, k = o & 7;
         const int dx = j1 - k - E1, dnx = dx_block(j1, E1);
-        KX2(j1)[k] = __expf(-(float)(dx * dx - dnx * dnx) * invkf);
+        KX2(j1)[k] = exp_wide(-(double)(dx * dx - dnx * dnx) * invk);
     }
     // Y-update kernel tables with the profiles of f + log mu absorbed (from f = fc)
     auto build_y = [&](double fc) {
@@ -422,7 +445,7 @@ __device__ __forceinline__ void run_cell(const FastArgs& g, int cell, lds_p<char
             if (!(tau > -1e299)) tau = 0.0;
             const double d = k - j2 + E2;
             const bool on = (xcol >> k) & 1u;
-            KY1(j2)[k] = on ? __expf((float)(phi[k] - d * d * invk - tau)) : 0.f;
+            KY1(j2)[k] = on ? exp_wide(phi[k] - d * d * invk - tau) : 0.0;
             if (k == 0) *SY1(j2) = -tau;
         }
         for (int o = tl; o < W1 * 8; o += 64 * NW) {
@@ -447,40 +470,34 @@ __device__ __forceinline__ void run_cell(const FastArgs& g, int cell, lds_p<char
     const int ntw = W1 > 8 * w ? min(RPL, (W1 - 8 * w + 8 * NW - 1) / (8 * NW)) : 0;
     const int nb = (W2 + 31) >> 5;
 
-    // ---- Y-update, first part: U1, WQ, ry (first wave), then per column j2:
-    //      t1 = LSE_i2 [WQ - cost] (relative to ry), V = ry + t1, My = max_i1 V, U2 = exp(V - My)
+    // ---- Y-update, first part: U1, ry (first wave), then per column j2 (float64):
+    //      V = LSE_i2 [f + log mu - cost], My = max_i1 (V - psi), U2 = exp(V - psi - My)
     auto y_first = [&](double fc) {
         if (w == 0) {
             const bool has = mu > 0.0;
             const double wv = has ? fc + lm - phi[c] : kNegD;
             const double ryv = max8(wv);
-            const float wq = has ? (float)(wv - ryv) : kNegF;
-            WQ[lane] = wq;
-            U1[lane] = __expf(wq);
+            U1[lane] = has ? exp_wide(wv - ryv) : 0.0;
             if (c == 0) ry[r] = ryv;
+            if (tl == 0) ired[1] = 0;  // no first-X-pass output is uncertain yet
         }
         Tm::sync();
         for (int j2 = tl >> 1; j2 < W2; j2 += 32 * NW) {  // lanes 2k, 2k + 1 share a column
             const int h = tl & 1;
-            float k1[8];
-            ld8(KY1(j2), k1);
+            double k1[8];
+            ld8d(KY1(j2), k1);
             const double sy = *SY1(j2);
             double v[4];
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
                 const int i1 = 4 * h + q;
-                float a[8];
-                ld8(U1 + i1 * 8, a);
-                float sm = a[0] * k1[0];
+                double a[8];
+                ld8d(U1 + i1 * 8, a);
+                double sm = a[0] * k1[0];
 #pragma unroll
-                for (int k = 1; k < 8; ++k) sm = fmaf(a[k], k1[k], sm);
-                double t1 = klog(sm) - sy;
-                const bool row_has = (xrow >> i1) & 1u;
-                if (__builtin_expect(row_has && !(sm >= kFloorF), 0)) {
-                    t1 = exact_y1(WQ + i1 * kA, phi, j2, E2, invk);
-                    atomicAdd(&g.ctrl[15], 1);
-                }
-                v[q] = row_has ? ry[i1] + t1 : kNegD;
+                for (int k = 1; k < 8; ++k) sm = fma(a[k], k1[k], sm);
+                const bool row_has = ((xrow >> i1) & 1u) && sm > 0.0;
+                v[q] = row_has ? ry[i1] + log_wide(sm) - sy : kNegD;
             }
             {
                 const lds_p<double> V = Vc(j2) + 4 * h;
@@ -577,7 +594,7 @@ __device__ __forceinline__ void run_cell(const FastArgs& g, int cell, lds_p<char
                     for (int pq = 0; pq < RC * 4; ++pq)
                         if (pq == q) Z[pq >> 2][pq & 3] = z;
                 }
-                if (c == 0 && r == 0) atomicAdd(&g.ctrl[14], 1);
+                if (c == 0 && r == 0) atomicAdd(&g.ctrl[15], 1);
             }
 #pragma unroll
             for (int t = 0; t < RC; ++t) {
@@ -609,12 +626,17 @@ __device__ __forceinline__ void run_cell(const FastArgs& g, int cell, lds_p<char
             const int e1 = dx_block(j1[t], E1);
             double R = m[t] + klog(a) - (double)(e1 * e1) * invk;
             const bool live = rv[t] && m[t] > kZeroMassLog;
-            if (__builtin_expect(live && !(a >= kFloorF), 0)) {
-                R = kNeedExact;
+            const bool unc = live && !(a >= kFloorF);
+            if (__builtin_expect(unc, 0)) {
+                // the sum is below the floor: keep an upper bound for now
+                R = m[t] + klog(2.f * kFloorF) - (double)(e1 * e1) * invk;
                 ired[1] = 1;
                 if (c == 0) atomicAdd(&g.ctrl[12], 1);
             }
-            if (rv[t]) Rr(j1[t])[c] = live ? R : kNegD;
+            if (rv[t]) {
+                Rr(j1[t])[c] = live ? R : kNegD;
+                UNC(j1[t])[c] = unc ? 1 : 0;
+            }
         }
     };
 
@@ -623,7 +645,7 @@ __device__ __forceinline__ void run_cell(const FastArgs& g, int cell, lds_p<char
     auto fix_rows = [&]() {
         for (int t = 0; t < ntw; ++t) {
             const int j1 = r + 8 * (w + NW * t), jr = min(j1, W1 - 1);
-            const bool need = j1 < W1 && Rr(jr)[c] == kNeedExact;
+            const bool need = j1 < W1 && UNC(jr)[c] != 0;
             const unsigned long long bm = __ballot(need);
             if (!bm) continue;  // wave-uniform
             const bool rowneed = ((bm >> (8 * r)) & 0xFFull) != 0;
@@ -674,9 +696,11 @@ __device__ __forceinline__ void run_cell(const FastArgs& g, int cell, lds_p<char
 #pragma unroll
             for (int k = 1; k < 8; ++k) Mc = c == k ? M[k] : Mc;
             const int e1 = dx_block(jr, E1);
-            if (need)
+            if (need) {
                 Rr(jr)[c] = ssum > 0.f ? Mc + (double)__logf(ssum) - (double)(e1 * e1) * invk
                                        : kNegD;
+                UNC(jr)[c] = 0;
+            }
         }
         Tm::sync();
     };
@@ -691,56 +715,88 @@ __device__ __forceinline__ void run_cell(const FastArgs& g, int cell, lds_p<char
             for (int ch = 0; RC * ch < ntw; ++ch) chunk(ch);
         }
         Tm::sync();
-        if (__builtin_expect(ired[1] != 0, 0)) {
-            fix_rows();
-            if (tl == 0) ired[1] = 0;
-        }
-        // second X pass: Mx(i2) = max_j1 R, S(i1, i2) = sum_j1 KX2(j1, i1) exp(R - Mx)
-        double mx = kNegD;
-        for (int t = 0; t < ntw; ++t) {
-            const int j1 = r + 8 * (w + NW * t);
-            const double v = Rr(min(j1, W1 - 1))[c];
-            mx = j1 < W1 ? fmax(mx, v) : mx;
-        }
-        mx = maxr(mx);
-        if constexpr (NW > 1) {
-            if (r == 0) xd[w * 8 + c] = mx;
-            Tm::sync();
-            mx = xd[c];
+        // second X pass (float64): Mx(i2) = max_j1 R, S(i1, i2) = sum_j1 KX2(j1, i1) exp(R - Mx),
+        // once without the uncertain first-pass outputs (lo) and once with their upper bounds
+        // (hi).  lo <= exact <= hi: when hi exceeds lo by at most 1e-9 everywhere, lo stands;
+        // otherwise the uncertain outputs are computed exactly and the pass is repeated.
+        for (;;) {
+            double mx = kNegD;
+            for (int t = 0; t < ntw; ++t) {
+                const int j1 = r + 8 * (w + NW * t);
+                const double v = Rr(min(j1, W1 - 1))[c];
+                mx = j1 < W1 ? fmax(mx, v) : mx;
+            }
+            mx = maxr(mx);
+            if constexpr (NW > 1) {
+                if (r == 0) xd[w * 8 + c] = mx;
+                Tm::sync();
+                mx = xd[c];
 #pragma unroll
-            for (int q = 1; q < NW; ++q) mx = fmax(mx, xd[q * 8 + c]);
-        }
-        float a2[8];
+                for (int q = 1; q < NW; ++q) mx = fmax(mx, xd[q * 8 + c]);
+            }
+            double lo[8], hi[8];
 #pragma unroll
-        for (int k = 0; k < 8; ++k) a2[k] = 0.f;
-        for (int t = 0; t < ntw; ++t) {
-            const int j1 = r + 8 * (w + NW * t), jc = min(j1, W1 - 1);
-            const double Rv = Rr(jc)[c];
-            const float u0 = __expf((float)(Rv - mx));
-            const float u4 = (j1 < W1 && Rv > kZeroMassLog) ? u0 : 0.f;
-            float kx[8];
-            ld8(KX2(jc), kx);
+            for (int k = 0; k < 8; ++k) lo[k] = hi[k] = 0.0;
+            for (int t = 0; t < ntw; ++t) {
+                const int j1 = r + 8 * (w + NW * t), jc = min(j1, W1 - 1);
+                const double Rv = Rr(jc)[c];
+                const double u4 = (j1 < W1 && Rv > kZeroMassLog) ? exp_wide(Rv - mx) : 0.0;
+                const double ul = UNC(jc)[c] ? 0.0 : u4;
+                double kx[8];
+                ld8d(KX2(jc), kx);
 #pragma unroll
-            for (int k = 0; k < 8; ++k) a2[k] = fmaf(kx[k], u4, a2[k]);
-        }
-        float Sv = rsr(a2, r);
-        if constexpr (NW > 1) {
-            xs[w * 64 + lane] = Sv;
-            Tm::sync();
+                for (int k = 0; k < 8; ++k) {
+                    hi[k] = fma(kx[k], u4, hi[k]);
+                    lo[k] = fma(kx[k], ul, lo[k]);
+                }
+            }
+            double Slo = rsrd(lo, r), Shi = rsrd(hi, r);
+            if constexpr (NW > 1) {
+                xs[w * 64 + lane] = Slo;
+                xs[(NW + w) * 64 + lane] = Shi;
+                Tm::sync();
+                if (w == 0) {
+                    Slo = xs[lane];
+                    Shi = xs[NW * 64 + lane];
+#pragma unroll
+                    for (int q = 1; q < NW; ++q) {
+                        Slo += xs[q * 64 + lane];
+                        Shi += xs[(NW + q) * 64 + lane];
+                    }
+                }
+            }
+            bool redo = false;
+            if (ired[1] != 0) {  // team-uniform: written before the last synchronisation
+                const bool off = w == 0 && mu > 0.0 && !(Shi <= Slo * (1.0 + 1e-9));
+                if constexpr (NW > 1) {
+                    if (tl == 0) ired[4] = 0;
+                    Tm::sync();
+                    if (off) ired[4] = 1;
+                    Tm::sync();
+                    redo = ired[4] != 0;
+                } else {
+                    redo = __ballot(off) != 0;
+                }
+            }
+            if (__builtin_expect(redo, 0)) {
+                fix_rows();
+                if (tl == 0) {
+                    ired[1] = 0;
+                    atomicAdd(&g.ctrl[14], 1);
+                }
+                Tm::sync();
+                continue;
+            }
             if (w == 0) {
-                Sv = xs[lane];
-#pragma unroll
-                for (int q = 1; q < NW; ++q) Sv += xs[q * 64 + lane];
+                double sr = lnref + mx + log_wide(Slo);
+                if (__builtin_expect(!(Slo > 0.0 && mx > kZeroMassLog), 0)) {
+                    sr = lnref + exact_x2(rows, r, c, W1, E1, invk);
+                    atomicAdd(&g.ctrl[13], 1);
+                }
+                s_out = sr;
+                if (want_err) err_out = wsum(mu > 0.0 ? mu * fabs(expm1(fc + sr)) : 0.0);
             }
-        }
-        if (w == 0) {
-            double sr = lnref + mx + klog(Sv);
-            if (__builtin_expect(!(Sv >= kFloorF && mx > kZeroMassLog), 0)) {
-                sr = lnref + exact_x2(rows, r, c, W1, E1, invk);
-                atomicAdd(&g.ctrl[13], 1);
-            }
-            s_out = sr;
-            if (want_err) err_out = wsum(mu > 0.0 ? mu * fabs(expm1(fc + sr)) : 0.0);
+            break;
         }
     };
 

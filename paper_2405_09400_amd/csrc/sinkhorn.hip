@@ -1492,8 +1492,8 @@ Status sk_solve(const SkBatch& p, const dd_sinkhorn_opts& o, hipStream_t caller_
     bs.finish_iters_max = finish ? hctl[8] : 0;
     if (fast) {
         bs.path = 1;
-        // exact fallbacks: first X pass (rows), second X pass (outputs), Y-update second pass
-        // (rows), Y-update first pass (outputs)
+        // fallbacks: first-X-pass outputs kept as upper bounds, exact second-X-pass outputs,
+        // repeats of the second X pass after exact first-pass outputs, exact Y-update entries
         bs.tile_small[0] = hctl[12];
         bs.tile_small[1] = hctl[13];
         bs.tile_big[0] = hctl[14];
