@@ -122,7 +122,9 @@ __device__ __forceinline__ double rsrd(const double (&a)[8], int r) {
 
 template <int NW>
 struct Team {
-    __device__ static int wave() { return NW == 1 ? 0 : (int)(threadIdx.x >> 6); }
+    __device__ static int wave() {
+        return NW == 1 ? 0 : (int)__builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    }
     // a wave alone works from LDS only and its LDS operations complete in order: keeping the
     // compiler from moving memory operations across this point is all it needs
     __device__ static void sync() {
@@ -185,19 +187,29 @@ constexpr int kRKY2 = 0, kRKX2 = 32, kRR = 96, kRSY2 = 160, kRUnc = 168;
 // column record fields
 constexpr int kCKY1 = 0, kCKX1 = 64, kCU2 = 96, kCMy = 128, kCSY1 = 136, kCV = 144,
               kCMyx = 208;
-__device__ __forceinline__ double klog(float x) { return (double)__logf(x); }
+// exp(x) for x <= 0 by the hardware's base-2 exponential (underflows to 0 below about -87,
+// which no kept term reaches), and ln of a positive normal float to about 1e-7 absolute: the
+// base-2 log of the mantissa in [0.5, 1) plus the exponent, combined in float64
+__device__ __forceinline__ float fexp(float x) {
+    return __builtin_amdgcn_exp2f(x * 1.4426950408889634f);
+}
+__device__ __forceinline__ double klog(float x) {
+    const float m = __builtin_amdgcn_frexp_mantf(x);
+    const int e = __builtin_amdgcn_frexp_expf(x);
+    return ((double)__builtin_amdgcn_logf(m) + (double)e) * 0.6931471805599453;
+}
 // exp of a float64 argument to float accuracy over the whole float64 range: 2^(x log2 e)
 // split into an integer power and a fraction
 __device__ __forceinline__ double exp_wide(double x) {
     const double t = x * 1.4426950408889634;
     const double k = fmin(fmax(floor(t), -2000.0), 1000.0);
-    return ldexp((double)exp2f((float)(t - k)), (int)k);
+    return ldexp((double)__builtin_amdgcn_exp2f((float)(t - k)), (int)k);
 }
 // log of a positive float64 to float accuracy: mantissa and exponent separately
 __device__ __forceinline__ double log_wide(double x) {
     int e;
     const double m = frexp(x, &e);
-    return (double)__logf((float)m) + e * 0.6931471805599453;
+    return ((double)__builtin_amdgcn_logf((float)m) + (double)e) * 0.6931471805599453;
 }
 
 __host__ __device__ constexpr int fixed_bytes(int NW) {
@@ -268,9 +280,9 @@ __device__ __forceinline__ double exact8(F in, int q, int e, double invk) {
 #pragma unroll
     for (int k = 0; k < kA; ++k) {
         const double d = k - q + e;
-        s += __expf((float)(in(k) - d * d * invk - m));
+        s += fexp((float)(in(k) - d * d * invk - m));
     }
-    return m + (double)__logf(s);
+    return m + klog(s);
 }
 // Y-update, second pass, entry (j1, j2): LSE_i1 [V(i1, j2) - (i1 - j1 + E1)^2 / kappa].
 __device__ __forceinline__ double exact_y2(lds_p<char> col, int j1, int E1, double invk) {
@@ -292,8 +304,8 @@ __device__ __noinline__ double exact_x2(lds_p<char> rows, int i1, int i2, int W1
     double m = -1e300;
     for (int j1 = 0; j1 < W1; ++j1) m = fmax(m, term(j1));
     float s = 0.f;
-    for (int j1 = 0; j1 < W1; ++j1) s += __expf((float)(term(j1) - m));
-    return m + (double)__logf(s);
+    for (int j1 = 0; j1 < W1; ++j1) s += fexp((float)(term(j1) - m));
+    return m + klog(s);
 }
 
 // One cell: load, iterate, store.  NW waves per cell, RPL box rows per lane at most, RC rows
@@ -416,7 +428,7 @@ __device__ __forceinline__ void run_cell(const FastArgs& g, int cell, lds_p<char
     for (int o = tl; o < W2 * 8; o += 64 * NW) {
         const int j2 = o >> 3, k = o & 7;
         const int dx = j2 - k - E2, dnx = dx_block(j2, E2);
-        KX1(j2)[k] = __expf(-(float)(dx * dx - dnx * dnx) * invkf);
+        KX1(j2)[k] = fexp(-(float)(dx * dx - dnx * dnx) * invkf);
     }
     for (int o = tl; o < W1 * 8; o += 64 * NW) {
         const int j1 = o >> 3, k = o & 7;
@@ -459,7 +471,7 @@ __device__ __forceinline__ void run_cell(const FastArgs& g, int cell, lds_p<char
             if (!(tau > -1e299)) tau = 0.0;
             const double d = k - j1 + E1;
             const bool on = (xrow >> k) & 1u;
-            KY2(j1)[k] = on ? __expf((float)(psi[k] - d * d * invk - tau)) : 0.f;
+            KY2(j1)[k] = on ? fexp((float)(psi[k] - d * d * invk - tau)) : 0.f;
             if (k == 0) *SY2(j1) = -tau;
         }
         Tm::sync();
@@ -515,10 +527,10 @@ __device__ __forceinline__ void run_cell(const FastArgs& g, int cell, lds_p<char
             double my = fmax(fmax(v[0], v[1]), fmax(v[2], v[3]));
             my = fmax(my, dppd<kDppXor1>(my));
             v4f o;
-            o.x = __expf((float)(v[0] - my));
-            o.y = __expf((float)(v[1] - my));
-            o.z = __expf((float)(v[2] - my));
-            o.w = __expf((float)(v[3] - my));
+            o.x = fexp((float)(v[0] - my));
+            o.y = fexp((float)(v[1] - my));
+            o.z = fexp((float)(v[2] - my));
+            o.w = fexp((float)(v[3] - my));
             *(lds_p<v4f>)(U2(j2) + 4 * h) = o;
             if (h == 0) {
                 const int e = dx_block(j2, E2);
@@ -535,11 +547,12 @@ __device__ __forceinline__ void run_cell(const FastArgs& g, int cell, lds_p<char
     //      R - dx1(j1)^2 / kappa = max + log acc - dx1(j1)^2 / kappa
     auto chunk = [&](int ch) {
         int j1[RC];
-        bool rv[RC];
+        bool rv[RC], tb[RC];  // tb: the wave's block of 8 rows reaches into the box (uniform)
         float ky[RC][8], acc[RC][8];
         double sy2[RC], m[RC];
 #pragma unroll
         for (int t = 0; t < RC; ++t) {
+            tb[t] = 8 * (w + NW * (RC * ch + t)) < W1;
             j1[t] = r + 8 * (w + NW * (RC * ch + t));
             rv[t] = j1[t] < W1;
             const int jr = min(j1[t], W1 - 1);
@@ -552,9 +565,28 @@ __device__ __forceinline__ void run_cell(const FastArgs& g, int cell, lds_p<char
         for (int b = 0; b < nb; ++b) {
             double Z[RC][4];
             unsigned badm = 0;  // entries whose Y-update sum underflowed
+            // log nu_J of the block's entries from global memory, all loads issued up front
+            double lnp[LNREG ? 1 : RC][4];
+            if constexpr (!LNREG) {
+                const double* lnb = p.lognu + bse;
+#pragma unroll
+                for (int t = 0; t < RC; ++t) {
+                    const int jr = min(j1[t], W1 - 1);
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) {
+                        const int jc = min(c + 8 * u + 32 * b, W2 - 1);
+                        lnp[t][u] = lnb[(unsigned)(jr * s1 + jc * s2)];
+                    }
+                }
+            }
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
                 const int j2 = c + 8 * u + 32 * b;
+                if (8 * u + 32 * b >= W2) {  // the whole column block lies past the box
+#pragma unroll
+                    for (int t = 0; t < RC; ++t) Z[t][u] = kNegD;
+                    continue;
+                }
                 const bool cv = j2 < W2;
                 const int jc = min(j2, W2 - 1);
                 float u2[8];
@@ -562,6 +594,10 @@ __device__ __forceinline__ void run_cell(const FastArgs& g, int cell, lds_p<char
                 const double myv = *Myx(jc);
 #pragma unroll
                 for (int t = 0; t < RC; ++t) {
+                    if (!tb[t]) {
+                        Z[t][u] = kNegD;
+                        continue;
+                    }
                     float y = ky[t][0] * u2[0];
 #pragma unroll
                     for (int k = 1; k < 8; ++k) y = fmaf(ky[t][k], u2[k], y);
@@ -569,8 +605,7 @@ __device__ __forceinline__ void run_cell(const FastArgs& g, int cell, lds_p<char
                     if constexpr (LNREG) {
                         lnv = (double)lnr[RC * ch + t][u];
                     } else {
-                        const double v = p.lognu[bse + (int64_t)min(j1[t], W1 - 1) * s1 +
-                                                 (int64_t)jc * s2];
+                        const double v = lnp[t][u];
                         lnv = v > kZeroMassLog ? v - lnref : kNegD;
                     }
                     const bool valid = rv[t] && cv && lnv > kZeroMassLog;
@@ -598,22 +633,25 @@ __device__ __forceinline__ void run_cell(const FastArgs& g, int cell, lds_p<char
             }
 #pragma unroll
             for (int t = 0; t < RC; ++t) {
+                if (!tb[t]) continue;
                 double mb = fmax(fmax(Z[t][0], Z[t][1]), fmax(Z[t][2], Z[t][3]));
                 mb = max8(mb);
                 const double mn = fmax(m[t], mb);
-                const float sc = __expf((float)(m[t] - mn));
+                const float sc = fexp((float)(m[t] - mn));
 #pragma unroll
                 for (int k = 0; k < 8; ++k) acc[t][k] *= sc;
                 m[t] = mn;
             }
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
+                if (8 * u + 32 * b >= W2) continue;
                 const int jc = min(c + 8 * u + 32 * b, W2 - 1);
                 float kx[8];
                 ld8(KX1(jc), kx);
 #pragma unroll
                 for (int t = 0; t < RC; ++t) {
-                    const float e0 = __expf((float)(Z[t][u] - m[t]));
+                    if (!tb[t]) continue;
+                    const float e0 = fexp((float)(Z[t][u] - m[t]));
                     const float e = Z[t][u] > kZeroMassLog ? e0 : 0.f;
 #pragma unroll
                     for (int k = 0; k < 8; ++k) acc[t][k] = fmaf(e, kx[k], acc[t][k]);
@@ -622,6 +660,7 @@ __device__ __forceinline__ void run_cell(const FastArgs& g, int cell, lds_p<char
         }
 #pragma unroll
         for (int t = 0; t < RC; ++t) {
+            if (!tb[t]) continue;
             const float a = rs8(acc[t], c);
             const int e1 = dx_block(j1[t], E1);
             double R = m[t] + klog(a) - (double)(e1 * e1) * invk;
@@ -675,10 +714,10 @@ __device__ __forceinline__ void run_cell(const FastArgs& g, int cell, lds_p<char
                         const double d = j2 - k - E2;
                         const double v = z - d * d * invk;
                         if (v > mo[k]) {
-                            so[k] = so[k] * (double)__expf((float)(mo[k] - v)) + 1.0;
+                            so[k] = so[k] * (double)fexp((float)(mo[k] - v)) + 1.0;
                             mo[k] = v;
                         } else {
-                            so[k] += (double)__expf((float)(v - mo[k]));
+                            so[k] += (double)fexp((float)(v - mo[k]));
                         }
                     }
                 }
@@ -689,7 +728,7 @@ __device__ __forceinline__ void run_cell(const FastArgs& g, int cell, lds_p<char
 #pragma unroll
             for (int k = 0; k < 8; ++k) {
                 M[k] = max8(mo[k]);
-                sf[k] = (float)(so[k] * (double)__expf((float)(mo[k] - M[k])));
+                sf[k] = (float)(so[k] * (double)fexp((float)(mo[k] - M[k])));
             }
             const float ssum = rs8(sf, c);
             double Mc = M[0];
@@ -697,7 +736,7 @@ __device__ __forceinline__ void run_cell(const FastArgs& g, int cell, lds_p<char
             for (int k = 1; k < 8; ++k) Mc = c == k ? M[k] : Mc;
             const int e1 = dx_block(jr, E1);
             if (need) {
-                Rr(jr)[c] = ssum > 0.f ? Mc + (double)__logf(ssum) - (double)(e1 * e1) * invk
+                Rr(jr)[c] = ssum > 0.f ? Mc + klog(ssum) - (double)(e1 * e1) * invk
                                        : kNegD;
                 UNC(jr)[c] = 0;
             }
