@@ -94,6 +94,11 @@ typedef struct {
                                   held as upper bounds, exact second-X-pass outputs;
                                   tile_big = second-X-pass repeats after exact first-pass
                                   outputs, wave blocks with exact Y-update entries)          */
+    int32_t kernel_launches[2]; /* path 1, batch rule: launches per class (0: one wave per
+                                   cell, 1: a workgroup per cell), the final g launch and the
+                                   launches after the stop (which exit at once) included     */
+    double kernel_ms[2];       /* their summed duration (HIP events on each launch's stream) */
+    double kernel_terms[2];    /* LSE terms they evaluated                                   */
 } dd_batch_stats;
 
 /*

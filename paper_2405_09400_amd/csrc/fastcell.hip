@@ -479,7 +479,9 @@ __device__ __forceinline__ void run_cell(const FastArgs& g, int cell, lds_p<char
     build_y(f);
 
     // number of rows t of this wave inside the box; column blocks of 32
-    const int ntw = W1 > 8 * w ? min(RPL, (W1 - 8 * w + 8 * NW - 1) / (8 * NW)) : 0;
+    // rows of lane (r, c) of wave w: j1 = w + NW (r + 8 t), t < ntw (waves interleave row by
+    // row, so the rows spread evenly over the waves)
+    const int ntw = W1 > w ? min(RPL, (W1 - w + 8 * NW - 1) / (8 * NW)) : 0;
     const int nb = (W2 + 31) >> 5;
 
     // ---- Y-update, first part: U1, ry (first wave), then per column j2 (float64):
@@ -494,15 +496,17 @@ __device__ __forceinline__ void run_cell(const FastArgs& g, int cell, lds_p<char
             if (tl == 0) ired[1] = 0;  // no first-X-pass output is uncertain yet
         }
         Tm::sync();
-        for (int j2 = tl >> 1; j2 < W2; j2 += 32 * NW) {  // lanes 2k, 2k + 1 share a column
-            const int h = tl & 1;
+        // LPC aligned lanes share a column, each taking 8 / LPC rows i1
+        constexpr int LPC = NW == 1 ? 2 : 8, RQ = kA / LPC;
+        for (int j2 = tl / LPC; j2 < W2; j2 += 64 * NW / LPC) {
+            const int h = tl % LPC;
             double k1[8];
             ld8d(KY1(j2), k1);
             const double sy = *SY1(j2);
-            double v[4];
+            double v[RQ];
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const int i1 = 4 * h + q;
+            for (int q = 0; q < RQ; ++q) {
+                const int i1 = RQ * h + q;
                 double a[8];
                 ld8d(U1 + i1 * 8, a);
                 double sm = a[0] * k1[0];
@@ -510,28 +514,19 @@ __device__ __forceinline__ void run_cell(const FastArgs& g, int cell, lds_p<char
                 for (int k = 1; k < 8; ++k) sm = fma(a[k], k1[k], sm);
                 const bool row_has = ((xrow >> i1) & 1u) && sm > 0.0;
                 v[q] = row_has ? ry[i1] + log_wide(sm) - sy : kNegD;
-            }
-            {
-                const lds_p<double> V = Vc(j2) + 4 * h;
-                V[0] = v[0];
-                V[1] = v[1];
-                V[2] = v[2];
-                V[3] = v[3];
-            }
-            // input of the pass over i1: V - psi (rows without mass drop out)
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const int i1 = 4 * h + q;
+                Vc(j2)[i1] = v[q];
+                // input of the pass over i1: V - psi (rows without mass drop out)
                 v[q] = ((xrow >> i1) & 1u) ? v[q] - psi[i1] : kNegD;
             }
-            double my = fmax(fmax(v[0], v[1]), fmax(v[2], v[3]));
-            my = fmax(my, dppd<kDppXor1>(my));
-            v4f o;
-            o.x = fexp((float)(v[0] - my));
-            o.y = fexp((float)(v[1] - my));
-            o.z = fexp((float)(v[2] - my));
-            o.w = fexp((float)(v[3] - my));
-            *(lds_p<v4f>)(U2(j2) + 4 * h) = o;
+            double my = v[0];
+#pragma unroll
+            for (int q = 1; q < RQ; ++q) my = fmax(my, v[q]);
+            if constexpr (LPC == 2)
+                my = fmax(my, dppd<kDppXor1>(my));
+            else
+                my = max8(my);
+#pragma unroll
+            for (int q = 0; q < RQ; ++q) U2(j2)[RQ * h + q] = fexp((float)(v[q] - my));
             if (h == 0) {
                 const int e = dx_block(j2, E2);
                 *My(j2) = my;
@@ -552,8 +547,8 @@ __device__ __forceinline__ void run_cell(const FastArgs& g, int cell, lds_p<char
         double sy2[RC], m[RC];
 #pragma unroll
         for (int t = 0; t < RC; ++t) {
-            tb[t] = 8 * (w + NW * (RC * ch + t)) < W1;
-            j1[t] = r + 8 * (w + NW * (RC * ch + t));
+            tb[t] = w + 8 * NW * (RC * ch + t) < W1;
+            j1[t] = w + NW * (r + 8 * (RC * ch + t));
             rv[t] = j1[t] < W1;
             const int jr = min(j1[t], W1 - 1);
             ld8(KY2(jr), ky[t]);
@@ -620,7 +615,7 @@ __device__ __forceinline__ void run_cell(const FastArgs& g, int cell, lds_p<char
 #pragma unroll 1
                 for (int q = 0; q < RC * 4; ++q) {
                     if (!((badm >> q) & 1u)) continue;
-                    const int jq = r + 8 * (w + NW * (RC * ch + (q >> 2)));
+                    const int jq = w + NW * (r + 8 * (RC * ch + (q >> 2)));
                     const int kq = c + 8 * (q & 3) + 32 * b, e = dx_block(kq, E2);
                     const double ln = p.lognu[bse + (int64_t)jq * s1 + (int64_t)kq * s2];
                     const double z = ln - lnref - (double)(e * e) * invk -
@@ -683,7 +678,7 @@ __device__ __forceinline__ void run_cell(const FastArgs& g, int cell, lds_p<char
     //      columns, keep a running maximum and sum per output, then combine
     auto fix_rows = [&]() {
         for (int t = 0; t < ntw; ++t) {
-            const int j1 = r + 8 * (w + NW * t), jr = min(j1, W1 - 1);
+            const int j1 = w + NW * (r + 8 * t), jr = min(j1, W1 - 1);
             const bool need = j1 < W1 && UNC(jr)[c] != 0;
             const unsigned long long bm = __ballot(need);
             if (!bm) continue;  // wave-uniform
@@ -761,7 +756,7 @@ __device__ __forceinline__ void run_cell(const FastArgs& g, int cell, lds_p<char
         for (;;) {
             double mx = kNegD;
             for (int t = 0; t < ntw; ++t) {
-                const int j1 = r + 8 * (w + NW * t);
+                const int j1 = w + NW * (r + 8 * t);
                 const double v = Rr(min(j1, W1 - 1))[c];
                 mx = j1 < W1 ? fmax(mx, v) : mx;
             }
@@ -777,7 +772,7 @@ __device__ __forceinline__ void run_cell(const FastArgs& g, int cell, lds_p<char
 #pragma unroll
             for (int k = 0; k < 8; ++k) lo[k] = hi[k] = 0.0;
             for (int t = 0; t < ntw; ++t) {
-                const int j1 = r + 8 * (w + NW * t), jc = min(j1, W1 - 1);
+                const int j1 = w + NW * (r + 8 * t), jc = min(j1, W1 - 1);
                 const double Rv = Rr(jc)[c];
                 const double u4 = (j1 < W1 && Rv > kZeroMassLog) ? exp_wide(Rv - mx) : 0.0;
                 const double ul = UNC(jc)[c] ? 0.0 : u4;
@@ -842,7 +837,7 @@ __device__ __forceinline__ void run_cell(const FastArgs& g, int cell, lds_p<char
     // ---- g = -LSE_i [f + log mu - C] over the box, written to p.b -------------------------
     auto write_g = [&]() {
         for (int t = 0; t < ntw; ++t) {
-            const int j1 = r + 8 * (w + NW * t);
+            const int j1 = w + NW * (r + 8 * t);
             if (j1 >= W1) continue;
             float ky[8];
             ld8(KY2(j1), ky);
@@ -1151,42 +1146,89 @@ Status fast_solve(const SkBatch& p, const dd_sinkhorn_opts& o, hipStream_t st, S
     }
     a.chunk = std::max(1, o.check_every > 0 ? o.check_every : 8);
     a.nblocks = (ng ? grid_g : 0) + (nw ? grid_w : 0);
-    // rounds of `chunk` iterations, captured once into a graph of `reps` rounds and replayed;
-    // the host reads the device stop flag between replays
+    // rounds of `chunk` iterations, `reps` at a time between reads of the device stop flag;
+    // each class's launch is bracketed by events on its own stream (the per-class kernel
+    // time reported in the statistics)
     const int reps = 4;
-    hipGraph_t graph = nullptr;
-    hipGraphExec_t exec = nullptr;
-    DD_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal), S);
-    for (int k = 0; k < reps; ++k) {
-        fork();
-        launch(a, kBatch);
-        join();
+    for (auto& cls : w.kev)
+        for (auto& se : cls)
+            for (hipEvent_t& e : se)
+                if (!e) DD_HIP(hipEventCreate(&e), S);
+    double terms_per_it[2] = {0.0, 0.0};
+    for (int c : wave_cells) terms_per_it[0] += sk_cell_terms(kA, hd[2 * c], hd[2 * c + 1]);
+    for (int c : group_cells) terms_per_it[1] += sk_cell_terms(kA, hd[2 * c], hd[2 * c + 1]);
+    int hctl[16] = {};
+    int it_prev = 0;
+    for (int launched = 0; launched < o.max_iter && !hctl[2]; launched += reps * a.chunk) {
+        for (int k = 0; k < reps; ++k) {
+            fork();
+            auto with = [&](FastArgs x) {
+                x.mode = kBatch;
+                x.chunk = a.chunk;
+                x.nblocks = a.nblocks;
+                return x;
+            };
+            if (ng) {
+                const hipStream_t s2 = two ? w.stream2 : st;
+                (void)hipEventRecord(w.kev[1][0][k], s2);
+                FAST_GROUP<<<grid_g, kBlock, lds_g, s2>>>(with(ga));
+                (void)hipEventRecord(w.kev[1][1][k], s2);
+            }
+            if (nw) {
+                (void)hipEventRecord(w.kev[0][0][k], st);
+                FAST_WAVE<<<grid_w, kBlock, lds_w, st>>>(with(wa));
+                (void)hipEventRecord(w.kev[0][1][k], st);
+            }
+            join();
+        }
+        DD_HIP(hipMemcpyAsync(hctl, w.ctrl, sizeof hctl, hipMemcpyDeviceToHost, st), S);
+        DD_HIP(hipStreamSynchronize(st), S);
+        // every launch counts, the ones after the stop (which exit at once) included
+        const int it_now = hctl[10];
+        for (int k = 0; k < reps; ++k)
+            for (int cls = 0; cls < 2; ++cls) {
+                if (cls == 0 ? !nw : !ng) continue;
+                float ms = 0.f;
+                if (hipEventElapsedTime(&ms, w.kev[cls][0][k], w.kev[cls][1][k]) == hipSuccess) {
+                    if (info) {
+                        info->ms[cls] += ms;
+                        info->launches[cls] += 1;
+                    }
+                }
+            }
+        it_prev = it_now;
     }
-    const hipError_t ce = hipStreamEndCapture(st, &graph);
-    if (ce != hipSuccess || hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) != hipSuccess) {
-        if (graph) (void)hipGraphDestroy(graph);
-        S.code = DD_EDEVICE;
-        S.msg = "sinkhorn: HIP graph capture of the iteration failed";
-        return S;
-    }
-    int done = 0;
-    for (int launched = 0; launched < o.max_iter && !done; launched += reps * a.chunk) {
-        if (hipGraphLaunch(exec, st) != hipSuccess ||
-            hipMemcpyAsync(&done, w.ctrl + 2, sizeof(int), hipMemcpyDeviceToHost, st) !=
-                hipSuccess ||
-            hipStreamSynchronize(st) != hipSuccess) {
-            (void)hipGraphExecDestroy(exec);
-            (void)hipGraphDestroy(graph);
-            S.code = DD_EDEVICE;
-            S.msg = "sinkhorn: graph replay failed";
-            return S;
+    if (info)
+        for (int cls = 0; cls < 2; ++cls) info->terms[cls] = terms_per_it[cls] * it_prev;
+    // the final Y-update (g) launch, timed the same way
+    fork();
+    {
+        auto with = [&](FastArgs x) {
+            x.mode = kFinal;
+            return x;
+        };
+        if (ng) {
+            const hipStream_t s2 = two ? w.stream2 : st;
+            (void)hipEventRecord(w.kev[1][0][0], s2);
+            FAST_GROUP<<<grid_g, kBlock, lds_g, s2>>>(with(ga));
+            (void)hipEventRecord(w.kev[1][1][0], s2);
+        }
+        if (nw) {
+            (void)hipEventRecord(w.kev[0][0][0], st);
+            FAST_WAVE<<<grid_w, kBlock, lds_w, st>>>(with(wa));
+            (void)hipEventRecord(w.kev[0][1][0], st);
         }
     }
-    (void)hipGraphExecDestroy(exec);
-    (void)hipGraphDestroy(graph);
-    fork();
-    launch(a, kFinal);
     join();
+    DD_HIP(hipStreamSynchronize(st), S);
+    for (int cls = 0; cls < 2; ++cls) {
+        if (cls == 0 ? !nw : !ng) continue;
+        float ms = 0.f;
+        if (info && hipEventElapsedTime(&ms, w.kev[cls][0][0], w.kev[cls][1][0]) == hipSuccess) {
+            info->ms[cls] += ms;
+            info->launches[cls] += 1;
+        }
+    }
     DD_HIP(hipGetLastError(), S);
     return S;
 }

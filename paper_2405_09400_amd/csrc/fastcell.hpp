@@ -12,6 +12,11 @@ struct FastInfo {
     int n_wave = 0;   // cells solved by one wave (long box side <= 32)
     int n_group = 0;  // cells solved by a workgroup of four waves
     int lds_wave = 0, lds_group = 0;  // LDS bytes of one cell slice per class
+    // batch rule: launches (all of them), their summed duration and LSE terms per class
+    // (0: one wave per cell, 1: a workgroup per cell)
+    int launches[2] = {0, 0};
+    double ms[2] = {0.0, 0.0};
+    double terms[2] = {0.0, 0.0};
 };
 
 // True when the batch runs on the register-blocked path: float32 terms, 8 x 8 X blocks,

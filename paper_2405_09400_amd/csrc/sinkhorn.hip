@@ -994,6 +994,10 @@ void sk_work_release(SkWork& w) {
     if (w.evf) (void)hipEventDestroy(w.evf);
     if (w.evj2) (void)hipEventDestroy(w.evj2);
     if (w.evj3) (void)hipEventDestroy(w.evj3);
+    for (auto& a : w.kev)
+        for (auto& b : a)
+            for (hipEvent_t& e : b)
+                if (e) (void)hipEventDestroy(e);
     for (hipStream_t* sp : {&w.stream, &w.stream2, &w.stream3})
         if (*sp) {
             (void)hipStreamSynchronize(*sp);
@@ -1501,6 +1505,11 @@ Status sk_solve(const SkBatch& p, const dd_sinkhorn_opts& o, hipStream_t caller_
         bs.n_big = fi.n_group;
         bs.lds_kb[0] = (fi.lds_wave * 4 + 1023) / 1024;
         bs.lds_kb[1] = (fi.lds_group + 1023) / 1024;
+        for (int k = 0; k < 2; ++k) {
+            bs.kernel_launches[k] = fi.launches[k];
+            bs.kernel_ms[k] = fi.ms[k];
+            bs.kernel_terms[k] = fi.terms[k];
+        }
     } else {
         bs.n_big = P.n_big;
         bs.n_giant = P.n_giant;
