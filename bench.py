@@ -189,6 +189,112 @@ def cpu_baseline(args, w):
                       f"({t_used:.1f}s of solver time)"}
 
 
+# ---- HBM traffic of the dominant kernel (rocprofv3 counters) ------------------------------
+#
+# `traffic` in the roofline line is read from a committed counter summary: FETCH_SIZE and
+# WRITE_SIZE (KiB per dispatch, one rocprofv3 --pmc run each) averaged over the dispatches of
+# the timed steps, each scaled by what the same counter reads for a plain copy of known size
+# (--copy-calibration).  The summary records the SHA-256 of the kernel's source; when the
+# source has changed since, traffic is null.
+
+KERNEL_SOURCE = os.path.join(ROOT, "paper_2405_09400_amd", "csrc", "fastcell.hip")
+TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "fast_kernel_mix512_traffic.md")
+COPY_MIB = 256
+
+
+def source_sha256(path=KERNEL_SOURCE):
+    import hashlib
+    with open(path, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()
+
+
+def copy_calibration():
+    """A plain device copy of COPY_MIB MiB, three times (the counters' reference)."""
+    import torch
+    n = COPY_MIB * 2 ** 20 // 4
+    src = torch.ones(n, device="cuda")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_mib": COPY_MIB, "copies": 3}), flush=True)
+
+
+def _pmc_rows(d):
+    import csv
+    import glob
+    out = []
+    for f in glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True):
+        out += list(csv.DictReader(open(f)))
+    return out
+
+
+def _per_dispatch(rows, name_part):
+    got = {}
+    for r in rows:
+        if name_part in r["Kernel_Name"]:
+            key = int(r["Dispatch_Id"])
+            got[key] = got.get(key, 0.0) + float(r["Counter_Value"])
+    return [got[k] for k in sorted(got)]
+
+
+def traffic_summary(args):
+    """Write the traffic summary from the four counter runs (directories given on the command
+    line): FETCH_SIZE and WRITE_SIZE of the benchmark and of the copy calibration."""
+    fb, wb, fc, wc = args.traffic_from
+    kern = args.traffic_kernel
+    last = args.traffic_last
+    ref_kib = COPY_MIB * 1024.0
+    f_copy = _per_dispatch(_pmc_rows(fc), "copyBuffer")
+    w_copy = _per_dispatch(_pmc_rows(wc), "copyBuffer")
+    ff = ref_kib / (sum(f_copy) / len(f_copy))
+    wf = ref_kib / (sum(w_copy) / len(w_copy))
+    fk = _per_dispatch(_pmc_rows(fb), kern)[-last:]
+    wk = _per_dispatch(_pmc_rows(wb), kern)[-last:]
+    fkib, wkib = sum(fk) / len(fk), sum(wk) / len(wk)
+    rec = {"kernel": kern, "source_sha256": source_sha256(), "dispatches": len(fk),
+           "fetch_kib_per_dispatch": fkib, "write_kib_per_dispatch": wkib,
+           "fetch_factor": ff, "write_factor": wf,
+           "bytes_per_launch": (fkib * ff + wkib * wf) * 1024.0}
+    cmd_b = ("rocprofv3 --pmc {c} --kernel-trace -d <out> -o run --output-format csv -- "
+             "python3 bench.py --steps 3 --warmup 1 --no-compare --no-cpu-baseline")
+    cmd_c = ("rocprofv3 --pmc {c} --kernel-trace -d <out> -o run --output-format csv -- "
+             "python3 bench.py --copy-calibration")
+    lines = [f"# HBM traffic of `{kern}`, mix512 (512², s = 4, κ = 1, tol 1e-5, batch rule)", "",
+             "Commands (from the repository root on the GPU box, after `cd /tmp && export "
+             "TMPDIR=/tmp`; one counter per run):", "", "```",
+             cmd_b.format(c="FETCH_SIZE"), cmd_b.format(c="WRITE_SIZE"),
+             cmd_c.format(c="FETCH_SIZE"), cmd_c.format(c="WRITE_SIZE"), "```", "",
+             f"Summarised by `python bench.py --traffic-from <four output dirs> --traffic-kernel "
+             f"'{kern}' --traffic-last {last}`.", "",
+             "| counter | copy of 256 MiB (KiB) | scale | kernel, KiB per dispatch | bytes per launch |",
+             "|---|---:|---:|---:|---:|",
+             f"| FETCH_SIZE | {sum(f_copy) / len(f_copy):.0f} | {ff:.3f} | {fkib:.1f} | "
+             f"{fkib * ff * 1024:.4g} |",
+             f"| WRITE_SIZE | {sum(w_copy) / len(w_copy):.0f} | {wf:.3f} | {wkib:.1f} | "
+             f"{wkib * wf * 1024:.4g} |", "",
+             f"Averaged over the last {len(fk)} dispatches of the kernel (the launches of the "
+             "timed steps, the ones after the stop, which exit at once, included).", "",
+             "traffic-json: " + json.dumps(rec)]
+    with open(args.traffic_out, "w") as f:
+        f.write("\n".join(lines) + "\n")
+    print("\n".join(lines))
+
+
+def traffic_bytes(kernel_name):
+    """HBM bytes per launch of `kernel_name` from the committed summary, or None when there is
+    none, it covers another kernel, or the kernel's source has changed since."""
+    if not os.path.exists(TRAFFIC_SUMMARY):
+        return None
+    for line in open(TRAFFIC_SUMMARY):
+        if line.startswith("traffic-json: "):
+            rec = json.loads(line[len("traffic-json: "):])
+            if rec["kernel"] in kernel_name and rec["source_sha256"] == source_sha256():
+                return rec["bytes_per_launch"]
+    return None
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -206,7 +312,18 @@ def main():
     ap.add_argument("--replay", type=int, default=4)
     ap.add_argument("--net-weights", default=os.path.join(ROOT, "paper_2405_09400_amd", "weights",
                                                           "warmstart_s4_k1.npz"))
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run the plain copy that calibrates the traffic counters")
+    ap.add_argument("--traffic-from", nargs=4, metavar="DIR",
+                    help="write the traffic summary from four rocprofv3 --pmc output "
+                         "directories: FETCH_SIZE and WRITE_SIZE of the benchmark, then of the copy")
+    ap.add_argument("--traffic-kernel", default="fast_kernel<4, 16, false, 2>")
+    ap.add_argument("--traffic-last", type=int, default=139)
+    ap.add_argument("--traffic-out", default=TRAFFIC_SUMMARY)
     args = ap.parse_args()
+    if args.traffic_from:
+        traffic_summary(args)
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
               "sharding of the method is described in DESIGN.md but not built.", file=sys.stderr)
@@ -217,6 +334,9 @@ def main():
     import paper_2405_09400_amd as dd
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
+    if args.copy_calibration:
+        copy_calibration()
+        return
     dd.lib()
 
     w, ctx, rule, k = setup(args)
@@ -253,6 +373,7 @@ def main():
             k_ms = ms_c
             k_terms = sum(s["sk"]["kernel_terms"][c] for s in stats)
     k_achieved = k_terms / (k_ms * 1e-3)
+    traffic = traffic_bytes(roof_kernel) if roof_kernel.startswith("fast_kernel") else None
     log(f"[bench] steps: sinkhorn iters {sk_iters}, sinkhorn {sk_ms / len(stats):.3f} ms/step, "
         f"wall {wall * 1e3 / len(stats):.3f} ms/step")
 
@@ -286,7 +407,10 @@ def main():
         "roofline": {
             "bound": "alu", "kernel": roof_kernel,
             "achieved": k_achieved / 1e12, "peak": TERM_PEAK / 1e12, "unit": "Tterm/s",
-            "frac": k_achieved / TERM_PEAK, "traffic": None,
+            "frac": k_achieved / TERM_PEAK, "traffic": traffic,
+            "traffic_unit": "HBM bytes per launch",
+            "traffic_gb_s": (traffic / (k_ms / max(k_launch, 1) * 1e-3) / 1e9
+                             if traffic is not None else None),
             "launches": k_launch, "kernel_ms_per_launch": k_ms / max(k_launch, 1),
             "terms_per_launch": k_terms / max(k_launch, 1),
             "all_sinkhorn_kernels_tterm_s": achieved / 1e12,
@@ -300,6 +424,11 @@ def main():
                             "tile_small": s["sk"]["tile_small"], "tile_big": s["sk"]["tile_big"]}
                            for s in stats[:2]],
             "finish_f64_iters": [s["sk"]["finish_iters_max"] for s in stats],
+            "class_kernel_ms_per_step": [sum(s["sk"]["kernel_ms"][c] for s in stats) / len(stats)
+                                         for c in (0, 1)],
+            "class_tterm_s": [sum(s["sk"]["kernel_terms"][c] for s in stats) /
+                              max(sum(s["sk"]["kernel_ms"][c] for s in stats), 1e-9) / 1e9
+                              for c in (0, 1)],
             "main_ms_per_step": sum(s["sk"]["main_ms"] for s in stats) / len(stats),
             "sinkhorn_ms_per_step": sk_ms / len(stats),
             "b2c_ms_per_step": sum(s["t_b2c_ms"] for s in stats) / len(stats),

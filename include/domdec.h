@@ -350,13 +350,20 @@ dd_status domdec_restore(dd_ctx* ctx);
  * cell problem's alpha, the input the paper's GPU Sinkhorn already takes, App. A.1).
  *
  * A 5-layer convolutional net (3x3 kernels, 32 channels, BF16 weights, FP32
- * accumulation) maps a 32x32 window of a cell, centred on its X block in the
- * box-local coordinates of the cell problem, to a predicted Y potential g on the
- * window; the starting X potential is one exact X-update of it,
- *   f(i) = -LSE_w [ g(w) + log nu_J(w) - |o + i - w|^2 / kappa ],  o = (32 - 2s)/2.
- * The stopping rule is untouched: the net changes only where Sinkhorn starts.
- * Window features (6 channels): nu_J feature max(log(nu_J/m_J) + 16, 0)/4 and its
- * support, the same for mu on the X block, and the two window coordinates.
+ * accumulation) maps a 32x32 window of a cell, centred on the X block in the
+ * box-local coordinates of the cell problem, to a correction dg of the Y potential
+ * on the window.  Its base is the previous-iterate start f0 (the zero start on the
+ * first visit of a partition):
+ *   g0(w) = -LSE_i [f0(i) + log mu(i) - |o + i - w|^2 / kappa],  o = (32 - 2s)/2,
+ * made mean-free under the weights nu_J / m_J.  The starting X potential is one
+ * exact X-update of the corrected potential,
+ *   f(i) = -LSE_w [g0(w) + dg(w) + log nu_J(w) - |o + i - w|^2 / kappa],
+ * so dg = 0 gives one Sinkhorn iteration from f0.  The stopping rule is untouched:
+ * the net changes only where Sinkhorn starts.  X blocks of side 2s <= 8 only.
+ * Window features (8 channels): nu_J feature max(log(nu_J/m_J) + 16, 0)/4 and its
+ * support, the same for mu on the X block, the two window coordinates, g0/8 on the
+ * support of nu_J, and f1 - f0 on the X block where mu > 0 (f1: the X-update of g0
+ * over the window).
  * ------------------------------------------------------------------------------ */
 typedef struct dd_net dd_net;
 
@@ -370,7 +377,7 @@ dd_status dd_net_create(const float* params, dd_net** out);
 /* Copy the FP32 master parameters to host memory (dd_net_param_count() floats). */
 dd_status dd_net_params(dd_net* net, float* params_out);
 
-/* Inference on n samples: x (device) [n][6][32][32] float32 -> y (device) [n][32][32]. */
+/* Inference on n samples: x (device) [n][8][32][32] float32 -> y (device) [n][32][32]. */
 dd_status dd_net_forward(dd_net* net, int32_t n, const float* x, float* y, void* stream);
 
 /* One Adam step (lr; betas 0.9, 0.999) on the gauge-invariant weighted squared error
@@ -387,11 +394,12 @@ const char* dd_net_strerror(const dd_net* net);
 dd_status domdec_set_net(dd_ctx* ctx, dd_net* net);
 
 /* Training samples from the last domdec_iterate: for each composite cell of that
- * partition, its window features x [n][6][32][32], the solved Y potential on the
- * window made mean-free under the weights (target [n][32][32]) and the weights
+ * partition, its window features x [n][8][32][32] (from that iteration's zero or
+ * previous-iterate start), the target correction -- the solved Y potential minus g0,
+ * both made mean-free under the weights -- (target [n][32][32]) and the weights
  * nu_J/m_J (weight [n][32][32]); device float32 buffers of the caller.  Two-call:
  * with all three buffers NULL only *n is set.  Errors: DD_ESTATE (no iteration
- * since init or flow_apply), DD_EINVAL (cap < n). */
+ * since init or flow_apply), DD_EINVAL (cap < n, X blocks of side > 8). */
 dd_status domdec_net_samples(dd_ctx* ctx, float* x, float* target, float* weight,
                              int32_t cap, int32_t* n);
 

@@ -312,14 +312,14 @@ class DomDec:
         _check(lib().domdec_set_net(self._ctx, net._net if net is not None else None), self._ctx)
 
     def net_samples(self):
-        """(x [n,6,32,32], target [n,32,32], weight [n,32,32]) float32 device tensors of the
-        cells of the last iteration (features, solved Y potential, weights)."""
+        """(x [n,8,32,32], target [n,32,32], weight [n,32,32]) float32 device tensors of the
+        cells of the last iteration (features, target correction of the Y potential, weights)."""
         import torch
         n = ctypes.c_int32(0)
         _check(lib().domdec_net_samples(self._ctx, None, None, None, 0, ctypes.byref(n)), self._ctx)
         k = int(n.value)
         dev = torch.device("cuda", torch.cuda.current_device())
-        x = torch.empty((k, 6, 32, 32), dtype=torch.float32, device=dev)
+        x = torch.empty((k, 8, 32, 32), dtype=torch.float32, device=dev)
         t = torch.empty((k, 32, 32), dtype=torch.float32, device=dev)
         w = torch.empty((k, 32, 32), dtype=torch.float32, device=dev)
         self._stream.synchronize()
@@ -440,7 +440,7 @@ class WarmStartNet:
 def net_init_params(seed: int = 0) -> np.ndarray:
     """He-normal weights, zero biases, in the dd_net parameter layout (seeded)."""
     rng = np.random.default_rng(seed)
-    layers = [(6, 32), (32, 32), (32, 32), (32, 32), (32, 4)]
+    layers = [(8, 32), (32, 32), (32, 32), (32, 32), (32, 4)]
     out = []
     for l, (cin, cout) in enumerate(layers):
         std = np.sqrt(2.0 / (cin * 9)) if l < len(layers) - 1 else np.sqrt(1.0 / (cin * 9))

@@ -94,6 +94,8 @@ void dd_ctx_release(dd_ctx* c) {
     F(c->d_b);
     F(c->d_nx);
     F(c->d_ng);
+    F(c->d_g0);
+    F(c->d_a0);
     dual_release(c->dual);
     F(c->snap.box);
     F(c->snap.base);
@@ -365,20 +367,28 @@ static dd_status iterate_impl(dd_ctx* c, int p, double eps, const dd_sinkhorn_op
     const double* logmu = c->d_logmu[p];
     launch_b2c(P, c->S, c->C, c->d_nuJ, lognu, hs);
     (void)hipEventRecord(c->ev[1], hs);
+    // the zero or previous-iterate start; a copy is kept as the base of the learned start's
+    // training samples (domdec_net_samples)
+    const size_t na = (size_t)nc * c->AS * c->AS;
+    if (grow(c->d_a0, c->a0_cap, na, st).code) return fail(c, st);
+    const int use_prev = (o.init != DD_INIT_ZERO && c->visited[p]) ? 1 : 0;
+    launch_warm_start(P, c->C, c->AS, apot, c->d_gst[p], c->kappa_a[p], kappa, use_prev, hs);
+    if (hipMemcpyAsync(c->d_a0, apot, na * sizeof(double), hipMemcpyDeviceToDevice, hs) !=
+        hipSuccess)
+        return fail(c, DD_EDEVICE, "domdec_iterate: copying the start failed");
     if (o.init == DD_INIT_NET) {
-        // learned start: features -> net -> one X-update of the predicted Y potential
+        // learned start: features of the previous-iterate start -> net -> one X-update of
+        // the corrected Y potential
         if (grow(c->d_nx, c->nx_cap, (size_t)nc * kNetCin * kNetWin * kNetWin, st).code ||
-            grow(c->d_ng, c->ng_cap, (size_t)nc * kNetWin * kNetWin, st).code)
+            grow(c->d_ng, c->ng_cap, (size_t)nc * kNetWin * kNetWin, st).code ||
+            grow(c->d_g0, c->g0_cap, (size_t)nc * kNetWin * kNetWin, st).code)
             return fail(c, st);
-        launch_net_features(nc, c->AS, c->C.dims, c->C.shift, c->C.base, logmu, lognu, nullptr,
-                            c->d_nx, nullptr, nullptr, hs);
+        launch_net_features(nc, c->AS, c->C.dims, c->C.shift, c->C.base, logmu, lognu, apot,
+                            kappa, nullptr, c->d_nx, c->d_g0, nullptr, nullptr, hs);
         const Status ns = net_forward(c->net, nc, c->d_nx, c->d_ng, hs);
         if (ns.code) return fail(c, ns);
-        launch_net_finit(nc, c->AS, c->C.dims, c->C.shift, c->C.base, lognu, c->C.gofs, c->d_ng,
-                         kappa, apot, c->d_gst[p], hs);
-    } else {
-        const int use_prev = (o.init == DD_INIT_PREV && c->visited[p]) ? 1 : 0;
-        launch_warm_start(P, c->C, c->AS, apot, c->d_gst[p], c->kappa_a[p], kappa, use_prev, hs);
+        launch_net_finit(nc, c->AS, c->C.dims, c->C.shift, c->C.base, lognu, c->C.gofs, c->d_g0,
+                         c->d_ng, kappa, apot, c->d_gst[p], hs);
     }
     (void)hipEventRecord(c->ev[4], hs);
     SkBatch B;
@@ -465,6 +475,8 @@ extern "C" dd_status domdec_iterate(dd_ctx* c, int32_t partition, double eps,
                     "domdec_iterate: init must be DD_INIT_ZERO, DD_INIT_PREV or DD_INIT_NET");
     if (o->init == DD_INIT_NET && !c->net)
         return fail(c, DD_ESTATE, "domdec_iterate: DD_INIT_NET needs a net (domdec_set_net)");
+    if (o->init == DD_INIT_NET && c->AS > 8)
+        return fail(c, DD_EINVAL, "domdec_iterate: DD_INIT_NET needs X blocks of side <= 8");
     return iterate_impl(c, partition, eps, *o, out);
 }
 
@@ -608,8 +620,10 @@ extern "C" dd_status domdec_net_samples(dd_ctx* c, float* x, float* target, floa
     if (!x && !target && !weight) return DD_OK;
     if (!x || !target || !weight || cap < nc)
         return fail(c, DD_EINVAL, "domdec_net_samples: buffers missing or cap < cells");
+    if (c->AS > 8) return fail(c, DD_EINVAL, "domdec_net_samples: needs X blocks of side <= 8");
     launch_net_features(nc, c->AS, c->C.dims, c->C.shift, c->C.base, c->d_logmu[p], c->d_lognu,
-                        c->d_b, x, target, weight, c->st);
+                        c->d_a0, c->last_eps / (c->h * c->h), c->d_b, x, nullptr, target,
+                        weight, c->st);
     if (hipStreamSynchronize(c->st) != hipSuccess || hipGetLastError() != hipSuccess)
         return fail(c, DD_EDEVICE, "domdec_net_samples: kernel failed");
     return DD_OK;

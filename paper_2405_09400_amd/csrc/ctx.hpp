@@ -60,10 +60,14 @@ struct dd_ctx {
     FlowState* flow = nullptr;
     // learned warm start (borrowed net) and its per-cell buffers
     dd_net* net = nullptr;
-    float* d_nx = nullptr;  // [cells][6][32][32] features
+    float* d_nx = nullptr;  // [cells][8][32][32] features
     size_t nx_cap = 0;
-    float* d_ng = nullptr;  // [cells][32][32] predicted Y potentials
+    float* d_ng = nullptr;  // [cells][32][32] predicted corrections of the Y potential
     size_t ng_cap = 0;
+    float* d_g0 = nullptr;  // [cells][32][32] base Y potential of the correction
+    size_t g0_cap = 0;
+    double* d_a0 = nullptr;  // [cells][xside^2] previous-iterate start of the last iteration
+    size_t a0_cap = 0;
     dd::DualWork dual;
     // one saved copy of the mutable state (domdec_save / domdec_restore)
     struct Snap {

@@ -479,9 +479,9 @@ __device__ __forceinline__ void run_cell(const FastArgs& g, int cell, lds_p<char
     build_y(f);
 
     // number of rows t of this wave inside the box; column blocks of 32
-    // rows of lane (r, c) of wave w: j1 = w + NW (r + 8 t), t < ntw (waves interleave row by
-    // row, so the rows spread evenly over the waves)
-    const int ntw = W1 > w ? min(RPL, (W1 - w + 8 * NW - 1) / (8 * NW)) : 0;
+    // rows of lane (r, c) of wave w: j1 = r + 8 (w + NW t), t < ntw (blocks of 8 rows dealt
+    // round the waves; a wave with fewer blocks leaves its SIMD to the other workgroups)
+    const int ntw = W1 > 8 * w ? min(RPL, (W1 - 8 * w + 8 * NW - 1) / (8 * NW)) : 0;
     const int nb = (W2 + 31) >> 5;
 
     // ---- Y-update, first part: U1, ry (first wave), then per column j2 (float64):
@@ -497,7 +497,7 @@ __device__ __forceinline__ void run_cell(const FastArgs& g, int cell, lds_p<char
         }
         Tm::sync();
         // LPC aligned lanes share a column, each taking 8 / LPC rows i1
-        constexpr int LPC = NW == 1 ? 2 : 8, RQ = kA / LPC;
+        constexpr int LPC = 2, RQ = kA / LPC;
         for (int j2 = tl / LPC; j2 < W2; j2 += 64 * NW / LPC) {
             const int h = tl % LPC;
             double k1[8];
@@ -547,8 +547,8 @@ __device__ __forceinline__ void run_cell(const FastArgs& g, int cell, lds_p<char
         double sy2[RC], m[RC];
 #pragma unroll
         for (int t = 0; t < RC; ++t) {
-            tb[t] = w + 8 * NW * (RC * ch + t) < W1;
-            j1[t] = w + NW * (r + 8 * (RC * ch + t));
+            tb[t] = 8 * (w + NW * (RC * ch + t)) < W1;
+            j1[t] = r + 8 * (w + NW * (RC * ch + t));
             rv[t] = j1[t] < W1;
             const int jr = min(j1[t], W1 - 1);
             ld8(KY2(jr), ky[t]);
@@ -615,7 +615,7 @@ __device__ __forceinline__ void run_cell(const FastArgs& g, int cell, lds_p<char
 #pragma unroll 1
                 for (int q = 0; q < RC * 4; ++q) {
                     if (!((badm >> q) & 1u)) continue;
-                    const int jq = w + NW * (r + 8 * (RC * ch + (q >> 2)));
+                    const int jq = r + 8 * (w + NW * (RC * ch + (q >> 2)));
                     const int kq = c + 8 * (q & 3) + 32 * b, e = dx_block(kq, E2);
                     const double ln = p.lognu[bse + (int64_t)jq * s1 + (int64_t)kq * s2];
                     const double z = ln - lnref - (double)(e * e) * invk -
@@ -678,7 +678,7 @@ __device__ __forceinline__ void run_cell(const FastArgs& g, int cell, lds_p<char
     //      columns, keep a running maximum and sum per output, then combine
     auto fix_rows = [&]() {
         for (int t = 0; t < ntw; ++t) {
-            const int j1 = w + NW * (r + 8 * t), jr = min(j1, W1 - 1);
+            const int j1 = r + 8 * (w + NW * t), jr = min(j1, W1 - 1);
             const bool need = j1 < W1 && UNC(jr)[c] != 0;
             const unsigned long long bm = __ballot(need);
             if (!bm) continue;  // wave-uniform
@@ -756,7 +756,7 @@ __device__ __forceinline__ void run_cell(const FastArgs& g, int cell, lds_p<char
         for (;;) {
             double mx = kNegD;
             for (int t = 0; t < ntw; ++t) {
-                const int j1 = w + NW * (r + 8 * t);
+                const int j1 = r + 8 * (w + NW * t);
                 const double v = Rr(min(j1, W1 - 1))[c];
                 mx = j1 < W1 ? fmax(mx, v) : mx;
             }
@@ -772,7 +772,7 @@ __device__ __forceinline__ void run_cell(const FastArgs& g, int cell, lds_p<char
 #pragma unroll
             for (int k = 0; k < 8; ++k) lo[k] = hi[k] = 0.0;
             for (int t = 0; t < ntw; ++t) {
-                const int j1 = w + NW * (r + 8 * t), jc = min(j1, W1 - 1);
+                const int j1 = r + 8 * (w + NW * t), jc = min(j1, W1 - 1);
                 const double Rv = Rr(jc)[c];
                 const double u4 = (j1 < W1 && Rv > kZeroMassLog) ? exp_wide(Rv - mx) : 0.0;
                 const double ul = UNC(jc)[c] ? 0.0 : u4;
@@ -837,7 +837,7 @@ __device__ __forceinline__ void run_cell(const FastArgs& g, int cell, lds_p<char
     // ---- g = -LSE_i [f + log mu - C] over the box, written to p.b -------------------------
     auto write_g = [&]() {
         for (int t = 0; t < ntw; ++t) {
-            const int j1 = w + NW * (r + 8 * t);
+            const int j1 = r + 8 * (w + NW * t);
             if (j1 >= W1) continue;
             float ky[8];
             ld8(KY2(j1), ky);
@@ -911,11 +911,15 @@ __device__ __forceinline__ void run_cell(const FastArgs& g, int cell, lds_p<char
     Tm::sync();
 }
 
+// threads of a workgroup: four one-wave teams, or one team of NW waves
+__host__ __device__ constexpr int team_block(int NW) { return NW == 1 ? kBlock : 64 * NW; }
+
 template <int NW, int RPL, bool LNREG, int RC>
-__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) fast_kernel(FastArgs g) {
+__global__ void __launch_bounds__(team_block(NW)) __attribute__((amdgpu_waves_per_eu(2)))
+fast_kernel(FastArgs g) {
     extern __shared__ __align__(16) char smem[];
     __shared__ int s_q, s_last;
-    __shared__ double s_red[kBlock / 64];
+    __shared__ double s_red[team_block(NW) / 64];
     int K = 0;
     if (g.mode == kBatch) {
         if (__atomic_load_n(&g.ctrl[2], __ATOMIC_RELAXED) != 0) return;
@@ -953,7 +957,7 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))
     if (!s_last) return;
     __threadfence();
     double e = 0.0, m = 0.0;
-    for (int c = threadIdx.x; c < g.p.ncells; c += kBlock) {
+    for (int c = threadIdx.x; c < g.p.ncells; c += team_block(NW)) {
         e += g.err[c];
         m += g.mass[c];
     }
@@ -1001,13 +1005,13 @@ int cus() {
 }
 
 template <typename Kern>
-Status prep(Kern k, size_t lds, int items, int& grid) {
+Status prep(Kern k, int block, size_t lds, int items, int& grid) {
     Status S;
     DD_HIP(hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize,
                                (int)lds),
            S);
     int per = 0;
-    DD_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k, kBlock, lds), S);
+    DD_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k, block, lds), S);
     grid = std::max(1, std::min(items, std::max(per, 1) * cus()));
     return S;
 }
@@ -1029,28 +1033,34 @@ Status fast_solve(const SkBatch& p, const dd_sinkhorn_opts& o, hipStream_t st, S
                   const std::vector<int32_t>& hd, int32_t* iters, double* errs, FastInfo* info) {
     Status S;
     const int n = p.ncells;
-    // classes (kernel frame: long side first), most work first within each
-    std::vector<int32_t> wave_cells, group_cells;
-    int w1w = 1, w2w = 1, w1g = 1, w2g = 1;
+    // Cell classes by the box's long side (kernel frame), most work first within each:
+    //   0: <= 32: one wave per cell (four per workgroup), log nu_J in registers;
+    //   1: the rest: a workgroup of four waves per cell, log nu_J from global memory.
+    using KernFn = void (*)(FastArgs);
+    const KernFn fns[kClasses] = {FAST_WAVE, FAST_GROUP};
+    const int team[kClasses] = {1, 4};
+    const int rpl[kClasses] = {4, 16};  // rows per lane: a team covers 8 * team * rpl rows
+    const int qidx[kClasses] = {9, 0};
+    const hipStream_t streams[kClasses] = {st, w.stream2};
+    std::vector<int32_t> cells[kClasses];
+    int W1m[kClasses] = {1, 1}, W2m[kClasses] = {1, 1};
     for (int c = 0; c < n; ++c) {
         const int a = std::max(std::max(hd[2 * c], hd[2 * c + 1]), 1);
         const int b = std::max(std::min(hd[2 * c], hd[2 * c + 1]), 1);
-        if (a <= kWaveSide) {
-            wave_cells.push_back(c);
-            w1w = std::max(w1w, a);
-            w2w = std::max(w2w, b);
-        } else {
-            group_cells.push_back(c);
-            w1g = std::max(w1g, a);
-            w2g = std::max(w2g, b);
-        }
+        const int k = a <= kWaveSide ? 0 : 1;
+        cells[k].push_back(c);
+        W1m[k] = std::max(W1m[k], a);
+        W2m[k] = std::max(W2m[k], b);
     }
     auto work = [&](int c) { return (double)std::max(hd[2 * c], 1) * std::max(hd[2 * c + 1], 1); };
     auto by_work = [&](int a, int b) { return work(a) > work(b); };
-    std::stable_sort(wave_cells.begin(), wave_cells.end(), by_work);
-    std::stable_sort(group_cells.begin(), group_cells.end(), by_work);
-    std::vector<int32_t> ord(group_cells);
-    ord.insert(ord.end(), wave_cells.begin(), wave_cells.end());
+    std::vector<int32_t> ord;
+    int first[kClasses];
+    for (int k = 0; k < kClasses; ++k) {
+        std::stable_sort(cells[k].begin(), cells[k].end(), by_work);
+        first[k] = (int)ord.size();
+        ord.insert(ord.end(), cells[k].begin(), cells[k].end());
+    }
     if (n > w.order_cap) {
         if (w.order) (void)hipFree(w.order);
         if (w.scr_off) (void)hipFree(w.scr_off);
@@ -1065,71 +1075,85 @@ Status fast_solve(const SkBatch& p, const dd_sinkhorn_opts& o, hipStream_t st, S
                S);
         DD_HIP(hipStreamSynchronize(st), S);  // `ord` goes out of scope with this function
     }
-    const int ng = (int)group_cells.size(), nw = (int)wave_cells.size();
-    const size_t lds_w = kBlock / 64 * slice_bytes(1, w1w, w2w);
-    const size_t lds_g = slice_bytes(4, w1g, w2g);
-    if (info) {
-        info->n_wave = nw;
-        info->n_group = ng;
-        info->lds_wave = (int)slice_bytes(1, w1w, w2w);
-        info->lds_group = (int)lds_g;
-    }
-    FastArgs ga{}, wa{};
-    ga.p = p;
-    ga.cells = w.order;
-    ga.n = ng;
-    ga.W1m = w1g;
-    ga.W2m = w2g;
-    ga.qidx = 0;
-    wa = ga;
-    wa.cells = w.order + ng;
-    wa.n = nw;
-    wa.W1m = w1w;
-    wa.W2m = w2w;
-    wa.qidx = 9;
-    for (FastArgs* a : {&ga, &wa}) {
-        a->ctrl = w.ctrl;
-        a->iters = iters;
-        a->err = errs;
-        a->mass = w.cell_mass;
-        a->dtot = w.dtot;
-        a->f_keep = w.a_alt;
-        a->tol = o.tol;
-        a->max_iter = o.max_iter;
-    }
-    int grid_g = 0, grid_w = 0;
-    if (ng) {
-        S = prep(FAST_GROUP, lds_g, ng, grid_g);
+    FastArgs args[kClasses];
+    size_t lds[kClasses];
+    int grid[kClasses] = {0, 0};
+    int ncls = 0, nblocks = 0;
+    for (int k = 0; k < kClasses; ++k) {
+        const int nk = (int)cells[k].size();
+        lds[k] = team[k] == 1 ? kBlock / 64 * slice_bytes(1, W1m[k], W2m[k])
+                              : slice_bytes(team[k], W1m[k], W2m[k]);
+        FastArgs& a = args[k];
+        a = FastArgs{};
+        a.p = p;
+        a.cells = w.order + first[k];
+        a.n = nk;
+        a.W1m = W1m[k];
+        a.W2m = W2m[k];
+        a.qidx = qidx[k];
+        a.ctrl = w.ctrl;
+        a.iters = iters;
+        a.err = errs;
+        a.mass = w.cell_mass;
+        a.dtot = w.dtot;
+        a.f_keep = w.a_alt;
+        a.tol = o.tol;
+        a.max_iter = o.max_iter;
+        if (info) {
+            info->n[k] = nk;
+            info->lds[k] = (int)lds[k];
+        }
+        if (!nk) continue;
+        if (W1m[k] > 8 * team[k] * rpl[k]) {
+            S.code = DD_EINVAL;
+            S.msg = "sinkhorn: box side beyond the register-blocked teams";
+            return S;
+        }
+        S = prep(fns[k], team_block(team[k]), lds[k], team[k] == 1 ? (nk + 3) / 4 : nk, grid[k]);
         if (S.code) return S;
+        ++ncls;
+        nblocks += grid[k];
     }
-    if (nw) {
-        S = prep(FAST_WAVE, lds_w, (nw + 3) / 4, grid_w);
-        if (S.code) return S;
-    }
-    // the workgroup class runs on the second stream, forked from `st` and joined back
-    const bool two = ng && nw;
+    // the classes run side by side on two streams, the second forked from `st` and joined
+    // back
+    const bool multi = ncls > 1;
     auto fork = [&]() {
-        if (!two) return;
+        if (!multi) return;
         (void)hipEventRecord(w.evf, st);
         (void)hipStreamWaitEvent(w.stream2, w.evf, 0);
     };
     auto join = [&]() {
-        if (!two) return;
+        if (!multi) return;
         (void)hipEventRecord(w.evj2, w.stream2);
         (void)hipStreamWaitEvent(st, w.evj2, 0);
     };
-    auto launch = [&](const FastArgs& a, int mode) {
-        auto with = [&](FastArgs x) {
+    // one launch of every class in `mode`; with `ev` the launches are bracketed by events
+    // (slot `slot`) on their own streams
+    auto launch = [&](const FastArgs& a, int mode, bool ev, int slot) {
+        for (int k = 0; k < kClasses; ++k) {
+            if (!args[k].n) continue;
+            FastArgs x = args[k];
             x.mode = mode;
             x.limit = a.limit;
             x.fixed = a.fixed;
             x.stall = a.stall;
             x.chunk = a.chunk;
             x.nblocks = a.nblocks;
-            return x;
-        };
-        if (ng) FAST_GROUP<<<grid_g, kBlock, lds_g, two ? w.stream2 : st>>>(with(ga));
-        if (nw) FAST_WAVE<<<grid_w, kBlock, lds_w, st>>>(with(wa));
+            const hipStream_t sk = multi ? streams[k] : st;
+            if (ev) (void)hipEventRecord(w.kev[k][0][slot], sk);
+            fns[k]<<<grid[k], team_block(team[k]), lds[k], sk>>>(x);
+            if (ev) (void)hipEventRecord(w.kev[k][1][slot], sk);
+        }
+    };
+    auto collect = [&](int slot) {
+        for (int k = 0; k < kClasses; ++k) {
+            if (!args[k].n || !info) continue;
+            float ms = 0.f;
+            if (hipEventElapsedTime(&ms, w.kev[k][0][slot], w.kev[k][1][slot]) == hipSuccess) {
+                info->ms[k] += ms;
+                info->launches[k] += 1;
+            }
+        }
     };
     fill_ints<<<1, 64, 0, st>>>(w.ctrl, 16);
     const bool fixed = o.fixed_iters > 0;
@@ -1139,96 +1163,43 @@ Status fast_solve(const SkBatch& p, const dd_sinkhorn_opts& o, hipStream_t st, S
         a.fixed = fixed ? 1 : 0;
         a.stall = fixed ? 0 : 32;  // a float64 finish follows
         fork();
-        launch(a, kSolve);
+        launch(a, kSolve, false, 0);
         join();
         DD_HIP(hipGetLastError(), S);
         return S;
     }
     a.chunk = std::max(1, o.check_every > 0 ? o.check_every : 8);
-    a.nblocks = (ng ? grid_g : 0) + (nw ? grid_w : 0);
+    a.nblocks = nblocks;
     // rounds of `chunk` iterations, `reps` at a time between reads of the device stop flag;
-    // each class's launch is bracketed by events on its own stream (the per-class kernel
-    // time reported in the statistics)
+    // every launch is bracketed by events on its own stream (the per-class kernel time of the
+    // statistics), the launches after the stop, which exit at once, included
     const int reps = 4;
     for (auto& cls : w.kev)
         for (auto& se : cls)
             for (hipEvent_t& e : se)
                 if (!e) DD_HIP(hipEventCreate(&e), S);
-    double terms_per_it[2] = {0.0, 0.0};
-    for (int c : wave_cells) terms_per_it[0] += sk_cell_terms(kA, hd[2 * c], hd[2 * c + 1]);
-    for (int c : group_cells) terms_per_it[1] += sk_cell_terms(kA, hd[2 * c], hd[2 * c + 1]);
+    double terms_per_it[kClasses] = {0.0, 0.0};
+    for (int k = 0; k < kClasses; ++k)
+        for (int c : cells[k]) terms_per_it[k] += sk_cell_terms(kA, hd[2 * c], hd[2 * c + 1]);
     int hctl[16] = {};
-    int it_prev = 0;
     for (int launched = 0; launched < o.max_iter && !hctl[2]; launched += reps * a.chunk) {
-        for (int k = 0; k < reps; ++k) {
+        for (int r = 0; r < reps; ++r) {
             fork();
-            auto with = [&](FastArgs x) {
-                x.mode = kBatch;
-                x.chunk = a.chunk;
-                x.nblocks = a.nblocks;
-                return x;
-            };
-            if (ng) {
-                const hipStream_t s2 = two ? w.stream2 : st;
-                (void)hipEventRecord(w.kev[1][0][k], s2);
-                FAST_GROUP<<<grid_g, kBlock, lds_g, s2>>>(with(ga));
-                (void)hipEventRecord(w.kev[1][1][k], s2);
-            }
-            if (nw) {
-                (void)hipEventRecord(w.kev[0][0][k], st);
-                FAST_WAVE<<<grid_w, kBlock, lds_w, st>>>(with(wa));
-                (void)hipEventRecord(w.kev[0][1][k], st);
-            }
+            launch(a, kBatch, true, r);
             join();
         }
         DD_HIP(hipMemcpyAsync(hctl, w.ctrl, sizeof hctl, hipMemcpyDeviceToHost, st), S);
         DD_HIP(hipStreamSynchronize(st), S);
-        // every launch counts, the ones after the stop (which exit at once) included
-        const int it_now = hctl[10];
-        for (int k = 0; k < reps; ++k)
-            for (int cls = 0; cls < 2; ++cls) {
-                if (cls == 0 ? !nw : !ng) continue;
-                float ms = 0.f;
-                if (hipEventElapsedTime(&ms, w.kev[cls][0][k], w.kev[cls][1][k]) == hipSuccess) {
-                    if (info) {
-                        info->ms[cls] += ms;
-                        info->launches[cls] += 1;
-                    }
-                }
-            }
-        it_prev = it_now;
+        for (int r = 0; r < reps; ++r) collect(r);
     }
     if (info)
-        for (int cls = 0; cls < 2; ++cls) info->terms[cls] = terms_per_it[cls] * it_prev;
-    // the final Y-update (g) launch, timed the same way
+        for (int k = 0; k < kClasses; ++k) info->terms[k] = terms_per_it[k] * hctl[10];
+    // the final Y-update (g), timed the same way
     fork();
-    {
-        auto with = [&](FastArgs x) {
-            x.mode = kFinal;
-            return x;
-        };
-        if (ng) {
-            const hipStream_t s2 = two ? w.stream2 : st;
-            (void)hipEventRecord(w.kev[1][0][0], s2);
-            FAST_GROUP<<<grid_g, kBlock, lds_g, s2>>>(with(ga));
-            (void)hipEventRecord(w.kev[1][1][0], s2);
-        }
-        if (nw) {
-            (void)hipEventRecord(w.kev[0][0][0], st);
-            FAST_WAVE<<<grid_w, kBlock, lds_w, st>>>(with(wa));
-            (void)hipEventRecord(w.kev[0][1][0], st);
-        }
-    }
+    launch(a, kFinal, true, 0);
     join();
     DD_HIP(hipStreamSynchronize(st), S);
-    for (int cls = 0; cls < 2; ++cls) {
-        if (cls == 0 ? !nw : !ng) continue;
-        float ms = 0.f;
-        if (info && hipEventElapsedTime(&ms, w.kev[cls][0][0], w.kev[cls][1][0]) == hipSuccess) {
-            info->ms[cls] += ms;
-            info->launches[cls] += 1;
-        }
-    }
+    collect(0);
     DD_HIP(hipGetLastError(), S);
     return S;
 }

@@ -7,16 +7,17 @@
 
 namespace dd {
 
-// Launch split of one solve on the register-blocked path.
+// Launch split of one solve on the register-blocked path, per cell class (box long side
+// <= 32: one wave per cell, log nu_J in registers; larger: a workgroup of four waves per
+// cell).
+constexpr int kClasses = 2;
 struct FastInfo {
-    int n_wave = 0;   // cells solved by one wave (long box side <= 32)
-    int n_group = 0;  // cells solved by a workgroup of four waves
-    int lds_wave = 0, lds_group = 0;  // LDS bytes of one cell slice per class
-    // batch rule: launches (all of them), their summed duration and LSE terms per class
-    // (0: one wave per cell, 1: a workgroup per cell)
-    int launches[2] = {0, 0};
-    double ms[2] = {0.0, 0.0};
-    double terms[2] = {0.0, 0.0};
+    int n[kClasses] = {0, 0};    // cells
+    int lds[kClasses] = {0, 0};  // LDS bytes per workgroup
+    // batch rule: launches (all of them), their summed duration and LSE terms
+    int launches[kClasses] = {0, 0};
+    double ms[kClasses] = {0.0, 0.0};
+    double terms[kClasses] = {0.0, 0.0};
 };
 
 // True when the batch runs on the register-blocked path: float32 terms, 8 x 8 X blocks,

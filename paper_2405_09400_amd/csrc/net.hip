@@ -299,29 +299,109 @@ __device__ __forceinline__ float feat(double lv, double lm) {
 }
 
 // Features of cell J on the 32x32 window; window position w maps to box-local j = w - o + E
-// and to X pixel i = w - o (o = (32 - xside)/2).
+// and to X pixel i = w - o (o = (32 - xside)/2).  One workgroup per cell:
+//   1. the cell's mass m_J, and f0 + log mu on the X block (LDS);
+//   2. g0(w) = -LSE_i [f0(i) + log mu(i) - C(i, w)] on the support of nu_J in the window;
+//   3. its mean under the weights nu_J / m_J, taken out;
+//   4. f1(i) = -LSE_w [g0(w) + log nu_J(w) - C(i, w)] on the X block (four lanes per X
+//      point, a quarter of the window each), and the channels.
 __global__ void __launch_bounds__(kT)
     net_features_kernel(int ncell, int xside, const int32_t* __restrict__ dims,
                         const int32_t* __restrict__ shift, const int64_t* __restrict__ base,
                         const double* __restrict__ logmu, const double* __restrict__ lognu,
-                        const double* __restrict__ b, float* __restrict__ x,
-                        float* __restrict__ tgt, float* __restrict__ wgt) {
+                        const double* __restrict__ a0, float invk, const double* __restrict__ b,
+                        float* __restrict__ x, float* __restrict__ g0, float* __restrict__ tgt,
+                        float* __restrict__ wgt) {
     __shared__ double red[8];
+    __shared__ double fx[64];         // f0 + log mu on the X block (kNegD without mass)
+    __shared__ float gv[kNetWin * kNetWin];  // g0 + log nu_J - lm (kNegF off the support)
+    __shared__ float gs[kNetWin * kNetWin];  // g0 (raw)
+    __shared__ float df[64];          // f1 - f0
     constexpr int W2 = kNetWin * kNetWin;
     const int N2 = xside * xside, o = (kNetWin - xside) / 2;
     for (int J = blockIdx.x; J < ncell; J += gridDim.x) {
         double m = 0.0;
         for (int i = threadIdx.x; i < N2; i += kT) {
             const double l = logmu[(int64_t)J * N2 + i];
-            if (l > kZeroMassLog) m += exp(l);
+            const bool h = l > kZeroMassLog;
+            if (h) m += exp(l);
+            fx[i] = h ? a0[(int64_t)J * N2 + i] + l : kNegD;
         }
-        m = block_sum(m, red);
+        m = block_sum(m, red);  // synchronises, so fx is complete
         const double lm = log(m);
         const int W1 = dims[2 * J], Wd2 = dims[2 * J + 1];
         const int E1 = shift[2 * J], E2 = shift[2 * J + 1];
         const int64_t bs = base[J];
+        double sw = 0.0, swp = 0.0, swg = 0.0;
+        for (int k = threadIdx.x; k < W2; k += kT) {
+            const int w1 = k / kNetWin, w2 = k % kNetWin;
+            const int j1 = w1 - o + E1, j2 = w2 - o + E2;
+            const bool inbox = j1 >= 0 && j1 < W1 && j2 >= 0 && j2 < Wd2;
+            const double ln = inbox ? lognu[bs + (int64_t)j1 * Wd2 + j2] : kNegD;
+            const bool has = ln > kZeroMassLog;
+            double g = 0.0;
+            if (has) {
+                double mx = kNegD;
+                for (int i = 0; i < N2; ++i) {
+                    const double d1 = o + i / xside - w1, d2 = o + i % xside - w2;
+                    mx = fmax(mx, fx[i] - (d1 * d1 + d2 * d2) * invk);
+                }
+                float sm = 0.f;
+                for (int i = 0; i < N2; ++i) {
+                    const double d1 = o + i / xside - w1, d2 = o + i % xside - w2;
+                    sm += __expf((float)(fx[i] - (d1 * d1 + d2 * d2) * invk - mx));
+                }
+                g = -(mx + log((double)sm));
+            }
+            const double wt = has ? exp(ln - lm) : 0.0;
+            gs[k] = (float)g;
+            gv[k] = has ? (float)(g + ln - lm) : kNegF;
+            sw += wt;
+            swp += wt * g;
+            if (tgt) {
+                swg += has ? wt * b[bs + (int64_t)j1 * Wd2 + j2] : 0.0;
+                wgt[(int64_t)J * W2 + k] = (float)wt;
+            }
+        }
+        sw = block_sum(sw, red);
+        swp = block_sum(swp, red);
+        const double gpm = sw > 0.0 ? swp / sw : 0.0;
+        // f1 on the X block: lane t takes X point t / 4 and the window rows q = t % 4 (mod 4)
+        {
+            const int i = threadIdx.x >> 2, q = threadIdx.x & 3;
+            const bool live = i < N2;
+            const int i1 = live ? i / xside : 0, i2 = live ? i % xside : 0;
+            float mx = kNegF;
+            for (int w1 = q; w1 < kNetWin; w1 += 4)
+                for (int w2 = 0; w2 < kNetWin; ++w2) {
+                    const float d1 = (float)(o + i1 - w1), d2 = (float)(o + i2 - w2);
+                    mx = fmaxf(mx, gv[w1 * kNetWin + w2] - (d1 * d1 + d2 * d2) * invk);
+                }
+            mx = fmaxf(mx, __shfl_xor(mx, 1, 64));
+            mx = fmaxf(mx, __shfl_xor(mx, 2, 64));
+            float sm = 0.f;
+            if (mx > 0.5f * kNegF)
+                for (int w1 = q; w1 < kNetWin; w1 += 4)
+                    for (int w2 = 0; w2 < kNetWin; ++w2) {
+                        const float d1 = (float)(o + i1 - w1), d2 = (float)(o + i2 - w2);
+                        sm += __expf(gv[w1 * kNetWin + w2] - (d1 * d1 + d2 * d2) * invk - mx);
+                    }
+            sm += __shfl_xor(sm, 1, 64);
+            sm += __shfl_xor(sm, 2, 64);
+            if (live && q == 0) {
+                // f1 = -(lm + mx + log sm); the gauge of g0 cancels in f1 - f0
+                const bool ok = fx[i] > 0.5 * kNegD && mx > 0.5f * kNegF && sm > 0.f;
+                const double f0 = ok ? fx[i] - logmu[(int64_t)J * N2 + i] : 0.0;
+                df[i] = ok ? (float)(-(lm + (double)mx + log((double)sm)) - f0) : 0.f;
+            }
+        }
+        if (tgt) {
+            swg = block_sum(swg, red);  // also makes df visible
+        } else {
+            __syncthreads();
+        }
+        const double gm = sw > 0.0 ? swg / sw : 0.0;
         float* xc = x + (int64_t)J * kNetCin * W2;
-        double sw = 0.0, swg = 0.0;
         for (int k = threadIdx.x; k < W2; k += kT) {
             const int w1 = k / kNetWin, w2 = k % kNetWin;
             const int j1 = w1 - o + E1, j2 = w2 - o + E2;
@@ -332,45 +412,32 @@ __global__ void __launch_bounds__(kT)
             const bool inx = i1 >= 0 && i1 < xside && i2 >= 0 && i2 < xside;
             const double lmu = inx ? logmu[(int64_t)J * N2 + i1 * xside + i2] : kNegD;
             const bool hmu = lmu > kZeroMassLog;
+            const float gc = has ? (float)((double)gs[k] - gpm) : 0.f;
             xc[0 * W2 + k] = has ? feat(ln, lm) : 0.f;
             xc[1 * W2 + k] = has ? 1.f : 0.f;
             xc[2 * W2 + k] = hmu ? feat(lmu, lm) : 0.f;
             xc[3 * W2 + k] = hmu ? 1.f : 0.f;
             xc[4 * W2 + k] = (w1 - 15.5f) * (1.f / 16.f);
             xc[5 * W2 + k] = (w2 - 15.5f) * (1.f / 16.f);
-            if (tgt) {
-                const double w = has ? exp(ln - lm) : 0.0;
-                const double g = has ? b[bs + (int64_t)j1 * Wd2 + j2] : 0.0;
-                sw += w;
-                swg += w * g;
-                wgt[(int64_t)J * W2 + k] = (float)w;
-            }
-        }
-        if (tgt) {
-            sw = block_sum(sw, red);
-            swg = block_sum(swg, red);
-            const double gm = sw > 0.0 ? swg / sw : 0.0;
-            for (int k = threadIdx.x; k < W2; k += kT) {
-                const int w1 = k / kNetWin, w2 = k % kNetWin;
-                const int j1 = w1 - o + E1, j2 = w2 - o + E2;
-                const bool inbox = j1 >= 0 && j1 < W1 && j2 >= 0 && j2 < Wd2;
-                const double ln = inbox ? lognu[bs + (int64_t)j1 * Wd2 + j2] : kNegD;
+            xc[6 * W2 + k] = gc * 0.125f;
+            xc[7 * W2 + k] = hmu ? df[i1 * xside + i2] : 0.f;
+            if (g0) g0[(int64_t)J * W2 + k] = gc;
+            if (tgt)
                 tgt[(int64_t)J * W2 + k] =
-                    ln > kZeroMassLog ? (float)(b[bs + (int64_t)j1 * Wd2 + j2] - gm) : 0.f;
-            }
+                    has ? (float)(b[bs + (int64_t)j1 * Wd2 + j2] - gm) - gc : 0.f;
         }
         __syncthreads();
     }
 }
 
-// f(i) = -LSE_w [ghat(w) + log nu_J(w) - ((o + i1 - w1)^2 + (o + i2 - w2)^2) / kappa] over
-// the window positions inside the box with nu_J > 0.
+// f(i) = -LSE_w [g0(w) + dg(w) + log nu_J(w) - ((o + i1 - w1)^2 + (o + i2 - w2)^2) / kappa]
+// over the window positions inside the box with nu_J > 0.
 __global__ void __launch_bounds__(kT)
     net_finit_kernel(int ncell, int xside, const int32_t* __restrict__ dims,
                      const int32_t* __restrict__ shift, const int64_t* __restrict__ base,
                      const double* __restrict__ lognu, const int32_t* __restrict__ gofs,
-                     const float* __restrict__ ghat, float invk, double* __restrict__ a,
-                     int32_t* __restrict__ g_stored) {
+                     const float* __restrict__ g0, const float* __restrict__ dg, float invk,
+                     double* __restrict__ a, int32_t* __restrict__ g_stored) {
     constexpr int W2 = kNetWin * kNetWin;
     __shared__ float v[W2];
     const int N2 = xside * xside, o = (kNetWin - xside) / 2;
@@ -384,7 +451,9 @@ __global__ void __launch_bounds__(kT)
             const int j1 = w1 - o + E1, j2 = w2 - o + E2;
             const bool inbox = j1 >= 0 && j1 < W1 && j2 >= 0 && j2 < Wd2;
             const double ln = inbox ? lognu[bs + (int64_t)j1 * Wd2 + j2] : kNegD;
-            v[k] = ln > kZeroMassLog ? ghat[(int64_t)J * W2 + k] + (float)ln : kNegF;
+            v[k] = ln > kZeroMassLog
+                       ? g0[(int64_t)J * W2 + k] + dg[(int64_t)J * W2 + k] + (float)ln
+                       : kNegF;
         }
         __syncthreads();
         for (int i = threadIdx.x; i < N2; i += kT) {
@@ -445,19 +514,22 @@ int64_t net_param_count() { return table().n; }
 
 void launch_net_features(int ncell, int xside, const int32_t* dims, const int32_t* shift,
                          const int64_t* base, const double* logmu, const double* lognu,
-                         const double* b, float* x, float* tgt, float* wgt, hipStream_t st) {
+                         const double* a0, double kappa, const double* b, float* x, float* g0,
+                         float* tgt, float* wgt, hipStream_t st) {
     if (ncell <= 0) return;
     net_features_kernel<<<grid_n(ncell, 4096), kT, 0, st>>>(ncell, xside, dims, shift, base,
-                                                            logmu, lognu, b, x, tgt, wgt);
+                                                            logmu, lognu, a0,
+                                                            (float)(1.0 / kappa), b, x, g0,
+                                                            tgt, wgt);
 }
 
 void launch_net_finit(int ncell, int xside, const int32_t* dims, const int32_t* shift,
                       const int64_t* base, const double* lognu, const int32_t* gofs,
-                      const float* ghat, double kappa, double* a, int32_t* g_stored,
-                      hipStream_t st) {
+                      const float* g0, const float* dg, double kappa, double* a,
+                      int32_t* g_stored, hipStream_t st) {
     if (ncell <= 0) return;
     net_finit_kernel<<<grid_n(ncell, 4096), kT, 0, st>>>(ncell, xside, dims, shift, base, lognu,
-                                                         gofs, ghat, (float)(1.0 / kappa), a,
+                                                         gofs, g0, dg, (float)(1.0 / kappa), a,
                                                          g_stored);
 }
 

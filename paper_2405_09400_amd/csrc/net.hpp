@@ -2,20 +2,25 @@
 //
 // The net maps a 32x32 window of the cell -- centred on the X block in the box-local
 // coordinates of the cell problem, so that window position w and X pixel i are at cost
-// |o + i - w|^2 / kappa with o = (32 - xside)/2 -- to a predicted Y potential g on that
-// window.  The X potential used to start Sinkhorn is then one exact X-update of the
-// prediction, f(i) = -LSE_w [g(w) + log nu_J(w) - C(i, w)], which is the slot for the
-// initial alpha of the cell solve (App. A.1, Alg. "SinkhornGPU" input alpha_init).
-// The stopping rule of the solve is untouched, so the prediction only changes where the
-// iteration starts.
+// |o + i - w|^2 / kappa with o = (32 - xside)/2 -- to a correction of the Y potential on
+// that window.  Its base is the previous-iterate start f0 (the X potential of the last
+// visit of the partition): g0(w) = -LSE_i [f0(i) + log mu(i) - C(i, w)], made mean-free
+// under the weights nu_J / m_J.  The X potential used to start Sinkhorn is one exact
+// X-update of the corrected potential, f(i) = -LSE_w [g0(w) + dg(w) + log nu_J(w) - C(i, w)],
+// which is the slot for the initial alpha of the cell solve (App. A.1, Alg. "SinkhornGPU"
+// input alpha_init).  With dg = 0 this is one Sinkhorn iteration from f0.  The stopping
+// rule of the solve is untouched, so the prediction only changes where the iteration
+// starts.
 //
 // Layers (3x3 kernels, 32 channels, BF16 weights, FP32 accumulation, ReLU between):
-//   L1  6 -> 32, stride 2      32x32 -> 16x16
+//   L1  8 -> 32, stride 2      32x32 -> 16x16
 //   L2 32 -> 32, dilation 1    16x16
 //   L3 32 -> 32, dilation 2    16x16
 //   L4 32 -> 32, dilation 4    16x16
 //   L5 32 -> 4,  dilation 1    16x16, pixel-shuffled to the 32x32 output (no ReLU)
-// Input channels: nu_J feature and support, mu feature and support, two window coordinates.
+// Input channels: nu_J feature and support, mu feature and support, two window coordinates,
+// g0 / 8 on the support of nu_J, and on the X block the change f1 - f0 of one Sinkhorn
+// iteration from f0 (f1 = the X-update of g0), where mu > 0.
 #pragma once
 
 #include "common.hpp"
@@ -23,7 +28,7 @@
 namespace dd {
 
 constexpr int kNetWin = 32;          // window side
-constexpr int kNetCin = 6;           // input channels
+constexpr int kNetCin = 8;           // input channels
 constexpr int kNetCh = 32;           // hidden channels
 constexpr int kNetLayers = 5;
 
@@ -36,18 +41,21 @@ struct ConvDesc {
 const ConvDesc* net_layers();
 int64_t net_param_count();
 
-// Cell features of a composite batch (box-local window), optionally with the training
-// target (the solved g, mean-free under the weights) and weights nu_J / m_J.
+// Cell features of a composite batch (box-local window) from the start f0 (a0 [ncell]
+// [xside^2]), the base g0 on the window (g0 [ncell][32][32], mean-free, 0 off the support),
+// and optionally the training target (the solved g minus g0, mean-free under the weights)
+// and the weights nu_J / m_J.
 void launch_net_features(int ncell, int xside, const int32_t* dims, const int32_t* shift,
                          const int64_t* base, const double* logmu, const double* lognu,
-                         const double* b, float* x, float* tgt, float* wgt, hipStream_t st);
+                         const double* a0, double kappa, const double* b, float* x, float* g0,
+                         float* tgt, float* wgt, hipStream_t st);
 
-// f(i) = -LSE_w [g(w) + log nu_J(w) - C(i, w)] over the window part of the box; also
-// records the gauge offsets of this solve (as the zero / previous-iterate start does).
+// f(i) = -LSE_w [g0(w) + dg(w) + log nu_J(w) - C(i, w)] over the window part of the box;
+// also records the gauge offsets of this solve (as the zero / previous-iterate start does).
 void launch_net_finit(int ncell, int xside, const int32_t* dims, const int32_t* shift,
                       const int64_t* base, const double* lognu, const int32_t* gofs,
-                      const float* ghat, double kappa, double* a, int32_t* g_stored,
-                      hipStream_t st);
+                      const float* g0, const float* dg, double kappa, double* a,
+                      int32_t* g_stored, hipStream_t st);
 
 }  // namespace dd
 
@@ -69,5 +77,5 @@ struct dd_net {
     std::string err;
 };
 
-// Forward pass on n samples (x [n][6][32][32] -> y [n][32][32]); keeps the activations.
+// Forward pass on n samples (x [n][8][32][32] -> y [n][32][32]); keeps the activations.
 dd::Status net_forward(dd_net* net, int n, const float* x, float* y, hipStream_t st);

@@ -3,11 +3,14 @@
 Data: domain decomposition on the 256x256 mixture workload (8-blob Gaussian mixtures,
 s = 4, Knothe-Rosenblatt start, eps-scaling kappa = 64 ... 2 with 4 half-iterations per
 stage), then half-iterations at kappa = 1 (eps = h^2) with the Sinkhorn tolerance 1e-5.
-After every kappa = 1 half-iteration the features of each composite cell and its solved
-Y potential are taken (domdec_net_samples).  Several seeds give different mixtures.
+After every kappa = 1 half-iteration (previous-iterate start) the features of each
+composite cell and the correction that takes the start's Y potential g0 to the solved one
+are taken (domdec_net_samples).  Several seeds give different mixtures.
 
-Training: Adam on the gauge-invariant weighted squared error of the predicted Y potential
+Training: Adam on the gauge-invariant weighted squared error of the predicted correction
 (dd_net_train_step), mini-batches drawn from a seeded permutation, cosine learning rate.
+The last layer starts at zero, so the untrained net gives the correction 0 (one Sinkhorn
+iteration from the previous-iterate start).
 Every step runs in the library's kernels; this script only orchestrates.
 
     python -m paper_2405_09400_amd.train_warmstart --out weights.npz
@@ -89,7 +92,9 @@ def main():
     n_tr = n - n_val
     log(f"[train] {n_tr} training / {n_val} validation samples; target |g| "
         f"p50={T.abs().median().item():.2f} max={T.abs().max().item():.2f}")
-    net = dd.WarmStartNet(dd.net_init_params(args.init_seed))
+    p0 = dd.net_init_params(args.init_seed)
+    p0[-(4 * 32 * 9 + 4):] = 0.0  # last layer (weights [4][32][3][3], bias [4])
+    net = dd.WarmStartNet(p0)
     gen = torch.Generator(device="cpu").manual_seed(args.init_seed)
     steps = args.epochs * (n_tr // args.batch)
     step = 0

@@ -14,7 +14,7 @@ import synth
 pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
 
-LAYERS = [(6, 32, 2, 1), (32, 32, 1, 1), (32, 32, 1, 2), (32, 32, 1, 4), (32, 4, 1, 1)]
+LAYERS = [(8, 32, 2, 1), (32, 32, 1, 1), (32, 32, 1, 2), (32, 32, 1, 4), (32, 4, 1, 1)]
 
 
 def _need_gpu():
@@ -53,7 +53,7 @@ def _ref_loss(y, t, w):
 
 def _inputs(n, seed):
     rng = np.random.default_rng(seed)
-    x = rng.normal(0.0, 1.0, (n, 6, 32, 32)).astype(np.float32)
+    x = rng.normal(0.0, 1.0, (n, 8, 32, 32)).astype(np.float32)
     t = rng.normal(0.0, 3.0, (n, 32, 32)).astype(np.float32)
     w = rng.uniform(0.0, 1.0, (n, 32, 32)).astype(np.float32)
     w[:, :4, :] = 0.0  # empty rows, as outside a box
@@ -148,7 +148,7 @@ def test_samples_and_net_start_keep_tolerance():
     for part in "ABAB":
         g.iterate(part, 4 * h * h, tol=1e-5)
     x, t, w = g.net_samples()
-    assert x.shape[1:] == (6, 32, 32) and t.shape[1:] == (32, 32)
+    assert x.shape[1:] == (8, 32, 32) and t.shape[1:] == (32, 32)
     wsum = w.sum(dim=(1, 2))
     assert torch.all(wsum <= 1.0 + 1e-5) and torch.all(wsum > 0.5)
     assert torch.all(((w * t).sum(dim=(1, 2))).abs() <= 1e-3 * (w * t.abs()).sum(dim=(1, 2)) + 1e-6)
@@ -156,6 +156,13 @@ def test_samples_and_net_start_keep_tolerance():
     assert set(torch.unique(x[:, 1]).tolist()) <= {0.0, 1.0}
     assert torch.all(x[:, 3, 12:20, 12:20].sum(dim=(1, 2)) > 0)
     assert torch.all(x[:, 3, :12].sum(dim=(1, 2)) == 0)
+    # the base g0 is mean-free under the weights and zero off the support of nu_J; the
+    # change of one Sinkhorn iteration lives on the X block where mu > 0
+    g0 = x[:, 6] * 8.0
+    assert torch.all((w * g0).sum(dim=(1, 2)).abs() <= 1e-3 * (w * g0.abs()).sum(dim=(1, 2)) + 1e-5)
+    assert torch.all(g0[x[:, 1] == 0] == 0)
+    assert torch.all(x[:, 7][x[:, 3] == 0] == 0)
+    assert torch.all(torch.isfinite(x))
     net = dd.WarmStartNet(dd.net_init_params(0))
     g.set_net(net)
     for part in "AB":
