@@ -282,6 +282,48 @@ def traffic_summary(args):
     print("\n".join(lines))
 
 
+def trace_summary(args):
+    """Write the kernel-time summary of a rocprofv3 --kernel-trace --stats run (directory on
+    the command line): per-kernel totals, and the average duration of the dispatches of the
+    timed steps of the two register-blocked kernels (the last --traffic-last of each)."""
+    import csv
+    import glob
+    d = args.trace_from
+    stats = list(csv.DictReader(open(glob.glob(os.path.join(d, "**", "*kernel_stats.csv"),
+                                               recursive=True)[0])))
+    trace = list(csv.DictReader(open(glob.glob(os.path.join(d, "**", "*kernel_trace.csv"),
+                                               recursive=True)[0])))
+    tot = sum(float(r["TotalDurationNs"]) for r in stats)
+    cmd = ("rocprofv3 --kernel-trace --stats -d <out> -o run --output-format csv -- "
+           "python3 bench.py --steps 3 --warmup 1 --no-compare --no-cpu-baseline")
+    lines = ["# Cell Sinkhorn kernels, mix512 (512², s = 4, κ = 1, tol 1e-5, batch rule)", "",
+             "Command (from the repository root on the GPU box, after `cd /tmp && export "
+             "TMPDIR=/tmp`):", "", "```", cmd, "```", "",
+             f"Summarised by `python bench.py --trace-from <out> --traffic-last "
+             f"{args.traffic_last}`.  Kernel source SHA-256 (fastcell.hip): "
+             f"`{source_sha256()}`.", "",
+             "Device: one MI355X (gfx950).  Per-kernel totals over the whole run (set-up "
+             "stages included):", "",
+             "| kernel | calls | total ms | average us | % |", "|---|---:|---:|---:|---:|"]
+    for r in sorted(stats, key=lambda r: -float(r["TotalDurationNs"]))[:12]:
+        name = r["Name"].replace("dd::(anonymous namespace)::", "").split("(")[0]
+        lines.append(f"| `{name}` | {r['Calls']} | {float(r['TotalDurationNs']) / 1e6:.2f} | "
+                     f"{float(r['AverageNs']) / 1e3:.1f} | "
+                     f"{100 * float(r['TotalDurationNs']) / tot:.1f} |")
+    for k in ("fast_kernel<4, 16, false, 2>", "fast_kernel<1, 4, true, 2>"):
+        rows = sorted((r for r in trace if k in r["Kernel_Name"]),
+                      key=lambda r: int(r["Start_Timestamp"]))[-args.traffic_last:]
+        durs = [(int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3 for r in rows]
+        if durs:
+            lines += ["", f"Timed steps: the last {len(durs)} dispatches of `{k}` (the "
+                      f"launches after the stop, which exit at once, included): average "
+                      f"{sum(durs) / len(durs):.1f} us, min {min(durs):.1f} us, max "
+                      f"{max(durs):.1f} us."]
+    with open(args.trace_out, "w") as f:
+        f.write("\n".join(lines) + "\n")
+    print("\n".join(lines))
+
+
 def traffic_bytes(kernel_name):
     """HBM bytes per launch of `kernel_name` from the committed summary, or None when there is
     none, it covers another kernel, or the kernel's source has changed since."""
@@ -320,9 +362,15 @@ def main():
     ap.add_argument("--traffic-kernel", default="fast_kernel<4, 16, false, 2>")
     ap.add_argument("--traffic-last", type=int, default=139)
     ap.add_argument("--traffic-out", default=TRAFFIC_SUMMARY)
+    ap.add_argument("--trace-from", metavar="DIR",
+                    help="write the kernel-time summary of a rocprofv3 kernel-trace run")
+    ap.add_argument("--trace-out", default=os.path.join(ROOT, "profiles", "fast_kernel_mix512.md"))
     args = ap.parse_args()
     if args.traffic_from:
         traffic_summary(args)
+        return
+    if args.trace_from:
+        trace_summary(args)
         return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
