@@ -67,7 +67,8 @@ def setup(args):
     for kappa, its in zip(w.kappas[:-1], w.stage_iters[:-1]):
         eps = kappa / w.N ** 2
         for _ in range(its):
-            st = ctx.iterate("AB"[k % 2], eps, tol=args.tol, stop_rule=rule, max_iter=args.max_iter)
+            st = ctx.iterate("AB"[k % 2], eps, tol=args.tol, stop_rule=rule, max_iter=args.max_iter,
+                             check_every=args.check_every)
             k += 1
         log(f"[bench] stage kappa={kappa:g}: last iters={st['sk']['iters_max']} "
             f"maxW={st['max_w1']}x{st['max_w2']} entries={st['nu_entries']}")
@@ -85,6 +86,7 @@ def run_steps(ctx, w, n, k0, args, rule, init=None, flows=None):
     for i in range(n):
         part = "AB"[(k0 + i) % 2]
         st = ctx.iterate(part, eps, tol=args.tol, stop_rule=rule, max_iter=args.max_iter,
+                         check_every=args.check_every,
                          init=dd.DD_INIT_PREV if init is None else init)
         out.append(st)
         if flow_every and part == "B":
@@ -125,7 +127,7 @@ def time_to_tol(ctx, w, k0, args, rule):
             if j:
                 ctx.restore()
             st = ctx.iterate("AB"[(k0 + r) % 2], eps, tol=args.tol, stop_rule=rule,
-                             max_iter=args.max_iter, init=init)
+                             max_iter=args.max_iter, check_every=args.check_every, init=init)
             d = rec[name]
             d["sinkhorn_ms"].append(round(st["t_sinkhorn_ms"], 3))
             d["init_ms"].append(round(st["t_init_ms"], 3))
@@ -347,6 +349,8 @@ def main():
     ap.add_argument("--tol", type=float, default=1e-5)
     ap.add_argument("--max-iter", type=int, default=20000)
     ap.add_argument("--stop-rule", choices=["batch", "cell"], default="batch")
+    ap.add_argument("--check-every", type=int, default=8,
+                    help="batch rule: iterations between stop tests (register-blocked path)")
     ap.add_argument("--prec", choices=["f32", "f64"], default="f32")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -449,7 +453,8 @@ def main():
         "data": "synthetic",
         "config": {
             "workload": WORKLOAD_TEXT.get(args.workload, args.workload).format(N=w.N, s=w.s),
-            "tol": args.tol, "stop_rule": args.stop_rule, "seed": args.seed,
+            "tol": args.tol, "stop_rule": args.stop_rule, "check_every": args.check_every,
+            "seed": args.seed,
             "cells_per_step": stats[0]["sk"]["ncells"],
         },
         "roofline": {

@@ -356,9 +356,10 @@ dd_status domdec_restore(dd_ctx* ctx);
  * first visit of a partition):
  *   g0(w) = -LSE_i [f0(i) + log mu(i) - |o + i - w|^2 / kappa],  o = (32 - 2s)/2,
  * made mean-free under the weights nu_J / m_J.  The starting X potential is one
- * exact X-update of the corrected potential,
- *   f(i) = -LSE_w [g0(w) + dg(w) + log nu_J(w) - |o + i - w|^2 / kappa],
- * so dg = 0 gives one Sinkhorn iteration from f0.  The stopping rule is untouched:
+ * exact X-update, over the whole box, of the corrected potential g = g0 + dg (dg made
+ * mean-free the same way, on the window part of the box; g0 elsewhere),
+ *   f(i) = -LSE_j [g(j) + log nu_J(j) - C(i, j)],
+ * so dg = 0 gives exactly one Sinkhorn iteration from f0.  The stopping rule is untouched:
  * the net changes only where Sinkhorn starts.  X blocks of side 2s <= 8 only.
  * Window features (8 channels): nu_J feature max(log(nu_J/m_J) + 16, 0)/4 and its
  * support, the same for mu on the X block, the two window coordinates, g0/8 on the

@@ -94,7 +94,6 @@ void dd_ctx_release(dd_ctx* c) {
     F(c->d_b);
     F(c->d_nx);
     F(c->d_ng);
-    F(c->d_g0);
     F(c->d_a0);
     dual_release(c->dual);
     F(c->snap.box);
@@ -377,18 +376,19 @@ static dd_status iterate_impl(dd_ctx* c, int p, double eps, const dd_sinkhorn_op
         hipSuccess)
         return fail(c, DD_EDEVICE, "domdec_iterate: copying the start failed");
     if (o.init == DD_INIT_NET) {
-        // learned start: features of the previous-iterate start -> net -> one X-update of
-        // the corrected Y potential
+        // learned start: features of the previous-iterate start -> net -> one X-update, over
+        // the whole box, of the corrected Y potential
         if (grow(c->d_nx, c->nx_cap, (size_t)nc * kNetCin * kNetWin * kNetWin, st).code ||
-            grow(c->d_ng, c->ng_cap, (size_t)nc * kNetWin * kNetWin, st).code ||
-            grow(c->d_g0, c->g0_cap, (size_t)nc * kNetWin * kNetWin, st).code)
+            grow(c->d_ng, c->ng_cap, (size_t)nc * kNetWin * kNetWin, st).code)
             return fail(c, st);
         launch_net_features(nc, c->AS, c->C.dims, c->C.shift, c->C.base, logmu, lognu, apot,
-                            kappa, nullptr, c->d_nx, c->d_g0, nullptr, nullptr, hs);
+                            kappa, nullptr, c->d_nx, nullptr, nullptr, hs);
         const Status ns = net_forward(c->net, nc, c->d_nx, c->d_ng, hs);
         if (ns.code) return fail(c, ns);
-        launch_net_finit(nc, c->AS, c->C.dims, c->C.shift, c->C.base, lognu, c->C.gofs, c->d_g0,
-                         c->d_ng, kappa, apot, c->d_gst[p], hs);
+        // (the c2b scratch, 4 doubles per box entry, is free until the solve has finished)
+        launch_net_start(nc, c->AS, c->C.dims, c->C.shift, c->C.base, logmu, lognu, c->C.gofs,
+                         c->d_ng, kappa, reinterpret_cast<float*>(c->d_tmp), apot, c->d_gst[p],
+                         hs);
     }
     (void)hipEventRecord(c->ev[4], hs);
     SkBatch B;
@@ -622,8 +622,7 @@ extern "C" dd_status domdec_net_samples(dd_ctx* c, float* x, float* target, floa
         return fail(c, DD_EINVAL, "domdec_net_samples: buffers missing or cap < cells");
     if (c->AS > 8) return fail(c, DD_EINVAL, "domdec_net_samples: needs X blocks of side <= 8");
     launch_net_features(nc, c->AS, c->C.dims, c->C.shift, c->C.base, c->d_logmu[p], c->d_lognu,
-                        c->d_a0, c->last_eps / (c->h * c->h), c->d_b, x, nullptr, target,
-                        weight, c->st);
+                        c->d_a0, c->last_eps / (c->h * c->h), c->d_b, x, target, weight, c->st);
     if (hipStreamSynchronize(c->st) != hipSuccess || hipGetLastError() != hipSuccess)
         return fail(c, DD_EDEVICE, "domdec_net_samples: kernel failed");
     return DD_OK;

@@ -64,8 +64,6 @@ struct dd_ctx {
     size_t nx_cap = 0;
     float* d_ng = nullptr;  // [cells][32][32] predicted corrections of the Y potential
     size_t ng_cap = 0;
-    float* d_g0 = nullptr;  // [cells][32][32] base Y potential of the correction
-    size_t g0_cap = 0;
     double* d_a0 = nullptr;  // [cells][xside^2] previous-iterate start of the last iteration
     size_t a0_cap = 0;
     dd::DualWork dual;

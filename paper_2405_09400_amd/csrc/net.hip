@@ -310,8 +310,7 @@ __global__ void __launch_bounds__(kT)
                         const int32_t* __restrict__ shift, const int64_t* __restrict__ base,
                         const double* __restrict__ logmu, const double* __restrict__ lognu,
                         const double* __restrict__ a0, float invk, const double* __restrict__ b,
-                        float* __restrict__ x, float* __restrict__ g0, float* __restrict__ tgt,
-                        float* __restrict__ wgt) {
+                        float* __restrict__ x, float* __restrict__ tgt, float* __restrict__ wgt) {
     __shared__ double red[8];
     __shared__ double fx[64];         // f0 + log mu on the X block (kNegD without mass)
     __shared__ float gv[kNetWin * kNetWin];  // g0 + log nu_J - lm (kNegF off the support)
@@ -421,7 +420,6 @@ __global__ void __launch_bounds__(kT)
             xc[5 * W2 + k] = (w2 - 15.5f) * (1.f / 16.f);
             xc[6 * W2 + k] = gc * 0.125f;
             xc[7 * W2 + k] = hmu ? df[i1 * xside + i2] : 0.f;
-            if (g0) g0[(int64_t)J * W2 + k] = gc;
             if (tgt)
                 tgt[(int64_t)J * W2 + k] =
                     has ? (float)(b[bs + (int64_t)j1 * Wd2 + j2] - gm) - gc : 0.f;
@@ -430,51 +428,120 @@ __global__ void __launch_bounds__(kT)
     }
 }
 
-// f(i) = -LSE_w [g0(w) + dg(w) + log nu_J(w) - ((o + i1 - w1)^2 + (o + i2 - w2)^2) / kappa]
-// over the window positions inside the box with nu_J > 0.
+// Y potential of the learned start on every box entry j (with nu_J > 0):
+//   g(j) = -LSE_i [f0(i) + log mu(i) - C(i, j)] + [j in the window] (dg(w) - mean dg),
+// with C(i, j) = ((i1 - j1 + E1)^2 + (i2 - j2 + E2)^2) / kappa and the mean of dg under the
+// weights nu_J / m_J on the window (the net's output has no fixed constant; inside and outside
+// the window the base is the same g0).  v = g + log nu_J is written packed like log nu_J
+// (float; -inf where nu_J = 0).
 __global__ void __launch_bounds__(kT)
-    net_finit_kernel(int ncell, int xside, const int32_t* __restrict__ dims,
-                     const int32_t* __restrict__ shift, const int64_t* __restrict__ base,
-                     const double* __restrict__ lognu, const int32_t* __restrict__ gofs,
-                     const float* __restrict__ g0, const float* __restrict__ dg, float invk,
-                     double* __restrict__ a, int32_t* __restrict__ g_stored) {
+    net_gbox_kernel(int ncell, int xside, const int32_t* __restrict__ dims,
+                    const int32_t* __restrict__ shift, const int64_t* __restrict__ base,
+                    const double* __restrict__ logmu, const double* __restrict__ lognu,
+                    const double* __restrict__ a0, const float* __restrict__ dg, float invk,
+                    float* __restrict__ v) {
+    __shared__ double red[8];
+    __shared__ double fx[64];
     constexpr int W2 = kNetWin * kNetWin;
-    __shared__ float v[W2];
     const int N2 = xside * xside, o = (kNetWin - xside) / 2;
+    for (int J = blockIdx.x; J < ncell; J += gridDim.x) {
+        double m = 0.0;
+        for (int i = threadIdx.x; i < N2; i += kT) {
+            const double l = logmu[(int64_t)J * N2 + i];
+            const bool h = l > kZeroMassLog;
+            if (h) m += exp(l);
+            fx[i] = h ? a0[(int64_t)J * N2 + i] + l : kNegD;
+        }
+        m = block_sum(m, red);
+        const double lm = log(m);
+        const int W1 = dims[2 * J], Wd2 = dims[2 * J + 1];
+        const int E1 = shift[2 * J], E2 = shift[2 * J + 1];
+        const int64_t bs = base[J];
+        double sw = 0.0, swd = 0.0;
+        for (int k = threadIdx.x; k < W2; k += kT) {
+            const int j1 = k / kNetWin - o + E1, j2 = k % kNetWin - o + E2;
+            const bool inbox = j1 >= 0 && j1 < W1 && j2 >= 0 && j2 < Wd2;
+            const double ln = inbox ? lognu[bs + (int64_t)j1 * Wd2 + j2] : kNegD;
+            if (ln > kZeroMassLog) {
+                const double wt = exp(ln - lm);
+                sw += wt;
+                swd += wt * dg[(int64_t)J * W2 + k];
+            }
+        }
+        sw = block_sum(sw, red);
+        swd = block_sum(swd, red);
+        const double dm = sw > 0.0 ? swd / sw : 0.0;
+        const int ne = W1 * Wd2;
+        for (int e = threadIdx.x; e < ne; e += kT) {
+            const int j1 = e / Wd2, j2 = e % Wd2;
+            const double ln = lognu[bs + e];
+            float out = kNegF;
+            if (ln > kZeroMassLog) {
+                double mx = kNegD;
+                for (int i = 0; i < N2; ++i) {
+                    const double d1 = i / xside - j1 + E1, d2 = i % xside - j2 + E2;
+                    mx = fmax(mx, fx[i] - (d1 * d1 + d2 * d2) * invk);
+                }
+                float sm = 0.f;
+                for (int i = 0; i < N2; ++i) {
+                    const double d1 = i / xside - j1 + E1, d2 = i % xside - j2 + E2;
+                    sm += __expf((float)(fx[i] - (d1 * d1 + d2 * d2) * invk - mx));
+                }
+                double g = -(mx + log((double)sm));
+                const int w1 = j1 + o - E1, w2 = j2 + o - E2;
+                if (w1 >= 0 && w1 < kNetWin && w2 >= 0 && w2 < kNetWin)
+                    g += (double)dg[(int64_t)J * W2 + w1 * kNetWin + w2] - dm;
+                out = (float)(g + ln);
+            }
+            v[bs + e] = out;
+        }
+        __syncthreads();
+    }
+}
+
+// The learned start: f(i) = -LSE_j [v(j) - C(i, j)] over the whole box (an exact X-update of
+// the corrected Y potential); four lanes per X point, each a quarter of the entries with an
+// online maximum.  Also records the gauge offsets of this solve (as the zero /
+// previous-iterate start does).
+__global__ void __launch_bounds__(kT)
+    net_fbox_kernel(int ncell, int xside, const int32_t* __restrict__ dims,
+                    const int32_t* __restrict__ shift, const int64_t* __restrict__ base,
+                    const int32_t* __restrict__ gofs, const float* __restrict__ v, float invk,
+                    double* __restrict__ a, int32_t* __restrict__ g_stored) {
+    const int N2 = xside * xside;
     for (int J = blockIdx.x; J < ncell; J += gridDim.x) {
         const int W1 = dims[2 * J], Wd2 = dims[2 * J + 1];
         const int E1 = shift[2 * J], E2 = shift[2 * J + 1];
         const int64_t bs = base[J];
-        __syncthreads();
-        for (int k = threadIdx.x; k < W2; k += kT) {
-            const int w1 = k / kNetWin, w2 = k % kNetWin;
-            const int j1 = w1 - o + E1, j2 = w2 - o + E2;
-            const bool inbox = j1 >= 0 && j1 < W1 && j2 >= 0 && j2 < Wd2;
-            const double ln = inbox ? lognu[bs + (int64_t)j1 * Wd2 + j2] : kNegD;
-            v[k] = ln > kZeroMassLog
-                       ? g0[(int64_t)J * W2 + k] + dg[(int64_t)J * W2 + k] + (float)ln
-                       : kNegF;
-        }
-        __syncthreads();
-        for (int i = threadIdx.x; i < N2; i += kT) {
-            const int i1 = i / xside, i2 = i % xside;
-            float mx = kNegF;
-            for (int k = 0; k < W2; ++k) {
-                const float d1 = (float)(o + i1 - k / kNetWin), d2 = (float)(o + i2 - k % kNetWin);
-                mx = fmaxf(mx, v[k] - (d1 * d1 + d2 * d2) * invk);
+        const int ne = W1 * Wd2;
+        const int i = threadIdx.x >> 2, q = threadIdx.x & 3;
+        const bool live = i < N2;
+        const int i1 = live ? i / xside : 0, i2 = live ? i % xside : 0;
+        float mx = kNegF, sm = 0.f;
+        for (int e = q; e < ne; e += 4) {
+            const float ve = v[bs + e];
+            if (!(ve > 0.5f * kNegF)) continue;
+            const float d1 = (float)(i1 - e / Wd2 + E1), d2 = (float)(i2 - e % Wd2 + E2);
+            const float x = ve - (d1 * d1 + d2 * d2) * invk;
+            if (x > mx) {
+                sm = sm * __expf(mx - x) + 1.f;
+                mx = x;
+            } else {
+                sm += __expf(x - mx);
             }
-            double f = 0.0;
-            if (mx > 0.5f * kNegF) {
-                float s = 0.f;
-                for (int k = 0; k < W2; ++k) {
-                    const float d1 = (float)(o + i1 - k / kNetWin),
-                                d2 = (float)(o + i2 - k % kNetWin);
-                    s += __expf(v[k] - (d1 * d1 + d2 * d2) * invk - mx);
-                }
-                f = -((double)mx + log((double)s));
-            }
-            a[(int64_t)J * N2 + i] = f;
         }
+        // combine the four partial (max, sum) pairs of an X point
+        for (int k = 1; k < 4; k <<= 1) {
+            const float mo = __shfl_xor(mx, k, 64), so = __shfl_xor(sm, k, 64);
+            const float mn = fmaxf(mx, mo);
+            sm = (mx > 0.5f * kNegF ? sm * __expf(mx - mn) : 0.f) +
+                 (mo > 0.5f * kNegF ? so * __expf(mo - mn) : 0.f);
+            mx = mn;
+        }
+        if (live && q == 0)
+            a[(int64_t)J * N2 + i] = (mx > 0.5f * kNegF && sm > 0.f)
+                                         ? -((double)mx + log((double)sm))
+                                         : 0.0;
         if (threadIdx.x == 0) {
             g_stored[2 * J] = gofs[2 * J];
             g_stored[2 * J + 1] = gofs[2 * J + 1];
@@ -514,23 +581,25 @@ int64_t net_param_count() { return table().n; }
 
 void launch_net_features(int ncell, int xside, const int32_t* dims, const int32_t* shift,
                          const int64_t* base, const double* logmu, const double* lognu,
-                         const double* a0, double kappa, const double* b, float* x, float* g0,
-                         float* tgt, float* wgt, hipStream_t st) {
+                         const double* a0, double kappa, const double* b, float* x, float* tgt,
+                         float* wgt, hipStream_t st) {
     if (ncell <= 0) return;
     net_features_kernel<<<grid_n(ncell, 4096), kT, 0, st>>>(ncell, xside, dims, shift, base,
                                                             logmu, lognu, a0,
-                                                            (float)(1.0 / kappa), b, x, g0,
-                                                            tgt, wgt);
+                                                            (float)(1.0 / kappa), b, x, tgt,
+                                                            wgt);
 }
 
-void launch_net_finit(int ncell, int xside, const int32_t* dims, const int32_t* shift,
-                      const int64_t* base, const double* lognu, const int32_t* gofs,
-                      const float* g0, const float* dg, double kappa, double* a,
+void launch_net_start(int ncell, int xside, const int32_t* dims, const int32_t* shift,
+                      const int64_t* base, const double* logmu, const double* lognu,
+                      const int32_t* gofs, const float* dg, double kappa, float* v, double* a,
                       int32_t* g_stored, hipStream_t st) {
     if (ncell <= 0) return;
-    net_finit_kernel<<<grid_n(ncell, 4096), kT, 0, st>>>(ncell, xside, dims, shift, base, lognu,
-                                                         gofs, g0, dg, (float)(1.0 / kappa), a,
-                                                         g_stored);
+    const float invk = (float)(1.0 / kappa);
+    net_gbox_kernel<<<grid_n(ncell, 4096), kT, 0, st>>>(ncell, xside, dims, shift, base, logmu,
+                                                        lognu, a, dg, invk, v);
+    net_fbox_kernel<<<grid_n(ncell, 4096), kT, 0, st>>>(ncell, xside, dims, shift, base, gofs, v,
+                                                        invk, a, g_stored);
 }
 
 }  // namespace dd

@@ -6,11 +6,13 @@
 // that window.  Its base is the previous-iterate start f0 (the X potential of the last
 // visit of the partition): g0(w) = -LSE_i [f0(i) + log mu(i) - C(i, w)], made mean-free
 // under the weights nu_J / m_J.  The X potential used to start Sinkhorn is one exact
-// X-update of the corrected potential, f(i) = -LSE_w [g0(w) + dg(w) + log nu_J(w) - C(i, w)],
+// X-update, over the whole box, of the corrected potential g0 + dg (dg on the window part
+// of the box, made mean-free the same way; g0 elsewhere):
+//   f(i) = -LSE_j [g(j) + log nu_J(j) - C(i, j)],
 // which is the slot for the initial alpha of the cell solve (App. A.1, Alg. "SinkhornGPU"
-// input alpha_init).  With dg = 0 this is one Sinkhorn iteration from f0.  The stopping
-// rule of the solve is untouched, so the prediction only changes where the iteration
-// starts.
+// input alpha_init).  With dg = 0 this is exactly one Sinkhorn iteration from f0.  The
+// stopping rule of the solve is untouched, so the prediction only changes where the
+// iteration starts.
 //
 // Layers (3x3 kernels, 32 channels, BF16 weights, FP32 accumulation, ReLU between):
 //   L1  8 -> 32, stride 2      32x32 -> 16x16
@@ -42,19 +44,21 @@ const ConvDesc* net_layers();
 int64_t net_param_count();
 
 // Cell features of a composite batch (box-local window) from the start f0 (a0 [ncell]
-// [xside^2]), the base g0 on the window (g0 [ncell][32][32], mean-free, 0 off the support),
-// and optionally the training target (the solved g minus g0, mean-free under the weights)
-// and the weights nu_J / m_J.
+// [xside^2]), and optionally the training target (the solved g minus g0, both mean-free
+// under the weights) and the weights nu_J / m_J.
 void launch_net_features(int ncell, int xside, const int32_t* dims, const int32_t* shift,
                          const int64_t* base, const double* logmu, const double* lognu,
-                         const double* a0, double kappa, const double* b, float* x, float* g0,
-                         float* tgt, float* wgt, hipStream_t st);
+                         const double* a0, double kappa, const double* b, float* x, float* tgt,
+                         float* wgt, hipStream_t st);
 
-// f(i) = -LSE_w [g0(w) + dg(w) + log nu_J(w) - C(i, w)] over the window part of the box;
-// also records the gauge offsets of this solve (as the zero / previous-iterate start does).
-void launch_net_finit(int ncell, int xside, const int32_t* dims, const int32_t* shift,
-                      const int64_t* base, const double* lognu, const int32_t* gofs,
-                      const float* g0, const float* dg, double kappa, double* a,
+// The learned start from the previous-iterate start f0 (in a, overwritten) and the net's
+// correction dg on the window: g = g0 + (dg - its weighted mean) on the window part of the
+// box, g0 elsewhere, written with log nu_J added to v (float scratch packed like log nu_J);
+// then f(i) = -LSE_j [g(j) + log nu_J(j) - C(i, j)] over the whole box, into a.  Also
+// records the gauge offsets of this solve (as the zero / previous-iterate start does).
+void launch_net_start(int ncell, int xside, const int32_t* dims, const int32_t* shift,
+                      const int64_t* base, const double* logmu, const double* lognu,
+                      const int32_t* gofs, const float* dg, double kappa, float* v, double* a,
                       int32_t* g_stored, hipStream_t st);
 
 }  // namespace dd
