@@ -61,9 +61,15 @@ typedef struct {
     int32_t max_iter;     /* iteration cap (>= 1)                                  */
     int32_t fixed_iters;  /* 0 = use tol                                           */
     int32_t stop_rule;    /* DD_STOP_BATCH | DD_STOP_CELL                          */
-    int32_t check_every;  /* batch rule: the float32 register-blocked path tests the
-                             error every k-th iteration (0 = 8); the other kernels test
-                             every iteration and poll the flag every k launches        */
+    int32_t check_every;  /* batch rule, k (0 = 8).  The float32 register-blocked
+                             path tests the error after 4k iterations, again 4k later,
+                             then after 80% of the iterations the decay of the last two
+                             tests predicts are still needed (at least k, at most 32k);
+                             its stop trails the first iteration that meets the rule by
+                             the overshoot of the last prediction (< k when the error
+                             decays no faster than predicted), which only lowers the
+                             error.  The other kernels test every iteration and poll
+                             the flag every k launches                                 */
     int32_t init;         /* DD_INIT_ZERO | PREV | NET (domdec_iterate only)      */
     int32_t reserved;     /* must be 0                                             */
 } dd_sinkhorn_opts;

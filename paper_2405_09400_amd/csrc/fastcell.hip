@@ -253,7 +253,7 @@ struct FastArgs {
     int W1m, W2m;          // slice bounds (kernel frame)
     int mode;
     int limit, fixed, stall;  // kSolve
-    int chunk, max_iter;      // kBatch
+    int chunk, max_iter;      // kBatch: least iterations between two tests, iteration cap
     double tol;
     int nblocks;              // kBatch: workgroups of all the launches of one round
     int* ctrl;
@@ -911,6 +911,11 @@ __device__ __forceinline__ void run_cell(const FastArgs& g, int cell, lds_p<char
     Tm::sync();
 }
 
+// batch rule: spacing of the tests in units of the least spacing (check_every), and the
+// fraction of the predicted remaining iterations run before the next test
+constexpr int kFirstRounds = 4, kMaxRounds = 32;
+constexpr double kAheadFrac = 0.8;
+
 // threads of a workgroup: four one-wave teams, or one team of NW waves
 __host__ __device__ constexpr int team_block(int NW) { return NW == 1 ? kBlock : 64 * NW; }
 
@@ -923,7 +928,10 @@ fast_kernel(FastArgs g) {
     int K = 0;
     if (g.mode == kBatch) {
         if (__atomic_load_n(&g.ctrl[2], __ATOMIC_RELAXED) != 0) return;
-        K = min(g.chunk, g.max_iter - __atomic_load_n(&g.ctrl[10], __ATOMIC_RELAXED));
+        // this round's length, set by the previous round's test (0: the first rounds)
+        const int next = __atomic_load_n(&g.ctrl[5], __ATOMIC_RELAXED);
+        K = min(next > 0 ? next : kFirstRounds * g.chunk,
+                g.max_iter - __atomic_load_n(&g.ctrl[10], __ATOMIC_RELAXED));
     }
     int* queue = &g.ctrl[g.qidx];
     if constexpr (NW == 1) {
@@ -967,10 +975,27 @@ fast_kernel(FastArgs g) {
         const int it = g.ctrl[10] + K;
         g.dtot[0] = e;
         g.dtot[1] = m;
-        const bool conv = e <= g.tol * m;
+        const double lim = g.tol * m;
+        const bool conv = e <= lim;
         if (conv) g.ctrl[4] = 1;
         g.ctrl[10] = it;
         if (conv || it >= g.max_iter || !(e == e)) __atomic_store_n(&g.ctrl[2], it, __ATOMIC_RELAXED);
+        // length of the next round: the first two tests come kFirstRounds * chunk iterations
+        // apart; later ones after a fraction of the iterations still needed if the error keeps
+        // the geometric decay of the last two tests (never fewer than chunk, never more than
+        // kMaxRounds * chunk)
+        const int it0 = g.ctrl[6];
+        const double e0 = g.dtot[5];
+        int next = it0 > 0 ? g.chunk : kFirstRounds * g.chunk;
+        if (it0 > 0 && !conv && e < e0 && e > lim && lim > 0.0) {
+            const double rate = log(e / e0) / (double)(it - it0);  // < 0
+            const double left = log(lim / e) / rate;               // > 0
+            next = (int)fmin(kAheadFrac * left, (double)(kMaxRounds * g.chunk));
+            next = max(next, g.chunk);
+        }
+        g.ctrl[5] = next;
+        g.ctrl[6] = it;
+        g.dtot[5] = e;
         g.ctrl[0] = 0;
         g.ctrl[9] = 0;
         g.ctrl[1] = 0;
@@ -1170,7 +1195,8 @@ Status fast_solve(const SkBatch& p, const dd_sinkhorn_opts& o, hipStream_t st, S
     }
     a.chunk = std::max(1, o.check_every > 0 ? o.check_every : 8);
     a.nblocks = nblocks;
-    // rounds of `chunk` iterations, `reps` at a time between reads of the device stop flag;
+    // rounds whose lengths the device sets (see the end of fast_kernel), `reps` at a time
+    // between reads of the device stop flag;
     // every launch is bracketed by events on its own stream (the per-class kernel time of the
     // statistics), the launches after the stop, which exit at once, included
     const int reps = 4;
@@ -1182,7 +1208,8 @@ Status fast_solve(const SkBatch& p, const dd_sinkhorn_opts& o, hipStream_t st, S
     for (int k = 0; k < kClasses; ++k)
         for (int c : cells[k]) terms_per_it[k] += sk_cell_terms(kA, hd[2 * c], hd[2 * c + 1]);
     int hctl[16] = {};
-    for (int launched = 0; launched < o.max_iter && !hctl[2]; launched += reps * a.chunk) {
+    // every round that starts before the stop runs at least one iteration
+    for (int rounds = 0; rounds < o.max_iter && !hctl[2]; rounds += reps) {
         for (int r = 0; r < reps; ++r) {
             fork();
             launch(a, kBatch, true, r);

@@ -28,8 +28,8 @@ constexpr int kFastMaxSide = 512;
 // The float32 phase of a solve (the caller runs the float64 finish): writes f to p.a, g to
 // p.b, per-cell iterations, errors and masses (w.cell_mass), and the control words read by
 // the statistics (done iteration ctrl[2], converged ctrl[4]).  Same options and stopping
-// rules as the general kernels, except that the batch rule is tested every
-// max(1, o.check_every)-th iteration.
+// rules as the general kernels, except that the batch rule is tested at iterations the
+// device chooses from the error's decay (at least max(1, o.check_every) apart).
 Status fast_solve(const SkBatch& p, const dd_sinkhorn_opts& o, hipStream_t st, SkWork& w,
                   const std::vector<int32_t>& hd, int32_t* iters, double* errs, FastInfo* info);
 
