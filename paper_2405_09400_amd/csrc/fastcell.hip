@@ -915,6 +915,11 @@ __device__ __forceinline__ void run_cell(const FastArgs& g, int cell, lds_p<char
 // fraction of the predicted remaining iterations run before the next test
 constexpr int kFirstRounds = 4, kMaxRounds = 32;
 constexpr double kAheadFrac = 0.8;
+// A tolerance solve's float32 phase aims below the tolerance, so that the float64 finish
+// usually certifies it with its first error (float32 and float64 errors differ by a few
+// percent, and every float64 iteration costs as much as ~15 float32 ones); it hands over
+// early when its error stalls within kStallNear of that target.
+constexpr double kF32Target = 0.85, kStallNear = 4.0, kStallRel = 1e-4;
 
 // threads of a workgroup: four one-wave teams, or one team of NW waves
 __host__ __device__ constexpr int team_block(int NW) { return NW == 1 ? kBlock : 64 * NW; }
@@ -979,13 +984,17 @@ fast_kernel(FastArgs g) {
         const bool conv = e <= lim;
         if (conv) g.ctrl[4] = 1;
         g.ctrl[10] = it;
-        if (conv || it >= g.max_iter || !(e == e)) __atomic_store_n(&g.ctrl[2], it, __ATOMIC_RELAXED);
+        const int it0 = g.ctrl[6];
+        const double e0 = g.dtot[5];
+        // an error near the target that no longer falls in float32 is left to the float64
+        // finish that follows this phase
+        const bool stalled = it0 > 0 && !conv && e <= kStallNear * lim && !(e < e0 * (1.0 - kStallRel));
+        if (conv || stalled || it >= g.max_iter || !(e == e))
+            __atomic_store_n(&g.ctrl[2], it, __ATOMIC_RELAXED);
         // length of the next round: the first two tests come kFirstRounds * chunk iterations
         // apart; later ones after a fraction of the iterations still needed if the error keeps
         // the geometric decay of the last two tests (never fewer than chunk, never more than
         // kMaxRounds * chunk)
-        const int it0 = g.ctrl[6];
-        const double e0 = g.dtot[5];
         int next = it0 > 0 ? g.chunk : kFirstRounds * g.chunk;
         if (it0 > 0 && !conv && e < e0 && e > lim && lim > 0.0) {
             const double rate = log(e / e0) / (double)(it - it0);  // < 0
@@ -1122,7 +1131,7 @@ Status fast_solve(const SkBatch& p, const dd_sinkhorn_opts& o, hipStream_t st, S
         a.mass = w.cell_mass;
         a.dtot = w.dtot;
         a.f_keep = w.a_alt;
-        a.tol = o.tol;
+        a.tol = o.fixed_iters > 0 ? o.tol : o.tol * kF32Target;
         a.max_iter = o.max_iter;
         if (info) {
             info->n[k] = nk;

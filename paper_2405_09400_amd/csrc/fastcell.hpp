@@ -29,7 +29,8 @@ constexpr int kFastMaxSide = 512;
 // p.b, per-cell iterations, errors and masses (w.cell_mass), and the control words read by
 // the statistics (done iteration ctrl[2], converged ctrl[4]).  Same options and stopping
 // rules as the general kernels, except that the batch rule is tested at iterations the
-// device chooses from the error's decay (at least max(1, o.check_every) apart).
+// device chooses from the error's decay (at least max(1, o.check_every) apart), and that a
+// tolerance solve aims at 0.85 o.tol (the float64 finish certifies o.tol).
 Status fast_solve(const SkBatch& p, const dd_sinkhorn_opts& o, hipStream_t st, SkWork& w,
                   const std::vector<int32_t>& hd, int32_t* iters, double* errs, FastInfo* info);
 
