@@ -540,7 +540,23 @@ __device__ __forceinline__ void run_cell(const FastArgs& g, int cell, lds_p<char
     //      Zx = g + log nu_J - lnref - dx2(j2)^2 / kappa (float64), online row maximum over
     //      column blocks, acc(i2) = sum_j2 exp(Zx - max) KX1(j2, i2),
     //      R - dx1(j1)^2 / kappa = max + log acc - dx1(j1)^2 / kappa
-    auto chunk = [&](int ch) {
+    // log nu_J of block (ch, b) (RC rows by 4 column groups of one column block) from global
+    // memory; `chunk` issues the next block's loads before it works on the current one, so
+    // their latency hides behind a block of work
+    using LnBlock = double[LNREG ? 1 : RC][4];
+    auto load_ln = [&](int ch, int b, LnBlock& dst) {
+        const double* lnb = p.lognu + bse;
+#pragma unroll
+        for (int t = 0; t < RC; ++t) {
+            const int jr = min(r + 8 * (w + NW * (RC * ch + t)), W1 - 1);
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int jc = min(c + 8 * u + 32 * b, W2 - 1);
+                dst[t][u] = lnb[(unsigned)(jr * s1 + jc * s2)];
+            }
+        }
+    };
+    auto chunk = [&](int ch, LnBlock& lnq) {
         int j1[RC];
         bool rv[RC], tb[RC];  // tb: the wave's block of 8 rows reaches into the box (uniform)
         float ky[RC][8], acc[RC][8];
@@ -560,19 +576,17 @@ __device__ __forceinline__ void run_cell(const FastArgs& g, int cell, lds_p<char
         for (int b = 0; b < nb; ++b) {
             double Z[RC][4];
             unsigned badm = 0;  // entries whose Y-update sum underflowed
-            // log nu_J of the block's entries from global memory, all loads issued up front
+            // log nu_J of the block's entries (loaded during the previous block), and the
+            // loads of the next block (this chunk's next column block, else the next chunk's
+            // first) issued now
             double lnp[LNREG ? 1 : RC][4];
             if constexpr (!LNREG) {
-                const double* lnb = p.lognu + bse;
 #pragma unroll
-                for (int t = 0; t < RC; ++t) {
-                    const int jr = min(j1[t], W1 - 1);
+                for (int t = 0; t < RC; ++t)
 #pragma unroll
-                    for (int u = 0; u < 4; ++u) {
-                        const int jc = min(c + 8 * u + 32 * b, W2 - 1);
-                        lnp[t][u] = lnb[(unsigned)(jr * s1 + jc * s2)];
-                    }
-                }
+                    for (int u = 0; u < 4; ++u) lnp[t][u] = lnq[t][u];
+                const int nch = b + 1 < nb ? ch : ch + 1, nbk = b + 1 < nb ? b + 1 : 0;
+                if (RC * nch < ntw) load_ln(nch, nbk, lnq);  // wave-uniform
             }
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
@@ -741,12 +755,14 @@ __device__ __forceinline__ void run_cell(const FastArgs& g, int cell, lds_p<char
 
     // ---- rest of one iteration from f = fc: returns s (first wave) and err ----------------
     auto iterate = [&](double fc, bool want_err, double& s_out, double& err_out) {
+        LnBlock lnq;
         if constexpr (LNREG) {
 #pragma unroll
             for (int ch = 0; ch < RPL / RC; ++ch)
-                if (RC * ch < ntw) chunk(ch);
+                if (RC * ch < ntw) chunk(ch, lnq);
         } else {
-            for (int ch = 0; RC * ch < ntw; ++ch) chunk(ch);
+            if (ntw > 0) load_ln(0, 0, lnq);
+            for (int ch = 0; RC * ch < ntw; ++ch) chunk(ch, lnq);
         }
         Tm::sync();
         // second X pass (float64): Mx(i2) = max_j1 R, S(i1, i2) = sum_j1 KX2(j1, i1) exp(R - Mx),
@@ -1075,7 +1091,9 @@ Status fast_solve(const SkBatch& p, const dd_sinkhorn_opts& o, hipStream_t st, S
     const int team[kClasses] = {1, 4};
     const int rpl[kClasses] = {4, 16};  // rows per lane: a team covers 8 * team * rpl rows
     const int qidx[kClasses] = {9, 0};
-    const hipStream_t streams[kClasses] = {st, w.stream2};
+    // the workgroup class goes on the caller's stream, which no event holds back, so that its
+    // workgroups are dispatched first
+    const hipStream_t streams[kClasses] = {w.stream2, st};
     std::vector<int32_t> cells[kClasses];
     int W1m[kClasses] = {1, 1}, W2m[kClasses] = {1, 1};
     for (int c = 0; c < n; ++c) {
@@ -1161,10 +1179,11 @@ Status fast_solve(const SkBatch& p, const dd_sinkhorn_opts& o, hipStream_t st, S
         (void)hipEventRecord(w.evj2, w.stream2);
         (void)hipStreamWaitEvent(st, w.evj2, 0);
     };
-    // one launch of every class in `mode`; with `ev` the launches are bracketed by events
-    // (slot `slot`) on their own streams
+    // one launch of every class in `mode`, the workgroup class first (its largest cells are
+    // the longest solves of a round, so they start at once); with `ev` the launches are
+    // bracketed by events (slot `slot`) on their own streams
     auto launch = [&](const FastArgs& a, int mode, bool ev, int slot) {
-        for (int k = 0; k < kClasses; ++k) {
+        for (int k = kClasses - 1; k >= 0; --k) {
             if (!args[k].n) continue;
             FastArgs x = args[k];
             x.mode = mode;
