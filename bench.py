@@ -312,7 +312,8 @@ def trace_summary(args):
         lines.append(f"| `{name}` | {r['Calls']} | {float(r['TotalDurationNs']) / 1e6:.2f} | "
                      f"{float(r['AverageNs']) / 1e3:.1f} | "
                      f"{100 * float(r['TotalDurationNs']) / tot:.1f} |")
-    for k in ("fast_kernel<4, 16, false, 2>", "fast_kernel<1, 4, true, 2>"):
+    for k in ("fast_kernel<4, 16, false, 2>", "fast_kernel<8, 8, false, 2>",
+              "fast_kernel<1, 4, true, 2>"):
         rows = sorted((r for r in trace if k in r["Kernel_Name"]),
                       key=lambda r: int(r["Start_Timestamp"]))[-args.traffic_last:]
         durs = [(int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3 for r in rows]
@@ -415,11 +416,12 @@ def main():
     # the stream it is launched on, summed over the launches of the timed steps that iterated)
     roof_kernel, k_launch, k_ms, k_terms = "sinkhorn (all kernels of the solve)", launches, sk_ms, terms
     if all(s["sk"]["path"] == 1 for s in stats) and rule == dd.DD_STOP_BATCH:
-        per = [(sum(s["sk"]["kernel_ms"][c] for s in stats), c) for c in (0, 1)]
+        per = [(sum(s["sk"]["kernel_ms"][c] for s in stats), c) for c in (0, 1, 2)]
         ms_c, c = max(per)
         if ms_c > 0:
-            names = ("fast_kernel<1, 4, true, 2> (one wave per cell)",
-                     "fast_kernel<4, 16, false, 2> (a workgroup per cell)")
+            names = ("fast_kernel<1, 4, true, 2> (box side <= 32: one wave per cell)",
+                     "fast_kernel<4, 16, false, 2> (up to 2048 box entries: four waves per cell)",
+                     "fast_kernel<8, 8, false, 2> (larger boxes: eight waves per cell)")
             roof_kernel = names[c]
             k_launch = sum(s["sk"]["kernel_launches"][c] for s in stats)
             k_ms = ms_c
@@ -478,10 +480,10 @@ def main():
                            for s in stats[:2]],
             "finish_f64_iters": [s["sk"]["finish_iters_max"] for s in stats],
             "class_kernel_ms_per_step": [sum(s["sk"]["kernel_ms"][c] for s in stats) / len(stats)
-                                         for c in (0, 1)],
+                                         for c in (0, 1, 2)],
             "class_tterm_s": [sum(s["sk"]["kernel_terms"][c] for s in stats) /
                               max(sum(s["sk"]["kernel_ms"][c] for s in stats), 1e-9) / 1e9
-                              for c in (0, 1)],
+                              for c in (0, 1, 2)],
             "main_ms_per_step": sum(s["sk"]["main_ms"] for s in stats) / len(stats),
             "sinkhorn_ms_per_step": sk_ms / len(stats),
             "b2c_ms_per_step": sum(s["t_b2c_ms"] for s in stats) / len(stats),

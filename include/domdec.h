@@ -94,17 +94,22 @@ typedef struct {
     int32_t tile_small[2];     /* LDS tile of the small-cell launch (W1, W2)             */
     int32_t tile_big[2];       /* LDS tile of the big-cell launch (W1, W2)               */
     int32_t path;              /* 0: general kernels; 1: register-blocked float32 path for
-                                  8 x 8 blocks (n_big = cells per workgroup, the rest one
-                                  per wave; lds_kb = LDS per workgroup of each launch;
-                                  fallback counts: tile_small = first-X-pass outputs
-                                  held as upper bounds, exact second-X-pass outputs;
-                                  tile_big = second-X-pass repeats after exact first-pass
-                                  outputs, wave blocks with exact Y-update entries)          */
-    int32_t kernel_launches[2]; /* path 1, batch rule: launches per class (0: one wave per
-                                   cell, 1: a workgroup per cell), the final g launch and the
-                                   launches after the stop (which exit at once) included     */
-    double kernel_ms[2];       /* their summed duration (HIP events on each launch's stream) */
-    double kernel_terms[2];    /* LSE terms they evaluated                                   */
+                                  8 x 8 blocks.  For path 1: n_big = cells solved by a
+                                  workgroup (the rest one per wave), n_giant = of those, the
+                                  cells of more than 2048 box entries (eight waves each, the
+                                  others four); lds_kb = LDS per workgroup of the wave class
+                                  and the largest of the workgroup classes; fallback counts:
+                                  tile_small = first-X-pass outputs held as upper bounds,
+                                  exact second-X-pass outputs; tile_big = second-X-pass
+                                  repeats after exact first-pass outputs, wave blocks with
+                                  exact Y-update entries                                    */
+    int32_t kernel_launches[3]; /* path 1, batch rule: launches per class (0: one wave per
+                                   cell; 1: four waves per cell; 2: eight waves per cell),
+                                   the final g launch and the launches after the stop (which
+                                   exit at once) included                                   */
+    int32_t reserved2;
+    double kernel_ms[3];       /* their summed duration (HIP events on each launch's stream) */
+    double kernel_terms[3];    /* LSE terms they evaluated                                   */
 } dd_batch_stats;
 
 /*

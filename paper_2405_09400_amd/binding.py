@@ -47,8 +47,9 @@ class BatchStats(ctypes.Structure):
                 ("finish_iters_max", ctypes.c_int32), ("n_big", ctypes.c_int32),
                 ("n_giant", ctypes.c_int32), ("lds_kb", ctypes.c_int32 * 2),
                 ("tile_small", ctypes.c_int32 * 2), ("tile_big", ctypes.c_int32 * 2),
-                ("path", ctypes.c_int32), ("kernel_launches", ctypes.c_int32 * 2),
-                ("kernel_ms", ctypes.c_double * 2), ("kernel_terms", ctypes.c_double * 2)]
+                ("path", ctypes.c_int32), ("kernel_launches", ctypes.c_int32 * 3),
+                ("reserved2", ctypes.c_int32),
+                ("kernel_ms", ctypes.c_double * 3), ("kernel_terms", ctypes.c_double * 3)]
 
 
 class Params(ctypes.Structure):

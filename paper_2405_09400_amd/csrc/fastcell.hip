@@ -1023,6 +1023,7 @@ fast_kernel(FastArgs g) {
         g.dtot[5] = e;
         g.ctrl[0] = 0;
         g.ctrl[9] = 0;
+        g.ctrl[11] = 0;
         g.ctrl[1] = 0;
     }
 }
@@ -1041,6 +1042,10 @@ __global__ void fill_ints(int* p, int n) {
 constexpr int kWaveSide = 32;
 #define FAST_WAVE fast_kernel<1, 4, true, FAST_WAVE_RC>
 #define FAST_GROUP fast_kernel<4, 16, false, FAST_GROUP_RC>
+#define FAST_BIG fast_kernel<8, 8, false, FAST_GROUP_RC>
+// Boxes of more entries than this take the longest per iteration (the time of smaller cells
+// is bounded by their latency): they get teams of eight waves and are dispatched first.
+constexpr int kBigEntries = 2048;
 
 int cus() {
     static int n = 0;
@@ -1083,23 +1088,25 @@ Status fast_solve(const SkBatch& p, const dd_sinkhorn_opts& o, hipStream_t st, S
                   const std::vector<int32_t>& hd, int32_t* iters, double* errs, FastInfo* info) {
     Status S;
     const int n = p.ncells;
-    // Cell classes by the box's long side (kernel frame), most work first within each:
-    //   0: <= 32: one wave per cell (four per workgroup), log nu_J in registers;
-    //   1: the rest: a workgroup of four waves per cell, log nu_J from global memory.
+    // Cell classes by box shape (kernel frame), most work first within each:
+    //   0: long side <= 32: one wave per cell (four per workgroup), log nu_J in registers;
+    //   1: the rest up to kBigEntries entries: a workgroup of four waves per cell;
+    //   2: larger boxes: a workgroup of eight waves per cell.
+    // Classes 1 and 2 read log nu_J from global memory.
     using KernFn = void (*)(FastArgs);
-    const KernFn fns[kClasses] = {FAST_WAVE, FAST_GROUP};
-    const int team[kClasses] = {1, 4};
-    const int rpl[kClasses] = {4, 16};  // rows per lane: a team covers 8 * team * rpl rows
-    const int qidx[kClasses] = {9, 0};
-    // the workgroup class goes on the caller's stream, which no event holds back, so that its
+    const KernFn fns[kClasses] = {FAST_WAVE, FAST_GROUP, FAST_BIG};
+    const int team[kClasses] = {1, 4, 8};
+    const int rpl[kClasses] = {4, 16, 8};  // rows per lane: a team covers 8 * team * rpl rows
+    const int qidx[kClasses] = {9, 0, 11};
+    // the eight-wave class goes on the caller's stream, which no event holds back, so that its
     // workgroups are dispatched first
-    const hipStream_t streams[kClasses] = {w.stream2, st};
+    const hipStream_t streams[kClasses] = {w.stream2, w.stream3, st};
     std::vector<int32_t> cells[kClasses];
-    int W1m[kClasses] = {1, 1}, W2m[kClasses] = {1, 1};
+    int W1m[kClasses] = {1, 1, 1}, W2m[kClasses] = {1, 1, 1};
     for (int c = 0; c < n; ++c) {
         const int a = std::max(std::max(hd[2 * c], hd[2 * c + 1]), 1);
         const int b = std::max(std::min(hd[2 * c], hd[2 * c + 1]), 1);
-        const int k = a <= kWaveSide ? 0 : 1;
+        const int k = a <= kWaveSide ? 0 : a * b > kBigEntries ? 2 : 1;
         cells[k].push_back(c);
         W1m[k] = std::max(W1m[k], a);
         W2m[k] = std::max(W2m[k], b);
@@ -1129,7 +1136,7 @@ Status fast_solve(const SkBatch& p, const dd_sinkhorn_opts& o, hipStream_t st, S
     }
     FastArgs args[kClasses];
     size_t lds[kClasses];
-    int grid[kClasses] = {0, 0};
+    int grid[kClasses] = {0, 0, 0};
     int ncls = 0, nblocks = 0;
     for (int k = 0; k < kClasses; ++k) {
         const int nk = (int)cells[k].size();
@@ -1166,22 +1173,25 @@ Status fast_solve(const SkBatch& p, const dd_sinkhorn_opts& o, hipStream_t st, S
         ++ncls;
         nblocks += grid[k];
     }
-    // the classes run side by side on two streams, the second forked from `st` and joined
-    // back
+    // the classes run side by side on three streams, the other two forked from `st` and
+    // joined back
     const bool multi = ncls > 1;
     auto fork = [&]() {
         if (!multi) return;
         (void)hipEventRecord(w.evf, st);
         (void)hipStreamWaitEvent(w.stream2, w.evf, 0);
+        (void)hipStreamWaitEvent(w.stream3, w.evf, 0);
     };
     auto join = [&]() {
         if (!multi) return;
         (void)hipEventRecord(w.evj2, w.stream2);
         (void)hipStreamWaitEvent(st, w.evj2, 0);
+        (void)hipEventRecord(w.evj3, w.stream3);
+        (void)hipStreamWaitEvent(st, w.evj3, 0);
     };
-    // one launch of every class in `mode`, the workgroup class first (its largest cells are
-    // the longest solves of a round, so they start at once); with `ev` the launches are
-    // bracketed by events (slot `slot`) on their own streams
+    // one launch of every class in `mode`, the largest cells first (they are the longest
+    // solves of a round, so they start at once); with `ev` the launches are bracketed by
+    // events (slot `slot`) on their own streams
     auto launch = [&](const FastArgs& a, int mode, bool ev, int slot) {
         for (int k = kClasses - 1; k >= 0; --k) {
             if (!args[k].n) continue;
@@ -1232,7 +1242,7 @@ Status fast_solve(const SkBatch& p, const dd_sinkhorn_opts& o, hipStream_t st, S
         for (auto& se : cls)
             for (hipEvent_t& e : se)
                 if (!e) DD_HIP(hipEventCreate(&e), S);
-    double terms_per_it[kClasses] = {0.0, 0.0};
+    double terms_per_it[kClasses] = {0.0, 0.0, 0.0};
     for (int k = 0; k < kClasses; ++k)
         for (int c : cells[k]) terms_per_it[k] += sk_cell_terms(kA, hd[2 * c], hd[2 * c + 1]);
     int hctl[16] = {};

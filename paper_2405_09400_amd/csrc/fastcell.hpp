@@ -7,17 +7,17 @@
 
 namespace dd {
 
-// Launch split of one solve on the register-blocked path, per cell class (box long side
-// <= 32: one wave per cell, log nu_J in registers; larger: a workgroup of four waves per
-// cell).
-constexpr int kClasses = 2;
+// Launch split of one solve on the register-blocked path, per cell class (0: box long side
+// <= 32, one wave per cell, log nu_J in registers; 1: the rest up to 2048 box entries, four
+// waves per cell; 2: larger boxes, eight waves per cell).
+constexpr int kClasses = 3;
 struct FastInfo {
-    int n[kClasses] = {0, 0};    // cells
-    int lds[kClasses] = {0, 0};  // LDS bytes per workgroup
+    int n[kClasses] = {0, 0, 0};    // cells
+    int lds[kClasses] = {0, 0, 0};  // LDS bytes per workgroup
     // batch rule: launches (all of them), their summed duration and LSE terms
-    int launches[kClasses] = {0, 0};
-    double ms[kClasses] = {0.0, 0.0};
-    double terms[kClasses] = {0.0, 0.0};
+    int launches[kClasses] = {0, 0, 0};
+    double ms[kClasses] = {0.0, 0.0, 0.0};
+    double terms[kClasses] = {0.0, 0.0, 0.0};
 };
 
 // True when the batch runs on the register-blocked path: float32 terms, 8 x 8 X blocks,

@@ -1502,9 +1502,10 @@ Status sk_solve(const SkBatch& p, const dd_sinkhorn_opts& o, hipStream_t caller_
         bs.tile_small[1] = hctl[13];
         bs.tile_big[0] = hctl[14];
         bs.tile_big[1] = hctl[15];
-        bs.n_big = fi.n[1];
+        bs.n_big = fi.n[1] + fi.n[2];
+        bs.n_giant = fi.n[2];
         bs.lds_kb[0] = (fi.lds[0] + 1023) / 1024;
-        bs.lds_kb[1] = (fi.lds[1] + 1023) / 1024;
+        bs.lds_kb[1] = (std::max(fi.lds[1], fi.lds[2]) + 1023) / 1024;
         for (int k = 0; k < kClasses; ++k) {
             bs.kernel_launches[k] = fi.launches[k];
             bs.kernel_ms[k] = fi.ms[k];

@@ -54,7 +54,7 @@ struct SkWork {
     hipStream_t stream2 = nullptr;  // and the other classes run side by side
     hipStream_t stream3 = nullptr;
     hipEvent_t evj3 = nullptr;
-    hipEvent_t kev[2][2][4] = {};  // register-blocked path: start/end of each class's rounds
+    hipEvent_t kev[3][2][4] = {};  // register-blocked path: start/end of each class's rounds
 };
 
 Status sk_work_reserve(SkWork& w, int ncells, size_t a_n);
