@@ -40,6 +40,8 @@ namespace {
 
 constexpr int kA = 8;  // X block side
 constexpr int kBlock = 256;
+// largest move of f (in units of kT) tolerated between rebuilds of the absorbed profiles
+constexpr double kProfileDrift = 32.0;
 // Smallest kernel-product sum trusted without the exact fallback.  Every factor is at most 1,
 // so the terms lost to float underflow (each below 1.2e-38, at most 512 of them) stay below
 // 1e-9 of any sum above the floor.
@@ -876,11 +878,28 @@ __device__ __forceinline__ void run_cell(const FastArgs& g, int cell, lds_p<char
     // stop f stays at the start of the last iteration: (f, g) is the pair whose X-marginal
     // error was measured.
     double fc = f, err = 0.0, eref = 1e300, s = 0.0;
+    double fprof = f;  // the f the absorbed profiles were built from (first wave)
     int it = 0;
     bool gpass = g.mode == kFinal;
     for (;;) {
-        // a long solve refreshes the absorbed profiles as f moves
-        if (g.mode == kSolve && it > 0 && (it & 15) == 0) build_y(fc);
+        if (it > 0) {
+            // The absorbed profiles follow f: a long solve refreshes them every 16 iterations,
+            // and any solve as soon as f has moved by more than kProfileDrift anywhere since
+            // they were built (e.g. the first iterations from a start far from the solution),
+            // before the float64 factors of the first Y pass could underflow.
+            double dv = (w == 0 && mu > 0.0) ? fabs(fc - fprof) : 0.0;
+            if (w == 0) dv = wmax(dv);
+            if constexpr (NW > 1) {
+                if (tl == 0) red[2] = dv;
+                Tm::sync();
+                dv = red[2];
+            }
+            dv = uni(dv);
+            if ((g.mode == kSolve && (it & 15) == 0) || dv > kProfileDrift) {
+                build_y(fc);
+                fprof = fc;
+            }
+        }
         y_first(fc);
         if (gpass) {
             write_g();

@@ -126,6 +126,30 @@ def test_register_blocked_path_box_shapes(shape):
         assert np.abs(P.sum(0) - O.sum(0)).sum() <= 1e-5 * m
 
 
+@pytest.mark.parametrize("its", [2, 5, 20])
+def test_register_blocked_path_far_start(its):
+    """A start far from the solution: the zero start of a composite cell whose plan moves mass
+    ~80 pixels (the Knothe-Rosenblatt start at kappa = 1), which in the cell's centred gauge is
+    f0(i) = -2 <G, i> / kappa with G ~ (81, -75), so f moves by thousands in the first
+    iterations.  The float32 path rebuilds its absorbed profiles as f moves and matches the
+    oracle from the same start."""
+    rng = np.random.default_rng(77)
+    cells = random_cells(rng, 12, 8, 8, 30, 1.0)
+    xs = cells["xside"]
+    i1, i2 = np.divmod(np.arange(xs * xs), xs)
+    G = rng.integers(-90, 91, size=(12, 2))
+    a0 = -2.0 * (G[:, :1] * i1[None, :] + G[:, 1:] * i2[None, :]) / cells["kappa"]
+    a, b, it, er, st, status = _run(cells, torch.float32, a0=a0, fixed_iters=its)
+    assert status == 0 and st["path"] == 1 and np.isfinite(st["err"])
+    plans, _, _, _ = oracle_solve(cells, a0=a0, fixed_iters=its)
+    for c in range(len(plans)):
+        P = gpu_plan(cells, c, a, b)
+        O = plans[c]
+        m = O.sum()
+        assert np.isfinite(P).all()
+        assert np.abs(P - O).sum() <= 3e-5 * m, (c, G[c], np.abs(P - O).sum() / m)
+
+
 @pytest.mark.parametrize("dtype", ["f32", "f64"])
 @pytest.mark.parametrize("rule", [0, 1])
 def test_tolerance_solve_matches_oracle(dtype, rule):
