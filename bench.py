@@ -243,42 +243,47 @@ def _per_dispatch(rows, name_part):
 
 def traffic_summary(args):
     """Write the traffic summary from the four counter runs (directories given on the command
-    line): FETCH_SIZE and WRITE_SIZE of the benchmark and of the copy calibration."""
+    line): FETCH_SIZE and WRITE_SIZE of the benchmark and of the copy calibration, for each of
+    the kernels named by --traffic-kernel."""
     fb, wb, fc, wc = args.traffic_from
-    kern = args.traffic_kernel
     last = args.traffic_last
     ref_kib = COPY_MIB * 1024.0
     f_copy = _per_dispatch(_pmc_rows(fc), "copyBuffer")
     w_copy = _per_dispatch(_pmc_rows(wc), "copyBuffer")
     ff = ref_kib / (sum(f_copy) / len(f_copy))
     wf = ref_kib / (sum(w_copy) / len(w_copy))
-    fk = _per_dispatch(_pmc_rows(fb), kern)[-last:]
-    wk = _per_dispatch(_pmc_rows(wb), kern)[-last:]
-    fkib, wkib = sum(fk) / len(fk), sum(wk) / len(wk)
-    rec = {"kernel": kern, "source_sha256": source_sha256(), "dispatches": len(fk),
-           "fetch_kib_per_dispatch": fkib, "write_kib_per_dispatch": wkib,
-           "fetch_factor": ff, "write_factor": wf,
-           "bytes_per_launch": (fkib * ff + wkib * wf) * 1024.0}
+    f_rows, w_rows = _pmc_rows(fb), _pmc_rows(wb)
     cmd_b = ("rocprofv3 --pmc {c} --kernel-trace -d <out> -o run --output-format csv -- "
              "python3 bench.py --steps 3 --warmup 1 --no-compare --no-cpu-baseline")
     cmd_c = ("rocprofv3 --pmc {c} --kernel-trace -d <out> -o run --output-format csv -- "
              "python3 bench.py --copy-calibration")
-    lines = [f"# HBM traffic of `{kern}`, mix512 (512², s = 4, κ = 1, tol 1e-5, batch rule)", "",
+    kinds = " ".join(f"'{k}'" for k in args.traffic_kernel)
+    lines = ["# HBM traffic of the register-blocked kernels, mix512 (512², s = 4, κ = 1, tol 1e-5, "
+             "batch rule)", "",
              "Commands (from the repository root on the GPU box, after `cd /tmp && export "
              "TMPDIR=/tmp`; one counter per run):", "", "```",
              cmd_b.format(c="FETCH_SIZE"), cmd_b.format(c="WRITE_SIZE"),
              cmd_c.format(c="FETCH_SIZE"), cmd_c.format(c="WRITE_SIZE"), "```", "",
              f"Summarised by `python bench.py --traffic-from <four output dirs> --traffic-kernel "
-             f"'{kern}' --traffic-last {last}`.", "",
-             "| counter | copy of 256 MiB (KiB) | scale | kernel, KiB per dispatch | bytes per launch |",
-             "|---|---:|---:|---:|---:|",
-             f"| FETCH_SIZE | {sum(f_copy) / len(f_copy):.0f} | {ff:.3f} | {fkib:.1f} | "
-             f"{fkib * ff * 1024:.4g} |",
-             f"| WRITE_SIZE | {sum(w_copy) / len(w_copy):.0f} | {wf:.3f} | {wkib:.1f} | "
-             f"{wkib * wf * 1024:.4g} |", "",
-             f"Averaged over the last {len(fk)} dispatches of the kernel (the launches of the "
-             "timed steps, the ones after the stop, which exit at once, included).", "",
-             "traffic-json: " + json.dumps(rec)]
+             f"{kinds} --traffic-last {last}`.", "",
+             f"Copy of 256 MiB: FETCH_SIZE reads {sum(f_copy) / len(f_copy):.0f} KiB (scale "
+             f"{ff:.3f}), WRITE_SIZE {sum(w_copy) / len(w_copy):.0f} KiB (scale {wf:.3f}).", "",
+             "| kernel | FETCH_SIZE KiB per dispatch | WRITE_SIZE KiB per dispatch | HBM bytes per "
+             "launch (scaled) |", "|---|---:|---:|---:|"]
+    recs = []
+    for kern in args.traffic_kernel:
+        fk = _per_dispatch(f_rows, kern)[-last:]
+        wk = _per_dispatch(w_rows, kern)[-last:]
+        fkib, wkib = sum(fk) / len(fk), sum(wk) / len(wk)
+        rec = {"kernel": kern, "source_sha256": source_sha256(), "dispatches": len(fk),
+               "fetch_kib_per_dispatch": fkib, "write_kib_per_dispatch": wkib,
+               "fetch_factor": ff, "write_factor": wf,
+               "bytes_per_launch": (fkib * ff + wkib * wf) * 1024.0}
+        recs.append(rec)
+        lines.append(f"| `{kern}` | {fkib:.1f} | {wkib:.1f} | {rec['bytes_per_launch']:.4g} |")
+    lines += ["", f"Averaged over the last {last} dispatches of each kernel (the launches of the "
+              "timed steps, the ones after the stop, which exit at once, included).", ""]
+    lines += ["traffic-json: " + json.dumps(r) for r in recs]
     with open(args.traffic_out, "w") as f:
         f.write("\n".join(lines) + "\n")
     print("\n".join(lines))
@@ -364,7 +369,9 @@ def main():
     ap.add_argument("--traffic-from", nargs=4, metavar="DIR",
                     help="write the traffic summary from four rocprofv3 --pmc output "
                          "directories: FETCH_SIZE and WRITE_SIZE of the benchmark, then of the copy")
-    ap.add_argument("--traffic-kernel", default="fast_kernel<4, 16, false, 2>")
+    ap.add_argument("--traffic-kernel", nargs="+",
+                    default=["fast_kernel<1, 4, true, 2>", "fast_kernel<4, 16, false, 2>",
+                             "fast_kernel<8, 8, false, 2>"])
     ap.add_argument("--traffic-last", type=int, default=139)
     ap.add_argument("--traffic-out", default=TRAFFIC_SUMMARY)
     ap.add_argument("--trace-from", metavar="DIR",
