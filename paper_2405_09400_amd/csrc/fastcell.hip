@@ -1092,14 +1092,36 @@ Status prep(Kern k, int block, size_t lds, int items, int& grid) {
 
 }  // namespace
 
+namespace {
+// class of a box with long side a and short side b (kernel frame)
+int cell_class(int a, int b) { return a <= kWaveSide ? 0 : a * b > kBigEntries ? 2 : 1; }
+constexpr int kClassTeam[kClasses] = {1, 4, 8};
+constexpr size_t kLdsPerCu = 160 * 1024;
+}  // namespace
+
 bool fast_eligible(const SkBatch& p, const std::vector<int32_t>& hd) {
     static const bool off = [] {
         const char* e = std::getenv("DD_FAST");
         return e && e[0] == '0';
     }();
     if (off || p.prec != DD_PREC_F32 || p.xside != kA) return false;
-    for (int c = 0; c < p.ncells; ++c)
-        if (std::max(hd[2 * c], hd[2 * c + 1]) > kFastMaxSide) return false;
+    int W1m[kClasses] = {1, 1, 1}, W2m[kClasses] = {1, 1, 1};
+    for (int c = 0; c < p.ncells; ++c) {
+        const int a = std::max(std::max(hd[2 * c], hd[2 * c + 1]), 1);
+        const int b = std::max(std::min(hd[2 * c], hd[2 * c + 1]), 1);
+        if (a > kFastMaxSide) return false;
+        const int k = cell_class(a, b);
+        W1m[k] = std::max(W1m[k], a);
+        W2m[k] = std::max(W2m[k], b);
+    }
+    // every class's workgroup must fit the LDS of a CU (large boxes of the eight-wave class
+    // may not: those batches take the general path)
+    for (int k = 0; k < kClasses; ++k) {
+        const int t = kClassTeam[k];
+        const size_t need = t == 1 ? kBlock / 64 * slice_bytes(1, W1m[k], W2m[k])
+                                   : slice_bytes(t, W1m[k], W2m[k]);
+        if (need > kLdsPerCu) return false;
+    }
     return true;
 }
 
@@ -1114,7 +1136,7 @@ Status fast_solve(const SkBatch& p, const dd_sinkhorn_opts& o, hipStream_t st, S
     // Classes 1 and 2 read log nu_J from global memory.
     using KernFn = void (*)(FastArgs);
     const KernFn fns[kClasses] = {FAST_WAVE, FAST_GROUP, FAST_BIG};
-    const int team[kClasses] = {1, 4, 8};
+    const int* team = kClassTeam;
     const int rpl[kClasses] = {4, 16, 8};  // rows per lane: a team covers 8 * team * rpl rows
     const int qidx[kClasses] = {9, 0, 11};
     // the eight-wave class goes on the caller's stream, which no event holds back, so that its
@@ -1125,7 +1147,7 @@ Status fast_solve(const SkBatch& p, const dd_sinkhorn_opts& o, hipStream_t st, S
     for (int c = 0; c < n; ++c) {
         const int a = std::max(std::max(hd[2 * c], hd[2 * c + 1]), 1);
         const int b = std::max(std::min(hd[2 * c], hd[2 * c + 1]), 1);
-        const int k = a <= kWaveSide ? 0 : a * b > kBigEntries ? 2 : 1;
+        const int k = cell_class(a, b);
         cells[k].push_back(c);
         W1m[k] = std::max(W1m[k], a);
         W2m[k] = std::max(W2m[k], b);

@@ -21,7 +21,8 @@ struct FastInfo {
 };
 
 // True when the batch runs on the register-blocked path: float32 terms, 8 x 8 X blocks,
-// every box side at most kFastMaxSide, and the path not switched off (DD_FAST=0).
+// every box side at most kFastMaxSide, every class's workgroup within the LDS of a CU, and
+// the path not switched off (DD_FAST=0).
 bool fast_eligible(const SkBatch& p, const std::vector<int32_t>& hd);
 constexpr int kFastMaxSide = 512;
 

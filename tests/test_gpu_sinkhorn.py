@@ -126,6 +126,25 @@ def test_register_blocked_path_box_shapes(shape):
         assert np.abs(P.sum(0) - O.sum(0)).sum() <= 1e-5 * m
 
 
+def test_boxes_beyond_register_blocked_lds_take_general_path():
+    """A 400 x 400 box needs more LDS per eight-wave workgroup than a CU has: the batch runs on
+    the general path (path 0) and still matches the oracle."""
+    rng = np.random.default_rng(88)
+    cells = random_cells(rng, 2, 8, 400, 400, 4.0)
+    a0 = _a0(rng, cells)
+    a, b, it, er, st, status = _run(cells, torch.float32, a0=a0, fixed_iters=10)
+    assert status == 0 and st["path"] == 0
+    plans, _, _, _ = oracle_solve(cells, a0=a0, fixed_iters=10)
+    # float32 sums over lines of W = 400 terms: a linear bound on the rounding accumulated over
+    # 10 iterations of 4 one-dimensional passes is 10 * 4 * W * 2^-24 ~ 1e-3 of the plan (the
+    # 3e-5 bar of the other float32 tests is for boxes up to ~70 a side)
+    bar = 10 * 4 * 400 * 2.0 ** -24
+    for c in range(len(plans)):
+        P = gpu_plan(cells, c, a, b)
+        O = plans[c]
+        assert np.abs(P - O).sum() <= bar * O.sum(), (c, np.abs(P - O).sum() / O.sum())
+
+
 @pytest.mark.parametrize("its", [2, 5, 20])
 def test_register_blocked_path_far_start(its):
     """A start far from the solution: the zero start of a composite cell whose plan moves mass
