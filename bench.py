@@ -260,7 +260,7 @@ def traffic_summary(args):
     kinds = " ".join(f"'{k}'" for k in args.traffic_kernel)
     lines = ["# HBM traffic of the register-blocked kernels, mix512 (512², s = 4, κ = 1, tol 1e-5, "
              "batch rule)", "",
-             "Commands (from the repository root on the GPU box, after `cd /tmp && export "
+             "Commands (from the repository root on the MI355X machine, after `cd /tmp && export "
              "TMPDIR=/tmp`; one counter per run):", "", "```",
              cmd_b.format(c="FETCH_SIZE"), cmd_b.format(c="WRITE_SIZE"),
              cmd_c.format(c="FETCH_SIZE"), cmd_c.format(c="WRITE_SIZE"), "```", "",
@@ -304,7 +304,7 @@ def trace_summary(args):
     cmd = ("rocprofv3 --kernel-trace --stats -d <out> -o run --output-format csv -- "
            "python3 bench.py --steps 3 --warmup 1 --no-compare --no-cpu-baseline")
     lines = ["# Cell Sinkhorn kernels, mix512 (512², s = 4, κ = 1, tol 1e-5, batch rule)", "",
-             "Command (from the repository root on the GPU box, after `cd /tmp && export "
+             "Command (from the repository root on the MI355X machine, after `cd /tmp && export "
              "TMPDIR=/tmp`):", "", "```", cmd, "```", "",
              f"Summarised by `python bench.py --trace-from <out> --traffic-last "
              f"{args.traffic_last}`.  Kernel source SHA-256 (fastcell.hip): "
@@ -386,7 +386,7 @@ def main():
         return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
-              "sharding of the method is described in DESIGN.md but not built.", file=sys.stderr)
+              "sharding of the method is not built (this benchmark runs one GPU).", file=sys.stderr)
         sys.exit(2)
 
     import torch
