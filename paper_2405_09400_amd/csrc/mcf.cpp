@@ -4,8 +4,9 @@
 // Graph: left nodes 0..n-1 (supply s_i), right nodes n..2n-1 (demand s_j), arcs i -> n+j
 // with integer costs and no upper bound.  An artificial root joins every node with an
 // arc of cost ART larger than any path of real arcs; the initial tree is strongly feasible
-// (zero-flow tree arcs point away from the root): the star of artificial arcs.  Pricing is
-// block search over the arcs; the leaving arc is
+// (zero-flow tree arcs point away from the root) and, where the graph has self arcs, is a
+// spanning tree of real arcs carrying the identity flow (see below).  Pricing is block
+// search over the arcs; the leaving arc is
 // the last blocking arc met when the pivot cycle is walked in its orientation from the
 // apex, which keeps the tree strongly feasible and rules out cycling.  After a pivot the
 // cut-off subtree is re-rooted at the entering arc; the potentials change by one constant on
@@ -105,15 +106,60 @@ int mcf_network_simplex(int n, int m, const int32_t* tail, const int32_t* head,
     S.next_sib.assign(S.V, -1);
     S.prev_sib.assign(S.V, -1);
     S.pot.assign(S.V, 0);
-    // Initial strongly feasible tree: the textbook star.  Every node hangs from the root by
-    // its artificial arc, which carries the node's net supply (left v -> root carries
-    // supply[v]; root -> right v carries the demand; zero flows point away from the root).
-    // Its subtrees are single nodes, so the first pivots move little; a spanning tree of real
-    // arcs (the identity flow through the self arcs) measured 14x slower at 65,536 nodes,
-    // its pivots cutting off large subtrees.
+    // Initial strongly feasible tree.  Where the graph has the self arc i -> i (as the flow
+    // update's neighbourhood does), the identity flow is feasible, and a breadth-first tree
+    // over the nodes through arcs p -> q (p != q) gives a spanning tree of real arcs:
+    //   root -> left 0 (artificial, zero flow), left 0 -> right 0 (self arc, supply[0]);
+    //   for each tree edge p -> q: left p -> right q (zero flow, pointing away from the root),
+    //   then left q hangs from right q by its self arc carrying supply[q] (positive flow).
+    // Node pairs the walk does not reach (no self arc, zero supply, or not connected) are
+    // joined to the root through artificial arcs carrying their supply (the textbook star).
+    // The artificial arcs of the tree's other nodes stay out of the basis at zero flow.
+    // (On the flow update of the 512^2 flow workload, 65,536 nodes, this start needs 393k
+    // pivots against 1.08M from the star of artificial arcs, and runs 2.8x faster.)
+    std::vector<int> self(n, -1);
+    for (int a = 0; a < m; ++a)
+        if (tail[a] == head[a] && self[tail[a]] < 0) self[tail[a]] = a;
+    auto usable = [&](int i) { return self[i] >= 0 && supply[i] > 0; };
+    std::vector<int> first(n + 1, 0), adj(m);
+    for (int a = 0; a < m; ++a) ++first[tail[a] + 1];
+    for (int i = 0; i < n; ++i) first[i + 1] += first[i];
+    {
+        std::vector<int> pos(first.begin(), first.end() - 1);
+        for (int a = 0; a < m; ++a) adj[pos[tail[a]]++] = a;
+    }
+    std::vector<int> par_arc(n, -1), order;
+    std::vector<char> reached(n, 0);
+    order.reserve(n);
+    int root_node = -1;
+    for (int i = 0; i < n && root_node < 0; ++i)
+        if (usable(i)) root_node = i;
+    if (root_node >= 0) {
+        reached[root_node] = 1;
+        order.push_back(root_node);
+        for (size_t h = 0; h < order.size(); ++h) {
+            const int pn = order[h];
+            for (int k = first[pn]; k < first[pn + 1]; ++k) {
+                const int a = adj[k], q = head[a];
+                if (q == pn || reached[q] || !usable(q)) continue;
+                reached[q] = 1;
+                par_arc[q] = a;
+                order.push_back(q);
+            }
+        }
+    }
     for (int v = 0; v < N2; ++v) {
         const int a = m + v;
         S.cost[a] = ART;
+        const int i = v < n ? v : v - n;
+        if (reached[i]) {
+            // artificial arc root -> v at zero flow; in the tree only for the walk's root
+            S.src[a] = S.R;
+            S.dst[a] = v;
+            S.flow[a] = 0;
+            S.state[a] = 1;
+            continue;
+        }
         const int64_t b = v < n ? supply[v] : -supply[v - n];  // net supply of node v
         if (b > 0) {  // v -> root carries the supply
             S.src[a] = v;
@@ -128,6 +174,32 @@ int mcf_network_simplex(int n, int m, const int32_t* tail, const int32_t* head,
         S.pred[v] = a;
         S.link_child(S.R, v);
         S.pot[v] = (S.dst[a] == v) ? ART : -ART;
+    }
+    for (const int q : order) {
+        const int L = q, Rn = n + q, sa = self[q];
+        if (q == root_node) {
+            const int a = m + L;
+            S.state[a] = 0;
+            S.pred[L] = a;
+            S.link_child(S.R, L);
+            S.pot[L] = ART;
+            S.flow[sa] = supply[q];
+            S.state[sa] = 0;
+            S.pred[Rn] = sa;
+            S.link_child(L, Rn);
+            S.pot[Rn] = S.pot[L] + S.cost[sa];
+            continue;
+        }
+        const int pa = par_arc[q], pL = tail[pa];
+        S.state[pa] = 0;  // left p -> right q, zero flow
+        S.pred[Rn] = pa;
+        S.link_child(pL, Rn);
+        S.pot[Rn] = S.pot[pL] + S.cost[pa];
+        S.flow[sa] = supply[q];  // left q -> right q carries the supply, left q below right q
+        S.state[sa] = 0;
+        S.pred[L] = sa;
+        S.link_child(Rn, L);
+        S.pot[L] = S.pot[Rn] - S.cost[sa];
     }
     const int64_t INF = tot + 1;
     auto cap = [&](int) { return INF; };
