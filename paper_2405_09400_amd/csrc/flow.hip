@@ -46,6 +46,7 @@ struct FlowState {
     int32_t* d_flags = nullptr;
     double* d_tmp = nullptr;
     size_t tmp_cap = 0;
+    McfWarm* mcf_warm = nullptr;  // the last min-cost flow's optimal basis (same graph, supplies)
 };
 
 namespace {
@@ -328,6 +329,7 @@ void flow_release(dd_ctx* c) {
     Fr(F->d_nsize);
     Fr(F->d_flags);
     Fr(F->d_tmp);
+    mcf_warm_free(F->mcf_warm);
     delete F;
     c->flow = nullptr;
 }
@@ -469,8 +471,11 @@ extern "C" dd_status flow_update(dd_ctx* c, dd_flow_stats* out) {
     for (double v : cbar) cmax = std::max(cmax, std::fabs(v));
     const double scale = cmax > 0 ? (double)((int64_t)1 << 30) / cmax : 0.0;
     for (int a = 0; a < na; ++a) cost[a] = (int64_t)std::nearbyint(cbar[a] * scale);
-    const int r = mcf_network_simplex(nI, na, F->tail.data(), F->head.data(), cost.data(), b.data(),
-                                      flow.data(), nullptr);
+    // successive updates share the graph and the supplies (the masses of mu): the last
+    // update's optimal basis starts this one
+    if (!F->mcf_warm) F->mcf_warm = mcf_warm_create();
+    const int r = mcf_network_simplex_warm(nI, na, F->tail.data(), F->head.data(), cost.data(),
+                                           b.data(), flow.data(), nullptr, F->mcf_warm);
     if (r != 0) return ffail(c, DD_ENUMERIC, "flow_update: min-cost flow failed");
     const auto t2 = clk::now();
     std::vector<double> w(na);

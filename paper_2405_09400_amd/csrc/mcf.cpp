@@ -23,8 +23,6 @@
 
 namespace dd {
 
-namespace {
-
 struct Simplex {
     int V = 0, M = 0, R = 0;  // nodes (incl. root), real arcs, root id
     std::vector<int> src, dst;
@@ -68,12 +66,35 @@ struct Simplex {
     }
 };
 
-}  // namespace
+// A solved problem kept for the next one on the same graph and supplies (the flow update of
+// successive B iterations): its optimal basis is a strongly feasible start for new costs.
+struct McfWarm {
+    bool valid = false;
+    int n = 0, m = 0;
+    std::vector<int32_t> tail, head;
+    std::vector<int64_t> supply;
+    Simplex S;
+};
+
+McfWarm* mcf_warm_create() { return new McfWarm(); }
+void mcf_warm_free(McfWarm* w) { delete w; }
 
 int mcf_network_simplex(int n, int m, const int32_t* tail, const int32_t* head,
                         const int64_t* cost, const int64_t* supply, int64_t* flow_out,
                         int64_t* pot_out) {
-    Simplex S;
+    return mcf_network_simplex_warm(n, m, tail, head, cost, supply, flow_out, pot_out, nullptr);
+}
+
+int mcf_network_simplex_warm(int n, int m, const int32_t* tail, const int32_t* head,
+                             const int64_t* cost, const int64_t* supply, int64_t* flow_out,
+                             int64_t* pot_out, McfWarm* warm) {
+    const bool reuse = warm && warm->valid && warm->n == n && warm->m == m &&
+                       std::equal(tail, tail + m, warm->tail.begin()) &&
+                       std::equal(head, head + m, warm->head.begin()) &&
+                       std::equal(supply, supply + n, warm->supply.begin());
+    Simplex fresh;
+    Simplex& S = reuse ? warm->S : fresh;
+    if (warm) warm->valid = false;  // until this solve ends
     const int N2 = 2 * n;
     S.V = N2 + 1;
     S.R = N2;
@@ -82,8 +103,10 @@ int mcf_network_simplex(int n, int m, const int32_t* tail, const int32_t* head,
     S.src.resize(A);
     S.dst.resize(A);
     S.cost.resize(A);
-    S.flow.assign(A, 0);
-    S.state.assign(A, 1);
+    if (!reuse) {
+        S.flow.assign(A, 0);
+        S.state.assign(A, 1);
+    }
     int64_t maxc = 1, tot = 0;
     for (int a = 0; a < m; ++a) {
         if (tail[a] < 0 || tail[a] >= n || head[a] < 0 || head[a] >= n) return -2;
@@ -98,127 +121,144 @@ int mcf_network_simplex(int n, int m, const int32_t* tail, const int32_t* head,
     }
     // no real path is longer than 2n arcs; ART dominates every real path cost
     const int64_t ART = maxc * (int64_t)(N2 + 1) + 1;
-    S.parent.assign(S.V, -1);
-    S.pred.assign(S.V, -1);
-    S.size.assign(S.V, 1);
-    S.mark.assign(S.V, 0);
-    S.first_child.assign(S.V, -1);
-    S.next_sib.assign(S.V, -1);
-    S.prev_sib.assign(S.V, -1);
-    S.pot.assign(S.V, 0);
-    // Initial strongly feasible tree.  Where the graph has the self arc i -> i (as the flow
-    // update's neighbourhood does), the identity flow is feasible, and a breadth-first tree
-    // over the nodes through arcs p -> q (p != q) gives a spanning tree of real arcs:
-    //   root -> left 0 (artificial, zero flow), left 0 -> right 0 (self arc, supply[0]);
-    //   for each tree edge p -> q: left p -> right q (zero flow, pointing away from the root),
-    //   then left q hangs from right q by its self arc carrying supply[q] (positive flow).
-    // Node pairs the walk does not reach (no self arc, zero supply, or not connected) are
-    // joined to the root through artificial arcs carrying their supply (the textbook star).
-    // The artificial arcs of the tree's other nodes stay out of the basis at zero flow.
-    // (On the flow update of the 512^2 flow workload, 65,536 nodes, this start needs 393k
-    // pivots against 1.08M from the star of artificial arcs, and runs 2.8x faster.)
-    std::vector<int> self(n, -1);
-    for (int a = 0; a < m; ++a)
-        if (tail[a] == head[a] && self[tail[a]] < 0) self[tail[a]] = a;
-    auto usable = [&](int i) { return self[i] >= 0 && supply[i] > 0; };
-    std::vector<int> first(n + 1, 0), adj(m);
-    for (int a = 0; a < m; ++a) ++first[tail[a] + 1];
-    for (int i = 0; i < n; ++i) first[i + 1] += first[i];
-    {
-        std::vector<int> pos(first.begin(), first.end() - 1);
-        for (int a = 0; a < m; ++a) adj[pos[tail[a]]++] = a;
-    }
-    std::vector<int> par_arc(n, -1), order;
-    std::vector<char> reached(n, 0);
-    order.reserve(n);
-    int root_node = -1;
-    for (int i = 0; i < n && root_node < 0; ++i)
-        if (usable(i)) root_node = i;
-    if (root_node >= 0) {
-        reached[root_node] = 1;
-        order.push_back(root_node);
-        for (size_t h = 0; h < order.size(); ++h) {
-            const int pn = order[h];
-            for (int k = first[pn]; k < first[pn + 1]; ++k) {
-                const int a = adj[k], q = head[a];
-                if (q == pn || reached[q] || !usable(q)) continue;
-                reached[q] = 1;
-                par_arc[q] = a;
-                order.push_back(q);
+    std::vector<int> stack, cyc_arc, path, own;
+    if (!reuse) {
+        S.parent.assign(S.V, -1);
+        S.pred.assign(S.V, -1);
+        S.size.assign(S.V, 1);
+        S.mark.assign(S.V, 0);
+        S.first_child.assign(S.V, -1);
+        S.next_sib.assign(S.V, -1);
+        S.prev_sib.assign(S.V, -1);
+        S.pot.assign(S.V, 0);
+        // Initial strongly feasible tree.  Where the graph has the self arc i -> i (as the flow
+        // update's neighbourhood does), the identity flow is feasible, and a breadth-first tree
+        // over the nodes through arcs p -> q (p != q) gives a spanning tree of real arcs:
+        //   root -> left 0 (artificial, zero flow), left 0 -> right 0 (self arc, supply[0]);
+        //   for each tree edge p -> q: left p -> right q (zero flow, pointing away from the root),
+        //   then left q hangs from right q by its self arc carrying supply[q] (positive flow).
+        // Node pairs the walk does not reach (no self arc, zero supply, or not connected) are
+        // joined to the root through artificial arcs carrying their supply (the textbook star).
+        // The artificial arcs of the tree's other nodes stay out of the basis at zero flow.
+        // (On the flow update of the 512^2 flow workload, 65,536 nodes, this start needs 393k
+        // pivots against 1.08M from the star of artificial arcs, and runs 2.8x faster.)
+        std::vector<int> self(n, -1);
+        for (int a = 0; a < m; ++a)
+            if (tail[a] == head[a] && self[tail[a]] < 0) self[tail[a]] = a;
+        auto usable = [&](int i) { return self[i] >= 0 && supply[i] > 0; };
+        std::vector<int> first(n + 1, 0), adj(m);
+        for (int a = 0; a < m; ++a) ++first[tail[a] + 1];
+        for (int i = 0; i < n; ++i) first[i + 1] += first[i];
+        {
+            std::vector<int> pos(first.begin(), first.end() - 1);
+            for (int a = 0; a < m; ++a) adj[pos[tail[a]]++] = a;
+        }
+        std::vector<int> par_arc(n, -1), order;
+        std::vector<char> reached(n, 0);
+        order.reserve(n);
+        int root_node = -1;
+        for (int i = 0; i < n && root_node < 0; ++i)
+            if (usable(i)) root_node = i;
+        if (root_node >= 0) {
+            reached[root_node] = 1;
+            order.push_back(root_node);
+            for (size_t h = 0; h < order.size(); ++h) {
+                const int pn = order[h];
+                for (int k = first[pn]; k < first[pn + 1]; ++k) {
+                    const int a = adj[k], q = head[a];
+                    if (q == pn || reached[q] || !usable(q)) continue;
+                    reached[q] = 1;
+                    par_arc[q] = a;
+                    order.push_back(q);
+                }
             }
         }
-    }
-    for (int v = 0; v < N2; ++v) {
-        const int a = m + v;
-        S.cost[a] = ART;
-        const int i = v < n ? v : v - n;
-        if (reached[i]) {
-            // artificial arc root -> v at zero flow; in the tree only for the walk's root
-            S.src[a] = S.R;
-            S.dst[a] = v;
-            S.flow[a] = 0;
-            S.state[a] = 1;
-            continue;
-        }
-        const int64_t b = v < n ? supply[v] : -supply[v - n];  // net supply of node v
-        if (b > 0) {  // v -> root carries the supply
-            S.src[a] = v;
-            S.dst[a] = S.R;
-            S.flow[a] = b;
-        } else {      // root -> v, zero flow points away from the root
-            S.src[a] = S.R;
-            S.dst[a] = v;
-            S.flow[a] = -b;
-        }
-        S.state[a] = 0;
-        S.pred[v] = a;
-        S.link_child(S.R, v);
-        S.pot[v] = (S.dst[a] == v) ? ART : -ART;
-    }
-    for (const int q : order) {
-        const int L = q, Rn = n + q, sa = self[q];
-        if (q == root_node) {
-            const int a = m + L;
+        for (int v = 0; v < N2; ++v) {
+            const int a = m + v;
+            S.cost[a] = ART;
+            const int i = v < n ? v : v - n;
+            if (reached[i]) {
+                // artificial arc root -> v at zero flow; in the tree only for the walk's root
+                S.src[a] = S.R;
+                S.dst[a] = v;
+                S.flow[a] = 0;
+                S.state[a] = 1;
+                continue;
+            }
+            const int64_t b = v < n ? supply[v] : -supply[v - n];  // net supply of node v
+            if (b > 0) {  // v -> root carries the supply
+                S.src[a] = v;
+                S.dst[a] = S.R;
+                S.flow[a] = b;
+            } else {      // root -> v, zero flow points away from the root
+                S.src[a] = S.R;
+                S.dst[a] = v;
+                S.flow[a] = -b;
+            }
             S.state[a] = 0;
-            S.pred[L] = a;
-            S.link_child(S.R, L);
-            S.pot[L] = ART;
-            S.flow[sa] = supply[q];
-            S.state[sa] = 0;
-            S.pred[Rn] = sa;
-            S.link_child(L, Rn);
-            S.pot[Rn] = S.pot[L] + S.cost[sa];
-            continue;
+            S.pred[v] = a;
+            S.link_child(S.R, v);
+            S.pot[v] = (S.dst[a] == v) ? ART : -ART;
         }
-        const int pa = par_arc[q], pL = tail[pa];
-        S.state[pa] = 0;  // left p -> right q, zero flow
-        S.pred[Rn] = pa;
-        S.link_child(pL, Rn);
-        S.pot[Rn] = S.pot[pL] + S.cost[pa];
-        S.flow[sa] = supply[q];  // left q -> right q carries the supply, left q below right q
-        S.state[sa] = 0;
-        S.pred[L] = sa;
-        S.link_child(Rn, L);
-        S.pot[L] = S.pot[Rn] - S.cost[sa];
+        for (const int q : order) {
+            const int L = q, Rn = n + q, sa = self[q];
+            if (q == root_node) {
+                const int a = m + L;
+                S.state[a] = 0;
+                S.pred[L] = a;
+                S.link_child(S.R, L);
+                S.pot[L] = ART;
+                S.flow[sa] = supply[q];
+                S.state[sa] = 0;
+                S.pred[Rn] = sa;
+                S.link_child(L, Rn);
+                S.pot[Rn] = S.pot[L] + S.cost[sa];
+                continue;
+            }
+            const int pa = par_arc[q], pL = tail[pa];
+            S.state[pa] = 0;  // left p -> right q, zero flow
+            S.pred[Rn] = pa;
+            S.link_child(pL, Rn);
+            S.pot[Rn] = S.pot[pL] + S.cost[pa];
+            S.flow[sa] = supply[q];  // left q -> right q carries the supply, left q below right q
+            S.state[sa] = 0;
+            S.pred[L] = sa;
+            S.link_child(Rn, L);
+            S.pot[L] = S.pot[Rn] - S.cost[sa];
+        }
+        // subtree sizes of the initial tree (children before parents in reverse preorder)
+        {
+            std::vector<int> pre;
+            pre.reserve(S.V);
+            stack.assign(1, S.R);
+            while (!stack.empty()) {
+                const int x = stack.back();
+                stack.pop_back();
+                pre.push_back(x);
+                for (int c = S.first_child[x]; c >= 0; c = S.next_sib[c]) stack.push_back(c);
+            }
+            if ((int)pre.size() != S.V) return -2;  // not a spanning tree: cannot happen
+            for (int k = S.V - 1; k > 0; --k) S.size[S.parent[pre[k]]] += S.size[pre[k]];
+        }
+    } else {
+        // the previous optimum: same tree, flows and artificial arcs; new costs, so new
+        // potentials from the root down
+        for (int v = 0; v < N2; ++v) S.cost[m + v] = ART;
+        stack.assign(1, S.R);
+        S.pot[S.R] = 0;
+        while (!stack.empty()) {
+            const int x = stack.back();
+            stack.pop_back();
+            if (x != S.R) {
+                const int p = S.parent[x], a = S.pred[x];
+                S.pot[x] = (S.dst[a] == x) ? S.pot[p] + S.cost[a] : S.pot[p] - S.cost[a];
+            }
+            for (int c = S.first_child[x]; c >= 0; c = S.next_sib[c]) stack.push_back(c);
+        }
     }
     const int64_t INF = tot + 1;
     auto cap = [&](int) { return INF; };
 
-    std::vector<int> stack, cyc_arc, path, own;
-    // subtree sizes of the initial tree (children before parents in reverse preorder)
-    {
-        std::vector<int> pre;
-        pre.reserve(S.V);
-        stack.assign(1, S.R);
-        while (!stack.empty()) {
-            const int x = stack.back();
-            stack.pop_back();
-            pre.push_back(x);
-            for (int c = S.first_child[x]; c >= 0; c = S.next_sib[c]) stack.push_back(c);
-        }
-        if ((int)pre.size() != S.V) return -2;  // not a spanning tree: cannot happen
-        for (int k = S.V - 1; k > 0; --k) S.size[S.parent[pre[k]]] += S.size[pre[k]];
-    }
     std::vector<int8_t> cyc_fwd;
     const int block = std::max(16, (int)std::sqrt((double)A));
     int next = 0;
@@ -340,6 +380,17 @@ int mcf_network_simplex(int n, int m, const int32_t* tail, const int32_t* head,
     for (int k = 0; k < m; ++k) flow_out[k] = S.flow[k];
     if (pot_out)
         for (int v = 0; v < N2; ++v) pot_out[v] = S.pot[v];
+    if (warm) {
+        if (!reuse) {
+            warm->S = std::move(fresh);
+            warm->n = n;
+            warm->m = m;
+            warm->tail.assign(tail, tail + m);
+            warm->head.assign(head, head + m);
+            warm->supply.assign(supply, supply + n);
+        }
+        warm->valid = true;
+    }
     return 0;
 }
 

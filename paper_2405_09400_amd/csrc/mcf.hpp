@@ -14,4 +14,15 @@ int mcf_network_simplex(int n, int m, const int32_t* tail, const int32_t* head,
                         const int64_t* cost, const int64_t* supply, int64_t* flow_out,
                         int64_t* pot_out);
 
+// The same with a kept state: when the graph and the supplies equal those of the last
+// successful solve kept in `warm`, that solve's optimal basis (tree and flows) is the start
+// and only the potentials are rebuilt for the new costs; the solve is then kept in `warm`.
+// warm may be null.
+struct McfWarm;
+McfWarm* mcf_warm_create();
+void mcf_warm_free(McfWarm* w);
+int mcf_network_simplex_warm(int n, int m, const int32_t* tail, const int32_t* head,
+                             const int64_t* cost, const int64_t* supply, int64_t* flow_out,
+                             int64_t* pot_out, McfWarm* warm);
+
 }  // namespace dd
