@@ -12,7 +12,8 @@
 // cut-off subtree is re-rooted at the entering arc; the potentials change by one constant on
 // one side of the entering arc, so the smaller side (by the subtree sizes the tree keeps) is
 // shifted, by a walk over explicit child lists.  The apex of a pivot cycle is found by
-// marking the path from one end to the root.
+// climbing from both ends in turn, and subtree sizes change only below it, so the tree
+// bookkeeping of a pivot costs the length of its cycle, not the depth of the tree.
 #include <algorithm>
 #include <cmath>
 #include <cstdint>
@@ -49,6 +50,33 @@ struct Simplex {
             first_child[p] = next_sib[c];
         if (next_sib[c] >= 0) prev_sib[next_sib[c]] = prev_sib[c];
         prev_sib[c] = next_sib[c] = -1;
+    }
+
+    // nearest common ancestor of a and b: the two ends climb in turn, each marking what it
+    // passes, until one reaches a node the other has marked, so the cost is the length of
+    // the pivot cycle rather than the depth of the tree
+    int apex(int a, int b) {
+        if (a == b) return a;
+        if (stamp > (1 << 30)) {  // a long run of warm-started solves: restart the stamps
+            std::fill(mark.begin(), mark.end(), 0);
+            stamp = 0;
+        }
+        stamp += 2;
+        const int ma = stamp - 1, mb = stamp;
+        mark[a] = ma;
+        mark[b] = mb;
+        for (;;) {
+            if (parent[a] >= 0) {
+                a = parent[a];
+                if (mark[a] == mb) return a;
+                mark[a] = ma;
+            }
+            if (parent[b] >= 0) {
+                b = parent[b];
+                if (mark[b] == ma) return b;
+                mark[b] = mb;
+            }
+        }
     }
 
     // add d to the potentials of the subtree rooted at r (skip < 0), or of the whole tree
@@ -289,10 +317,7 @@ int mcf_network_simplex_warm(int n, int m, const int32_t* tail, const int32_t* h
 
         // pivot cycle: enter u -> v, tree paths from u and v to the apex
         const int u = S.src[enter], v = S.dst[enter];
-        ++S.stamp;
-        for (int x = u; x >= 0; x = S.parent[x]) S.mark[x] = S.stamp;
-        int join = v;
-        while (S.mark[join] != S.stamp) join = S.parent[join];
+        const int join = S.apex(u, v);
         // walk in orientation order: apex -> ... -> u, u -> v, v -> ... -> apex
         cyc_arc.clear();
         cyc_fwd.clear();
@@ -339,8 +364,9 @@ int mcf_network_simplex_warm(int n, int m, const int32_t* tail, const int32_t* h
         const bool u_side = leave_k < pos_enter;
         const int w_in = u_side ? u : v, z_in = u_side ? v : u;
         // the cut subtree leaves the ancestors of q ...
+        // (the apex and its ancestors lose it and regain it below z_in: their sizes stay)
         const int sub = S.size[q];
-        for (int y = S.parent[q]; y >= 0; y = S.parent[y]) S.size[y] -= sub;
+        for (int y = S.parent[q]; y != join; y = S.parent[y]) S.size[y] -= sub;
         // ... is re-rooted at w_in (parent pointers reversed from w_in up to q).  A path node
         // keeps its old subtree minus the branch towards w_in, and gains the path above it:
         // its new size is the sum of those own parts from q down to it ...
@@ -365,7 +391,7 @@ int mcf_network_simplex_warm(int n, int m, const int32_t* tail, const int32_t* h
             S.size[path[k]] = acc;
         }
         // ... and hangs below z_in
-        for (int y = z_in; y >= 0; y = S.parent[y]) S.size[y] += sub;
+        for (int y = z_in; y != join; y = S.parent[y]) S.size[y] += sub;
         S.state[enter] = 0;
         S.state[leave] = 1;
         // the entering arc gets reduced cost 0: the side of w_in moves by d against the other
