@@ -2,10 +2,12 @@
 // X-update that turns a predicted Y potential into the initial X potential.
 //
 // All kernels are direct 3x3 convolutions on the vector ALUs: one workgroup of 256 lanes
-// per sample, one output pixel per lane (every layer has a 16x16 output), the sample's
-// input and the layer's weights staged in LDS (weights converted from BF16 once per
-// workgroup, laid out [ci][tap][co] so that each lane reads them as broadcasts), FP32
-// accumulation.  Training keeps FP32 master weights with Adam and refreshes the BF16
+// per sample, one output pixel per lane (every layer has a 16x16 output), FP32
+// accumulation.  The forward kernel stages the sample's input in LDS and reads the weights
+// (the BF16 values widened to FP32 after every update, laid out [ci][tap][co]) with
+// wave-uniform loads from global memory, so they arrive through the scalar cache and feed the
+// multiply-adds as scalar operands instead of occupying LDS bandwidth.  The backward kernels
+// stage the weights in LDS.  Training keeps FP32 master weights with Adam and refreshes the BF16
 // copy after every step.  The weight gradients are reduced over the batch in a fixed
 // order (per-workgroup partials, then one reduction), so training is deterministic.
 #include "net.hpp"
@@ -73,16 +75,12 @@ __device__ __forceinline__ uint16_t f2bf(float f) {
 template <int CO>
 __global__ void __launch_bounds__(kT)
     conv_fwd_kernel(ConvDesc d, int n, const float* __restrict__ x,
-                    const uint16_t* __restrict__ wbf, const float* __restrict__ params,
+                    const float* __restrict__ wfwd, const float* __restrict__ params,
                     float* __restrict__ y, int shuffle) {
     extern __shared__ float sm[];
     const int xin = d.cin * d.hin * d.win;
     float* xs = sm;
-    float* ws = sm + xin;  // [ci][tap][co]
-    for (int k = threadIdx.x; k < d.cin * 9 * CO; k += blockDim.x) {
-        const int co = k % CO, t = (k / CO) % 9, ci = k / (9 * CO);
-        ws[k] = bf2f(wbf[d.woff + ((int64_t)co * d.cin + ci) * 9 + t]);
-    }
+    const float* __restrict__ ws = wfwd + d.woff;  // [ci][tap][co]
     const int p = threadIdx.x;
     const int oy = p / d.wout, ox = p % d.wout;
     float bias[CO];
@@ -292,6 +290,16 @@ __global__ void to_bf16_kernel(int64_t np, const float* __restrict__ th, uint16_
     for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < np;
          k += (int64_t)gridDim.x * blockDim.x)
         wbf[k] = f2bf(th[k]);
+}
+
+// wfwd[ci][tap][co] = the BF16 weight W[co][ci][tap] as FP32, for one layer
+__global__ void widen_kernel(ConvDesc d, const uint16_t* __restrict__ wbf,
+                             float* __restrict__ wfwd) {
+    const int nw = d.cout * d.cin * 9;
+    for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < nw; k += gridDim.x * blockDim.x) {
+        const int co = k % d.cout, t = (k / d.cout) % 9, ci = k / (9 * d.cout);
+        wfwd[d.woff + k] = bf2f(wbf[d.woff + ((int64_t)co * d.cin + ci) * 9 + t]);
+    }
 }
 
 __device__ __forceinline__ float feat(double lv, double lm) {
@@ -557,20 +565,27 @@ void lds_attr(K k, size_t bytes) {
                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
 }
 
-size_t fwd_lds(const ConvDesc& d) {
-    return sizeof(float) * ((size_t)d.cin * d.hin * d.win + (size_t)d.cin * 9 * d.cout);
-}
+size_t fwd_lds(const ConvDesc& d) { return sizeof(float) * (size_t)d.cin * d.hin * d.win; }
 
-void launch_fwd(const ConvDesc& d, int n, const float* x, const uint16_t* wbf,
+void launch_fwd(const ConvDesc& d, int n, const float* x, const float* wfwd,
                 const float* params, float* y, int shuffle, hipStream_t st) {
     const size_t lds = fwd_lds(d);
     const int g = grid_n(n, 2048);
     if (d.cout == kNetCh) {
         lds_attr(conv_fwd_kernel<kNetCh>, lds);
-        conv_fwd_kernel<kNetCh><<<g, kT, lds, st>>>(d, n, x, wbf, params, y, shuffle);
+        conv_fwd_kernel<kNetCh><<<g, kT, lds, st>>>(d, n, x, wfwd, params, y, shuffle);
     } else {
         lds_attr(conv_fwd_kernel<4>, lds);
-        conv_fwd_kernel<4><<<g, kT, lds, st>>>(d, n, x, wbf, params, y, shuffle);
+        conv_fwd_kernel<4><<<g, kT, lds, st>>>(d, n, x, wfwd, params, y, shuffle);
+    }
+}
+
+// refresh the forward kernels' FP32 weights from the BF16 copy
+void widen_weights(dd_net* net, hipStream_t st) {
+    const ConvDesc* L = table().L;
+    for (int l = 0; l < kNetLayers; ++l) {
+        const int nw = L[l].cout * L[l].cin * 9;
+        widen_kernel<<<(nw + 255) / 256, 256, 0, st>>>(L[l], net->wbf, net->wfwd);
     }
 }
 
@@ -638,7 +653,7 @@ Status net_forward(dd_net* net, int n, const float* x, float* y, hipStream_t st)
     for (int l = 0; l < dd::kNetLayers; ++l) {
         const bool last = l == dd::kNetLayers - 1;
         float* o = last ? y : net->act + l * per;
-        dd::launch_fwd(L[l], n, in, net->wbf, net->master, o, last ? 1 : 0, st);
+        dd::launch_fwd(L[l], n, in, net->wfwd, net->master, o, last ? 1 : 0, st);
         in = o;
     }
     DD_HIP(hipGetLastError(), s);
@@ -699,6 +714,7 @@ Status net_train(dd_net* net, int n, const float* x, const float* tgt, const flo
     const int64_t np = net_param_count();
     adam_kernel<<<(int)std::min<int64_t>((np + 255) / 256, 1024), 256, 0, st>>>(
         np, net->master, net->adam_m, net->adam_v, net->grad, net->wbf, lr, c1, c2);
+    dd::widen_weights(net, st);
     DD_HIP(hipGetLastError(), s);
     if (loss) {
         std::vector<float> lb(n);
@@ -733,7 +749,8 @@ extern "C" dd_status dd_net_create(const float* params, dd_net** out) {
         hipMalloc(&net->adam_m, np * sizeof(float)) != hipSuccess ||
         hipMalloc(&net->adam_v, np * sizeof(float)) != hipSuccess ||
         hipMalloc(&net->grad, np * sizeof(float)) != hipSuccess ||
-        hipMalloc(&net->wbf, np * sizeof(uint16_t)) != hipSuccess) {
+        hipMalloc(&net->wbf, np * sizeof(uint16_t)) != hipSuccess ||
+        hipMalloc(&net->wfwd, np * sizeof(float)) != hipSuccess) {
         s.code = DD_ENOMEM;
         s.msg = "dd_net_create: device allocation failed";
         return bail(s);
@@ -747,6 +764,7 @@ extern "C" dd_status dd_net_create(const float* params, dd_net** out) {
     }
     dd::to_bf16_kernel<<<(int)std::min<int64_t>((np + 255) / 256, 1024), 256>>>(np, net->master,
                                                                               net->wbf);
+    dd::widen_weights(net, nullptr);
     if (hipDeviceSynchronize() != hipSuccess) {
         s.code = DD_EDEVICE;
         s.msg = "dd_net_create: kernel failed";
@@ -793,7 +811,7 @@ extern "C" void dd_net_free(dd_net* net) {
     if (!net) return;
     (void)hipDeviceSynchronize();
     for (void* p : {(void*)net->master, (void*)net->adam_m, (void*)net->adam_v, (void*)net->grad,
-                    (void*)net->wbf, (void*)net->part, (void*)net->act, (void*)net->ga,
+                    (void*)net->wbf, (void*)net->wfwd, (void*)net->part, (void*)net->act, (void*)net->ga,
                     (void*)net->out, (void*)net->loss_b})
         if (p) (void)hipFree(p);
     delete net;
