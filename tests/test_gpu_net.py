@@ -116,6 +116,12 @@ def test_train_step_matches_torch():
     assert np.allclose(np.abs(step[big]), lr, rtol=1e-3)
     # parameters with zero gradient do not move
     assert np.all(np.abs(step) <= lr * 1.001)
+    # the forward pass after the step uses the updated (BF16-rounded) weights
+    y1 = net.forward(torch.from_numpy(x).cuda()).cpu()
+    with torch.no_grad():
+        ref1 = _ref_forward(torch.from_numpy(p1), torch.from_numpy(x))
+    err = (y1 - ref1).abs().max().item()
+    assert err <= 2e-5 * ref1.abs().max().item() + 1e-6, err
     net.close()
 
 
