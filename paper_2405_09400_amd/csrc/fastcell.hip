@@ -26,9 +26,11 @@
 //     global memory, L2-resident while the cell runs);
 //   * an underflowed kernel-product sum (every input near the output negligible against the
 //     line maximum) is recomputed for that output by an exact log-sum-exp in float64.
-// The batch rule runs `check_every` iterations per launch and reduces the per-cell errors
-// once per launch (last-workgroup ticket, fixed cell order); launches are replayed from a
-// captured HIP graph.
+// The batch rule runs in rounds: one launch per cell class runs K iterations of each of its
+// cells, and the last workgroup of the round (ticket shared by the classes) reduces the
+// per-cell errors in fixed cell order, tests the rule, raises the device stop flag or sets K
+// of the next round from the error's decay.  Rounds are plain launches queued a few at a time
+// between host reads of the stop flag; a round queued after the stop exits at once.
 #include "fastcell.hpp"
 
 #include <algorithm>

@@ -140,3 +140,44 @@ def test_stitched_dual_weak_duality_and_zero_gap():
     dd.alpha["A"][0] = dd.alpha["A"][0] - 1.25
     D1, _, _ = dd.stitched_dual(eps)
     assert abs(D1 - D0) <= 1e-12 * abs(D0)
+
+
+@pytest.mark.parametrize("name,N", [("mix256", 64), ("flow512", 64), ("mix256", 128)])
+def test_sparse_init_aggregates_to_feasible_basic_marginals(name, N):
+    """Right after init from a sparse coupling (Knothe-Rosenblatt or a map coupling), the basic
+    cell Y-marginals carry the masses of the coupling (Sec. 2.3, the state nu_i is the
+    Y-marginal of pi restricted to X_i x Y): sum_y nu_i = m_i and sum_i nu_i = nu."""
+    w = synth.workload(name, N=N)
+    o = oracle.DomDec(w.mu, w.nu, w.s, w.init)
+    mi = np.array([v.sum() for _, v in o.nu_i])
+    assert np.abs(mi - o.m).max() <= 1e-15
+    tot = np.zeros(N * N)
+    for idx, v in o.nu_i:
+        assert np.all(np.diff(idx) > 0) and np.all(v >= 0)
+        np.add.at(tot, idx, v)
+    assert np.abs(tot - o.nu).max() <= 1e-15
+    assert np.abs(tot - o.nu).sum() <= 1e-14
+
+
+@pytest.mark.parametrize("s", [1, 2, 4])
+def test_sparse_init_matches_dense_brute_force(s):
+    """Brute force on a tiny grid: materialise the coupling as a dense (N^2, N^2) matrix and sum
+    its rows over each basic cell's s x s pixel block by explicit loops over (k1, k2)."""
+    N = 8
+    mu, nu = _small(N, s=2, seed=5)
+    x, y, m = synth.kr_coupling(mu, nu)
+    P = np.zeros((N * N, N * N))
+    for a, b, v in zip(x, y, m):
+        P[a, b] += v
+    o = oracle.DomDec(mu, nu, s, (x, y, m))
+    n = N // s
+    for r in range(n):
+        for c in range(n):
+            want = np.zeros(N * N)
+            for k1 in range(r * s, (r + 1) * s):
+                for k2 in range(c * s, (c + 1) * s):
+                    want += P[k1 * N + k2]
+            got = np.zeros(N * N)
+            idx, v = o.nu_i[r * n + c]
+            got[idx] = v
+            assert np.abs(got - want).max() <= 1e-17, (r, c)
