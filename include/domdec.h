@@ -148,7 +148,11 @@ typedef struct {
  *   kappa         eps / h^2.
  *   max_w1/max_w2 upper bounds of W1, W2 over the batch (size the on-chip tiles).
  *   opts          (host) options; init and reserved are ignored here.
- *   cell_iters    int32 [ncells] out, may be NULL: iterations per cell.
+ *   cell_iters    int32 [ncells] out, may be NULL: iterations per cell (Y-updates of
+ *                 the iterate sequence; after a float64 finish both phases, the
+ *                 finish's first Y-update -- the float32 phase's last one repeated in
+ *                 float64 -- counted once).  A fixed count from the same start
+ *                 reproduces the solve.
  *   cell_err      double [ncells] out, may be NULL: final error per cell.
  *   stream        hipStream_t; the call synchronises it before returning.
  *   stats         (host) out, may be NULL.
@@ -319,6 +323,42 @@ typedef struct {
  * those sizes.  Synchronises the context stream.
  */
 dd_status extract_plan(dd_ctx* ctx, dd_plan_view* view);
+
+/* Host view of one partition's composite-cell potentials (two-call protocol). */
+typedef struct {
+    int32_t partition;   /* in: DD_PART_A | DD_PART_B                                   */
+    int32_t n_cells;     /* out: composite cells of the partition                         */
+    int32_t xside;       /* out: X block side 2s                                          */
+    int32_t has_beta;    /* out: 1 if this partition's iteration is the context's last one
+                            (no flow update or restore since), so beta is available       */
+    double eps;          /* out: eps of the partition's last iteration                    */
+    int64_t n_y;         /* out: composite Y-box entries of that iteration (0 without beta) */
+    int32_t* xorig;      /* (host) [n_cells][2] X block origin pixel (k1, k2); B boundary
+                            cells start at -s (their block is padded), or NULL            */
+    double* alpha;       /* (host) [n_cells][xside^2] alpha, row-major over the block, or
+                            NULL; entries on padding pixels (outside the grid) are
+                            meaningless                                                   */
+    int32_t* yorig;      /* (host) [n_cells][2] composite Y-box origin, or NULL           */
+    int32_t* ydims;      /* (host) [n_cells][2] composite Y-box dims (W1, W2), or NULL    */
+    int64_t* ybase;      /* (host) [n_cells+1] offsets into beta, or NULL                 */
+    double* beta;        /* (host) [n_y] beta, row-major per box; NaN where nu_J or nu is
+                            zero, or NULL                                                 */
+} dd_potentials_view;
+
+/*
+ * extract_potentials -- the dual potentials (alpha_J, beta_J) of the composite cells of one
+ * partition (the optional potentials of the output plan; Sec. 2.3 Alg. "DomDecIter" cell
+ * problem, Sec. 2.2 Prop. "Optimal entropic transport couplings"), in energy units with the
+ * paper's reference measure mu_J (x) nu:
+ *     pi_J(x, y) = exp((alpha_J(x) + beta_J(y) - |x - y|^2) / eps) mu(x) nu(y).
+ * alpha is the X potential the partition's last iteration ended with (the warm start of its
+ * next visit); beta that iteration's last Y-update, on the composite boxes of that iteration.
+ * Both are fixed up to (alpha + t, beta - t) per cell.  First call with all pointers NULL to
+ * read the sizes, then with caller buffers.  Synchronises the context stream.
+ * Errors: DD_EINVAL (partition), DD_ESTATE (partition never iterated; or Y data asked for
+ * while has_beta is 0), DD_EDEVICE.
+ */
+dd_status extract_potentials(dd_ctx* ctx, dd_potentials_view* view);
 
 /* Quality measures (App. A.2.2 "Solution quality"). */
 typedef struct {

@@ -24,7 +24,8 @@ _NAMES = {0: "DD_OK", 1: "DD_NOTCONV", -1: "DD_EINVAL", -2: "DD_ENOMEM", -3: "DD
 SYMBOLS = ("sinkhorn_batch", "sinkhorn_batch_f64", "domdec_init", "domdec_iterate", "flow_update",
            "flow_costs", "flow_apply", "dd_mcf_solve", "extract_plan", "domdec_evaluate", "domdec_free",
            "domdec_strerror", "dd_net_param_count", "dd_net_create", "dd_net_params", "dd_net_forward",
-           "dd_net_train_step", "dd_net_free", "dd_net_strerror", "domdec_set_net", "domdec_net_samples", "domdec_save", "domdec_restore")
+           "dd_net_train_step", "dd_net_free", "dd_net_strerror", "domdec_set_net", "domdec_net_samples", "domdec_save", "domdec_restore",
+           "extract_potentials")
 
 
 class DomDecError(RuntimeError):
@@ -77,6 +78,14 @@ class PlanView(ctypes.Structure):
     _fields_ = [("n_cells", ctypes.c_int64), ("n_entries", ctypes.c_int64),
                 ("offsets", ctypes.POINTER(ctypes.c_int32)), ("dims", ctypes.POINTER(ctypes.c_int32)),
                 ("base", ctypes.POINTER(ctypes.c_int64)), ("data", ctypes.POINTER(ctypes.c_double))]
+
+
+class PotentialsView(ctypes.Structure):
+    _fields_ = [("partition", ctypes.c_int32), ("n_cells", ctypes.c_int32), ("xside", ctypes.c_int32),
+                ("has_beta", ctypes.c_int32), ("eps", ctypes.c_double), ("n_y", ctypes.c_int64),
+                ("xorig", ctypes.POINTER(ctypes.c_int32)), ("alpha", ctypes.POINTER(ctypes.c_double)),
+                ("yorig", ctypes.POINTER(ctypes.c_int32)), ("ydims", ctypes.POINTER(ctypes.c_int32)),
+                ("ybase", ctypes.POINTER(ctypes.c_int64)), ("beta", ctypes.POINTER(ctypes.c_double))]
 
 
 class Eval(ctypes.Structure):
@@ -135,6 +144,8 @@ def lib():
     L.dd_mcf_solve.argtypes = [ctypes.c_int32, ctypes.c_int32, i32p, i32p, i64p, i64p, i64p, i64p]
     L.extract_plan.restype = ctypes.c_int
     L.extract_plan.argtypes = [vp, ctypes.POINTER(PlanView)]
+    L.extract_potentials.restype = ctypes.c_int
+    L.extract_potentials.argtypes = [vp, ctypes.POINTER(PotentialsView)]
     L.domdec_evaluate.restype = ctypes.c_int
     L.domdec_evaluate.argtypes = [vp, ctypes.POINTER(Eval)]
     L.domdec_free.restype = None
@@ -365,6 +376,34 @@ class DomDec:
         v.data = data.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
         _check(lib().extract_plan(self._ctx, ctypes.byref(v)), self._ctx)
         return off, dims, base, data[:nE]
+
+    def extract_potentials(self, partition: str, beta: bool = True) -> dict:
+        """Composite-cell potentials of one partition in energy units (extract_potentials):
+        dict with eps, xorig [n,2], alpha [n, xside^2] and, when the partition's iteration is the
+        last one and `beta`, yorig [n,2], ydims [n,2], ybase [n+1], beta (packed boxes)."""
+        v = PotentialsView()
+        v.partition = {"A": DD_PART_A, "B": DD_PART_B}[partition] if isinstance(partition, str) \
+            else int(partition)
+        _check(lib().extract_potentials(self._ctx, ctypes.byref(v)), self._ctx)
+        n, xs, ny = int(v.n_cells), int(v.xside), int(v.n_y)
+        out = {"eps": float(v.eps), "xside": xs, "has_beta": bool(v.has_beta)}
+        xorig = np.zeros((n, 2), np.int32)
+        alpha = np.zeros((n, xs * xs), np.float64)
+        v.xorig = xorig.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+        v.alpha = alpha.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        if beta and v.has_beta:
+            yorig = np.zeros((n, 2), np.int32)
+            ydims = np.zeros((n, 2), np.int32)
+            ybase = np.zeros(n + 1, np.int64)
+            b = np.zeros(max(ny, 1), np.float64)
+            v.yorig = yorig.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+            v.ydims = ydims.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+            v.ybase = ybase.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))
+            v.beta = b.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+            out.update(yorig=yorig, ydims=ydims, ybase=ybase, beta=b[:ny])
+        _check(lib().extract_potentials(self._ctx, ctypes.byref(v)), self._ctx)
+        out.update(xorig=xorig, alpha=alpha)
+        return out
 
     def nu_i_sparse(self):
         """The stored basic-cell Y-marginals as (flat indices, values) lists (host)."""

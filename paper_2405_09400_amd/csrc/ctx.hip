@@ -513,6 +513,110 @@ extern "C" dd_status extract_plan(dd_ctx* c, dd_plan_view* v) {
     return DD_OK;
 }
 
+// Potentials in energy units with the paper's reference measure mu_J (x) nu (Sec. 2.3).  The
+// solver's f, g use reference mu_J (x) nu_J and the local cost C = |i - j + E|^2 / kappa of a
+// box at pixel origin pY, with G = pX - pY - E; the true cost over eps is
+// C + 2<G, i>/kappa - 2<G, j - E>/kappa + |G|^2/kappa, hence
+//   alpha(i) = eps (f(i) + 2<G, i>/kappa),
+//   beta(j)  = eps (g(j) - 2<G, j - E>/kappa + |G|^2/kappa + log nu_J(j) - log nu(j)).
+extern "C" dd_status extract_potentials(dd_ctx* c, dd_potentials_view* v) {
+    if (!c || !v) return fail(c, DD_EINVAL, "extract_potentials: null argument");
+    const int p = v->partition;
+    if (p != DD_PART_A && p != DD_PART_B)
+        return fail(c, DD_EINVAL, "extract_potentials: partition must be DD_PART_A or DD_PART_B");
+    if (!c->visited[p])
+        return fail(c, DD_ESTATE, "extract_potentials: the partition has not been iterated");
+    const hipStream_t hs = c->st;
+    const int nc = c->part[p].ncell, AS = c->AS, A2 = AS * AS;
+    const double kappa = c->kappa_a[p];
+    const double eps = kappa * c->h * c->h;
+    const bool has_beta = c->last_part == p;
+    int64_t ny = 0;
+    if (has_beta && (hipMemcpyAsync(&ny, c->C.base + nc, sizeof ny, hipMemcpyDeviceToHost, hs) !=
+                         hipSuccess ||
+                     hipStreamSynchronize(hs) != hipSuccess))
+        return fail(c, DD_EDEVICE, "extract_potentials: copy failed");
+    v->n_cells = nc;
+    v->xside = AS;
+    v->has_beta = has_beta ? 1 : 0;
+    v->eps = eps;
+    v->n_y = ny;
+    if (!v->xorig && !v->alpha && !v->yorig && !v->ydims && !v->ybase && !v->beta) return DD_OK;
+    std::vector<double> f((size_t)nc * A2);
+    std::vector<int32_t> gst(2 * (size_t)nc);
+    if (hipMemcpyAsync(f.data(), c->d_a[p], f.size() * sizeof(double), hipMemcpyDeviceToHost, hs) !=
+            hipSuccess ||
+        hipMemcpyAsync(gst.data(), c->d_gst[p], gst.size() * 4, hipMemcpyDeviceToHost, hs) !=
+            hipSuccess ||
+        hipStreamSynchronize(hs) != hipSuccess)
+        return fail(c, DD_EDEVICE, "extract_potentials: copy failed");
+    if (v->xorig) std::copy(c->pxorig[p].begin(), c->pxorig[p].end(), v->xorig);
+    if (v->alpha)
+        for (int J = 0; J < nc; ++J)
+            for (int il = 0; il < A2; ++il) {
+                const int i1 = il / AS, i2 = il % AS;
+                const double lin = 2.0 * ((double)gst[2 * J] * i1 + (double)gst[2 * J + 1] * i2);
+                v->alpha[(size_t)J * A2 + il] = eps * (f[(size_t)J * A2 + il] + lin / kappa);
+            }
+    const bool want_y = v->yorig || v->ydims || v->ybase || v->beta;
+    if (!want_y) return DD_OK;
+    if (!has_beta)
+        return fail(c, DD_ESTATE,
+                    "extract_potentials: beta needs the partition's iteration to be the last one");
+    std::vector<int32_t> dims(2 * (size_t)nc), orig(2 * (size_t)nc), shift(2 * (size_t)nc),
+        gofs(2 * (size_t)nc);
+    std::vector<int64_t> base((size_t)nc + 1);
+    bool ok = hipMemcpyAsync(dims.data(), c->C.dims, dims.size() * 4, hipMemcpyDeviceToHost, hs) ==
+                  hipSuccess &&
+              hipMemcpyAsync(orig.data(), c->C.orig, orig.size() * 4, hipMemcpyDeviceToHost, hs) ==
+                  hipSuccess &&
+              hipMemcpyAsync(shift.data(), c->C.shift, shift.size() * 4, hipMemcpyDeviceToHost,
+                             hs) == hipSuccess &&
+              hipMemcpyAsync(gofs.data(), c->C.gofs, gofs.size() * 4, hipMemcpyDeviceToHost, hs) ==
+                  hipSuccess &&
+              hipMemcpyAsync(base.data(), c->C.base, base.size() * 8, hipMemcpyDeviceToHost, hs) ==
+                  hipSuccess;
+    std::vector<double> g, lnuJ, lnu;
+    if (ok && v->beta) {
+        g.resize((size_t)ny);
+        lnuJ.resize((size_t)ny);
+        lnu.resize((size_t)c->N * c->N);
+        ok = (ny == 0 || (hipMemcpyAsync(g.data(), c->d_b, ny * sizeof(double),
+                                         hipMemcpyDeviceToHost, hs) == hipSuccess &&
+                          hipMemcpyAsync(lnuJ.data(), c->d_lognu, ny * sizeof(double),
+                                         hipMemcpyDeviceToHost, hs) == hipSuccess)) &&
+             hipMemcpyAsync(lnu.data(), c->d_lognu_glob, lnu.size() * sizeof(double),
+                            hipMemcpyDeviceToHost, hs) == hipSuccess;
+    }
+    if (!ok || hipStreamSynchronize(hs) != hipSuccess)
+        return fail(c, DD_EDEVICE, "extract_potentials: copy failed");
+    if (v->yorig) std::copy(orig.begin(), orig.end(), v->yorig);
+    if (v->ydims) std::copy(dims.begin(), dims.end(), v->ydims);
+    if (v->ybase) std::copy(base.begin(), base.end(), v->ybase);
+    if (v->beta) {
+        const double nan = std::nan("");
+        for (int J = 0; J < nc; ++J) {
+            const int W1 = dims[2 * J], W2 = dims[2 * J + 1];
+            const double G1 = gofs[2 * J], G2 = gofs[2 * J + 1];
+            const int E1 = shift[2 * J], E2 = shift[2 * J + 1];
+            const double cst = (G1 * G1 + G2 * G2) / kappa;
+            for (int j1 = 0; j1 < W1; ++j1)
+                for (int j2 = 0; j2 < W2; ++j2) {
+                    const int64_t k = base[J] + (int64_t)j1 * W2 + j2;
+                    const int y1 = orig[2 * J] + j1, y2 = orig[2 * J + 1] + j2;
+                    const double ln = lnu[(size_t)y1 * c->N + y2];
+                    if (!(lnuJ[k] > -1e29) || !(ln > -1e29)) {
+                        v->beta[k] = nan;
+                        continue;
+                    }
+                    const double lin = 2.0 * (G1 * (j1 - E1) + G2 * (j2 - E2)) / kappa;
+                    v->beta[k] = eps * (g[k] - lin + cst + lnuJ[k] - ln);
+                }
+        }
+    }
+    return DD_OK;
+}
+
 void dd_eval_cells(dd_ctx* c) {
     const int p = c->last_part;
     EvalArgs e;

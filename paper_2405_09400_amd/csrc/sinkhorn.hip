@@ -925,6 +925,14 @@ __global__ void __launch_bounds__(kThreads)
     }
 }
 
+// After a float64 finish, per-cell iterations count both phases.  The finish starts with a
+// Y-update of the X potential the float32 phase stopped at, which repeats that phase's last
+// Y-update in float64, so the two phases share one iteration.
+__global__ void merge_iters_kernel(int ncells, int32_t* iters, const int32_t* iters64) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c < ncells && iters64[c] > 0) iters[c] += iters64[c] - 1;
+}
+
 }  // namespace
 
 size_t sk_lds_bytes(int xside, int prec) {
@@ -1468,6 +1476,9 @@ Status sk_solve(const SkBatch& p, const dd_sinkhorn_opts& o, hipStream_t caller_
     }
     sk_stats_kernel<<<1, kThreads, 0, st>>>(p.ncells, iters, finish ? w.iters64 : nullptr, errs,
                                             w.cell_mass, o.tol, p.dims, p.xside, w.dtot, w.ctrl);
+    if (finish)
+        merge_iters_kernel<<<(p.ncells + kThreads - 1) / kThreads, kThreads, 0, st>>>(p.ncells, iters,
+                                                                                     w.iters64);
     DD_HIP(hipEventRecord(w.ev1, st), S);
     int hctl[16];
     double htot[8];
