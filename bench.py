@@ -32,6 +32,8 @@ sys.path.insert(0, ROOT)
 
 # LSE terms/s: one fused multiply-add per term at the FP32 vector peak (157.3 TFLOP/s)
 TERM_PEAK = 157.3e12 / 2
+# the same at the FP64 vector peak (78.6 TFLOP/s)
+TERM_PEAK_F64 = 78.6e12 / 2
 HBM_PEAK = 8.0e12
 
 
@@ -51,17 +53,17 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def setup(args):
+def setup(args, workload, prec_name):
     import torch
 
     import paper_2405_09400_amd as dd
     import synth
 
-    w = synth.workload(args.workload, seed=args.seed)
-    prec = dd.DD_PREC_F32 if args.prec == "f32" else dd.DD_PREC_F64
+    w = synth.workload(workload, seed=args.seed)
+    prec = dd.DD_PREC_F32 if prec_name == "f32" else dd.DD_PREC_F64
     t0 = time.perf_counter()
     ctx = dd.DomDec(w.mu, w.nu, w.s, w.init, prec=prec)
-    log(f"[bench] init {args.workload} N={w.N} s={w.s} in {time.perf_counter() - t0:.2f}s")
+    log(f"[bench] init {workload} N={w.N} s={w.s} {prec_name} in {time.perf_counter() - t0:.2f}s")
     rule = dd.DD_STOP_CELL if args.stop_rule == "cell" else dd.DD_STOP_BATCH
     k = 0
     for kappa, its in zip(w.kappas[:-1], w.stage_iters[:-1]):
@@ -85,9 +87,11 @@ def run_steps(ctx, w, n, k0, args, rule, init=None, flows=None):
     out = []
     for i in range(n):
         part = "AB"[(k0 + i) % 2]
+        t0 = time.perf_counter()
         st = ctx.iterate(part, eps, tol=args.tol, stop_rule=rule, max_iter=args.max_iter,
                          check_every=args.check_every,
                          init=dd.DD_INIT_PREV if init is None else init)
+        st["wall_ms"] = (time.perf_counter() - t0) * 1e3  # iterate synchronises the stream
         out.append(st)
         if flow_every and part == "B":
             fs = ctx.flow_update()
@@ -119,7 +123,8 @@ def time_to_tol(ctx, w, k0, args, rule):
     eps = w.kappas[-1] / w.N ** 2
     kinds = [("zero", dd.DD_INIT_ZERO)] + ([("learned_net", dd.DD_INIT_NET)] if net else []) + \
         [("prev_iterate", dd.DD_INIT_PREV)]
-    rec = {name: {"ms": [], "iters": [], "sinkhorn_ms": [], "init_ms": []} for name, _ in kinds}
+    rec = {name: {"ms": [], "iters": [], "f64_finish_iters": [], "sinkhorn_ms": [], "init_ms": []}
+           for name, _ in kinds}
     for r in range(args.replay):
         log(f"[bench] replay state {r}")
         ctx.save()
@@ -132,63 +137,170 @@ def time_to_tol(ctx, w, k0, args, rule):
             d["sinkhorn_ms"].append(round(st["t_sinkhorn_ms"], 3))
             d["init_ms"].append(round(st["t_init_ms"], 3))
             d["ms"].append(round(st["t_sinkhorn_ms"] + st["t_init_ms"], 3))
+            # float32 iterations (the stop of the float32 phase: at 0.85 tol, or handed over
+            # when its error stalls) and the float64 finish that certifies the tolerance
             d["iters"].append(st["sk"]["iters_max"])
-    out = {"tol": args.tol, "states": args.replay, "_steps": args.replay}
+            d["f64_finish_iters"].append(st["sk"]["finish_iters_max"])
+    out = {"tol": args.tol, "states": args.replay, "_steps": args.replay,
+           "time": "start + Sinkhorn on the device clock; sums and medians over the states"}
     for name, _ in kinds:
         out[name] = rec[name]
+        rec[name]["sum_ms"] = round(sum(rec[name]["ms"]), 3)
+        rec[name]["median_ms"] = round(float(np.median(rec[name]["ms"])), 3)
     if not net:
         out["learned_net"] = None
     tot = {name: sum(rec[name]["ms"]) for name, _ in kinds}
+    med = {name: float(np.median(rec[name]["ms"])) for name, _ in kinds}
     out["speedup_prev_vs_zero"] = tot["zero"] / tot["prev_iterate"]
+    out["speedup_prev_vs_zero_median"] = med["zero"] / med["prev_iterate"]
     if net:
         out["speedup_net_vs_zero"] = tot["zero"] / tot["learned_net"]
         out["speedup_net_vs_prev"] = tot["prev_iterate"] / tot["learned_net"]
+        out["speedup_net_vs_zero_median"] = med["zero"] / med["learned_net"]
+        out["speedup_net_vs_prev_median"] = med["prev_iterate"] / med["learned_net"]
         ctx.set_net(None)
         net.close()
     return out
 
 
-def cpu_baseline(args, w):
-    """Oracle dense cell Sinkhorn on a bounded sample: the first composite cells of partition A
-    on the workload's initial coupling at kappa = 1, a fixed number of iterations."""
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def _cell_objective(od, xpix, ysup, plan, eps):
+    """<c, pi> + eps sum pi (log(pi / (mu nu)) - 1) of one composite plan."""
+    d = od.coords[xpix][:, None, :] - od.coords[ysup][None, :, :]
+    c = (d ** 2).sum(axis=2)
+    ref = od.mu[xpix][:, None] * od.nu[ysup][None, :]
+    pos = plan > 0
+    return float((c * plan).sum() + eps * (plan[pos] * (np.log(plan[pos] / ref[pos]) - 1.0)).sum())
+
+
+def cpu_baseline(args, w, ctx, k, rule):
+    """The oracle on the state the GPU is timed on, and the GPU's error against it.
+
+    One more half-iteration of the benchmark's trajectory runs on the GPU (untimed, exactly as
+    the timed ones).  The oracle takes the state just before it (basic-cell Y-marginals and the
+    partition's X potentials, read through the C ABI) and solves a seeded random sample of the
+    same composite cells for the same number of Sinkhorn iterations, with its dense float64
+    cell solver: one warm-up, then the median of `runs` runs on one thread and on all host
+    threads.  The same oracle solve gives the GPU result's error on the sampled cells (new
+    basic-cell Y-marginals, both plan marginals, cell objective; relative, worst cell)."""
     import oracle
 
-    t0 = time.perf_counter()
-    od = oracle.DomDec(w.mu, w.nu, w.s, w.init)
-    log(f"[bench] oracle state built in {time.perf_counter() - t0:.1f}s")
+    import paper_2405_09400_amd as dd
+    part = "AB"[k % 2]
     eps = w.kappas[-1] / w.N ** 2
-    parts = od.parts["A"]
-    iters = 10
-    nthreads = os.cpu_count() or 1
-    done_cells, t_used, bytes_alg = 0, 0.0, 0.0
-    chunk = 64
-    while t_used < args.cpu_seconds:
-        start = done_cells % len(parts)
-        cells = parts[start:start + chunk]
-        xo, yo, X, M, Y, V = [0], [0], [], [], [], []
-        for basic in cells:
+    nu_before = ctx.nu_i_sparse()
+    pre = ctx.extract_potentials(part, beta=False)
+    st = ctx.iterate(part, eps, tol=args.tol, stop_rule=rule, max_iter=args.max_iter,
+                     check_every=args.check_every, init=dd.DD_INIT_PREV)
+    sk = st["sk"]
+    n_its = sk["iters_max"] + max(sk["finish_iters_max"] - 1, 0)
+    nu_after = ctx.nu_i_sparse()
+    post = ctx.extract_potentials(part)
+    t0 = time.perf_counter()
+    cells = oracle.basic_cell_pixels(w.N, w.s)
+    xs = np.concatenate([np.full(len(i), cells[c][0], np.int64) for c, (i, _) in enumerate(nu_before)])
+    od = oracle.DomDec(w.mu, w.nu, w.s, (xs, np.concatenate([i for i, _ in nu_before]),
+                                         np.concatenate([v for _, v in nu_before])))
+    log(f"[bench] oracle state built in {time.perf_counter() - t0:.1f}s")
+    parts = od.parts[part]
+    xside = pre["xside"]
+
+    def alpha0(J, xpix):
+        k1, k2 = np.divmod(xpix, w.N)
+        xo = pre["xorig"][J]
+        return pre["alpha"][J][(k1 - xo[0]) * xside + (k2 - xo[1])]
+
+    def batch(sample):
+        xo, yo, X, M, Y, V, R, A = [0], [0], [], [], [], [], [], []
+        nbytes = 0.0
+        for J in sample:
+            basic = parts[J]
             xpix = np.concatenate([od.cells[i] for i in basic])
             ysup, nuJ = oracle.sparse_sum([od.nu_i[i] for i in basic])
             X.append(od.coords[xpix])
             M.append(od.mu[xpix])
             Y.append(od.coords[ysup])
             V.append(nuJ)
+            R.append(od.nu[ysup])
+            A.append(alpha0(J, xpix))
             xo.append(xo[-1] + len(xpix))
             yo.append(yo[-1] + len(ysup))
-            k1, k2 = ysup // w.N, ysup % w.N
-            W1 = int(k1.max() - k1.min() + 1)
-            W2 = int(k2.max() - k2.min() + 1)
-            bytes_alg += iters * 12.0 * (len(xpix) + W1 * W2)
-        Vc = np.concatenate(V)
+            W1, W2 = post["ydims"][J]
+            nbytes += n_its * 12.0 * (xside * xside + int(W1) * int(W2))
+        arrs = (np.array(xo), np.concatenate(X), np.concatenate(M), np.array(yo), np.concatenate(Y),
+                np.concatenate(V), np.concatenate(R))
+        return arrs, np.concatenate(A), nbytes
+
+    def run(arrs, a0, nthreads):
         t1 = time.perf_counter()
-        oracle.sinkhorn_cells(np.array(xo), np.concatenate(X), np.concatenate(M), np.array(yo),
-                              np.concatenate(Y), Vc, Vc, eps, fixed_iters=iters, nthreads=nthreads)
-        t_used += time.perf_counter() - t1
-        done_cells += len(cells)
-    return {"value": bytes_alg / t_used / 1e9, "unit": "GB/s", "cores": nthreads, "kind": "oracle",
-            "sample": f"{done_cells} cell solves (partition A cells in order, repeated) on the initial "
-                      f"coupling at kappa=1, {iters} dense float64 Sinkhorn iterations each "
-                      f"({t_used:.1f}s of solver time)"}
+        oracle.sinkhorn_cells(*arrs, eps, fixed_iters=n_its, alpha=a0, nthreads=nthreads)
+        return time.perf_counter() - t1
+
+    rng = np.random.default_rng(4096 + args.seed)
+    order = rng.permutation(len(parts))
+    # size the sample so that one single-thread run takes about cpu_seconds / 12
+    n = 4
+    arrs, a0, nbytes = batch(order[:n])
+    t_one = run(arrs, a0, 1)
+    n = int(min(len(parts), max(4, n * (args.cpu_seconds / 12.0) / max(t_one, 1e-3))))
+    sample = sorted(order[:n].tolist())
+    arrs, a0, nbytes = batch(sample)
+    nthreads = os.cpu_count() or 1
+    runs = max(args.cpu_runs, 1)
+    res = {}
+    for name, th in (("single", 1), ("all", nthreads)):
+        run(arrs, a0, th)  # warm-up
+        ts = [run(arrs, a0, th) for _ in range(runs)]
+        res[name] = float(np.median(ts))
+    # the GPU's error on the sampled cells against the oracle's solve of the same problems
+    for J in sample:
+        od.alpha[part][J] = alpha0(J, np.concatenate([od.cells[i] for i in parts[J]]))
+    od.iterate(part, eps, fixed_iters=n_its, cells=sample)
+    worst = {"basic_nu_i": 0.0, "x_marginal": 0.0, "y_marginal": 0.0, "objective": 0.0}
+    for J, cs in zip(sample, od.last[part]):
+        for i in parts[J]:
+            a = np.zeros(w.N * w.N)
+            b = np.zeros(w.N * w.N)
+            a[nu_after[i][0]] = nu_after[i][1]
+            b[od.nu_i[i][0]] = od.nu_i[i][1]
+            worst["basic_nu_i"] = max(worst["basic_nu_i"], float(np.abs(a - b).sum() / od.m[i]))
+        P_or = oracle.cell_plan(od.coords[cs.xpix], od.mu[cs.xpix], cs.alpha, od.coords[cs.ysup],
+                                od.nu[cs.ysup], cs.beta, eps)
+        k1, k2 = np.divmod(cs.xpix, w.N)
+        xo = pre["xorig"][J]
+        a_g = post["alpha"][J][(k1 - xo[0]) * xside + (k2 - xo[1])]
+        y1, y2 = np.divmod(cs.ysup, w.N)
+        W2 = post["ydims"][J][1]
+        b_g = post["beta"][post["ybase"][J] + (y1 - post["yorig"][J][0]) * W2 +
+                           (y2 - post["yorig"][J][1])]
+        P_g = oracle.cell_plan(od.coords[cs.xpix], od.mu[cs.xpix], a_g, od.coords[cs.ysup],
+                               od.nu[cs.ysup], b_g, eps)
+        m = P_or.sum()
+        worst["x_marginal"] = max(worst["x_marginal"], float(np.abs(P_g.sum(1) - P_or.sum(1)).sum() / m))
+        worst["y_marginal"] = max(worst["y_marginal"], float(np.abs(P_g.sum(0) - P_or.sum(0)).sum() / m))
+        e_or = _cell_objective(od, cs.xpix, cs.ysup, P_or, eps)
+        e_g = _cell_objective(od, cs.xpix, cs.ysup, P_g, eps)
+        worst["objective"] = max(worst["objective"], abs(e_g - e_or) / abs(e_or))
+    return {"value": nbytes / res["all"] / 1e9, "unit": "GB/s", "cores": nthreads, "kind": "oracle",
+            "single_thread_value": nbytes / res["single"] / 1e9,
+            "cpu_model": cpu_model(),
+            "statistic": f"median of {runs} runs after one warm-up, single thread and {nthreads} threads",
+            "sample": f"{len(sample)} random composite cells of the half-iteration after the timed "
+                      f"ones (partition {part}, kappa=1), solved from the GPU's start of that "
+                      f"half-iteration for its {n_its} Sinkhorn iterations by the dense float64 "
+                      f"oracle ({res['single']:.2f} s single thread, {res['all']:.2f} s all "
+                      f"threads per run)",
+            "gpu_vs_oracle": {"cells": len(sample), "iterations": n_its,
+                              "worst_relative": worst}}
 
 
 # ---- HBM traffic of the dominant kernel (rocprofv3 counters) ------------------------------
@@ -359,9 +471,13 @@ def main():
                     help="batch rule: iterations between stop tests (register-blocked path)")
     ap.add_argument("--prec", choices=["f32", "f64"], default="f32")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--cpu-runs", type=int, default=5)
+    ap.add_argument("--no-extra", action="store_true",
+                    help="skip the float64 and 1024^2 records of the mix512 line")
+    ap.add_argument("--extra-steps", type=int, default=4)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-compare", action="store_true")
-    ap.add_argument("--replay", type=int, default=4)
+    ap.add_argument("--replay", type=int, default=8)
     ap.add_argument("--net-weights", default=os.path.join(ROOT, "paper_2405_09400_amd", "weights",
                                                           "warmstart_s4_k1.npz"))
     ap.add_argument("--copy-calibration", action="store_true",
@@ -399,18 +515,45 @@ def main():
         return
     dd.lib()
 
-    w, ctx, rule, k = setup(args)
-    log(f"[bench] warmup {args.warmup} steps")
-    run_steps(ctx, w, args.warmup, k, args, rule)
-    k += args.warmup
+    line = measure(args, args.workload, args.prec, args.steps, args.warmup,
+                   replay=0 if args.no_compare else args.replay, cpu=not args.no_cpu_baseline)
+    if not args.no_extra and args.workload == "mix512":
+        # the same step in the paper's arithmetic (float64 throughout), and the 1024^2 workload
+        sub = measure(args, "mix512", "f64", args.extra_steps, 1, replay=0, cpu=False)
+        line["f64"] = {key: sub[key] for key in ("value", "unit", "ms_per_step", "ms_per_step_median",
+                                                 "dtype", "roofline")}
+        line["f64"]["detail"] = {key: sub["detail"][key] for key in
+                                 ("sinkhorn_iters", "sinkhorn_ms_per_step", "x_marginal_l1",
+                                  "y_marginal_l1", "primal", "dual", "pd_gap")}
+        sub = measure(args, "mix1024", args.prec, args.extra_steps, 1, replay=0, cpu=False)
+        line["mix1024"] = {key: sub[key] for key in ("value", "unit", "ms_per_step",
+                                                     "ms_per_step_median", "dtype", "roofline")}
+        line["mix1024"]["config"] = sub["config"]
+        line["mix1024"]["value_frac_of_hbm_peak"] = sub["value"] * 1e9 / HBM_PEAK
+        line["mix1024"]["detail"] = {key: sub["detail"][key] for key in
+                                     ("sinkhorn_iters", "sinkhorn_ms_per_step", "max_box",
+                                      "x_marginal_l1", "y_marginal_l1", "primal", "pd_gap")}
+    print(json.dumps(line), flush=True)
+
+
+def measure(args, workload, prec, steps, warmup, replay=0, cpu=False):
+    """Set-up (untimed), warm-up, `steps` timed half-iterations, then optionally the replay
+    protocol and the oracle leg; returns the JSON record."""
+    import torch
+
+    import paper_2405_09400_amd as dd
+    w, ctx, rule, k = setup(args, workload, prec)
+    log(f"[bench] warmup {warmup} steps")
+    run_steps(ctx, w, warmup, k, args, rule)
+    k += warmup
     torch.cuda.synchronize()
-    log(f"[bench] timing {args.steps} steps")
+    log(f"[bench] timing {steps} steps ({workload}, {prec})")
     t0 = time.perf_counter()
     flows = []
-    stats = run_steps(ctx, w, args.steps, k, args, rule, flows=flows)
+    stats = run_steps(ctx, w, steps, k, args, rule, flows=flows)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    k += args.steps
+    k += steps
     if flows and "AB"[(k - 1) % 2] == "B":
         # the plan after a flow update has no composite potentials yet: evaluate after one
         # more (untimed) half-iteration
@@ -424,6 +567,7 @@ def main():
     sk_iters = [s["sk"]["iters_max"] for s in stats]
     launches = sum((s["sk"]["iters_max"] + 1) if rule == dd.DD_STOP_BATCH else 1 for s in stats)
     achieved = terms / (sk_ms * 1e-3)
+    peak = TERM_PEAK if prec == "f32" else TERM_PEAK_F64
     # the dominant kernel: the register-blocked class with the most device time (HIP events on
     # the stream it is launched on, summed over the launches of the timed steps that iterated)
     roof_kernel, k_launch, k_ms, k_terms = "sinkhorn (all kernels of the solve)", launches, sk_ms, terms
@@ -439,52 +583,63 @@ def main():
             k_ms = ms_c
             k_terms = sum(s["sk"]["kernel_terms"][c] for s in stats)
     k_achieved = k_terms / (k_ms * 1e-3)
-    traffic = traffic_bytes(roof_kernel) if roof_kernel.startswith("fast_kernel") else None
+    traffic = traffic_bytes(roof_kernel) if (roof_kernel.startswith("fast_kernel") and
+                                             workload == "mix512") else None
+    step_ms = [s["wall_ms"] for s in stats]
     log(f"[bench] steps: sinkhorn iters {sk_iters}, sinkhorn {sk_ms / len(stats):.3f} ms/step, "
         f"wall {wall * 1e3 / len(stats):.3f} ms/step")
 
     compare = None
-    if not args.no_compare:
-        compare = time_to_tol(ctx, w, k, args, rule)
+    if replay:
+        a = argparse.Namespace(**vars(args))
+        a.replay = replay
+        compare = time_to_tol(ctx, w, k, a, rule)
         k += compare.pop("_steps")
 
-    cpu = None
-    if not args.no_cpu_baseline:
-        cpu = cpu_baseline(args, w)
+    cpu_rec = None
+    if cpu:
+        cpu_rec = cpu_baseline(args, w, ctx, k, rule)
+        k += 1
 
+    traffic_gb_s = (traffic / (k_ms / max(k_launch, 1) * 1e-3) / 1e9) if traffic is not None else None
     out = {
         "metric": "cell-Sinkhorn LSE GB/s + time-to-marginal-err 1e-5 at 512^2, warm-start vs plain",
         "value": alg_bytes / wall / 1e9,
         "unit": "GB/s",
+        "value_kind": "algorithmic bytes (12 (|X_J| + W1 W2) per cell-iteration) / wall time of "
+                      "the timed steps",
         "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": wall * 1e3 / args.steps,
+        "steps": steps,
+        "warmup": warmup,
+        "ms_per_step": wall * 1e3 / steps,
+        "ms_per_step_median": float(np.median(step_ms)),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32" if args.prec == "f32" else "f64",
+        "dtype": prec,
         "data": "synthetic",
         "config": {
-            "workload": WORKLOAD_TEXT.get(args.workload, args.workload).format(N=w.N, s=w.s),
+            "workload": WORKLOAD_TEXT.get(workload, workload).format(N=w.N, s=w.s),
             "tol": args.tol, "stop_rule": args.stop_rule, "check_every": args.check_every,
             "seed": args.seed,
             "cells_per_step": stats[0]["sk"]["ncells"],
         },
         "roofline": {
             "bound": "alu", "kernel": roof_kernel,
-            "achieved": k_achieved / 1e12, "peak": TERM_PEAK / 1e12, "unit": "Tterm/s",
-            "frac": k_achieved / TERM_PEAK, "traffic": traffic,
+            "achieved": k_achieved / 1e12, "peak": peak / 1e12, "unit": "Tterm/s",
+            "frac": k_achieved / peak, "traffic": traffic,
             "traffic_unit": "HBM bytes per launch",
-            "traffic_gb_s": (traffic / (k_ms / max(k_launch, 1) * 1e-3) / 1e9
-                             if traffic is not None else None),
+            "traffic_gb_s": traffic_gb_s,
+            "traffic_frac_of_hbm_peak": traffic_gb_s * 1e9 / HBM_PEAK if traffic_gb_s else None,
             "launches": k_launch, "kernel_ms_per_launch": k_ms / max(k_launch, 1),
             "terms_per_launch": k_terms / max(k_launch, 1),
             "all_sinkhorn_kernels_tterm_s": achieved / 1e12,
         },
-        "cpu_baseline": cpu,
+        "cpu_baseline": cpu_rec,
+        "error_vs_oracle": cpu_rec["gpu_vs_oracle"] if cpu_rec else None,
         "time_to_tol": compare,
         "detail": {
+            "step_ms": [round(t, 3) for t in step_ms],
             "sinkhorn_iters": sk_iters,
             "cell_split": [{"n_big": s["sk"]["n_big"], "n_giant": s["sk"]["n_giant"],
                             "lds_kb": s["sk"]["lds_kb"],
@@ -516,8 +671,8 @@ def main():
             "assemble_ms": sum(f["t_assemble_ms"] for f in flows) / len(flows),
             "value": [f["value"] for f in flows], "moved_mass": [f["moved_mass"] for f in flows],
         }
-    print(json.dumps(out), flush=True)
     ctx.close()
+    return out
 
 
 if __name__ == "__main__":

@@ -117,3 +117,15 @@ def objective(cells, c, P):
     L[pos] = np.log(P[pos])
     ref = np.log(mu)[:, None] + np.log(nuJ)[None, :]
     return float((P * (C + L - ref))[pos].sum() - P.sum())
+
+
+def subset(cells, idx):
+    """The cells `idx` of a batch as a batch of their own (Y boxes repacked)."""
+    idx = [int(c) for c in idx]
+    dims = cells["dims"][idx]
+    sizes = dims[:, 0].astype(np.int64) * dims[:, 1]
+    base = np.concatenate([[0], np.cumsum(sizes)[:-1]]).astype(np.int64)
+    lognu = np.concatenate([cells["lognu"][cells["base"][c]:cells["base"][c] + sizes[k]]
+                            for k, c in enumerate(idx)]) if idx else np.zeros(0)
+    return dict(dims=dims, base=base, shift=cells["shift"][idx], logmu=cells["logmu"][idx],
+                lognu=lognu, xside=cells["xside"], kappa=cells["kappa"])

@@ -78,6 +78,12 @@ def test_eps_schedule_and_warm_start_follow_oracle():
 
 @pytest.mark.parametrize("rule", [0, 1])
 def test_f32_tolerance_solve_matches_oracle(rule):
+    """Float32 solves to tol 1e-5 along an eps schedule.  Batch rule: the oracle runs each
+    half-iteration for the GPU's own iteration count (both phases of the float32 solve), so the
+    two trajectories differ by float32 rounding only: objective within 1e-6 relative, marginals
+    within 1e-5.  Per-cell rule: each side stops on its own test, so cells may stop an iteration
+    apart (their X-marginals then differ by up to 2 tol and E by up to 2 tol range(alpha) to
+    first order); both meet the tolerance."""
     import paper_2405_09400_amd as dd
     _need_gpu()
     w, g, o = _pair("mix256", N=64, prec=dd.DD_PREC_F32)
@@ -88,25 +94,42 @@ def test_f32_tolerance_solve_matches_oracle(rule):
         for k in range(2):
             part = "AB"[k % 2]
             st = g.iterate(part, eps, tol=tol, stop_rule=rule, max_iter=5000)
-            assert st["sk"]["converged"] == 1
-            o.iterate(part, eps, tol=tol, rule=rule, max_iter=5000)
+            sk = st["sk"]
+            assert sk["converged"] == 1
+            if rule == 0:
+                assert sk["iters_min"] == sk["iters_max"]
+                n = sk["iters_max"] + max(sk["finish_iters_max"] - 1, 0)
+                o.iterate(part, eps, fixed_iters=n)
+            else:
+                o.iterate(part, eps, tol=tol, rule=rule, max_iter=5000)
     ev = g.evaluate()
     Eo = o.primal(eps)
-    # Two solves that both meet the tolerance may stop one Sinkhorn iteration apart; their
-    # X-marginals then differ by up to 2 tol (L1) and E by up to eps * 2 tol * range(alpha/eps)
-    # (first order; the Y-marginals are exact).  Beyond that the bar is 1e-6 relative.
-    rng_alpha = max(float(cs.alpha.max() - cs.alpha.min()) for cs in o.last[o.last_which])
-    allow = 2.0 * tol * rng_alpha
-    assert abs(ev["primal"] - Eo) <= 1e-6 * abs(Eo) + allow, (ev["primal"], Eo, allow)
+    print(f"rule {rule}: primal {ev['primal']:.10e} vs {Eo:.10e}, X-marginal errors "
+          f"{ev['x_marginal_l1']:.3e} vs {o.x_marginal_error():.3e}", flush=True)
+    if rule == 0:
+        assert abs(ev["primal"] - Eo) <= 1e-6 * abs(Eo), (ev["primal"], Eo)
+    else:
+        rng_alpha = max(float(cs.alpha.max() - cs.alpha.min()) for cs in o.last[o.last_which])
+        allow = 2.0 * tol * rng_alpha
+        assert abs(ev["primal"] - Eo) <= 1e-6 * abs(Eo) + allow, (ev["primal"], Eo, allow)
     assert ev["x_marginal_l1"] <= tol * (1.0 + 1e-9)
+    # X-marginal errors of the two runs (each about tol): within 1e-5 of the total mass (1) at
+    # equal counts; within 2 tol when each side stops on its own
+    assert abs(ev["x_marginal_l1"] - o.x_marginal_error()) <= (1e-5 if rule == 0 else 2.0 * tol)
     assert ev["y_marginal_l1"] <= 1e-9
     # balancing is exact; truncation then drops entries below 1e-15, up to ~1e4 per basic
     # cell at this size
     assert ev["basic_mass_err"] <= 1e-11
     G = _dense(g.nu_i_sparse(), w.N)
     O = _dense(o.nu_i, w.N)
-    # the basic-cell marginals of the two runs agree to O(tol) in L1
-    assert np.abs(G - O).sum() <= 4 * tol
+    d = np.abs(G - O).sum(axis=1) / np.array(o.m)
+    print(f"rule {rule}: primal rel diff {abs(ev['primal'] - Eo) / abs(Eo):.2e}, "
+          f"worst basic nu_i rel L1 {d.max():.2e}", flush=True)
+    # the basic-cell marginals: float32 rounding at equal counts; O(tol) in L1 with own stops
+    if rule == 0:
+        assert d.max() <= 1e-5
+    else:
+        assert np.abs(G - O).sum() <= 4 * tol
     g.close()
 
 

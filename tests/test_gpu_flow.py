@@ -106,3 +106,88 @@ def test_flow_requires_a_b_iteration():
     with pytest.raises(dd.DomDecError):
         g.flow_update()
     g.close()
+
+
+def test_f32_flow_update_matches_oracle_on_the_gpu_state():
+    """The flow workload's configuration at reduced size (512 -> 64, s = 2, map start, kappa = 1):
+    float32 cell solves to tol 1e-5 with float64 mass bookkeeping, then a flow update.  The
+    oracle replays the flow update from the GPU's own state (basic-cell Y-marginals and the B
+    potentials, read through extract_plan and extract_potentials), so float32 rounding of the
+    preceding solves drops out: edge costs match brute force, the optimal values agree, the
+    oracle's flow applied on both sides gives the same marginals, and the GPU's own update keeps
+    every basic cell's mass (sum_y nu_hat_j = m_j) and the Y-marginal."""
+    import paper_2405_09400_amd as dd
+    _need_gpu()
+    w = synth.workload("flow512", N=64)
+    print("flow f32 flow512 N=64 s=2", flush=True)
+    g = dd.DomDec(w.mu, w.nu, w.s, w.init, prec=dd.DD_PREC_F32)
+    eps = w.kappas[-1] / w.N ** 2
+    st = g.iterate("A", eps, tol=1e-5, stop_rule=dd.DD_STOP_BATCH, max_iter=20000)
+    assert st["sk"]["converged"] == 1
+    nu_pre = g.nu_i_sparse()
+    st = g.iterate("B", eps, tol=1e-5, stop_rule=dd.DD_STOP_BATCH, max_iter=20000)
+    assert st["sk"]["converged"] == 1
+    nu_post = g.nu_i_sparse()
+    pot = g.extract_potentials("B")
+    ev0 = g.evaluate()
+    cg = g.flow_costs()
+
+    # the oracle on the same state: nu_i after B, and B's composite solves from its potentials
+    cells = oracle.basic_cell_pixels(w.N, w.s)
+    xs = np.concatenate([np.full(len(i), cells[k][0], np.int64) for k, (i, _) in enumerate(nu_post)])
+    o = oracle.DomDec(w.mu, w.nu, w.s, (xs, np.concatenate([i for i, _ in nu_post]),
+                                        np.concatenate([v for _, v in nu_post])))
+    solves = []
+    for J, basic in enumerate(o.parts["B"]):
+        xpix = np.concatenate([o.cells[i] for i in basic])
+        ysup, nuJ = oracle.sparse_sum([nu_pre[i] for i in basic])
+        keep = nuJ > 0
+        ysup, nuJ = ysup[keep], nuJ[keep]
+        k1, k2 = np.divmod(xpix, w.N)
+        xo = pot["xorig"][J]
+        alpha = pot["alpha"][J][(k1 - xo[0]) * pot["xside"] + (k2 - xo[1])]
+        y1, y2 = np.divmod(ysup, w.N)
+        W2 = pot["ydims"][J][1]
+        beta = pot["beta"][pot["ybase"][J] + (y1 - pot["yorig"][J][0]) * W2 + (y2 - pot["yorig"][J][1])]
+        assert np.all(np.isfinite(beta))
+        solves.append(oracle.CellSolve(basic, xpix, [len(o.cells[i]) for i in basic], ysup, nuJ,
+                                       alpha, beta))
+    o.last["B"] = solves
+    o.last_eps["B"] = eps
+    o.last_which = "B"
+    res = o.flow_update(truncate=True)
+    co = res["cbar"]
+    assert np.max(np.abs(cg - co)) <= 1e-11 * np.max(np.abs(co)), np.max(np.abs(cg - co))
+    # the oracle's flow keeps the masses: sum_j w_ij = m_i (to rounding), and sum_i w_ij = m_j
+    # up to the integer supplies b_i = round(m_i 2^40): w_ij = flow_ij m_i / b_i differs from
+    # flow_ij 2^-40 by at most flow_ij 2^-40 / b_i, so with flow_ij <= b_i the in-flow of a
+    # cell misses m_j by at most 2^-40 per in-arc (5 arcs: 4.5e-12)
+    tail, head = oracle.neighbourhood(w.N // w.s)
+    assert np.abs(np.bincount(tail, res["w"], len(o.m)) - o.m).max() <= 1e-15
+    assert np.abs(np.bincount(head, res["w"], len(o.m)) - o.m).max() <= 5 * 2.0 ** -40
+    # the same flow on the GPU state gives the oracle's new marginals
+    g.save()
+    g.flow_apply(res["w"])
+    G = _dense(g.nu_i_sparse(), w.N)
+    O = _dense(o.nu_i, w.N)
+    assert np.abs(G - O).sum() <= 1e-13
+    # the GPU's own flow update: same optimal value, masses and Y-marginal kept
+    # (a fresh context replays the same float32 solves: a restored state needs a new iteration
+    # before a flow update)
+    g2 = dd.DomDec(w.mu, w.nu, w.s, w.init, prec=dd.DD_PREC_F32)
+    g2.iterate("A", eps, tol=1e-5, stop_rule=dd.DD_STOP_BATCH, max_iter=20000)
+    g2.iterate("B", eps, tol=1e-5, stop_rule=dd.DD_STOP_BATCH, max_iter=20000)
+    assert np.max(np.abs(g2.flow_costs() - co)) <= 1e-11 * np.max(np.abs(co))
+    fs = g2.flow_update()
+    assert abs(fs["value"] - res["value"]) <= 1e-9 * abs(res["value"]) + 1e-15
+    ev = g2.evaluate()
+    assert ev["basic_mass_err"] <= 5 * 2.0 ** -40 + 1e-15
+    assert ev["y_marginal_l1"] <= ev0["y_marginal_l1"] + 1e-13
+    # and the cycle goes on: A, B after the flow, both converged, masses kept
+    for part in "AB":
+        st = g2.iterate(part, eps, tol=1e-5, stop_rule=dd.DD_STOP_BATCH, max_iter=20000)
+        assert st["sk"]["converged"] == 1
+    ev = g2.evaluate()
+    assert ev["basic_mass_err"] <= 1e-11 and ev["x_marginal_l1"] <= 1e-5 * (1 + 1e-9)
+    g.close()
+    g2.close()

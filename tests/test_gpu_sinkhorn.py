@@ -8,7 +8,7 @@ relative (the tolerance the method's float32 path is held to).  Y-marginals are 
 import numpy as np
 import pytest
 
-from cellcases import gpu_plan, objective, oracle_solve, random_cells
+from cellcases import gpu_plan, objective, oracle_solve, random_cells, subset
 
 pytestmark = pytest.mark.gpu
 
@@ -172,35 +172,47 @@ def test_register_blocked_path_far_start(its):
 @pytest.mark.parametrize("dtype", ["f32", "f64"])
 @pytest.mark.parametrize("rule", [0, 1])
 def test_tolerance_solve_matches_oracle(dtype, rule):
+    """A solve to tol 1e-5: the tolerance holds in float64 (the float32 solve ends with a float64
+    finish), and the plans equal the oracle's after the same number of iterations from the same
+    start, cell by cell (cell_iters reports each cell's count, both phases of a float32 solve
+    together): marginals within 1e-5 and the cell objective within 1e-6 relative in float32,
+    rounding only in float64."""
     tdt = torch.float32 if dtype == "f32" else torch.float64
     rng = np.random.default_rng(300 + rule)
     cells = random_cells(rng, 61, 8, 6, 36, 1.0)
     tol = 1e-5
     a, b, it, er, st, status = _run(cells, tdt, tol=tol, stop_rule=rule, max_iter=20000, check_every=4)
     assert status == 0 and st["converged"] == 1
-    plans, oit, oerr, onit = oracle_solve(cells, tol=tol, rule=rule, max_iter=20000)
-    if rule == 0 and dtype == "f64":
-        assert abs(int(it.max()) - int(onit)) <= 1
+    if rule == 0:
+        assert it.min() == it.max()
     tot_err, tot_mass = 0.0, 0.0
-    for c in range(len(plans)):
-        P = gpu_plan(cells, c, a, b)
-        O = plans[c]
-        xi_mu = np.exp(cells["logmu"][c][cells["logmu"][c] > -1e29])
-        e = np.abs(P.sum(1) - xi_mu).sum()
-        tot_err += e
-        tot_mass += xi_mu.sum()
-        # the float32 solve ends with a float64 finish: tolerance and Y-marginal hold in float64
-        if rule == 1:
-            assert e <= tol * xi_mu.sum() * (1.0 + 1e-9), (c, e)
-        assert np.abs(P.sum(0) - O.sum(0)).sum() <= 1e-13 * O.sum(), \
-            (c, np.abs(P.sum(0) - O.sum(0)).sum() / O.sum())
-        # both plans meet the tolerance but may stop an iteration apart: their X-marginals differ
-        # by up to 2 tol m (L1), which moves E/eps by up to 2 tol m range(f) to first order
-        xi = cells["logmu"][c] > -1e29
-        rng_f = float(a[c][xi].max() - a[c][xi].min())
-        eo, eg = objective(cells, c, O), objective(cells, c, P)
-        assert abs(eg - eo) <= 1e-6 * abs(eo) + 2 * tol * O.sum() * rng_f, (c, eg, eo)
+    worst = {"x": 0.0, "y": 0.0, "plan": 0.0, "obj": 0.0}
+    for n in sorted(set(it.tolist())):
+        idx = np.nonzero(it == n)[0]
+        sub = subset(cells, idx)
+        plans, oit, _, _ = oracle_solve(sub, fixed_iters=int(n))
+        assert np.all(oit == n)
+        for k, c in enumerate(idx):
+            P = gpu_plan(cells, c, a, b)
+            O = plans[k]
+            m = O.sum()
+            xi_mu = np.exp(cells["logmu"][c][cells["logmu"][c] > -1e29])
+            e = np.abs(P.sum(1) - xi_mu).sum()
+            tot_err += e
+            tot_mass += xi_mu.sum()
+            if rule == 1:
+                assert e <= tol * xi_mu.sum() * (1.0 + 1e-9), (c, e)
+            worst["x"] = max(worst["x"], np.abs(P.sum(1) - O.sum(1)).sum() / m)
+            worst["y"] = max(worst["y"], np.abs(P.sum(0) - O.sum(0)).sum() / m)
+            worst["plan"] = max(worst["plan"], np.abs(P - O).sum() / m)
+            eo, eg = objective(cells, c, O), objective(cells, c, P)
+            worst["obj"] = max(worst["obj"], abs(eg - eo) / abs(eo))
+    print(f"{dtype} rule {rule}: iterations {sorted(set(it.tolist()))[:6]}..., worst {worst}", flush=True)
     assert tot_err <= tol * tot_mass * (1.0 + 1e-9)
+    if dtype == "f32":
+        assert worst["x"] <= 1e-5 and worst["y"] <= 1e-5 and worst["obj"] <= 1e-6, worst
+    else:
+        assert max(worst.values()) <= 1e-11, worst
 
 
 def test_empty_batch_and_tiny_boxes():
