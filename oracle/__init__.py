@@ -246,19 +246,8 @@ class DomDec:
     TRUNC = 1e-15
 
     def __init__(self, mu: np.ndarray, nu: np.ndarray, s: int, init=None, trunc: float = 1e-15):
-        N = mu.shape[0]
-        assert mu.shape == (N, N) and nu.shape == (N, N) and N % (2 * s) == 0
-        self.N, self.s, self.n = N, s, N // s
-        self.h = 1.0 / N
-        self.mu = mu.reshape(-1).astype(np.float64)
-        self.nu = nu.reshape(-1).astype(np.float64)
-        self.coords = pixel_coords(N)
-        self.cells = basic_cell_pixels(N, s)
-        self.m = np.array([self.mu[p].sum() for p in self.cells])
-        if np.any(self.m <= 0):
-            raise ValueError("every basic cell needs positive mass")
-        self.trunc = trunc
-        self.nu_i: List[Tuple[np.ndarray, np.ndarray]] = []
+        self._setup(mu, nu, s, trunc)
+        N = self.N
         if init is None:
             sup = np.nonzero(self.nu > 0)[0].astype(np.int64)
             for mi in self.m:
@@ -278,6 +267,22 @@ class DomDec:
             starts = np.searchsorted(cid, np.arange(len(self.cells) + 1))
             for i in range(len(self.cells)):
                 self.nu_i.append((yy[starts[i]:starts[i + 1]].copy(), acc[starts[i]:starts[i + 1]].copy()))
+
+    def _setup(self, mu: np.ndarray, nu: np.ndarray, s: int, trunc: float) -> None:
+        """Grid, basic cells and their masses, partitions; no coupling yet."""
+        N = mu.shape[0]
+        assert mu.shape == (N, N) and nu.shape == (N, N) and N % (2 * s) == 0
+        self.N, self.s, self.n = N, s, N // s
+        self.h = 1.0 / N
+        self.mu = mu.reshape(-1).astype(np.float64)
+        self.nu = nu.reshape(-1).astype(np.float64)
+        self.coords = pixel_coords(N)
+        self.cells = basic_cell_pixels(N, s)
+        self.m = np.array([self.mu[p].sum() for p in self.cells])
+        if np.any(self.m <= 0):
+            raise ValueError("every basic cell needs positive mass")
+        self.trunc = trunc
+        self.nu_i: List[Tuple[np.ndarray, np.ndarray]] = []
         self.parts = {w: composite_partition(self.n, w) for w in ("A", "B")}
         self.alpha: Dict[str, List[Optional[np.ndarray]]] = {
             w: [None] * len(self.parts[w]) for w in ("A", "B")}
@@ -444,6 +449,22 @@ class DomDec:
             beta(y) = -eps log sum_x mu(x) exp((alpha(x) - c(x, y)) / eps),
         so that D(alpha, beta) = <alpha, mu> + <beta, nu> (dual_value's last term vanishes).
         Returns (D, alpha^dagger, beta^dagger); beta is nan off supp nu."""
+        alpha = self.stitched_alpha()
+        sup = self.nu > 0
+        N2 = self.N * self.N
+        beta = np.full(N2, np.nan)
+        C = self.coords
+        for y in np.nonzero(sup)[0]:
+            z = (alpha - ((C - C[y]) ** 2).sum(axis=1)) / eps
+            pos = self.mu > 0
+            zm = z[pos].max()
+            beta[y] = -eps * (zm + np.log((self.mu[pos] * np.exp(z[pos] - zm)).sum()))
+        D = float((alpha * self.mu).sum() + (beta[sup] * self.nu[sup]).sum())
+        return D, alpha, beta
+
+    def stitched_alpha(self) -> np.ndarray:
+        """alpha^dagger of stitched_dual: the A cells' potentials (energy units) with the offsets
+        of the breadth-first walk over the A/B overlap graph, on every pixel."""
         if any(a is None for a in self.alpha["A"]) or any(a is None for a in self.alpha["B"]):
             raise ValueError("stitched_dual needs both partitions visited")
         N2 = self.N * self.N
@@ -482,16 +503,61 @@ class DomDec:
         for J, basic in enumerate(self.parts["A"]):
             for i in basic:
                 alpha[self.cells[i]] -= sA[J]
-        sup = self.nu > 0
-        beta = np.full(N2, np.nan)
-        C = self.coords
-        for y in np.nonzero(sup)[0]:
-            z = (alpha - ((C - C[y]) ** 2).sum(axis=1)) / eps
-            pos = self.mu > 0
-            zm = z[pos].max()
-            beta[y] = -eps * (zm + np.log((self.mu[pos] * np.exp(z[pos] - zm)).sum()))
-        D = float((alpha * self.mu).sum() + (beta[sup] * self.nu[sup]).sum())
-        return D, alpha, beta
+        return alpha
+
+    # -- multiscale ---------------------------------------------------------------
+    def refine(self, mu_f: np.ndarray, nu_f: np.ndarray) -> "DomDec":
+        """The coarse-to-fine step of multiscale domain decomposition (App. A.2.1 "Multi-scale and
+        eps-scaling", Sec. 5.3): the state of the next layer, on the 2N x 2N grid whose 2 x 2
+        pixel sums are this layer's mu and nu, with the same basic-cell side s.  The paper defers
+        the step to earlier work; the reading taken here:
+          * coupling: a fine basic cell i' is one of the 2 x 2 children of a coarse basic cell i,
+            and a fine pixel y' one of the 2 x 2 children of a coarse pixel y = P(y'); the coarse
+            mass nu_i(y) is split among the X children in proportion to their mu mass and among
+            the Y children in proportion to the fine nu:
+                nu_i'(y') = (m_i' / m_i) nu_i(P(y')) nu_f(y') / nu(P(y')),
+            so that sum_y' nu_i'(y') = m_i' and sum_i' nu_i'(y') = nu_f(y') hold exactly;
+          * potentials: the stitched global alpha of this layer (energy units,
+            stitched_alpha), interpolated bilinearly at the fine pixel centres (linearly
+            extrapolated beyond the outermost coarse centres), is the starting alpha of every
+            composite cell of both fine partitions (their first visit is a previous-iterate
+            start from it)."""
+        N, Nf, s = self.N, 2 * self.N, self.s
+        mu_f = np.asarray(mu_f, np.float64).reshape(Nf, Nf)
+        nu_f = np.asarray(nu_f, np.float64).reshape(Nf, Nf)
+        if np.abs(coarsen(mu_f).reshape(-1) - self.mu).max() > 1e-12 or \
+                np.abs(coarsen(nu_f).reshape(-1) - self.nu).max() > 1e-12:
+            raise ValueError("refine: the fine marginals must sum to this layer's over 2 x 2 blocks")
+        alpha_c = self.stitched_alpha().reshape(N, N)
+        fine = DomDec.__new__(DomDec)
+        fine._setup(mu_f, nu_f, s, self.trunc)
+        nf = fine.n
+        # coupling
+        nu_c = self.nu
+        for r in range(nf):
+            for c in range(nf):
+                i_f = r * nf + c
+                i_c = (r // 2) * self.n + (c // 2)
+                idx, val = self.nu_i[i_c]
+                y1, y2 = np.divmod(idx, N)
+                kids, vals = [], []
+                for a in (0, 1):
+                    for b in (0, 1):
+                        yf = (2 * y1 + a) * Nf + (2 * y2 + b)
+                        share = nu_f.reshape(-1)[yf] / nu_c[idx]
+                        kids.append(yf)
+                        vals.append(val * share * (fine.m[i_f] / self.m[i_c]))
+                yf = np.concatenate(kids)
+                v = np.concatenate(vals)
+                order = np.argsort(yf)
+                keep = v[order] > 0
+                fine.nu_i.append((yf[order][keep], v[order][keep]))
+        alpha_f = upsample_bilinear(alpha_c).reshape(-1)
+        for which in ("A", "B"):
+            for J, basic in enumerate(fine.parts[which]):
+                xpix = np.concatenate([fine.cells[i] for i in basic])
+                fine.alpha[which][J] = alpha_f[xpix].copy()
+        return fine
 
     def transport_cost(self, which: Optional[str] = None) -> float:
         """<c, pi> of the composite plans."""
@@ -590,6 +656,24 @@ class DomDec:
 # ---------------------------------------------------------------------------
 # Global problems (tiny grids)
 # ---------------------------------------------------------------------------
+
+def upsample_bilinear(a: np.ndarray) -> np.ndarray:
+    """Values of a function known at the pixel centres of an N x N grid, at the pixel centres of
+    the 2N x 2N grid: bilinear interpolation between the four nearest coarse centres, linear
+    extrapolation beyond the outermost ones.  Fine pixel k lies at coarse index (k - 1/2) / 2."""
+    N = a.shape[0]
+    u = (np.arange(2 * N) - 0.5) / 2.0
+    k0 = np.clip(np.floor(u).astype(np.int64), 0, N - 2)
+    t = u - k0
+    rows = (1 - t)[:, None] * a[k0, :] + t[:, None] * a[k0 + 1, :]
+    return (1 - t)[None, :] * rows[:, k0] + t[None, :] * rows[:, k0 + 1]
+
+
+def coarsen(a: np.ndarray) -> np.ndarray:
+    """The next coarser layer of a measure on an N x N grid: sums over 2 x 2 pixel blocks."""
+    N = a.shape[0]
+    return a.reshape(N // 2, 2, N // 2, 2).sum(axis=(1, 3))
+
 
 def global_sinkhorn(mu: np.ndarray, nu: np.ndarray, eps: float, tol: float = 1e-13,
                     max_iter: int = 200000):
