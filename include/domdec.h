@@ -181,6 +181,29 @@ dd_status sinkhorn_batch_f64(int32_t ncells, int32_t xside, const int32_t* dims,
                              int32_t* cell_iters, double* cell_err, void* stream,
                              dd_batch_stats* stats);
 
+/*
+ * sinkhorn_batch_noalloc -- sinkhorn_batch for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid hipMalloc).
+ * Same arguments, arithmetic, stopping rules and results as sinkhorn_batch; it calls no
+ * hipMalloc / hipFree and creates no streams, events or graphs.  Its workspace (control
+ * words, per-cell errors, masses and counts, the second X-potential buffer, processing
+ * orders, global scratch for boxes beyond the on-chip tiles) is carved from one fixed
+ * 64 MiB device buffer per GPU, held by the library until the process ends.  All of the
+ * work runs on `stream` (the cell classes one after the other instead of side by side), and
+ * the statistics carry no times (time_ms, main_ms and kernel_ms are 0).
+ * Calls that overlap on one GPU share that buffer and race: serialise them.  The buffer
+ * keeps the last call's contents; every call initialises what it reads.
+ * Errors: those of sinkhorn_batch, and DD_EINVAL when the batch needs more workspace than
+ * the buffer holds (roughly 0.6 KB per cell with 8 x 8 blocks, plus the global scratch of the
+ * largest boxes); nothing is written to a or b then.
+ */
+dd_status sinkhorn_batch_noalloc(int32_t ncells, int32_t xside, const int32_t* dims,
+                                 const int64_t* base, const int32_t* shift, const double* logmu,
+                                 const double* lognu, double* a, double* b, double kappa,
+                                 int32_t max_w1, int32_t max_w2, const dd_sinkhorn_opts* opts,
+                                 int32_t* cell_iters, double* cell_err, void* stream,
+                                 dd_batch_stats* stats);
+
 /* ------------------------------------------------------------------------- */
 /* Domain-decomposition context                                              */
 /* ------------------------------------------------------------------------- */

@@ -25,7 +25,7 @@ SYMBOLS = ("sinkhorn_batch", "sinkhorn_batch_f64", "domdec_init", "domdec_iterat
            "flow_costs", "flow_apply", "dd_mcf_solve", "extract_plan", "domdec_evaluate", "domdec_free",
            "domdec_strerror", "dd_net_param_count", "dd_net_create", "dd_net_params", "dd_net_forward",
            "dd_net_train_step", "dd_net_free", "dd_net_strerror", "domdec_set_net", "domdec_net_samples", "domdec_save", "domdec_restore",
-           "extract_potentials")
+           "extract_potentials", "sinkhorn_batch_noalloc")
 
 
 class DomDecError(RuntimeError):
@@ -122,7 +122,7 @@ def lib():
     L = ctypes.CDLL(_LIB_PATH)
     vp, i32p, i64p = ctypes.c_void_p, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int64)
     dp = ctypes.POINTER(ctypes.c_double)
-    for name in ("sinkhorn_batch", "sinkhorn_batch_f64"):
+    for name in ("sinkhorn_batch", "sinkhorn_batch_f64", "sinkhorn_batch_noalloc"):
         f = getattr(L, name)
         f.restype = ctypes.c_int
         f.argtypes = [ctypes.c_int32, ctypes.c_int32, vp, vp, vp, vp, vp, vp, vp, ctypes.c_double,
@@ -224,8 +224,9 @@ def _stream_ptr(stream):
 
 def sinkhorn_batch(dims, base, shift, logmu, lognu, a, b, kappa, max_w1, max_w2, *, prec=DD_PREC_F32,
                    tol=1e-5, max_iter=10000, fixed_iters=0, stop_rule=DD_STOP_BATCH, check_every=8,
-                   cell_iters=None, cell_err=None, stream=None, raise_on_error=True):
-    """Batched cell Sinkhorn on device tensors (see sinkhorn_batch in include/domdec.h).
+                   cell_iters=None, cell_err=None, stream=None, raise_on_error=True, noalloc=False):
+    """Batched cell Sinkhorn on device tensors (see sinkhorn_batch in include/domdec.h;
+    noalloc=True calls sinkhorn_batch_noalloc, float32 only).
 
     dims int32 [n,2], base int64 [n], shift int32 [n,2], float64 logmu [n, xside^2], lognu packed,
     a [n, xside^2] (f, in/out), b packed (g, out).  prec DD_PREC_F32 -> sinkhorn_batch
@@ -247,7 +248,10 @@ def sinkhorn_batch(dims, base, shift, logmu, lognu, a, b, kappa, max_w1, max_w2,
         if np.any(hd < 1) or np.any(hb < 0) or np.any(hb + hd[:, 0] * hd[:, 1] > lognu.numel()) \
                 or b.numel() != lognu.numel():
             raise ValueError("sinkhorn_batch: a Y box lies outside lognu/b")
-    f = lib().sinkhorn_batch if prec == DD_PREC_F32 else lib().sinkhorn_batch_f64
+    if noalloc and prec != DD_PREC_F32:
+        raise ValueError("sinkhorn_batch_noalloc is the float32 entry point")
+    f = lib().sinkhorn_batch_noalloc if noalloc else (
+        lib().sinkhorn_batch if prec == DD_PREC_F32 else lib().sinkhorn_batch_f64)
     st = BatchStats()
     o = _opts(tol, max_iter, fixed_iters, stop_rule, check_every)
     status = f(n, xside, _ptr(dims), _ptr(base), _ptr(shift), _ptr(logmu), _ptr(lognu), _ptr(a), _ptr(b),

@@ -1163,7 +1163,13 @@ Status fast_solve(const SkBatch& p, const dd_sinkhorn_opts& o, hipStream_t st, S
         first[k] = (int)ord.size();
         ord.insert(ord.end(), cells[k].begin(), cells[k].end());
     }
-    if (n > w.order_cap) {
+    const bool arena = w.arena != nullptr;  // no-allocation mode: caller's stream, no events
+    if (arena) {
+        if ((S = arena_take(w, w.order, (size_t)n)).code ||
+            (S = arena_take(w, w.scr_off, (size_t)n)).code)
+            return S;
+        w.order_cap = n;
+    } else if (n > w.order_cap) {
         if (w.order) (void)hipFree(w.order);
         if (w.scr_off) (void)hipFree(w.scr_off);
         w.order = nullptr;
@@ -1218,7 +1224,7 @@ Status fast_solve(const SkBatch& p, const dd_sinkhorn_opts& o, hipStream_t st, S
     }
     // the classes run side by side on three streams, the other two forked from `st` and
     // joined back
-    const bool multi = ncls > 1;
+    const bool multi = ncls > 1 && !arena;
     auto fork = [&]() {
         if (!multi) return;
         (void)hipEventRecord(w.evf, st);
@@ -1281,10 +1287,11 @@ Status fast_solve(const SkBatch& p, const dd_sinkhorn_opts& o, hipStream_t st, S
     // every launch is bracketed by events on its own stream (the per-class kernel time of the
     // statistics), the launches after the stop, which exit at once, included
     const int reps = 4;
-    for (auto& cls : w.kev)
-        for (auto& se : cls)
-            for (hipEvent_t& e : se)
-                if (!e) DD_HIP(hipEventCreate(&e), S);
+    if (!arena)
+        for (auto& cls : w.kev)
+            for (auto& se : cls)
+                for (hipEvent_t& e : se)
+                    if (!e) DD_HIP(hipEventCreate(&e), S);
     double terms_per_it[kClasses] = {0.0, 0.0, 0.0};
     for (int k = 0; k < kClasses; ++k)
         for (int c : cells[k]) terms_per_it[k] += sk_cell_terms(kA, hd[2 * c], hd[2 * c + 1]);
@@ -1293,21 +1300,22 @@ Status fast_solve(const SkBatch& p, const dd_sinkhorn_opts& o, hipStream_t st, S
     for (int rounds = 0; rounds < o.max_iter && !hctl[2]; rounds += reps) {
         for (int r = 0; r < reps; ++r) {
             fork();
-            launch(a, kBatch, true, r);
+            launch(a, kBatch, !arena, r);
             join();
         }
         DD_HIP(hipMemcpyAsync(hctl, w.ctrl, sizeof hctl, hipMemcpyDeviceToHost, st), S);
         DD_HIP(hipStreamSynchronize(st), S);
-        for (int r = 0; r < reps; ++r) collect(r);
+        if (!arena)
+            for (int r = 0; r < reps; ++r) collect(r);
     }
     if (info)
         for (int k = 0; k < kClasses; ++k) info->terms[k] = terms_per_it[k] * hctl[10];
     // the final Y-update (g), timed the same way
     fork();
-    launch(a, kFinal, true, 0);
+    launch(a, kFinal, !arena, 0);
     join();
     DD_HIP(hipStreamSynchronize(st), S);
-    collect(0);
+    if (!arena) collect(0);
     DD_HIP(hipGetLastError(), S);
     return S;
 }

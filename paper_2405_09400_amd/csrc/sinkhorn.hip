@@ -943,6 +943,20 @@ size_t sk_lds_bytes(int xside, int prec) {
 
 Status sk_work_reserve(SkWork& w, int ncells, size_t a_n) {
     Status st;
+    if (w.arena) {
+        // no-allocation mode: carve the per-solve buffers from the start of the arena
+        w.arena_used = 0;
+        if ((st = arena_take(w, w.ctrl, 16)).code || (st = arena_take(w, w.dtot, 8)).code ||
+            (st = arena_take(w, w.cell_err, (size_t)ncells)).code ||
+            (st = arena_take(w, w.cell_mass, (size_t)ncells)).code ||
+            (st = arena_take(w, w.cell_iters, (size_t)ncells)).code ||
+            (st = arena_take(w, w.iters64, (size_t)ncells)).code ||
+            (st = arena_take(w, w.a_alt, a_n)).code)
+            return st;
+        w.cap = ncells;
+        w.a_alt_n = a_n;
+        return st;
+    }
     if (!w.ctrl) {
         DD_HIP(hipMalloc(&w.ctrl, 16 * sizeof(int)), st);
         DD_HIP(hipMalloc(&w.dtot, 8 * sizeof(double)), st);
@@ -983,6 +997,7 @@ Status sk_work_reserve(SkWork& w, int ncells, size_t a_n) {
 }
 
 void sk_work_release(SkWork& w) {
+    if (w.arena) return;  // no-allocation mode: nothing of its own to release
     if (w.order) (void)hipFree(w.order);
     if (w.scr_off) (void)hipFree(w.scr_off);
     if (w.order64) (void)hipFree(w.order64);
@@ -1061,7 +1076,8 @@ Status run_solver(const SkBatch& p0, const std::vector<CellClass>& cls, const dd
     Status S;
     double* big = reinterpret_cast<double*>(w.big);
     // the small and giant classes run on `st`, the big class on the second stream, side by side
-    const hipStream_t streams[3] = {st, w.stream2, st};
+    const bool one_stream = w.arena != nullptr;  // no-allocation mode: the caller's stream only
+    const hipStream_t streams[3] = {st, one_stream ? st : w.stream2, st};
     hipEvent_t joins[3] = {nullptr, w.evj2, nullptr};
     const int qidx[3] = {0, 9, 11};
     const int ncls = (int)cls.size();
@@ -1077,12 +1093,12 @@ Status run_solver(const SkBatch& p0, const std::vector<CellClass>& cls, const dd
     }
     // classes on the second stream are forked from `st` and joined back
     auto fork = [&]() {
-        if (ncls < 2) return;
+        if (ncls < 2 || one_stream) return;
         (void)hipEventRecord(w.evf, st);
         (void)hipStreamWaitEvent(streams[1], w.evf, 0);
     };
     auto join = [&]() {
-        if (ncls < 2) return;
+        if (ncls < 2 || one_stream) return;
         (void)hipEventRecord(joins[1], streams[1]);
         (void)hipStreamWaitEvent(st, joins[1], 0);
     };
@@ -1120,41 +1136,50 @@ Status run_solver(const SkBatch& p0, const std::vector<CellClass>& cls, const dd
     const int chunk = o.check_every > 0 ? o.check_every : 8;
     // a chunk of identical iterations (every class's launch, forked and joined) is captured
     // into a HIP graph once and replayed; the host reads the device stop flag between replays
+    // (in no-allocation mode the chunk is launched directly, no graph is built)
+    auto chunk_launches = [&]() {
+        for (int r = 0; r < chunk; ++r) {
+            fork();
+            for (int k = 0; k < ncls; ++k) {
+                auto ik = cls[k].mode == kBig ? sk_iter_kernel<T, kBig> : sk_iter_kernel<T, kSmall>;
+                ik<<<grid[k], kThreads, lds[k], streams[k]>>>(pk[k], bufs[0], bufs[1], o.max_iter,
+                                                              o.tol, nblocks, w.ctrl, errs,
+                                                              w.cell_mass, w.dtot, big);
+            }
+            join();
+        }
+    };
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
-    DD_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal), S);
-    for (int r = 0; r < chunk; ++r) {
-        fork();
-        for (int k = 0; k < ncls; ++k) {
-            auto ik = cls[k].mode == kBig ? sk_iter_kernel<T, kBig> : sk_iter_kernel<T, kSmall>;
-            ik<<<grid[k], kThreads, lds[k], streams[k]>>>(pk[k], bufs[0], bufs[1], o.max_iter,
-                                                          o.tol, nblocks, w.ctrl, errs,
-                                                          w.cell_mass, w.dtot, big);
+    if (!one_stream) {
+        DD_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal), S);
+        chunk_launches();
+        const hipError_t ce = hipStreamEndCapture(st, &graph);
+        if (ce != hipSuccess ||
+            hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) != hipSuccess) {
+            if (graph) (void)hipGraphDestroy(graph);
+            S.code = DD_EDEVICE;
+            S.msg = "sinkhorn: HIP graph capture of the iteration failed";
+            return S;
         }
-        join();
-    }
-    const hipError_t ce = hipStreamEndCapture(st, &graph);
-    if (ce != hipSuccess || hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) != hipSuccess) {
-        if (graph) (void)hipGraphDestroy(graph);
-        S.code = DD_EDEVICE;
-        S.msg = "sinkhorn: HIP graph capture of the iteration failed";
-        return S;
     }
     int done = 0;
     for (int launched = 0; launched < o.max_iter && !done; launched += chunk) {
-        if (hipGraphLaunch(exec, st) != hipSuccess ||
+        if (one_stream)
+            chunk_launches();
+        if ((!one_stream && hipGraphLaunch(exec, st) != hipSuccess) ||
             hipMemcpyAsync(&done, w.ctrl + 2, sizeof(int), hipMemcpyDeviceToHost, st) !=
                 hipSuccess ||
             hipStreamSynchronize(st) != hipSuccess) {
-            (void)hipGraphExecDestroy(exec);
-            (void)hipGraphDestroy(graph);
+            if (exec) (void)hipGraphExecDestroy(exec);
+            if (graph) (void)hipGraphDestroy(graph);
             S.code = DD_EDEVICE;
             S.msg = "sinkhorn: graph replay failed";
             return S;
         }
     }
-    (void)hipGraphExecDestroy(exec);
-    (void)hipGraphDestroy(graph);
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
     if (done < 1) done = o.max_iter;  // unreachable: the kernel sets done at max_iter
     if (((done - 1) & 1) == 1)
         DD_HIP(hipMemcpyAsync(p0.a, bufs[1], a_bytes, hipMemcpyDeviceToDevice, st), S);
@@ -1333,10 +1358,12 @@ struct StreamJoin {
     hipStream_t caller, own;
     hipEvent_t ev;
     StreamJoin(hipStream_t c, hipStream_t o, hipEvent_t e) : caller(c), own(o), ev(e) {
+        if (!ev) return;  // no-allocation mode: the caller's stream is used directly
         (void)hipEventRecord(ev, caller);
         (void)hipStreamWaitEvent(own, ev, 0);
     }
     ~StreamJoin() {
+        if (!ev) return;
         (void)hipEventRecord(ev, own);
         (void)hipStreamWaitEvent(caller, ev, 0);
     }
@@ -1361,8 +1388,9 @@ Status sk_solve(const SkBatch& p, const dd_sinkhorn_opts& o, hipStream_t caller_
     }
     S = sk_work_reserve(w, p.ncells, (size_t)p.ncells * p.xside * p.xside);
     if (S.code) return S;
-    const StreamJoin join(caller_st, w.stream, w.evj);
-    const hipStream_t st = w.stream;
+    const bool arena = w.arena != nullptr;
+    const StreamJoin join(caller_st, arena ? caller_st : w.stream, arena ? nullptr : w.evj);
+    const hipStream_t st = arena ? caller_st : w.stream;
     int32_t* iters = cell_iters_out ? cell_iters_out : w.cell_iters;
     double* errs = cell_err_out ? cell_err_out : w.cell_err;
     if (p.ncells == 0) {
@@ -1415,7 +1443,12 @@ Status sk_solve(const SkBatch& p, const dd_sinkhorn_opts& o, hipStream_t caller_
                             : Plan{};
     auto put = [&](int32_t*& dev_ord, int64_t*& dev_off, int& cap, const Plan& pl) -> Status {
         Status E;
-        if (p.ncells > cap) {
+        if (arena) {
+            if ((E = arena_take(w, dev_ord, (size_t)p.ncells)).code ||
+                (E = arena_take(w, dev_off, (size_t)p.ncells)).code)
+                return E;
+            cap = p.ncells;
+        } else if (p.ncells > cap) {
             if (dev_ord) (void)hipFree(dev_ord);
             if (dev_off) (void)hipFree(dev_off);
             dev_ord = nullptr;
@@ -1447,7 +1480,13 @@ Status sk_solve(const SkBatch& p, const dd_sinkhorn_opts& o, hipStream_t caller_
         q64.scr_off = w.scr_off64;
     }
     const int64_t scr = std::max(P.scr, P64.scr);
-    if (scr > 0) {
+    if (arena) {
+        double* bigp = nullptr;
+        S = arena_take(w, bigp, (size_t)std::max<int64_t>(scr, 0) + 8);
+        if (S.code) return S;
+        w.big = bigp;
+        w.big_bytes = ((size_t)std::max<int64_t>(scr, 0) + 8) * sizeof(double);
+    } else if (scr > 0) {
         const size_t need = (size_t)scr * sizeof(double) + 64;
         if (need > w.big_bytes) {
             if (w.big) (void)hipFree(w.big);
@@ -1458,7 +1497,7 @@ Status sk_solve(const SkBatch& p, const dd_sinkhorn_opts& o, hipStream_t caller_
     }
     // the host vectors above outlive the copies: wait before they go out of scope
     DD_HIP(hipStreamSynchronize(st), S);
-    DD_HIP(hipEventRecord(w.ev0, st), S);
+    if (!arena) DD_HIP(hipEventRecord(w.ev0, st), S);
     zero_ints<<<1, 64, 0, st>>>(w.ctrl, 16);
     FastInfo fi;
     if (fast)
@@ -1467,7 +1506,7 @@ Status sk_solve(const SkBatch& p, const dd_sinkhorn_opts& o, hipStream_t caller_
         S = p.prec == DD_PREC_F32 ? run_solver<float>(q, P.classes, o, st, w, iters, errs)
                                   : run_solver<double>(q, P.classes, o, st, w, iters, errs);
     if (S.code) return S;
-    DD_HIP(hipEventRecord(w.ev2, st), S);
+    if (!arena) DD_HIP(hipEventRecord(w.ev2, st), S);
     if (finish) {
         // float64 finish: continue the same stopping rule in float64 from the float32 state;
         // the tolerance is then certified by a float64 error (usually after one Y-update)
@@ -1479,15 +1518,17 @@ Status sk_solve(const SkBatch& p, const dd_sinkhorn_opts& o, hipStream_t caller_
     if (finish)
         merge_iters_kernel<<<(p.ncells + kThreads - 1) / kThreads, kThreads, 0, st>>>(p.ncells, iters,
                                                                                      w.iters64);
-    DD_HIP(hipEventRecord(w.ev1, st), S);
+    if (!arena) DD_HIP(hipEventRecord(w.ev1, st), S);
     int hctl[16];
     double htot[8];
     DD_HIP(hipMemcpyAsync(hctl, w.ctrl, sizeof hctl, hipMemcpyDeviceToHost, st), S);
     DD_HIP(hipMemcpyAsync(htot, w.dtot, sizeof htot, hipMemcpyDeviceToHost, st), S);
     DD_HIP(hipStreamSynchronize(st), S);
     float ms = 0.f, ms_main = 0.f;
-    DD_HIP(hipEventElapsedTime(&ms, w.ev0, w.ev1), S);
-    DD_HIP(hipEventElapsedTime(&ms_main, w.ev0, w.ev2), S);
+    if (!arena) {
+        DD_HIP(hipEventElapsedTime(&ms, w.ev0, w.ev1), S);
+        DD_HIP(hipEventElapsedTime(&ms_main, w.ev0, w.ev2), S);
+    }
     if (hctl[3]) {
         S.code = DD_EINVAL;
         S.msg = "sinkhorn: a cell's Y box is empty or exceeds max_w1/max_w2";
@@ -1538,7 +1579,7 @@ Status sk_solve(const SkBatch& p, const dd_sinkhorn_opts& o, hipStream_t caller_
         bs.converged = hctl[7];
     else
         bs.converged = hctl[4];
-    if (!fast && bs.lse_terms > 0.0) tuner().record(key, choice, ms_main / bs.lse_terms);
+    if (!fast && !arena && bs.lse_terms > 0.0) tuner().record(key, choice, ms_main / bs.lse_terms);
     if (stats) *stats = bs;
     if (!std::isfinite(bs.err)) {
         S.code = DD_ENUMERIC;
@@ -1609,4 +1650,88 @@ extern "C" dd_status sinkhorn_batch_f64(int32_t ncells, int32_t xside, const int
                                         double* cell_err, void* stream, dd_batch_stats* stats) {
     return batch_entry(DD_PREC_F64, ncells, xside, dims, base, shift, logmu, lognu, a, b, kappa,
                        max_w1, max_w2, opts, cell_iters, cell_err, stream, stats);
+}
+
+// ---------------------------------------------------------------------------
+// No-allocation entry point
+// ---------------------------------------------------------------------------
+namespace {
+// The fixed device buffer every workspace of sinkhorn_batch_noalloc is carved from (control
+// words, per-cell errors, masses and iteration counts, the second X-potential buffer, the
+// processing orders and the global scratch of boxes beyond the LDS tiles).  Each device holds
+// its own copy for the life of the process.  Host code never passes `scratch` itself to a
+// kernel (in host code the name is not a device address): it uses the per-device address
+// from hipGetSymbolAddress.
+constexpr size_t kNoAllocBytes = (size_t)64 << 20;
+__device__ __align__(256) char scratch[kNoAllocBytes];
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+char* g_scratch_ptr[kMaxDevices] = {};
+
+// The device address of this device's `scratch`, looked up once per device with the device
+// current.
+dd::Status scratch_address(char*& out) {
+    dd::Status st;
+    int dev = -1;
+    DD_HIP(hipGetDevice(&dev), st);
+    if (dev < 0 || dev >= kMaxDevices) {
+        st.code = DD_EDEVICE;
+        st.msg = "sinkhorn_batch_noalloc: device index beyond the supported range";
+        return st;
+    }
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* ptr = nullptr;
+        DD_HIP(hipGetSymbolAddress((void**)&ptr, HIP_SYMBOL(scratch)), st);
+        if (!ptr) {
+            st.code = DD_EDEVICE;
+            st.msg = "sinkhorn_batch_noalloc: no device address for the scratch buffer";
+            return st;
+        }
+        g_scratch_ptr[dev] = static_cast<char*>(ptr);
+    }
+    out = g_scratch_ptr[dev];
+    return st;
+}
+}  // namespace
+
+extern "C" dd_status sinkhorn_batch_noalloc(int32_t ncells, int32_t xside, const int32_t* dims,
+                                            const int64_t* base, const int32_t* shift,
+                                            const double* logmu, const double* lognu, double* a,
+                                            double* b, double kappa, int32_t max_w1,
+                                            int32_t max_w2, const dd_sinkhorn_opts* opts,
+                                            int32_t* cell_iters, double* cell_err, void* stream,
+                                            dd_batch_stats* stats) {
+    if (!opts || (ncells > 0 && (!dims || !base || !shift || !logmu || !lognu || !a || !b))) {
+        dd::set_global_error("sinkhorn_batch_noalloc: null argument");
+        return DD_EINVAL;
+    }
+    char* arena = nullptr;
+    dd::Status s = scratch_address(arena);
+    if (s.code != DD_OK) {
+        dd::set_global_error(s.msg);
+        return s.code;
+    }
+    dd::SkBatch p;
+    p.ncells = ncells;
+    p.xside = xside;
+    p.dims = dims;
+    p.base = base;
+    p.shift = shift;
+    p.logmu = logmu;
+    p.lognu = lognu;
+    p.a = a;
+    p.b = b;
+    p.kappa = kappa;
+    p.max_w1 = max_w1;
+    p.max_w2 = max_w2;
+    p.prec = DD_PREC_F32;
+    dd::SkWork w;
+    w.arena = arena;
+    w.arena_bytes = kNoAllocBytes;
+    const hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    s = dd::sk_solve(p, *opts, st, w, stats, cell_iters, cell_err);
+    (void)hipStreamSynchronize(st);
+    if (s.code != DD_OK) dd::set_global_error(s.msg);
+    return s.code;
 }

@@ -55,7 +55,30 @@ struct SkWork {
     hipStream_t stream3 = nullptr;
     hipEvent_t evj3 = nullptr;
     hipEvent_t kev[3][2][4] = {};  // register-blocked path: start/end of each class's rounds
+    // No-allocation mode: every buffer above is carved from a device arena the caller owns
+    // (bump allocation from the start of the arena on every solve), all work runs on the
+    // caller's stream, and no events, streams or graphs are created (statistics carry no
+    // times).
+    char* arena = nullptr;
+    size_t arena_bytes = 0, arena_used = 0;
 };
+
+// Carve n elements from the no-allocation arena (256-byte aligned); DD_EINVAL when the arena
+// is too small for the batch.
+template <typename P>
+inline Status arena_take(SkWork& w, P*& p, size_t n) {
+    Status st;
+    const size_t bytes = ((n > 0 ? n : 1) * sizeof(P) + 255) & ~(size_t)255;
+    if (w.arena_used + bytes > w.arena_bytes) {
+        st.code = DD_EINVAL;
+        st.msg = "sinkhorn: the batch needs more scratch than the no-allocation entry point's "
+                 "fixed buffer holds";
+        return st;
+    }
+    p = reinterpret_cast<P*>(w.arena + w.arena_used);
+    w.arena_used += bytes;
+    return st;
+}
 
 Status sk_work_reserve(SkWork& w, int ncells, size_t a_n);
 void sk_work_release(SkWork& w);
