@@ -44,6 +44,12 @@ WORKLOAD_TEXT = {
               "eps-scaling 64..2 untimed, timed DD iterations at eps=h^2",
     "mix1024": "mix1024: {N}x{N} 16-blob Gaussian mixtures + 1e-4 floor, s={s}, KR init, "
                "eps-scaling 64..2 untimed, timed DD iterations at eps=h^2",
+    "ms512": "ms512: the mix512 marginals solved coarse to fine (untimed): layers 32^2 ... 256^2 "
+             "of 2x2 block sums, eps = 2h^2, h^2, h^2/2 per layer (4 DD iterations each), then "
+             "512^2 at 2h^2; timed DD iterations at eps=h^2, s={s}",
+    "ms1024": "ms1024: the mix1024 marginals solved coarse to fine (untimed): layers 32^2 ... "
+              "512^2, eps = 2h^2, h^2, h^2/2 per layer (4 DD iterations each), then 1024^2 at "
+              "2h^2; timed DD iterations at eps=h^2, s={s}",
     "flow512": "flow512: {N}x{N}, mu 8-blob mixture, nu = mu rotated 30 deg, contracted 0.36, "
                "shifted (0.25, 0); s={s}; map init; eps=h^2; hybrid A, B, flow update",
 }
@@ -62,10 +68,22 @@ def setup(args, workload, prec_name):
     w = synth.workload(workload, seed=args.seed)
     prec = dd.DD_PREC_F32 if prec_name == "f32" else dd.DD_PREC_F64
     t0 = time.perf_counter()
-    ctx = dd.DomDec(w.mu, w.nu, w.s, w.init, prec=prec)
+    levels = w.extra.get("levels", 0)
+    ctx = dd.DomDec(w.mu, w.nu, w.s, w.init, prec=prec, levels=levels)
     log(f"[bench] init {workload} N={w.N} s={w.s} {prec_name} in {time.perf_counter() - t0:.2f}s")
     rule = dd.DD_STOP_CELL if args.stop_rule == "cell" else dd.DD_STOP_BATCH
     k = 0
+    # coarser layers of a multiscale workload: their eps stages, then the refinement
+    for layer in range(levels):
+        for kappa in w.extra["layer_kappas"]:
+            eps = kappa / ctx.N ** 2
+            for _ in range(w.extra["layer_iters"]):
+                st = ctx.iterate("AB"[k % 2], eps, tol=args.tol, stop_rule=rule,
+                                 max_iter=args.max_iter, check_every=args.check_every)
+                k += 1
+        log(f"[bench] layer {ctx.N}x{ctx.N} done: last iters={st['sk']['iters_max']} "
+            f"maxW={st['max_w1']}x{st['max_w2']}")
+        ctx.refine()
     for kappa, its in zip(w.kappas[:-1], w.stage_iters[:-1]):
         eps = kappa / w.N ** 2
         for _ in range(its):

@@ -215,7 +215,10 @@ typedef struct {
     int32_t s;         /* basic cell side; N % (2 s) == 0, 1 <= s <= 8              */
     double trunc;      /* truncation threshold for nu_i entries (e.g. 1e-15)       */
     int32_t prec;      /* DD_PREC_F32 | DD_PREC_F64                                */
-    int32_t reserved;  /* must be 0                                                */
+    int32_t levels;    /* coarser layers of multiscale DD below the N x N grid
+                          (0: single scale).  With L > 0 the context starts on the
+                          (N / 2^L)^2 layer; domdec_refine moves to the next finer one.
+                          N / 2^L must be a multiple of 2 s.                        */
 } dd_params;
 
 /*
@@ -236,6 +239,10 @@ typedef struct {
  *              mu and nu within 1e-12 (checked).
  *   stream     hipStream_t for all later work of this context.
  *   out        receives the context (NULL on failure).
+ * Multiscale (params.levels = L > 0; App. A.2.1 "Multi-scale and eps-scaling", Sec. 5.3):
+ *   the layers are the 2 x 2 block sums of mu and nu, L times; the context starts on the
+ *   coarsest, with the initial coupling summed over the same blocks (the product coupling of
+ *   the coarsest layer when n_init == 0).
  * Errors: DD_EINVAL (shapes, negative/NaN masses, sums, m_i == 0, marginals),
  * DD_ENOMEM, DD_EDEVICE.
  */
@@ -248,7 +255,7 @@ typedef struct {
     dd_batch_stats sk;        /* the cell solve                                       */
     int32_t partition;
     int32_t max_w1, max_w2;   /* largest composite Y box                              */
-    int32_t reserved;
+    int32_t grid_n;           /* grid side of the current layer                       */
     int64_t nu_entries;       /* stored nu_i entries after truncation                 */
     int64_t comp_entries;     /* composite Y-box entries solved                       */
     double t_b2c_ms;          /* BasicToComposite                                     */
@@ -275,6 +282,28 @@ typedef struct {
  */
 dd_status domdec_iterate(dd_ctx* ctx, int32_t partition, double eps,
                          const dd_sinkhorn_opts* opts, dd_iter_stats* stats);
+
+/*
+ * domdec_refine -- the coarse-to-fine step of multiscale domain decomposition (App. A.2.1
+ * "Multi-scale and eps-scaling", Sec. 5.3; the paper defers the step to earlier work, so the
+ * reading is stated here).  Moves the context to the next finer layer (grid side 2N, same s):
+ *   coupling: a fine basic cell i' is one of the 2 x 2 children of a coarse basic cell i and a
+ *     fine pixel y' one of the 2 x 2 children of a coarse pixel P(y'); the coarse mass is
+ *     split among the X children in proportion to their mu mass and among the Y children in
+ *     proportion to the fine nu:
+ *         nu_i'(y') = (m_i' / m_i) nu_i(P(y')) nu_fine(y') / nu(P(y')),
+ *     which keeps both marginal constraints exactly;
+ *   potentials: the stitched global alpha of the coarse layer (the A cells' potentials offset
+ *     as for the dual of domdec_evaluate), interpolated bilinearly at the fine pixel centres
+ *     and extrapolated linearly beyond the outermost coarse centres, becomes the X potential
+ *     of every composite cell of both fine partitions: their next iteration with
+ *     DD_INIT_PREV starts from it.
+ * Needs an iteration of both partitions on the current layer.  The context handle stays
+ * valid; the coarse layer's state (and any saved copy, flow-update basis) is released.
+ * Errors: DD_ESTATE (already on the finest layer, or a partition not iterated on this
+ * layer), DD_ENOMEM, DD_EDEVICE.
+ */
+dd_status domdec_refine(dd_ctx* ctx);
 
 /* Flow update statistics. */
 typedef struct {

@@ -25,7 +25,7 @@ SYMBOLS = ("sinkhorn_batch", "sinkhorn_batch_f64", "domdec_init", "domdec_iterat
            "flow_costs", "flow_apply", "dd_mcf_solve", "extract_plan", "domdec_evaluate", "domdec_free",
            "domdec_strerror", "dd_net_param_count", "dd_net_create", "dd_net_params", "dd_net_forward",
            "dd_net_train_step", "dd_net_free", "dd_net_strerror", "domdec_set_net", "domdec_net_samples", "domdec_save", "domdec_restore",
-           "extract_potentials", "sinkhorn_batch_noalloc")
+           "extract_potentials", "sinkhorn_batch_noalloc", "domdec_refine")
 
 
 class DomDecError(RuntimeError):
@@ -55,12 +55,12 @@ class BatchStats(ctypes.Structure):
 
 class Params(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int32), ("s", ctypes.c_int32), ("trunc", ctypes.c_double),
-                ("prec", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("prec", ctypes.c_int32), ("levels", ctypes.c_int32)]
 
 
 class IterStats(ctypes.Structure):
     _fields_ = [("sk", BatchStats), ("partition", ctypes.c_int32), ("max_w1", ctypes.c_int32),
-                ("max_w2", ctypes.c_int32), ("reserved", ctypes.c_int32), ("nu_entries", ctypes.c_int64),
+                ("max_w2", ctypes.c_int32), ("grid_n", ctypes.c_int32), ("nu_entries", ctypes.c_int64),
                 ("comp_entries", ctypes.c_int64), ("t_b2c_ms", ctypes.c_double),
                 ("t_sinkhorn_ms", ctypes.c_double), ("t_c2b_ms", ctypes.c_double),
                 ("t_total_ms", ctypes.c_double), ("t_init_ms", ctypes.c_double)]
@@ -169,7 +169,7 @@ def lib():
     L.dd_net_strerror.argtypes = [vp]
     L.domdec_set_net.restype = ctypes.c_int
     L.domdec_set_net.argtypes = [vp, vp]
-    for name in ("domdec_save", "domdec_restore"):
+    for name in ("domdec_save", "domdec_restore", "domdec_refine"):
         getattr(L, name).restype = ctypes.c_int
         getattr(L, name).argtypes = [vp]
     L.domdec_net_samples.restype = ctypes.c_int
@@ -266,14 +266,17 @@ class DomDec:
     """A device-resident domain-decomposition state (dd_ctx) on the current HIP device."""
 
     def __init__(self, mu: np.ndarray, nu: np.ndarray, s: int, init=None, trunc: float = 1e-15,
-                 prec: int = DD_PREC_F32, stream=None):
+                 prec: int = DD_PREC_F32, stream=None, levels: int = 0):
+        """levels > 0: multiscale; the context starts on the (N / 2^levels)^2 layer and refine()
+        moves to the next finer one (self.N is the grid side of the current layer)."""
         import torch
-        self.N = int(mu.shape[0])
+        self.N = int(mu.shape[0]) >> int(levels)
+        self.levels = int(levels)
         self.s = int(s)
         self._stream = stream if stream is not None else torch.cuda.current_stream()
         mu64 = np.ascontiguousarray(mu.reshape(-1), dtype=np.float64)
         nu64 = np.ascontiguousarray(nu.reshape(-1), dtype=np.float64)
-        p = Params(self.N, self.s, float(trunc), int(prec), 0)
+        p = Params(int(mu.shape[0]), self.s, float(trunc), int(prec), int(levels))
         ctx = ctypes.c_void_p()
         dp = ctypes.POINTER(ctypes.c_double)
         i64p = ctypes.POINTER(ctypes.c_int64)
@@ -313,6 +316,11 @@ class DomDec:
         d = _struct_dict(st)
         d["status"] = status
         return d
+
+    def refine(self) -> None:
+        """Move to the next finer layer of a multiscale context (domdec_refine)."""
+        _check(lib().domdec_refine(self._ctx), self._ctx)
+        self.N *= 2
 
     def save(self) -> None:
         """Keep a copy of the mutable state (domdec_save)."""

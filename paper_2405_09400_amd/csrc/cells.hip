@@ -416,6 +416,74 @@ __global__ void fill_i32_kernel(int32_t* p, int n, int32_t v) {
 
 int grid_cells(int ncell) { return std::max(1, std::min(ncell, 4096)); }
 
+// ---- coarse-to-fine refinement of multiscale DD ------------------------------------------
+
+// Fine basic cell i' = (r', c') is a child of coarse basic cell (r'/2, c'/2); its Y box covers
+// the 2 x 2 children of every pixel of the parent's box.
+__global__ void refine_boxes_kernel(int nf, int nc, const int32_t* __restrict__ cbox,
+                                    int32_t* __restrict__ fbox, int64_t* __restrict__ fsize) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nf * nf) return;
+    const int p = (i / nf / 2) * nc + (i % nf) / 2;
+    const int w1 = cbox[4 * p + 2], w2 = cbox[4 * p + 3];
+    fbox[4 * i] = 2 * cbox[4 * p];
+    fbox[4 * i + 1] = 2 * cbox[4 * p + 1];
+    fbox[4 * i + 2] = 2 * w1;
+    fbox[4 * i + 3] = 2 * w2;
+    fsize[i] = 4 * (int64_t)w1 * w2;
+}
+
+// nu_i'(y') = (m_i' / m_i) nu_i(P(y')) nu_f(y') / nu_c(P(y')); one workgroup per fine cell.
+__global__ void __launch_bounds__(kT)
+    refine_values_kernel(int nf, int nc, int Nc, const int32_t* __restrict__ cbox,
+                         const int64_t* __restrict__ cbase, const double* __restrict__ cdata,
+                         const double* __restrict__ cm, const double* __restrict__ cnu,
+                         const int64_t* __restrict__ fbase, const double* __restrict__ fm,
+                         const double* __restrict__ fnu, double* __restrict__ fdata) {
+    const int Nf = 2 * Nc;
+    for (int i = blockIdx.x; i < nf * nf; i += gridDim.x) {
+        const int p = (i / nf / 2) * nc + (i % nf) / 2;
+        const int o1 = cbox[4 * p], o2 = cbox[4 * p + 1], w2 = cbox[4 * p + 3];
+        const int W2 = 2 * w2;
+        const int64_t n = fbase[i + 1] - fbase[i];
+        const double share = fm[i] / cm[p];
+        for (int64_t e = threadIdx.x; e < n; e += blockDim.x) {
+            const int r = (int)(e / W2), q = (int)(e - (int64_t)r * W2);
+            const int c1 = o1 + (r >> 1), c2 = o2 + (q >> 1);
+            const double v = cdata[cbase[p] + (int64_t)(r >> 1) * w2 + (q >> 1)];
+            const double nc_p = cnu[(int64_t)c1 * Nc + c2];
+            const double nf_y = fnu[(int64_t)(2 * o1 + r) * Nf + (2 * o2 + q)];
+            fdata[fbase[i] + e] = nc_p > 0.0 ? share * v * (nf_y / nc_p) : 0.0;
+        }
+    }
+}
+
+// The fine X potentials of one partition in units of eps: bilinear interpolation of the
+// coarse stitched potential (same units) at the fine pixel centres, fine pixel k at coarse
+// index (k - 1/2) / 2, extrapolated linearly beyond the outermost coarse centres; padding
+// pixels outside the grid get 0.
+__global__ void refine_alpha_kernel(int ncell, int xside, int Nc, const int32_t* __restrict__ xorig,
+                                    const double* __restrict__ fc, double* __restrict__ a) {
+    const int N2 = xside * xside, Nf = 2 * Nc;
+    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < (int64_t)ncell * N2;
+         t += (int64_t)gridDim.x * blockDim.x) {
+        const int J = (int)(t / N2), il = (int)(t - (int64_t)J * N2);
+        const int k1 = xorig[2 * J] + il / xside, k2 = xorig[2 * J + 1] + il % xside;
+        if (k1 < 0 || k1 >= Nf || k2 < 0 || k2 >= Nf) {
+            a[t] = 0.0;
+            continue;
+        }
+        const double u1 = (k1 - 0.5) * 0.5, u2 = (k2 - 0.5) * 0.5;
+        const int a1 = min(max((int)floor(u1), 0), Nc - 2), a2 = min(max((int)floor(u2), 0), Nc - 2);
+        const double t1 = u1 - a1, t2 = u2 - a2;
+        const double* r0 = fc + (int64_t)a1 * Nc;
+        const double* r1 = r0 + Nc;
+        const double lo = (1.0 - t1) * r0[a2] + t1 * r1[a2];
+        const double hi = (1.0 - t1) * r0[a2 + 1] + t1 * r1[a2 + 1];
+        a[t] = (1.0 - t2) * lo + t2 * hi;
+    }
+}
+
 }  // namespace
 
 void launch_fill_i32(int32_t* p, int n, int32_t v, hipStream_t st) {
@@ -476,5 +544,24 @@ void launch_compact(const PartDev& P, const CompDev& C, const double* tmp, doubl
                                                        tmp, trunc, nbox, nbase, flags, ndata);
 }
 
+
+void launch_refine_boxes(int nf, int nc, const int32_t* cbox, int32_t* fbox, int64_t* fsize,
+                         hipStream_t st) {
+    refine_boxes_kernel<<<(nf * nf + kT - 1) / kT, kT, 0, st>>>(nf, nc, cbox, fbox, fsize);
+}
+
+void launch_refine_values(int nf, int nc, int Nc, const BoxSet& C, const double* cm,
+                          const double* cnu, const int64_t* fbase, const double* fm,
+                          const double* fnu, double* fdata, hipStream_t st) {
+    refine_values_kernel<<<grid_cells(nf * nf), kT, 0, st>>>(nf, nc, Nc, C.box, C.base, C.data,
+                                                             cm, cnu, fbase, fm, fnu, fdata);
+}
+
+void launch_refine_alpha(const PartDev& P, int xside, int Nc, const double* fc, double* a,
+                         hipStream_t st) {
+    const int64_t n = (int64_t)P.ncell * xside * xside;
+    refine_alpha_kernel<<<(int)std::min<int64_t>((n + kT - 1) / kT, 8192), kT, 0, st>>>(
+        P.ncell, xside, Nc, P.xorig, fc, a);
+}
 
 }  // namespace dd

@@ -57,4 +57,15 @@ void launch_compact(const PartDev& P, const CompDev& C, const double* tmp, doubl
                     const int32_t* nbox, const int64_t* nbase, const int32_t* flags,
                     double* ndata, hipStream_t st);
 
+// Coarse-to-fine refinement (multiscale DD): fine basic-cell boxes and sizes from the coarse
+// boxes (nf, nc basic cells per side), the refined values, and the interpolated potentials
+// of one partition (fc: the coarse stitched potential on the Nc x Nc grid).
+void launch_refine_boxes(int nf, int nc, const int32_t* cbox, int32_t* fbox, int64_t* fsize,
+                         hipStream_t st);
+void launch_refine_values(int nf, int nc, int Nc, const BoxSet& C, const double* cm,
+                          const double* cnu, const int64_t* fbase, const double* fm,
+                          const double* fnu, double* fdata, hipStream_t st);
+void launch_refine_alpha(const PartDev& P, int xside, int Nc, const double* fc, double* a,
+                         hipStream_t st);
+
 }  // namespace dd

@@ -119,52 +119,23 @@ void dd_ctx_release(dd_ctx* c) {
     flow_release(c);
 }
 
-extern "C" dd_status domdec_init(const dd_params* prm, const double* mu, const double* nu,
-                                 int64_t n_init, const int64_t* init_x, const int64_t* init_y,
-                                 const double* init_m, void* stream, dd_ctx** out) {
-    if (out) *out = nullptr;
-    if (!prm || !mu || !nu || !out) return fail(nullptr, DD_EINVAL, "domdec_init: null argument");
-    const int N = prm->n, s = prm->s;
-    if (N < 2 || s < 1 || s > 8 || N % (2 * s) != 0 || prm->reserved != 0 ||
-        (prm->prec != DD_PREC_F32 && prm->prec != DD_PREC_F64) || !(prm->trunc >= 0.0))
-        return fail(nullptr, DD_EINVAL,
-                    "domdec_init: need N % (2s) == 0, 1 <= s <= 8, prec F32|F64, trunc >= 0");
-    if (n_init < 0 || (n_init > 0 && (!init_x || !init_y || !init_m)))
-        return fail(nullptr, DD_EINVAL, "domdec_init: bad initial coupling arrays");
-    const int64_t NN = (int64_t)N * N;
-    double smu = 0, snu = 0;
-    for (int64_t k = 0; k < NN; ++k) {
-        if (!(mu[k] >= 0.0) || !(nu[k] >= 0.0) || !std::isfinite(mu[k]) || !std::isfinite(nu[k]))
-            return fail(nullptr, DD_EINVAL, "domdec_init: masses must be finite and >= 0");
-        smu += mu[k];
-        snu += nu[k];
-    }
-    if (std::fabs(smu - 1.0) > 1e-12 || std::fabs(snu - 1.0) > 1e-12)
-        return fail(nullptr, DD_EINVAL, "domdec_init: mu and nu must each sum to 1 (within 1e-12)");
+namespace {
 
-    dd_ctx* c = new dd_ctx();
+// Everything of a layer but its coupling: grid, basic-cell masses, both partitions (members,
+// X origins, log mu on the padded blocks, zero potentials), mu, nu and log nu on the device,
+// and the work buffers sized by the layer.  c->s, prec, trunc and st are set by the caller.
+Status setup_layer(dd_ctx* c, int N, const double* mu, const double* nu) {
+    Status st;
+    const int s = c->s;
     c->N = N;
-    c->s = s;
     c->n = N / s;
     c->nI = c->n * c->n;
     c->AS = 2 * s;
     c->h = 1.0 / N;
-    c->trunc = prm->trunc;
-    c->prec = prm->prec;
-    c->st = reinterpret_cast<hipStream_t>(stream);
-    Status st;
     const hipStream_t hs = c->st;
-    auto bail = [&](const Status& e) {
-        dd_ctx_release(c);
-        delete c;
-        return fail(nullptr, e);
-    };
+    const int64_t NN = (int64_t)N * N;
     for (auto& e : c->ev)
-        if (hipEventCreate(&e) != hipSuccess) {
-            st.code = DD_EDEVICE;
-            st.msg = "domdec_init: hipEventCreate failed";
-            return bail(st);
-        }
+        if (!e) DD_HIP(hipEventCreate(&e), st);
     const int n = c->n, AS = c->AS;
     // basic cell masses (pixel order inside the block, row-major)
     c->m.assign(c->nI, 0.0);
@@ -177,7 +148,7 @@ extern "C" dd_status domdec_init(const dd_params* prm, const double* mu, const d
             if (!(t > 0.0)) {
                 st.code = DD_EINVAL;
                 st.msg = "domdec_init: every basic cell needs positive mass";
-                return bail(st);
+                return st;
             }
         }
     // partitions
@@ -208,18 +179,45 @@ extern "C" dd_status domdec_init(const dd_params* prm, const double* mu, const d
         c->part[q].ncell = nc * nc;
         c->pmembers[q] = mem;
         c->pxorig[q] = xo;
-        if (upload(c->part[q].members, mem, hs, st).code) return bail(st);
-        if (upload(c->part[q].xorig, xo, hs, st).code) return bail(st);
+        if (upload(c->part[q].members, mem, hs, st).code) return st;
+        if (upload(c->part[q].xorig, xo, hs, st).code) return st;
         double* plm = nullptr;
-        if (upload(plm, lm, hs, st).code) return bail(st);
+        if (upload(plm, lm, hs, st).code) return st;
         c->d_logmu[q] = plm;
         double* pa = nullptr;
-        if (upload(pa, std::vector<double>(lm.size(), 0.0), hs, st).code) return bail(st);
+        if (upload(pa, std::vector<double>(lm.size(), 0.0), hs, st).code) return st;
         c->d_a[q] = pa;
         if (upload(c->d_gst[q], std::vector<int32_t>(2 * (size_t)nc * nc, 0), hs, st).code)
-            return bail(st);
+            return st;
     }
-    // initial basic-cell Y-marginals in bounding-box form
+    std::vector<double> vmu(mu, mu + NN), vnu(nu, nu + NN), lnu(NN);
+    for (int64_t k = 0; k < NN; ++k) lnu[k] = nu[k] > 0 ? std::log(nu[k]) : -INFINITY;
+    if (upload(c->d_mu, vmu, hs, st).code || upload(c->d_nu, vnu, hs, st).code ||
+        upload(c->d_lognu_glob, lnu, hs, st).code || upload(c->d_m, c->m, hs, st).code)
+        return st;
+    const int mc = std::max(c->part[0].ncell, c->part[1].ncell);
+    if (alloc(c->S.box, 4 * (size_t)c->nI, st).code || alloc(c->S.base, c->nI + 1, st).code ||
+        alloc(c->S2.box, 4 * (size_t)c->nI, st).code || alloc(c->S2.base, c->nI + 1, st).code ||
+        alloc(c->C.dims, 2 * (size_t)mc, st).code || alloc(c->C.orig, 2 * (size_t)mc, st).code ||
+        alloc(c->C.shift, 2 * (size_t)mc, st).code || alloc(c->C.gofs, 2 * (size_t)mc, st).code ||
+        alloc(c->C.size, mc, st).code || alloc(c->C.base, mc + 1, st).code ||
+        alloc(c->C.info, 8, st).code || alloc(c->d_py2, c->nI, st).code ||
+        alloc(c->d_nsize, c->nI, st).code || alloc(c->d_flags, c->nI + 1, st).code ||
+        alloc(c->d_iters, mc, st).code || alloc(c->d_cerr, mc, st).code ||
+        alloc(c->d_scratch, std::max<int64_t>(NN, c->nI), st).code ||
+        alloc(c->d_cell_out, 4 * (size_t)mc, st).code ||
+        alloc(c->d_basic_out, 3 * (size_t)c->nI, st).code || alloc(c->d_eval, 8, st).code)
+        return st;
+    return st;
+}
+
+// The layer's basic-cell Y-marginals in bounding-box form from a host coupling: the product
+// coupling nu_i = m_i nu (n_init == 0), or a sparse (x, y, mass) list with marginals mu, nu.
+Status boxes_from_host(dd_ctx* c, const double* mu, const double* nu, int64_t n_init,
+                       const int64_t* init_x, const int64_t* init_y, const double* init_m) {
+    Status st;
+    const int N = c->N, s = c->s, n = c->n;
+    const int64_t NN = (int64_t)N * N;
     std::vector<int32_t> box(4 * (size_t)c->nI);
     std::vector<int64_t> base(c->nI + 1, 0);
     std::vector<double> data;
@@ -237,7 +235,7 @@ extern "C" dd_status domdec_init(const dd_params* prm, const double* mu, const d
         if ((double)w1 * w2 * c->nI > 4.0e8) {
             st.code = DD_ENOMEM;
             st.msg = "domdec_init: the product coupling is too large here; pass a sparse init";
-            return bail(st);
+            return st;
         }
         data.resize((size_t)(w1 * w2 * c->nI));
         for (int i = 0; i < c->nI; ++i) {
@@ -259,7 +257,7 @@ extern "C" dd_status domdec_init(const dd_params* prm, const double* mu, const d
             if (x < 0 || x >= NN || y < 0 || y >= NN || !(init_m[e] >= 0.0)) {
                 st.code = DD_EINVAL;
                 st.msg = "domdec_init: initial coupling entry out of range or negative";
-                return bail(st);
+                return st;
             }
             px[x] += init_m[e];
             py[y] += init_m[e];
@@ -271,7 +269,7 @@ extern "C" dd_status domdec_init(const dd_params* prm, const double* mu, const d
             if (std::fabs(px[k] - mu[k]) > 1e-12 || std::fabs(py[k] - nu[k]) > 1e-12) {
                 st.code = DD_EINVAL;
                 st.msg = "domdec_init: the initial coupling's marginals differ from mu, nu";
-                return bail(st);
+                return st;
             }
         for (int i = 0; i < c->nI; ++i) cnt[i + 1] += cnt[i];
         std::vector<int64_t> order(n_init), fill(cnt.begin(), cnt.end() - 1);
@@ -289,7 +287,7 @@ extern "C" dd_status domdec_init(const dd_params* prm, const double* mu, const d
             if (hi1 < 0) {
                 st.code = DD_EINVAL;
                 st.msg = "domdec_init: a basic cell has no mass in the initial coupling";
-                return bail(st);
+                return st;
             }
             const int w1 = hi1 - lo1 + 1, w2 = hi2 - lo2 + 1;
             box[4 * i] = lo1;
@@ -307,32 +305,197 @@ extern "C" dd_status domdec_init(const dd_params* prm, const double* mu, const d
                     init_m[e];
             }
     }
-    std::vector<double> vmu(mu, mu + NN), vnu(nu, nu + NN), lnu(NN);
-    for (int64_t k = 0; k < NN; ++k) lnu[k] = nu[k] > 0 ? std::log(nu[k]) : -INFINITY;
-    if (upload(c->d_mu, vmu, hs, st).code || upload(c->d_nu, vnu, hs, st).code ||
-        upload(c->d_lognu_glob, lnu, hs, st).code || upload(c->d_m, c->m, hs, st).code ||
-        upload(c->S.box, box, hs, st).code || upload(c->S.base, base, hs, st).code ||
-        upload(c->S.data, data, hs, st).code)
-        return bail(st);
+    const hipStream_t hs = c->st;
+    if (hipMemcpyAsync(c->S.box, box.data(), box.size() * 4, hipMemcpyHostToDevice, hs) !=
+            hipSuccess ||
+        hipMemcpyAsync(c->S.base, base.data(), base.size() * 8, hipMemcpyHostToDevice, hs) !=
+            hipSuccess) {
+        st.code = DD_EDEVICE;
+        st.msg = "domdec_init: copying the initial coupling failed";
+        return st;
+    }
+    if (upload(c->S.data, data, hs, st).code) return st;
     c->S.cap = std::max<size_t>(data.size(), 1);
-    const int mc = std::max(c->part[0].ncell, c->part[1].ncell);
-    if (alloc(c->S2.box, 4 * (size_t)c->nI, st).code || alloc(c->S2.base, c->nI + 1, st).code ||
-        alloc(c->C.dims, 2 * (size_t)mc, st).code || alloc(c->C.orig, 2 * (size_t)mc, st).code ||
-        alloc(c->C.shift, 2 * (size_t)mc, st).code || alloc(c->C.gofs, 2 * (size_t)mc, st).code ||
-        alloc(c->C.size, mc, st).code || alloc(c->C.base, mc + 1, st).code ||
-        alloc(c->C.info, 8, st).code || alloc(c->d_py2, c->nI, st).code ||
-        alloc(c->d_nsize, c->nI, st).code || alloc(c->d_flags, c->nI + 1, st).code ||
-        alloc(c->d_iters, mc, st).code || alloc(c->d_cerr, mc, st).code ||
-        alloc(c->d_scratch, std::max<int64_t>(NN, c->nI), st).code ||
-        alloc(c->d_cell_out, 4 * (size_t)mc, st).code ||
-        alloc(c->d_basic_out, 3 * (size_t)c->nI, st).code || alloc(c->d_eval, 8, st).code)
-        return bail(st);
-    if (hipStreamSynchronize(hs) != hipSuccess) {
+    DD_HIP(hipStreamSynchronize(hs), st);
+    return st;
+}
+
+// 2 x 2 block sums of an N x N array.
+std::vector<double> coarsen(const std::vector<double>& a, int N) {
+    const int M = N / 2;
+    std::vector<double> out((size_t)M * M);
+    for (int r = 0; r < M; ++r)
+        for (int q = 0; q < M; ++q)
+            out[(size_t)r * M + q] = a[(size_t)(2 * r) * N + 2 * q] + a[(size_t)(2 * r) * N + 2 * q + 1] +
+                                     a[(size_t)(2 * r + 1) * N + 2 * q] +
+                                     a[(size_t)(2 * r + 1) * N + 2 * q + 1];
+    return out;
+}
+
+}  // namespace
+
+extern "C" dd_status domdec_init(const dd_params* prm, const double* mu, const double* nu,
+                                 int64_t n_init, const int64_t* init_x, const int64_t* init_y,
+                                 const double* init_m, void* stream, dd_ctx** out) {
+    if (out) *out = nullptr;
+    if (!prm || !mu || !nu || !out) return fail(nullptr, DD_EINVAL, "domdec_init: null argument");
+    const int N = prm->n, s = prm->s, L = prm->levels;
+    if (N < 2 || s < 1 || s > 8 || N % (2 * s) != 0 ||
+        (prm->prec != DD_PREC_F32 && prm->prec != DD_PREC_F64) || !(prm->trunc >= 0.0))
+        return fail(nullptr, DD_EINVAL,
+                    "domdec_init: need N % (2s) == 0, 1 <= s <= 8, prec F32|F64, trunc >= 0");
+    if (L < 0 || L > 12 || N % (1 << L) != 0 || (N >> L) % (2 * s) != 0)
+        return fail(nullptr, DD_EINVAL,
+                    "domdec_init: levels must be >= 0 with N / 2^levels a multiple of 2s");
+    if (n_init < 0 || (n_init > 0 && (!init_x || !init_y || !init_m)))
+        return fail(nullptr, DD_EINVAL, "domdec_init: bad initial coupling arrays");
+    const int64_t NN = (int64_t)N * N;
+    double smu = 0, snu = 0;
+    for (int64_t k = 0; k < NN; ++k) {
+        if (!(mu[k] >= 0.0) || !(nu[k] >= 0.0) || !std::isfinite(mu[k]) || !std::isfinite(nu[k]))
+            return fail(nullptr, DD_EINVAL, "domdec_init: masses must be finite and >= 0");
+        smu += mu[k];
+        snu += nu[k];
+    }
+    if (std::fabs(smu - 1.0) > 1e-12 || std::fabs(snu - 1.0) > 1e-12)
+        return fail(nullptr, DD_EINVAL, "domdec_init: mu and nu must each sum to 1 (within 1e-12)");
+
+    dd_ctx* c = new dd_ctx();
+    c->s = s;
+    c->trunc = prm->trunc;
+    c->prec = prm->prec;
+    c->st = reinterpret_cast<hipStream_t>(stream);
+    c->levels = L;
+    c->layer = 0;
+    // the layers: 2 x 2 block sums, coarsest first
+    c->pyr_mu.assign(L + 1, {});
+    c->pyr_nu.assign(L + 1, {});
+    c->pyr_mu[L].assign(mu, mu + NN);
+    c->pyr_nu[L].assign(nu, nu + NN);
+    for (int l = L; l > 0; --l) {
+        c->pyr_mu[l - 1] = coarsen(c->pyr_mu[l], N >> (L - l));
+        c->pyr_nu[l - 1] = coarsen(c->pyr_nu[l], N >> (L - l));
+    }
+    const int Nc = N >> L;
+    const double* cmu = c->pyr_mu[0].data();
+    const double* cnu = c->pyr_nu[0].data();
+    Status st = setup_layer(c, Nc, cmu, cnu);
+    if (!st.code) {
+        if (L == 0 || n_init == 0) {
+            st = boxes_from_host(c, cmu, cnu, n_init, init_x, init_y, init_m);
+        } else {
+            // the coupling on the finest grid, summed over the blocks of the coarsest layer
+            std::vector<double> px(NN, 0.0), py(NN, 0.0);
+            std::vector<int64_t> cx(n_init), cy(n_init);
+            bool ok = true;
+            for (int64_t e = 0; e < n_init && ok; ++e) {
+                const int64_t x = init_x[e], y = init_y[e];
+                if (x < 0 || x >= NN || y < 0 || y >= NN || !(init_m[e] >= 0.0)) {
+                    ok = false;
+                    break;
+                }
+                px[x] += init_m[e];
+                py[y] += init_m[e];
+                cx[e] = ((x / N) >> L) * Nc + ((x % N) >> L);
+                cy[e] = ((y / N) >> L) * Nc + ((y % N) >> L);
+            }
+            for (int64_t k = 0; k < NN && ok; ++k)
+                ok = std::fabs(px[k] - mu[k]) <= 1e-12 && std::fabs(py[k] - nu[k]) <= 1e-12;
+            if (!ok) {
+                st.code = DD_EINVAL;
+                st.msg = "domdec_init: initial coupling out of range, negative, or with marginals "
+                         "other than mu, nu";
+            } else {
+                st = boxes_from_host(c, cmu, cnu, n_init, cx.data(), cy.data(), init_m);
+            }
+        }
+    }
+    if (!st.code && hipStreamSynchronize(c->st) != hipSuccess) {
         st.code = DD_EDEVICE;
         st.msg = "domdec_init: stream synchronisation failed";
-        return bail(st);
+    }
+    if (st.code) {
+        dd_ctx_release(c);
+        delete c;
+        return fail(nullptr, st);
     }
     *out = c;
+    return DD_OK;
+}
+
+extern "C" dd_status domdec_refine(dd_ctx* c) {
+    if (!c) return fail(c, DD_EINVAL, "domdec_refine: null context");
+    if (c->layer >= c->levels)
+        return fail(c, DD_ESTATE, "domdec_refine: already on the finest layer");
+    if (!c->visited[0] || !c->visited[1])
+        return fail(c, DD_ESTATE, "domdec_refine: both partitions must be iterated on this layer");
+    const hipStream_t hs = c->st;
+    // the stitched potential of this layer, in units of eps of the A partition's last solve
+    DualArgs a;
+    a.N = c->N;
+    a.s = c->s;
+    a.xside = c->AS;
+    for (int q = 0; q < 2; ++q) {
+        a.ncell[q] = c->part[q].ncell;
+        a.members[q] = c->pmembers[q].data();
+        a.xorig[q] = c->part[q].xorig;
+        a.a[q] = c->d_a[q];
+        a.gst[q] = c->d_gst[q];
+        a.kappa[q] = c->kappa_a[q];
+    }
+    a.kappa_eval = c->kappa_a[0];
+    a.eps = a.kappa_eval * c->h * c->h;
+    a.mu = c->d_mu;
+    a.nu = c->d_nu;
+    const double* fdag = nullptr;
+    Status st = stitched_alpha(a, c->dual, hs, &fdag);
+    if (st.code) return fail(c, st);
+    // the finer layer, its coupling and its potentials
+    dd_ctx* f = new dd_ctx();
+    f->s = c->s;
+    f->trunc = c->trunc;
+    f->prec = c->prec;
+    f->st = hs;
+    f->levels = c->levels;
+    f->layer = c->layer + 1;
+    const int Nc = c->N, Nf = 2 * Nc;
+    st = setup_layer(f, Nf, c->pyr_mu[f->layer].data(), c->pyr_nu[f->layer].data());
+    int64_t total = 0;
+    if (!st.code) {
+        launch_refine_boxes(f->n, c->n, c->S.box, f->S.box, f->d_nsize, hs);
+        launch_scan(f->d_nsize, f->S.base, f->nI, hs);
+        if (hipMemcpyAsync(&total, f->S.base + f->nI, sizeof total, hipMemcpyDeviceToHost, hs) !=
+                hipSuccess ||
+            hipStreamSynchronize(hs) != hipSuccess) {
+            st.code = DD_EDEVICE;
+            st.msg = "domdec_refine: reading the refined sizes failed";
+        }
+    }
+    if (!st.code && !grow(f->S.data, f->S.cap, (size_t)std::max<int64_t>(total, 1), st).code) {
+        launch_refine_values(f->n, c->n, Nc, c->S, c->d_m, c->d_nu, f->S.base, f->d_m, f->d_nu,
+                             f->S.data, hs);
+        const double kappa_f = a.kappa_eval * 4.0;  // the same eps in units of the finer h^2
+        for (int q = 0; q < 2; ++q) {
+            launch_refine_alpha(f->part[q], f->AS, Nc, fdag, f->d_a[q], hs);
+            f->visited[q] = true;
+            f->kappa_a[q] = kappa_f;
+        }
+        if (hipStreamSynchronize(hs) != hipSuccess || hipGetLastError() != hipSuccess) {
+            st.code = DD_EDEVICE;
+            st.msg = "domdec_refine: a kernel failed";
+        }
+    }
+    if (st.code) {
+        dd_ctx_release(f);
+        delete f;
+        return fail(c, st);
+    }
+    f->pyr_mu = std::move(c->pyr_mu);
+    f->pyr_nu = std::move(c->pyr_nu);
+    f->net = c->net;
+    std::swap(*c, *f);
+    dd_ctx_release(f);  // the coarse layer
+    delete f;
     return DD_OK;
 }
 
@@ -442,6 +605,7 @@ static dd_status iterate_impl(dd_ctx* c, int p, double eps, const dd_sinkhorn_op
         s.partition = p;
         s.max_w1 = mw1;
         s.max_w2 = mw2;
+        s.grid_n = c->N;
         s.nu_entries = ntot;
         s.comp_entries = total;
         float t = 0.f;

@@ -12,7 +12,11 @@ struct FlowState;
 struct dd_net;
 
 struct dd_ctx {
-    // problem
+    // multiscale: coarser layers below the finest, the current layer (0 = coarsest) and the
+    // marginals of every layer (host, [0] coarsest ... [levels] finest)
+    int levels = 0, layer = 0;
+    std::vector<std::vector<double>> pyr_mu, pyr_nu;
+    // problem (of the current layer)
     int N = 0, s = 0, n = 0, nI = 0, AS = 0, prec = DD_PREC_F32;
     double h = 0.0, trunc = 1e-15;
     hipStream_t st = nullptr;

@@ -137,7 +137,7 @@ __global__ void __launch_bounds__(kT)
 
 }  // namespace
 
-Status stitched_dual(const DualArgs& a, DualWork& w, hipStream_t st, double* D) {
+Status stitched_alpha(const DualArgs& a, DualWork& w, hipStream_t st, const double** fdag_out) {
     Status S;
     const int N = a.N, s = a.s, n = N / s;
     const int64_t N2 = (int64_t)N * N;
@@ -154,7 +154,6 @@ Status stitched_dual(const DualArgs& a, DualWork& w, hipStream_t st, double* D) 
     double* fB = w.buf + N2;
     double* fdag = w.buf + 2 * N2;
     double* wv = w.buf + 3 * N2;
-    double* T = w.buf + 4 * N2;
     const double two_invk[2] = {2.0 / a.kappa[0], 2.0 / a.kappa[1]};
     double* fx[2] = {fA, fB};
     for (int q = 0; q < 2; ++q)
@@ -211,6 +210,21 @@ Status stitched_dual(const DualArgs& a, DualWork& w, hipStream_t st, double* D) 
     DD_HIP(hipMemcpyAsync(w.sA, sA.data(), nA * sizeof(double), hipMemcpyHostToDevice, st), S);
     alpha_dag_kernel<<<grid_n(N2 / kT + 1, 8192), kT, 0, st>>>(n, s, N, a.mu, fA, w.own, w.sA,
                                                               fdag, wv);
+    *fdag_out = fdag;
+    return S;
+}
+
+Status stitched_dual(const DualArgs& a, DualWork& w, hipStream_t st, double* D) {
+    const double* fdag_c = nullptr;
+    Status S = stitched_alpha(a, w, st, &fdag_c);
+    if (S.code) return S;
+    const int N = a.N;
+    const int64_t N2 = (int64_t)N * N;
+    constexpr int kParts = 1024;
+    double* fB = w.buf + N2;
+    double* fdag = w.buf + 2 * N2;
+    double* wv = w.buf + 3 * N2;
+    double* T = w.buf + 4 * N2;
     const double invk = 1.0 / a.kappa_eval;
     gy_pass1_kernel<<<grid_n(N2 / kT + 1, 8192), kT, 0, st>>>(N, wv, invk, T);
     double* g = fB;  // fB is no longer needed

@@ -26,6 +26,9 @@ struct DualWork {
     double* part = nullptr;  // partial sums
 };
 
+// alpha+ / eps_eval on every pixel (device [N*N], inside w): the A cells' potentials with the
+// breadth-first offsets; valid until the next call on w.
+Status stitched_alpha(const DualArgs& a, DualWork& w, hipStream_t st, const double** fdag);
 // D = eps (<alpha+/eps, mu> + <beta+/eps, nu>) of the stitched dual point.
 Status stitched_dual(const DualArgs& a, DualWork& w, hipStream_t st, double* D);
 void dual_release(DualWork& w);

@@ -164,6 +164,8 @@ def workload(name: str, seed: int = 0, N: Optional[int] = None) -> Workload:
                 init (id, T)_# mu; hybrid DD + flow schedule.
     mix512    : the mix256 generator at 512x512 (s=4).
     mix1024   : 1024x1024, 16 blobs + 1e-4 floor, s=4, eps down to h^2, KR init.
+    ms256, ms512, ms1024: the mixN marginals on a coarse-to-fine schedule (see the code); the
+                extra fields hold the number of coarser layers and their eps stages.
     `N` overrides the grid size (used by tests to shrink a workload).
     """
     if name == "small32":
@@ -179,6 +181,14 @@ def workload(name: str, seed: int = 0, N: Optional[int] = None) -> Workload:
         ks = [float(k) for k in _kappa_schedule(64)]
         its = [4] * (len(ks) - 1) + [20]
         return Workload(name, n, 4, mu, nu, ks, its, kr_coupling(mu, nu), seed)
+    if name in ("ms256", "ms512", "ms1024"):
+        # the mixture workloads of the same size and seed, solved coarse to fine: layers of
+        # 2 x 2 block sums down to 32 x 32 (product coupling there), eps = 2h^2, h^2, h^2/2 on
+        # each coarser layer (h its pixel size), then 2h^2 and h^2 on the finest
+        base = workload("mix" + name[2:], seed=seed, N=N)
+        levels = int(round(math.log2(base.N // 32)))
+        return Workload(name, base.N, base.s, base.mu, base.nu, [2.0, 1.0], [4, 20], None, seed,
+                        {"levels": levels, "layer_kappas": [2.0, 1.0, 0.5], "layer_iters": 4})
     if name == "flow512":
         n = N or 512
         mu = gaussian_mixture(n, 8, 1e-4, seed)
@@ -188,4 +198,4 @@ def workload(name: str, seed: int = 0, N: Optional[int] = None) -> Workload:
     raise KeyError(name)
 
 
-WORKLOADS = ("small32", "mix256", "flow512", "mix512", "mix1024")
+WORKLOADS = ("small32", "mix256", "flow512", "mix512", "mix1024", "ms256", "ms512", "ms1024")
