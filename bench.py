@@ -1,12 +1,14 @@
 """Benchmark: batched cell-Sinkhorn inside domain decomposition on one MI355X.
 
-Workload (mix512): mu, nu = seeded 8-blob Gaussian mixtures (+1e-4 floor) on 512x512,
-basic cells 4x4 (16,384 basic cells; 4,096 A / 4,225 B composite problems), initial
-coupling = Knothe-Rosenblatt.  Untimed set-up: eps-scaling kappa = eps/h^2 = 64, 32, ..., 2
-with 4 DD iterations per stage.  Timed: K domain-decomposition iterations (alternating A/B)
-at kappa = 1 (eps = h^2), Sinkhorn tolerance 1e-5 on the X-marginal (App. A.2.1 rule),
-warm-started from the previous visit of the partition.  A step = one DD iteration =
-BasicToComposite + cell Sinkhorn to tolerance + CompositeToBasic + balancing + truncation.
+Workload (default ms512): mu, nu = seeded 8-blob Gaussian mixtures (+1e-4 floor) on 512x512,
+basic cells 4x4 (16,384 basic cells; 4,096 A / 4,225 B composite problems).  Untimed set-up:
+multiscale domain decomposition from the 8x8 layer (2x2 block sums) up to 512x512, eps =
+2h^2, h^2, h^2/2 per layer, then 2h^2 on the finest layer (8 half-iterations per stage).  Timed: K domain-decomposition
+half-iterations (alternating A/B) at eps = h^2, Sinkhorn tolerance 1e-5 on the X-marginal
+(App. A.2.1 batch rule), warm-started from the previous visit of the partition.  A step = one
+half-iteration = BasicToComposite + cell Sinkhorn to tolerance + CompositeToBasic + balancing
++ truncation.  (--workload mix512: the same marginals from a Knothe-Rosenblatt start with the
+single-scale eps schedule 64h^2 ... 2h^2.)
 
 value  = algorithmic LSE bytes of the timed steps / wall time of the timed steps (GB/s);
          12 (|X_J| + W1 W2) bytes per cell per Sinkhorn iteration (read f, log nu_J, write g;
@@ -14,8 +16,14 @@ value  = algorithmic LSE bytes of the timed steps / wall time of the timed steps
 roofline: the Sinkhorn kernel does one multiply-add per LSE term (exponentials per input
          and output only): achieved = LSE terms / kernel time, peak = the FP32 vector rate
          157.3 TFLOP/s / 2 FLOP per term.
-cpu_baseline: the oracle's dense float64 cell solver on a bounded sample of the same
-         workload's cell problems, on the host's cores.
+cpu_baseline: the oracle's dense float64 cell solver on a random sample of the composite cells
+         of one more half-iteration of the same trajectory, from the same start and for the
+         same number of iterations as the GPU (single thread and all host threads, medians of
+         5 runs); the same solve gives the GPU result's error against the oracle.
+time_to_tol: the replay protocol (8 consecutive states; zero, previous-iterate and learned
+         starts, the same tolerance and stop rule).
+f64, mix1024 / ms1024, full_solve: the same step in float64, the 1024^2 workload, and the whole
+         multiscale solve down to eps = h^2/4 (the paper's schedule).
 """
 from __future__ import annotations
 
@@ -44,12 +52,12 @@ WORKLOAD_TEXT = {
               "eps-scaling 64..2 untimed, timed DD iterations at eps=h^2",
     "mix1024": "mix1024: {N}x{N} 16-blob Gaussian mixtures + 1e-4 floor, s={s}, KR init, "
                "eps-scaling 64..2 untimed, timed DD iterations at eps=h^2",
-    "ms512": "ms512: the mix512 marginals solved coarse to fine (untimed): layers 32^2 ... 256^2 "
-             "of 2x2 block sums, eps = 2h^2, h^2, h^2/2 per layer (4 DD iterations each), then "
-             "512^2 at 2h^2; timed DD iterations at eps=h^2, s={s}",
-    "ms1024": "ms1024: the mix1024 marginals solved coarse to fine (untimed): layers 32^2 ... "
-              "512^2, eps = 2h^2, h^2, h^2/2 per layer (4 DD iterations each), then 1024^2 at "
-              "2h^2; timed DD iterations at eps=h^2, s={s}",
+    "ms512": "ms512: the mix512 marginals solved coarse to fine (untimed): layers 8^2 ... 256^2 "
+             "of 2x2 block sums, eps = 2h^2, h^2, h^2/2 per layer (8 DD half-iterations each), "
+             "then 512^2 at 2h^2 (8); timed DD half-iterations at eps=h^2, s={s}",
+    "ms1024": "ms1024: the mix1024 marginals solved coarse to fine (untimed): layers 8^2 ... "
+              "512^2, eps = 2h^2, h^2, h^2/2 per layer (8 DD half-iterations each), then 1024^2 "
+              "at 2h^2 (8); timed DD half-iterations at eps=h^2, s={s}",
     "flow512": "flow512: {N}x{N}, mu 8-blob mixture, nu = mu rotated 30 deg, contracted 0.36, "
                "shifted (0.25, 0); s={s}; map init; eps=h^2; hybrid A, B, flow update",
 }
@@ -480,7 +488,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="mix512")
+    ap.add_argument("--workload", default="ms512")
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--tol", type=float, default=1e-5)
     ap.add_argument("--max-iter", type=int, default=20000)
@@ -535,23 +543,74 @@ def main():
 
     line = measure(args, args.workload, args.prec, args.steps, args.warmup,
                    replay=0 if args.no_compare else args.replay, cpu=not args.no_cpu_baseline)
-    if not args.no_extra and args.workload == "mix512":
+    larger = {"mix512": "mix1024", "ms512": "ms1024"}
+    if not args.no_extra and args.workload in larger:
         # the same step in the paper's arithmetic (float64 throughout), and the 1024^2 workload
-        sub = measure(args, "mix512", "f64", args.extra_steps, 1, replay=0, cpu=False)
+        sub = measure(args, args.workload, "f64", args.extra_steps, 1, replay=0, cpu=False)
         line["f64"] = {key: sub[key] for key in ("value", "unit", "ms_per_step", "ms_per_step_median",
                                                  "dtype", "roofline")}
         line["f64"]["detail"] = {key: sub["detail"][key] for key in
                                  ("sinkhorn_iters", "sinkhorn_ms_per_step", "x_marginal_l1",
                                   "y_marginal_l1", "primal", "dual", "pd_gap")}
-        sub = measure(args, "mix1024", args.prec, args.extra_steps, 1, replay=0, cpu=False)
-        line["mix1024"] = {key: sub[key] for key in ("value", "unit", "ms_per_step",
-                                                     "ms_per_step_median", "dtype", "roofline")}
-        line["mix1024"]["config"] = sub["config"]
-        line["mix1024"]["value_frac_of_hbm_peak"] = sub["value"] * 1e9 / HBM_PEAK
-        line["mix1024"]["detail"] = {key: sub["detail"][key] for key in
-                                     ("sinkhorn_iters", "sinkhorn_ms_per_step", "max_box",
-                                      "x_marginal_l1", "y_marginal_l1", "primal", "pd_gap")}
+        sub = measure(args, larger[args.workload], args.prec, args.extra_steps, 1, replay=0,
+                      cpu=False)
+        rec = {key: sub[key] for key in ("value", "unit", "ms_per_step", "ms_per_step_median",
+                                         "dtype", "roofline")}
+        rec["config"] = sub["config"]
+        rec["value_frac_of_hbm_peak"] = sub["value"] * 1e9 / HBM_PEAK
+        rec["detail"] = {key: sub["detail"][key] for key in
+                         ("sinkhorn_iters", "sinkhorn_ms_per_step", "max_box", "x_marginal_l1",
+                          "y_marginal_l1", "primal", "pd_gap")}
+        line["size1024"] = rec
+        if args.workload.startswith("ms"):
+            # the whole multiscale solve at the paper's arithmetic and stopping tolerance
+            line["full_solve"] = full_solve(args, args.workload, "f64", 1e-4)
     print(json.dumps(line), flush=True)
+
+
+def full_solve(args, workload, prec_name, tol):
+    """The whole multiscale solve, timed end to end: set-up, every layer's eps stages and
+    refinements, and on the finest layer eps = 2h^2, h^2, h^2/2, h^2/4 (the paper's schedule,
+    App. A.2.1), each stage `layer_iters` half-iterations; then the relative primal-dual gap
+    and the marginal errors of the result (evaluated after the clock stops)."""
+    import torch
+
+    import paper_2405_09400_amd as dd
+    import synth
+    w = synth.workload(workload, seed=args.seed)
+    L = w.extra["levels"]
+    prec = dd.DD_PREC_F32 if prec_name == "f32" else dd.DD_PREC_F64
+    rule = dd.DD_STOP_BATCH
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ctx = dd.DomDec(w.mu, w.nu, w.s, w.init, prec=prec, levels=L)
+    k, sk_ms, box_ms, its = 0, 0.0, 0.0, 0
+    for layer in range(L + 1):
+        kappas = w.extra["layer_kappas"] if layer < L else [2.0, 1.0, 0.5, 0.25]
+        for kappa in kappas:
+            for _ in range(w.extra["layer_iters"]):
+                st = ctx.iterate("AB"[k % 2], kappa / ctx.N ** 2, tol=tol, stop_rule=rule,
+                                 max_iter=args.max_iter, check_every=args.check_every)
+                k += 1
+                sk_ms += st["t_sinkhorn_ms"]
+                box_ms += st["t_b2c_ms"] + st["t_c2b_ms"]
+                its += st["sk"]["iters_max"]
+        if layer < L:
+            ctx.refine()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ev = ctx.evaluate()
+    ctx.close()
+    log(f"[bench] full multiscale solve {workload} {prec_name} tol {tol}: {wall:.2f} s, relative "
+        f"PD gap {ev['pd_gap'] / ev['primal']:.3e}")
+    return {"workload": workload, "dtype": prec_name, "tol": tol, "wall_s": wall,
+            "sinkhorn_s": sk_ms / 1e3, "bbox_and_balance_s": box_ms / 1e3, "half_iterations": k,
+            "sinkhorn_iterations": its, "layers": [w.N >> (L - l) for l in range(L + 1)],
+            "relative_pd_gap": ev["pd_gap"] / ev["primal"], "primal": ev["primal"],
+            "dual": ev["dual"], "x_marginal_l1": ev["x_marginal_l1"],
+            "y_marginal_l1": ev["y_marginal_l1"],
+            "schedule": "eps = 2h^2, h^2, h^2/2 per layer, finest 2h^2, h^2, h^2/2, h^2/4, "
+                        f"{w.extra['layer_iters']} half-iterations per stage"}
 
 
 def measure(args, workload, prec, steps, warmup, replay=0, cpu=False):

@@ -183,12 +183,13 @@ def workload(name: str, seed: int = 0, N: Optional[int] = None) -> Workload:
         return Workload(name, n, 4, mu, nu, ks, its, kr_coupling(mu, nu), seed)
     if name in ("ms256", "ms512", "ms1024"):
         # the mixture workloads of the same size and seed, solved coarse to fine: layers of
-        # 2 x 2 block sums down to 32 x 32 (product coupling there), eps = 2h^2, h^2, h^2/2 on
-        # each coarser layer (h its pixel size), then 2h^2 and h^2 on the finest
+        # 2 x 2 block sums down to 8 x 8 (product coupling there; with s = 4 its A partition
+        # is one cell), eps = 2h^2, h^2, h^2/2 on each coarser layer (h its pixel size), then
+        # 2h^2 and h^2 on the finest, 8 half-iterations per stage
         base = workload("mix" + name[2:], seed=seed, N=N)
-        levels = int(round(math.log2(base.N // 32)))
-        return Workload(name, base.N, base.s, base.mu, base.nu, [2.0, 1.0], [4, 20], None, seed,
-                        {"levels": levels, "layer_kappas": [2.0, 1.0, 0.5], "layer_iters": 4})
+        levels = int(round(math.log2(base.N // 8)))
+        return Workload(name, base.N, base.s, base.mu, base.nu, [2.0, 1.0], [8, 20], None, seed,
+                        {"levels": levels, "layer_kappas": [2.0, 1.0, 0.5], "layer_iters": 8})
     if name == "flow512":
         n = N or 512
         mu = gaussian_mixture(n, 8, 1e-4, seed)
