@@ -36,6 +36,9 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdlib>
+#include <map>
+#include <mutex>
+#include <tuple>
 
 namespace dd {
 namespace {
@@ -1080,15 +1083,40 @@ int cus() {
     return n;
 }
 
+// Workgroups per CU of a kernel at a block size and LDS size, asked of the runtime once per
+// (kernel, block, LDS) on this device and then remembered.
 template <typename Kern>
 Status prep(Kern k, int block, size_t lds, int items, int& grid) {
     Status S;
-    DD_HIP(hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize,
-                               (int)lds),
-           S);
-    int per = 0;
-    DD_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k, block, lds), S);
-    grid = std::max(1, std::min(items, std::max(per, 1) * cus()));
+    struct Key {
+        const void* k;
+        int block, dev;
+        size_t lds;
+        bool operator<(const Key& o) const {
+            return std::tie(k, block, dev, lds) < std::tie(o.k, o.block, o.dev, o.lds);
+        }
+    };
+    static std::mutex mu;
+    static std::map<Key, int> per_cu;
+    static std::map<std::pair<const void*, int>, size_t> lds_set;
+    int dev = 0;
+    DD_HIP(hipGetDevice(&dev), S);
+    const Key key{(const void*)k, block, dev, lds};
+    std::lock_guard<std::mutex> lock(mu);
+    size_t& set = lds_set[{(const void*)k, dev}];
+    if (lds > set) {
+        DD_HIP(hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                   (int)lds),
+               S);
+        set = lds;
+    }
+    auto it = per_cu.find(key);
+    if (it == per_cu.end()) {
+        int per = 0;
+        DD_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k, block, lds), S);
+        it = per_cu.emplace(key, std::max(per, 1)).first;
+    }
+    grid = std::max(1, std::min(items, it->second * cus()));
     return S;
 }
 
@@ -1128,7 +1156,8 @@ bool fast_eligible(const SkBatch& p, const std::vector<int32_t>& hd) {
 }
 
 Status fast_solve(const SkBatch& p, const dd_sinkhorn_opts& o, hipStream_t st, SkWork& w,
-                  const std::vector<int32_t>& hd, int32_t* iters, double* errs, FastInfo* info) {
+                  const std::vector<int32_t>& hd, const std::vector<int32_t>& order,
+                  int32_t* iters, double* errs, FastInfo* info) {
     Status S;
     const int n = p.ncells;
     // Cell classes by box shape (kernel frame), most work first within each:
@@ -1146,7 +1175,7 @@ Status fast_solve(const SkBatch& p, const dd_sinkhorn_opts& o, hipStream_t st, S
     const hipStream_t streams[kClasses] = {w.stream2, w.stream3, st};
     std::vector<int32_t> cells[kClasses];
     int W1m[kClasses] = {1, 1, 1}, W2m[kClasses] = {1, 1, 1};
-    for (int c = 0; c < n; ++c) {
+    for (int c : order) {  // most work first within each class
         const int a = std::max(std::max(hd[2 * c], hd[2 * c + 1]), 1);
         const int b = std::max(std::min(hd[2 * c], hd[2 * c + 1]), 1);
         const int k = cell_class(a, b);
@@ -1154,12 +1183,10 @@ Status fast_solve(const SkBatch& p, const dd_sinkhorn_opts& o, hipStream_t st, S
         W1m[k] = std::max(W1m[k], a);
         W2m[k] = std::max(W2m[k], b);
     }
-    auto work = [&](int c) { return (double)std::max(hd[2 * c], 1) * std::max(hd[2 * c + 1], 1); };
-    auto by_work = [&](int a, int b) { return work(a) > work(b); };
     std::vector<int32_t> ord;
+    ord.reserve(n);
     int first[kClasses];
     for (int k = 0; k < kClasses; ++k) {
-        std::stable_sort(cells[k].begin(), cells[k].end(), by_work);
         first[k] = (int)ord.size();
         ord.insert(ord.end(), cells[k].begin(), cells[k].end());
     }

@@ -32,7 +32,9 @@ constexpr int kFastMaxSide = 512;
 // rules as the general kernels, except that the batch rule is tested at iterations the
 // device chooses from the error's decay (at least max(1, o.check_every) apart), and that a
 // tolerance solve aims at 0.85 o.tol (the float64 finish certifies o.tol).
+// `ord`: the cells in order of decreasing work (each class keeps that order, most work first).
 Status fast_solve(const SkBatch& p, const dd_sinkhorn_opts& o, hipStream_t st, SkWork& w,
-                  const std::vector<int32_t>& hd, int32_t* iters, double* errs, FastInfo* info);
+                  const std::vector<int32_t>& hd, const std::vector<int32_t>& ord,
+                  int32_t* iters, double* errs, FastInfo* info);
 
 }  // namespace dd

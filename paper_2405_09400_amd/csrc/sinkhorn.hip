@@ -1070,9 +1070,11 @@ struct CellClass {
     size_t budget = 0;
 };
 
+// first_chunk: iterations launched before the first read of the stop flag (batch rule; 0: a
+// whole chunk of check_every)
 template <typename T>
 Status run_solver(const SkBatch& p0, const std::vector<CellClass>& cls, const dd_sinkhorn_opts& o,
-                  hipStream_t st, SkWork& w, int32_t* iters, double* errs) {
+                  hipStream_t st, SkWork& w, int32_t* iters, double* errs, int first_chunk = 0) {
     Status S;
     double* big = reinterpret_cast<double*>(w.big);
     // the small and giant classes run on `st`, the big class on the second stream, side by side
@@ -1149,9 +1151,35 @@ Status run_solver(const SkBatch& p0, const std::vector<CellClass>& cls, const dd
             join();
         }
     };
+    // The first `first_chunk` launches go out directly (a float64 finish usually stops in its
+    // first iteration, so it pays for no capture); if the rule has not stopped by then, a chunk
+    // of `chunk` launches is captured once and replayed.
+    int done = 0, launched = 0;
+    auto read_done = [&]() {
+        return hipMemcpyAsync(&done, w.ctrl + 2, sizeof(int), hipMemcpyDeviceToHost, st) ==
+                   hipSuccess &&
+               hipStreamSynchronize(st) == hipSuccess;
+    };
+    const int first = std::max(1, std::min(first_chunk > 0 ? first_chunk : chunk, o.max_iter));
+    for (int r = 0; r < first; ++r) {
+        fork();
+        for (int k = 0; k < ncls; ++k) {
+            auto ik = cls[k].mode == kBig ? sk_iter_kernel<T, kBig> : sk_iter_kernel<T, kSmall>;
+            ik<<<grid[k], kThreads, lds[k], streams[k]>>>(pk[k], bufs[0], bufs[1], o.max_iter,
+                                                          o.tol, nblocks, w.ctrl, errs,
+                                                          w.cell_mass, w.dtot, big);
+        }
+        join();
+    }
+    launched = first;
+    if (!read_done()) {
+        S.code = DD_EDEVICE;
+        S.msg = "sinkhorn: reading the stop flag failed";
+        return S;
+    }
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
-    if (!one_stream) {
+    if (!done && launched < o.max_iter && !one_stream) {
         DD_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal), S);
         chunk_launches();
         const hipError_t ce = hipStreamEndCapture(st, &graph);
@@ -1163,14 +1191,10 @@ Status run_solver(const SkBatch& p0, const std::vector<CellClass>& cls, const dd
             return S;
         }
     }
-    int done = 0;
-    for (int launched = 0; launched < o.max_iter && !done; launched += chunk) {
+    for (; launched < o.max_iter && !done; launched += chunk) {
         if (one_stream)
             chunk_launches();
-        if ((!one_stream && hipGraphLaunch(exec, st) != hipSuccess) ||
-            hipMemcpyAsync(&done, w.ctrl + 2, sizeof(int), hipMemcpyDeviceToHost, st) !=
-                hipSuccess ||
-            hipStreamSynchronize(st) != hipSuccess) {
+        if ((!one_stream && hipGraphLaunch(exec, st) != hipSuccess) || !read_done()) {
             if (exec) (void)hipGraphExecDestroy(exec);
             if (graph) (void)hipGraphDestroy(graph);
             S.code = DD_EDEVICE;
@@ -1202,27 +1226,39 @@ void plan_tile(const std::vector<int32_t>& hd, const std::vector<int32_t>& cells
     const int n = (int)cells.size();
     if (n == 0) return;
     auto fits = [&](int a, int b) { return lds_layout_bytes(xside, a, b, elem) <= budget; };
-    std::vector<int> d1(n), d2(n);
-    for (int k = 0; k < n; ++k) {
-        d1[k] = hd[2 * cells[k]];
-        d2[k] = hd[2 * cells[k] + 1];
+    // per-axis order statistics of the box dims from histograms (dims are small integers)
+    int m1 = 1, m2 = 1;
+    for (int c : cells) {
+        m1 = std::max(m1, hd[2 * c]);
+        m2 = std::max(m2, hd[2 * c + 1]);
     }
-    std::sort(d1.begin(), d1.end());
-    std::sort(d2.begin(), d2.end());
-    if (fits(d1[n - 1], d2[n - 1])) {
-        lw1 = d1[n - 1];
-        lw2 = d2[n - 1];
+    std::vector<int> h1(m1 + 1, 0), h2(m2 + 1, 0);
+    for (int c : cells) {
+        ++h1[std::max(hd[2 * c], 0)];
+        ++h2[std::max(hd[2 * c + 1], 0)];
+    }
+    auto kth = [](const std::vector<int>& h, int k) {  // the k-th smallest (0-based)
+        int acc = 0;
+        for (int v = 0; v < (int)h.size(); ++v)
+            if ((acc += h[v]) > k) return v;
+        return (int)h.size() - 1;
+    };
+    if (fits(kth(h1, n - 1), kth(h2, n - 1))) {
+        lw1 = kth(h1, n - 1);
+        lw2 = kth(h2, n - 1);
         return;
     }
     for (double q : {0.99, 0.97, 0.95, 0.9, 0.85, 0.8, 0.7, 0.6, 0.5, 0.3, 0.1}) {
         const int k = std::min(n - 1, (int)(q * n));
-        if (fits(d1[k], d2[k])) {
-            lw1 = d1[k];
-            lw2 = d2[k];
+        const int a = kth(h1, k), b = kth(h2, k);
+        if (fits(a, b)) {
+            lw1 = a;
+            lw2 = b;
             return;
         }
     }
 }
+
 constexpr size_t kBudgets[] = {52 * 1024, 78 * 1024};  // small and big launches
 constexpr size_t kBigBudget = 156 * 1024;
 
@@ -1242,25 +1278,36 @@ struct Plan {
     int small_tile[2] = {0, 0}, big_tile[2] = {0, 0};
 };
 
-Plan plan_classes(const std::vector<int32_t>& hd, int ncells, int AS, size_t elem,
-                  size_t small_budget, size_t big_budget) {
+// `ord`: the cells in order of decreasing LSE work per iteration (ties by index).
+Plan plan_classes(const std::vector<int32_t>& hd, const std::vector<int32_t>& ord, int ncells,
+                  int AS, size_t elem, size_t small_budget, size_t big_budget) {
     Plan P;
     auto work = [&](int c) {
         return sk_cell_terms(AS, std::max(hd[2 * c], 0), std::max(hd[2 * c + 1], 0));
     };
     auto fits = [&](int c, const int* t) { return hd[2 * c] <= t[0] && hd[2 * c + 1] <= t[1]; };
-    std::vector<int32_t> ord(ncells);
-    for (int c = 0; c < ncells; ++c) ord[c] = c;
-    std::stable_sort(ord.begin(), ord.end(), [&](int a, int b) { return work(a) > work(b); });
     const double small_terms = 64.0 * 1024.0;
     std::vector<int32_t> cand, rest, small_cells, big_cells, giant_cells;
-    for (int c : ord) (work(c) < small_terms ? cand : rest).push_back(c);
+    std::vector<uint8_t> to_rest(ncells, 0);
+    for (int c : ord) {
+        if (work(c) < small_terms)
+            cand.push_back(c);
+        else
+            to_rest[c] = 1;
+    }
     CellClass sc, bc, gc;
     sc.mode = kSmall;
     sc.budget = small_budget;
     plan_tile(hd, cand, AS, elem, small_budget / kWaves, sc.t[0], sc.t[1]);
-    for (int c : cand) (fits(c, sc.t) ? small_cells : rest).push_back(c);
-    std::stable_sort(rest.begin(), rest.end(), [&](int a, int b) { return work(a) > work(b); });
+    for (int c : cand) {
+        if (fits(c, sc.t))
+            small_cells.push_back(c);
+        else
+            to_rest[c] = 1;
+    }
+    // the rest in the same order (most work first)
+    for (int c : ord)
+        if (to_rest[c]) rest.push_back(c);
     bc.budget = big_budget;
     plan_tile(hd, rest, AS, elem, big_budget, bc.t[0], bc.t[1]);
     for (int c : rest) (fits(c, bc.t) ? big_cells : giant_cells).push_back(c);
@@ -1420,9 +1467,16 @@ Status sk_solve(const SkBatch& p, const dd_sinkhorn_opts& o, hipStream_t caller_
     auto work = [&](int c) {
         return sk_cell_terms(AS, std::max(hd[2 * c], 0), std::max(hd[2 * c + 1], 0));
     };
+    // cells in order of decreasing LSE work per iteration, ties by index: one sort of packed
+    // integer keys (the work of a cell is an integer below 2^32)
+    std::vector<uint64_t> keys(p.ncells);
+    for (int c = 0; c < p.ncells; ++c) {
+        const double wk = std::min(work(c), 4294967295.0);
+        keys[c] = ((uint64_t)(4294967295u - (uint32_t)wk) << 32) | (uint32_t)c;
+    }
+    std::sort(keys.begin(), keys.end());
     std::vector<int32_t> ord(p.ncells);
-    for (int c = 0; c < p.ncells; ++c) ord[c] = c;
-    std::stable_sort(ord.begin(), ord.end(), [&](int a, int b) { return work(a) > work(b); });
+    for (int k = 0; k < p.ncells; ++k) ord[k] = (int32_t)(keys[k] & 0xffffffffu);
     const size_t elem = p.prec == DD_PREC_F64 ? sizeof(double) : sizeof(float);
     // Launch plans, one per precision (the float64 finish has its own tiles).  The two LDS
     // budgets come from the tuner, keyed by block side, precision, stop rule and the size
@@ -1438,8 +1492,12 @@ Status sk_solve(const SkBatch& p, const dd_sinkhorn_opts& o, hipStream_t caller_
     const size_t small_budget = kBudgets[choice % kNumBudgets];
     const size_t big_budget = kBudgets[choice / kNumBudgets];
     const bool finish = p.prec == DD_PREC_F32 && o.fixed_iters == 0;
-    const Plan P = plan_classes(hd, p.ncells, AS, elem, small_budget, big_budget);
-    const Plan P64 = finish ? plan_classes(hd, p.ncells, AS, sizeof(double), kBudgets[1], kBudgets[1])
+    const bool fast = fast_eligible(p, hd);
+    // the general path's plan (not needed when the register-blocked path takes the batch), and
+    // the float64 finish's
+    const Plan P = fast ? Plan{} : plan_classes(hd, ord, p.ncells, AS, elem, small_budget, big_budget);
+    const Plan P64 = finish ? plan_classes(hd, ord, p.ncells, AS, sizeof(double), kBudgets[1],
+                                           kBudgets[1])
                             : Plan{};
     auto put = [&](int32_t*& dev_ord, int64_t*& dev_off, int& cap, const Plan& pl) -> Status {
         Status E;
@@ -1464,7 +1522,6 @@ Status sk_solve(const SkBatch& p, const dd_sinkhorn_opts& o, hipStream_t caller_
         return E;
     };
     // 8 x 8 blocks in float32 take the register-blocked path (same iteration and rules)
-    const bool fast = fast_eligible(p, hd);
     if (!fast) {
         S = put(w.order, w.scr_off, w.order_cap, P);
         if (S.code) return S;
@@ -1501,7 +1558,7 @@ Status sk_solve(const SkBatch& p, const dd_sinkhorn_opts& o, hipStream_t caller_
     zero_ints<<<1, 64, 0, st>>>(w.ctrl, 16);
     FastInfo fi;
     if (fast)
-        S = fast_solve(p, o, st, w, hd, iters, errs, &fi);
+        S = fast_solve(p, o, st, w, hd, ord, iters, errs, &fi);
     else
         S = p.prec == DD_PREC_F32 ? run_solver<float>(q, P.classes, o, st, w, iters, errs)
                                   : run_solver<double>(q, P.classes, o, st, w, iters, errs);
@@ -1510,7 +1567,7 @@ Status sk_solve(const SkBatch& p, const dd_sinkhorn_opts& o, hipStream_t caller_
     if (finish) {
         // float64 finish: continue the same stopping rule in float64 from the float32 state;
         // the tolerance is then certified by a float64 error (usually after one Y-update)
-        S = run_solver<double>(q64, P64.classes, o, st, w, w.iters64, errs);
+        S = run_solver<double>(q64, P64.classes, o, st, w, w.iters64, errs, 2);
         if (S.code) return S;
     }
     sk_stats_kernel<<<1, kThreads, 0, st>>>(p.ncells, iters, finish ? w.iters64 : nullptr, errs,
