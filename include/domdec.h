@@ -204,6 +204,40 @@ dd_status sinkhorn_batch_noalloc(int32_t ncells, int32_t xside, const int32_t* d
                                  int32_t* cell_iters, double* cell_err, void* stream,
                                  dd_batch_stats* stats);
 
+/* Statistics of a global Sinkhorn solve. */
+typedef struct {
+    int32_t iters;       /* Y-updates run                                              */
+    int32_t converged;   /* 1 if the tolerance (or the fixed count) was reached         */
+    double err;          /* X-marginal L1 error of the returned pair                    */
+    double time_ms;      /* device time of the solve (HIP events)                       */
+    double lse_terms;    /* log-sum-exp terms evaluated: 4 N^3 per iteration            */
+} dd_global_stats;
+
+/*
+ * global_sinkhorn -- entropic OT on the whole N x N grid by log-domain Sinkhorn, without
+ * domain decomposition: the comparison solver of App. A.2.1 ("Compared algorithms and
+ * implementations", a global GPU Sinkhorn).  It solves eq. (entropic-transport) as the
+ * single-cell problem X = Y = the grid, with the cell solver's iteration and stopping rule:
+ * one iteration = Y-update, X-marginal L1 error, then (unless stopped) X-update; stop once
+ * err <= opts->tol (mu, nu are probability measures), or after opts->fixed_iters Y-updates.
+ * Float64 throughout; each log-sum-exp is two exact 1D passes (the cost is separable).
+ *   n          grid side N (1..4096; 4 N doubles must fit the LDS of a workgroup).
+ *   mu, nu     (dev) float64 [N*N], row-major, >= 0 (zero entries are zero mass).
+ *   eps        regularisation, > 0 (the cost is |x - y|^2 on pixel centres of [0,1]^2).
+ *   alpha      (dev) float64 [N*N] in: starting X potential (energy units; zeros for a cold
+ *              start, the previous solution for eps-scaling); out: alpha of the last Y-update.
+ *   beta       (dev) float64 [N*N] out: beta (energy units; reference measure mu (x) nu, so
+ *              pi = exp((alpha + beta - |x - y|^2) / eps) mu nu); meaningless where nu = 0.
+ *   opts       (host) tol, max_iter, fixed_iters; stop_rule, check_every, init ignored.
+ *   stream     hipStream_t; the call synchronises it (it reads the error every iteration).
+ *   stats      (host) out, may be NULL.
+ * Work arrays (6 N^2 doubles) are allocated per call.
+ * Errors: DD_EINVAL, DD_ENOMEM, DD_EDEVICE, DD_ENUMERIC, DD_NOTCONV (warning).
+ */
+dd_status global_sinkhorn(int32_t n, const double* mu, const double* nu, double eps,
+                          double* alpha, double* beta, const dd_sinkhorn_opts* opts,
+                          void* stream, dd_global_stats* stats);
+
 /* ------------------------------------------------------------------------- */
 /* Domain-decomposition context                                              */
 /* ------------------------------------------------------------------------- */

@@ -25,7 +25,7 @@ SYMBOLS = ("sinkhorn_batch", "sinkhorn_batch_f64", "domdec_init", "domdec_iterat
            "flow_costs", "flow_apply", "dd_mcf_solve", "extract_plan", "domdec_evaluate", "domdec_free",
            "domdec_strerror", "dd_net_param_count", "dd_net_create", "dd_net_params", "dd_net_forward",
            "dd_net_train_step", "dd_net_free", "dd_net_strerror", "domdec_set_net", "domdec_net_samples", "domdec_save", "domdec_restore",
-           "extract_potentials", "sinkhorn_batch_noalloc", "domdec_refine")
+           "extract_potentials", "sinkhorn_batch_noalloc", "domdec_refine", "global_sinkhorn")
 
 
 class DomDecError(RuntimeError):
@@ -88,6 +88,11 @@ class PotentialsView(ctypes.Structure):
                 ("ybase", ctypes.POINTER(ctypes.c_int64)), ("beta", ctypes.POINTER(ctypes.c_double))]
 
 
+class GlobalStats(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int32), ("converged", ctypes.c_int32), ("err", ctypes.c_double),
+                ("time_ms", ctypes.c_double), ("lse_terms", ctypes.c_double)]
+
+
 class Eval(ctypes.Structure):
     _fields_ = [("y_marginal_l1", ctypes.c_double), ("x_marginal_l1", ctypes.c_double),
                 ("primal", ctypes.c_double), ("transport", ctypes.c_double),
@@ -144,6 +149,9 @@ def lib():
     L.dd_mcf_solve.argtypes = [ctypes.c_int32, ctypes.c_int32, i32p, i32p, i64p, i64p, i64p, i64p]
     L.extract_plan.restype = ctypes.c_int
     L.extract_plan.argtypes = [vp, ctypes.POINTER(PlanView)]
+    L.global_sinkhorn.restype = ctypes.c_int
+    L.global_sinkhorn.argtypes = [ctypes.c_int32, vp, vp, ctypes.c_double, vp, vp,
+                                  ctypes.POINTER(SinkhornOpts), vp, ctypes.POINTER(GlobalStats)]
     L.extract_potentials.restype = ctypes.c_int
     L.extract_potentials.argtypes = [vp, ctypes.POINTER(PotentialsView)]
     L.domdec_evaluate.restype = ctypes.c_int
@@ -257,6 +265,23 @@ def sinkhorn_batch(dims, base, shift, logmu, lognu, a, b, kappa, max_w1, max_w2,
     status = f(n, xside, _ptr(dims), _ptr(base), _ptr(shift), _ptr(logmu), _ptr(lognu), _ptr(a), _ptr(b),
                float(kappa), int(max_w1), int(max_w2), ctypes.byref(o), _ptr(cell_iters), _ptr(cell_err),
                _stream_ptr(stream), ctypes.byref(st))
+    if raise_on_error:
+        _check(status)
+    return status, _struct_dict(st)
+
+
+def global_sinkhorn(mu, nu, eps, alpha, beta, *, tol=1e-5, max_iter=100000, fixed_iters=0,
+                    stream=None, raise_on_error=True):
+    """Global Sinkhorn on the whole grid (global_sinkhorn in include/domdec.h): mu, nu float64
+    [N, N] device tensors, alpha (in/out) and beta (out) float64 [N, N].  Returns (status, stats)."""
+    import torch
+    N = int(mu.shape[0])
+    for t in (mu, nu, alpha, beta):
+        assert t.dtype == torch.float64 and t.is_cuda and t.is_contiguous() and tuple(t.shape) == (N, N)
+    st = GlobalStats()
+    o = _opts(tol, max_iter, fixed_iters, DD_STOP_BATCH, 0)
+    status = lib().global_sinkhorn(N, _ptr(mu), _ptr(nu), float(eps), _ptr(alpha), _ptr(beta),
+                                   ctypes.byref(o), _stream_ptr(stream), ctypes.byref(st))
     if raise_on_error:
         _check(status)
     return status, _struct_dict(st)
