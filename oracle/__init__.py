@@ -576,8 +576,53 @@ class DomDec:
         return P
 
     # -- flow update ------------------------------------------------------------
-    def flow_update(self, mass_bits: int = 40, cost_bits: int = 30, truncate: bool = True) -> dict:
-        """Flow update with product gluing candidates (Def. "Flow update", Remark "eps-gamma").
+    def glued_gamma(self, i: int, j: int, eps_gamma: float) -> np.ndarray:
+        """gamma_ij of a gluing edge candidate (Def. "Gluing edge candidate", Remark "eps-gamma"):
+        the entropic optimal transport plan between mu_i/m_i and mu_j/m_j for the cost
+        |x - x'|^2 at regularisation eps_gamma, by the oracle's dense Sinkhorn to 1e-14.
+        Rows: the pixels of X_i, columns: those of X_j (both in row-major block order)."""
+        xi, xj = self.cells[i], self.cells[j]
+        mi = self.mu[xi] / self.m[i]
+        mj = self.mu[xj] / self.m[j]
+        a, b, _, _, _ = sinkhorn_cells(np.array([0, len(xi)]), self.coords[xi], mi,
+                                       np.array([0, len(xj)]), self.coords[xj], mj, mj, eps_gamma,
+                                       tol=1e-14, max_iter=200000)
+        return cell_plan(self.coords[xi], mi, a, self.coords[xj], mj, b, eps_gamma)
+
+    def basic_plans(self, which: Optional[str] = None):
+        """pi_i for every basic cell: the rows of X_i of the composite plan of the last
+        iteration, as (ysup, rows [|X_i|, |ysup|]) with rows in the block order of X_i."""
+        which = which or self.last_which
+        eps = self.last_eps[which]
+        out = [None] * len(self.cells)
+        for cs in self.last[which]:
+            plan = cell_plan(self.coords[cs.xpix], self.mu[cs.xpix], cs.alpha,
+                             self.coords[cs.ysup], self.nu[cs.ysup], cs.beta, eps)
+            row = 0
+            for k, i in enumerate(cs.basic):
+                out[i] = (cs.ysup, plan[row:row + cs.xcount[k]])
+                row += cs.xcount[k]
+        return out
+
+    def glued_candidate(self, i: int, j: int, eps_gamma: float, plans=None):
+        """The gluing edge candidate pihat_ij (eq. glued-plan) on X_j x supp(pi_i), densely:
+            pihat_ij(x', y) = (1/m_i) sum_{x in X_i} (gamma_ij)_x(x') pi_i(x, y),
+        with (gamma_ij)_x = gamma_ij(x, .) / sum_x' gamma_ij(x, x') the disintegration of gamma_ij
+        at x, and mu_i(x) (pi_i)_x read as the plan's own row pi_i(x, .) (so the candidate's
+        Y-marginal is exactly the plan's nu_i / m_i).  Returns (ysup, pihat)."""
+        plans = plans or self.basic_plans()
+        ysup, rows = plans[i]
+        g = self.glued_gamma(i, j, eps_gamma)
+        cond = g / g.sum(axis=1, keepdims=True)
+        return ysup, cond.T @ rows / self.m[i]
+
+    def flow_update(self, mass_bits: int = 40, cost_bits: int = 30, truncate: bool = True,
+                    eps_gamma: Optional[float] = None) -> dict:
+        """Flow update with gluing edge candidates (Def. "Flow update", Def. "Gluing edge
+        candidate", Remark "eps-gamma").  eps_gamma None: the product candidates; else the
+        candidates glued from entropic plans gamma_ij at regularisation eps_gamma, with
+            cbar_ij = <c, pihat_ij> - <c, pi_i>/m_i
+        summed by brute force over X_j x supp(pi_i) (glued_candidate).
 
         pi_i is the restriction to X_i x Y of the composite plan of the immediately
         preceding DD iteration (instantiated from its potentials).  For every arc (i, j)
@@ -605,9 +650,15 @@ class DomDec:
                 row += cs.xcount[k]
         tail, head = neighbourhood(n)
         cbar = np.zeros(len(tail))
+        plans = self.basic_plans(which) if eps_gamma is not None else None
         for a in range(len(tail)):
             i, j = int(tail[a]), int(head[a])
             if i == j:
+                continue
+            if eps_gamma is not None:
+                ysup, ph = self.glued_candidate(i, j, eps_gamma, plans)
+                d = self.coords[self.cells[j]][:, None, :] - self.coords[ysup][None, :, :]
+                cbar[a] = float(((d ** 2).sum(axis=2) * ph).sum()) - ctotal[i] / self.m[i]
                 continue
             idx, val = self.nu_i[i]
             xj = self.coords[self.cells[j]]

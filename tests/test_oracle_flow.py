@@ -179,3 +179,90 @@ def test_largest_remainder_rounding():
     b = oracle.largest_remainder(m, T)
     assert int(b.sum()) == T
     assert np.all(np.abs(b - m * T) < 1.0)
+
+
+# ---- gluing edge candidates from entropic gamma_ij (Remark "eps-gamma") ----------------------
+
+def _tight_state(N=8, s=2, angle=90.0, scale=1.0, seed=0, uniform=False):
+    """A state whose composite plans have exact X-marginals (cell solves to 1e-13), so that the
+    candidates' X-marginals are mu_j / m_j to rounding."""
+    mu = np.full((N, N), 1.0 / N ** 2) if uniform else synth.gaussian_mixture(N, 3, 1e-2, seed)
+    tgt = synth.rotation_map(N, angle, scale, (0.0, 0.0))
+    nu, init = synth.map_coupling(mu, tgt)
+    dd = oracle.DomDec(mu, nu, s, init)
+    eps = (1.0 / N) ** 2
+    dd.iterate("A", eps, tol=1e-13, max_iter=100000, balance=False, truncate=False)
+    dd.iterate("B", eps, tol=1e-13, max_iter=100000, balance=False, truncate=False)
+    return dd, eps
+
+
+def test_glued_candidate_marginals():
+    """Lemma "properties of the gluing edge candidates", item 1: pihat_ij in
+    Pi(mu_j / m_j, nu_i / m_i)."""
+    dd, eps = _tight_state()
+    plans = dd.basic_plans()
+    tail, head = oracle.neighbourhood(dd.n)
+    for a in range(0, len(tail), 3):
+        i, j = int(tail[a]), int(head[a])
+        if i == j:
+            continue
+        ysup, ph = dd.glued_candidate(i, j, 0.3 * eps, plans)
+        assert np.abs(ph.sum(1) - dd.mu[dd.cells[j]] / dd.m[j]).max() <= 1e-12
+        assert np.abs(ph.sum(0) - plans[i][1].sum(0) / dd.m[i]).max() <= 1e-15
+
+
+def test_glued_candidate_limits():
+    """Remark "eps-gamma": eps_gamma -> infinity gives the product candidate
+    mu_j / m_j (x) nu_i / m_i; on a uniform mu, where the optimal map between neighbouring
+    cells is the translation, eps_gamma -> 0 gives pi_i translated onto X_j."""
+    dd, eps = _tight_state()
+    plans = dd.basic_plans()
+    i, j = 5, 6  # horizontal neighbours in the 4 x 4 basic-cell grid
+    ysup, ph = dd.glued_candidate(i, j, 1e6, plans)
+    prod = np.outer(dd.mu[dd.cells[j]] / dd.m[j], plans[i][1].sum(0) / dd.m[i])
+    assert np.abs(ph - prod).max() <= 1e-6 * prod.max()
+    du, eps = _tight_state(uniform=True)
+    plans = du.basic_plans()
+    # X_i and X_j are row-major 2 x 2 blocks, X_j = X_i shifted by one cell (the same order);
+    # the distance to the translated plan falls as eps_gamma does
+    dev = []
+    for f in (0.4, 0.2, 0.1):
+        ysup, ph = du.glued_candidate(i, j, f / du.N ** 2, plans)
+        dev.append(np.abs(ph - plans[i][1] / du.m[i]).max() / ph.max())
+    assert dev[0] > dev[1] > dev[2] and dev[2] <= 1e-4, dev
+
+
+def test_glued_flow_update_does_not_increase_the_objective():
+    """Prop. "flow update decreases score" with gluing candidates (Lemma "properties of the
+    gluing edge candidates", item 3; Lemma "transport non-increasing"): on the dense plans,
+    marginals are kept and E(pihat) <= E(pi)."""
+    dd, eps = _tight_state()
+    pi = _dense_pi(dd)
+    plans = dd.basic_plans()
+    tail, head = oracle.neighbourhood(dd.n)
+    eps_g = 0.5 * eps
+    cands = {}
+    for a in range(len(tail)):
+        i, j = int(tail[a]), int(head[a])
+        if i != j:
+            cands[a] = dd.glued_candidate(i, j, eps_g, plans)
+    res = dd.flow_update(truncate=False, eps_gamma=eps_g)
+    w = res["w"]
+    NN = dd.N * dd.N
+    P = np.zeros((NN, NN))
+    for a in range(len(tail)):
+        i, j = int(tail[a]), int(head[a])
+        if w[a] == 0:
+            continue
+        if i == j:
+            P[dd.cells[i]] += (w[a] / dd.m[i]) * pi[dd.cells[i]]
+        else:
+            ysup, ph = cands[a]
+            P[np.ix_(dd.cells[j], ysup)] += w[a] * ph
+    assert np.abs(P.sum(0) - pi.sum(0)).max() <= 1e-15
+    assert np.abs(P.sum(1) - pi.sum(1)).max() <= 5 * 2.0 ** -40 + 1e-13
+    c = _cost_matrix(dd)
+    E = lambda Q: float((c * Q).sum()) + eps * _kl(dd, Q)  # noqa: E731
+    assert res["value"] < 0.0
+    assert abs(float((c * P).sum() - (c * pi).sum()) - res["value"]) <= 1e-13
+    assert E(P) <= E(pi) + 1e-14
