@@ -350,29 +350,40 @@ typedef struct {
     double t_costs_ms, t_mcf_ms, t_assemble_ms;
 } dd_flow_stats;
 
+enum { DD_CAND_PRODUCT = 0, DD_CAND_GLUED = 1 };  /* edge candidates of the flow update */
+
 /*
- * flow_update -- flow update with product gluing candidates (Sec. 3.2
- * Def. "Flow update", Def. "Gluing edge candidate", Remark "eps-gamma";
- * implementation steps of Sec. 5.1).  Must follow a B iteration: pi_i is the
- * restriction to X_i x Y of that iteration's composite plans.
- *   Edge costs cbar_ij = <c, mu_j/m_j (x) nu_i/m_i> - <c, pi_i>/m_i over the
- *   4-neighbourhood plus self loops (cbar_ii = 0; arcs listed per tail i =
- *   r*(N/s)+c in ascending head order), computed on the device in float64 from
- *   cell moments; min-cost flow (MinCostFlow) on the host by network simplex,
+ * flow_update -- flow update with gluing edge candidates (Sec. 3.2 Def. "Flow
+ * update", Def. "Gluing edge candidate", Remark "eps-gamma"; implementation steps
+ * of Sec. 5.1).  Must follow a B iteration: pi_i is the restriction to X_i x Y of
+ * that iteration's composite plans.
+ *   candidate   DD_CAND_PRODUCT: pihat_ij = mu_j/m_j (x) nu_i/m_i (the eps_gamma = inf
+ *               limit; eps_gamma ignored);
+ *               DD_CAND_GLUED: pihat_ij(x', y) = (1/m_i) sum_{x in X_i} (gamma_ij)_x(x')
+ *               pi_i(x, y), gamma_ij the entropic optimal plan between mu_i/m_i and mu_j/m_j
+ *               for |x - x'|^2 at regularisation eps_gamma (> 0, finite; s <= 8), computed on
+ *               the device once per eps_gamma, and (gamma_ij)_x its normalised row at x.
+ *   Edge costs cbar_ij = <c, pihat_ij> - <c, pi_i>/m_i over the 4-neighbourhood plus
+ *   self loops (cbar_ii = 0; arcs listed per tail i = r*(N/s)+c in ascending head
+ *   order), computed on the device in float64 from cell (product) or per-pixel (glued)
+ *   moments of the plans; min-cost flow (MinCostFlow) on the host by network simplex,
  *   integerised with masses b_i (largest remainder to a total of 2^40, ties by
  *   index) and costs round(cbar 2^30 / max|cbar|), mapped back as
  *   w_ij = flow_ij m_i / b_i; new marginals nu_hat_j = sum_i w_ij nu_i / m_i
  *   (eq. flow-update-cell-marginals) assembled on the device, then truncated.
  *   Equivalent to flow_costs + dd_mcf_solve + flow_apply.  stats (host) may be
  *   NULL.  Synchronises the context stream.
- * Errors: DD_ESTATE if the last iteration was not on partition B.
+ * Errors: DD_ESTATE if the last iteration was not on partition B; DD_EINVAL for a bad
+ * candidate or eps_gamma.
  */
-dd_status flow_update(dd_ctx* ctx, dd_flow_stats* stats);
+dd_status flow_update(dd_ctx* ctx, int32_t candidate, double eps_gamma, dd_flow_stats* stats);
 
 /* flow_costs -- step 1 of flow_update: writes the edge costs cbar (host, float64,
- * [n_arcs], may be NULL) and the arc count (may be NULL).  DD_ESTATE unless the last
- * iteration was on partition B. */
-dd_status flow_costs(dd_ctx* ctx, double* cbar, int32_t* n_arcs);
+ * [n_arcs], may be NULL) and the arc count (may be NULL) for the given candidates.
+ * DD_ESTATE unless the last iteration was on partition B; DD_EINVAL for a bad candidate
+ * or eps_gamma. */
+dd_status flow_costs(dd_ctx* ctx, int32_t candidate, double eps_gamma, double* cbar,
+                     int32_t* n_arcs);
 
 /* flow_apply -- step 3 of flow_update for a given flow w (host, float64, [n_arcs], in
  * the arc order of flow_costs; w must satisfy the divergence constraint

@@ -16,6 +16,7 @@ DD_PREC_F32, DD_PREC_F64 = 0, 1
 DD_STOP_BATCH, DD_STOP_CELL = 0, 1
 DD_INIT_ZERO, DD_INIT_PREV, DD_INIT_NET = 0, 1, 2
 DD_PART_A, DD_PART_B = 0, 1
+DD_CAND_PRODUCT, DD_CAND_GLUED = 0, 1
 
 _NAMES = {0: "DD_OK", 1: "DD_NOTCONV", -1: "DD_EINVAL", -2: "DD_ENOMEM", -3: "DD_EDEVICE",
           -4: "DD_ESTATE", -5: "DD_ENUMERIC"}
@@ -140,9 +141,9 @@ def lib():
     L.domdec_iterate.argtypes = [vp, ctypes.c_int32, ctypes.c_double, ctypes.POINTER(SinkhornOpts),
                                  ctypes.POINTER(IterStats)]
     L.flow_update.restype = ctypes.c_int
-    L.flow_update.argtypes = [vp, ctypes.POINTER(FlowStats)]
+    L.flow_update.argtypes = [vp, ctypes.c_int32, ctypes.c_double, ctypes.POINTER(FlowStats)]
     L.flow_costs.restype = ctypes.c_int
-    L.flow_costs.argtypes = [vp, dp, i32p]
+    L.flow_costs.argtypes = [vp, ctypes.c_int32, ctypes.c_double, dp, i32p]
     L.flow_apply.restype = ctypes.c_int
     L.flow_apply.argtypes = [vp, dp]
     L.dd_mcf_solve.restype = ctypes.c_int
@@ -222,6 +223,10 @@ def _ptr(t) -> Optional[int]:
 def _opts(tol, max_iter, fixed_iters, stop_rule, check_every, init=DD_INIT_PREV) -> SinkhornOpts:
     return SinkhornOpts(float(tol), int(max_iter), int(fixed_iters), int(stop_rule), int(check_every),
                         int(init), 0)
+
+
+def _candidate(eps_gamma):
+    return (DD_CAND_PRODUCT, 0.0) if eps_gamma is None else (DD_CAND_GLUED, float(eps_gamma))
 
 
 def _stream_ptr(stream):
@@ -376,16 +381,21 @@ class DomDec:
                self._ctx)
         return x, t, w
 
-    def flow_update(self) -> dict:
+    def flow_update(self, eps_gamma=None) -> dict:
+        """Flow update (flow_update): product candidates, or with eps_gamma the candidates glued
+        from entropic plans at that regularisation."""
         st = FlowStats()
-        _check(lib().flow_update(self._ctx, ctypes.byref(st)), self._ctx)
+        cand, eg = _candidate(eps_gamma)
+        _check(lib().flow_update(self._ctx, cand, eg, ctypes.byref(st)), self._ctx)
         return _struct_dict(st)
 
-    def flow_costs(self) -> np.ndarray:
+    def flow_costs(self, eps_gamma=None) -> np.ndarray:
         n = ctypes.c_int32()
-        _check(lib().flow_costs(self._ctx, None, ctypes.byref(n)), self._ctx)
+        cand, eg = _candidate(eps_gamma)
+        _check(lib().flow_costs(self._ctx, cand, eg, None, ctypes.byref(n)), self._ctx)
         out = np.zeros(n.value, dtype=np.float64)
-        _check(lib().flow_costs(self._ctx, out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), None),
+        _check(lib().flow_costs(self._ctx, cand, eg,
+                                out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), None),
                self._ctx)
         return out
 

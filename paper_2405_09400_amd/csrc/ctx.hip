@@ -781,7 +781,7 @@ extern "C" dd_status extract_potentials(dd_ctx* c, dd_potentials_view* v) {
     return DD_OK;
 }
 
-void dd_eval_cells(dd_ctx* c) {
+void dd_eval_cells(dd_ctx* c, double* pix_out) {
     const int p = c->last_part;
     EvalArgs e;
     e.ncell = c->part[p].ncell;
@@ -807,6 +807,7 @@ void dd_eval_cells(dd_ctx* c) {
     e.cell_out = c->d_cell_out;
     e.basic_out = c->d_basic_out;
     e.totals = c->d_eval + 4;
+    e.pix_out = pix_out;
     launch_cell_eval(e, c->st);
 }
 

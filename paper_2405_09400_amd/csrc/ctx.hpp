@@ -87,5 +87,7 @@ struct dd_ctx {
 };
 
 void dd_ctx_release(dd_ctx* c);
-void dd_eval_cells(dd_ctx* c);
+// Evaluation reductions of the last iteration's composite plans; with pix_out ([N*N][3]) also
+// the per-pixel X moments of the plans.
+void dd_eval_cells(dd_ctx* c, double* pix_out = nullptr);
 void flow_release(dd_ctx* c);

@@ -112,7 +112,8 @@ __global__ void __launch_bounds__(kT)
                      const int64_t* __restrict__ cbase, const T* __restrict__ logmu,
                      const T* __restrict__ a, const T* __restrict__ b,
                      const T* __restrict__ lognuJ, const double* __restrict__ nuJ, const double* __restrict__ lognu_glob, int N,
-                     double kappa, double* cell_out /*[ncell][4]*/, double* basic_out /*[nI][3]*/) {
+                     double kappa, double* cell_out /*[ncell][4]*/, double* basic_out /*[nI][3]*/,
+                     double* pix_out /*[N*N][3] or null*/) {
     extern __shared__ __align__(16) char smem[];
     double* red = reinterpret_cast<double*>(smem);
     double* u0 = red + 8;
@@ -180,6 +181,13 @@ __global__ void __launch_bounds__(kT)
             const double xx = x1 * x1 + x2 * x2;
             const double xy = x1 * m1 + x2 * m2;
             tx += xx * m0 - 2.0 * xy;
+            if (pix_out) {
+                // the per-pixel X moments of the plan (gluing edge candidates of the flow update)
+                const int64_t px = (int64_t)(px1 + i1) * N + (px2 + i2);
+                pix_out[3 * px] = m0;
+                pix_out[3 * px + 1] = m1;
+                pix_out[3 * px + 2] = m2;
+            }
             const int k = (i1 >= s ? 2 : 0) + (i2 >= s ? 1 : 0);
             bm0[k] += m0;
             bx2[k] += xx * m0;
@@ -250,7 +258,7 @@ void launch_cell_eval(const EvalArgs& e, hipStream_t st) {
     k<<<std::max(1, std::min(e.ncell, 4096)), kT, lds, st>>>(
         e.ncell, e.xside, e.s, e.maxw1, e.maxw2, e.members, e.xorig, e.cdims, e.corig, e.cshift,
         e.gofs, e.cbase, e.logmu, e.a, e.b, e.lognuJ, e.nuJ, e.lognu_glob, e.N, e.kappa, e.cell_out,
-        e.basic_out);
+        e.basic_out, e.pix_out);
     sum4_kernel<<<1, kT, 0, st>>>(e.ncell, e.cell_out, e.totals);
 }
 

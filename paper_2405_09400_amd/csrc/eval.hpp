@@ -17,6 +17,8 @@ struct EvalArgs {
     double* cell_out = nullptr;   // [ncell][4]: E/eps part, <c,pi> (pixel units), X err, mass
     double* basic_out = nullptr;  // [nI][3]: sum m0, sum |x|^2 m0, sum <x,y> pi (pixel units), may be null
     double* totals = nullptr;     // [4] sums of cell_out columns
+    double* pix_out = nullptr;    // [N*N][3]: per X pixel with mass, sum_y pi(x,y) and
+                                  // sum_y (y_k + 1/2) pi(x,y) (pixel units), may be null
 };
 
 void launch_fill(double* p, size_t n, double v, hipStream_t st);

@@ -17,6 +17,18 @@
 //      order, then truncated below the threshold and repacked.
 // The neighbourhood is the 4-neighbourhood plus self loops on the basic-cell grid; arcs are
 // listed per tail in ascending head order.
+//
+// Gluing edge candidates from entropic plans (Def. "Gluing edge candidate", Remark "eps-gamma";
+// the candidate choice of Sec. 5.1 step 1): gamma_ij is the entropic optimal transport plan
+// between mu_i/m_i and mu_j/m_j (cost |x - x'|^2, regularisation eps_gamma), computed once per
+// eps_gamma (mu does not change); the candidate
+//     pihat_ij(x', y) = (1/m_i) sum_{x in X_i} (gamma_ij)_x(x') pi_i(x, y)
+// (with (gamma_ij)_x the row of gamma_ij at x, normalised) has the edge cost
+//     cbar_ij = (1/m_i) sum_{x in X_i} [(a(x) - |x|^2) P0(x) - 2 <b(x) - x, P1(x)>]
+// where a(x), b(x) are the conditional second and first moments of x' under (gamma_ij)_x and
+// P0(x), P1(x) = sum_y pi_i(x, y) (1, y) the per-pixel moments of the plan (the P2 terms of
+// the candidate and of pi_i cancel).  With gamma_ij the product plan this is the product
+// candidate's cost above.
 #include <algorithm>
 #include <chrono>
 #include <cmath>
@@ -47,6 +59,10 @@ struct FlowState {
     double* d_tmp = nullptr;
     size_t tmp_cap = 0;
     McfWarm* mcf_warm = nullptr;  // the last min-cost flow's optimal basis (same graph, supplies)
+    // gluing candidates: per arc and pixel x of X_tail, a(x) - |x|^2, b1(x) - x1, b2(x) - x2
+    double* d_cand = nullptr;     // [narcs][s*s][3]
+    double cand_eps = -1.0;       // eps_gamma d_cand was computed for
+    double* d_pix = nullptr;      // [N*N][3] per-pixel moments of the last B plans
 };
 
 namespace {
@@ -99,6 +115,109 @@ __global__ void cbar_kernel(int narcs, const int32_t* __restrict__ tail, const i
                             ys2[i];
         const double self = h * h * (pstat[3 * i + 1] - 2.0 * pstat[3 * i + 2]) + py2[i];
         cbar[a] = (cand - self) / mi;
+    }
+}
+
+// gamma_ij for arc (i, j), i != j, by log-domain Sinkhorn on the s^2 x s^2 problem (one thread
+// per arc, float64), then the conditional moments of its rows.  Rows x: the pixels of X_i with
+// weights mu/m_i; columns x': those of X_j.  Only the column potential enters the normalised
+// rows, so the iteration stops once it no longer moves (or after kGammaIters).
+constexpr int kMaxS2 = 64, kGammaIters = 20000;
+__global__ void gamma_kernel(int narcs, const int32_t* __restrict__ tail,
+                             const int32_t* __restrict__ head, int n, int s, int N,
+                             const double* __restrict__ mu, double h, double eps_g,
+                             double* __restrict__ cand) {
+    const int a = blockIdx.x * blockDim.x + threadIdx.x;
+    if (a >= narcs) return;
+    const int i = tail[a], j = head[a], S2 = s * s;
+    double* out = cand + (int64_t)a * S2 * 3;
+    if (i == j) {
+        for (int k = 0; k < 3 * S2; ++k) out[k] = 0.0;
+        return;
+    }
+    const int ri = (i / n) * s, ci = (i % n) * s, rj = (j / n) * s, cj = (j % n) * s;
+    double lmi[kMaxS2], lmj[kMaxS2], f[kMaxS2], g[kMaxS2];
+    for (int u = 0; u < S2; ++u) {
+        const double vi = mu[(int64_t)(ri + u / s) * N + ci + u % s];
+        const double vj = mu[(int64_t)(rj + u / s) * N + cj + u % s];
+        lmi[u] = vi > 0.0 ? log(vi) : kNegD;
+        lmj[u] = vj > 0.0 ? log(vj) : kNegD;
+        f[u] = 0.0;
+        g[u] = 0.0;
+    }
+    // cost in units of eps_gamma: h^2 |p - p'|^2 / eps_g in pixel offsets
+    const double ck = h * h / eps_g;
+    auto cost = [&](int u, int v) {
+        const double d1 = (ri + u / s) - (rj + v / s), d2 = (ci + u % s) - (cj + v % s);
+        return ck * (d1 * d1 + d2 * d2);
+    };
+    for (int it = 0; it < kGammaIters; ++it) {
+        // g(x') = -LSE_x [f(x) + log mu_i(x) - c(x, x')]  (the mass normalisations are constants)
+        double moved = 0.0;
+        for (int v = 0; v < S2; ++v) {
+            double m = -1e300;
+            for (int u = 0; u < S2; ++u)
+                if (lmi[u] > kZeroMassLog) m = fmax(m, f[u] + lmi[u] - cost(u, v));
+            double t = 0.0;
+            for (int u = 0; u < S2; ++u)
+                if (lmi[u] > kZeroMassLog) t += exp(f[u] + lmi[u] - cost(u, v) - m);
+            const double gv = -(m + log(t));
+            moved = fmax(moved, fabs(gv - g[v]));
+            g[v] = gv;
+        }
+        if (it > 0 && moved <= 1e-13) break;
+        // f(x) = -LSE_x' [g(x') + log mu_j(x') - c(x, x')]
+        for (int u = 0; u < S2; ++u) {
+            double m = -1e300;
+            for (int v = 0; v < S2; ++v)
+                if (lmj[v] > kZeroMassLog) m = fmax(m, g[v] + lmj[v] - cost(u, v));
+            double t = 0.0;
+            for (int v = 0; v < S2; ++v)
+                if (lmj[v] > kZeroMassLog) t += exp(g[v] + lmj[v] - cost(u, v) - m);
+            f[u] = -(m + log(t));
+        }
+    }
+    // conditional moments of the normalised rows, in [0, 1] coordinates
+    for (int u = 0; u < S2; ++u) {
+        double m = -1e300;
+        for (int v = 0; v < S2; ++v)
+            if (lmj[v] > kZeroMassLog) m = fmax(m, g[v] + lmj[v] - cost(u, v));
+        double w0 = 0.0, w1 = 0.0, w2 = 0.0, wq = 0.0;
+        for (int v = 0; v < S2; ++v) {
+            if (!(lmj[v] > kZeroMassLog)) continue;
+            const double r = exp(g[v] + lmj[v] - cost(u, v) - m);
+            const double y1 = (rj + v / s + 0.5) * h, y2 = (cj + v % s + 0.5) * h;
+            w0 += r;
+            w1 += r * y1;
+            w2 += r * y2;
+            wq += r * (y1 * y1 + y2 * y2);
+        }
+        const double x1 = (ri + u / s + 0.5) * h, x2 = (ci + u % s + 0.5) * h;
+        out[3 * u] = wq / w0 - (x1 * x1 + x2 * x2);
+        out[3 * u + 1] = w1 / w0 - x1;
+        out[3 * u + 2] = w2 / w0 - x2;
+    }
+}
+
+__global__ void cbar_glued_kernel(int narcs, const int32_t* __restrict__ tail,
+                                  const int32_t* __restrict__ head, int n, int s, int N,
+                                  const double* __restrict__ m, const double* __restrict__ cand,
+                                  const double* __restrict__ pix, double h, double* cbar) {
+    for (int a = blockIdx.x * blockDim.x + threadIdx.x; a < narcs; a += gridDim.x * blockDim.x) {
+        const int i = tail[a], j = head[a];
+        if (i == j) {
+            cbar[a] = 0.0;
+            continue;
+        }
+        const int ri = (i / n) * s, ci = (i % n) * s, S2 = s * s;
+        const double* cd = cand + (int64_t)a * S2 * 3;
+        double t = 0.0;
+        for (int u = 0; u < S2; ++u) {
+            const double* p = pix + 3 * ((int64_t)(ri + u / s) * N + ci + u % s);
+            // P1 = h (sum_y (y_pix + 1/2) pi) in [0, 1] coordinates
+            t += cd[3 * u] * p[0] - 2.0 * h * (cd[3 * u + 1] * p[1] + cd[3 * u + 2] * p[2]);
+        }
+        cbar[a] = t / m[i];
     }
 }
 
@@ -329,13 +448,20 @@ void flow_release(dd_ctx* c) {
     Fr(F->d_nsize);
     Fr(F->d_flags);
     Fr(F->d_tmp);
+    Fr(F->d_cand);
+    Fr(F->d_pix);
     mcf_warm_free(F->mcf_warm);
     delete F;
     c->flow = nullptr;
 }
 
-extern "C" dd_status flow_costs(dd_ctx* c, double* cbar, int32_t* n_arcs) {
+extern "C" dd_status flow_costs(dd_ctx* c, int32_t candidate, double eps_gamma, double* cbar,
+                                int32_t* n_arcs) {
     if (!c) return ffail(c, DD_EINVAL, "flow_costs: null context");
+    if (candidate != DD_CAND_PRODUCT && candidate != DD_CAND_GLUED)
+        return ffail(c, DD_EINVAL, "flow_costs: candidate must be DD_CAND_PRODUCT or DD_CAND_GLUED");
+    if (candidate == DD_CAND_GLUED && (!(eps_gamma > 0.0) || !std::isfinite(eps_gamma) || c->s > 8))
+        return ffail(c, DD_EINVAL, "flow_costs: glued candidates need 0 < eps_gamma < inf, s <= 8");
     if (c->last_part != DD_PART_B)
         return ffail(c, DD_ESTATE, "flow_costs: the last iteration must be on partition B");
     dd_status st = flow_prepare(c);
@@ -343,12 +469,30 @@ extern "C" dd_status flow_costs(dd_ctx* c, double* cbar, int32_t* n_arcs) {
     FlowState* F = c->flow;
     if (n_arcs) *n_arcs = F->narcs;
     const hipStream_t hs = c->st;
-    dd_eval_cells(c);  // X moments of pi_i from the last B solve -> d_basic_out
-    const int nb = std::max(1, std::min(c->nI, 4096));
-    ystat_kernel<<<nb, kT, 0, hs>>>(c->nI, c->S.box, c->S.base, c->S.data, c->h, F->d_ystat, F->d_ys2);
-    cbar_kernel<<<std::max(1, (F->narcs + kT - 1) / kT), kT, 0, hs>>>(
-        F->narcs, F->d_tail, F->d_head, c->d_m, F->d_xstat, F->d_ystat, F->d_ys2, c->d_basic_out,
-        c->d_py2, c->h, F->d_cbar);
+    const int ab = std::max(1, (F->narcs + kT - 1) / kT);
+    if (candidate == DD_CAND_PRODUCT) {
+        dd_eval_cells(c);  // X moments of pi_i from the last B solve -> d_basic_out
+        const int nb = std::max(1, std::min(c->nI, 4096));
+        ystat_kernel<<<nb, kT, 0, hs>>>(c->nI, c->S.box, c->S.base, c->S.data, c->h, F->d_ystat,
+                                        F->d_ys2);
+        cbar_kernel<<<ab, kT, 0, hs>>>(F->narcs, F->d_tail, F->d_head, c->d_m, F->d_xstat,
+                                       F->d_ystat, F->d_ys2, c->d_basic_out, c->d_py2, c->h,
+                                       F->d_cbar);
+    } else {
+        const int S2 = c->s * c->s;
+        if (!F->d_cand && !dalloc(F->d_cand, (size_t)F->narcs * S2 * 3))
+            return ffail(c, DD_ENOMEM, "flow_costs: allocating the candidates failed");
+        if (!F->d_pix && !dalloc(F->d_pix, (size_t)c->N * c->N * 3))
+            return ffail(c, DD_ENOMEM, "flow_costs: allocating the pixel moments failed");
+        if (F->cand_eps != eps_gamma) {
+            gamma_kernel<<<ab, kT, 0, hs>>>(F->narcs, F->d_tail, F->d_head, c->n, c->s, c->N,
+                                            c->d_mu, c->h, eps_gamma, F->d_cand);
+            F->cand_eps = eps_gamma;
+        }
+        dd_eval_cells(c, F->d_pix);  // per-pixel X moments of pi_i from the last B solve
+        cbar_glued_kernel<<<ab, kT, 0, hs>>>(F->narcs, F->d_tail, F->d_head, c->n, c->s, c->N,
+                                             c->d_m, F->d_cand, F->d_pix, c->h, F->d_cbar);
+    }
     if (cbar && hipMemcpyAsync(cbar, F->d_cbar, F->narcs * sizeof(double), hipMemcpyDeviceToHost, hs) !=
                     hipSuccess)
         return ffail(c, DD_EDEVICE, "flow_costs: copy failed");
@@ -435,7 +579,8 @@ extern "C" dd_status dd_mcf_solve(int32_t n, int32_t m, const int32_t* tail, con
     return r == -2 ? DD_EINVAL : DD_ENUMERIC;
 }
 
-extern "C" dd_status flow_update(dd_ctx* c, dd_flow_stats* out) {
+extern "C" dd_status flow_update(dd_ctx* c, int32_t candidate, double eps_gamma,
+                                 dd_flow_stats* out) {
     if (!c) return ffail(c, DD_EINVAL, "flow_update: null context");
     using clk = std::chrono::steady_clock;
     const auto t0 = clk::now();
@@ -444,7 +589,7 @@ extern "C" dd_status flow_update(dd_ctx* c, dd_flow_stats* out) {
     if (st != DD_OK) return st;
     FlowState* F = c->flow;
     std::vector<double> cbar(F->narcs);
-    st = flow_costs(c, cbar.data(), &na);
+    st = flow_costs(c, candidate, eps_gamma, cbar.data(), &na);
     if (st != DD_OK) return st;
     const auto t1 = clk::now();
     // integerise: masses by largest remainder to 2^40, costs to 2^30 / max|cbar|

@@ -61,6 +61,49 @@ def test_edge_costs_match_brute_force(N, s):
     g.close()
 
 
+@pytest.mark.parametrize("N,s,eg", [(16, 2, 0.5), (32, 2, 1.0), (32, 4, 0.5)])
+def test_glued_edge_costs_match_brute_force(N, s, eg):
+    """Gluing candidates from entropic gamma_ij (Remark "eps-gamma"): the device's edge costs,
+    from per-arc conditional moments of gamma_ij and per-pixel moments of pi_i, against the
+    oracle's brute force over X_j x supp(pi_i) with its own gamma_ij; then the same flow on both
+    sides."""
+    _need_gpu()
+    g, o, eps = _pair(N, s)
+    eps_gamma = eg * eps
+    print(f"glued flow costs N={N} s={s} eps_gamma={eps_gamma:.3e}", flush=True)
+    cg = g.flow_costs(eps_gamma=eps_gamma)
+    res = o.flow_update(truncate=True, eps_gamma=eps_gamma)
+    co = res["cbar"]
+    assert np.max(np.abs(cg - co)) <= 1e-10 * np.max(np.abs(co)), np.max(np.abs(cg - co))
+    # glued and product costs differ (the candidates are not the product)
+    assert np.max(np.abs(cg - g.flow_costs())) >= 1e-4 * np.max(np.abs(co))
+    g.flow_apply(res["w"])
+    G = _dense(g.nu_i_sparse(), N)
+    O = _dense(o.nu_i, N)
+    assert np.abs(G - O).sum() <= 1e-13
+    g.close()
+
+
+def test_glued_hybrid_schedule_decreases_objective():
+    """A, B, flow with gluing candidates: the objective after each B iteration never increases
+    (Prop. "flow update decreases score")."""
+    _need_gpu()
+    g, o, eps = _pair(32, 2, angle=90.0)
+    print("glued hybrid N=32 s=2", flush=True)
+    E = [g.evaluate()["primal"]]
+    for rnd in range(4):
+        st = g.flow_update(eps_gamma=0.5 * eps)
+        assert st["value"] <= 0.0
+        g.iterate("A", eps, fixed_iters=60)
+        g.iterate("B", eps, fixed_iters=60)
+        E.append(g.evaluate()["primal"])
+    E = np.array(E)
+    assert np.all(np.diff(E) <= 1e-9 * abs(E[0])), E
+    with pytest.raises(Exception):
+        g.flow_costs(eps_gamma=-1.0)
+    g.close()
+
+
 def test_flow_update_invariants_and_value():
     _need_gpu()
     g, o, eps = _pair(32, 2, angle=90.0)
