@@ -29,6 +29,7 @@ from __future__ import annotations
 
 import argparse
 import json
+import math
 import os
 import sys
 import time
@@ -120,7 +121,8 @@ def run_steps(ctx, w, n, k0, args, rule, init=None, flows=None):
         st["wall_ms"] = (time.perf_counter() - t0) * 1e3  # iterate synchronises the stream
         out.append(st)
         if flow_every and part == "B":
-            fs = ctx.flow_update()
+            eg = None if args.flow_eps_gamma is None else args.flow_eps_gamma / w.N ** 2
+            fs = ctx.flow_update(eps_gamma=eg)
             log(f"[bench] flow update: costs {fs['t_costs_ms']:.1f} ms, min-cost flow "
                 f"{fs['t_mcf_ms']:.1f} ms, assembly {fs['t_assemble_ms']:.1f} ms, "
                 f"moved mass {fs['moved_mass']:.3e}")
@@ -501,6 +503,12 @@ def main():
     ap.add_argument("--no-extra", action="store_true",
                     help="skip the float64 and 1024^2 records of the mix512 line")
     ap.add_argument("--extra-steps", type=int, default=4)
+    ap.add_argument("--no-global", action="store_true",
+                    help="skip the global Sinkhorn comparison record")
+    ap.add_argument("--global-max-iter", type=int, default=4000)
+    ap.add_argument("--flow-eps-gamma", type=float, default=None,
+                    help="flow workload: glued edge candidates at this eps_gamma (units of h^2); "
+                         "default: product candidates")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-compare", action="store_true")
     ap.add_argument("--replay", type=int, default=8)
@@ -563,8 +571,15 @@ def main():
                           "y_marginal_l1", "primal", "pd_gap")}
         line["size1024"] = rec
         if args.workload.startswith("ms"):
-            # the whole multiscale solve at the paper's arithmetic and stopping tolerance
+            # the whole multiscale solve at the paper's arithmetic and stopping tolerance, and
+            # the global Sinkhorn on the same problem
             line["full_solve"] = full_solve(args, args.workload, "f64", 1e-4)
+            if not args.no_global:
+                g = global_record(args, args.workload)
+                fs = line["full_solve"]
+                g["dd_full_solve_speedup"] = g["wall_s"] / fs["wall_s"]
+                g["dual_rel_diff_vs_dd_primal"] = abs(g["dual"] - fs["primal"]) / abs(fs["primal"])
+                line["global"] = g
     print(json.dumps(line), flush=True)
 
 
@@ -611,6 +626,48 @@ def full_solve(args, workload, prec_name, tol):
             "y_marginal_l1": ev["y_marginal_l1"],
             "schedule": "eps = 2h^2, h^2, h^2/2 per layer, finest 2h^2, h^2, h^2/2, h^2/4, "
                         f"{w.extra['layer_iters']} half-iterations per stage"}
+
+
+def global_record(args, workload):
+    """global_sinkhorn on the whole grid of the workload's marginals, with eps-scaling from
+    eps = 1 (the squared diameter scale) halving down to h^2/4, tolerance 1e-4 at every stage
+    (the paper's), warm-started across stages: the global GPU Sinkhorn of the paper's
+    comparison (Table 1), on the same GPU as the domain decomposition."""
+    import torch
+
+    import paper_2405_09400_amd as dd
+    import synth
+    w = synth.workload(workload, seed=args.seed)
+    N = w.N
+    dev = torch.device("cuda", torch.cuda.current_device())
+    mu = torch.tensor(w.mu, dtype=torch.float64, device=dev)
+    nu = torch.tensor(w.nu, dtype=torch.float64, device=dev)
+    a = torch.zeros((N, N), dtype=torch.float64, device=dev)
+    b = torch.zeros_like(a)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    its, terms, dev_ms, status = 0, 0.0, 0.0, 0
+    k = int(round(math.log2(N * N)))
+    stages = []
+    for e in range(k, -3, -1):
+        kappa = 2.0 ** e
+        status, st = dd.global_sinkhorn(mu, nu, kappa / N ** 2, a, b, tol=1e-4,
+                                        max_iter=args.global_max_iter, raise_on_error=False)
+        its += st["iters"]
+        terms += st["lse_terms"]
+        dev_ms += st["time_ms"]
+        stages.append(st["iters"])
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    D = float((a * mu).sum() + (b * nu).sum())
+    log(f"[bench] global Sinkhorn {N}x{N}: {wall:.1f} s, {its} iterations, err {st['err']:.2e}")
+    return {"solver": "global_sinkhorn (float64, whole grid, no domain decomposition)",
+            "grid": N, "tol": 1e-4, "wall_s": wall, "device_s": dev_ms / 1e3, "iterations": its,
+            "iterations_per_stage": stages, "final_err": st["err"],
+            "converged": bool(st["converged"]), "dual": D,
+            "lse_tterm_s": terms / (dev_ms * 1e-3) / 1e12,
+            "schedule": "eps = 2^k h^2 from 1 down to h^2/4, warm-started, tol 1e-4 per stage, "
+                        f"at most {args.global_max_iter} iterations per stage"}
 
 
 def measure(args, workload, prec, steps, warmup, replay=0, cpu=False):
