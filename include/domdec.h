@@ -253,6 +253,20 @@ typedef struct {
                           (0: single scale).  With L > 0 the context starts on the
                           (N / 2^L)^2 layer; domdec_refine moves to the next finer one.
                           N / 2^L must be a multiple of 2 s.                        */
+    /* Device-memory supplier (optional; both NULL: hipMalloc / hipFree).  With both set,
+       every device buffer of the context -- its layers, the stored nu_i, the composite work,
+       the cell solver's and the dual's workspaces and the flow update's structures -- comes
+       from dev_alloc(bytes, alloc_ud) and goes back through dev_free(ptr, alloc_ud), e.g. a
+       caching allocator of the caller's framework.  The memory must be usable on the
+       context's stream; the library returns a buffer only after every kernel that touches it
+       has been ordered before the return on that stream, so a stream-ordered caching
+       allocator may hand it out again at once.  dev_alloc returning NULL fails the call with
+       DD_ENOMEM.  The hooks run on the calling thread, from domdec_* / extract_* / flow_*
+       calls and domdec_free, never from a device callback.  Context-free entry points
+       (sinkhorn_batch, global_sinkhorn) and dd_net keep hipMalloc.                       */
+    void* (*dev_alloc)(size_t bytes, void* alloc_ud);
+    void (*dev_free)(void* ptr, void* alloc_ud);
+    void* alloc_ud;
 } dd_params;
 
 /*

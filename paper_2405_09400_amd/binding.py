@@ -54,9 +54,55 @@ class BatchStats(ctypes.Structure):
                 ("kernel_ms", ctypes.c_double * 3), ("kernel_terms", ctypes.c_double * 3)]
 
 
+# dd_params.dev_alloc / dev_free
+ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
+FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p)
+
+
 class Params(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int32), ("s", ctypes.c_int32), ("trunc", ctypes.c_double),
-                ("prec", ctypes.c_int32), ("levels", ctypes.c_int32)]
+                ("prec", ctypes.c_int32), ("levels", ctypes.c_int32), ("dev_alloc", ALLOC_FN),
+                ("dev_free", FREE_FN), ("alloc_ud", ctypes.c_void_p)]
+
+
+class TorchAllocator:
+    """dd_params hooks that take the context's device memory from PyTorch's caching allocator
+    on the context's stream (torch.cuda.caching_allocator_alloc / _delete).  `live` counts the
+    blocks the library holds, `peak_bytes` the most it held at once."""
+
+    def __init__(self, stream, device=None):
+        import torch
+        self._torch = torch
+        self._stream = stream
+        self._device = torch.cuda.current_device() if device is None else device
+        self._sizes = {}
+        self.live_bytes = 0
+        self.peak_bytes = 0
+        self.calls = 0
+        self.alloc_fn = ALLOC_FN(self._alloc)
+        self.free_fn = FREE_FN(self._free)
+
+    @property
+    def live(self) -> int:
+        return len(self._sizes)
+
+    def _alloc(self, nbytes, _ud):
+        try:
+            p = int(self._torch.cuda.caching_allocator_alloc(int(nbytes), self._device,
+                                                             self._stream))
+        except Exception:  # out of memory (or any failure): NULL -> DD_ENOMEM
+            return None
+        self._sizes[p] = int(nbytes)
+        self.live_bytes += int(nbytes)
+        self.peak_bytes = max(self.peak_bytes, self.live_bytes)
+        self.calls += 1
+        return p
+
+    def _free(self, ptr, _ud):
+        if not ptr:
+            return
+        self.live_bytes -= self._sizes.pop(int(ptr), 0)
+        self._torch.cuda.caching_allocator_delete(int(ptr))
 
 
 class IterStats(ctypes.Structure):
@@ -296,9 +342,11 @@ class DomDec:
     """A device-resident domain-decomposition state (dd_ctx) on the current HIP device."""
 
     def __init__(self, mu: np.ndarray, nu: np.ndarray, s: int, init=None, trunc: float = 1e-15,
-                 prec: int = DD_PREC_F32, stream=None, levels: int = 0):
+                 prec: int = DD_PREC_F32, stream=None, levels: int = 0, allocator=None):
         """levels > 0: multiscale; the context starts on the (N / 2^levels)^2 layer and refine()
-        moves to the next finer one (self.N is the grid side of the current layer)."""
+        moves to the next finer one (self.N is the grid side of the current layer).
+        allocator: None (the library's hipMalloc), "torch" (PyTorch's caching allocator on the
+        context's stream) or an object with alloc_fn / free_fn hooks (TorchAllocator's shape)."""
         import torch
         self.N = int(mu.shape[0]) >> int(levels)
         self.levels = int(levels)
@@ -307,6 +355,12 @@ class DomDec:
         mu64 = np.ascontiguousarray(mu.reshape(-1), dtype=np.float64)
         nu64 = np.ascontiguousarray(nu.reshape(-1), dtype=np.float64)
         p = Params(int(mu.shape[0]), self.s, float(trunc), int(prec), int(levels))
+        if allocator == "torch":
+            allocator = TorchAllocator(self._stream)
+        self.allocator = allocator  # keeps the hooks alive as long as the context
+        if allocator is not None:
+            p.dev_alloc = allocator.alloc_fn
+            p.dev_free = allocator.free_fn
         ctx = ctypes.c_void_p()
         dp = ctypes.POINTER(ctypes.c_double)
         i64p = ctypes.POINTER(ctypes.c_int64)

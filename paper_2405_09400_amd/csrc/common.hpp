@@ -77,10 +77,34 @@ const char* global_error();
             char b_[256];                                                                 \
             snprintf(b_, sizeof b_, "%s failed: %s (%s:%d)", #call, hipGetErrorString(e_), \
                      __FILE__, __LINE__);                                                 \
-            st_ret.code = DD_EDEVICE;                                                     \
+            st_ret.code = e_ == hipErrorOutOfMemory ? DD_ENOMEM : DD_EDEVICE;              \
             st_ret.msg = b_;                                                              \
             return st_ret;                                                                \
         }                                                                                 \
     } while (0)
+
+// Device-memory supplier of a context: the caller's hooks (dd_params.dev_alloc / dev_free)
+// when both are set, else hipMalloc / hipFree.  A hook allocation that returns NULL is
+// reported as out of memory.  Buffers are released only after every kernel that touches them
+// has been ordered before the release on the context's stream.
+struct Mem {
+    void* (*alloc)(size_t, void*) = nullptr;
+    void (*release)(void*, void*) = nullptr;
+    void* ud = nullptr;
+
+    template <typename P>
+    hipError_t get(P** p, size_t bytes) const {
+        if (!alloc) return hipMalloc(p, bytes);
+        *p = static_cast<P*>(alloc(bytes, ud));
+        return *p ? hipSuccess : hipErrorOutOfMemory;
+    }
+    void put(void* p) const {
+        if (!p) return;
+        if (alloc)
+            release(p, ud);
+        else
+            (void)hipFree(p);
+    }
+};
 
 }  // namespace dd

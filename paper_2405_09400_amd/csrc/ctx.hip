@@ -24,25 +24,25 @@ using namespace dd;
 namespace {
 
 template <typename P>
-Status grow(P*& p, size_t& cap, size_t need, Status& st, double slack = 1.25) {
+Status grow(const Mem& M, P*& p, size_t& cap, size_t need, Status& st, double slack = 1.25) {
     if (need <= cap && p) return st;
-    if (p) (void)hipFree(p);
+    M.put(p);
     p = nullptr;
     const size_t n = std::max<size_t>((size_t)(need * slack) + 16, 64);
-    DD_HIP(hipMalloc(&p, n * sizeof(P)), st);
+    DD_HIP(M.get(&p, n * sizeof(P)), st);
     cap = n;
     return st;
 }
 
 template <typename P>
-Status alloc(P*& p, size_t n, Status& st) {
-    DD_HIP(hipMalloc(&p, std::max<size_t>(n, 1) * sizeof(P)), st);
+Status alloc(const Mem& M, P*& p, size_t n, Status& st) {
+    DD_HIP(M.get(&p, std::max<size_t>(n, 1) * sizeof(P)), st);
     return st;
 }
 
 template <typename P>
-Status upload(P*& p, const std::vector<P>& v, hipStream_t s, Status& st) {
-    if (alloc(p, v.size(), st).code) return st;
+Status upload(const Mem& M, P*& p, const std::vector<P>& v, hipStream_t s, Status& st) {
+    if (alloc(M, p, v.size(), st).code) return st;
     if (!v.empty()) {
         // the host vector may be a temporary: finish the copy before returning
         DD_HIP(hipMemcpyAsync(p, v.data(), v.size() * sizeof(P), hipMemcpyHostToDevice, s), st);
@@ -59,11 +59,18 @@ dd_status fail(dd_ctx* c, dd_status code, const std::string& m) {
 
 dd_status fail(dd_ctx* c, const Status& s) { return fail(c, s.code, s.msg); }
 
+// every device buffer of the context, its solver workspace and its dual workspace from M
+void use_mem(dd_ctx* c, const Mem& M) {
+    c->mem = M;
+    c->skw.mem = M;
+    c->dual.mem = M;
+}
+
 }  // namespace
 
 void dd_ctx_release(dd_ctx* c) {
-    auto F = [](auto& p) {
-        if (p) (void)hipFree(p);
+    auto F = [c](auto& p) {
+        c->mem.put(p);
         p = nullptr;
     };
     F(c->d_mu);
@@ -179,34 +186,30 @@ Status setup_layer(dd_ctx* c, int N, const double* mu, const double* nu) {
         c->part[q].ncell = nc * nc;
         c->pmembers[q] = mem;
         c->pxorig[q] = xo;
-        if (upload(c->part[q].members, mem, hs, st).code) return st;
-        if (upload(c->part[q].xorig, xo, hs, st).code) return st;
-        double* plm = nullptr;
-        if (upload(plm, lm, hs, st).code) return st;
-        c->d_logmu[q] = plm;
-        double* pa = nullptr;
-        if (upload(pa, std::vector<double>(lm.size(), 0.0), hs, st).code) return st;
-        c->d_a[q] = pa;
-        if (upload(c->d_gst[q], std::vector<int32_t>(2 * (size_t)nc * nc, 0), hs, st).code)
+        if (upload(c->mem, c->part[q].members, mem, hs, st).code) return st;
+        if (upload(c->mem, c->part[q].xorig, xo, hs, st).code) return st;
+        if (upload(c->mem, c->d_logmu[q], lm, hs, st).code) return st;
+        if (upload(c->mem, c->d_a[q], std::vector<double>(lm.size(), 0.0), hs, st).code) return st;
+        if (upload(c->mem, c->d_gst[q], std::vector<int32_t>(2 * (size_t)nc * nc, 0), hs, st).code)
             return st;
     }
     std::vector<double> vmu(mu, mu + NN), vnu(nu, nu + NN), lnu(NN);
     for (int64_t k = 0; k < NN; ++k) lnu[k] = nu[k] > 0 ? std::log(nu[k]) : -INFINITY;
-    if (upload(c->d_mu, vmu, hs, st).code || upload(c->d_nu, vnu, hs, st).code ||
-        upload(c->d_lognu_glob, lnu, hs, st).code || upload(c->d_m, c->m, hs, st).code)
+    if (upload(c->mem, c->d_mu, vmu, hs, st).code || upload(c->mem, c->d_nu, vnu, hs, st).code ||
+        upload(c->mem, c->d_lognu_glob, lnu, hs, st).code || upload(c->mem, c->d_m, c->m, hs, st).code)
         return st;
     const int mc = std::max(c->part[0].ncell, c->part[1].ncell);
-    if (alloc(c->S.box, 4 * (size_t)c->nI, st).code || alloc(c->S.base, c->nI + 1, st).code ||
-        alloc(c->S2.box, 4 * (size_t)c->nI, st).code || alloc(c->S2.base, c->nI + 1, st).code ||
-        alloc(c->C.dims, 2 * (size_t)mc, st).code || alloc(c->C.orig, 2 * (size_t)mc, st).code ||
-        alloc(c->C.shift, 2 * (size_t)mc, st).code || alloc(c->C.gofs, 2 * (size_t)mc, st).code ||
-        alloc(c->C.size, mc, st).code || alloc(c->C.base, mc + 1, st).code ||
-        alloc(c->C.info, 8, st).code || alloc(c->d_py2, c->nI, st).code ||
-        alloc(c->d_nsize, c->nI, st).code || alloc(c->d_flags, c->nI + 1, st).code ||
-        alloc(c->d_iters, mc, st).code || alloc(c->d_cerr, mc, st).code ||
-        alloc(c->d_scratch, std::max<int64_t>(NN, c->nI), st).code ||
-        alloc(c->d_cell_out, 4 * (size_t)mc, st).code ||
-        alloc(c->d_basic_out, 3 * (size_t)c->nI, st).code || alloc(c->d_eval, 8, st).code)
+    if (alloc(c->mem, c->S.box, 4 * (size_t)c->nI, st).code || alloc(c->mem, c->S.base, c->nI + 1, st).code ||
+        alloc(c->mem, c->S2.box, 4 * (size_t)c->nI, st).code || alloc(c->mem, c->S2.base, c->nI + 1, st).code ||
+        alloc(c->mem, c->C.dims, 2 * (size_t)mc, st).code || alloc(c->mem, c->C.orig, 2 * (size_t)mc, st).code ||
+        alloc(c->mem, c->C.shift, 2 * (size_t)mc, st).code || alloc(c->mem, c->C.gofs, 2 * (size_t)mc, st).code ||
+        alloc(c->mem, c->C.size, mc, st).code || alloc(c->mem, c->C.base, mc + 1, st).code ||
+        alloc(c->mem, c->C.info, 8, st).code || alloc(c->mem, c->d_py2, c->nI, st).code ||
+        alloc(c->mem, c->d_nsize, c->nI, st).code || alloc(c->mem, c->d_flags, c->nI + 1, st).code ||
+        alloc(c->mem, c->d_iters, mc, st).code || alloc(c->mem, c->d_cerr, mc, st).code ||
+        alloc(c->mem, c->d_scratch, std::max<int64_t>(NN, c->nI), st).code ||
+        alloc(c->mem, c->d_cell_out, 4 * (size_t)mc, st).code ||
+        alloc(c->mem, c->d_basic_out, 3 * (size_t)c->nI, st).code || alloc(c->mem, c->d_eval, 8, st).code)
         return st;
     return st;
 }
@@ -314,7 +317,7 @@ Status boxes_from_host(dd_ctx* c, const double* mu, const double* nu, int64_t n_
         st.msg = "domdec_init: copying the initial coupling failed";
         return st;
     }
-    if (upload(c->S.data, data, hs, st).code) return st;
+    if (upload(c->mem, c->S.data, data, hs, st).code) return st;
     c->S.cap = std::max<size_t>(data.size(), 1);
     DD_HIP(hipStreamSynchronize(hs), st);
     return st;
@@ -360,7 +363,11 @@ extern "C" dd_status domdec_init(const dd_params* prm, const double* mu, const d
     if (std::fabs(smu - 1.0) > 1e-12 || std::fabs(snu - 1.0) > 1e-12)
         return fail(nullptr, DD_EINVAL, "domdec_init: mu and nu must each sum to 1 (within 1e-12)");
 
+    if ((prm->dev_alloc == nullptr) != (prm->dev_free == nullptr))
+        return fail(nullptr, DD_EINVAL, "domdec_init: dev_alloc and dev_free must both be set or "
+                                        "both be NULL");
     dd_ctx* c = new dd_ctx();
+    use_mem(c, Mem{prm->dev_alloc, prm->dev_free, prm->alloc_ud});
     c->s = s;
     c->trunc = prm->trunc;
     c->prec = prm->prec;
@@ -452,6 +459,7 @@ extern "C" dd_status domdec_refine(dd_ctx* c) {
     if (st.code) return fail(c, st);
     // the finer layer, its coupling and its potentials
     dd_ctx* f = new dd_ctx();
+    use_mem(f, c->mem);
     f->s = c->s;
     f->trunc = c->trunc;
     f->prec = c->prec;
@@ -471,7 +479,7 @@ extern "C" dd_status domdec_refine(dd_ctx* c) {
             st.msg = "domdec_refine: reading the refined sizes failed";
         }
     }
-    if (!st.code && !grow(f->S.data, f->S.cap, (size_t)std::max<int64_t>(total, 1), st).code) {
+    if (!st.code && !grow(c->mem, f->S.data, f->S.cap, (size_t)std::max<int64_t>(total, 1), st).code) {
         launch_refine_values(f->n, c->n, Nc, c->S, c->d_m, c->d_nu, f->S.base, f->d_m, f->d_nu,
                              f->S.data, hs);
         const double kappa_f = a.kappa_eval * 4.0;  // the same eps in units of the finer h^2
@@ -518,10 +526,10 @@ static dd_status iterate_impl(dd_ctx* c, int p, double eps, const dd_sinkhorn_op
         hipStreamSynchronize(hs) != hipSuccess)
         return fail(c, DD_EDEVICE, "domdec_iterate: reading composite sizes failed");
     const int mw1 = info[0], mw2 = info[1];
-    if (grow(c->d_nuJ, c->nuJ_cap, (size_t)total, st).code ||
-        grow(c->d_lognu, c->lognu_cap, (size_t)total, st).code ||
-        grow(c->d_b, c->b_cap, (size_t)total, st).code ||
-        grow(c->d_tmp, c->tmp_cap, 4 * (size_t)total, st).code)
+    if (grow(c->mem, c->d_nuJ, c->nuJ_cap, (size_t)total, st).code ||
+        grow(c->mem, c->d_lognu, c->lognu_cap, (size_t)total, st).code ||
+        grow(c->mem, c->d_b, c->b_cap, (size_t)total, st).code ||
+        grow(c->mem, c->d_tmp, c->tmp_cap, 4 * (size_t)total, st).code)
         return fail(c, st);
     double* lognu = c->d_lognu;
     double* bpot = c->d_b;
@@ -532,7 +540,7 @@ static dd_status iterate_impl(dd_ctx* c, int p, double eps, const dd_sinkhorn_op
     // the zero or previous-iterate start; a copy is kept as the base of the learned start's
     // training samples (domdec_net_samples)
     const size_t na = (size_t)nc * c->AS * c->AS;
-    if (grow(c->d_a0, c->a0_cap, na, st).code) return fail(c, st);
+    if (grow(c->mem, c->d_a0, c->a0_cap, na, st).code) return fail(c, st);
     const int use_prev = (o.init != DD_INIT_ZERO && c->visited[p]) ? 1 : 0;
     launch_warm_start(P, c->C, c->AS, apot, c->d_gst[p], c->kappa_a[p], kappa, use_prev, hs);
     if (hipMemcpyAsync(c->d_a0, apot, na * sizeof(double), hipMemcpyDeviceToDevice, hs) !=
@@ -541,8 +549,8 @@ static dd_status iterate_impl(dd_ctx* c, int p, double eps, const dd_sinkhorn_op
     if (o.init == DD_INIT_NET) {
         // learned start: features of the previous-iterate start -> net -> one X-update, over
         // the whole box, of the corrected Y potential
-        if (grow(c->d_nx, c->nx_cap, (size_t)nc * kNetCin * kNetWin * kNetWin, st).code ||
-            grow(c->d_ng, c->ng_cap, (size_t)nc * kNetWin * kNetWin, st).code)
+        if (grow(c->mem, c->d_nx, c->nx_cap, (size_t)nc * kNetCin * kNetWin * kNetWin, st).code ||
+            grow(c->mem, c->d_ng, c->ng_cap, (size_t)nc * kNetWin * kNetWin, st).code)
             return fail(c, st);
         launch_net_features(nc, c->AS, c->C.dims, c->C.shift, c->C.base, logmu, lognu, apot,
                             kappa, nullptr, c->d_nx, nullptr, nullptr, hs);
@@ -588,7 +596,7 @@ static dd_status iterate_impl(dd_ctx* c, int p, double eps, const dd_sinkhorn_op
             hipSuccess ||
         hipStreamSynchronize(hs) != hipSuccess)
         return fail(c, DD_EDEVICE, "domdec_iterate: reading truncated sizes failed");
-    if (grow(c->S2.data, c->S2.cap, (size_t)ntot, st).code) return fail(c, st);
+    if (grow(c->mem, c->S2.data, c->S2.cap, (size_t)ntot, st).code) return fail(c, st);
     launch_compact(P, c->C, c->d_tmp, c->trunc, c->S2.box, c->S2.base, c->d_flags, c->S2.data, hs);
     std::swap(c->S, c->S2);
     (void)hipEventRecord(c->ev[3], hs);
@@ -913,14 +921,14 @@ extern "C" dd_status domdec_save(dd_ctx* c) {
             hipSuccess ||
         hipStreamSynchronize(hs) != hipSuccess)
         return fail(c, DD_EDEVICE, "domdec_save: copy failed");
-    if ((!S.box && alloc(S.box, 4 * (size_t)c->nI, st).code) ||
-        (!S.base && alloc(S.base, (size_t)c->nI + 1, st).code) ||
-        grow(S.data, S.data_cap, (size_t)std::max<int64_t>(ntot, 1), st).code)
+    if ((!S.box && alloc(c->mem, S.box, 4 * (size_t)c->nI, st).code) ||
+        (!S.base && alloc(c->mem, S.base, (size_t)c->nI + 1, st).code) ||
+        grow(c->mem, S.data, S.data_cap, (size_t)std::max<int64_t>(ntot, 1), st).code)
         return fail(c, st);
     for (int q = 0; q < 2; ++q) {
         const size_t nc = c->part[q].ncell;
-        if ((!S.a[q] && alloc(S.a[q], nc * c->AS * c->AS, st).code) ||
-            (!S.gst[q] && alloc(S.gst[q], 2 * nc, st).code))
+        if ((!S.a[q] && alloc(c->mem, S.a[q], nc * c->AS * c->AS, st).code) ||
+            (!S.gst[q] && alloc(c->mem, S.gst[q], 2 * nc, st).code))
             return fail(c, st);
     }
     bool ok = d2d(S.box, c->S.box, 4 * (size_t)c->nI * sizeof(int32_t), hs) == hipSuccess &&
@@ -946,7 +954,7 @@ extern "C" dd_status domdec_restore(dd_ctx* c) {
     if (!S.valid) return fail(c, DD_ESTATE, "domdec_restore: nothing saved");
     Status st;
     const hipStream_t hs = c->st;
-    if (grow(c->S.data, c->S.cap, (size_t)std::max<int64_t>(S.ntot, 1), st).code)
+    if (grow(c->mem, c->S.data, c->S.cap, (size_t)std::max<int64_t>(S.ntot, 1), st).code)
         return fail(c, st);
     bool ok = d2d(c->S.box, S.box, 4 * (size_t)c->nI * sizeof(int32_t), hs) == hipSuccess &&
               d2d(c->S.base, S.base, ((size_t)c->nI + 1) * sizeof(int64_t), hs) == hipSuccess &&

@@ -20,6 +20,7 @@ struct dd_ctx {
     int N = 0, s = 0, n = 0, nI = 0, AS = 0, prec = DD_PREC_F32;
     double h = 0.0, trunc = 1e-15;
     hipStream_t st = nullptr;
+    dd::Mem mem;  // device-memory supplier of every buffer below and of the workspaces
     std::string err;
     std::vector<double> m;  // basic cell masses (host copy)
     std::vector<int32_t> pmembers[2], pxorig[2];

@@ -144,11 +144,11 @@ Status stitched_alpha(const DualArgs& a, DualWork& w, hipStream_t st, const doub
     const int nI = n * n;
     constexpr int kParts = 1024;
     if (!w.buf) {
-        DD_HIP(hipMalloc(&w.buf, (size_t)5 * N2 * sizeof(double)), S);
-        DD_HIP(hipMalloc(&w.d, (size_t)nI * sizeof(double)), S);
-        DD_HIP(hipMalloc(&w.own, (size_t)nI * sizeof(int32_t)), S);
-        DD_HIP(hipMalloc(&w.sA, (size_t)a.ncell[0] * sizeof(double)), S);
-        DD_HIP(hipMalloc(&w.part, kParts * sizeof(double)), S);
+        DD_HIP(w.mem.get(&w.buf, (size_t)5 * N2 * sizeof(double)), S);
+        DD_HIP(w.mem.get(&w.d, (size_t)nI * sizeof(double)), S);
+        DD_HIP(w.mem.get(&w.own, (size_t)nI * sizeof(int32_t)), S);
+        DD_HIP(w.mem.get(&w.sA, (size_t)a.ncell[0] * sizeof(double)), S);
+        DD_HIP(w.mem.get(&w.part, kParts * sizeof(double)), S);
     }
     double* fA = w.buf;
     double* fB = w.buf + N2;
@@ -242,8 +242,10 @@ Status stitched_dual(const DualArgs& a, DualWork& w, hipStream_t st, double* D) 
 
 void dual_release(DualWork& w) {
     for (void* p : {(void*)w.buf, (void*)w.d, (void*)w.own, (void*)w.sA, (void*)w.part})
-        if (p) (void)hipFree(p);
+        w.mem.put(p);
+    const Mem m = w.mem;
     w = DualWork{};
+    w.mem = m;
 }
 
 }  // namespace dd

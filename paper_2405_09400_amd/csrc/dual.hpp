@@ -24,6 +24,7 @@ struct DualWork {
     int32_t* own = nullptr;  // [nI]
     double* sA = nullptr;    // [ncell A]
     double* part = nullptr;  // partial sums
+    Mem mem;                 // supplier of the buffers above
 };
 
 // alpha+ / eps_eval on every pixel (device [N*N], inside w): the A cells' potentials with the

@@ -1197,13 +1197,13 @@ Status fast_solve(const SkBatch& p, const dd_sinkhorn_opts& o, hipStream_t st, S
             return S;
         w.order_cap = n;
     } else if (n > w.order_cap) {
-        if (w.order) (void)hipFree(w.order);
-        if (w.scr_off) (void)hipFree(w.scr_off);
+        w.mem.put(w.order);
+        w.mem.put(w.scr_off);
         w.order = nullptr;
         w.scr_off = nullptr;
         w.order_cap = std::max(n, 1024);
-        DD_HIP(hipMalloc(&w.order, w.order_cap * sizeof(int32_t)), S);
-        DD_HIP(hipMalloc(&w.scr_off, w.order_cap * sizeof(int64_t)), S);
+        DD_HIP(w.mem.get(&w.order, w.order_cap * sizeof(int32_t)), S);
+        DD_HIP(w.mem.get(&w.scr_off, w.order_cap * sizeof(int64_t)), S);
     }
     if (n > 0) {
         DD_HIP(hipMemcpyAsync(w.order, ord.data(), n * sizeof(int32_t), hipMemcpyHostToDevice, st),

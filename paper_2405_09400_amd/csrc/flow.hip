@@ -358,8 +358,8 @@ dd_status ffail(dd_ctx* c, dd_status code, const std::string& m) {
 }
 
 template <typename P>
-bool dalloc(P*& p, size_t n) {
-    return hipMalloc(&p, std::max<size_t>(n, 1) * sizeof(P)) == hipSuccess;
+bool dalloc(const dd::Mem& M, P*& p, size_t n) {
+    return M.get(&p, std::max<size_t>(n, 1) * sizeof(P)) == hipSuccess;
 }
 
 // Build the static flow structures on first use.
@@ -409,12 +409,12 @@ dd_status flow_prepare(dd_ctx* c) {
             xstat[3 * j + 1] = x1 / c->m[j];
             xstat[3 * j + 2] = x2 / c->m[j];
         }
-    bool ok = dalloc(F->d_tail, F->narcs) && dalloc(F->d_head, F->narcs) &&
-              dalloc(F->d_in_start, nI + 1) && dalloc(F->d_in_arc, F->narcs) &&
-              dalloc(F->d_xstat, 3 * (size_t)nI) && dalloc(F->d_ystat, 3 * (size_t)nI) &&
-              dalloc(F->d_ys2, nI) && dalloc(F->d_cbar, F->narcs) && dalloc(F->d_w, F->narcs) &&
-              dalloc(F->d_nbox, 4 * (size_t)nI) && dalloc(F->d_nsize, nI) &&
-              dalloc(F->d_flags, nI + 1);
+    bool ok = dalloc(c->mem, F->d_tail, F->narcs) && dalloc(c->mem, F->d_head, F->narcs) &&
+              dalloc(c->mem, F->d_in_start, nI + 1) && dalloc(c->mem, F->d_in_arc, F->narcs) &&
+              dalloc(c->mem, F->d_xstat, 3 * (size_t)nI) && dalloc(c->mem, F->d_ystat, 3 * (size_t)nI) &&
+              dalloc(c->mem, F->d_ys2, nI) && dalloc(c->mem, F->d_cbar, F->narcs) && dalloc(c->mem, F->d_w, F->narcs) &&
+              dalloc(c->mem, F->d_nbox, 4 * (size_t)nI) && dalloc(c->mem, F->d_nsize, nI) &&
+              dalloc(c->mem, F->d_flags, nI + 1);
     ok = ok &&
          hipMemcpy(F->d_tail, F->tail.data(), F->narcs * 4, hipMemcpyHostToDevice) == hipSuccess &&
          hipMemcpy(F->d_head, F->head.data(), F->narcs * 4, hipMemcpyHostToDevice) == hipSuccess &&
@@ -431,8 +431,8 @@ dd_status flow_prepare(dd_ctx* c) {
 void flow_release(dd_ctx* c) {
     FlowState* F = c->flow;
     if (!F) return;
-    auto Fr = [](auto& p) {
-        if (p) (void)hipFree(p);
+    auto Fr = [c](auto& p) {
+        c->mem.put(p);
         p = nullptr;
     };
     Fr(F->d_tail);
@@ -480,9 +480,9 @@ extern "C" dd_status flow_costs(dd_ctx* c, int32_t candidate, double eps_gamma, 
                                        F->d_cbar);
     } else {
         const int S2 = c->s * c->s;
-        if (!F->d_cand && !dalloc(F->d_cand, (size_t)F->narcs * S2 * 3))
+        if (!F->d_cand && !dalloc(c->mem, F->d_cand, (size_t)F->narcs * S2 * 3))
             return ffail(c, DD_ENOMEM, "flow_costs: allocating the candidates failed");
-        if (!F->d_pix && !dalloc(F->d_pix, (size_t)c->N * c->N * 3))
+        if (!F->d_pix && !dalloc(c->mem, F->d_pix, (size_t)c->N * c->N * 3))
             return ffail(c, DD_ENOMEM, "flow_costs: allocating the pixel moments failed");
         if (F->cand_eps != eps_gamma) {
             gamma_kernel<<<ab, kT, 0, hs>>>(F->narcs, F->d_tail, F->d_head, c->n, c->s, c->N,
@@ -519,15 +519,15 @@ extern "C" dd_status flow_apply(dd_ctx* c, const double* w) {
         hipStreamSynchronize(hs) != hipSuccess)
         return ffail(c, DD_EDEVICE, "flow_apply: reading sizes failed");
     if ((size_t)utot > F->tmp_cap) {
-        if (F->d_tmp) (void)hipFree(F->d_tmp);
+        c->mem.put(F->d_tmp);
         F->d_tmp = nullptr;
         F->tmp_cap = (size_t)(utot * 1.25) + 64;
-        if (hipMalloc(&F->d_tmp, F->tmp_cap * sizeof(double)) != hipSuccess)
+        if (c->mem.get(&F->d_tmp, F->tmp_cap * sizeof(double)) != hipSuccess)
             return ffail(c, DD_ENOMEM, "flow_apply: out of memory");
     }
     // keep the union bases: copy into a scratch int64 array (reuse d_nsize after the scan)
     int64_t* ubase = nullptr;
-    if (hipMalloc(&ubase, (nI + 1) * sizeof(int64_t)) != hipSuccess)
+    if (c->mem.get(&ubase, (nI + 1) * sizeof(int64_t)) != hipSuccess)
         return ffail(c, DD_ENOMEM, "flow_apply: out of memory");
     (void)hipMemcpyAsync(ubase, c->S2.base, (nI + 1) * sizeof(int64_t), hipMemcpyDeviceToDevice, hs);
     const int nb = std::max(1, std::min(nI, 4096));
@@ -540,25 +540,25 @@ extern "C" dd_status flow_apply(dd_ctx* c, const double* w) {
     int64_t ntot = 0;
     if (hipMemcpyAsync(&ntot, c->S2.base + nI, sizeof ntot, hipMemcpyDeviceToHost, hs) != hipSuccess ||
         hipStreamSynchronize(hs) != hipSuccess) {
-        (void)hipFree(ubase);
+        c->mem.put(ubase);
         return ffail(c, DD_EDEVICE, "flow_apply: reading sizes failed");
     }
     if ((size_t)ntot > c->S2.cap) {
-        if (c->S2.data) (void)hipFree(c->S2.data);
+        c->mem.put(c->S2.data);
         c->S2.data = nullptr;
         c->S2.cap = (size_t)(ntot * 1.25) + 64;
-        if (hipMalloc(&c->S2.data, c->S2.cap * sizeof(double)) != hipSuccess) {
-            (void)hipFree(ubase);
+        if (c->mem.get(&c->S2.data, c->S2.cap * sizeof(double)) != hipSuccess) {
+            c->mem.put(ubase);
             return ffail(c, DD_ENOMEM, "flow_apply: out of memory");
         }
     }
     fcompact_kernel<<<nb, kT, 0, hs>>>(nI, F->d_nbox, ubase, F->d_tmp, c->trunc, c->S2.box, c->S2.base,
                                        F->d_flags, c->S2.data);
     if (hipStreamSynchronize(hs) != hipSuccess || hipGetLastError() != hipSuccess) {
-        (void)hipFree(ubase);
+        c->mem.put(ubase);
         return ffail(c, DD_EDEVICE, "flow_apply: a kernel failed");
     }
-    (void)hipFree(ubase);
+    c->mem.put(ubase);
     std::swap(c->S, c->S2);
     // the composite plans no longer describe the state: X-marginal / primal need a new iteration
     c->last_part = -1;

@@ -958,8 +958,8 @@ Status sk_work_reserve(SkWork& w, int ncells, size_t a_n) {
         return st;
     }
     if (!w.ctrl) {
-        DD_HIP(hipMalloc(&w.ctrl, 16 * sizeof(int)), st);
-        DD_HIP(hipMalloc(&w.dtot, 8 * sizeof(double)), st);
+        DD_HIP(w.mem.get(&w.ctrl, 16 * sizeof(int)), st);
+        DD_HIP(w.mem.get(&w.dtot, 8 * sizeof(double)), st);
         DD_HIP(hipEventCreate(&w.ev0), st);
         DD_HIP(hipEventCreate(&w.ev1), st);
         DD_HIP(hipEventCreate(&w.ev2), st);
@@ -972,25 +972,25 @@ Status sk_work_reserve(SkWork& w, int ncells, size_t a_n) {
         DD_HIP(hipEventCreateWithFlags(&w.evj3, hipEventDisableTiming), st);
     }
     if (ncells > w.cap) {
-        if (w.cell_err) (void)hipFree(w.cell_err);
-        if (w.cell_mass) (void)hipFree(w.cell_mass);
-        if (w.cell_iters) (void)hipFree(w.cell_iters);
+        w.mem.put(w.cell_err);
+        w.mem.put(w.cell_mass);
+        w.mem.put(w.cell_iters);
         w.cell_err = nullptr;
         w.cell_mass = nullptr;
         w.cell_iters = nullptr;
         const int cap = std::max(ncells, 1024);
-        DD_HIP(hipMalloc(&w.cell_err, cap * sizeof(double)), st);
-        DD_HIP(hipMalloc(&w.cell_mass, cap * sizeof(double)), st);
-        DD_HIP(hipMalloc(&w.cell_iters, cap * sizeof(int32_t)), st);
-        if (w.iters64) (void)hipFree(w.iters64);
+        DD_HIP(w.mem.get(&w.cell_err, cap * sizeof(double)), st);
+        DD_HIP(w.mem.get(&w.cell_mass, cap * sizeof(double)), st);
+        DD_HIP(w.mem.get(&w.cell_iters, cap * sizeof(int32_t)), st);
+        w.mem.put(w.iters64);
         w.iters64 = nullptr;
-        DD_HIP(hipMalloc(&w.iters64, cap * sizeof(int32_t)), st);
+        DD_HIP(w.mem.get(&w.iters64, cap * sizeof(int32_t)), st);
         w.cap = cap;
     }
     if (a_n > w.a_alt_n) {
-        if (w.a_alt) (void)hipFree(w.a_alt);
+        w.mem.put(w.a_alt);
         w.a_alt = nullptr;
-        DD_HIP(hipMalloc(&w.a_alt, a_n * sizeof(double)), st);
+        DD_HIP(w.mem.get(&w.a_alt, a_n * sizeof(double)), st);
         w.a_alt_n = a_n;
     }
     return st;
@@ -998,18 +998,18 @@ Status sk_work_reserve(SkWork& w, int ncells, size_t a_n) {
 
 void sk_work_release(SkWork& w) {
     if (w.arena) return;  // no-allocation mode: nothing of its own to release
-    if (w.order) (void)hipFree(w.order);
-    if (w.scr_off) (void)hipFree(w.scr_off);
-    if (w.order64) (void)hipFree(w.order64);
-    if (w.scr_off64) (void)hipFree(w.scr_off64);
-    if (w.big) (void)hipFree(w.big);
-    if (w.iters64) (void)hipFree(w.iters64);
-    if (w.a_alt) (void)hipFree(w.a_alt);
-    if (w.cell_err) (void)hipFree(w.cell_err);
-    if (w.cell_mass) (void)hipFree(w.cell_mass);
-    if (w.cell_iters) (void)hipFree(w.cell_iters);
-    if (w.ctrl) (void)hipFree(w.ctrl);
-    if (w.dtot) (void)hipFree(w.dtot);
+    w.mem.put(w.order);
+    w.mem.put(w.scr_off);
+    w.mem.put(w.order64);
+    w.mem.put(w.scr_off64);
+    w.mem.put(w.big);
+    w.mem.put(w.iters64);
+    w.mem.put(w.a_alt);
+    w.mem.put(w.cell_err);
+    w.mem.put(w.cell_mass);
+    w.mem.put(w.cell_iters);
+    w.mem.put(w.ctrl);
+    w.mem.put(w.dtot);
     if (w.ev0) (void)hipEventDestroy(w.ev0);
     if (w.ev1) (void)hipEventDestroy(w.ev1);
     if (w.ev2) (void)hipEventDestroy(w.ev2);
@@ -1026,7 +1026,9 @@ void sk_work_release(SkWork& w) {
             (void)hipStreamSynchronize(*sp);
             (void)hipStreamDestroy(*sp);
         }
+    const Mem m = w.mem;
     w = SkWork{};
+    w.mem = m;
 }
 
 namespace {
@@ -1507,13 +1509,13 @@ Status sk_solve(const SkBatch& p, const dd_sinkhorn_opts& o, hipStream_t caller_
                 return E;
             cap = p.ncells;
         } else if (p.ncells > cap) {
-            if (dev_ord) (void)hipFree(dev_ord);
-            if (dev_off) (void)hipFree(dev_off);
+            w.mem.put(dev_ord);
+            w.mem.put(dev_off);
             dev_ord = nullptr;
             dev_off = nullptr;
             cap = std::max(p.ncells, 1024);
-            DD_HIP(hipMalloc(&dev_ord, cap * sizeof(int32_t)), E);
-            DD_HIP(hipMalloc(&dev_off, cap * sizeof(int64_t)), E);
+            DD_HIP(w.mem.get(&dev_ord, cap * sizeof(int32_t)), E);
+            DD_HIP(w.mem.get(&dev_off, cap * sizeof(int64_t)), E);
         }
         DD_HIP(hipMemcpyAsync(dev_ord, pl.ord.data(), pl.ord.size() * 4, hipMemcpyHostToDevice, st),
                E);
@@ -1546,9 +1548,9 @@ Status sk_solve(const SkBatch& p, const dd_sinkhorn_opts& o, hipStream_t caller_
     } else if (scr > 0) {
         const size_t need = (size_t)scr * sizeof(double) + 64;
         if (need > w.big_bytes) {
-            if (w.big) (void)hipFree(w.big);
+            w.mem.put(w.big);
             w.big = nullptr;
-            DD_HIP(hipMalloc(&w.big, need), S);
+            DD_HIP(w.mem.get(&w.big, need), S);
             w.big_bytes = need;
         }
     }

@@ -61,6 +61,7 @@ struct SkWork {
     // times).
     char* arena = nullptr;
     size_t arena_bytes = 0, arena_used = 0;
+    Mem mem;  // supplier of the buffers above outside no-allocation mode
 };
 
 // Carve n elements from the no-allocation arena (256-byte aligned); DD_EINVAL when the arena

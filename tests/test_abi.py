@@ -10,7 +10,9 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 def _declared():
     text = open(os.path.join(ROOT, "include", "domdec.h")).read()
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    names = re.findall(r"^\s*(?:const\s+)?[a-z_0-9]+\s*\*?\s*([a-z_0-9]+)\s*\(", text, flags=re.M)
+    # "type name(" or "type* name(" at the start of a line (not "type (*member)(")
+    names = re.findall(r"^\s*(?:const\s+)?[a-z_0-9]+(?:\s+|\s*\*\s*)([a-z_0-9]+)\s*\(", text,
+                       flags=re.M)
     return sorted(set(names))
 
 
