@@ -390,6 +390,31 @@ class DomDec:
                 e[src] += e[dst]
                 e[dst] = 0.0
 
+    # -- batching and clustering (App. A.1 "Batching and clustering") ------------
+    def composite_box_dims(self, which: str) -> np.ndarray:
+        """(W1, W2) of each composite cell's Y bounding box: the smallest pixel rectangle
+        holding the supports of its basic cells' nu_i (rows, then columns)."""
+        N = self.N
+        out = np.zeros((len(self.parts[which]), 2), dtype=np.int64)
+        for J, basic in enumerate(self.parts[which]):
+            sup = np.concatenate([self.nu_i[i][0] for i in basic])
+            r, c = sup // N, sup % N
+            out[J] = (r.max() - r.min() + 1, c.max() - c.min() + 1)
+        return out
+
+    def iterate_batched(self, which: str, eps: float, k: int, **kw) -> dict:
+        """CreateBatches / CombineBatches: cluster the composite cells of `which` by their
+        bounding-box dimensions (kmeans_boxes) and run DomDecIter on one cluster after the
+        other, each with its own stopping test.  The clusters are formed from the state
+        before the iteration; the cells of one partition are independent, so solving them
+        in sequence is the same as one batch apart from the stopping rule's scope."""
+        groups = kmeans_boxes(self.composite_box_dims(which), k)
+        stats = []
+        for g in groups:
+            stats.append(self.iterate(which, eps, cells=g, **kw))
+        self.last_which = None  # the composite plans were split over the batches
+        return {"batches": groups, "stats": stats}
+
     # -- ε rescaling is implicit: alpha is kept in energy units across eps changes.
 
     # -- evaluation -----------------------------------------------------------
@@ -707,6 +732,40 @@ class DomDec:
 # ---------------------------------------------------------------------------
 # Global problems (tiny grids)
 # ---------------------------------------------------------------------------
+
+def kmeans_boxes(dims: np.ndarray, k: int) -> List[List[int]]:
+    """K-means clustering of bounding-box dimensions (App. A.1 "Batching and clustering";
+    App. A.2.1, Fig. "clustering": K-means on the width and height of the composite cells'
+    Y-marginal boxes).  Lloyd's algorithm: assign every box to its nearest centre in the
+    (W1, W2) plane (ties to the lower centre index), move every centre to the mean of its
+    boxes, until no assignment changes.  Reading (the paper does not state an
+    initialisation): the k starting centres are the boxes at ranks floor((q + 1/2) n / k),
+    q = 0..k-1, of the order by area W1 W2 (stable).  Returns the non-empty clusters as
+    ascending cell lists, by decreasing centre area."""
+    dims = np.asarray(dims, dtype=np.float64).reshape(-1, 2)
+    n = len(dims)
+    k = max(1, min(int(k), n))
+    area = dims[:, 0] * dims[:, 1]
+    order = sorted(range(n), key=lambda i: area[i])
+    cent = np.array([dims[order[min(n - 1, int((q + 0.5) * n / k))]] for q in range(k)])
+    lab = [-1] * n
+    for _ in range(100):
+        changed = False
+        for i in range(n):
+            d = [(dims[i, 0] - cent[q, 0]) ** 2 + (dims[i, 1] - cent[q, 1]) ** 2 for q in range(k)]
+            best = min(range(k), key=lambda q: (d[q], q))
+            changed |= lab[i] != best
+            lab[i] = best
+        if not changed:
+            break
+        for q in range(k):
+            mem = [i for i in range(n) if lab[i] == q]
+            if mem:
+                cent[q] = dims[mem].mean(axis=0)
+    groups = [[i for i in range(n) if lab[i] == q] for q in range(k)]
+    qs = sorted(range(k), key=lambda q: -cent[q, 0] * cent[q, 1])
+    return [groups[q] for q in qs if groups[q]]
+
 
 def upsample_bilinear(a: np.ndarray) -> np.ndarray:
     """Values of a function known at the pixel centres of an N x N grid, at the pixel centres of
