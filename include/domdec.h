@@ -312,6 +312,10 @@ typedef struct {
     double t_total_ms;        /* whole iteration (device)                             */
     double t_init_ms;         /* X-potential start (warm start, or the net's features,
                                  inference and X-update) before the Sinkhorn solve     */
+    int32_t batches;          /* composite-cell batches solved one after another       */
+    int32_t reserved3;
+    int64_t peak_comp_entries;/* composite Y-box entries of the largest batch: the size
+                                 of the composite work arrays (7 doubles per entry)    */
 } dd_iter_stats;
 
 /*
@@ -330,6 +334,26 @@ typedef struct {
  */
 dd_status domdec_iterate(dd_ctx* ctx, int32_t partition, double eps,
                          const dd_sinkhorn_opts* opts, dd_iter_stats* stats);
+
+/*
+ * domdec_set_clusters -- batching and clustering of the composite cells (App. A.1 "Batching
+ * and clustering"; App. A.2.1 "Batching and clustering", which uses one cluster up to
+ * N = 256 and N / 256 clusters above).  With k > 1 every later domdec_iterate clusters the
+ * partition's composite cells by K-means on their Y-box dimensions (W1, W2) into at most k
+ * clusters and solves them one after another as separate batches (CreateBatches): each batch
+ * runs BasicToComposite, the start, the cell solve with its own stopping rule (the batch rule
+ * then holds per batch, as in the paper), CompositeToBasic, balancing and truncation, and
+ * the new basic-cell Y-marginals are assembled once every batch is done (CombineBatches).
+ * The composite work arrays then hold the largest batch only (dd_iter_stats.
+ * peak_comp_entries).  Each cell's result does not depend on its batch: at fixed iteration
+ * counts or with DD_STOP_CELL the state is the same as unbatched.  After a batched
+ * iteration the composite plans are not kept whole, so domdec_evaluate reports the basic-
+ * cell quantities only (primal, dual, X-marginal NaN), and extract_potentials without beta;
+ * flow_update needs an unbatched B iteration.  DD_INIT_NET runs unbatched only.
+ * k = 1 (the default) restores the single batch.  The setting carries over domdec_refine.
+ * Errors: DD_EINVAL (k < 1).
+ */
+dd_status domdec_set_clusters(dd_ctx* ctx, int32_t k);
 
 /*
  * domdec_refine -- the coarse-to-fine step of multiscale domain decomposition (App. A.2.1

@@ -26,7 +26,8 @@ SYMBOLS = ("sinkhorn_batch", "sinkhorn_batch_f64", "domdec_init", "domdec_iterat
            "flow_costs", "flow_apply", "dd_mcf_solve", "extract_plan", "domdec_evaluate", "domdec_free",
            "domdec_strerror", "dd_net_param_count", "dd_net_create", "dd_net_params", "dd_net_forward",
            "dd_net_train_step", "dd_net_free", "dd_net_strerror", "domdec_set_net", "domdec_net_samples", "domdec_save", "domdec_restore",
-           "extract_potentials", "sinkhorn_batch_noalloc", "domdec_refine", "global_sinkhorn")
+           "extract_potentials", "sinkhorn_batch_noalloc", "domdec_refine", "global_sinkhorn",
+           "domdec_set_clusters")
 
 
 class DomDecError(RuntimeError):
@@ -110,7 +111,9 @@ class IterStats(ctypes.Structure):
                 ("max_w2", ctypes.c_int32), ("grid_n", ctypes.c_int32), ("nu_entries", ctypes.c_int64),
                 ("comp_entries", ctypes.c_int64), ("t_b2c_ms", ctypes.c_double),
                 ("t_sinkhorn_ms", ctypes.c_double), ("t_c2b_ms", ctypes.c_double),
-                ("t_total_ms", ctypes.c_double), ("t_init_ms", ctypes.c_double)]
+                ("t_total_ms", ctypes.c_double), ("t_init_ms", ctypes.c_double),
+                ("batches", ctypes.c_int32), ("reserved3", ctypes.c_int32),
+                ("peak_comp_entries", ctypes.c_int64)]
 
 
 class FlowStats(ctypes.Structure):
@@ -183,6 +186,8 @@ def lib():
     L.domdec_init.restype = ctypes.c_int
     L.domdec_init.argtypes = [ctypes.POINTER(Params), dp, dp, ctypes.c_int64, i64p, i64p, dp, vp,
                               ctypes.POINTER(vp)]
+    L.domdec_set_clusters.restype = ctypes.c_int
+    L.domdec_set_clusters.argtypes = [vp, ctypes.c_int32]
     L.domdec_iterate.restype = ctypes.c_int
     L.domdec_iterate.argtypes = [vp, ctypes.c_int32, ctypes.c_double, ctypes.POINTER(SinkhornOpts),
                                  ctypes.POINTER(IterStats)]
@@ -400,6 +405,11 @@ class DomDec:
         d = _struct_dict(st)
         d["status"] = status
         return d
+
+    def set_clusters(self, k: int) -> None:
+        """Solve each later iteration's composite cells in k bounding-box clusters, one batch
+        after another (domdec_set_clusters); k = 1: one batch."""
+        _check(lib().domdec_set_clusters(self._ctx, int(k)), self._ctx)
 
     def refine(self) -> None:
         """Move to the next finer layer of a multiscale context (domdec_refine)."""

@@ -484,6 +484,50 @@ __global__ void refine_alpha_kernel(int ncell, int xside, int Nc, const int32_t*
     }
 }
 
+// ---- sequential batches of composite cells (bounding-box clusters) ----------------------
+
+// dst[j][k] = src[idx[j]][k] (k < width), or the reverse direction with `back`
+template <typename V>
+__global__ void rows_kernel(int n, const int32_t* __restrict__ idx, int width, const V* src, V* dst,
+                            int back) {
+    const int64_t total = (int64_t)n * width;
+    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < total;
+         t += (int64_t)gridDim.x * blockDim.x) {
+        const int j = (int)(t / width), k = (int)(t - (int64_t)j * width);
+        const int64_t far = (int64_t)idx[j] * width + k;
+        if (back)
+            dst[far] = src[t];
+        else
+            dst[t] = src[far];
+    }
+}
+
+// sizes of the listed basic cells, in list order
+__global__ void list_sizes_kernel(int n, const int32_t* __restrict__ list,
+                                  const int64_t* __restrict__ nsize, int64_t* out) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < n) out[k] = nsize[list[k]];
+}
+
+// staging offsets of the listed basic cells: offset + their exclusive prefix sums
+__global__ void stage_base_kernel(int n, const int32_t* __restrict__ list,
+                                  const int64_t* __restrict__ local, int64_t offset,
+                                  int64_t* stage_base) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < n) stage_base[list[k]] = offset + local[k];
+}
+
+// every basic cell's truncated box from its staging slot to its place in the new state
+__global__ void __launch_bounds__(kT)
+    unstage_kernel(int nI, const int64_t* __restrict__ nsize, const int64_t* __restrict__ stage_base,
+                   const double* __restrict__ staging, const int64_t* __restrict__ nbase,
+                   double* ndata) {
+    for (int i = blockIdx.x; i < nI; i += gridDim.x) {
+        const int64_t n = nsize[i], src = stage_base[i], dst = nbase[i];
+        for (int64_t o = threadIdx.x; o < n; o += blockDim.x) ndata[dst + o] = staging[src + o];
+    }
+}
+
 }  // namespace
 
 void launch_fill_i32(int32_t* p, int n, int32_t v, hipStream_t st) {
@@ -562,6 +606,40 @@ void launch_refine_alpha(const PartDev& P, int xside, int Nc, const double* fc, 
     const int64_t n = (int64_t)P.ncell * xside * xside;
     refine_alpha_kernel<<<(int)std::min<int64_t>((n + kT - 1) / kT, 8192), kT, 0, st>>>(
         P.ncell, xside, Nc, P.xorig, fc, a);
+}
+
+void launch_gather_rows(int n, const int32_t* idx, int width, const double* src, double* dst,
+                        hipStream_t st) {
+    const int64_t t = (int64_t)n * width;
+    if (t > 0)
+        rows_kernel<double><<<(int)std::min<int64_t>((t + kT - 1) / kT, 8192), kT, 0, st>>>(
+            n, idx, width, src, dst, 0);
+}
+void launch_scatter_rows(int n, const int32_t* idx, int width, const double* src, double* dst,
+                         hipStream_t st) {
+    const int64_t t = (int64_t)n * width;
+    if (t > 0)
+        rows_kernel<double><<<(int)std::min<int64_t>((t + kT - 1) / kT, 8192), kT, 0, st>>>(
+            n, idx, width, src, dst, 1);
+}
+void launch_gather_rows_i32(int n, const int32_t* idx, int width, const int32_t* src, int32_t* dst,
+                            int back, hipStream_t st) {
+    const int64_t t = (int64_t)n * width;
+    if (t > 0)
+        rows_kernel<int32_t><<<(int)std::min<int64_t>((t + kT - 1) / kT, 8192), kT, 0, st>>>(
+            n, idx, width, src, dst, back);
+}
+void launch_list_sizes(int n, const int32_t* list, const int64_t* nsize, int64_t* out,
+                       hipStream_t st) {
+    if (n > 0) list_sizes_kernel<<<(n + kT - 1) / kT, kT, 0, st>>>(n, list, nsize, out);
+}
+void launch_stage_base(int n, const int32_t* list, const int64_t* local, int64_t offset,
+                       int64_t* stage_base, hipStream_t st) {
+    if (n > 0) stage_base_kernel<<<(n + kT - 1) / kT, kT, 0, st>>>(n, list, local, offset, stage_base);
+}
+void launch_unstage(int nI, const int64_t* nsize, const int64_t* stage_base, const double* staging,
+                    const int64_t* nbase, double* ndata, hipStream_t st) {
+    unstage_kernel<<<grid_cells(nI), kT, 0, st>>>(nI, nsize, stage_base, staging, nbase, ndata);
 }
 
 }  // namespace dd

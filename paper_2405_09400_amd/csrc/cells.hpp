@@ -68,4 +68,20 @@ void launch_refine_values(int nf, int nc, int Nc, const BoxSet& C, const double*
 void launch_refine_alpha(const PartDev& P, int xside, int Nc, const double* fc, double* a,
                          hipStream_t st);
 
+// Sequential batches of one partition's composite cells: gathers of per-cell rows into a
+// batch's own arrays (and back), and the staging of the truncated basic-cell boxes of each
+// batch, copied to their place in the new state once every batch is done.
+void launch_gather_rows(int n, const int32_t* idx, int width, const double* src, double* dst,
+                        hipStream_t st);
+void launch_scatter_rows(int n, const int32_t* idx, int width, const double* src, double* dst,
+                         hipStream_t st);
+void launch_gather_rows_i32(int n, const int32_t* idx, int width, const int32_t* src, int32_t* dst,
+                            int back, hipStream_t st);
+void launch_list_sizes(int n, const int32_t* list, const int64_t* nsize, int64_t* out,
+                       hipStream_t st);
+void launch_stage_base(int n, const int32_t* list, const int64_t* local, int64_t offset,
+                       int64_t* stage_base, hipStream_t st);
+void launch_unstage(int nI, const int64_t* nsize, const int64_t* stage_base, const double* staging,
+                    const int64_t* nbase, double* ndata, hipStream_t st);
+
 }  // namespace dd

@@ -120,6 +120,16 @@ void dd_ctx_release(dd_ctx* c) {
     F(c->d_cell_out);
     F(c->d_basic_out);
     F(c->d_eval);
+    for (int32_t** q : {&c->bt.C.dims, &c->bt.C.orig, &c->bt.C.shift, &c->bt.C.gofs, &c->bt.C.info,
+                        &c->bt.idx, &c->bt.members, &c->bt.xorig, &c->bt.gst, &c->bt.list})
+        F(*q);
+    F(c->bt.C.size);
+    F(c->bt.C.base);
+    F(c->bt.a);
+    F(c->bt.logmu);
+    F(c->bt.lsize);
+    F(c->bt.stage_base);
+    F(c->bt.staging);
     for (auto& e : c->ev)
         if (e) (void)hipEventDestroy(e);
     sk_work_release(c->skw);
@@ -460,6 +470,7 @@ extern "C" dd_status domdec_refine(dd_ctx* c) {
     // the finer layer, its coupling and its potentials
     dd_ctx* f = new dd_ctx();
     use_mem(f, c->mem);
+    f->clusters = c->clusters;
     f->s = c->s;
     f->trunc = c->trunc;
     f->prec = c->prec;
@@ -616,6 +627,8 @@ static dd_status iterate_impl(dd_ctx* c, int p, double eps, const dd_sinkhorn_op
         s.grid_n = c->N;
         s.nu_entries = ntot;
         s.comp_entries = total;
+        s.batches = 1;
+        s.peak_comp_entries = total;
         float t = 0.f;
         (void)hipEventElapsedTime(&t, c->ev[0], c->ev[1]);
         s.t_b2c_ms = t;
@@ -635,6 +648,339 @@ static dd_status iterate_impl(dd_ctx* c, int p, double eps, const dd_sinkhorn_op
     return DD_OK;
 }
 
+namespace {
+
+// K-means on the composite Y-box dimensions (W1, W2) into at most k clusters (Lloyd's
+// iteration from the boxes at evenly spaced ranks of the area order); returns the clusters'
+// cells, each in ascending order, the clusters by decreasing centre area.  Deterministic.
+std::vector<std::vector<int32_t>> kmeans_batches(const std::vector<int32_t>& dims, int k) {
+    const int n = (int)(dims.size() / 2);
+    k = std::max(1, std::min(k, n));
+    std::vector<int32_t> order(n);
+    std::iota(order.begin(), order.end(), 0);
+    auto area = [&](int i) { return (int64_t)dims[2 * i] * dims[2 * i + 1]; };
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return area(a) < area(b); });
+    std::vector<double> c1(k), c2(k);
+    for (int q = 0; q < k; ++q) {
+        const int i = order[std::min<size_t>(n - 1, (size_t)(((double)q + 0.5) * n / k))];
+        c1[q] = dims[2 * i];
+        c2[q] = dims[2 * i + 1];
+    }
+    std::vector<int> lab(n, -1);
+    for (int it = 0; it < 100; ++it) {
+        bool changed = false;
+        for (int i = 0; i < n; ++i) {
+            int best = 0;
+            double bd = 1e300;
+            for (int q = 0; q < k; ++q) {
+                const double d1 = dims[2 * i] - c1[q], d2 = dims[2 * i + 1] - c2[q];
+                const double d = d1 * d1 + d2 * d2;
+                if (d < bd) {
+                    bd = d;
+                    best = q;
+                }
+            }
+            changed |= lab[i] != best;
+            lab[i] = best;
+        }
+        if (!changed) break;
+        std::vector<double> s1(k, 0.0), s2(k, 0.0);
+        std::vector<int> cnt(k, 0);
+        for (int i = 0; i < n; ++i) {
+            s1[lab[i]] += dims[2 * i];
+            s2[lab[i]] += dims[2 * i + 1];
+            ++cnt[lab[i]];
+        }
+        for (int q = 0; q < k; ++q)
+            if (cnt[q]) {
+                c1[q] = s1[q] / cnt[q];
+                c2[q] = s2[q] / cnt[q];
+            }
+    }
+    std::vector<std::vector<int32_t>> groups(k);
+    for (int i = 0; i < n; ++i) groups[lab[i]].push_back(i);
+    std::vector<int> qs(k);
+    std::iota(qs.begin(), qs.end(), 0);
+    std::stable_sort(qs.begin(), qs.end(), [&](int a, int b) { return c1[a] * c2[a] > c1[b] * c2[b]; });
+    std::vector<std::vector<int32_t>> out;
+    for (int q : qs)
+        if (!groups[q].empty()) out.push_back(std::move(groups[q]));
+    return out;
+}
+
+Status reserve_batches(dd_ctx* c, int n) {
+    Status st;
+    auto& B = c->bt;
+    if (!B.stage_base && alloc(c->mem, B.stage_base, (size_t)c->nI, st).code) return st;
+    if (n <= B.cap) return st;
+    auto F = [c](auto& p) {
+        c->mem.put(p);
+        p = nullptr;
+    };
+    for (int32_t** q : {&B.C.dims, &B.C.orig, &B.C.shift, &B.C.gofs, &B.idx, &B.members, &B.xorig,
+                        &B.gst, &B.list})
+        F(*q);
+    F(B.C.size);
+    F(B.C.base);
+    F(B.a);
+    F(B.logmu);
+    F(B.lsize);
+    B.cap = 0;
+    const size_t A2 = (size_t)c->AS * c->AS;
+    if (alloc(c->mem, B.C.dims, 2 * (size_t)n, st).code ||
+        alloc(c->mem, B.C.orig, 2 * (size_t)n, st).code ||
+        alloc(c->mem, B.C.shift, 2 * (size_t)n, st).code ||
+        alloc(c->mem, B.C.gofs, 2 * (size_t)n, st).code || alloc(c->mem, B.C.size, n, st).code ||
+        alloc(c->mem, B.C.base, (size_t)n + 1, st).code ||
+        (!B.C.info && alloc(c->mem, B.C.info, 8, st).code) || alloc(c->mem, B.idx, n, st).code ||
+        alloc(c->mem, B.members, 4 * (size_t)n, st).code ||
+        alloc(c->mem, B.xorig, 2 * (size_t)n, st).code || alloc(c->mem, B.gst, 2 * (size_t)n, st).code ||
+        alloc(c->mem, B.a, A2 * n, st).code || alloc(c->mem, B.logmu, A2 * n, st).code ||
+        alloc(c->mem, B.list, 4 * (size_t)n, st).code ||
+        alloc(c->mem, B.lsize, 2 * (4 * (size_t)n + 1), st).code)
+        return st;
+    B.cap = n;
+    return st;
+}
+
+// staging buffer of at least `need` entries that keeps its first `used` entries
+Status grow_staging(dd_ctx* c, size_t need, size_t used) {
+    Status st;
+    auto& B = c->bt;
+    if (need <= B.staging_cap && B.staging) return st;
+    const size_t cap = std::max<size_t>((size_t)(need * 1.25) + 64, 1024);
+    double* fresh = nullptr;
+    if (alloc(c->mem, fresh, cap, st).code) return st;
+    if (used > 0)
+        DD_HIP(hipMemcpyAsync(fresh, B.staging, used * sizeof(double), hipMemcpyDeviceToDevice,
+                              c->st),
+               st);
+    DD_HIP(hipStreamSynchronize(c->st), st);  // the old buffer is read until here
+    c->mem.put(B.staging);
+    B.staging = fresh;
+    B.staging_cap = cap;
+    return st;
+}
+
+void add_stats(dd_batch_stats& a, const dd_batch_stats& b, bool first) {
+    if (first) {
+        a = b;
+        return;
+    }
+    a.ncells += b.ncells;
+    a.iters_max = std::max(a.iters_max, b.iters_max);
+    a.iters_min = std::min(a.iters_min, b.iters_min);
+    a.converged = a.converged && b.converged;
+    a.cell_iters += b.cell_iters;
+    a.err += b.err;
+    a.mass += b.mass;
+    a.lse_terms += b.lse_terms;
+    a.alg_bytes += b.alg_bytes;
+    a.time_ms += b.time_ms;
+    a.main_ms += b.main_ms;
+    a.finish_iters_max = std::max(a.finish_iters_max, b.finish_iters_max);
+    a.n_big += b.n_big;
+    a.n_giant += b.n_giant;
+    for (int k = 0; k < 3; ++k) {
+        a.kernel_launches[k] += b.kernel_launches[k];
+        a.kernel_ms[k] += b.kernel_ms[k];
+        a.kernel_terms[k] += b.kernel_terms[k];
+    }
+}
+
+}  // namespace
+
+// One DD half-iteration with the partition's composite cells split into bounding-box clusters
+// solved one after another (App. A.1 "Batching and clustering": CreateBatches /
+// CombineBatches): the composite work arrays hold one batch at a time.  Each batch runs
+// BasicToComposite, the start, the cell solve (its own stopping rule), CompositeToBasic,
+// balancing and truncation; its truncated basic-cell boxes are staged, and the new state is
+// assembled from the staging once every batch is done.
+static dd_status iterate_batched(dd_ctx* c, int p, double eps, const dd_sinkhorn_opts& o,
+                                 dd_iter_stats* out) {
+    Status st;
+    const hipStream_t hs = c->st;
+    PartDev& P = c->part[p];
+    const int nc = P.ncell, AS = c->AS, A2 = AS * AS;
+    const double kappa = eps / (c->h * c->h);
+    auto& B = c->bt;
+    (void)hipEventRecord(c->ev[0], hs);
+    // every composite cell's box: the clustering's input
+    launch_comp_boxes(P, c->S, AS, c->C, hs);
+    std::vector<int32_t> dims(2 * (size_t)nc);
+    if (hipMemcpyAsync(dims.data(), c->C.dims, dims.size() * 4, hipMemcpyDeviceToHost, hs) !=
+            hipSuccess ||
+        hipStreamSynchronize(hs) != hipSuccess)
+        return fail(c, DD_EDEVICE, "domdec_iterate: reading composite boxes failed");
+    const std::vector<std::vector<int32_t>> groups = kmeans_batches(dims, c->clusters);
+    size_t most = 0;
+    for (const auto& g : groups) most = std::max(most, g.size());
+    {
+        const Status rs = reserve_batches(c, (int)most);
+        if (rs.code) return fail(c, rs);
+    }
+    launch_fill_i32(c->d_flags, c->nI + 1, 0, hs);
+    const int use_prev = (o.init != DD_INIT_ZERO && c->visited[p]) ? 1 : 0;
+    const double kappa_old = c->kappa_a[p];
+    dd_batch_stats agg{};
+    int64_t staged = 0, comp_total = 0, peak = 0;
+    int mw1_all = 0, mw2_all = 0;
+    bool notconv = false;
+    std::string notconv_msg;
+    for (size_t gi = 0; gi < groups.size(); ++gi) {
+        const std::vector<int32_t>& g = groups[gi];
+        const int nb = (int)g.size();
+        std::vector<int32_t> mem(4 * (size_t)nb), xo(2 * (size_t)nb), list;
+        for (int j = 0; j < nb; ++j) {
+            for (int k = 0; k < 4; ++k) {
+                mem[4 * j + k] = c->pmembers[p][4 * (size_t)g[j] + k];
+                if (mem[4 * j + k] >= 0) list.push_back(mem[4 * j + k]);
+            }
+            xo[2 * j] = c->pxorig[p][2 * (size_t)g[j]];
+            xo[2 * j + 1] = c->pxorig[p][2 * (size_t)g[j] + 1];
+        }
+        const int nl = (int)list.size();
+        PartDev Pb;
+        Pb.ncell = nb;
+        Pb.members = B.members;
+        Pb.xorig = B.xorig;
+        // (the host vectors stay alive until the synchronisation below)
+        if (hipMemcpyAsync(B.idx, g.data(), (size_t)nb * 4, hipMemcpyHostToDevice, hs) != hipSuccess ||
+            hipMemcpyAsync(B.members, mem.data(), mem.size() * 4, hipMemcpyHostToDevice, hs) !=
+                hipSuccess ||
+            hipMemcpyAsync(B.xorig, xo.data(), xo.size() * 4, hipMemcpyHostToDevice, hs) !=
+                hipSuccess ||
+            hipMemcpyAsync(B.list, list.data(), (size_t)nl * 4, hipMemcpyHostToDevice, hs) !=
+                hipSuccess)
+            return fail(c, DD_EDEVICE, "domdec_iterate: uploading a batch failed");
+        launch_gather_rows(nb, B.idx, A2, c->d_logmu[p], B.logmu, hs);
+        launch_gather_rows(nb, B.idx, A2, c->d_a[p], B.a, hs);
+        launch_gather_rows_i32(nb, B.idx, 2, c->d_gst[p], B.gst, 0, hs);
+        launch_comp_boxes(Pb, c->S, AS, B.C, hs);
+        launch_scan(B.C.size, B.C.base, nb, hs);
+        launch_comp_max(B.C, nb, hs);
+        int32_t info[2];
+        int64_t total = 0;
+        if (hipMemcpyAsync(info, B.C.info, sizeof info, hipMemcpyDeviceToHost, hs) != hipSuccess ||
+            hipMemcpyAsync(&total, B.C.base + nb, sizeof total, hipMemcpyDeviceToHost, hs) !=
+                hipSuccess ||
+            hipStreamSynchronize(hs) != hipSuccess)
+            return fail(c, DD_EDEVICE, "domdec_iterate: reading a batch's sizes failed");
+        const int mw1 = info[0], mw2 = info[1];
+        mw1_all = std::max(mw1_all, mw1);
+        mw2_all = std::max(mw2_all, mw2);
+        comp_total += total;
+        peak = std::max(peak, total);
+        if (grow(c->mem, c->d_nuJ, c->nuJ_cap, (size_t)total, st).code ||
+            grow(c->mem, c->d_lognu, c->lognu_cap, (size_t)total, st).code ||
+            grow(c->mem, c->d_b, c->b_cap, (size_t)total, st).code ||
+            grow(c->mem, c->d_tmp, c->tmp_cap, 4 * (size_t)total, st).code)
+            return fail(c, st);
+        launch_b2c(Pb, c->S, B.C, c->d_nuJ, c->d_lognu, hs);
+        launch_warm_start(Pb, B.C, AS, B.a, B.gst, kappa_old, kappa, use_prev, hs);
+        SkBatch sb;
+        sb.ncells = nb;
+        sb.xside = AS;
+        sb.dims = B.C.dims;
+        sb.base = B.C.base;
+        sb.shift = B.C.shift;
+        sb.logmu = B.logmu;
+        sb.lognu = c->d_lognu;
+        sb.a = B.a;
+        sb.b = c->d_b;
+        sb.kappa = kappa;
+        sb.max_w1 = mw1;
+        sb.max_w2 = mw2;
+        sb.prec = c->prec;
+        dd_batch_stats bs{};
+        const Status ss = sk_solve(sb, o, hs, c->skw, &bs, c->d_iters, c->d_cerr);
+        if (ss.code != DD_OK && ss.code != DD_NOTCONV) return fail(c, ss);
+        if (ss.code == DD_NOTCONV) {
+            notconv = true;
+            notconv_msg = ss.msg;
+        }
+        add_stats(agg, bs, gi == 0);
+        launch_c2b(Pb, B.C, AS, c->s, mw2, B.a, B.logmu, c->d_nuJ, kappa, c->h, c->d_tmp,
+                   c->d_py2, hs);
+        launch_balance(Pb, B.C, c->d_m, c->d_tmp, hs);
+        launch_trunc_boxes(Pb, B.C, c->d_tmp, c->trunc, c->nI, c->S2.box, c->d_nsize, c->d_flags,
+                           hs);
+        // the batch's truncated boxes go to the staging, after the earlier batches'
+        int64_t* lpre = B.lsize + 4 * (size_t)B.cap + 1;
+        launch_list_sizes(nl, B.list, c->d_nsize, B.lsize, hs);
+        launch_scan(B.lsize, lpre, nl, hs);
+        int64_t add = 0;
+        if (hipMemcpyAsync(&add, lpre + nl, sizeof add, hipMemcpyDeviceToHost, hs) != hipSuccess ||
+            hipStreamSynchronize(hs) != hipSuccess)
+            return fail(c, DD_EDEVICE, "domdec_iterate: reading a batch's truncated sizes failed");
+        {
+            const Status gs = grow_staging(c, (size_t)(staged + add), (size_t)staged);
+            if (gs.code) return fail(c, gs);
+        }
+        launch_stage_base(nl, B.list, lpre, staged, B.stage_base, hs);
+        launch_compact(Pb, B.C, c->d_tmp, c->trunc, c->S2.box, B.stage_base, c->d_flags, B.staging,
+                       hs);
+        staged += add;
+        launch_scatter_rows(nb, B.idx, A2, B.a, c->d_a[p], hs);
+        launch_gather_rows_i32(nb, B.idx, 2, B.gst, c->d_gst[p], 1, hs);
+    }
+    // CombineBatches: the new state in basic-cell order
+    launch_scan(c->d_nsize, c->S2.base, c->nI, hs);
+    int64_t ntot = 0;
+    int32_t kept = 0;
+    if (hipMemcpyAsync(&ntot, c->S2.base + c->nI, sizeof ntot, hipMemcpyDeviceToHost, hs) !=
+            hipSuccess ||
+        hipMemcpyAsync(&kept, c->d_flags + c->nI, sizeof kept, hipMemcpyDeviceToHost, hs) !=
+            hipSuccess ||
+        hipStreamSynchronize(hs) != hipSuccess)
+        return fail(c, DD_EDEVICE, "domdec_iterate: reading truncated sizes failed");
+    if (grow(c->mem, c->S2.data, c->S2.cap, (size_t)std::max<int64_t>(ntot, 1), st).code)
+        return fail(c, st);
+    launch_unstage(c->nI, c->d_nsize, B.stage_base, B.staging, c->S2.base, c->S2.data, hs);
+    std::swap(c->S, c->S2);
+    (void)hipEventRecord(c->ev[3], hs);
+    if (hipStreamSynchronize(hs) != hipSuccess || hipGetLastError() != hipSuccess)
+        return fail(c, DD_EDEVICE, "domdec_iterate: a kernel failed");
+    c->visited[p] = true;
+    c->kappa_a[p] = kappa;
+    // the composite plans of this iteration were spread over the batches: the evaluation of
+    // composite quantities, beta and the flow update need an unbatched iteration
+    c->last_part = -1;
+    c->last_eps = eps;
+    c->untruncated_cells = kept;
+    B.peak_entries = peak;
+    B.count = (int)groups.size();
+    if (out) {
+        dd_iter_stats s{};
+        s.sk = agg;
+        s.partition = p;
+        s.max_w1 = mw1_all;
+        s.max_w2 = mw2_all;
+        s.grid_n = c->N;
+        s.nu_entries = ntot;
+        s.comp_entries = comp_total;
+        s.batches = (int32_t)groups.size();
+        s.peak_comp_entries = peak;
+        s.t_sinkhorn_ms = agg.time_ms;
+        float t = 0.f;
+        (void)hipEventElapsedTime(&t, c->ev[0], c->ev[3]);
+        s.t_total_ms = t;
+        *out = s;
+    }
+    if (notconv) {
+        c->err = notconv_msg;
+        return DD_NOTCONV;
+    }
+    return DD_OK;
+}
+
+extern "C" dd_status domdec_set_clusters(dd_ctx* c, int32_t clusters) {
+    if (!c) return fail(c, DD_EINVAL, "domdec_set_clusters: null context");
+    if (clusters < 1) return fail(c, DD_EINVAL, "domdec_set_clusters: clusters must be >= 1");
+    c->clusters = clusters;
+    return DD_OK;
+}
+
 extern "C" dd_status domdec_iterate(dd_ctx* c, int32_t partition, double eps,
                                     const dd_sinkhorn_opts* o, dd_iter_stats* out) {
     if (!c || !o) return fail(c, DD_EINVAL, "domdec_iterate: null argument");
@@ -649,6 +995,11 @@ extern "C" dd_status domdec_iterate(dd_ctx* c, int32_t partition, double eps,
         return fail(c, DD_ESTATE, "domdec_iterate: DD_INIT_NET needs a net (domdec_set_net)");
     if (o->init == DD_INIT_NET && c->AS > 8)
         return fail(c, DD_EINVAL, "domdec_iterate: DD_INIT_NET needs X blocks of side <= 8");
+    if (c->clusters > 1) {
+        if (o->init == DD_INIT_NET)
+            return fail(c, DD_EINVAL, "domdec_iterate: DD_INIT_NET runs unbatched (clusters 1)");
+        return iterate_batched(c, partition, eps, *o, out);
+    }
     return iterate_impl(c, partition, eps, *o, out);
 }
 

@@ -72,6 +72,25 @@ struct dd_ctx {
     double* d_a0 = nullptr;  // [cells][xside^2] previous-iterate start of the last iteration
     size_t a0_cap = 0;
     dd::DualWork dual;
+    // sequential batches of composite cells (bounding-box clusters; domdec_set_clusters)
+    int clusters = 1;
+    struct Batch {
+        dd::CompDev C;                 // the batch's composite boxes ([cap] cells)
+        int32_t* idx = nullptr;        // [cap] composite cells of the batch (partition ids)
+        int32_t* members = nullptr;    // [cap][4]
+        int32_t* xorig = nullptr;      // [cap][2]
+        int32_t* gst = nullptr;        // [cap][2]
+        double* a = nullptr;           // [cap][xside^2] X potentials
+        double* logmu = nullptr;       // [cap][xside^2]
+        int32_t* list = nullptr;       // [4 cap] basic cells of the batch
+        int64_t* lsize = nullptr;      // [4 cap + 1] their sizes, then prefix sums
+        int cap = 0;
+        int64_t* stage_base = nullptr; // [nI] staging offset of every basic cell
+        double* staging = nullptr;     // truncated boxes of all batches, batch after batch
+        size_t staging_cap = 0;
+        int64_t peak_entries = 0;      // largest batch of the last iteration (composite entries)
+        int count = 0;                 // batches of the last iteration
+    } bt;
     // one saved copy of the mutable state (domdec_save / domdec_restore)
     struct Snap {
         bool valid = false;
