@@ -230,7 +230,7 @@ def cpu_baseline(args, w, ctx, k, rule):
     st = ctx.iterate(part, eps, tol=args.tol, stop_rule=rule, max_iter=args.max_iter,
                      check_every=args.check_every, init=dd.DD_INIT_PREV)
     sk = st["sk"]
-    n_its = sk["iters_max"] + max(sk["finish_iters_max"] - 1, 0)
+    n_its = sk["iters_max"]  # both phases
     nu_after = ctx.nu_i_sparse()
     post = ctx.extract_potentials(part)
     t0 = time.perf_counter()
@@ -509,6 +509,8 @@ def main():
     ap.add_argument("--flow-eps-gamma", type=float, default=None,
                     help="flow workload: glued edge candidates at this eps_gamma (units of h^2); "
                          "default: product candidates")
+    ap.add_argument("--no-clusters", action="store_true",
+                    help="skip the clustering study (time against K-means clusters at 1024^2)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-compare", action="store_true")
     ap.add_argument("--replay", type=int, default=8)
@@ -570,6 +572,8 @@ def main():
                          ("sinkhorn_iters", "sinkhorn_ms_per_step", "max_box", "x_marginal_l1",
                           "y_marginal_l1", "primal", "pd_gap")}
         line["size1024"] = rec
+        if not args.no_clusters:
+            line["clusters"] = clusters_record(args, larger[args.workload])
         if args.workload.startswith("ms"):
             # the whole multiscale solve at the paper's arithmetic and stopping tolerance, and
             # the global Sinkhorn on the same problem
@@ -581,6 +585,40 @@ def main():
                 g["dual_rel_diff_vs_dd_primal"] = abs(g["dual"] - fs["primal"]) / abs(fs["primal"])
                 line["global"] = g
     print(json.dumps(line), flush=True)
+
+
+def clusters_record(args, workload, ks=(1, 2, 4, 8), steps=4):
+    """Batching and clustering (App. A.1, App. A.2.1 Fig. "clustering": the time of the last
+    multiscale layer against the number of K-means clusters, N = 1024, s = 4).  From the
+    workload's untimed set-up, one saved state; for each k the state is restored and `steps`
+    half-iterations at the timed eps run with the partition split into k clusters solved one
+    after another (each batch with its own stopping test).  Reports the wall time per
+    half-iteration and the composite work arrays' size (7 float64 per composite entry of the
+    largest batch) against one batch."""
+    import torch
+
+    w, ctx, rule, k0 = setup(args, workload, args.prec)
+    ctx.save()
+    out = []
+    for k in ks:
+        ctx.restore()
+        ctx.set_clusters(k)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        sts = run_steps(ctx, w, steps, k0, args, rule)
+        wall = (time.perf_counter() - t0) * 1e3 / steps
+        peak = max(st["peak_comp_entries"] for st in sts)
+        total = max(st["comp_entries"] for st in sts)
+        out.append({"clusters": k, "batches": [st["batches"] for st in sts],
+                    "ms_per_step": wall,
+                    "sinkhorn_iters": [st["sk"]["iters_max"] for st in sts],
+                    "peak_comp_entries": peak, "comp_entries": total,
+                    "work_bytes": 56 * peak, "work_frac_of_one_batch": peak / total})
+        log(f"[bench] clusters {k}: {wall:.2f} ms/step, batches {out[-1]['batches']}, composite "
+            f"work {56 * peak / 2**20:.1f} MiB ({peak / total:.2f} of one batch)")
+    ctx.close()
+    return {"workload": workload, "dtype": args.prec, "steps": steps,
+            "heuristic_clusters": max(1, w.N // 256), "runs": out}
 
 
 def full_solve(args, workload, prec_name, tol):

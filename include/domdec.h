@@ -77,7 +77,8 @@ typedef struct {
 /* Statistics of one batched cell solve. */
 typedef struct {
     int32_t ncells;
-    int32_t iters_max;         /* iterations of the batch (max over cells)             */
+    int32_t iters_max;         /* iterations of the batch (max over cells), both phases
+                                  of a float32 solve with its float64 finish              */
     int32_t iters_min;
     int32_t converged;         /* 1 if the stopping rule was met                       */
     int64_t cell_iters;        /* sum over cells of iterations run                     */
@@ -87,7 +88,7 @@ typedef struct {
     double alg_bytes;          /* algorithmic bytes: 12 (|X_J| + W1 W2) per cell-iter  */
     double time_ms;            /* device time of the whole solve (HIP events)          */
     double main_ms;            /* device time of the main (float32 or float64) loop    */
-    int32_t finish_iters_max;  /* float64-finish iterations (sinkhorn_batch, tol mode)  */
+    int32_t finish_iters_max;  /* of those, float64-finish iterations (tolerance mode)  */
     int32_t n_big;             /* cells solved by a whole workgroup (the rest by a wave) */
     int32_t n_giant;           /* of those, cells in the whole-CU-LDS launch             */
     int32_t lds_kb[2];         /* LDS budget per workgroup, small and big launches (KB)  */

@@ -1157,7 +1157,7 @@ bool fast_eligible(const SkBatch& p, const std::vector<int32_t>& hd) {
 
 Status fast_solve(const SkBatch& p, const dd_sinkhorn_opts& o, hipStream_t st, SkWork& w,
                   const std::vector<int32_t>& hd, const std::vector<int32_t>& order,
-                  int32_t* iters, double* errs, FastInfo* info) {
+                  int32_t* iters, double* errs, FastInfo* info, bool final_pass) {
     Status S;
     const int n = p.ncells;
     // Cell classes by box shape (kernel frame), most work first within each:
@@ -1337,6 +1337,14 @@ Status fast_solve(const SkBatch& p, const dd_sinkhorn_opts& o, hipStream_t st, S
     }
     if (info)
         for (int k = 0; k < kClasses; ++k) info->terms[k] = terms_per_it[k] * hctl[10];
+    if (info) info->stop_it = hctl[2];
+    if (!final_pass && hctl[2] < o.max_iter) {
+        // a float64 finish follows from the X potential the last round ended with
+        launch_done_iters(n, iters, w.ctrl, st);
+        if (info) info->final_done = false;
+        DD_HIP(hipGetLastError(), S);
+        return S;
+    }
     // the final Y-update (g), timed the same way
     fork();
     launch(a, kFinal, !arena, 0);

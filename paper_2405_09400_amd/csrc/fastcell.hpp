@@ -18,6 +18,8 @@ struct FastInfo {
     int launches[kClasses] = {0, 0, 0};
     double ms[kClasses] = {0.0, 0.0, 0.0};
     double terms[kClasses] = {0.0, 0.0, 0.0};
+    int stop_it = 0;          // batch rule: the iteration the rule stopped at
+    bool final_done = true;   // f and g of that iteration are in p.a, p.b
 };
 
 // True when the batch runs on the register-blocked path: float32 terms, 8 x 8 X blocks,
@@ -33,8 +35,12 @@ constexpr int kFastMaxSide = 512;
 // device chooses from the error's decay (at least max(1, o.check_every) apart), and that a
 // tolerance solve aims at 0.85 o.tol (the float64 finish certifies o.tol).
 // `ord`: the cells in order of decreasing work (each class keeps that order, most work first).
+// `final_pass` (batch rule): end with the Y-update of the X potential whose error stopped the
+// rule (f and g of that iteration in p.a, p.b); without it, when a float64 finish follows, p.a
+// keeps the X-update of the last iteration (the start of the next one) and p.b is left to the
+// finish, and every cell's iteration count is the float32 phase's.
 Status fast_solve(const SkBatch& p, const dd_sinkhorn_opts& o, hipStream_t st, SkWork& w,
                   const std::vector<int32_t>& hd, const std::vector<int32_t>& ord,
-                  int32_t* iters, double* errs, FastInfo* info);
+                  int32_t* iters, double* errs, FastInfo* info, bool final_pass = true);
 
 }  // namespace dd

@@ -925,15 +925,27 @@ __global__ void __launch_bounds__(kThreads)
     }
 }
 
-// After a float64 finish, per-cell iterations count both phases.  The finish starts with a
-// Y-update of the X potential the float32 phase stopped at, which repeats that phase's last
-// Y-update in float64, so the two phases share one iteration.
-__global__ void merge_iters_kernel(int ncells, int32_t* iters, const int32_t* iters64) {
+// After a float64 finish, per-cell iterations count both phases.  When the finish starts with
+// a Y-update of the X potential the float32 phase stopped at (`shared`), it repeats that
+// phase's last Y-update in float64 and the two phases share one iteration; from the X-update
+// that followed (the register-blocked path) the finish's iterations come on top.
+__global__ void merge_iters_kernel(int ncells, int32_t* iters, const int32_t* iters64, int shared) {
     const int c = blockIdx.x * blockDim.x + threadIdx.x;
-    if (c < ncells && iters64[c] > 0) iters[c] += iters64[c] - 1;
+    if (c < ncells && iters64[c] > 0) iters[c] += iters64[c] - shared;
+}
+
+__global__ void done_iters_kernel(int ncells, int32_t* iters, const int* ctrl) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c < ncells) iters[c] = ctrl[2];
 }
 
 }  // namespace
+
+void launch_done_iters(int ncells, int32_t* iters, const int* ctrl, hipStream_t st) {
+    if (ncells > 0)
+        done_iters_kernel<<<(ncells + kThreads - 1) / kThreads, kThreads, 0, st>>>(ncells, iters,
+                                                                                  ctrl);
+}
 
 size_t sk_lds_bytes(int xside, int prec) {
     if (xside < 2 || xside > 16) return 0;
@@ -1076,7 +1088,8 @@ struct CellClass {
 // whole chunk of check_every)
 template <typename T>
 Status run_solver(const SkBatch& p0, const std::vector<CellClass>& cls, const dd_sinkhorn_opts& o,
-                  hipStream_t st, SkWork& w, int32_t* iters, double* errs, int first_chunk = 0) {
+                  hipStream_t st, SkWork& w, int32_t* iters, double* errs, int first_chunk = 0,
+                  int* done_out = nullptr) {
     Status S;
     double* big = reinterpret_cast<double*>(w.big);
     // the small and giant classes run on `st`, the big class on the second stream, side by side
@@ -1209,12 +1222,10 @@ Status run_solver(const SkBatch& p0, const std::vector<CellClass>& cls, const dd
     if (done < 1) done = o.max_iter;  // unreachable: the kernel sets done at max_iter
     if (((done - 1) & 1) == 1)
         DD_HIP(hipMemcpyAsync(p0.a, bufs[1], a_bytes, hipMemcpyDeviceToDevice, st), S);
-    fork();
-    for (int k = 0; k < ncls; ++k) {
-        auto fk = cls[k].mode == kBig ? sk_final_kernel<T, kBig> : sk_final_kernel<T, kSmall>;
-        fk<<<grid[k], kThreads, lds[k], streams[k]>>>(pk[k], w.ctrl, iters, big);
-    }
-    join();
+    // g of the stopping iteration is already in p.b (every Y-update writes it, and no
+    // iteration runs after the stop); each cell's count is the stop iteration
+    launch_done_iters(p0.ncells, iters, w.ctrl, st);
+    if (done_out) *done_out = done;
     DD_HIP(hipGetLastError(), S);
     return S;
 }
@@ -1559,24 +1570,34 @@ Status sk_solve(const SkBatch& p, const dd_sinkhorn_opts& o, hipStream_t caller_
     if (!arena) DD_HIP(hipEventRecord(w.ev0, st), S);
     zero_ints<<<1, 64, 0, st>>>(w.ctrl, 16);
     FastInfo fi;
+    int k32 = 0;  // batch rule: the float32 phase's stop iteration
     if (fast)
-        S = fast_solve(p, o, st, w, hd, ord, iters, errs, &fi);
+        S = fast_solve(p, o, st, w, hd, ord, iters, errs, &fi, !finish);
     else
-        S = p.prec == DD_PREC_F32 ? run_solver<float>(q, P.classes, o, st, w, iters, errs)
+        S = p.prec == DD_PREC_F32 ? run_solver<float>(q, P.classes, o, st, w, iters, errs, 0, &k32)
                                   : run_solver<double>(q, P.classes, o, st, w, iters, errs);
     if (S.code) return S;
+    if (fast) k32 = fi.stop_it;
     if (!arena) DD_HIP(hipEventRecord(w.ev2, st), S);
-    if (finish) {
-        // float64 finish: continue the same stopping rule in float64 from the float32 state;
-        // the tolerance is then certified by a float64 error (usually after one Y-update)
-        S = run_solver<double>(q64, P64.classes, o, st, w, w.iters64, errs, 2);
+    // float64 finish: continue the same stopping rule in float64 from the float32 state; the
+    // tolerance is then certified by a float64 error (usually after one Y-update).  It starts
+    // from the float32 phase's last (f, g) -- its first Y-update repeats that iteration -- or,
+    // on the register-blocked path, from the X-update after it (one more iteration); under
+    // the batch rule both phases together stay within max_iter.
+    const bool shared = !(fast && !fi.final_done);
+    dd_sinkhorn_opts o64 = o;
+    if (o.stop_rule == DD_STOP_BATCH) o64.max_iter = o.max_iter - k32 + (shared ? 1 : 0);
+    const bool run64 = finish && o64.max_iter >= 1;
+    if (run64) {
+        S = run_solver<double>(q64, P64.classes, o64, st, w, w.iters64, errs, 2);
         if (S.code) return S;
     }
-    sk_stats_kernel<<<1, kThreads, 0, st>>>(p.ncells, iters, finish ? w.iters64 : nullptr, errs,
+    // per-cell iterations of both phases, then the statistics over them
+    if (run64)
+        merge_iters_kernel<<<(p.ncells + kThreads - 1) / kThreads, kThreads, 0, st>>>(
+            p.ncells, iters, w.iters64, shared ? 1 : 0);
+    sk_stats_kernel<<<1, kThreads, 0, st>>>(p.ncells, iters, run64 ? w.iters64 : nullptr, errs,
                                             w.cell_mass, o.tol, p.dims, p.xside, w.dtot, w.ctrl);
-    if (finish)
-        merge_iters_kernel<<<(p.ncells + kThreads - 1) / kThreads, kThreads, 0, st>>>(p.ncells, iters,
-                                                                                     w.iters64);
     if (!arena) DD_HIP(hipEventRecord(w.ev1, st), S);
     int hctl[16];
     double htot[8];

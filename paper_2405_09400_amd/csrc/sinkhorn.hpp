@@ -91,6 +91,9 @@ size_t sk_lds_bytes(int xside, int prec);
 Status sk_solve(const SkBatch& p, const dd_sinkhorn_opts& o, hipStream_t st, SkWork& w,
                 dd_batch_stats* stats, int32_t* cell_iters_out, double* cell_err_out);
 
+// iters[c] = ctrl[2] (the batch rule's stop iteration) for every cell
+void launch_done_iters(int ncells, int32_t* iters, const int* ctrl, hipStream_t st);
+
 // Algorithmic work of one iteration of one cell (for the statistics).
 inline double sk_cell_terms(int a, int W1, int W2) {
     return (double)a * W2 * (a + W1) + (double)a * W1 * (W2 + a);

@@ -98,7 +98,7 @@ def test_f32_tolerance_solve_matches_oracle(rule):
             assert sk["converged"] == 1
             if rule == 0:
                 assert sk["iters_min"] == sk["iters_max"]
-                n = sk["iters_max"] + max(sk["finish_iters_max"] - 1, 0)
+                n = sk["iters_max"]  # both phases
                 o.iterate(part, eps, fixed_iters=n)
             else:
                 o.iterate(part, eps, tol=tol, rule=rule, max_iter=5000)
