@@ -132,6 +132,8 @@ void dd_ctx_release(dd_ctx* c) {
     F(c->bt.staging);
     for (auto& e : c->ev)
         if (e) (void)hipEventDestroy(e);
+    if (c->h_small) (void)hipHostFree(c->h_small);
+    c->h_small = nullptr;
     sk_work_release(c->skw);
     flow_release(c);
 }
@@ -529,18 +531,29 @@ static dd_status iterate_impl(dd_ctx* c, int p, double eps, const dd_sinkhorn_op
     launch_comp_boxes(P, c->S, c->AS, c->C, hs);
     launch_scan(c->C.size, c->C.base, nc, hs);
     launch_comp_max(c->C, nc, hs);
+    // the one read-back before the solve: the composite sizes and box dims (which the solver
+    // plans its launches from)
     int32_t info[2];
     int64_t total = 0;
+    c->h_dims.resize(2 * (size_t)nc);
+    if (!c->h_small && hipHostMalloc((void**)&c->h_small, 8 * sizeof(int64_t)) != hipSuccess)
+        return fail(c, DD_ENOMEM, "domdec_iterate: pinned host buffer");
     if (hipMemcpyAsync(info, c->C.info, sizeof info, hipMemcpyDeviceToHost, hs) != hipSuccess ||
         hipMemcpyAsync(&total, c->C.base + nc, sizeof total, hipMemcpyDeviceToHost, hs) !=
             hipSuccess ||
+        hipMemcpyAsync(c->h_dims.data(), c->C.dims, c->h_dims.size() * 4, hipMemcpyDeviceToHost,
+                       hs) != hipSuccess ||
         hipStreamSynchronize(hs) != hipSuccess)
         return fail(c, DD_EDEVICE, "domdec_iterate: reading composite sizes failed");
     const int mw1 = info[0], mw2 = info[1];
+    // the new state's entries are at most four times the composite entries (each basic cell's
+    // truncated box lies in its composite cell's box), so its buffer is sized here and the
+    // truncated sizes are read only at the end
     if (grow(c->mem, c->d_nuJ, c->nuJ_cap, (size_t)total, st).code ||
         grow(c->mem, c->d_lognu, c->lognu_cap, (size_t)total, st).code ||
         grow(c->mem, c->d_b, c->b_cap, (size_t)total, st).code ||
-        grow(c->mem, c->d_tmp, c->tmp_cap, 4 * (size_t)total, st).code)
+        grow(c->mem, c->d_tmp, c->tmp_cap, 4 * (size_t)total, st).code ||
+        grow(c->mem, c->S2.data, c->S2.cap, std::max<size_t>(4 * (size_t)total, 1), st).code)
         return fail(c, st);
     double* lognu = c->d_lognu;
     double* bpot = c->d_b;
@@ -588,8 +601,9 @@ static dd_status iterate_impl(dd_ctx* c, int p, double eps, const dd_sinkhorn_op
     B.max_w2 = mw2;
     B.prec = c->prec;
     dd_batch_stats bs{};
-    const Status ss = sk_solve(B, o, hs, c->skw, &bs, c->d_iters, c->d_cerr);
-    if (ss.code != DD_OK && ss.code != DD_NOTCONV) return fail(c, ss);
+    const Status ss = sk_solve(B, o, hs, c->skw, &bs, c->d_iters, c->d_cerr, c->h_dims.data(),
+                               /*defer=*/true);
+    if (ss.code) return fail(c, ss);
     c->visited[p] = true;
     c->kappa_a[p] = kappa;
     (void)hipEventRecord(c->ev[2], hs);
@@ -599,20 +613,21 @@ static dd_status iterate_impl(dd_ctx* c, int p, double eps, const dd_sinkhorn_op
     launch_fill_i32(c->d_flags, c->nI + 1, 0, hs);
     launch_trunc_boxes(P, c->C, c->d_tmp, c->trunc, c->nI, c->S2.box, c->d_nsize, c->d_flags, hs);
     launch_scan(c->d_nsize, c->S2.base, c->nI, hs);
-    int64_t ntot = 0;
-    int32_t kept = 0;
-    if (hipMemcpyAsync(&ntot, c->S2.base + c->nI, sizeof ntot, hipMemcpyDeviceToHost, hs) !=
-            hipSuccess ||
-        hipMemcpyAsync(&kept, c->d_flags + c->nI, sizeof kept, hipMemcpyDeviceToHost, hs) !=
-            hipSuccess ||
-        hipStreamSynchronize(hs) != hipSuccess)
-        return fail(c, DD_EDEVICE, "domdec_iterate: reading truncated sizes failed");
-    if (grow(c->mem, c->S2.data, c->S2.cap, (size_t)ntot, st).code) return fail(c, st);
     launch_compact(P, c->C, c->d_tmp, c->trunc, c->S2.box, c->S2.base, c->d_flags, c->S2.data, hs);
     std::swap(c->S, c->S2);
     (void)hipEventRecord(c->ev[3], hs);
-    if (hipStreamSynchronize(hs) != hipSuccess || hipGetLastError() != hipSuccess)
+    // the one wait at the end: the new state's size, the untruncated cells, the solve's
+    // statistics
+    if (hipMemcpyAsync(c->h_small, c->S.base + c->nI, sizeof(int64_t), hipMemcpyDeviceToHost, hs) !=
+            hipSuccess ||
+        hipMemcpyAsync(c->h_small + 1, c->d_flags + c->nI, sizeof(int32_t), hipMemcpyDeviceToHost,
+                       hs) != hipSuccess ||
+        hipStreamSynchronize(hs) != hipSuccess || hipGetLastError() != hipSuccess)
         return fail(c, DD_EDEVICE, "domdec_iterate: a kernel failed");
+    const int64_t ntot = c->h_small[0];
+    const int32_t kept = *reinterpret_cast<const int32_t*>(c->h_small + 1);
+    const Status fs = sk_finish(c->skw, &bs);
+    if (fs.code != DD_OK && fs.code != DD_NOTCONV) return fail(c, fs);
     c->last_part = p;
     c->last_eps = eps;
     c->last_mw1 = mw1;
@@ -641,8 +656,8 @@ static dd_status iterate_impl(dd_ctx* c, int p, double eps, const dd_sinkhorn_op
         s.t_init_ms = t;
         *out = s;
     }
-    if (ss.code == DD_NOTCONV) {
-        c->err = ss.msg;
+    if (fs.code == DD_NOTCONV) {
+        c->err = fs.msg;
         return DD_NOTCONV;
     }
     return DD_OK;

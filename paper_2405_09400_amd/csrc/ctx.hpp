@@ -21,6 +21,8 @@ struct dd_ctx {
     double h = 0.0, trunc = 1e-15;
     hipStream_t st = nullptr;
     dd::Mem mem;  // device-memory supplier of every buffer below and of the workspaces
+    std::vector<int32_t> h_dims;  // composite box dims of the current iteration (host)
+    int64_t* h_small = nullptr;   // pinned: sizes read back at the end of an iteration
     std::string err;
     std::vector<double> m;  // basic cell masses (host copy)
     std::vector<int32_t> pmembers[2], pxorig[2];

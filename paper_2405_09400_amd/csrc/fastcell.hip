@@ -256,6 +256,7 @@ __device__ __forceinline__ void ld8d(lds_p<double> p, double (&v)[8]) {
 struct FastArgs {
     SkBatch p;
     const int32_t* cells;  // the cells of this launch, most work first
+    const int4* recs;      // per queue slot: {cell, W1, W2, -}, {shift 1, shift 2, base lo, hi}
     int n;
     int W1m, W2m;          // slice bounds (kernel frame)
     int mode;
@@ -319,12 +320,15 @@ __device__ __noinline__ double exact_x2(lds_p<char> rows, int i1, int i2, int W1
 // per lane processed together; LNREG: log nu_J held in registers (NW == 1, box within
 // 32 x 32).
 template <int NW, int RPL, bool LNREG, int RC>
-__device__ __forceinline__ void run_cell(const FastArgs& g, int cell, lds_p<char> sb, int K) {
+__device__ __forceinline__ void run_cell(const FastArgs& g, int q, lds_p<char> sb, int K) {
     using Tm = Team<NW>;
     const SkBatch& p = g.p;
     const int lane = threadIdx.x & 63, w = Tm::wave(), tl = w * 64 + lane;
     const int r = lane >> 3, c = lane & 7;
-    const int W1o = p.dims[2 * cell], W2o = p.dims[2 * cell + 1];
+    // the slot's packed record: one load for everything the cell's other loads depend on
+    const int4 ra = g.recs[2 * q], rb = g.recs[2 * q + 1];
+    const int cell = ra.x;
+    const int W1o = ra.y, W2o = ra.z;
     const bool T = W2o > W1o;
     const int W1 = T ? W2o : W1o, W2 = T ? W1o : W2o;
     if (W1o < 1 || W2o < 1 || W1o > p.max_w1 || W2o > p.max_w2 || W1 > g.W1m || W2 > g.W2m) {
@@ -336,8 +340,8 @@ __device__ __forceinline__ void run_cell(const FastArgs& g, int cell, lds_p<char
         }
         return;
     }
-    const int E1 = p.shift[2 * cell + (T ? 1 : 0)], E2 = p.shift[2 * cell + (T ? 0 : 1)];
-    const int64_t bse = p.base[cell];
+    const int E1 = T ? rb.y : rb.x, E2 = T ? rb.x : rb.y;
+    const int64_t bse = (int64_t)(((uint64_t)(uint32_t)rb.w << 32) | (uint32_t)rb.z);
     const int s1 = T ? 1 : W2o, s2 = T ? W2o : 1;  // kernel-frame (j1, j2) -> packed offset
     const int xo = T ? c * kA + r : r * kA + c;    // this lane's X point (i1 = r, i2 = c)
     const double invk = 1.0 / p.kappa;
@@ -368,42 +372,44 @@ __device__ __forceinline__ void run_cell(const FastArgs& g, int cell, lds_p<char
     auto Myx = [&](int j) { return (lds_p<double>)(colp(j) + kCMyx); };
 
     // ---- load: X state (first wave), log nu_J, which X rows and columns carry mass --------
+    // (every load of the visit is issued before the first wait: they all depend on the slot's
+    // record only)
     const double* fsrc = g.mode == kFinal ? g.f_keep : p.a;
     double f = 0.0, lm = kNegD, mu = 0.0;
     if (w == 0) {
         f = fsrc[(int64_t)cell * 64 + xo];
         lm = p.logmu[(int64_t)cell * 64 + xo];
-        mu = lm > kZeroMassLog ? exp(lm) : 0.0;
     }
-    if (tl == 0) ired[1] = 0;  // underflow flag of the first X pass
-    Tm::sync();
     float lnr[LNREG ? RPL : 1][4];
     double lnref = 0.0;
     if constexpr (LNREG) {
-        double m = kNegD;
+        double v[RPL][4];
 #pragma unroll
         for (int t = 0; t < RPL; ++t)
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
                 const int j1 = r + 8 * t, j2 = c + 8 * u;
-                const double v = (j1 < W1 && j2 < W2)
-                                     ? p.lognu[bse + (int64_t)j1 * s1 + (int64_t)j2 * s2]
-                                     : kNegD;
-                if (v > kZeroMassLog) m = fmax(m, v);
+                v[t][u] = (j1 < W1 && j2 < W2)
+                              ? p.lognu[bse + (int64_t)j1 * s1 + (int64_t)j2 * s2]
+                              : kNegD;
             }
+        double m = kNegD;
+#pragma unroll
+        for (int t = 0; t < RPL; ++t)
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+                if (v[t][u] > kZeroMassLog) m = fmax(m, v[t][u]);
         lnref = uni(wmax(m));
         if (!(lnref > kZeroMassLog)) lnref = 0.0;
 #pragma unroll
         for (int t = 0; t < RPL; ++t)
 #pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                const int j1 = r + 8 * t, j2 = c + 8 * u;
-                const double v = (j1 < W1 && j2 < W2)
-                                     ? p.lognu[bse + (int64_t)j1 * s1 + (int64_t)j2 * s2]
-                                     : kNegD;
-                lnr[t][u] = v > kZeroMassLog ? (float)(v - lnref) : kNegF;
-            }
+            for (int u = 0; u < 4; ++u)
+                lnr[t][u] = v[t][u] > kZeroMassLog ? (float)(v[t][u] - lnref) : kNegF;
     }
+    if (w == 0) mu = lm > kZeroMassLog ? exp(lm) : 0.0;
+    if (tl == 0) ired[1] = 0;  // underflow flag of the first X pass
+    Tm::sync();
     // X rows / columns with mass (kernel frame), and the cell's mass
     unsigned xrow = 0, xcol = 0;
     double mass_all = 0.0;
@@ -988,7 +994,7 @@ fast_kernel(FastArgs g) {
             if (lane == 0) q = atomicAdd(queue, 1);
             q = __builtin_amdgcn_readfirstlane(__shfl(q, 0, 64));
             if (q >= g.n) break;
-            run_cell<NW, RPL, LNREG, RC>(g, g.cells[q], base, K);
+            run_cell<NW, RPL, LNREG, RC>(g, q, base, K);
         }
     } else {
         const lds_p<char> base = (lds_p<char>)smem;
@@ -998,7 +1004,7 @@ fast_kernel(FastArgs g) {
             __syncthreads();
             const int q = s_q;
             if (q >= g.n) break;
-            run_cell<NW, RPL, LNREG, RC>(g, g.cells[q], base, K);
+            run_cell<NW, RPL, LNREG, RC>(g, q, base, K);
         }
     }
     if (g.mode != kBatch) return;
@@ -1050,6 +1056,19 @@ fast_kernel(FastArgs g) {
         g.ctrl[11] = 0;
         g.ctrl[1] = 0;
     }
+}
+
+// the records of the queue slots: the cell, its box dims, shifts and base
+__global__ void pack_recs_kernel(int n, const int32_t* __restrict__ order,
+                                 const int32_t* __restrict__ dims, const int32_t* __restrict__ shift,
+                                 const int64_t* __restrict__ base, int4* recs) {
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= n) return;
+    const int c = order[q];
+    const uint64_t b = (uint64_t)base[c];
+    recs[2 * q] = make_int4(c, dims[2 * c], dims[2 * c + 1], 0);
+    recs[2 * q + 1] = make_int4(shift[2 * c], shift[2 * c + 1], (int)(uint32_t)b,
+                                (int)(uint32_t)(b >> 32));
 }
 
 __global__ void fill_ints(int* p, int n) {
@@ -1157,7 +1176,8 @@ bool fast_eligible(const SkBatch& p, const std::vector<int32_t>& hd) {
 
 Status fast_solve(const SkBatch& p, const dd_sinkhorn_opts& o, hipStream_t st, SkWork& w,
                   const std::vector<int32_t>& hd, const std::vector<int32_t>& order,
-                  int32_t* iters, double* errs, FastInfo* info, bool final_pass) {
+                  int32_t* iters, double* errs, FastInfo* info, bool final_pass,
+                  int32_t* h_ord) {
     Status S;
     const int n = p.ncells;
     // Cell classes by box shape (kernel frame), most work first within each:
@@ -1193,9 +1213,11 @@ Status fast_solve(const SkBatch& p, const dd_sinkhorn_opts& o, hipStream_t st, S
     const bool arena = w.arena != nullptr;  // no-allocation mode: caller's stream, no events
     if (arena) {
         if ((S = arena_take(w, w.order, (size_t)n)).code ||
-            (S = arena_take(w, w.scr_off, (size_t)n)).code)
+            (S = arena_take(w, w.scr_off, (size_t)n)).code ||
+            (S = arena_take(w, w.recs, 2 * (size_t)n)).code)
             return S;
         w.order_cap = n;
+        w.recs_cap = n;
     } else if (n > w.order_cap) {
         w.mem.put(w.order);
         w.mem.put(w.scr_off);
@@ -1205,10 +1227,20 @@ Status fast_solve(const SkBatch& p, const dd_sinkhorn_opts& o, hipStream_t st, S
         DD_HIP(w.mem.get(&w.order, w.order_cap * sizeof(int32_t)), S);
         DD_HIP(w.mem.get(&w.scr_off, w.order_cap * sizeof(int64_t)), S);
     }
+    if (!arena && n > w.recs_cap) {
+        w.mem.put(w.recs);
+        w.recs = nullptr;
+        w.recs_cap = std::max(n, 1024);
+        DD_HIP(w.mem.get(&w.recs, 2 * (size_t)w.recs_cap * sizeof(int4)), S);
+    }
     if (n > 0) {
-        DD_HIP(hipMemcpyAsync(w.order, ord.data(), n * sizeof(int32_t), hipMemcpyHostToDevice, st),
+        if (h_ord) std::copy(ord.begin(), ord.end(), h_ord);
+        DD_HIP(hipMemcpyAsync(w.order, h_ord ? h_ord : ord.data(), n * sizeof(int32_t),
+                              hipMemcpyHostToDevice, st),
                S);
-        DD_HIP(hipStreamSynchronize(st), S);  // `ord` goes out of scope with this function
+        pack_recs_kernel<<<(n + 255) / 256, 256, 0, st>>>(n, w.order, p.dims, p.shift, p.base,
+                                                          w.recs);
+        if (!h_ord) DD_HIP(hipStreamSynchronize(st), S);  // `ord` goes out of scope here
     }
     FastArgs args[kClasses];
     size_t lds[kClasses];
@@ -1222,6 +1254,7 @@ Status fast_solve(const SkBatch& p, const dd_sinkhorn_opts& o, hipStream_t st, S
         a = FastArgs{};
         a.p = p;
         a.cells = w.order + first[k];
+        a.recs = w.recs + 2 * (size_t)first[k];
         a.n = nk;
         a.W1m = W1m[k];
         a.W2m = W2m[k];

@@ -41,6 +41,9 @@ constexpr int kFastMaxSide = 512;
 // finish, and every cell's iteration count is the float32 phase's.
 Status fast_solve(const SkBatch& p, const dd_sinkhorn_opts& o, hipStream_t st, SkWork& w,
                   const std::vector<int32_t>& hd, const std::vector<int32_t>& ord,
-                  int32_t* iters, double* errs, FastInfo* info, bool final_pass = true);
+                  int32_t* iters, double* errs, FastInfo* info, bool final_pass = true,
+                  int32_t* h_ord = nullptr);
+// h_ord: pinned host room for n ints (the order is uploaded from there without waiting), or
+// NULL (no-allocation mode: uploaded from a temporary, then waited for)
 
 }  // namespace dd

@@ -1012,6 +1012,10 @@ void sk_work_release(SkWork& w) {
     if (w.arena) return;  // no-allocation mode: nothing of its own to release
     w.mem.put(w.order);
     w.mem.put(w.scr_off);
+    w.mem.put(w.recs);
+    if (w.h_stage) (void)hipHostFree(w.h_stage);
+    if (w.h_ctl) (void)hipHostFree(w.h_ctl);
+    if (w.h_tot) (void)hipHostFree(w.h_tot);
     w.mem.put(w.order64);
     w.mem.put(w.scr_off64);
     w.mem.put(w.big);
@@ -1430,9 +1434,13 @@ struct StreamJoin {
 };
 }  // namespace
 
+Status finish_stats(SkWork& w, const int* hctl, const double* htot, dd_batch_stats* stats);
+
 Status sk_solve(const SkBatch& p, const dd_sinkhorn_opts& o, hipStream_t caller_st, SkWork& w,
-                dd_batch_stats* stats, int32_t* cell_iters_out, double* cell_err_out) {
+                dd_batch_stats* stats, int32_t* cell_iters_out, double* cell_err_out,
+                const int32_t* host_dims, bool defer) {
     Status S;
+    w.pend.active = false;
     if (p.ncells < 0 || p.xside < 2 || p.xside > 16 || !(p.kappa > 0.0) || p.max_w1 < 1 ||
         p.max_w2 < 1 || (p.prec != DD_PREC_F32 && p.prec != DD_PREC_F64)) {
         S.code = DD_EINVAL;
@@ -1464,10 +1472,40 @@ Status sk_solve(const SkBatch& p, const dd_sinkhorn_opts& o, hipStream_t caller_
     // into big (workgroup) and small (wave) cells, an LDS tile per class, and global scratch
     // for the boxes beyond their tile
     std::vector<int32_t> hd(2 * (size_t)p.ncells);
-    std::vector<int64_t> hb(p.ncells);
-    DD_HIP(hipMemcpyAsync(hd.data(), p.dims, hd.size() * 4, hipMemcpyDeviceToHost, st), S);
-    DD_HIP(hipMemcpyAsync(hb.data(), p.base, hb.size() * 8, hipMemcpyDeviceToHost, st), S);
-    DD_HIP(hipStreamSynchronize(st), S);
+    if (host_dims) {
+        std::copy(host_dims, host_dims + hd.size(), hd.begin());
+    } else {
+        DD_HIP(hipMemcpyAsync(hd.data(), p.dims, hd.size() * 4, hipMemcpyDeviceToHost, st), S);
+        DD_HIP(hipStreamSynchronize(st), S);
+    }
+    // pinned staging of the launch plans and the statistics (outside no-allocation mode):
+    // [order64 | off64 | order | off | fast order], 8-byte aligned
+    const bool pinned = !arena;
+    if (defer && !pinned) {
+        S.code = DD_EINVAL;
+        S.msg = "sinkhorn: deferred statistics need the allocating entry points";
+        return S;
+    }
+    const size_t nn = (size_t)p.ncells, o4 = (nn * 4 + 7) & ~(size_t)7;
+    const size_t stage_need = 3 * o4 + 2 * nn * 8;
+    if (pinned) {
+        if (!w.h_ctl) DD_HIP(hipHostMalloc((void**)&w.h_ctl, 16 * sizeof(int)), S);
+        if (!w.h_tot) DD_HIP(hipHostMalloc((void**)&w.h_tot, 8 * sizeof(double)), S);
+        if (stage_need > w.h_stage_cap) {
+            if (w.h_stage) (void)hipHostFree(w.h_stage);
+            w.h_stage = nullptr;
+            w.h_stage_cap = 0;
+            const size_t cap = std::max<size_t>(stage_need + stage_need / 4, 1 << 16);
+            DD_HIP(hipHostMalloc((void**)&w.h_stage, cap), S);
+            w.h_stage_cap = cap;
+        }
+    }
+    auto region = [&](size_t off) { return pinned ? w.h_stage + off : nullptr; };
+    int32_t* h_ord64 = (int32_t*)region(0);
+    int64_t* h_off64 = (int64_t*)region(o4);
+    int32_t* h_ordg = (int32_t*)region(o4 + nn * 8);
+    int64_t* h_offg = (int64_t*)region(2 * o4 + nn * 8);
+    int32_t* h_ordf = (int32_t*)region(2 * o4 + 2 * nn * 8);
     const int AS = p.xside;
     // a box outside [1, max_w] is rejected before any launch (a and b untouched)
     for (int c = 0; c < p.ncells; ++c)
@@ -1512,7 +1550,8 @@ Status sk_solve(const SkBatch& p, const dd_sinkhorn_opts& o, hipStream_t caller_
     const Plan P64 = finish ? plan_classes(hd, ord, p.ncells, AS, sizeof(double), kBudgets[1],
                                            kBudgets[1])
                             : Plan{};
-    auto put = [&](int32_t*& dev_ord, int64_t*& dev_off, int& cap, const Plan& pl) -> Status {
+    auto put = [&](int32_t*& dev_ord, int64_t*& dev_off, int& cap, const Plan& pl,
+                   int32_t* h_o, int64_t* h_f) -> Status {
         Status E;
         if (arena) {
             if ((E = arena_take(w, dev_ord, (size_t)p.ncells)).code ||
@@ -1528,15 +1567,21 @@ Status sk_solve(const SkBatch& p, const dd_sinkhorn_opts& o, hipStream_t caller_
             DD_HIP(w.mem.get(&dev_ord, cap * sizeof(int32_t)), E);
             DD_HIP(w.mem.get(&dev_off, cap * sizeof(int64_t)), E);
         }
-        DD_HIP(hipMemcpyAsync(dev_ord, pl.ord.data(), pl.ord.size() * 4, hipMemcpyHostToDevice, st),
-               E);
-        DD_HIP(hipMemcpyAsync(dev_off, pl.off.data(), pl.off.size() * 8, hipMemcpyHostToDevice, st),
-               E);
+        const void* so = pl.ord.data();
+        const void* sf = pl.off.data();
+        if (h_o) {
+            std::copy(pl.ord.begin(), pl.ord.end(), h_o);
+            std::copy(pl.off.begin(), pl.off.end(), h_f);
+            so = h_o;
+            sf = h_f;
+        }
+        DD_HIP(hipMemcpyAsync(dev_ord, so, pl.ord.size() * 4, hipMemcpyHostToDevice, st), E);
+        DD_HIP(hipMemcpyAsync(dev_off, sf, pl.off.size() * 8, hipMemcpyHostToDevice, st), E);
         return E;
     };
     // 8 x 8 blocks in float32 take the register-blocked path (same iteration and rules)
     if (!fast) {
-        S = put(w.order, w.scr_off, w.order_cap, P);
+        S = put(w.order, w.scr_off, w.order_cap, P, h_ordg, h_offg);
         if (S.code) return S;
     }
     SkBatch q = p;
@@ -1544,7 +1589,7 @@ Status sk_solve(const SkBatch& p, const dd_sinkhorn_opts& o, hipStream_t caller_
     q.scr_off = w.scr_off;
     SkBatch q64 = p;
     if (finish) {
-        S = put(w.order64, w.scr_off64, w.order64_cap, P64);
+        S = put(w.order64, w.scr_off64, w.order64_cap, P64, h_ord64, h_off64);
         if (S.code) return S;
         q64.order = w.order64;
         q64.scr_off = w.scr_off64;
@@ -1565,14 +1610,14 @@ Status sk_solve(const SkBatch& p, const dd_sinkhorn_opts& o, hipStream_t caller_
             w.big_bytes = need;
         }
     }
-    // the host vectors above outlive the copies: wait before they go out of scope
-    DD_HIP(hipStreamSynchronize(st), S);
+    // without the pinned staging the copies read the plans' own vectors: wait for them
+    if (!pinned) DD_HIP(hipStreamSynchronize(st), S);
     if (!arena) DD_HIP(hipEventRecord(w.ev0, st), S);
     zero_ints<<<1, 64, 0, st>>>(w.ctrl, 16);
     FastInfo fi;
     int k32 = 0;  // batch rule: the float32 phase's stop iteration
     if (fast)
-        S = fast_solve(p, o, st, w, hd, ord, iters, errs, &fi, !finish);
+        S = fast_solve(p, o, st, w, hd, ord, iters, errs, &fi, !finish, h_ordf);
     else
         S = p.prec == DD_PREC_F32 ? run_solver<float>(q, P.classes, o, st, w, iters, errs, 0, &k32)
                                   : run_solver<double>(q, P.classes, o, st, w, iters, errs);
@@ -1599,11 +1644,55 @@ Status sk_solve(const SkBatch& p, const dd_sinkhorn_opts& o, hipStream_t caller_
     sk_stats_kernel<<<1, kThreads, 0, st>>>(p.ncells, iters, run64 ? w.iters64 : nullptr, errs,
                                             w.cell_mass, o.tol, p.dims, p.xside, w.dtot, w.ctrl);
     if (!arena) DD_HIP(hipEventRecord(w.ev1, st), S);
+    auto& pd = w.pend;
+    pd = SkWork::Pend{};
+    pd.active = true;
+    pd.fast = fast;
+    pd.run64 = run64;
+    pd.ncells = p.ncells;
+    pd.fixed_iters = o.fixed_iters;
+    pd.stop_rule = o.stop_rule;
+    pd.tune = !fast && !arena;
+    pd.choice = choice;
+    pd.key[0] = key.as;
+    pd.key[1] = key.prec;
+    pd.key[2] = key.rule;
+    pd.key[3] = key.bucket;
+    for (int k = 0; k < kClasses; ++k) {
+        pd.n[k] = fi.n[k];
+        pd.lds[k] = fi.lds[k];
+        pd.launches[k] = fi.launches[k];
+        pd.ms[k] = fi.ms[k];
+        pd.terms[k] = fi.terms[k];
+    }
+    pd.n_big = P.n_big;
+    pd.n_giant = P.n_giant;
+    pd.small_tile[0] = P.small_tile[0];
+    pd.small_tile[1] = P.small_tile[1];
+    pd.big_tile[0] = P.big_tile[0];
+    pd.big_tile[1] = P.big_tile[1];
+    pd.small_budget = small_budget;
+    pd.big_budget = big_budget;
+    if (pinned) {
+        DD_HIP(hipMemcpyAsync(w.h_ctl, w.ctrl, 16 * sizeof(int), hipMemcpyDeviceToHost, st), S);
+        DD_HIP(hipMemcpyAsync(w.h_tot, w.dtot, 8 * sizeof(double), hipMemcpyDeviceToHost, st), S);
+        if (defer) return S;  // the caller synchronises, then sk_finish
+        DD_HIP(hipStreamSynchronize(st), S);
+        return sk_finish(w, stats);
+    }
     int hctl[16];
     double htot[8];
     DD_HIP(hipMemcpyAsync(hctl, w.ctrl, sizeof hctl, hipMemcpyDeviceToHost, st), S);
     DD_HIP(hipMemcpyAsync(htot, w.dtot, sizeof htot, hipMemcpyDeviceToHost, st), S);
     DD_HIP(hipStreamSynchronize(st), S);
+    return finish_stats(w, hctl, htot, stats);
+}
+
+Status finish_stats(SkWork& w, const int* hctl, const double* htot, dd_batch_stats* stats) {
+    Status S;
+    const SkWork::Pend& pd = w.pend;
+    w.pend.active = false;
+    const bool arena = w.arena != nullptr;
     float ms = 0.f, ms_main = 0.f;
     if (!arena) {
         DD_HIP(hipEventElapsedTime(&ms, w.ev0, w.ev1), S);
@@ -1615,7 +1704,7 @@ Status sk_solve(const SkBatch& p, const dd_sinkhorn_opts& o, hipStream_t caller_
         return S;
     }
     dd_batch_stats bs{};
-    bs.ncells = p.ncells;
+    bs.ncells = pd.ncells;
     bs.iters_min = hctl[5];
     bs.iters_max = hctl[6];
     bs.err = htot[0];
@@ -1625,8 +1714,8 @@ Status sk_solve(const SkBatch& p, const dd_sinkhorn_opts& o, hipStream_t caller_
     bs.alg_bytes = htot[4];
     bs.time_ms = ms;
     bs.main_ms = ms_main;
-    bs.finish_iters_max = finish ? hctl[8] : 0;
-    if (fast) {
+    bs.finish_iters_max = pd.run64 ? hctl[8] : 0;
+    if (pd.fast) {
         bs.path = 1;
         // fallbacks: first-X-pass outputs kept as upper bounds, exact second-X-pass outputs,
         // repeats of the second X pass after exact first-pass outputs, exact Y-update entries
@@ -1634,32 +1723,34 @@ Status sk_solve(const SkBatch& p, const dd_sinkhorn_opts& o, hipStream_t caller_
         bs.tile_small[1] = hctl[13];
         bs.tile_big[0] = hctl[14];
         bs.tile_big[1] = hctl[15];
-        bs.n_big = fi.n[1] + fi.n[2];
-        bs.n_giant = fi.n[2];
-        bs.lds_kb[0] = (fi.lds[0] + 1023) / 1024;
-        bs.lds_kb[1] = (std::max(fi.lds[1], fi.lds[2]) + 1023) / 1024;
+        bs.n_big = pd.n[1] + pd.n[2];
+        bs.n_giant = pd.n[2];
+        bs.lds_kb[0] = (pd.lds[0] + 1023) / 1024;
+        bs.lds_kb[1] = (std::max(pd.lds[1], pd.lds[2]) + 1023) / 1024;
         for (int k = 0; k < kClasses; ++k) {
-            bs.kernel_launches[k] = fi.launches[k];
-            bs.kernel_ms[k] = fi.ms[k];
-            bs.kernel_terms[k] = fi.terms[k];
+            bs.kernel_launches[k] = pd.launches[k];
+            bs.kernel_ms[k] = pd.ms[k];
+            bs.kernel_terms[k] = pd.terms[k];
         }
     } else {
-        bs.n_big = P.n_big;
-        bs.n_giant = P.n_giant;
-        bs.lds_kb[0] = (int32_t)(small_budget / 1024);
-        bs.lds_kb[1] = (int32_t)(big_budget / 1024);
-        bs.tile_small[0] = P.small_tile[0];
-        bs.tile_small[1] = P.small_tile[1];
-        bs.tile_big[0] = P.big_tile[0];
-        bs.tile_big[1] = P.big_tile[1];
+        bs.n_big = pd.n_big;
+        bs.n_giant = pd.n_giant;
+        bs.lds_kb[0] = (int32_t)(pd.small_budget / 1024);
+        bs.lds_kb[1] = (int32_t)(pd.big_budget / 1024);
+        bs.tile_small[0] = pd.small_tile[0];
+        bs.tile_small[1] = pd.small_tile[1];
+        bs.tile_big[0] = pd.big_tile[0];
+        bs.tile_big[1] = pd.big_tile[1];
     }
-    if (o.fixed_iters > 0)
+    if (pd.fixed_iters > 0)
         bs.converged = 1;
-    else if (o.stop_rule == DD_STOP_CELL)
+    else if (pd.stop_rule == DD_STOP_CELL)
         bs.converged = hctl[7];
     else
         bs.converged = hctl[4];
-    if (!fast && !arena && bs.lse_terms > 0.0) tuner().record(key, choice, ms_main / bs.lse_terms);
+    if (pd.tune && bs.lse_terms > 0.0)
+        tuner().record(TuneKey{pd.key[0], pd.key[1], pd.key[2], pd.key[3]}, pd.choice,
+                       ms_main / bs.lse_terms);
     if (stats) *stats = bs;
     if (!std::isfinite(bs.err)) {
         S.code = DD_ENUMERIC;
@@ -1671,6 +1762,12 @@ Status sk_solve(const SkBatch& p, const dd_sinkhorn_opts& o, hipStream_t caller_
         S.msg = "sinkhorn: iteration limit reached before the tolerance";
     }
     return S;
+}
+
+Status sk_finish(SkWork& w, dd_batch_stats* stats) {
+    // (an empty batch has already reported its statistics)
+    if (!w.pend.active) return Status{};
+    return finish_stats(w, w.h_ctl, w.h_tot, stats);
 }
 
 }  // namespace dd

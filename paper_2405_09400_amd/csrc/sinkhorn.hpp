@@ -43,6 +43,8 @@ struct SkWork {
     int64_t* scr_off = nullptr; // [cap] per-cell scratch offsets
     int32_t* order = nullptr;   // processing order of the main run
     int order_cap = 0;
+    int4* recs = nullptr;       // register-blocked path: per queue slot, the cell's record
+    int recs_cap = 0;
     int32_t* order64 = nullptr; // processing order and scratch offsets of the float64 finish
     int64_t* scr_off64 = nullptr;
     int order64_cap = 0;
@@ -62,6 +64,23 @@ struct SkWork {
     char* arena = nullptr;
     size_t arena_bytes = 0, arena_used = 0;
     Mem mem;  // supplier of the buffers above outside no-allocation mode
+    // Pinned host staging (outside no-allocation mode): the launch plans are copied to the
+    // device from here without waiting, and the statistics come back here; a solve's uploads
+    // are complete before the next solve starts (every solve synchronises at least once).
+    char* h_stage = nullptr;
+    size_t h_stage_cap = 0;
+    int* h_ctl = nullptr;       // [16] control words of the last solve
+    double* h_tot = nullptr;    // [8] its totals
+    // what a solve with deferred statistics leaves for sk_finish
+    struct Pend {
+        bool active = false, fast = false, run64 = false, tune = false;
+        int ncells = 0, fixed_iters = 0, stop_rule = 0, choice = 0;
+        int key[4] = {0, 0, 0, 0};
+        int n[3] = {0, 0, 0}, lds[3] = {0, 0, 0}, launches[3] = {0, 0, 0};
+        double ms[3] = {0.0, 0.0, 0.0}, terms[3] = {0.0, 0.0, 0.0};
+        int n_big = 0, n_giant = 0, small_tile[2] = {0, 0}, big_tile[2] = {0, 0};
+        size_t small_budget = 0, big_budget = 0;
+    } pend;
 };
 
 // Carve n elements from the no-allocation arena (256-byte aligned); DD_EINVAL when the arena
@@ -88,8 +107,14 @@ void sk_work_release(SkWork& w);
 // LDS tile run from global scratch), or 0 when xside is out of range.
 size_t sk_lds_bytes(int xside, int prec);
 
+// host_dims: the cells' box dims already on the host ([ncells][2], as p.dims), or NULL to read
+// them back.  defer: leave the statistics in w (pinned) and return without waiting for the
+// solve; the caller synchronises its stream and then calls sk_finish, which also reports a
+// stop that missed the tolerance.  Not in no-allocation mode.
 Status sk_solve(const SkBatch& p, const dd_sinkhorn_opts& o, hipStream_t st, SkWork& w,
-                dd_batch_stats* stats, int32_t* cell_iters_out, double* cell_err_out);
+                dd_batch_stats* stats, int32_t* cell_iters_out, double* cell_err_out,
+                const int32_t* host_dims = nullptr, bool defer = false);
+Status sk_finish(SkWork& w, dd_batch_stats* stats);
 
 // iters[c] = ctrl[2] (the batch rule's stop iteration) for every cell
 void launch_done_iters(int ncells, int32_t* iters, const int* ctrl, hipStream_t st);
