@@ -809,6 +809,15 @@ def measure(args, workload, prec, steps, warmup, replay=0, cpu=False):
         },
         "cpu_baseline": cpu_rec,
         "error_vs_oracle": cpu_rec["gpu_vs_oracle"] if cpu_rec else None,
+        # the register-blocked path's cell classes in the timed steps (the tuner's pick:
+        # boxes with long side <= wave_side one wave, more than big_entries entries eight)
+        "tuner": {"classes": sorted({(s["sk"]["wave_side"], s["sk"]["big_entries"])
+                                     for s in stats}),
+                  "candidates": [[32, 2048], [32, 1024], [32, 4096], [24, 2048], [24, 1024],
+                                 [24, 4096]],
+                  "host_waits_per_half_iteration": "4 typical: composite sizes, device stop "
+                                                   "flag of the float32 rounds, float64 "
+                                                   "finish stop flag, end of iteration"},
         "time_to_tol": compare,
         "detail": {
             "step_ms": [round(t, 3) for t in step_ms],

@@ -108,9 +108,13 @@ typedef struct {
                                    cell; 1: four waves per cell; 2: eight waves per cell),
                                    the final g launch and the launches after the stop (which
                                    exit at once) included                                   */
-    int32_t reserved2;
+    int32_t wave_side;         /* path 1: the class thresholds used -- boxes whose long side
+                                  is at most wave_side take one wave, ...                   */
     double kernel_ms[3];       /* their summed duration (HIP events on each launch's stream) */
     double kernel_terms[3];    /* LSE terms they evaluated                                   */
+    int32_t big_entries;       /* ... boxes of more entries than this eight waves, the rest
+                                  four (sinkhorn_set_classes; the tuner's pick otherwise)    */
+    int32_t reserved4;
 } dd_batch_stats;
 
 /*
@@ -198,6 +202,21 @@ dd_status sinkhorn_batch_f64(int32_t ncells, int32_t xside, const int32_t* dims,
  * the buffer holds (roughly 0.6 KB per cell with 8 x 8 blocks, plus the global scratch of the
  * largest boxes); nothing is written to a or b then.
  */
+/*
+ * sinkhorn_set_classes -- the cell classes of the register-blocked float32 path (8 x 8 X
+ * blocks; the launch side of App. A.1 "Batching and clustering"): boxes whose long side is at
+ * most wave_side (8..32) are solved by one wave each, boxes of more than big_entries
+ * (64..65536) entries by eight waves, the rest by four.  (0, 0) -- the default -- hands the
+ * choice to the library's tuner, which then starts afresh: per key (stopping mode, mean box
+ * area and cell count, each in powers of two) it tries every candidate pair on consecutive
+ * solves, then keeps the one with the least float32 device time per LSE term; a solve's pick
+ * is reported in dd_batch_stats.wave_side / big_entries.  The choice changes which kernel solves a cell, not
+ * the iteration: results agree to float32 rounding (the one-wave kernel holds log nu_J in
+ * float32 registers, the others read it in float64).  Process-wide;
+ * not safe against concurrent solves.  Errors: DD_EINVAL (out of range).
+ */
+dd_status sinkhorn_set_classes(int32_t wave_side, int32_t big_entries);
+
 dd_status sinkhorn_batch_noalloc(int32_t ncells, int32_t xside, const int32_t* dims,
                                  const int64_t* base, const int32_t* shift, const double* logmu,
                                  const double* lognu, double* a, double* b, double kappa,

@@ -9,7 +9,7 @@ from .binding import (  # noqa: F401
     DD_OK, DD_NOTCONV, DD_EINVAL, DD_ENOMEM, DD_EDEVICE, DD_ESTATE, DD_ENUMERIC,
     DD_PREC_F32, DD_PREC_F64, DD_STOP_BATCH, DD_STOP_CELL, DD_INIT_ZERO, DD_INIT_PREV, DD_INIT_NET,
     DomDecError, lib, lib_path, exported_symbols, sinkhorn_batch, global_sinkhorn, mcf_solve, DomDec,
-    TorchAllocator,
+    TorchAllocator, set_classes,
     WarmStartNet,
     net_param_count, net_init_params,
 )

@@ -27,7 +27,7 @@ SYMBOLS = ("sinkhorn_batch", "sinkhorn_batch_f64", "domdec_init", "domdec_iterat
            "domdec_strerror", "dd_net_param_count", "dd_net_create", "dd_net_params", "dd_net_forward",
            "dd_net_train_step", "dd_net_free", "dd_net_strerror", "domdec_set_net", "domdec_net_samples", "domdec_save", "domdec_restore",
            "extract_potentials", "sinkhorn_batch_noalloc", "domdec_refine", "global_sinkhorn",
-           "domdec_set_clusters")
+           "domdec_set_clusters", "sinkhorn_set_classes")
 
 
 class DomDecError(RuntimeError):
@@ -51,8 +51,9 @@ class BatchStats(ctypes.Structure):
                 ("n_giant", ctypes.c_int32), ("lds_kb", ctypes.c_int32 * 2),
                 ("tile_small", ctypes.c_int32 * 2), ("tile_big", ctypes.c_int32 * 2),
                 ("path", ctypes.c_int32), ("kernel_launches", ctypes.c_int32 * 3),
-                ("reserved2", ctypes.c_int32),
-                ("kernel_ms", ctypes.c_double * 3), ("kernel_terms", ctypes.c_double * 3)]
+                ("wave_side", ctypes.c_int32),
+                ("kernel_ms", ctypes.c_double * 3), ("kernel_terms", ctypes.c_double * 3),
+                ("big_entries", ctypes.c_int32), ("reserved4", ctypes.c_int32)]
 
 
 # dd_params.dev_alloc / dev_free
@@ -186,6 +187,8 @@ def lib():
     L.domdec_init.restype = ctypes.c_int
     L.domdec_init.argtypes = [ctypes.POINTER(Params), dp, dp, ctypes.c_int64, i64p, i64p, dp, vp,
                               ctypes.POINTER(vp)]
+    L.sinkhorn_set_classes.restype = ctypes.c_int
+    L.sinkhorn_set_classes.argtypes = [ctypes.c_int32, ctypes.c_int32]
     L.domdec_set_clusters.restype = ctypes.c_int
     L.domdec_set_clusters.argtypes = [vp, ctypes.c_int32]
     L.domdec_iterate.restype = ctypes.c_int
@@ -341,6 +344,15 @@ def global_sinkhorn(mu, nu, eps, alpha, beta, *, tol=1e-5, max_iter=100000, fixe
     if raise_on_error:
         _check(status)
     return status, _struct_dict(st)
+
+
+def set_classes(wave_side: int = 0, big_entries: int = 0) -> None:
+    """Cell classes of the register-blocked path (sinkhorn_set_classes): boxes with long side
+    <= wave_side one wave, more than big_entries entries eight waves, the rest four; (0, 0)
+    hands the choice back to the library's tuner."""
+    st = lib().sinkhorn_set_classes(int(wave_side), int(big_entries))
+    if st != DD_OK:
+        raise DomDecError(st, lib().domdec_strerror(None, st).decode())
 
 
 class DomDec:

@@ -34,6 +34,7 @@
 #include "fastcell.hpp"
 
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstdlib>
 #include <map>
@@ -797,34 +798,51 @@ __device__ __forceinline__ void run_cell(const FastArgs& g, int q, lds_p<char> s
 #pragma unroll
                 for (int q = 1; q < NW; ++q) mx = fmax(mx, xd[q * 8 + c]);
             }
+            // (the upper sums only while some first-pass output is uncertain: team-uniform)
+            const bool unc = __builtin_amdgcn_readfirstlane(ired[1]) != 0;
             double lo[8], hi[8];
 #pragma unroll
             for (int k = 0; k < 8; ++k) lo[k] = hi[k] = 0.0;
-            for (int t = 0; t < ntw; ++t) {
-                const int j1 = r + 8 * (w + NW * t), jc = min(j1, W1 - 1);
-                const double Rv = Rr(jc)[c];
-                const double u4 = (j1 < W1 && Rv > kZeroMassLog) ? exp_wide(Rv - mx) : 0.0;
-                const double ul = UNC(jc)[c] ? 0.0 : u4;
-                double kx[8];
-                ld8d(KX2(jc), kx);
+            if (unc) {
+                for (int t = 0; t < ntw; ++t) {
+                    const int j1 = r + 8 * (w + NW * t), jc = min(j1, W1 - 1);
+                    const double Rv = Rr(jc)[c];
+                    const double u4 = (j1 < W1 && Rv > kZeroMassLog) ? exp_wide(Rv - mx) : 0.0;
+                    const double ul = UNC(jc)[c] ? 0.0 : u4;
+                    double kx[8];
+                    ld8d(KX2(jc), kx);
 #pragma unroll
-                for (int k = 0; k < 8; ++k) {
-                    hi[k] = fma(kx[k], u4, hi[k]);
-                    lo[k] = fma(kx[k], ul, lo[k]);
+                    for (int k = 0; k < 8; ++k) {
+                        hi[k] = fma(kx[k], u4, hi[k]);
+                        lo[k] = fma(kx[k], ul, lo[k]);
+                    }
+                }
+            } else {
+                for (int t = 0; t < ntw; ++t) {
+                    const int j1 = r + 8 * (w + NW * t), jc = min(j1, W1 - 1);
+                    const double Rv = Rr(jc)[c];
+                    const double u4 = (j1 < W1 && Rv > kZeroMassLog) ? exp_wide(Rv - mx) : 0.0;
+                    double kx[8];
+                    ld8d(KX2(jc), kx);
+#pragma unroll
+                    for (int k = 0; k < 8; ++k) lo[k] = fma(kx[k], u4, lo[k]);
                 }
             }
-            double Slo = rsrd(lo, r), Shi = rsrd(hi, r);
+            double Slo = rsrd(lo, r);
+            double Shi = unc ? rsrd(hi, r) : Slo;
             if constexpr (NW > 1) {
                 xs[w * 64 + lane] = Slo;
-                xs[(NW + w) * 64 + lane] = Shi;
+                if (unc) xs[(NW + w) * 64 + lane] = Shi;
                 Tm::sync();
                 if (w == 0) {
                     Slo = xs[lane];
-                    Shi = xs[NW * 64 + lane];
 #pragma unroll
-                    for (int q = 1; q < NW; ++q) {
-                        Slo += xs[q * 64 + lane];
-                        Shi += xs[(NW + q) * 64 + lane];
+                    for (int q = 1; q < NW; ++q) Slo += xs[q * 64 + lane];
+                    Shi = Slo;
+                    if (unc) {
+                        Shi = xs[NW * 64 + lane];
+#pragma unroll
+                        for (int q = 1; q < NW; ++q) Shi += xs[(NW + q) * 64 + lane];
                     }
                 }
             }
@@ -1082,7 +1100,7 @@ __global__ void fill_ints(int* p, int n) {
 #ifndef FAST_GROUP_RC
 #define FAST_GROUP_RC 2
 #endif
-constexpr int kWaveSide = 32;
+constexpr int kWaveSide = 32;  // the most rows a one-wave team covers (4 per lane)
 #define FAST_WAVE fast_kernel<1, 4, true, FAST_WAVE_RC>
 #define FAST_GROUP fast_kernel<4, 16, false, FAST_GROUP_RC>
 #define FAST_BIG fast_kernel<8, 8, false, FAST_GROUP_RC>
@@ -1143,28 +1161,75 @@ Status prep(Kern k, int block, size_t lds, int items, int& grid) {
 
 namespace {
 // class of a box with long side a and short side b (kernel frame)
-int cell_class(int a, int b) { return a <= kWaveSide ? 0 : a * b > kBigEntries ? 2 : 1; }
+int cell_class(const FastClasses& k, int a, int b) {
+    return a <= k.wave_side ? 0 : a * b > k.big_entries ? 2 : 1;
+}
 constexpr int kClassTeam[kClasses] = {1, 4, 8};
 constexpr size_t kLdsPerCu = 160 * 1024;
-}  // namespace
 
-bool fast_eligible(const SkBatch& p, const std::vector<int32_t>& hd) {
-    static const bool off = [] {
-        const char* e = std::getenv("DD_FAST");
-        return e && e[0] == '0';
-    }();
-    if (off || p.prec != DD_PREC_F32 || p.xside != kA) return false;
+// Candidate class thresholds, the measured default first (sweeps on the 512^2 mixtures).
+constexpr FastClasses kCandidates[] = {{kWaveSide, kBigEntries}, {32, 1024}, {32, 4096},
+                                       {24, 2048},                {24, 1024}, {24, 4096}};
+constexpr int kNumCandidates = sizeof(kCandidates) / sizeof(kCandidates[0]);
+static_assert(kWaveSide == 32, "one-wave teams cover 32 rows (4 per lane)");
+
+class ClassTuner {
+   public:
+    int pick(const std::array<int, 3>& k) {
+        std::lock_guard<std::mutex> g(mu_);
+        Entry& e = tab_[k];
+        for (int c = 0; c < kNumCandidates; ++c)
+            if (e.n[c] == 0) return c;
+        int best = 0;
+        for (int c = 1; c < kNumCandidates; ++c)
+            if (e.t[c] < e.t[best]) best = c;
+        return best;
+    }
+    void record(const std::array<int, 3>& k, int c, double t) {
+        std::lock_guard<std::mutex> g(mu_);
+        Entry& e = tab_[k];
+        e.t[c] = e.n[c] ? std::min(e.t[c], t) : t;
+        e.n[c] += 1;
+    }
+    // a pair to use from now on, or (0, 0): back to tuning, from scratch
+    void force(int ws, int be) {
+        std::lock_guard<std::mutex> g(mu_);
+        forced_ = FastClasses{ws, be};
+        has_forced_ = ws > 0;
+        if (!has_forced_) tab_.clear();
+    }
+    bool forced(FastClasses* k) {
+        std::lock_guard<std::mutex> g(mu_);
+        if (has_forced_) *k = forced_;
+        return has_forced_;
+    }
+
+   private:
+    struct Entry {
+        double t[kNumCandidates] = {};
+        int n[kNumCandidates] = {};
+    };
+    std::mutex mu_;
+    std::map<std::array<int, 3>, Entry> tab_;
+    FastClasses forced_;
+    bool has_forced_ = false;
+};
+
+ClassTuner& class_tuner() {
+    static ClassTuner t;
+    return t;
+}
+
+bool eligible_with(const SkBatch& p, const std::vector<int32_t>& hd, const FastClasses& cls) {
     int W1m[kClasses] = {1, 1, 1}, W2m[kClasses] = {1, 1, 1};
     for (int c = 0; c < p.ncells; ++c) {
         const int a = std::max(std::max(hd[2 * c], hd[2 * c + 1]), 1);
         const int b = std::max(std::min(hd[2 * c], hd[2 * c + 1]), 1);
         if (a > kFastMaxSide) return false;
-        const int k = cell_class(a, b);
+        const int k = cell_class(cls, a, b);
         W1m[k] = std::max(W1m[k], a);
         W2m[k] = std::max(W2m[k], b);
     }
-    // every class's workgroup must fit the LDS of a CU (large boxes of the eight-wave class
-    // may not: those batches take the general path)
     for (int k = 0; k < kClasses; ++k) {
         const int t = kClassTeam[k];
         const size_t need = t == 1 ? kBlock / 64 * slice_bytes(1, W1m[k], W2m[k])
@@ -1174,15 +1239,63 @@ bool fast_eligible(const SkBatch& p, const std::vector<int32_t>& hd) {
     return true;
 }
 
+bool fast_off() {
+    static const bool off = [] {
+        const char* e = std::getenv("DD_FAST");
+        return e && e[0] == '0';
+    }();
+    return off;
+}
+}  // namespace
+
+void fast_force(int wave_side, int big_entries) { class_tuner().force(wave_side, big_entries); }
+
+void fast_record(const int key[3], int choice, double ms_per_term) {
+    if (choice < 0 || choice >= kNumCandidates || !(ms_per_term > 0.0)) return;
+    class_tuner().record({key[0], key[1], key[2]}, choice, ms_per_term);
+}
+
+bool fast_plan(const SkBatch& p, const std::vector<int32_t>& hd, const dd_sinkhorn_opts& o,
+               FastClasses* cls, int* choice, int key[3]) {
+    *choice = -1;
+    if (fast_off() || p.prec != DD_PREC_F32 || p.xside != kA) return false;
+    FastClasses f;
+    if (class_tuner().forced(&f)) {
+        *cls = f;
+        return eligible_with(p, hd, f);
+    }
+    double area = 0.0;
+    for (int c = 0; c < p.ncells; ++c)
+        area += (double)std::max(hd[2 * c], 1) * std::max(hd[2 * c + 1], 1);
+    key[0] = o.fixed_iters > 0 ? 2 : o.stop_rule;
+    key[1] = (int)std::log2(std::max(1.0, area / std::max(p.ncells, 1)));
+    key[2] = (int)std::log2(std::max(1, p.ncells));
+    const int c = class_tuner().pick({key[0], key[1], key[2]});
+    if (eligible_with(p, hd, kCandidates[c])) {
+        *cls = kCandidates[c];
+        *choice = c;
+        return true;
+    }
+    // a candidate whose classes do not fit the LDS: the default, untimed
+    *cls = kCandidates[0];
+    return eligible_with(p, hd, kCandidates[0]);
+}
+
+bool fast_eligible(const SkBatch& p, const std::vector<int32_t>& hd) {
+    if (fast_off() || p.prec != DD_PREC_F32 || p.xside != kA) return false;
+    return eligible_with(p, hd, FastClasses{});
+}
+
 Status fast_solve(const SkBatch& p, const dd_sinkhorn_opts& o, hipStream_t st, SkWork& w,
                   const std::vector<int32_t>& hd, const std::vector<int32_t>& order,
                   int32_t* iters, double* errs, FastInfo* info, bool final_pass,
-                  int32_t* h_ord) {
+                  int32_t* h_ord, FastClasses classes) {
     Status S;
     const int n = p.ncells;
     // Cell classes by box shape (kernel frame), most work first within each:
-    //   0: long side <= 32: one wave per cell (four per workgroup), log nu_J in registers;
-    //   1: the rest up to kBigEntries entries: a workgroup of four waves per cell;
+    //   0: long side <= classes.wave_side (<= 32): one wave per cell (four per workgroup),
+    //      log nu_J in registers;
+    //   1: the rest up to classes.big_entries entries: a workgroup of four waves per cell;
     //   2: larger boxes: a workgroup of eight waves per cell.
     // Classes 1 and 2 read log nu_J from global memory.
     using KernFn = void (*)(FastArgs);
@@ -1198,7 +1311,7 @@ Status fast_solve(const SkBatch& p, const dd_sinkhorn_opts& o, hipStream_t st, S
     for (int c : order) {  // most work first within each class
         const int a = std::max(std::max(hd[2 * c], hd[2 * c + 1]), 1);
         const int b = std::max(std::min(hd[2 * c], hd[2 * c + 1]), 1);
-        const int k = cell_class(a, b);
+        const int k = cell_class(classes, a, b);
         cells[k].push_back(c);
         W1m[k] = std::max(W1m[k], a);
         W2m[k] = std::max(W2m[k], b);

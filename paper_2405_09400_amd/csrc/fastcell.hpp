@@ -26,6 +26,21 @@ struct FastInfo {
 // every box side at most kFastMaxSide, every class's workgroup within the LDS of a CU, and
 // the path not switched off (DD_FAST=0).
 bool fast_eligible(const SkBatch& p, const std::vector<int32_t>& hd);
+
+// Cell classes of the register-blocked path: boxes whose long side is at most wave_side get a
+// wave each, boxes of more than big_entries entries eight waves, the rest four.
+struct FastClasses {
+    int wave_side = 32, big_entries = 2048;
+};
+// The classes for a batch: a forced pair (sinkhorn_set_classes), or the tuner's pick for the
+// batch's key (the mode, the mean box area and the cell count, each in powers of two); every
+// candidate is tried once on consecutive solves of a key, then the one with the least float32
+// time per LSE term stays.  Returns false when the batch does not take the register-blocked
+// path.  `choice` / `key` identify the pick for fast_record.
+bool fast_plan(const SkBatch& p, const std::vector<int32_t>& hd, const dd_sinkhorn_opts& o,
+               FastClasses* cls, int* choice, int key[3]);
+void fast_record(const int key[3], int choice, double ms_per_term);
+void fast_force(int wave_side, int big_entries);
 constexpr int kFastMaxSide = 512;
 
 // The float32 phase of a solve (the caller runs the float64 finish): writes f to p.a, g to
@@ -42,7 +57,7 @@ constexpr int kFastMaxSide = 512;
 Status fast_solve(const SkBatch& p, const dd_sinkhorn_opts& o, hipStream_t st, SkWork& w,
                   const std::vector<int32_t>& hd, const std::vector<int32_t>& ord,
                   int32_t* iters, double* errs, FastInfo* info, bool final_pass = true,
-                  int32_t* h_ord = nullptr);
+                  int32_t* h_ord = nullptr, FastClasses cls = FastClasses{});
 // h_ord: pinned host room for n ints (the order is uploaded from there without waiting), or
 // NULL (no-allocation mode: uploaded from a temporary, then waited for)
 

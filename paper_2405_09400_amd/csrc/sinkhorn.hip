@@ -1543,7 +1543,9 @@ Status sk_solve(const SkBatch& p, const dd_sinkhorn_opts& o, hipStream_t caller_
     const size_t small_budget = kBudgets[choice % kNumBudgets];
     const size_t big_budget = kBudgets[choice / kNumBudgets];
     const bool finish = p.prec == DD_PREC_F32 && o.fixed_iters == 0;
-    const bool fast = fast_eligible(p, hd);
+    FastClasses fcls;
+    int fchoice = -1, fkey[3] = {0, 0, 0};
+    const bool fast = fast_plan(p, hd, o, &fcls, &fchoice, fkey);
     // the general path's plan (not needed when the register-blocked path takes the batch), and
     // the float64 finish's
     const Plan P = fast ? Plan{} : plan_classes(hd, ord, p.ncells, AS, elem, small_budget, big_budget);
@@ -1617,7 +1619,7 @@ Status sk_solve(const SkBatch& p, const dd_sinkhorn_opts& o, hipStream_t caller_
     FastInfo fi;
     int k32 = 0;  // batch rule: the float32 phase's stop iteration
     if (fast)
-        S = fast_solve(p, o, st, w, hd, ord, iters, errs, &fi, !finish, h_ordf);
+        S = fast_solve(p, o, st, w, hd, ord, iters, errs, &fi, !finish, h_ordf, fcls);
     else
         S = p.prec == DD_PREC_F32 ? run_solver<float>(q, P.classes, o, st, w, iters, errs, 0, &k32)
                                   : run_solver<double>(q, P.classes, o, st, w, iters, errs);
@@ -1673,6 +1675,13 @@ Status sk_solve(const SkBatch& p, const dd_sinkhorn_opts& o, hipStream_t caller_
     pd.big_tile[1] = P.big_tile[1];
     pd.small_budget = small_budget;
     pd.big_budget = big_budget;
+    if (fast) {
+        pd.fchoice = arena ? -1 : fchoice;
+        for (int k = 0; k < 3; ++k) pd.fkey[k] = fkey[k];
+        pd.wave_side = fcls.wave_side;
+        pd.big_entries = fcls.big_entries;
+        for (int k = 0; k < kClasses; ++k) pd.terms32 += fi.terms[k];
+    }
     if (pinned) {
         DD_HIP(hipMemcpyAsync(w.h_ctl, w.ctrl, 16 * sizeof(int), hipMemcpyDeviceToHost, st), S);
         DD_HIP(hipMemcpyAsync(w.h_tot, w.dtot, 8 * sizeof(double), hipMemcpyDeviceToHost, st), S);
@@ -1732,6 +1741,10 @@ Status finish_stats(SkWork& w, const int* hctl, const double* htot, dd_batch_sta
             bs.kernel_ms[k] = pd.ms[k];
             bs.kernel_terms[k] = pd.terms[k];
         }
+        bs.wave_side = pd.wave_side;
+        bs.big_entries = pd.big_entries;
+        // the tuner learns from the float32 phase's device time per LSE term
+        if (pd.fchoice >= 0 && pd.terms32 > 0.0) fast_record(pd.fkey, pd.fchoice, ms_main / pd.terms32);
     } else {
         bs.n_big = pd.n_big;
         bs.n_giant = pd.n_giant;
@@ -1808,6 +1821,20 @@ dd_status batch_entry(int prec, int32_t ncells, int32_t xside, const int32_t* di
     return s.code;
 }
 }  // namespace
+
+extern "C" dd_status sinkhorn_set_classes(int32_t wave_side, int32_t big_entries) {
+    if (wave_side == 0 && big_entries == 0) {
+        dd::fast_force(0, 0);
+        return DD_OK;
+    }
+    if (wave_side < 8 || wave_side > 32 || big_entries < 64 || big_entries > 65536) {
+        dd::set_global_error("sinkhorn_set_classes: wave_side in [8, 32], big_entries in "
+                             "[64, 65536], or both 0");
+        return DD_EINVAL;
+    }
+    dd::fast_force(wave_side, big_entries);
+    return DD_OK;
+}
 
 extern "C" dd_status sinkhorn_batch(int32_t ncells, int32_t xside, const int32_t* dims,
                                     const int64_t* base, const int32_t* shift, const double* logmu,

@@ -80,6 +80,9 @@ struct SkWork {
         double ms[3] = {0.0, 0.0, 0.0}, terms[3] = {0.0, 0.0, 0.0};
         int n_big = 0, n_giant = 0, small_tile[2] = {0, 0}, big_tile[2] = {0, 0};
         size_t small_budget = 0, big_budget = 0;
+        int fchoice = -1, fkey[3] = {0, 0, 0};  // register-blocked path: the tuner's pick
+        int wave_side = 0, big_entries = 0;     // and the class thresholds used
+        double terms32 = 0.0;                   // LSE terms of the float32 phase
     } pend;
 };
 
