@@ -208,12 +208,12 @@ dd_status sinkhorn_batch_f64(int32_t ncells, int32_t xside, const int32_t* dims,
  * most wave_side (8..32) are solved by one wave each, boxes of more than big_entries
  * (64..65536) entries by eight waves, the rest by four.  (0, 0) -- the default -- hands the
  * choice to the library's tuner, which then starts afresh: per key (stopping mode, mean box
- * area and cell count, each in powers of two) it tries every candidate pair on consecutive
- * solves, then keeps the one with the least float32 device time per LSE term; a solve's pick
- * is reported in dd_batch_stats.wave_side / big_entries.  The choice changes which kernel solves a cell, not
- * the iteration: results agree to float32 rounding (the one-wave kernel holds log nu_J in
- * float32 registers, the others read it in float64).  Process-wide;
- * not safe against concurrent solves.  Errors: DD_EINVAL (out of range).
+ * area in powers of four, cell count in powers of two) it tries every candidate pair on
+ * consecutive solves, then keeps the one with the least float32 device time per LSE term; a
+ * solve's pick is reported in dd_batch_stats.wave_side / big_entries.  The choice changes
+ * which kernel solves a cell, not the iteration: results agree to float32 rounding (the
+ * one-wave kernel holds log nu_J in float32 registers, the others read it in float64).
+ * Process-wide; not safe against concurrent solves.  Errors: DD_EINVAL (out of range).
  */
 dd_status sinkhorn_set_classes(int32_t wave_side, int32_t big_entries);
 

@@ -79,6 +79,27 @@ __device__ __forceinline__ double dppd(double v) {
         (unsigned)__builtin_amdgcn_mov_dpp((int)(unsigned)(u >> 32), CTRL, 0xF, 0xF, false);
     return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
 }
+// The value of lane ^ 32 or lane ^ 16 by gfx950's lane swaps (VALU, no LDS round trip):
+// permlane32_swap(v, v) hands every lane l the pair (v[l & 31], v[(l & 31) + 32]),
+// permlane16_swap(v, v) the pair (v[l & ~16], v[l | 16]).
+template <int B>
+__device__ __forceinline__ unsigned xoru(unsigned v) {
+    static_assert(B == 16 || B == 32, "lane swaps of 16 or 32");
+    const bool upper = (threadIdx.x & B) != 0;
+    if constexpr (B == 32) {
+        const auto p = __builtin_amdgcn_permlane32_swap(v, v, false, false);
+        return upper ? p[0] : p[1];
+    } else {
+        const auto p = __builtin_amdgcn_permlane16_swap(v, v, false, false);
+        return upper ? p[0] : p[1];
+    }
+}
+template <int B>
+__device__ __forceinline__ double xord(double v) {
+    const unsigned long long u = __builtin_bit_cast(unsigned long long, v);
+    const unsigned lo = xoru<B>((unsigned)u), hi = xoru<B>((unsigned)(u >> 32));
+    return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
+}
 // maximum over the aligned group of 8 lanes (same r); every lane gets the same result
 __device__ __forceinline__ double max8(double v) {
     v = fmax(v, dppd<kDppXor1>(v));
@@ -88,18 +109,26 @@ __device__ __forceinline__ double max8(double v) {
 // maximum over the 8 lanes with the same c (lane bits 3..5)
 __device__ __forceinline__ double maxr(double v) {
     v = fmax(v, dppd<kDppRor8>(v));
-    v = fmax(v, __shfl_xor(v, 16, 64));
-    return fmax(v, __shfl_xor(v, 32, 64));
+    v = fmax(v, xord<16>(v));
+    return fmax(v, xord<32>(v));
 }
+// sum / maximum over the wave (every lane gets the result): quads, then pairs of quads
+// (lane i <-> 7 - i), of 8, of 16 and of 32 lanes
 __device__ __forceinline__ double wsum(double v) {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-    return v;
+    v += dppd<kDppXor1>(v);
+    v += dppd<kDppXor2>(v);
+    v += dppd<kDppMirror8>(v);
+    v += dppd<kDppRor8>(v);
+    v += xord<16>(v);
+    return v + xord<32>(v);
 }
 __device__ __forceinline__ double wmax(double v) {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
-    return v;
+    v = fmax(v, dppd<kDppXor1>(v));
+    v = fmax(v, dppd<kDppXor2>(v));
+    v = fmax(v, dppd<kDppMirror8>(v));
+    v = fmax(v, dppd<kDppRor8>(v));
+    v = fmax(v, xord<16>(v));
+    return fmax(v, xord<32>(v));
 }
 // Reduce-scatter of a[0..7] over the 8 lanes with the same r: lane c gets the sum over those
 // lanes of a[c] (recursive halving with partners 7 - c, c ^ 2, c ^ 1).
@@ -121,10 +150,10 @@ __device__ __forceinline__ double rsrd(const double (&a)[8], int r) {
     double h[4], e[2];
 #pragma unroll
     for (int q = 0; q < 4; ++q)
-        h[q] = (b2 ? a[4 + q] : a[q]) + __shfl_xor(b2 ? a[q] : a[4 + q], 32, 64);
+        h[q] = (b2 ? a[4 + q] : a[q]) + xord<32>(b2 ? a[q] : a[4 + q]);
 #pragma unroll
     for (int q = 0; q < 2; ++q)
-        e[q] = (b1 ? h[2 + q] : h[q]) + __shfl_xor(b1 ? h[q] : h[2 + q], 16, 64);
+        e[q] = (b1 ? h[2 + q] : h[q]) + xord<16>(b1 ? h[q] : h[2 + q]);
     return (b0 ? e[1] : e[0]) + dppd<kDppRor8>(b0 ? e[0] : e[1]);
 }
 
@@ -1264,11 +1293,14 @@ bool fast_plan(const SkBatch& p, const std::vector<int32_t>& hd, const dd_sinkho
         *cls = f;
         return eligible_with(p, hd, f);
     }
+    // the key: the mode and the cell count (a DD layer's partitions share it across the eps
+    // stages, so the candidates are tried in the first solves of a layer); the mean box area
+    // in powers of four
     double area = 0.0;
     for (int c = 0; c < p.ncells; ++c)
         area += (double)std::max(hd[2 * c], 1) * std::max(hd[2 * c + 1], 1);
     key[0] = o.fixed_iters > 0 ? 2 : o.stop_rule;
-    key[1] = (int)std::log2(std::max(1.0, area / std::max(p.ncells, 1)));
+    key[1] = (int)std::log2(std::max(1.0, area / std::max(p.ncells, 1))) / 2;
     key[2] = (int)std::log2(std::max(1, p.ncells));
     const int c = class_tuner().pick({key[0], key[1], key[2]});
     if (eligible_with(p, hd, kCandidates[c])) {

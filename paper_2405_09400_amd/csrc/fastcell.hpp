@@ -33,7 +33,8 @@ struct FastClasses {
     int wave_side = 32, big_entries = 2048;
 };
 // The classes for a batch: a forced pair (sinkhorn_set_classes), or the tuner's pick for the
-// batch's key (the mode, the mean box area and the cell count, each in powers of two); every
+// batch's key (the mode, the mean box area in powers of four, the cell count in powers of two);
+// every
 // candidate is tried once on consecutive solves of a key, then the one with the least float32
 // time per LSE term stays.  Returns false when the batch does not take the register-blocked
 // path.  `choice` / `key` identify the pick for fast_record.
