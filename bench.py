@@ -340,7 +340,16 @@ def cpu_baseline(args, w, ctx, k, rule):
 # source has changed since, traffic is null.
 
 KERNEL_SOURCE = os.path.join(ROOT, "paper_2405_09400_amd", "csrc", "fastcell.hip")
-TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "fast_kernel_mix512_traffic.md")
+def traffic_summary_path(workload):
+    return os.path.join(ROOT, "profiles", f"fast_kernel_{workload}_traffic.md")
+
+
+def trace_summary_path(workload):
+    return os.path.join(ROOT, "profiles", f"fast_kernel_{workload}.md")
+
+
+WORKLOAD_TITLE = {"ms512": "ms512 (512² coarse to fine, s = 4, timed at κ = 1, tol 1e-5, batch rule)",
+                  "mix512": "mix512 (512², s = 4, κ = 1, tol 1e-5, batch rule)"}
 COPY_MIB = 256
 
 
@@ -394,18 +403,18 @@ def traffic_summary(args):
     wf = ref_kib / (sum(w_copy) / len(w_copy))
     f_rows, w_rows = _pmc_rows(fb), _pmc_rows(wb)
     cmd_b = ("rocprofv3 --pmc {c} --kernel-trace -d <out> -o run --output-format csv -- "
-             "python3 bench.py --steps 3 --warmup 1 --no-compare --no-cpu-baseline")
+             f"python3 bench.py --workload {args.workload} --steps 3 --warmup 1 --no-compare "
+             "--no-cpu-baseline --no-extra --classes 32,2048")
     cmd_c = ("rocprofv3 --pmc {c} --kernel-trace -d <out> -o run --output-format csv -- "
              "python3 bench.py --copy-calibration")
     kinds = " ".join(f"'{k}'" for k in args.traffic_kernel)
-    lines = ["# HBM traffic of the register-blocked kernels, mix512 (512², s = 4, κ = 1, tol 1e-5, "
-             "batch rule)", "",
+    lines = [f"# HBM traffic of the register-blocked kernels, {WORKLOAD_TITLE[args.workload]}", "",
              "Commands (from the repository root on the MI355X machine, after `cd /tmp && export "
              "TMPDIR=/tmp`; one counter per run):", "", "```",
              cmd_b.format(c="FETCH_SIZE"), cmd_b.format(c="WRITE_SIZE"),
              cmd_c.format(c="FETCH_SIZE"), cmd_c.format(c="WRITE_SIZE"), "```", "",
-             f"Summarised by `python bench.py --traffic-from <four output dirs> --traffic-kernel "
-             f"{kinds} --traffic-last {last}`.", "",
+             f"Summarised by `python bench.py --workload {args.workload} --traffic-from <four output "
+             f"dirs> --traffic-kernel {kinds} --traffic-last {last}`.", "",
              f"Copy of 256 MiB: FETCH_SIZE reads {sum(f_copy) / len(f_copy):.0f} KiB (scale "
              f"{ff:.3f}), WRITE_SIZE {sum(w_copy) / len(w_copy):.0f} KiB (scale {wf:.3f}).", "",
              "| kernel | FETCH_SIZE KiB per dispatch | WRITE_SIZE KiB per dispatch | HBM bytes per "
@@ -415,7 +424,8 @@ def traffic_summary(args):
         fk = _per_dispatch(f_rows, kern)[-last:]
         wk = _per_dispatch(w_rows, kern)[-last:]
         fkib, wkib = sum(fk) / len(fk), sum(wk) / len(wk)
-        rec = {"kernel": kern, "source_sha256": source_sha256(), "dispatches": len(fk),
+        rec = {"kernel": kern, "source_sha256": source_sha256(), "classes": [32, 2048],
+               "dispatches": len(fk),
                "fetch_kib_per_dispatch": fkib, "write_kib_per_dispatch": wkib,
                "fetch_factor": ff, "write_factor": wf,
                "bytes_per_launch": (fkib * ff + wkib * wf) * 1024.0}
@@ -424,7 +434,7 @@ def traffic_summary(args):
     lines += ["", f"Averaged over the last {last} dispatches of each kernel (the launches of the "
               "timed steps, the ones after the stop, which exit at once, included).", ""]
     lines += ["traffic-json: " + json.dumps(r) for r in recs]
-    with open(args.traffic_out, "w") as f:
+    with open(args.traffic_out or traffic_summary_path(args.workload), "w") as f:
         f.write("\n".join(lines) + "\n")
     print("\n".join(lines))
 
@@ -442,12 +452,13 @@ def trace_summary(args):
                                                recursive=True)[0])))
     tot = sum(float(r["TotalDurationNs"]) for r in stats)
     cmd = ("rocprofv3 --kernel-trace --stats -d <out> -o run --output-format csv -- "
-           "python3 bench.py --steps 3 --warmup 1 --no-compare --no-cpu-baseline")
-    lines = ["# Cell Sinkhorn kernels, mix512 (512², s = 4, κ = 1, tol 1e-5, batch rule)", "",
+           f"python3 bench.py --workload {args.workload} --steps 3 --warmup 1 --no-compare "
+           "--no-cpu-baseline --no-extra --classes 32,2048")
+    lines = [f"# Cell Sinkhorn kernels, {WORKLOAD_TITLE[args.workload]}", "",
              "Command (from the repository root on the MI355X machine, after `cd /tmp && export "
              "TMPDIR=/tmp`):", "", "```", cmd, "```", "",
-             f"Summarised by `python bench.py --trace-from <out> --traffic-last "
-             f"{args.traffic_last}`.  Kernel source SHA-256 (fastcell.hip): "
+             f"Summarised by `python bench.py --workload {args.workload} --trace-from <out> "
+             f"--traffic-last {args.traffic_last}`.  Kernel source SHA-256 (fastcell.hip): "
              f"`{source_sha256()}`.", "",
              "Device: one MI355X (gfx950).  Per-kernel totals over the whole run (set-up "
              "stages included):", "",
@@ -467,20 +478,23 @@ def trace_summary(args):
                       f"launches after the stop, which exit at once, included): average "
                       f"{sum(durs) / len(durs):.1f} us, min {min(durs):.1f} us, max "
                       f"{max(durs):.1f} us."]
-    with open(args.trace_out, "w") as f:
+    with open(args.trace_out or trace_summary_path(args.workload), "w") as f:
         f.write("\n".join(lines) + "\n")
     print("\n".join(lines))
 
 
-def traffic_bytes(kernel_name):
-    """HBM bytes per launch of `kernel_name` from the committed summary, or None when there is
-    none, it covers another kernel, or the kernel's source has changed since."""
-    if not os.path.exists(TRAFFIC_SUMMARY):
+def traffic_bytes(kernel_name, workload, classes):
+    """HBM bytes per launch of `kernel_name` from the committed summary of the workload, or
+    None when there is none, it covers another kernel or other cell classes, or the kernel's
+    source has changed since."""
+    path = traffic_summary_path(workload)
+    if not os.path.exists(path):
         return None
-    for line in open(TRAFFIC_SUMMARY):
+    for line in open(path):
         if line.startswith("traffic-json: "):
             rec = json.loads(line[len("traffic-json: "):])
-            if rec["kernel"] in kernel_name and rec["source_sha256"] == source_sha256():
+            if (rec["kernel"] in kernel_name and rec["source_sha256"] == source_sha256() and
+                    [list(c) for c in classes] == [rec.get("classes")]):
                 return rec["bytes_per_launch"]
     return None
 
@@ -511,6 +525,9 @@ def main():
                          "default: product candidates")
     ap.add_argument("--no-clusters", action="store_true",
                     help="skip the clustering study (time against K-means clusters at 1024^2)")
+    ap.add_argument("--classes", default=None, metavar="WS,BE",
+                    help="force the register-blocked path's cell classes (one-wave side limit, "
+                         "eight-wave entry threshold) instead of the library's tuner")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-compare", action="store_true")
     ap.add_argument("--replay", type=int, default=8)
@@ -525,10 +542,10 @@ def main():
                     default=["fast_kernel<1, 4, true, 2>", "fast_kernel<4, 16, false, 2>",
                              "fast_kernel<8, 8, false, 2>"])
     ap.add_argument("--traffic-last", type=int, default=139)
-    ap.add_argument("--traffic-out", default=TRAFFIC_SUMMARY)
+    ap.add_argument("--traffic-out", default=None)
     ap.add_argument("--trace-from", metavar="DIR",
                     help="write the kernel-time summary of a rocprofv3 kernel-trace run")
-    ap.add_argument("--trace-out", default=os.path.join(ROOT, "profiles", "fast_kernel_mix512.md"))
+    ap.add_argument("--trace-out", default=None)
     args = ap.parse_args()
     if args.traffic_from:
         traffic_summary(args)
@@ -550,6 +567,9 @@ def main():
         copy_calibration()
         return
     dd.lib()
+    if args.classes:
+        ws, be = (int(x) for x in args.classes.split(","))
+        dd.set_classes(ws, be)
 
     line = measure(args, args.workload, args.prec, args.steps, args.warmup,
                    replay=0 if args.no_compare else args.replay, cpu=not args.no_cpu_baseline)
@@ -755,8 +775,9 @@ def measure(args, workload, prec, steps, warmup, replay=0, cpu=False):
             k_ms = ms_c
             k_terms = sum(s["sk"]["kernel_terms"][c] for s in stats)
     k_achieved = k_terms / (k_ms * 1e-3)
-    traffic = traffic_bytes(roof_kernel) if (roof_kernel.startswith("fast_kernel") and
-                                             workload == "mix512") else None
+    run_classes = sorted({(s["sk"]["wave_side"], s["sk"]["big_entries"]) for s in stats})
+    traffic = traffic_bytes(roof_kernel, workload, run_classes) \
+        if roof_kernel.startswith("fast_kernel") else None
     step_ms = [s["wall_ms"] for s in stats]
     log(f"[bench] steps: sinkhorn iters {sk_iters}, sinkhorn {sk_ms / len(stats):.3f} ms/step, "
         f"wall {wall * 1e3 / len(stats):.3f} ms/step")

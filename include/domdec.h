@@ -209,7 +209,8 @@ dd_status sinkhorn_batch_f64(int32_t ncells, int32_t xside, const int32_t* dims,
  * (64..65536) entries by eight waves, the rest by four.  (0, 0) -- the default -- hands the
  * choice to the library's tuner, which then starts afresh: per key (stopping mode, mean box
  * area in powers of four, cell count in powers of two) it tries every candidate pair on
- * consecutive solves, then keeps the one with the least float32 device time per LSE term; a
+ * consecutive solves, then keeps the one with the least float32 device time per LSE term (the
+ * first, measured default, unless another is faster by more than 3%); a
  * solve's pick is reported in dd_batch_stats.wave_side / big_entries.  The choice changes
  * which kernel solves a cell, not the iteration: results agree to float32 rounding (the
  * one-wave kernel holds log nu_J in float32 registers, the others read it in float64).

@@ -1203,15 +1203,18 @@ constexpr int kNumCandidates = sizeof(kCandidates) / sizeof(kCandidates[0]);
 static_assert(kWaveSide == 32, "one-wave teams cover 32 rows (4 per lane)");
 
 class ClassTuner {
+    static constexpr double kMargin = 0.97;
+
    public:
     int pick(const std::array<int, 3>& k) {
         std::lock_guard<std::mutex> g(mu_);
         Entry& e = tab_[k];
         for (int c = 0; c < kNumCandidates; ++c)
             if (e.n[c] == 0) return c;
+        // the default stays unless another candidate is faster by more than run-to-run noise
         int best = 0;
         for (int c = 1; c < kNumCandidates; ++c)
-            if (e.t[c] < e.t[best]) best = c;
+            if (e.t[c] < kMargin * e.t[0] && e.t[c] < e.t[best]) best = c;
         return best;
     }
     void record(const std::array<int, 3>& k, int c, double t) {
