@@ -588,6 +588,11 @@ dd_status dd_net_params(dd_net* net, float* params_out);
 /* Inference on n samples: x (device) [n][8][32][32] float32 -> y (device) [n][32][32]. */
 dd_status dd_net_forward(dd_net* net, int32_t n, const float* x, float* y, void* stream);
 
+/* The same inference with the four 32-channel layers on the matrix cores (MFMA, BF16 inputs,
+ * FP32 sums): each such layer's input is rounded to BF16 first.  This is the forward pass of
+ * the DD_INIT_NET start of domdec_iterate. */
+dd_status dd_net_infer(dd_net* net, int32_t n, const float* x, float* y, void* stream);
+
 /* One Adam step (lr; betas 0.9, 0.999) on the gauge-invariant weighted squared error
  *   loss_b = sum_w weight (y - target - c)^2,  c = sum_w weight (y - target) / sum_w weight,
  * averaged over the n samples (device arrays, layouts as dd_net_forward; target and

@@ -24,7 +24,7 @@ _NAMES = {0: "DD_OK", 1: "DD_NOTCONV", -1: "DD_EINVAL", -2: "DD_ENOMEM", -3: "DD
 # every function include/domdec.h declares
 SYMBOLS = ("sinkhorn_batch", "sinkhorn_batch_f64", "domdec_init", "domdec_iterate", "flow_update",
            "flow_costs", "flow_apply", "dd_mcf_solve", "extract_plan", "domdec_evaluate", "domdec_free",
-           "domdec_strerror", "dd_net_param_count", "dd_net_create", "dd_net_params", "dd_net_forward",
+           "domdec_strerror", "dd_net_param_count", "dd_net_create", "dd_net_params", "dd_net_forward", "dd_net_infer",
            "dd_net_train_step", "dd_net_free", "dd_net_strerror", "domdec_set_net", "domdec_net_samples", "domdec_save", "domdec_restore",
            "extract_potentials", "sinkhorn_batch_noalloc", "domdec_refine", "global_sinkhorn",
            "domdec_set_clusters", "sinkhorn_set_classes")
@@ -224,6 +224,8 @@ def lib():
     L.dd_net_params.argtypes = [vp, fp]
     L.dd_net_forward.restype = ctypes.c_int
     L.dd_net_forward.argtypes = [vp, ctypes.c_int32, vp, vp, vp]
+    L.dd_net_infer.restype = ctypes.c_int
+    L.dd_net_infer.argtypes = [vp, ctypes.c_int32, vp, vp, vp]
     L.dd_net_train_step.restype = ctypes.c_int
     L.dd_net_train_step.argtypes = [vp, ctypes.c_int32, vp, vp, vp, ctypes.c_float, vp, dp]
     L.dd_net_free.restype = None
@@ -578,6 +580,15 @@ class WarmStartNet:
         y = torch.empty((n, 32, 32), dtype=torch.float32, device=x.device)
         s = stream if stream is not None else torch.cuda.current_stream()
         self._check(lib().dd_net_forward(self._net, n, _ptr(x.contiguous()), _ptr(y), _stream_ptr(s)))
+        return y
+
+    def infer(self, x, stream=None):
+        """The DD start's inference (dd_net_infer): 32-channel layers on the matrix cores."""
+        import torch
+        n = int(x.shape[0])
+        y = torch.empty((n, 32, 32), dtype=torch.float32, device=x.device)
+        s = stream if stream is not None else torch.cuda.current_stream()
+        self._check(lib().dd_net_infer(self._net, n, _ptr(x.contiguous()), _ptr(y), _stream_ptr(s)))
         return y
 
     def train_step(self, x, target, weight, lr: float, stream=None) -> float:

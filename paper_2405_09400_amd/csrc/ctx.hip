@@ -578,7 +578,7 @@ static dd_status iterate_impl(dd_ctx* c, int p, double eps, const dd_sinkhorn_op
             return fail(c, st);
         launch_net_features(nc, c->AS, c->C.dims, c->C.shift, c->C.base, logmu, lognu, apot,
                             kappa, nullptr, c->d_nx, nullptr, nullptr, hs);
-        const Status ns = net_forward(c->net, nc, c->d_nx, c->d_ng, hs);
+        const Status ns = net_infer(c->net, nc, c->d_nx, c->d_ng, hs);
         if (ns.code) return fail(c, ns);
         // (the c2b scratch, 4 doubles per box entry, is free until the solve has finished)
         launch_net_start(nc, c->AS, c->C.dims, c->C.shift, c->C.base, logmu, lognu, c->C.gofs,

@@ -121,6 +121,72 @@ __global__ void __launch_bounds__(kT)
     }
 }
 
+// A layer with 32 output channels on the matrix cores (inference): per cell the product
+// D[p][co] = sum_k A[p][k] B[k][co] + bias over the 256 output pixels p (8 tiles of 32 rows),
+// k = tap * CIN + ci (so that each 8-wide K step of v_mfma_f32_32x32x8 bf16 has one tap and 8
+// consecutive channels), A the input window at pixel p and tap (zero outside the input), B the
+// BF16 weights.  The inputs are rounded to BF16 (the weights already are); the products are
+// summed in FP32.  The cell's input is staged in LDS as BF16 with the channel innermost, so a
+// lane's four A values are one 8-byte read; every lane keeps the B fragments of all K steps.
+// Operand layouts of the instruction (checked on the device): A[m][k] in lane m + 32 (k / 4),
+// element k % 4; B[k][n] in lane n + 32 (k / 4), element k % 4; D[m][n] in lane
+// n + 32 ((m / 4) % 2), element 4 (m / 8) + m % 4.
+typedef short bf4 __attribute__((ext_vector_type(4)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+
+template <int CIN>
+__global__ void __launch_bounds__(kT)
+    conv_fwd_mfma_kernel(ConvDesc d, int n, const float* __restrict__ x,
+                         const uint16_t* __restrict__ wbf, const float* __restrict__ params,
+                         float* __restrict__ y) {
+    static_assert(CIN % 8 == 0, "8 channels per K step");
+    constexpr int kSteps = CIN * 9 / 8;
+    extern __shared__ __align__(16) char smem_raw[];
+    uint16_t* xs = reinterpret_cast<uint16_t*>(smem_raw);  // [hin][win][CIN]
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, half = lane >> 5;
+    const int col = lane & 31;
+    bf4 bfrag[kSteps];
+#pragma unroll
+    for (int s = 0; s < kSteps; ++s) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int k = 8 * s + 4 * half + i, tap = k / CIN, ci = k % CIN;
+            bfrag[s][i] = (short)wbf[d.woff + ((int64_t)col * CIN + ci) * 9 + tap];
+        }
+    }
+    const float bias = params[d.boff + col];
+    const int hw = d.hin * d.win;
+    for (int b = blockIdx.x; b < n; b += gridDim.x) {
+        __syncthreads();
+        for (int t = threadIdx.x; t < CIN * hw; t += kT) {
+            const int ci = t / hw, pix = t - ci * hw;
+            xs[pix * CIN + ci] = f2bf(x[(int64_t)b * CIN * hw + t]);
+        }
+        __syncthreads();
+        for (int tile = wv; tile < kPix / 32; tile += kT / 64) {
+            const int p = tile * 32 + col, oy = p / d.wout, ox = p % d.wout;
+            f32x16 acc = {};
+#pragma unroll
+            for (int s = 0; s < kSteps; ++s) {
+                const int k0 = 8 * s + 4 * half, tap = k0 / CIN, ci0 = k0 % CIN;
+                const int iy = oy * d.stride + (tap / 3) * d.dil - d.pad;
+                const int ix = ox * d.stride + (tap % 3) * d.dil - d.pad;
+                bf4 a = {0, 0, 0, 0};
+                if (iy >= 0 && iy < d.hin && ix >= 0 && ix < d.win)
+                    a = *reinterpret_cast<const bf4*>(&xs[(iy * d.win + ix) * CIN + ci0]);
+                acc = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(a, bfrag[s], acc, 0, 0, 0);
+            }
+#pragma unroll
+            for (int j = 0; j < 16; ++j) {
+                const int m = 8 * (j / 4) + 4 * half + (j % 4);
+                float v = acc[j] + bias;
+                if (d.relu) v = fmaxf(v, 0.f);
+                y[((int64_t)b * kNetCh + col) * kPix + tile * 32 + m] = v;
+            }
+        }
+    }
+}
+
 // Gradient with respect to the input of a stride-1 layer:
 // dX[ci][iy][ix] = sum_co sum_tap dZ[co][iy - ky*dil + pad][ix - kx*dil + pad] W[co][ci][tap],
 // dZ = dA * [A > 0] for a ReLU layer (A = the layer's output), dZ = dA otherwise.
@@ -580,6 +646,25 @@ void launch_fwd(const ConvDesc& d, int n, const float* x, const float* wfwd,
     }
 }
 
+// inference: the 32-channel layers on the matrix cores, the last one as in training
+void launch_infer(const ConvDesc& d, int n, const float* x, const uint16_t* wbf,
+                  const float* wfwd, const float* params, float* y, int shuffle,
+                  hipStream_t st) {
+    if (d.cout != kNetCh || d.hout * d.wout != kPix || (d.cin != kNetCin && d.cin != kNetCh)) {
+        launch_fwd(d, n, x, wfwd, params, y, shuffle, st);
+        return;
+    }
+    const size_t lds = (size_t)d.cin * d.hin * d.win * sizeof(uint16_t);
+    const int g = grid_n(n, 2048);
+    if (d.cin == kNetCin) {
+        lds_attr(conv_fwd_mfma_kernel<kNetCin>, lds);
+        conv_fwd_mfma_kernel<kNetCin><<<g, kT, lds, st>>>(d, n, x, wbf, params, y);
+    } else {
+        lds_attr(conv_fwd_mfma_kernel<kNetCh>, lds);
+        conv_fwd_mfma_kernel<kNetCh><<<g, kT, lds, st>>>(d, n, x, wbf, params, y);
+    }
+}
+
 // refresh the forward kernels' FP32 weights from the BF16 copy
 void widen_weights(dd_net* net, hipStream_t st) {
     const ConvDesc* L = table().L;
@@ -643,6 +728,22 @@ Status net_reserve(dd_net* net, int n) {
 }
 
 }  // namespace
+
+Status net_infer(dd_net* net, int n, const float* x, float* y, hipStream_t st) {
+    Status s = net_reserve(net, n);
+    if (s.code || n == 0) return s;
+    const dd::ConvDesc* L = dd::net_layers();
+    const size_t per = (size_t)dd::kNetCh * dd::kPix * n;
+    const float* in = x;
+    for (int l = 0; l < dd::kNetLayers; ++l) {
+        const bool last = l == dd::kNetLayers - 1;
+        float* o = last ? y : net->act + (l % 2) * per;
+        dd::launch_infer(L[l], n, in, net->wbf, net->wfwd, net->master, o, last ? 1 : 0, st);
+        in = o;
+    }
+    DD_HIP(hipGetLastError(), s);
+    return s;
+}
 
 Status net_forward(dd_net* net, int n, const float* x, float* y, hipStream_t st) {
     Status s = net_reserve(net, n);
@@ -792,6 +893,18 @@ extern "C" dd_status dd_net_forward(dd_net* net, int32_t n, const float* x, floa
     if (s.code) return net_fail(net, s.code, s.msg);
     if (hipStreamSynchronize(st) != hipSuccess)
         return net_fail(net, DD_EDEVICE, "dd_net_forward: kernel failed");
+    return DD_OK;
+}
+
+extern "C" dd_status dd_net_infer(dd_net* net, int32_t n, const float* x, float* y,
+                                  void* stream) {
+    if (!net || n < 0 || (n > 0 && (!x || !y)))
+        return net_fail(net, DD_EINVAL, "dd_net_infer: bad argument");
+    const hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    const Status s = net_infer(net, n, x, y, st);
+    if (s.code) return net_fail(net, s.code, s.msg);
+    if (hipStreamSynchronize(st) != hipSuccess)
+        return net_fail(net, DD_EDEVICE, "dd_net_infer: kernel failed");
     return DD_OK;
 }
 

@@ -85,3 +85,6 @@ struct dd_net {
 
 // Forward pass on n samples (x [n][8][32][32] -> y [n][32][32]); keeps the activations.
 dd::Status net_forward(dd_net* net, int n, const float* x, float* y, hipStream_t st);
+// the same net with the 32-channel layers on the matrix cores (inputs rounded to BF16): the
+// learned start of domdec_iterate
+dd::Status net_infer(dd_net* net, int n, const float* x, float* y, hipStream_t st);

@@ -45,6 +45,21 @@ def _ref_forward(params, x):
     return F.pixel_shuffle(h, 2)[:, 0]
 
 
+def _ref_infer(params, x):
+    """The same net as dd_net_infer computes it: the input of each 32-channel layer rounded to
+    BF16 (round to nearest even), products summed in FP32."""
+    F = torch.nn.functional
+    h = x
+    for l, ((w, b), (_, cout, stride, dil)) in enumerate(zip(_unpack(params), LAYERS)):
+        wb = w.to(torch.bfloat16).to(torch.float32)
+        if cout == 32:
+            h = h.to(torch.bfloat16).to(torch.float32)
+        h = F.conv2d(h, wb, b, stride=stride, padding=dil, dilation=dil)
+        if l < len(LAYERS) - 1:
+            h = torch.relu(h)
+    return F.pixel_shuffle(h, 2)[:, 0]
+
+
 def _ref_loss(y, t, w):
     sw = w.sum(dim=(1, 2), keepdim=True)
     c = (w * (y - t)).sum(dim=(1, 2), keepdim=True) / sw
@@ -86,6 +101,26 @@ def test_forward_matches_torch(n):
     ref = _ref_forward(torch.from_numpy(p), torch.from_numpy(x))
     err = (y - ref).abs().max().item()
     assert err <= 2e-5 * ref.abs().max().item() + 1e-6, err
+    net.close()
+
+
+@pytest.mark.parametrize("n", [1, 7, 300])
+def test_infer_on_matrix_cores_matches_torch(n):
+    import paper_2405_09400_amd as dd
+    _need_gpu()
+    print(f"net infer n={n}", flush=True)
+    p = _params(5)
+    x, _, _ = _inputs(n, 13)
+    net = dd.WarmStartNet(p)
+    y = net.infer(torch.from_numpy(x).cuda()).cpu()
+    ref = _ref_infer(torch.from_numpy(p), torch.from_numpy(x))
+    err = (y - ref).abs().max().item()
+    # FP32 sums in another order than the CPU's, and an occasional input rounded the other way
+    # where the two sides' FP32 activations straddle a BF16 rounding boundary
+    assert err <= 2e-3 * ref.abs().max().item(), err
+    # and against the FP32 forward: the BF16 inputs move the output by well under 1%
+    y32 = net.forward(torch.from_numpy(x).cuda()).cpu()
+    assert (y - y32).abs().max().item() <= 2e-2 * y32.abs().max().item()
     net.close()
 
 
