@@ -372,13 +372,39 @@ __device__ __forceinline__ float feat(double lv, double lm) {
     return (float)(fmax(lv - lm + 16.0, 0.0) * 0.25);
 }
 
+// Separable pieces of the X <-> Y log-sum-exps of the learned start.  The cost splits into
+// c(i1 - j1 + E1) + c(i2 - j2 + E2) with c(d) = d^2 / kappa, so an LSE over the X block (or
+// over the box) is two LSEs over one axis each, the first into LDS.  Each row of the
+// two-pass LSE takes its maximum in the precision of its inputs and sums the exponentials in
+// FP32 relative to it.
+constexpr int kRows = 64;  // box rows per pass of the Y-side kernels
+
+// row LSE of fx[.][i2] (double, X block) against the column cost of one box row:
+//   t = LSE_{i1} [fx(i1, i2) - c(i1 - j1 + E1)]
+__device__ __forceinline__ double lse_xcol(const double* fx, int xside, int i2, int dj,
+                                           float invk) {
+    double mx = kNegD;
+    for (int i1 = 0; i1 < xside; ++i1) {
+        const double d = i1 + dj;
+        mx = fmax(mx, fx[i1 * xside + i2] - d * d * invk);
+    }
+    float sm = 0.f;
+    for (int i1 = 0; i1 < xside; ++i1) {
+        const double d = i1 + dj;
+        sm += __expf((float)(fx[i1 * xside + i2] - d * d * invk - mx));
+    }
+    return mx + log((double)sm);
+}
+
 // Features of cell J on the 32x32 window; window position w maps to box-local j = w - o + E
 // and to X pixel i = w - o (o = (32 - xside)/2).  One workgroup per cell:
 //   1. the cell's mass m_J, and f0 + log mu on the X block (LDS);
-//   2. g0(w) = -LSE_i [f0(i) + log mu(i) - C(i, w)] on the support of nu_J in the window;
+//   2. g0(w) = -LSE_i [f0(i) + log mu(i) - C(i, w)] on the support of nu_J in the window,
+//      separably: LSE over i1 for every window row and X column into LDS, then over i2;
 //   3. its mean under the weights nu_J / m_J, taken out;
-//   4. f1(i) = -LSE_w [g0(w) + log nu_J(w) - C(i, w)] on the X block (four lanes per X
-//      point, a quarter of the window each), and the channels.
+//   4. f1(i) = -LSE_w [g0(w) + log nu_J(w) - C(i, w)] on the X block, separably: LSE over
+//      w2 for every window row and X column into LDS, then over w1 (four lanes per X point,
+//      a quarter of the rows each), and the channels.
 __global__ void __launch_bounds__(kT)
     net_features_kernel(int ncell, int xside, const int32_t* __restrict__ dims,
                         const int32_t* __restrict__ shift, const int64_t* __restrict__ base,
@@ -390,6 +416,8 @@ __global__ void __launch_bounds__(kT)
     __shared__ float gv[kNetWin * kNetWin];  // g0 + log nu_J - lm (kNegF off the support)
     __shared__ float gs[kNetWin * kNetWin];  // g0 (raw)
     __shared__ float df[64];          // f1 - f0
+    __shared__ double tw[kNetWin * 8];  // LSE over i1, per window row and X column
+    __shared__ float sw1[kNetWin * 8];  // LSE over w2, per window row and X column
     constexpr int W2 = kNetWin * kNetWin;
     const int N2 = xside * xside, o = (kNetWin - xside) / 2;
     for (int J = blockIdx.x; J < ncell; J += gridDim.x) {
@@ -402,6 +430,11 @@ __global__ void __launch_bounds__(kT)
         }
         m = block_sum(m, red);  // synchronises, so fx is complete
         const double lm = log(m);
+        for (int k = threadIdx.x; k < kNetWin * xside; k += kT) {
+            const int w1 = k / xside, i2 = k - w1 * xside;
+            tw[k] = lse_xcol(fx, xside, i2, o - w1, invk);
+        }
+        __syncthreads();
         const int W1 = dims[2 * J], Wd2 = dims[2 * J + 1];
         const int E1 = shift[2 * J], E2 = shift[2 * J + 1];
         const int64_t bs = base[J];
@@ -414,15 +447,16 @@ __global__ void __launch_bounds__(kT)
             const bool has = ln > kZeroMassLog;
             double g = 0.0;
             if (has) {
+                const double* t = tw + w1 * xside;
                 double mx = kNegD;
-                for (int i = 0; i < N2; ++i) {
-                    const double d1 = o + i / xside - w1, d2 = o + i % xside - w2;
-                    mx = fmax(mx, fx[i] - (d1 * d1 + d2 * d2) * invk);
+                for (int i2 = 0; i2 < xside; ++i2) {
+                    const double d = o + i2 - w2;
+                    mx = fmax(mx, t[i2] - d * d * invk);
                 }
                 float sm = 0.f;
-                for (int i = 0; i < N2; ++i) {
-                    const double d1 = o + i / xside - w1, d2 = o + i % xside - w2;
-                    sm += __expf((float)(fx[i] - (d1 * d1 + d2 * d2) * invk - mx));
+                for (int i2 = 0; i2 < xside; ++i2) {
+                    const double d = o + i2 - w2;
+                    sm += __expf((float)(t[i2] - d * d * invk - mx));
                 }
                 g = -(mx + log((double)sm));
             }
@@ -439,28 +473,50 @@ __global__ void __launch_bounds__(kT)
         sw = block_sum(sw, red);
         swp = block_sum(swp, red);
         const double gpm = sw > 0.0 ? swp / sw : 0.0;
-        // f1 on the X block: lane t takes X point t / 4 and the window rows q = t % 4 (mod 4)
+        // f1 on the X block: the LSE over w2 per window row and X column (block_sum above
+        // synchronised, so gv is complete), then lane t takes X point t / 4 and the window
+        // rows q = t % 4 (mod 4)
+        for (int k = threadIdx.x; k < kNetWin * xside; k += kT) {
+            const int w1 = k / xside, i2 = k - w1 * xside;
+            const float* row = gv + w1 * kNetWin;
+            float rm = kNegF;
+            for (int w2 = 0; w2 < kNetWin; ++w2) {
+                const float d = (float)(o + i2 - w2);
+                rm = fmaxf(rm, row[w2] - d * d * invk);
+            }
+            float rs = 0.f;
+            if (rm > 0.5f * kNegF)
+                for (int w2 = 0; w2 < kNetWin; ++w2) {
+                    const float d = (float)(o + i2 - w2);
+                    rs += __expf(row[w2] - d * d * invk - rm);
+                }
+            sw1[k] = rm > 0.5f * kNegF ? rm + __logf(rs) : kNegF;
+        }
+        __syncthreads();
         {
             const int i = threadIdx.x >> 2, q = threadIdx.x & 3;
             const bool live = i < N2;
             const int i1 = live ? i / xside : 0, i2 = live ? i % xside : 0;
-            float mx = kNegF;
-            for (int w1 = q; w1 < kNetWin; w1 += 4)
-                for (int w2 = 0; w2 < kNetWin; ++w2) {
-                    const float d1 = (float)(o + i1 - w1), d2 = (float)(o + i2 - w2);
-                    mx = fmaxf(mx, gv[w1 * kNetWin + w2] - (d1 * d1 + d2 * d2) * invk);
+            float mx = kNegF, sm = 0.f;
+            for (int w1 = q; w1 < kNetWin; w1 += 4) {
+                const float s = sw1[w1 * xside + i2];
+                if (!(s > 0.5f * kNegF)) continue;
+                const float d = (float)(o + i1 - w1);
+                const float x = s - d * d * invk;
+                if (x > mx) {
+                    sm = sm * __expf(mx - x) + 1.f;
+                    mx = x;
+                } else {
+                    sm += __expf(x - mx);
                 }
-            mx = fmaxf(mx, __shfl_xor(mx, 1, 64));
-            mx = fmaxf(mx, __shfl_xor(mx, 2, 64));
-            float sm = 0.f;
-            if (mx > 0.5f * kNegF)
-                for (int w1 = q; w1 < kNetWin; w1 += 4)
-                    for (int w2 = 0; w2 < kNetWin; ++w2) {
-                        const float d1 = (float)(o + i1 - w1), d2 = (float)(o + i2 - w2);
-                        sm += __expf(gv[w1 * kNetWin + w2] - (d1 * d1 + d2 * d2) * invk - mx);
-                    }
-            sm += __shfl_xor(sm, 1, 64);
-            sm += __shfl_xor(sm, 2, 64);
+            }
+            for (int k = 1; k < 4; k <<= 1) {
+                const float mo = __shfl_xor(mx, k, 64), so = __shfl_xor(sm, k, 64);
+                const float mn = fmaxf(mx, mo);
+                sm = (mx > 0.5f * kNegF ? sm * __expf(mx - mn) : 0.f) +
+                     (mo > 0.5f * kNegF ? so * __expf(mo - mn) : 0.f);
+                mx = mn;
+            }
             if (live && q == 0) {
                 // f1 = -(lm + mx + log sm); the gauge of g0 cancels in f1 - f0
                 const bool ok = fx[i] > 0.5 * kNegD && mx > 0.5f * kNegF && sm > 0.f;
@@ -507,7 +563,8 @@ __global__ void __launch_bounds__(kT)
 // with C(i, j) = ((i1 - j1 + E1)^2 + (i2 - j2 + E2)^2) / kappa and the mean of dg under the
 // weights nu_J / m_J on the window (the net's output has no fixed constant; inside and outside
 // the window the base is the same g0).  v = g + log nu_J is written packed like log nu_J
-// (float; -inf where nu_J = 0).
+// (float; -inf where nu_J = 0).  Separable: t(j1, i2) = LSE_{i1} [...] for a pass of box
+// rows into LDS, then g(j1, j2) = -LSE_{i2} [t(j1, i2) - c(i2 - j2 + E2)].
 __global__ void __launch_bounds__(kT)
     net_gbox_kernel(int ncell, int xside, const int32_t* __restrict__ dims,
                     const int32_t* __restrict__ shift, const int64_t* __restrict__ base,
@@ -516,6 +573,7 @@ __global__ void __launch_bounds__(kT)
                     float* __restrict__ v) {
     __shared__ double red[8];
     __shared__ double fx[64];
+    __shared__ double tr[kRows * 8];
     constexpr int W2 = kNetWin * kNetWin;
     const int N2 = xside * xside, o = (kNetWin - xside) / 2;
     for (int J = blockIdx.x; J < ncell; J += gridDim.x) {
@@ -545,64 +603,95 @@ __global__ void __launch_bounds__(kT)
         sw = block_sum(sw, red);
         swd = block_sum(swd, red);
         const double dm = sw > 0.0 ? swd / sw : 0.0;
-        const int ne = W1 * Wd2;
-        for (int e = threadIdx.x; e < ne; e += kT) {
-            const int j1 = e / Wd2, j2 = e % Wd2;
-            const double ln = lognu[bs + e];
-            float out = kNegF;
-            if (ln > kZeroMassLog) {
-                double mx = kNegD;
-                for (int i = 0; i < N2; ++i) {
-                    const double d1 = i / xside - j1 + E1, d2 = i % xside - j2 + E2;
-                    mx = fmax(mx, fx[i] - (d1 * d1 + d2 * d2) * invk);
-                }
-                float sm = 0.f;
-                for (int i = 0; i < N2; ++i) {
-                    const double d1 = i / xside - j1 + E1, d2 = i % xside - j2 + E2;
-                    sm += __expf((float)(fx[i] - (d1 * d1 + d2 * d2) * invk - mx));
-                }
-                double g = -(mx + log((double)sm));
-                const int w1 = j1 + o - E1, w2 = j2 + o - E2;
-                if (w1 >= 0 && w1 < kNetWin && w2 >= 0 && w2 < kNetWin)
-                    g += (double)dg[(int64_t)J * W2 + w1 * kNetWin + w2] - dm;
-                out = (float)(g + ln);
+        for (int r0 = 0; r0 < W1; r0 += kRows) {
+            const int nr = min(kRows, W1 - r0);
+            for (int k = threadIdx.x; k < nr * xside; k += kT) {
+                const int j1 = r0 + k / xside, i2 = k % xside;
+                tr[k] = lse_xcol(fx, xside, i2, E1 - j1, invk);
             }
-            v[bs + e] = out;
+            __syncthreads();
+            for (int e = threadIdx.x; e < nr * Wd2; e += kT) {
+                const int r = e / Wd2, j1 = r0 + r, j2 = e - r * Wd2;
+                const int64_t at = bs + (int64_t)j1 * Wd2 + j2;
+                const double ln = lognu[at];
+                float out = kNegF;
+                if (ln > kZeroMassLog) {
+                    const double* t = tr + r * xside;
+                    double mx = kNegD;
+                    for (int i2 = 0; i2 < xside; ++i2) {
+                        const double d = i2 - j2 + E2;
+                        mx = fmax(mx, t[i2] - d * d * invk);
+                    }
+                    float sm = 0.f;
+                    for (int i2 = 0; i2 < xside; ++i2) {
+                        const double d = i2 - j2 + E2;
+                        sm += __expf((float)(t[i2] - d * d * invk - mx));
+                    }
+                    double g = -(mx + log((double)sm));
+                    const int w1 = j1 + o - E1, w2 = j2 + o - E2;
+                    if (w1 >= 0 && w1 < kNetWin && w2 >= 0 && w2 < kNetWin)
+                        g += (double)dg[(int64_t)J * W2 + w1 * kNetWin + w2] - dm;
+                    out = (float)(g + ln);
+                }
+                v[at] = out;
+            }
+            __syncthreads();
         }
-        __syncthreads();
     }
 }
 
 // The learned start: f(i) = -LSE_j [v(j) - C(i, j)] over the whole box (an exact X-update of
-// the corrected Y potential); four lanes per X point, each a quarter of the entries with an
-// online maximum.  Also records the gauge offsets of this solve (as the zero /
-// previous-iterate start does).
+// the corrected Y potential).  Separable: s(j1, i2) = LSE_{j2} [v(j1, j2) - c(i2 - j2 + E2)]
+// for a pass of box rows into LDS, then four lanes per X point fold the pass's rows
+// (j1 = q mod 4) into an online maximum and sum, f = -LSE_{j1} [s(j1, i2) - c(i1 - j1 + E1)].
+// Also records the gauge offsets of this solve (as the zero / previous-iterate start does).
 __global__ void __launch_bounds__(kT)
     net_fbox_kernel(int ncell, int xside, const int32_t* __restrict__ dims,
                     const int32_t* __restrict__ shift, const int64_t* __restrict__ base,
                     const int32_t* __restrict__ gofs, const float* __restrict__ v, float invk,
                     double* __restrict__ a, int32_t* __restrict__ g_stored) {
+    __shared__ float sr[kRows * 8];
     const int N2 = xside * xside;
+    const int i = threadIdx.x >> 2, q = threadIdx.x & 3;
+    const bool live = i < N2;
+    const int i1 = live ? i / xside : 0, i2 = live ? i % xside : 0;
     for (int J = blockIdx.x; J < ncell; J += gridDim.x) {
         const int W1 = dims[2 * J], Wd2 = dims[2 * J + 1];
         const int E1 = shift[2 * J], E2 = shift[2 * J + 1];
         const int64_t bs = base[J];
-        const int ne = W1 * Wd2;
-        const int i = threadIdx.x >> 2, q = threadIdx.x & 3;
-        const bool live = i < N2;
-        const int i1 = live ? i / xside : 0, i2 = live ? i % xside : 0;
         float mx = kNegF, sm = 0.f;
-        for (int e = q; e < ne; e += 4) {
-            const float ve = v[bs + e];
-            if (!(ve > 0.5f * kNegF)) continue;
-            const float d1 = (float)(i1 - e / Wd2 + E1), d2 = (float)(i2 - e % Wd2 + E2);
-            const float x = ve - (d1 * d1 + d2 * d2) * invk;
-            if (x > mx) {
-                sm = sm * __expf(mx - x) + 1.f;
-                mx = x;
-            } else {
-                sm += __expf(x - mx);
+        for (int r0 = 0; r0 < W1; r0 += kRows) {
+            const int nr = min(kRows, W1 - r0);
+            for (int k = threadIdx.x; k < nr * xside; k += kT) {
+                const int r = k / xside, c = k - r * xside;
+                const float* row = v + bs + (int64_t)(r0 + r) * Wd2;
+                float rm = kNegF;
+                for (int j2 = 0; j2 < Wd2; ++j2) {
+                    const float d = (float)(c - j2 + E2);
+                    rm = fmaxf(rm, row[j2] - d * d * invk);
+                }
+                float rs = 0.f;
+                if (rm > 0.5f * kNegF)
+                    for (int j2 = 0; j2 < Wd2; ++j2) {
+                        const float d = (float)(c - j2 + E2);
+                        rs += __expf(row[j2] - d * d * invk - rm);
+                    }
+                sr[k] = rm > 0.5f * kNegF ? rm + __logf(rs) : kNegF;
             }
+            __syncthreads();
+            for (int r = q; r < nr; r += 4) {
+                const float s = sr[r * xside + i2];
+                if (!(s > 0.5f * kNegF)) continue;
+                const float d = (float)(i1 - (r0 + r) + E1);
+                const float x = s - d * d * invk;
+                if (x > mx) {
+                    sm = sm * __expf(mx - x) + 1.f;
+                    mx = x;
+                } else {
+                    sm += __expf(x - mx);
+                }
+            }
+            __syncthreads();
         }
         // combine the four partial (max, sum) pairs of an X point
         for (int k = 1; k < 4; k <<= 1) {

@@ -217,6 +217,51 @@ def test_samples_and_net_start_keep_tolerance():
     net.close()
 
 
+def test_zero_correction_start_is_one_sinkhorn_iteration():
+    """With a zero last layer (dg = 0) the learned start is one exact Y-update then X-update
+    from the previous-iterate start f0 (over the whole box), so k float64 iterations from it
+    end where k + 1 from f0 end.  The start's separable sums are FP32, so the plans agree to
+    float32 rounding, not bit for bit."""
+    import paper_2405_09400_amd as dd
+    _need_gpu()
+    print("net start with dg = 0 vs one more iteration, N=64 s=4", flush=True)
+    wl = synth.workload("mix256", N=64)
+    g = dd.DomDec(wl.mu, wl.nu, 4, wl.init, prec=dd.DD_PREC_F64)
+    h = 1.0 / 64
+    for part in "ABAB":
+        g.iterate(part, 2 * h * h, fixed_iters=20)
+    p = dd.net_init_params(3)
+    p[-(4 * 32 * 9 + 4):] = 0.0
+    net = dd.WarmStartNet(p)
+    g.set_net(net)
+
+    def dense(nu_i):
+        out = np.zeros((len(nu_i), 64 * 64))
+        for k, (i, v) in enumerate(nu_i):
+            out[k, i] = v
+        return out
+
+    for part, k in (("A", 1), ("B", 6)):
+        g.save()
+        g.iterate(part, h * h, fixed_iters=k, init=dd.DD_INIT_NET)
+        p1 = dense(g.nu_i_sparse())
+        g.restore()
+        g.iterate(part, h * h, fixed_iters=k + 1, init=dd.DD_INIT_PREV)
+        p2 = dense(g.nu_i_sparse())
+        err = np.abs(p1 - p2).sum() / p2.sum()
+        assert err <= 2e-6, (part, k, err)
+        # and it is not the same as k iterations from f0
+        g.restore()
+        g.iterate(part, h * h, fixed_iters=k, init=dd.DD_INIT_PREV)
+        p0 = dense(g.nu_i_sparse())
+        assert np.abs(p0 - p2).sum() / p2.sum() > 100 * err
+        g.restore()
+        g.iterate(part, h * h, fixed_iters=k + 1, init=dd.DD_INIT_PREV)
+    g.set_net(None)
+    g.close()
+    net.close()
+
+
 def test_net_start_requires_net():
     import paper_2405_09400_amd as dd
     _need_gpu()
