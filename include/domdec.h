@@ -588,9 +588,10 @@ dd_status dd_net_params(dd_net* net, float* params_out);
 /* Inference on n samples: x (device) [n][8][32][32] float32 -> y (device) [n][32][32]. */
 dd_status dd_net_forward(dd_net* net, int32_t n, const float* x, float* y, void* stream);
 
-/* The same inference with the four 32-channel layers on the matrix cores (MFMA, BF16 inputs,
- * FP32 sums): each such layer's input is rounded to BF16 first.  This is the forward pass of
- * the DD_INIT_NET start of domdec_iterate. */
+/* The same inference in one kernel with every layer on the matrix cores (MFMA, BF16 inputs,
+ * FP32 sums): each layer's input is rounded to BF16 first; bias and ReLU are applied in FP32.
+ * This is the forward pass of the DD_INIT_NET start of domdec_iterate.  Needs no memory beyond
+ * x and y.  Errors: DD_EINVAL (null net, n < 0, null x or y with n > 0), DD_EDEVICE. */
 dd_status dd_net_infer(dd_net* net, int32_t n, const float* x, float* y, void* stream);
 
 /* One Adam step (lr; betas 0.9, 0.999) on the gauge-invariant weighted squared error

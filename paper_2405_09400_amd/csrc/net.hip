@@ -1,15 +1,18 @@
 // Learned warm start: conv-net inference and training kernels, cell features and the
 // X-update that turns a predicted Y potential into the initial X potential.
 //
-// All kernels are direct 3x3 convolutions on the vector ALUs: one workgroup of 256 lanes
-// per sample, one output pixel per lane (every layer has a 16x16 output), FP32
-// accumulation.  The forward kernel stages the sample's input in LDS and reads the weights
-// (the BF16 values widened to FP32 after every update, laid out [ci][tap][co]) with
-// wave-uniform loads from global memory, so they arrive through the scalar cache and feed the
-// multiply-adds as scalar operands instead of occupying LDS bandwidth.  The backward kernels
-// stage the weights in LDS.  Training keeps FP32 master weights with Adam and refreshes the BF16
-// copy after every step.  The weight gradients are reduced over the batch in a fixed
-// order (per-workgroup partials, then one reduction), so training is deterministic.
+// Inference (the learned start of the cell solves) is one kernel for the whole net: one
+// workgroup per cell, every layer on the matrix cores (BF16 operands, FP32 accumulation),
+// the activations kept in LDS between layers.  Training runs direct 3x3 convolutions on the
+// vector ALUs: one workgroup of 256 lanes per sample, one output pixel per lane (every layer
+// has a 16x16 output), FP32 accumulation.  The training forward kernel stages the sample's
+// input in LDS and reads the weights (the BF16 values widened to FP32 after every update, laid
+// out [ci][tap][co]) with wave-uniform loads from global memory, so they arrive through the
+// scalar cache and feed the multiply-adds as scalar operands instead of occupying LDS
+// bandwidth.  The backward kernels stage the weights in LDS.  Training keeps FP32 master
+// weights with Adam and refreshes the BF16 copy after every step.  The weight gradients are
+// reduced over the batch in a fixed order (per-workgroup partials, then one reduction), so
+// training is deterministic.
 #include "net.hpp"
 
 #include <algorithm>
@@ -121,70 +124,153 @@ __global__ void __launch_bounds__(kT)
     }
 }
 
-// A layer with 32 output channels on the matrix cores (inference): per cell the product
-// D[p][co] = sum_k A[p][k] B[k][co] + bias over the 256 output pixels p (8 tiles of 32 rows),
-// k = tap * CIN + ci (so that each 8-wide K step of v_mfma_f32_32x32x8 bf16 has one tap and 8
-// consecutive channels), A the input window at pixel p and tap (zero outside the input), B the
-// BF16 weights.  The inputs are rounded to BF16 (the weights already are); the products are
-// summed in FP32.  The cell's input is staged in LDS as BF16 with the channel innermost, so a
-// lane's four A values are one 8-byte read; every lane keeps the B fragments of all K steps.
-// Operand layouts of the instruction (checked on the device): A[m][k] in lane m + 32 (k / 4),
-// element k % 4; B[k][n] in lane n + 32 (k / 4), element k % 4; D[m][n] in lane
-// n + 32 ((m / 4) % 2), element 4 (m / 8) + m % 4.
+// Operand layouts of v_mfma_f32_32x32x8 bf16 (checked on the device): A[m][k] in lane
+// m + 32 (k / 4), element k % 4; B[k][n] in lane n + 32 (k / 4), element k % 4; D[m][n] in
+// lane n + 32 ((m / 4) % 2), element 4 (m / 8) + m % 4.
 typedef short bf4 __attribute__((ext_vector_type(4)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 
-template <int CIN>
-__global__ void __launch_bounds__(kT)
-    conv_fwd_mfma_kernel(ConvDesc d, int n, const float* __restrict__ x,
-                         const uint16_t* __restrict__ wbf, const float* __restrict__ params,
-                         float* __restrict__ y) {
-    static_assert(CIN % 8 == 0, "8 channels per K step");
-    constexpr int kSteps = CIN * 9 / 8;
-    extern __shared__ __align__(16) char smem_raw[];
-    uint16_t* xs = reinterpret_cast<uint16_t*>(smem_raw);  // [hin][win][CIN]
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, half = lane >> 5;
-    const int col = lane & 31;
-    bf4 bfrag[kSteps];
+// The whole net's inference for one cell per workgroup, every layer on the matrix cores, the
+// activations kept in LDS between layers (BF16, channel innermost).  Per layer the product
+// D[p][co] = sum_k A[p][k] B[k][co] over the 256 output pixels (8 tiles of 32 rows; wave w
+// takes tiles w and w + 4, two independent accumulators), k = tap * CIN + ci.  The B
+// fragments come from a table in the instruction's operand order (one 8-byte load per lane
+// and K step, see frag_kernel); the last layer's 4 output channels fill columns 0..3 of the
+// tile (the rest are zero weights) and are pixel-shuffled into the 32x32 output.  The input of
+// every layer is rounded to BF16; products are summed in FP32; bias and ReLU are applied in
+// FP32 before the rounding.
+constexpr int kAStr = 36;  // LDS stride of a pixel's 32 channels (BF16): 72 bytes, so the
+                           // 8-byte reads of 32 consecutive pixels hit 64 distinct banks
+constexpr int kFragSteps = (kNetCin * 9 + (kNetLayers - 1) * kNetCh * 9) / 8;
+
+template <int CIN, int S, int DIL, int HIN, int ISTR, int COUT>
+__device__ __forceinline__ void infer_layer(const uint16_t* __restrict__ in,
+                                            const uint2* __restrict__ frag,
+                                            const float* __restrict__ bias,
+                                            uint16_t* __restrict__ out, float* __restrict__ y,
+                                            int wv, int lane) {
+    constexpr int kGroups = CIN / 8;  // K steps per tap
+    const int half = lane >> 5, col = lane & 31;
+    const int pa = wv * 32 + col, pb = pa + 128;
+    const int oya = pa >> 4, oxa = pa & 15, oyb = pb >> 4, oxb = pb & 15;
+    f32x16 acc0 = {}, acc1 = {};
+#pragma unroll 1
+    for (int tap = 0; tap < 9; ++tap) {
+        const int dy = (tap / 3 - 1) * DIL, dx = (tap % 3 - 1) * DIL;
+        const int iya = oya * S + dy, ixa = oxa * S + dx;
+        const int iyb = oyb * S + dy, ixb = oxb * S + dx;
+        const bool ina = (unsigned)iya < (unsigned)HIN && (unsigned)ixa < (unsigned)HIN;
+        const bool inb = (unsigned)iyb < (unsigned)HIN && (unsigned)ixb < (unsigned)HIN;
+        const uint16_t* ra = in + (ina ? (iya * HIN + ixa) * ISTR : 0) + 4 * half;
+        const uint16_t* rb = in + (inb ? (iyb * HIN + ixb) * ISTR : 0) + 4 * half;
+        const uint2* ft = frag + tap * kGroups * 64 + lane;
+        uint2 w[kGroups];
 #pragma unroll
-    for (int s = 0; s < kSteps; ++s) {
+        for (int g = 0; g < kGroups; ++g) w[g] = ft[g * 64];
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const int k = 8 * s + 4 * half + i, tap = k / CIN, ci = k % CIN;
-            bfrag[s][i] = (short)wbf[d.woff + ((int64_t)col * CIN + ci) * 9 + tap];
+        for (int g = 0; g < kGroups; ++g) {
+            bf4 a0 = {0, 0, 0, 0}, a1 = {0, 0, 0, 0};
+            if (ina) a0 = *reinterpret_cast<const bf4*>(ra + 8 * g);
+            if (inb) a1 = *reinterpret_cast<const bf4*>(rb + 8 * g);
+            bf4 bw;
+            bw[0] = (short)(w[g].x & 0xffffu);
+            bw[1] = (short)(w[g].x >> 16);
+            bw[2] = (short)(w[g].y & 0xffffu);
+            bw[3] = (short)(w[g].y >> 16);
+            acc0 = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(a0, bw, acc0, 0, 0, 0);
+            acc1 = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(a1, bw, acc1, 0, 0, 0);
         }
     }
-    const float bias = params[d.boff + col];
-    const int hw = d.hin * d.win;
+    // row m = 8 (j / 4) + 4 half + j % 4 of the tile: a per-lane base plus a constant offset
+    if (COUT == kNetCh) {
+        const float bv = bias[col];
+        uint16_t* ob = out + (wv * 32 + 4 * half) * kAStr + col;
+#pragma unroll
+        for (int j = 0; j < 16; ++j) {
+            const int mo = 8 * (j / 4) + j % 4;
+            ob[mo * kAStr] = f2bf(fmaxf(acc0[j] + bv, 0.f));
+            ob[(128 + mo) * kAStr] = f2bf(fmaxf(acc1[j] + bv, 0.f));
+        }
+    } else if (col < COUT) {
+        // channel 2 a + c of output pixel p = (oy, ox) -> y[2 oy + a][2 ox + c]; with
+        // p = 32 w + m: oy = 2 w + j / 8, ox = 8 ((j / 4) % 2) + 4 half + j % 4
+        const float bv = bias[col];
+        const int a = col >> 1, c = col & 1;
+        float* yb = y + (4 * wv + a) * kNetWin + 8 * half + c;
+#pragma unroll
+        for (int j = 0; j < 16; ++j) {
+            const int yo = 2 * (j / 8) * kNetWin + 2 * (8 * ((j / 4) % 2) + j % 4);
+            yb[yo] = acc0[j] + bv;
+            yb[16 * kNetWin + yo] = acc1[j] + bv;  // tile w + 4: oy + 8
+        }
+    }
+}
+
+struct InferBias {
+    int64_t boff[kNetLayers];
+};
+
+__global__ void __launch_bounds__(kT) __attribute__((amdgpu_waves_per_eu(4)))
+    net_infer_kernel(int n, const float* __restrict__ x, const uint2* __restrict__ frag,
+                     const float* __restrict__ params, InferBias ib, float* __restrict__ y) {
+    static_assert(kNetWin * kNetWin * kNetCin <= kPix * kAStr, "input fits the second buffer");
+    __shared__ __align__(16) uint16_t buf0[kPix * kAStr];
+    __shared__ __align__(16) uint16_t buf1[kPix * kAStr];  // also the 32x32x8 input
+    constexpr int W2 = kNetWin * kNetWin;
+    constexpr int o2 = kNetCin * 9 / 8, o3 = o2 + kNetCh * 9 / 8, o4 = o3 + kNetCh * 9 / 8,
+                  o5 = o4 + kNetCh * 9 / 8;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     for (int b = blockIdx.x; b < n; b += gridDim.x) {
-        __syncthreads();
-        for (int t = threadIdx.x; t < CIN * hw; t += kT) {
-            const int ci = t / hw, pix = t - ci * hw;
-            xs[pix * CIN + ci] = f2bf(x[(int64_t)b * CIN * hw + t]);
+        const float* xb = x + (int64_t)b * kNetCin * W2;
+        __syncthreads();  // the previous cell's last layer has read buf1
+        for (int pix = threadIdx.x; pix < W2; pix += kT) {
+            uint4 w;
+            w.x = f2bf(xb[0 * W2 + pix]) | ((uint32_t)f2bf(xb[1 * W2 + pix]) << 16);
+            w.y = f2bf(xb[2 * W2 + pix]) | ((uint32_t)f2bf(xb[3 * W2 + pix]) << 16);
+            w.z = f2bf(xb[4 * W2 + pix]) | ((uint32_t)f2bf(xb[5 * W2 + pix]) << 16);
+            w.w = f2bf(xb[6 * W2 + pix]) | ((uint32_t)f2bf(xb[7 * W2 + pix]) << 16);
+            *reinterpret_cast<uint4*>(&buf1[pix * kNetCin]) = w;
         }
         __syncthreads();
-        for (int tile = wv; tile < kPix / 32; tile += kT / 64) {
-            const int p = tile * 32 + col, oy = p / d.wout, ox = p % d.wout;
-            f32x16 acc = {};
-#pragma unroll
-            for (int s = 0; s < kSteps; ++s) {
-                const int k0 = 8 * s + 4 * half, tap = k0 / CIN, ci0 = k0 % CIN;
-                const int iy = oy * d.stride + (tap / 3) * d.dil - d.pad;
-                const int ix = ox * d.stride + (tap % 3) * d.dil - d.pad;
-                bf4 a = {0, 0, 0, 0};
-                if (iy >= 0 && iy < d.hin && ix >= 0 && ix < d.win)
-                    a = *reinterpret_cast<const bf4*>(&xs[(iy * d.win + ix) * CIN + ci0]);
-                acc = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(a, bfrag[s], acc, 0, 0, 0);
-            }
-#pragma unroll
-            for (int j = 0; j < 16; ++j) {
-                const int m = 8 * (j / 4) + 4 * half + (j % 4);
-                float v = acc[j] + bias;
-                if (d.relu) v = fmaxf(v, 0.f);
-                y[((int64_t)b * kNetCh + col) * kPix + tile * 32 + m] = v;
-            }
-        }
+        infer_layer<kNetCin, 2, 1, kNetWin, kNetCin, kNetCh>(buf1, frag, params + ib.boff[0],
+                                                             buf0, nullptr, wv, lane);
+        __syncthreads();
+        infer_layer<kNetCh, 1, 1, 16, kAStr, kNetCh>(buf0, frag + o2 * 64, params + ib.boff[1],
+                                                     buf1, nullptr, wv, lane);
+        __syncthreads();
+        infer_layer<kNetCh, 1, 2, 16, kAStr, kNetCh>(buf1, frag + o3 * 64, params + ib.boff[2],
+                                                     buf0, nullptr, wv, lane);
+        __syncthreads();
+        infer_layer<kNetCh, 1, 4, 16, kAStr, kNetCh>(buf0, frag + o4 * 64, params + ib.boff[3],
+                                                     buf1, nullptr, wv, lane);
+        __syncthreads();
+        infer_layer<kNetCh, 1, 1, 16, kAStr, 4>(buf1, frag + o5 * 64, params + ib.boff[4],
+                                                nullptr, y + (int64_t)b * W2, wv, lane);
     }
+}
+
+// The B-fragment table of net_infer_kernel: entry (step s of layer l, lane L) holds
+// B[k][n] = W[n][ci][tap] for n = L % 32, k = 8 s + 4 (L / 32) + e, e = 0..3 (packed BF16,
+// e in the low half first), k = tap * cin + ci; zero for n >= cout.
+struct FragDesc {
+    int64_t woff[kNetLayers];
+    int cin[kNetLayers], cout[kNetLayers], soff[kNetLayers + 1];
+};
+
+__global__ void frag_kernel(FragDesc fd, const uint16_t* __restrict__ wbf,
+                            uint2* __restrict__ frag) {
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= fd.soff[kNetLayers] * 64) return;
+    const int gs = idx >> 6, lane = idx & 63;
+    int l = 0;
+    while (gs >= fd.soff[l + 1]) ++l;
+    const int s = gs - fd.soff[l], nn = lane & 31, cin = fd.cin[l];
+    uint32_t h[4];
+    for (int e = 0; e < 4; ++e) {
+        const int k = 8 * s + 4 * (lane >> 5) + e, tap = k / cin, ci = k % cin;
+        h[e] = nn < fd.cout[l] ? wbf[fd.woff[l] + ((int64_t)nn * cin + ci) * 9 + tap] : 0u;
+    }
+    frag[idx] = make_uint2(h[0] | (h[1] << 16), h[2] | (h[3] << 16));
 }
 
 // Gradient with respect to the input of a stride-1 layer:
@@ -735,32 +821,32 @@ void launch_fwd(const ConvDesc& d, int n, const float* x, const float* wfwd,
     }
 }
 
-// inference: the 32-channel layers on the matrix cores, the last one as in training
-void launch_infer(const ConvDesc& d, int n, const float* x, const uint16_t* wbf,
-                  const float* wfwd, const float* params, float* y, int shuffle,
-                  hipStream_t st) {
-    if (d.cout != kNetCh || d.hout * d.wout != kPix || (d.cin != kNetCin && d.cin != kNetCh)) {
-        launch_fwd(d, n, x, wfwd, params, y, shuffle, st);
-        return;
-    }
-    const size_t lds = (size_t)d.cin * d.hin * d.win * sizeof(uint16_t);
-    const int g = grid_n(n, 2048);
-    if (d.cin == kNetCin) {
-        lds_attr(conv_fwd_mfma_kernel<kNetCin>, lds);
-        conv_fwd_mfma_kernel<kNetCin><<<g, kT, lds, st>>>(d, n, x, wbf, params, y);
-    } else {
-        lds_attr(conv_fwd_mfma_kernel<kNetCh>, lds);
-        conv_fwd_mfma_kernel<kNetCh><<<g, kT, lds, st>>>(d, n, x, wbf, params, y);
-    }
-}
-
-// refresh the forward kernels' FP32 weights from the BF16 copy
+// refresh the forward kernels' FP32 weights and the inference kernel's fragment table from
+// the BF16 copy
 void widen_weights(dd_net* net, hipStream_t st) {
     const ConvDesc* L = table().L;
+    FragDesc fd;
+    fd.soff[0] = 0;
     for (int l = 0; l < kNetLayers; ++l) {
         const int nw = L[l].cout * L[l].cin * 9;
         widen_kernel<<<(nw + 255) / 256, 256, 0, st>>>(L[l], net->wbf, net->wfwd);
+        fd.woff[l] = L[l].woff;
+        fd.cin[l] = L[l].cin;
+        fd.cout[l] = L[l].cout;
+        fd.soff[l + 1] = fd.soff[l] + L[l].cin * 9 / 8;
     }
+    frag_kernel<<<(kFragSteps * 64 + 255) / 256, 256, 0, st>>>(fd, net->wbf, net->wfrag);
+}
+
+// the layer table is the one net_infer_kernel is written for
+bool infer_shapes_match() {
+    const ConvDesc* L = table().L;
+    const int st[kNetLayers] = {2, 1, 1, 1, 1}, dl[kNetLayers] = {1, 1, 2, 4, 1};
+    for (int l = 0; l < kNetLayers; ++l)
+        if (L[l].stride != st[l] || L[l].dil != dl[l] || L[l].pad != dl[l] ||
+            L[l].hout != 16 || L[l].wout != 16 || L[l].cout != (l + 1 < kNetLayers ? kNetCh : 4))
+            return false;
+    return L[0].cin == kNetCin && L[0].hin == kNetWin;
 }
 
 }  // namespace
@@ -819,17 +905,18 @@ Status net_reserve(dd_net* net, int n) {
 }  // namespace
 
 Status net_infer(dd_net* net, int n, const float* x, float* y, hipStream_t st) {
-    Status s = net_reserve(net, n);
-    if (s.code || n == 0) return s;
+    Status s;
+    if (n == 0) return s;
     const dd::ConvDesc* L = dd::net_layers();
-    const size_t per = (size_t)dd::kNetCh * dd::kPix * n;
-    const float* in = x;
-    for (int l = 0; l < dd::kNetLayers; ++l) {
-        const bool last = l == dd::kNetLayers - 1;
-        float* o = last ? y : net->act + (l % 2) * per;
-        dd::launch_infer(L[l], n, in, net->wbf, net->wfwd, net->master, o, last ? 1 : 0, st);
-        in = o;
+    if (!dd::infer_shapes_match()) {
+        s.code = DD_EINVAL;
+        s.msg = "net_infer: layer table differs from the inference kernel";
+        return s;
     }
+    dd::InferBias ib;
+    for (int l = 0; l < dd::kNetLayers; ++l) ib.boff[l] = L[l].boff;
+    dd::net_infer_kernel<<<dd::grid_n(n, 4096), dd::kT, 0, st>>>(n, x, net->wfrag, net->master,
+                                                                 ib, y);
     DD_HIP(hipGetLastError(), s);
     return s;
 }
@@ -940,7 +1027,8 @@ extern "C" dd_status dd_net_create(const float* params, dd_net** out) {
         hipMalloc(&net->adam_v, np * sizeof(float)) != hipSuccess ||
         hipMalloc(&net->grad, np * sizeof(float)) != hipSuccess ||
         hipMalloc(&net->wbf, np * sizeof(uint16_t)) != hipSuccess ||
-        hipMalloc(&net->wfwd, np * sizeof(float)) != hipSuccess) {
+        hipMalloc(&net->wfwd, np * sizeof(float)) != hipSuccess ||
+        hipMalloc(&net->wfrag, (size_t)dd::kFragSteps * 64 * sizeof(uint2)) != hipSuccess) {
         s.code = DD_ENOMEM;
         s.msg = "dd_net_create: device allocation failed";
         return bail(s);
@@ -1013,7 +1101,7 @@ extern "C" void dd_net_free(dd_net* net) {
     if (!net) return;
     (void)hipDeviceSynchronize();
     for (void* p : {(void*)net->master, (void*)net->adam_m, (void*)net->adam_v, (void*)net->grad,
-                    (void*)net->wbf, (void*)net->wfwd, (void*)net->part, (void*)net->act, (void*)net->ga,
+                    (void*)net->wbf, (void*)net->wfwd, (void*)net->wfrag, (void*)net->part, (void*)net->act, (void*)net->ga,
                     (void*)net->out, (void*)net->loss_b})
         if (p) (void)hipFree(p);
     delete net;

@@ -72,6 +72,8 @@ struct dd_net {
     uint16_t* wbf = nullptr;  // BF16 copy used by the kernels (weights; biases stay FP32)
     float* wfwd = nullptr;    // the BF16 weights widened to FP32, [ci][tap][co] per layer,
                               // for the forward kernels (read as wave-uniform loads)
+    uint2* wfrag = nullptr;   // the BF16 weights in the matrix-core operand order of the
+                              // inference kernel (B fragments per layer, K step and lane)
     float* part = nullptr;    // weight-gradient partials [blocks][layer params]
     size_t part_cap = 0;
     float* act = nullptr;     // activations of the last forward (training) [4][n][32][256]

@@ -46,14 +46,13 @@ def _ref_forward(params, x):
 
 
 def _ref_infer(params, x):
-    """The same net as dd_net_infer computes it: the input of each 32-channel layer rounded to
-    BF16 (round to nearest even), products summed in FP32."""
+    """The same net as dd_net_infer computes it: the input of every layer rounded to BF16
+    (round to nearest even), products summed in FP32."""
     F = torch.nn.functional
     h = x
     for l, ((w, b), (_, cout, stride, dil)) in enumerate(zip(_unpack(params), LAYERS)):
         wb = w.to(torch.bfloat16).to(torch.float32)
-        if cout == 32:
-            h = h.to(torch.bfloat16).to(torch.float32)
+        h = h.to(torch.bfloat16).to(torch.float32)
         h = F.conv2d(h, wb, b, stride=stride, padding=dil, dilation=dil)
         if l < len(LAYERS) - 1:
             h = torch.relu(h)
@@ -104,7 +103,7 @@ def test_forward_matches_torch(n):
     net.close()
 
 
-@pytest.mark.parametrize("n", [1, 7, 300])
+@pytest.mark.parametrize("n", [1, 7, 300, 4100])
 def test_infer_on_matrix_cores_matches_torch(n):
     import paper_2405_09400_amd as dd
     _need_gpu()
@@ -114,10 +113,18 @@ def test_infer_on_matrix_cores_matches_torch(n):
     net = dd.WarmStartNet(p)
     y = net.infer(torch.from_numpy(x).cuda()).cpu()
     ref = _ref_infer(torch.from_numpy(p), torch.from_numpy(x))
-    err = (y - ref).abs().max().item()
-    # FP32 sums in another order than the CPU's, and an occasional input rounded the other way
-    # where the two sides' FP32 activations straddle a BF16 rounding boundary
-    assert err <= 2e-3 * ref.abs().max().item(), err
+    scale = ref.abs().max().item()
+    err = (y - ref).abs().amax(dim=(1, 2))  # per sample
+    print(f"per-sample max error / output scale: median {err.median().item() / scale:.2e}, "
+          f"max {err.max().item() / scale:.2e}", flush=True)
+    # FP32 sums in another order than the CPU's, and now and then an input rounded the other
+    # way where the two sides' FP32 activations straddle a BF16 rounding boundary (one such
+    # flip moves an activation by 2^-9 of itself); the samples of a workgroup's later passes
+    # (n > 4096) are held to the same bound
+    assert err.max().item() <= 5e-3 * scale, err.max().item()
+    assert torch.quantile(err, 0.99).item() <= 2e-3 * scale
+    if n > 4096:
+        assert err[4096:].max().item() <= 5e-3 * scale
     # and against the FP32 forward: the BF16 inputs move the output by well under 1%
     y32 = net.forward(torch.from_numpy(x).cuda()).cpu()
     assert (y - y32).abs().max().item() <= 2e-2 * y32.abs().max().item()
