@@ -340,12 +340,29 @@ def cpu_baseline(args, w, ctx, k, rule):
 # source has changed since, traffic is null.
 
 KERNEL_SOURCE = os.path.join(ROOT, "paper_2405_09400_amd", "csrc", "fastcell.hip")
-def traffic_summary_path(workload):
-    return os.path.join(ROOT, "profiles", f"fast_kernel_{workload}_traffic.md")
+DEFAULT_CLASSES = (32, 2048)
 
 
-def trace_summary_path(workload):
-    return os.path.join(ROOT, "profiles", f"fast_kernel_{workload}.md")
+def _classes_suffix(classes):
+    """'' for the library's default cell classes, '_c<side>_<entries>' for another pair."""
+    return "" if tuple(classes) == DEFAULT_CLASSES else f"_c{classes[0]}_{classes[1]}"
+
+
+def traffic_summary_path(workload, classes=DEFAULT_CLASSES):
+    return os.path.join(ROOT, "profiles",
+                        f"fast_kernel_{workload}{_classes_suffix(classes)}_traffic.md")
+
+
+def trace_summary_path(workload, classes=DEFAULT_CLASSES):
+    return os.path.join(ROOT, "profiles", f"fast_kernel_{workload}{_classes_suffix(classes)}.md")
+
+
+def summary_classes(args):
+    """The cell classes a profile summary is written for (--classes, else the default)."""
+    if not args.classes:
+        return DEFAULT_CLASSES
+    ws, be = (int(v) for v in args.classes.split(","))
+    return (ws, be)
 
 
 WORKLOAD_TITLE = {"ms512": "ms512 (512² coarse to fine, s = 4, timed at κ = 1, tol 1e-5, batch rule)",
@@ -402,19 +419,22 @@ def traffic_summary(args):
     ff = ref_kib / (sum(f_copy) / len(f_copy))
     wf = ref_kib / (sum(w_copy) / len(w_copy))
     f_rows, w_rows = _pmc_rows(fb), _pmc_rows(wb)
+    cls = summary_classes(args)
     cmd_b = ("rocprofv3 --pmc {c} --kernel-trace -d <out> -o run --output-format csv -- "
              f"python3 bench.py --workload {args.workload} --steps 3 --warmup 1 --no-compare "
-             "--no-cpu-baseline --no-extra --classes 32,2048")
+             f"--no-cpu-baseline --no-extra --classes {cls[0]},{cls[1]}")
     cmd_c = ("rocprofv3 --pmc {c} --kernel-trace -d <out> -o run --output-format csv -- "
              "python3 bench.py --copy-calibration")
     kinds = " ".join(f"'{k}'" for k in args.traffic_kernel)
-    lines = [f"# HBM traffic of the register-blocked kernels, {WORKLOAD_TITLE[args.workload]}", "",
+    lines = [f"# HBM traffic of the register-blocked kernels, {WORKLOAD_TITLE[args.workload]}, "
+             f"cell classes {cls[0]},{cls[1]}", "",
              "Commands (from the repository root on the MI355X machine, after `cd /tmp && export "
              "TMPDIR=/tmp`; one counter per run):", "", "```",
              cmd_b.format(c="FETCH_SIZE"), cmd_b.format(c="WRITE_SIZE"),
              cmd_c.format(c="FETCH_SIZE"), cmd_c.format(c="WRITE_SIZE"), "```", "",
-             f"Summarised by `python bench.py --workload {args.workload} --traffic-from <four output "
-             f"dirs> --traffic-kernel {kinds} --traffic-last {last}`.", "",
+             f"Summarised by `python bench.py --workload {args.workload} --classes {cls[0]},{cls[1]} "
+             f"--traffic-from <four output dirs> --traffic-kernel {kinds} --traffic-last {last}`.",
+             "",
              f"Copy of 256 MiB: FETCH_SIZE reads {sum(f_copy) / len(f_copy):.0f} KiB (scale "
              f"{ff:.3f}), WRITE_SIZE {sum(w_copy) / len(w_copy):.0f} KiB (scale {wf:.3f}).", "",
              "| kernel | FETCH_SIZE KiB per dispatch | WRITE_SIZE KiB per dispatch | HBM bytes per "
@@ -424,7 +444,7 @@ def traffic_summary(args):
         fk = _per_dispatch(f_rows, kern)[-last:]
         wk = _per_dispatch(w_rows, kern)[-last:]
         fkib, wkib = sum(fk) / len(fk), sum(wk) / len(wk)
-        rec = {"kernel": kern, "source_sha256": source_sha256(), "classes": [32, 2048],
+        rec = {"kernel": kern, "source_sha256": source_sha256(), "classes": list(cls),
                "dispatches": len(fk),
                "fetch_kib_per_dispatch": fkib, "write_kib_per_dispatch": wkib,
                "fetch_factor": ff, "write_factor": wf,
@@ -434,7 +454,7 @@ def traffic_summary(args):
     lines += ["", f"Averaged over the last {last} dispatches of each kernel (the launches of the "
               "timed steps, the ones after the stop, which exit at once, included).", ""]
     lines += ["traffic-json: " + json.dumps(r) for r in recs]
-    with open(args.traffic_out or traffic_summary_path(args.workload), "w") as f:
+    with open(args.traffic_out or traffic_summary_path(args.workload, cls), "w") as f:
         f.write("\n".join(lines) + "\n")
     print("\n".join(lines))
 
@@ -451,14 +471,18 @@ def trace_summary(args):
     trace = list(csv.DictReader(open(glob.glob(os.path.join(d, "**", "*kernel_trace.csv"),
                                                recursive=True)[0])))
     tot = sum(float(r["TotalDurationNs"]) for r in stats)
+    cls = summary_classes(args)
     cmd = ("rocprofv3 --kernel-trace --stats -d <out> -o run --output-format csv -- "
            f"python3 bench.py --workload {args.workload} --steps 3 --warmup 1 --no-compare "
-           "--no-cpu-baseline --no-extra --classes 32,2048")
-    lines = [f"# Cell Sinkhorn kernels, {WORKLOAD_TITLE[args.workload]}", "",
+           f"--no-cpu-baseline --no-extra --classes {cls[0]},{cls[1]}")
+    lines = [f"# Cell Sinkhorn kernels, {WORKLOAD_TITLE[args.workload]}, cell classes "
+             f"{cls[0]},{cls[1]}", "",
              "Command (from the repository root on the MI355X machine, after `cd /tmp && export "
              "TMPDIR=/tmp`):", "", "```", cmd, "```", "",
-             f"Summarised by `python bench.py --workload {args.workload} --trace-from <out> "
-             f"--traffic-last {args.traffic_last}`.  Kernel source SHA-256 (fastcell.hip): "
+             f"Summarised by `python bench.py --workload {args.workload} --classes "
+             f"{cls[0]},{cls[1]} --trace-from <out> --trace-json <its JSON line> --traffic-last "
+             f"{args.traffic_last}`.  Kernel "
+             f"source SHA-256 (fastcell.hip): "
              f"`{source_sha256()}`.", "",
              "Device: one MI355X (gfx950).  Per-kernel totals over the whole run (set-up "
              "stages included):", "",
@@ -478,7 +502,13 @@ def trace_summary(args):
                       f"launches after the stop, which exit at once, included): average "
                       f"{sum(durs) / len(durs):.1f} us, min {min(durs):.1f} us, max "
                       f"{max(durs):.1f} us."]
-    with open(args.trace_out or trace_summary_path(args.workload), "w") as f:
+    if args.trace_json:
+        with open(args.trace_json) as f:
+            r = json.load(f)["roofline"]
+        lines += ["", f"The JSON line of the same run: dominant kernel `{r['kernel']}`, "
+                  f"{r['launches']} launches in the timed steps, "
+                  f"{1e3 * r['kernel_ms_per_launch']:.1f} us per launch on its HIP events."]
+    with open(args.trace_out or trace_summary_path(args.workload, cls), "w") as f:
         f.write("\n".join(lines) + "\n")
     print("\n".join(lines))
 
@@ -487,8 +517,8 @@ def traffic_bytes(kernel_name, workload, classes):
     """HBM bytes per launch of `kernel_name` from the committed summary of the workload, or
     None when there is none, it covers another kernel or other cell classes, or the kernel's
     source has changed since."""
-    path = traffic_summary_path(workload)
-    if not os.path.exists(path):
+    path = traffic_summary_path(workload, tuple(classes[0])) if len(classes) == 1 else None
+    if not path or not os.path.exists(path):
         return None
     for line in open(path):
         if line.startswith("traffic-json: "):
@@ -546,6 +576,9 @@ def main():
     ap.add_argument("--trace-from", metavar="DIR",
                     help="write the kernel-time summary of a rocprofv3 kernel-trace run")
     ap.add_argument("--trace-out", default=None)
+    ap.add_argument("--trace-json", default=None,
+                    help="with --trace-from: the JSON line the profiled run printed, whose "
+                         "per-launch time of the dominant kernel is quoted beside the trace's")
     args = ap.parse_args()
     if args.traffic_from:
         traffic_summary(args)
