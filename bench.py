@@ -553,6 +553,8 @@ def main():
     ap.add_argument("--flow-eps-gamma", type=float, default=None,
                     help="flow workload: glued edge candidates at this eps_gamma (units of h^2); "
                          "default: product candidates")
+    ap.add_argument("--no-flow", action="store_true",
+                    help="skip the flow workload record (hybrid A, B, flow schedule at 512^2)")
     ap.add_argument("--no-clusters", action="store_true",
                     help="skip the clustering study (time against K-means clusters at 1024^2)")
     ap.add_argument("--classes", default=None, metavar="WS,BE",
@@ -627,6 +629,8 @@ def main():
         line["size1024"] = rec
         if not args.no_clusters:
             line["clusters"] = clusters_record(args, larger[args.workload])
+        if not args.no_flow:
+            line["flow"] = flow_record(args)
         if args.workload.startswith("ms"):
             # the whole multiscale solve at the paper's arithmetic and stopping tolerance, and
             # the global Sinkhorn on the same problem
@@ -638,6 +642,20 @@ def main():
                 g["dual_rel_diff_vs_dd_primal"] = abs(g["dual"] - fs["primal"]) / abs(fs["primal"])
                 line["global"] = g
     print(json.dumps(line), flush=True)
+
+
+def flow_record(args, steps=6, warmup=2):
+    """The flow workload (Sec. 5.1: 512^2, s = 2, 65,536 basic cells, nu = a rotated, contracted,
+    shifted mu, map start, eps = h^2) on the hybrid schedule A, B, flow update: the warm-up's
+    A, B and first flow update (its min-cost flow from scratch), then `steps` half-iterations
+    with a flow update after every B (each from the previous optimal basis)."""
+    sub = measure(args, "flow512", args.prec, steps, warmup, replay=0, cpu=False)
+    rec = {key: sub[key] for key in ("value", "unit", "ms_per_step", "ms_per_step_median", "dtype")}
+    rec["config"] = sub["config"]
+    rec["detail"] = {key: sub["detail"][key] for key in
+                     ("step_ms", "sinkhorn_iters", "sinkhorn_ms_per_step", "flow", "primal",
+                      "x_marginal_l1", "y_marginal_l1")}
+    return rec
 
 
 def clusters_record(args, workload, ks=(1, 2, 4, 8), steps=4):
@@ -769,7 +787,8 @@ def measure(args, workload, prec, steps, warmup, replay=0, cpu=False):
     import paper_2405_09400_amd as dd
     w, ctx, rule, k = setup(args, workload, prec)
     log(f"[bench] warmup {warmup} steps")
-    run_steps(ctx, w, warmup, k, args, rule)
+    warm_flows = []
+    run_steps(ctx, w, warmup, k, args, rule, flows=warm_flows)
     k += warmup
     torch.cuda.synchronize()
     log(f"[bench] timing {steps} steps ({workload}, {prec})")
@@ -903,8 +922,15 @@ def measure(args, workload, prec, steps, warmup, replay=0, cpu=False):
             "updates": len(flows), "nodes": flows[0]["n_nodes"], "arcs": flows[0]["n_arcs"],
             "costs_ms": sum(f["t_costs_ms"] for f in flows) / len(flows),
             "mcf_ms": sum(f["t_mcf_ms"] for f in flows) / len(flows),
+            "mcf_ms_each": [round(f["t_mcf_ms"], 2) for f in flows],
             "assemble_ms": sum(f["t_assemble_ms"] for f in flows) / len(flows),
             "value": [f["value"] for f in flows], "moved_mass": [f["moved_mass"] for f in flows],
+            # the first update of the run (in the warm-up) solves its min-cost flow from scratch;
+            # later ones start from the previous optimal basis
+            "first_update_mcf_ms": warm_flows[0]["t_mcf_ms"] if warm_flows else None,
+            # one cycle of the hybrid schedule: A, B, flow update
+            "cycle_ms": wall * 1e3 / len(flows),
+            "mcf_share_of_cycle": (sum(f["t_mcf_ms"] for f in flows) / (wall * 1e3)),
         }
     ctx.close()
     return out
