@@ -553,6 +553,9 @@ def main():
     ap.add_argument("--flow-eps-gamma", type=float, default=None,
                     help="flow workload: glued edge candidates at this eps_gamma (units of h^2); "
                          "default: product candidates")
+    ap.add_argument("--paper-table", action="store_true",
+                    help="only run the whole float64 multiscale solve at 64^2 ... 1024^2 "
+                         "(Table 1's DomDecGPU setting) and print one JSON line")
     ap.add_argument("--no-flow", action="store_true",
                     help="skip the flow workload record (hybrid A, B, flow schedule at 512^2)")
     ap.add_argument("--no-clusters", action="store_true",
@@ -601,6 +604,9 @@ def main():
     if args.copy_calibration:
         copy_calibration()
         return
+    if args.paper_table:
+        paper_table(args)
+        return
     dd.lib()
     if args.classes:
         ws, be = (int(x) for x in args.classes.split(","))
@@ -635,6 +641,8 @@ def main():
             # the whole multiscale solve at the paper's arithmetic and stopping tolerance, and
             # the global Sinkhorn on the same problem
             line["full_solve"] = full_solve(args, args.workload, "f64", 1e-4)
+            # the megapixel solve (Table 1's 1024^2 column)
+            line["full_solve_1024"] = full_solve(args, larger[args.workload], "f64", 1e-4)
             if not args.no_global:
                 g = global_record(args, args.workload)
                 fs = line["full_solve"]
@@ -692,7 +700,7 @@ def clusters_record(args, workload, ks=(1, 2, 4, 8), steps=4):
             "heuristic_clusters": max(1, w.N // 256), "runs": out}
 
 
-def full_solve(args, workload, prec_name, tol):
+def full_solve(args, workload, prec_name, tol, N=None, seed=None):
     """The whole multiscale solve, timed end to end: set-up, every layer's eps stages and
     refinements, and on the finest layer eps = 2h^2, h^2, h^2/2, h^2/4 (the paper's schedule,
     App. A.2.1), each stage `layer_iters` half-iterations; then the relative primal-dual gap
@@ -701,7 +709,7 @@ def full_solve(args, workload, prec_name, tol):
 
     import paper_2405_09400_amd as dd
     import synth
-    w = synth.workload(workload, seed=args.seed)
+    w = synth.workload(workload, seed=args.seed if seed is None else seed, N=N)
     L = w.extra["levels"]
     prec = dd.DD_PREC_F32 if prec_name == "f32" else dd.DD_PREC_F64
     rule = dd.DD_STOP_BATCH
@@ -727,7 +735,8 @@ def full_solve(args, workload, prec_name, tol):
     ctx.close()
     log(f"[bench] full multiscale solve {workload} {prec_name} tol {tol}: {wall:.2f} s, relative "
         f"PD gap {ev['pd_gap'] / ev['primal']:.3e}")
-    return {"workload": workload, "dtype": prec_name, "tol": tol, "wall_s": wall,
+    return {"workload": workload, "grid": w.N, "seed": w.seed, "dtype": prec_name, "tol": tol,
+            "wall_s": wall,
             "sinkhorn_s": sk_ms / 1e3, "bbox_and_balance_s": box_ms / 1e3, "half_iterations": k,
             "sinkhorn_iterations": its, "layers": [w.N >> (L - l) for l in range(L + 1)],
             "relative_pd_gap": ev["pd_gap"] / ev["primal"], "primal": ev["primal"],
@@ -735,6 +744,27 @@ def full_solve(args, workload, prec_name, tol):
             "y_marginal_l1": ev["y_marginal_l1"],
             "schedule": "eps = 2h^2, h^2, h^2/2 per layer, finest 2h^2, h^2, h^2/2, h^2/4, "
                         f"{w.extra['layer_iters']} half-iterations per stage"}
+
+
+def paper_table(args, sizes=(64, 128, 256, 512, 1024), seeds=3):
+    """The whole multiscale solve in float64 at tolerance 1e-4 (Table 1's DomDecGPU setting:
+    s = 4, eps down to h^2/4 on the finest layer) at every grid size, `seeds` seeded mixture
+    pairs per size (one at 1024^2); one JSON line."""
+    rows = []
+    for N in sizes:
+        name = {512: "ms512", 1024: "ms1024"}.get(N, "ms256")
+        recs = [full_solve(args, name, "f64", 1e-4, N=N, seed=sd)
+                for sd in range(seeds if N < 1024 else 1)]
+        rows.append({"grid": N, "seeds": [r["seed"] for r in recs],
+                     "wall_s": [r["wall_s"] for r in recs],
+                     "sinkhorn_s": [r["sinkhorn_s"] for r in recs],
+                     "bbox_and_balance_s": [r["bbox_and_balance_s"] for r in recs],
+                     "relative_pd_gap": [r["relative_pd_gap"] for r in recs],
+                     "x_marginal_l1": [r["x_marginal_l1"] for r in recs],
+                     "y_marginal_l1": [r["y_marginal_l1"] for r in recs]})
+    print(json.dumps({"paper_table": rows, "dtype": "f64", "tol": 1e-4,
+                      "data": "synthetic seeded Gaussian mixtures (8 blobs, 16 at 1024^2)"}),
+          flush=True)
 
 
 def global_record(args, workload):
