@@ -918,9 +918,11 @@ def measure(args, workload, prec, steps, warmup, replay=0, cpu=False):
                                      for s in stats}),
                   "candidates": [[32, 2048], [32, 1024], [32, 4096], [24, 2048], [24, 1024],
                                  [24, 4096]],
-                  "host_waits_per_half_iteration": "4 typical: composite sizes, device stop "
-                                                   "flag of the float32 rounds, float64 "
-                                                   "finish stop flag, end of iteration"},
+                  # host waits for the device per timed half-iteration (1: the composite
+                  # boxes predicted by the previous iteration and the whole solve enqueued;
+                  # more when the enqueued rounds were not enough and the solve was resumed)
+                  "host_waits": [s["host_waits"] for s in stats],
+                  "resumed": [s["spec_resumed"] for s in stats]},
         "time_to_tol": compare,
         "detail": {
             "step_ms": [round(t, 3) for t in step_ms],

@@ -334,9 +334,15 @@ typedef struct {
     double t_init_ms;         /* X-potential start (warm start, or the net's features,
                                  inference and X-update) before the Sinkhorn solve     */
     int32_t batches;          /* composite-cell batches solved one after another       */
-    int32_t reserved3;
+    int32_t host_waits;       /* times the host waited for the device during the call:
+                                 1 in the steady state of one batch (the iteration's
+                                 composite boxes come from the previous iteration, and
+                                 the solve is enqueued whole; its end is the one wait)  */
     int64_t peak_comp_entries;/* composite Y-box entries of the largest batch: the size
                                  of the composite work arrays (7 doubles per entry)    */
+    int32_t spec_resumed;     /* 1 when the solve enqueued whole was not enough and was
+                                 continued after the wait (the same result either way) */
+    int32_t reserved4;
 } dd_iter_stats;
 
 /*

@@ -113,8 +113,9 @@ class IterStats(ctypes.Structure):
                 ("comp_entries", ctypes.c_int64), ("t_b2c_ms", ctypes.c_double),
                 ("t_sinkhorn_ms", ctypes.c_double), ("t_c2b_ms", ctypes.c_double),
                 ("t_total_ms", ctypes.c_double), ("t_init_ms", ctypes.c_double),
-                ("batches", ctypes.c_int32), ("reserved3", ctypes.c_int32),
-                ("peak_comp_entries", ctypes.c_int64)]
+                ("batches", ctypes.c_int32), ("host_waits", ctypes.c_int32),
+                ("peak_comp_entries", ctypes.c_int64), ("spec_resumed", ctypes.c_int32),
+                ("reserved4", ctypes.c_int32)]
 
 
 class FlowStats(ctypes.Structure):

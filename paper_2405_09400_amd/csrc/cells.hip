@@ -56,6 +56,28 @@ __global__ void comp_boxes_kernel(int ncell, const int32_t* __restrict__ members
     size[J] = (int64_t)W1 * W2;
 }
 
+__global__ void comp_dims_kernel(int ncell, const int32_t* __restrict__ members,
+                                 const int32_t* __restrict__ box, int32_t* dims) {
+    const int J = blockIdx.x * blockDim.x + threadIdx.x;
+    if (J >= ncell) return;
+    int lo1 = 0x7fffffff, lo2 = 0x7fffffff, hi1 = -0x7fffffff, hi2 = -0x7fffffff;
+    for (int k = 0; k < 4; ++k) {
+        const int i = members[4 * J + k];
+        if (i < 0) continue;
+        lo1 = min(lo1, box[4 * i]);
+        lo2 = min(lo2, box[4 * i + 1]);
+        hi1 = max(hi1, box[4 * i] + box[4 * i + 2]);
+        hi2 = max(hi2, box[4 * i + 1] + box[4 * i + 3]);
+    }
+    dims[2 * J] = hi1 - lo1;
+    dims[2 * J + 1] = hi2 - lo2;
+}
+
+__global__ void dims_check_kernel(int n, const int32_t* a, const int32_t* b, int32_t* flag) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < n && a[k] != b[k]) flag[0] = 1;
+}
+
 __global__ void comp_max_kernel(int ncell, const int32_t* dims, int32_t* info) {
     __shared__ int s1[kT / 64], s2[kT / 64];
     int m1 = 0, m2 = 0;
@@ -538,6 +560,15 @@ void launch_comp_boxes(const PartDev& P, const BoxSet& S, int xside, CompDev& C,
     const int nb = (P.ncell + 255) / 256;
     comp_boxes_kernel<<<std::max(nb, 1), 256, 0, st>>>(P.ncell, P.members, P.xorig, S.box, xside,
                                                       C.dims, C.orig, C.shift, C.gofs, C.size);
+}
+
+void launch_comp_dims(const PartDev& P, const int32_t* box, int32_t* dims, hipStream_t st) {
+    if (P.ncell > 0)
+        comp_dims_kernel<<<(P.ncell + 255) / 256, 256, 0, st>>>(P.ncell, P.members, box, dims);
+}
+
+void launch_dims_check(int n, const int32_t* a, const int32_t* b, int32_t* flag, hipStream_t st) {
+    if (n > 0) dims_check_kernel<<<(n + 255) / 256, 256, 0, st>>>(n, a, b, flag);
 }
 
 void launch_scan(const int64_t* in, int64_t* out, int n, hipStream_t st) {

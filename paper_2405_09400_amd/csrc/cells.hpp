@@ -35,6 +35,11 @@ void launch_fill_i32(int32_t* p, int n, int32_t v, hipStream_t st);
 void launch_comp_boxes(const PartDev& P, const BoxSet& S, int xside, CompDev& C, hipStream_t st);
 void launch_scan(const int64_t* in, int64_t* out, int n, hipStream_t st);
 void launch_comp_max(const CompDev& C, int ncell, hipStream_t st);
+// dims[J] = (W1, W2) of every composite cell of P over the basic boxes `box`, as
+// launch_comp_boxes computes them
+void launch_comp_dims(const PartDev& P, const int32_t* box, int32_t* dims, hipStream_t st);
+// flag[0] = 1 where a[k] != b[k] for some k < n (flag is not cleared)
+void launch_dims_check(int n, const int32_t* a, const int32_t* b, int32_t* flag, hipStream_t st);
 
 void launch_b2c(const PartDev& P, const BoxSet& S, const CompDev& C, double* nuJ, double* lognu,
                 hipStream_t st);

@@ -120,6 +120,13 @@ void dd_ctx_release(dd_ctx* c) {
     F(c->d_cell_out);
     F(c->d_basic_out);
     F(c->d_eval);
+    for (int q = 0; q < 2; ++q) {
+        F(c->d_pred[q]);
+        if (c->h_pred[q]) (void)hipHostFree(c->h_pred[q]);
+        c->h_pred[q] = nullptr;
+    }
+    F(c->d_pcheck);
+    dd_forget_pred(c);
     for (int32_t** q : {&c->bt.C.dims, &c->bt.C.orig, &c->bt.C.shift, &c->bt.C.gofs, &c->bt.C.info,
                         &c->bt.idx, &c->bt.members, &c->bt.xorig, &c->bt.gst, &c->bt.list})
         F(*q);
@@ -444,6 +451,7 @@ extern "C" dd_status domdec_init(const dd_params* prm, const double* mu, const d
 
 extern "C" dd_status domdec_refine(dd_ctx* c) {
     if (!c) return fail(c, DD_EINVAL, "domdec_refine: null context");
+    dd_forget_pred(c);
     if (c->layer >= c->levels)
         return fail(c, DD_ESTATE, "domdec_refine: already on the finest layer");
     if (!c->visited[0] || !c->visited[1])
@@ -527,25 +535,54 @@ static dd_status iterate_impl(dd_ctx* c, int p, double eps, const dd_sinkhorn_op
     PartDev& P = c->part[p];
     const int nc = P.ncell;
     const double kappa = eps / (c->h * c->h);
+    // the composite dims predicted by the last iteration (consumed here; the end of this one
+    // predicts them again)
+    const bool use_pred = c->pred_ok[p] && c->h_pred[p] && c->d_pred[p];
+    dd_forget_pred(c);
+    const int64_t waits0 = c->skw.waits;
+    int waits = 0;  // the waits here (the solver counts its own)
+    bool resumed = false;
+    if (!c->h_small && hipHostMalloc((void**)&c->h_small, 8 * sizeof(int64_t)) != hipSuccess)
+        return fail(c, DD_ENOMEM, "domdec_iterate: pinned host buffer");
+    for (int q = 0; q < 2; ++q) {
+        const size_t n2 = 2 * (size_t)std::max(c->part[q].ncell, 1);
+        if (!c->d_pred[q] && alloc(c->mem, c->d_pred[q], n2, st).code) return fail(c, st);
+        if (!c->h_pred[q] && hipHostMalloc((void**)&c->h_pred[q], n2 * sizeof(int32_t)) != hipSuccess)
+            return fail(c, DD_ENOMEM, "domdec_iterate: pinned host buffer");
+    }
+    if (!c->d_pcheck && alloc(c->mem, c->d_pcheck, 1, st).code) return fail(c, st);
     (void)hipEventRecord(c->ev[0], hs);
     launch_comp_boxes(P, c->S, c->AS, c->C, hs);
     launch_scan(c->C.size, c->C.base, nc, hs);
     launch_comp_max(c->C, nc, hs);
-    // the one read-back before the solve: the composite sizes and box dims (which the solver
-    // plans its launches from)
-    int32_t info[2];
+    launch_fill_i32(c->d_pcheck, 1, 0, hs);
+    int mw1 = 1, mw2 = 1;
     int64_t total = 0;
     c->h_dims.resize(2 * (size_t)nc);
-    if (!c->h_small && hipHostMalloc((void**)&c->h_small, 8 * sizeof(int64_t)) != hipSuccess)
-        return fail(c, DD_ENOMEM, "domdec_iterate: pinned host buffer");
-    if (hipMemcpyAsync(info, c->C.info, sizeof info, hipMemcpyDeviceToHost, hs) != hipSuccess ||
-        hipMemcpyAsync(&total, c->C.base + nc, sizeof total, hipMemcpyDeviceToHost, hs) !=
-            hipSuccess ||
-        hipMemcpyAsync(c->h_dims.data(), c->C.dims, c->h_dims.size() * 4, hipMemcpyDeviceToHost,
-                       hs) != hipSuccess ||
-        hipStreamSynchronize(hs) != hipSuccess)
-        return fail(c, DD_EDEVICE, "domdec_iterate: reading composite sizes failed");
-    const int mw1 = info[0], mw2 = info[1];
+    if (use_pred) {
+        // no wait: the dims come from the prediction, which the device checks against the
+        // boxes it has just computed
+        std::copy(c->h_pred[p], c->h_pred[p] + 2 * (size_t)nc, c->h_dims.begin());
+        for (int J = 0; J < nc; ++J) {
+            mw1 = std::max(mw1, c->h_dims[2 * J]);
+            mw2 = std::max(mw2, c->h_dims[2 * J + 1]);
+            total += (int64_t)c->h_dims[2 * J] * c->h_dims[2 * J + 1];
+        }
+        launch_dims_check(2 * nc, c->C.dims, c->d_pred[p], c->d_pcheck, hs);
+    } else {
+        // the composite sizes and box dims (which the solver plans its launches from)
+        int32_t info[2];
+        if (hipMemcpyAsync(info, c->C.info, sizeof info, hipMemcpyDeviceToHost, hs) != hipSuccess ||
+            hipMemcpyAsync(&total, c->C.base + nc, sizeof total, hipMemcpyDeviceToHost, hs) !=
+                hipSuccess ||
+            hipMemcpyAsync(c->h_dims.data(), c->C.dims, c->h_dims.size() * 4,
+                           hipMemcpyDeviceToHost, hs) != hipSuccess ||
+            hipStreamSynchronize(hs) != hipSuccess)
+            return fail(c, DD_EDEVICE, "domdec_iterate: reading composite sizes failed");
+        ++waits;
+        mw1 = info[0];
+        mw2 = info[1];
+    }
     // the new state's entries are at most four times the composite entries (each basic cell's
     // truncated box lies in its composite cell's box), so its buffer is sized here and the
     // truncated sizes are read only at the end
@@ -601,33 +638,64 @@ static dd_status iterate_impl(dd_ctx* c, int p, double eps, const dd_sinkhorn_op
     B.max_w2 = mw2;
     B.prec = c->prec;
     dd_batch_stats bs{};
+    // the solve is enqueued whole where it can be (speculative rounds, sk_solve), so that the
+    // one wait of the iteration is the one at its end
     const Status ss = sk_solve(B, o, hs, c->skw, &bs, c->d_iters, c->d_cerr, c->h_dims.data(),
-                               /*defer=*/true);
+                               /*defer=*/true, /*spec=*/true);
     if (ss.code) return fail(c, ss);
+    // CompositeToBasic, balance, truncate and compact into S2; then the next iteration's
+    // composite dims of both partitions from S2; then the one wait: the new state's size, the
+    // untruncated cells, the prediction check, the solve's statistics
+    auto tail = [&]() -> bool {
+        ++waits;
+        (void)hipEventRecord(c->ev[2], hs);
+        launch_c2b(P, c->C, c->AS, c->s, mw2, apot, logmu, c->d_nuJ, kappa, c->h, c->d_tmp,
+                   c->d_py2, hs);
+        launch_balance(P, c->C, c->d_m, c->d_tmp, hs);
+        launch_fill_i32(c->d_flags, c->nI + 1, 0, hs);
+        launch_trunc_boxes(P, c->C, c->d_tmp, c->trunc, c->nI, c->S2.box, c->d_nsize, c->d_flags,
+                           hs);
+        launch_scan(c->d_nsize, c->S2.base, c->nI, hs);
+        launch_compact(P, c->C, c->d_tmp, c->trunc, c->S2.box, c->S2.base, c->d_flags,
+                       c->S2.data, hs);
+        (void)hipEventRecord(c->ev[3], hs);
+        for (int q = 0; q < 2; ++q) {
+            launch_comp_dims(c->part[q], c->S2.box, c->d_pred[q], hs);
+            if (hipMemcpyAsync(c->h_pred[q], c->d_pred[q],
+                               2 * (size_t)c->part[q].ncell * sizeof(int32_t),
+                               hipMemcpyDeviceToHost, hs) != hipSuccess)
+                return false;
+        }
+        return hipMemcpyAsync(c->h_small, c->S2.base + c->nI, sizeof(int64_t),
+                              hipMemcpyDeviceToHost, hs) == hipSuccess &&
+               hipMemcpyAsync(c->h_small + 1, c->d_flags + c->nI, sizeof(int32_t),
+                              hipMemcpyDeviceToHost, hs) == hipSuccess &&
+               hipMemcpyAsync(c->h_small + 2, c->d_pcheck, sizeof(int32_t),
+                              hipMemcpyDeviceToHost, hs) == hipSuccess &&
+               hipStreamSynchronize(hs) == hipSuccess && hipGetLastError() == hipSuccess;
+    };
+    if (!tail()) return fail(c, DD_EDEVICE, "domdec_iterate: a kernel failed");
+    Status fs = sk_finish(c->skw, &bs);
+    if (c->skw.spec.need_resume) {
+        // the speculative rounds were not enough: continue the solve where it stands, then
+        // redo the steps behind it
+        resumed = true;
+        const Status rs = sk_resume(c->skw);
+        if (rs.code) return fail(c, rs);
+        if (!tail()) return fail(c, DD_EDEVICE, "domdec_iterate: a kernel failed");
+        fs = sk_finish(c->skw, &bs);
+        if (c->skw.spec.need_resume)
+            return fail(c, DD_EDEVICE, "domdec_iterate: the resumed solve did not finish");
+    }
+    if (fs.code != DD_OK && fs.code != DD_NOTCONV) return fail(c, fs);
+    if (*reinterpret_cast<const int32_t*>(c->h_small + 2) != 0)
+        return fail(c, DD_EDEVICE, "domdec_iterate: predicted composite boxes were stale");
+    std::swap(c->S, c->S2);
     c->visited[p] = true;
     c->kappa_a[p] = kappa;
-    (void)hipEventRecord(c->ev[2], hs);
-    launch_c2b(P, c->C, c->AS, c->s, mw2, apot, logmu, c->d_nuJ, kappa, c->h, c->d_tmp, c->d_py2,
-               hs);
-    launch_balance(P, c->C, c->d_m, c->d_tmp, hs);
-    launch_fill_i32(c->d_flags, c->nI + 1, 0, hs);
-    launch_trunc_boxes(P, c->C, c->d_tmp, c->trunc, c->nI, c->S2.box, c->d_nsize, c->d_flags, hs);
-    launch_scan(c->d_nsize, c->S2.base, c->nI, hs);
-    launch_compact(P, c->C, c->d_tmp, c->trunc, c->S2.box, c->S2.base, c->d_flags, c->S2.data, hs);
-    std::swap(c->S, c->S2);
-    (void)hipEventRecord(c->ev[3], hs);
-    // the one wait at the end: the new state's size, the untruncated cells, the solve's
-    // statistics
-    if (hipMemcpyAsync(c->h_small, c->S.base + c->nI, sizeof(int64_t), hipMemcpyDeviceToHost, hs) !=
-            hipSuccess ||
-        hipMemcpyAsync(c->h_small + 1, c->d_flags + c->nI, sizeof(int32_t), hipMemcpyDeviceToHost,
-                       hs) != hipSuccess ||
-        hipStreamSynchronize(hs) != hipSuccess || hipGetLastError() != hipSuccess)
-        return fail(c, DD_EDEVICE, "domdec_iterate: a kernel failed");
+    c->pred_ok[0] = c->pred_ok[1] = true;
     const int64_t ntot = c->h_small[0];
     const int32_t kept = *reinterpret_cast<const int32_t*>(c->h_small + 1);
-    const Status fs = sk_finish(c->skw, &bs);
-    if (fs.code != DD_OK && fs.code != DD_NOTCONV) return fail(c, fs);
     c->last_part = p;
     c->last_eps = eps;
     c->last_mw1 = mw1;
@@ -644,6 +712,8 @@ static dd_status iterate_impl(dd_ctx* c, int p, double eps, const dd_sinkhorn_op
         s.comp_entries = total;
         s.batches = 1;
         s.peak_comp_entries = total;
+        s.host_waits = waits + (int32_t)(c->skw.waits - waits0);
+        s.spec_resumed = resumed ? 1 : 0;
         float t = 0.f;
         (void)hipEventElapsedTime(&t, c->ev[0], c->ev[1]);
         s.t_b2c_ms = t;
@@ -815,6 +885,7 @@ static dd_status iterate_batched(dd_ctx* c, int p, double eps, const dd_sinkhorn
                                  dd_iter_stats* out) {
     Status st;
     const hipStream_t hs = c->st;
+    dd_forget_pred(c);
     PartDev& P = c->part[p];
     const int nc = P.ncell, AS = c->AS, A2 = AS * AS;
     const double kappa = eps / (c->h * c->h);
@@ -992,6 +1063,7 @@ static dd_status iterate_batched(dd_ctx* c, int p, double eps, const dd_sinkhorn
 extern "C" dd_status domdec_set_clusters(dd_ctx* c, int32_t clusters) {
     if (!c) return fail(c, DD_EINVAL, "domdec_set_clusters: null context");
     if (clusters < 1) return fail(c, DD_EINVAL, "domdec_set_clusters: clusters must be >= 1");
+    dd_forget_pred(c);
     c->clusters = clusters;
     return DD_OK;
 }
@@ -1248,6 +1320,7 @@ extern "C" const char* domdec_strerror(const dd_ctx* c, dd_status) {
 
 extern "C" dd_status domdec_set_net(dd_ctx* c, dd_net* net) {
     if (!c) return fail(c, DD_EINVAL, "domdec_set_net: null context");
+    dd_forget_pred(c);
     c->net = net;
     return DD_OK;
 }
@@ -1316,6 +1389,7 @@ extern "C" dd_status domdec_save(dd_ctx* c) {
 
 extern "C" dd_status domdec_restore(dd_ctx* c) {
     if (!c) return fail(c, DD_EINVAL, "domdec_restore: null context");
+    dd_forget_pred(c);
     auto& S = c->snap;
     if (!S.valid) return fail(c, DD_ESTATE, "domdec_restore: nothing saved");
     Status st;

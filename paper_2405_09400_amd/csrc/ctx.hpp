@@ -60,6 +60,14 @@ struct dd_ctx {
     double* d_eval = nullptr;
     dd::SkWork skw;
     hipEvent_t ev[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+    // composite box dims of both partitions, computed on the device at the end of the last
+    // iteration from the state it left and copied to pinned memory with its final wait, so
+    // that the next iteration plans its solve without waiting; valid until anything else
+    // changes the state (dd_forget_pred)
+    int32_t* d_pred[2] = {nullptr, nullptr};  // [cells][2]
+    int32_t* h_pred[2] = {nullptr, nullptr};  // pinned copies
+    bool pred_ok[2] = {false, false};
+    int32_t* d_pcheck = nullptr;  // [1] set on the device when a prediction was wrong
     int last_part = -1;
     double last_eps = 0.0;
     int last_mw1 = 0, last_mw2 = 0;
@@ -109,6 +117,8 @@ struct dd_ctx {
 };
 
 void dd_ctx_release(dd_ctx* c);
+// Called by every entry point that changes the state other than an iteration.
+inline void dd_forget_pred(dd_ctx* c) { c->pred_ok[0] = c->pred_ok[1] = false; }
 // Evaluation reductions of the last iteration's composite plans; with pix_out ([N*N][3]) also
 // the per-pixel X moments of the plans.
 void dd_eval_cells(dd_ctx* c, double* pix_out = nullptr);

@@ -1008,6 +1008,7 @@ __device__ __forceinline__ void run_cell(const FastArgs& g, int q, lds_p<char> s
 // fraction of the predicted remaining iterations run before the next test
 constexpr int kFirstRounds = 4, kMaxRounds = 32;
 constexpr double kAheadFrac = 0.8;
+constexpr int kSpecRounds = 4;  // rounds of a speculative solve (and between host reads)
 // A tolerance solve's float32 phase aims below the tolerance, so that the float64 finish
 // usually certifies it with its first error (float32 and float64 errors differ by a few
 // percent, and every float64 iteration costs as much as ~15 float32 ones); it hands over
@@ -1062,8 +1063,10 @@ fast_kernel(FastArgs g) {
     __syncthreads();
     if (!s_last) return;
     __threadfence();
+    // by the first 256 threads in every class, so that the sum (and the stop) does not depend
+    // on which class's workgroup comes last (the eight-wave class's other waves add zeros)
     double e = 0.0, m = 0.0;
-    for (int c = threadIdx.x; c < g.p.ncells; c += team_block(NW)) {
+    for (int c = threadIdx.x; threadIdx.x < 256 && c < g.p.ncells; c += 256) {
         e += g.err[c];
         m += g.mass[c];
     }
@@ -1316,6 +1319,10 @@ bool fast_plan(const SkBatch& p, const std::vector<int32_t>& hd, const dd_sinkho
     return eligible_with(p, hd, kCandidates[0]);
 }
 
+int fast_spec_max_iters(int chunk) {
+    return kSpecRounds * std::max(kFirstRounds, kMaxRounds) * std::max(chunk, 1);
+}
+
 bool fast_eligible(const SkBatch& p, const std::vector<int32_t>& hd) {
     if (fast_off() || p.prec != DD_PREC_F32 || p.xside != kA) return false;
     return eligible_with(p, hd, FastClasses{});
@@ -1324,9 +1331,10 @@ bool fast_eligible(const SkBatch& p, const std::vector<int32_t>& hd) {
 Status fast_solve(const SkBatch& p, const dd_sinkhorn_opts& o, hipStream_t st, SkWork& w,
                   const std::vector<int32_t>& hd, const std::vector<int32_t>& order,
                   int32_t* iters, double* errs, FastInfo* info, bool final_pass,
-                  int32_t* h_ord, FastClasses classes) {
+                  int32_t* h_ord, FastClasses classes, int phase) {
     Status S;
     const int n = p.ncells;
+    const bool resume = phase == kFastResume;
     // Cell classes by box shape (kernel frame), most work first within each:
     //   0: long side <= classes.wave_side (<= 32): one wave per cell (four per workgroup),
     //      log nu_J in registers;
@@ -1381,14 +1389,17 @@ Status fast_solve(const SkBatch& p, const dd_sinkhorn_opts& o, hipStream_t st, S
         w.recs_cap = std::max(n, 1024);
         DD_HIP(w.mem.get(&w.recs, 2 * (size_t)w.recs_cap * sizeof(int4)), S);
     }
-    if (n > 0) {
+    if (n > 0 && !resume) {  // (a resumed solve's order and records are on the device)
         if (h_ord) std::copy(ord.begin(), ord.end(), h_ord);
         DD_HIP(hipMemcpyAsync(w.order, h_ord ? h_ord : ord.data(), n * sizeof(int32_t),
                               hipMemcpyHostToDevice, st),
                S);
         pack_recs_kernel<<<(n + 255) / 256, 256, 0, st>>>(n, w.order, p.dims, p.shift, p.base,
                                                           w.recs);
-        if (!h_ord) DD_HIP(hipStreamSynchronize(st), S);  // `ord` goes out of scope here
+        if (!h_ord) {
+            DD_HIP(hipStreamSynchronize(st), S);
+            ++w.waits;
+        }  // `ord` goes out of scope here
     }
     FastArgs args[kClasses];
     size_t lds[kClasses];
@@ -1475,7 +1486,7 @@ Status fast_solve(const SkBatch& p, const dd_sinkhorn_opts& o, hipStream_t st, S
             }
         }
     };
-    fill_ints<<<1, 64, 0, st>>>(w.ctrl, 16);
+    if (!resume) fill_ints<<<1, 64, 0, st>>>(w.ctrl, 16);
     const bool fixed = o.fixed_iters > 0;
     FastArgs a{};
     if (fixed || o.stop_rule == DD_STOP_CELL) {
@@ -1494,7 +1505,7 @@ Status fast_solve(const SkBatch& p, const dd_sinkhorn_opts& o, hipStream_t st, S
     // between reads of the device stop flag;
     // every launch is bracketed by events on its own stream (the per-class kernel time of the
     // statistics), the launches after the stop, which exit at once, included
-    const int reps = 4;
+    const int reps = kSpecRounds;
     if (!arena)
         for (auto& cls : w.kev)
             for (auto& se : cls)
@@ -1503,7 +1514,31 @@ Status fast_solve(const SkBatch& p, const dd_sinkhorn_opts& o, hipStream_t st, S
     double terms_per_it[kClasses] = {0.0, 0.0, 0.0};
     for (int k = 0; k < kClasses; ++k)
         for (int c : cells[k]) terms_per_it[k] += sk_cell_terms(kA, hd[2 * c], hd[2 * c + 1]);
+    if (info)
+        for (int k = 0; k < kClasses; ++k) info->terms_per_it[k] = terms_per_it[k];
     int hctl[16] = {};
+    if (phase == kFastSpec) {
+        // `reps` rounds with no host wait: the caller reads the control words after the whole
+        // half-iteration and resumes here if the rule had not stopped by then
+        for (int r = 0; r < reps; ++r) {
+            fork();
+            launch(a, kBatch, true, r);
+            join();
+        }
+        launch_done_iters(n, iters, w.ctrl, st);
+        if (info) {
+            info->final_done = false;
+            info->spec_slots = reps;
+        }
+        DD_HIP(hipGetLastError(), S);
+        return S;
+    }
+    if (resume) {
+        // the speculative rounds' control words (read back after the caller's wait) and their
+        // launch times
+        std::copy(w.h_ctl32, w.h_ctl32 + 16, hctl);
+        for (int r = 0; r < w.pend.spec_slots; ++r) collect(r);
+    }
     // every round that starts before the stop runs at least one iteration
     for (int rounds = 0; rounds < o.max_iter && !hctl[2]; rounds += reps) {
         for (int r = 0; r < reps; ++r) {
@@ -1513,6 +1548,7 @@ Status fast_solve(const SkBatch& p, const dd_sinkhorn_opts& o, hipStream_t st, S
         }
         DD_HIP(hipMemcpyAsync(hctl, w.ctrl, sizeof hctl, hipMemcpyDeviceToHost, st), S);
         DD_HIP(hipStreamSynchronize(st), S);
+        ++w.waits;
         if (!arena)
             for (int r = 0; r < reps; ++r) collect(r);
     }
@@ -1531,6 +1567,7 @@ Status fast_solve(const SkBatch& p, const dd_sinkhorn_opts& o, hipStream_t st, S
     launch(a, kFinal, !arena, 0);
     join();
     DD_HIP(hipStreamSynchronize(st), S);
+    ++w.waits;
     if (!arena) collect(0);
     DD_HIP(hipGetLastError(), S);
     return S;

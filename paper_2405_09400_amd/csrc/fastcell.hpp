@@ -20,7 +20,16 @@ struct FastInfo {
     double terms[kClasses] = {0.0, 0.0, 0.0};
     int stop_it = 0;          // batch rule: the iteration the rule stopped at
     bool final_done = true;   // f and g of that iteration are in p.a, p.b
+    double terms_per_it[kClasses] = {0.0, 0.0, 0.0};  // LSE terms of one iteration per class
+    int spec_slots = 0;       // kFastSpec: event slots of the rounds enqueued
 };
+
+// fast_solve phases: the whole solve; rounds enqueued with no host wait (batch rule, the
+// caller resumes if they were not enough); the resumption of such a solve
+constexpr int kFastAll = 0, kFastSpec = 1, kFastResume = 2;
+
+// An upper bound on the iterations kFastSpec's rounds run (stop tests `chunk` apart at least).
+int fast_spec_max_iters(int chunk);
 
 // True when the batch runs on the register-blocked path: float32 terms, 8 x 8 X blocks,
 // every box side at most kFastMaxSide, every class's workgroup within the LDS of a CU, and
@@ -58,8 +67,13 @@ constexpr int kFastMaxSide = 512;
 Status fast_solve(const SkBatch& p, const dd_sinkhorn_opts& o, hipStream_t st, SkWork& w,
                   const std::vector<int32_t>& hd, const std::vector<int32_t>& ord,
                   int32_t* iters, double* errs, FastInfo* info, bool final_pass = true,
-                  int32_t* h_ord = nullptr, FastClasses cls = FastClasses{});
+                  int32_t* h_ord = nullptr, FastClasses cls = FastClasses{},
+                  int phase = kFastAll);
 // h_ord: pinned host room for n ints (the order is uploaded from there without waiting), or
-// NULL (no-allocation mode: uploaded from a temporary, then waited for)
+// NULL (no-allocation mode: uploaded from a temporary, then waited for).
+// phase kFastSpec (batch rule, not in no-allocation mode): enqueue four rounds and the
+// per-cell counts of their stop iteration (0 if none) without a host wait, and return;
+// kFastResume (same arguments, after the caller has waited and copied w.ctrl to w.h_ctl32):
+// continue that solve from where the four rounds left it.
 
 }  // namespace dd

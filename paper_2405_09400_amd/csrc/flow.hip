@@ -458,6 +458,7 @@ void flow_release(dd_ctx* c) {
 extern "C" dd_status flow_costs(dd_ctx* c, int32_t candidate, double eps_gamma, double* cbar,
                                 int32_t* n_arcs) {
     if (!c) return ffail(c, DD_EINVAL, "flow_costs: null context");
+    dd_forget_pred(c);
     if (candidate != DD_CAND_PRODUCT && candidate != DD_CAND_GLUED)
         return ffail(c, DD_EINVAL, "flow_costs: candidate must be DD_CAND_PRODUCT or DD_CAND_GLUED");
     if (candidate == DD_CAND_GLUED && (!(eps_gamma > 0.0) || !std::isfinite(eps_gamma) || c->s > 8))
@@ -503,6 +504,7 @@ extern "C" dd_status flow_costs(dd_ctx* c, int32_t candidate, double eps_gamma, 
 
 extern "C" dd_status flow_apply(dd_ctx* c, const double* w) {
     if (!c || !w) return ffail(c, DD_EINVAL, "flow_apply: null argument");
+    dd_forget_pred(c);
     dd_status st = flow_prepare(c);
     if (st != DD_OK) return st;
     FlowState* F = c->flow;
@@ -582,6 +584,7 @@ extern "C" dd_status dd_mcf_solve(int32_t n, int32_t m, const int32_t* tail, con
 extern "C" dd_status flow_update(dd_ctx* c, int32_t candidate, double eps_gamma,
                                  dd_flow_stats* out) {
     if (!c) return ffail(c, DD_EINVAL, "flow_update: null context");
+    dd_forget_pred(c);
     using clk = std::chrono::steady_clock;
     const auto t0 = clk::now();
     int32_t na = 0;

@@ -39,6 +39,7 @@
 #include "fastcell.hpp"
 
 #include <algorithm>
+#include <cstdlib>
 #include <cmath>
 #include <map>
 #include <mutex>
@@ -687,9 +688,14 @@ struct SolveCell {
 // side on separate streams.  A launch covers order[q_lo, q_hi) with its tile (lw1, lw2):
 // MODE 0 = one cell per workgroup, MODE 1 = one cell per wave.
 constexpr int kBig = 0, kSmall = 1;
+// A workgroup of up to kBigThreads threads per cell (MODE 0): every sum has the same terms in
+// the same order for any workgroup size (a pass's outputs are spread over the threads, each
+// output's sum over a fixed group of lanes of one wave; a cell's error over its first wave),
+// so the size changes the speed of a class and not its results.
+constexpr int kBigThreads = 512;
 
 template <typename T, int MODE>
-__global__ void __launch_bounds__(kThreads)
+__global__ void __launch_bounds__(MODE == kBig ? kBigThreads : kThreads)
     sk_cell_kernel(SkBatch p, double tol, int limit, int fixed, int stall_window, int* queue,
                    int* ctrl, int32_t* iters_out, double* err_out, double* mass_out,
                    double* big_scratch) {
@@ -813,7 +819,7 @@ __device__ __forceinline__ void for_items(const SkBatch& p, lds_p<char> base, do
 // take one ticket each; the last of all (`nblocks` in total) reduces the per-cell errors in
 // fixed cell order and sets the stop flag.
 template <typename T, int MODE>
-__global__ void __launch_bounds__(kThreads)
+__global__ void __launch_bounds__(MODE == kBig ? kBigThreads : kThreads)
     sk_iter_kernel(SkBatch p, double* fa, double* fb, int limit, double tol, int nblocks,
                    int* ctrl, double* cell_err, double* cell_mass, double* dtot,
                    double* big_scratch) {
@@ -835,8 +841,10 @@ __global__ void __launch_bounds__(kThreads)
     __syncthreads();
     if (!s_last) return;
     __threadfence();
+    // by the first kThreads threads whatever the workgroup size, so that the sum (and the
+    // stop) does not depend on which class's workgroup comes last (the others add zeros)
     double e = 0.0, m = 0.0;
-    for (int c = threadIdx.x; c < p.ncells; c += blockDim.x) {
+    for (int c = threadIdx.x; threadIdx.x < kThreads && c < p.ncells; c += kThreads) {
         e += cell_err[c];
         m += cell_mass[c];
     }
@@ -854,7 +862,7 @@ __global__ void __launch_bounds__(kThreads)
 }
 
 template <typename T, int MODE>
-__global__ void __launch_bounds__(kThreads) sk_final_kernel(SkBatch p, int* ctrl,
+__global__ void __launch_bounds__(MODE == kBig ? kBigThreads : kThreads) sk_final_kernel(SkBatch p, int* ctrl,
                                                            int32_t* iters_out,
                                                            double* big_scratch) {
     extern __shared__ __align__(16) char smem[];
@@ -971,6 +979,8 @@ Status sk_work_reserve(SkWork& w, int ncells, size_t a_n) {
     }
     if (!w.ctrl) {
         DD_HIP(w.mem.get(&w.ctrl, 16 * sizeof(int)), st);
+        DD_HIP(w.mem.get(&w.ctrl64, 16 * sizeof(int)), st);
+        DD_HIP(hipHostMalloc((void**)&w.h_ctl32, 16 * sizeof(int)), st);
         DD_HIP(w.mem.get(&w.dtot, 8 * sizeof(double)), st);
         DD_HIP(hipEventCreate(&w.ev0), st);
         DD_HIP(hipEventCreate(&w.ev1), st);
@@ -1015,6 +1025,8 @@ void sk_work_release(SkWork& w) {
     w.mem.put(w.recs);
     if (w.h_stage) (void)hipHostFree(w.h_stage);
     if (w.h_ctl) (void)hipHostFree(w.h_ctl);
+    if (w.h_ctl32) (void)hipHostFree(w.h_ctl32);
+    w.mem.put(w.ctrl64);
     if (w.h_tot) (void)hipHostFree(w.h_tot);
     w.mem.put(w.order64);
     w.mem.put(w.scr_off64);
@@ -1069,10 +1081,10 @@ Status set_lds_attr(K kernel, size_t bytes, Status& st) {
 }
 
 template <typename K>
-int grid_for(K kernel, size_t lds, int items) {
+int grid_for(K kernel, size_t lds, int items, int threads = kThreads) {
     int per_cu = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(kernel),
-                                                     kThreads, lds) != hipSuccess ||
+                                                     threads, lds) != hipSuccess ||
         per_cu < 1)
         per_cu = 1;
     const long g = (long)per_cu * num_cus();
@@ -1086,15 +1098,33 @@ struct CellClass {
     int lo = 0, hi = 0;
     int t[2] = {0, 0};  // LDS tile (W1, W2)
     size_t budget = 0;
+    int threads = kThreads;  // workgroup size (MODE kBig: up to kBigThreads)
 };
 
 // first_chunk: iterations launched before the first read of the stop flag (batch rule; 0: a
-// whole chunk of check_every)
+// whole chunk of check_every).  Batch rule only: `ctl` is the control block (default w.ctrl);
+// phase kRunSpec launches the first iterations without reading the stop flag (the caller has
+// cleared `ctl`, or marked it done so that they exit at once), then picks the output buffer
+// and the per-cell counts on the device; kRunResume continues such a run from the stop-flag
+// read (the state on the device is that of a run at the same point).
+constexpr int kRunAll = 0, kRunSpec = 1, kRunResume = 2;
+
+__global__ void pick_final_kernel(int64_t n, double* a, const double* alt, const int* ctrl) {
+    // the last X-update of a batch-rule run that stopped at iteration `done` is in `alt`
+    // when done is even (odd iterations read a and write alt)
+    const int done = __atomic_load_n(&ctrl[2], __ATOMIC_RELAXED);
+    if (done <= 0 || ((done - 1) & 1) == 0) return;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        a[i] = alt[i];
+}
+
 template <typename T>
 Status run_solver(const SkBatch& p0, const std::vector<CellClass>& cls, const dd_sinkhorn_opts& o,
                   hipStream_t st, SkWork& w, int32_t* iters, double* errs, int first_chunk = 0,
-                  int* done_out = nullptr) {
+                  int* done_out = nullptr, int* ctl = nullptr, int phase = kRunAll) {
     Status S;
+    if (!ctl) ctl = w.ctrl;
     double* big = reinterpret_cast<double*>(w.big);
     // the small and giant classes run on `st`, the big class on the second stream, side by side
     const bool one_stream = w.arena != nullptr;  // no-allocation mode: the caller's stream only
@@ -1124,7 +1154,7 @@ Status run_solver(const SkBatch& p0, const std::vector<CellClass>& cls, const dd
         (void)hipStreamWaitEvent(st, joins[1], 0);
     };
     const bool fixed = o.fixed_iters > 0;
-    zero_ints<<<1, 64, 0, st>>>(w.ctrl, 12);
+    if (phase == kRunAll) zero_ints<<<1, 64, 0, st>>>(ctl, 12);
     if (fixed || o.stop_rule == DD_STOP_CELL) {
         const int limit = fixed ? o.fixed_iters : o.max_iter;
         // stall detection only where a float64 finish follows
@@ -1134,9 +1164,9 @@ Status run_solver(const SkBatch& p0, const std::vector<CellClass>& cls, const dd
             const int n = cls[k].hi - cls[k].lo;
             auto kern = cls[k].mode == kBig ? sk_cell_kernel<T, kBig> : sk_cell_kernel<T, kSmall>;
             if (set_lds_attr(kern, lds[k], S).code) return S;
-            kern<<<grid_for(kern, lds[k], class_items(cls[k].mode, n)), kThreads, lds[k],
-                   streams[k]>>>(pk[k], o.tol, limit, fixed ? 1 : 0, stall, w.ctrl + qidx[k],
-                                 w.ctrl, iters, errs, w.cell_mass, big);
+            kern<<<grid_for(kern, lds[k], class_items(cls[k].mode, n), cls[k].threads),
+                   cls[k].threads, lds[k], streams[k]>>>(pk[k], o.tol, limit, fixed ? 1 : 0, stall, ctl + qidx[k],
+                                 ctl, iters, errs, w.cell_mass, big);
         }
         join();
         DD_HIP(hipGetLastError(), S);
@@ -1149,7 +1179,7 @@ Status run_solver(const SkBatch& p0, const std::vector<CellClass>& cls, const dd
         auto ik = cls[k].mode == kBig ? sk_iter_kernel<T, kBig> : sk_iter_kernel<T, kSmall>;
         auto fk = cls[k].mode == kBig ? sk_final_kernel<T, kBig> : sk_final_kernel<T, kSmall>;
         if (set_lds_attr(ik, lds[k], S).code || set_lds_attr(fk, lds[k], S).code) return S;
-        grid[k] = grid_for(ik, lds[k], class_items(cls[k].mode, n));
+        grid[k] = grid_for(ik, lds[k], class_items(cls[k].mode, n), cls[k].threads);
         nblocks += grid[k];
     }
     double* bufs[2] = {p0.a, w.a_alt};
@@ -1163,8 +1193,8 @@ Status run_solver(const SkBatch& p0, const std::vector<CellClass>& cls, const dd
             fork();
             for (int k = 0; k < ncls; ++k) {
                 auto ik = cls[k].mode == kBig ? sk_iter_kernel<T, kBig> : sk_iter_kernel<T, kSmall>;
-                ik<<<grid[k], kThreads, lds[k], streams[k]>>>(pk[k], bufs[0], bufs[1], o.max_iter,
-                                                              o.tol, nblocks, w.ctrl, errs,
+                ik<<<grid[k], cls[k].threads, lds[k], streams[k]>>>(pk[k], bufs[0], bufs[1], o.max_iter,
+                                                              o.tol, nblocks, ctl, errs,
                                                               w.cell_mass, w.dtot, big);
             }
             join();
@@ -1175,22 +1205,34 @@ Status run_solver(const SkBatch& p0, const std::vector<CellClass>& cls, const dd
     // of `chunk` launches is captured once and replayed.
     int done = 0, launched = 0;
     auto read_done = [&]() {
-        return hipMemcpyAsync(&done, w.ctrl + 2, sizeof(int), hipMemcpyDeviceToHost, st) ==
+        ++w.waits;
+        return hipMemcpyAsync(&done, ctl + 2, sizeof(int), hipMemcpyDeviceToHost, st) ==
                    hipSuccess &&
                hipStreamSynchronize(st) == hipSuccess;
     };
-    const int first = std::max(1, std::min(first_chunk > 0 ? first_chunk : chunk, o.max_iter));
-    for (int r = 0; r < first; ++r) {
+    // (a speculative run and its resumption take first_chunk as it is, 0 included)
+    const int first = phase != kRunAll
+                          ? std::max(0, std::min(first_chunk, o.max_iter))
+                          : std::max(1, std::min(first_chunk > 0 ? first_chunk : chunk, o.max_iter));
+    for (int r = 0; phase != kRunResume && r < first; ++r) {
         fork();
         for (int k = 0; k < ncls; ++k) {
             auto ik = cls[k].mode == kBig ? sk_iter_kernel<T, kBig> : sk_iter_kernel<T, kSmall>;
-            ik<<<grid[k], kThreads, lds[k], streams[k]>>>(pk[k], bufs[0], bufs[1], o.max_iter,
-                                                          o.tol, nblocks, w.ctrl, errs,
+            ik<<<grid[k], cls[k].threads, lds[k], streams[k]>>>(pk[k], bufs[0], bufs[1], o.max_iter,
+                                                          o.tol, nblocks, ctl, errs,
                                                           w.cell_mass, w.dtot, big);
         }
         join();
     }
     launched = first;
+    if (phase == kRunSpec) {
+        const int64_t na = (int64_t)p0.ncells * p0.xside * p0.xside;
+        pick_final_kernel<<<(int)std::min<int64_t>((na + 255) / 256, 1024), 256, 0, st>>>(
+            na, p0.a, bufs[1], ctl);
+        launch_done_iters(p0.ncells, iters, ctl, st);
+        DD_HIP(hipGetLastError(), S);
+        return S;
+    }
     if (!read_done()) {
         S.code = DD_EDEVICE;
         S.msg = "sinkhorn: reading the stop flag failed";
@@ -1228,7 +1270,7 @@ Status run_solver(const SkBatch& p0, const std::vector<CellClass>& cls, const dd
         DD_HIP(hipMemcpyAsync(p0.a, bufs[1], a_bytes, hipMemcpyDeviceToDevice, st), S);
     // g of the stopping iteration is already in p.b (every Y-update writes it, and no
     // iteration runs after the stop); each cell's count is the stop iteration
-    launch_done_iters(p0.ncells, iters, w.ctrl, st);
+    launch_done_iters(p0.ncells, iters, ctl, st);
     if (done_out) *done_out = done;
     DD_HIP(hipGetLastError(), S);
     return S;
@@ -1329,6 +1371,9 @@ Plan plan_classes(const std::vector<int32_t>& hd, const std::vector<int32_t>& or
     plan_tile(hd, rest, AS, elem, big_budget, bc.t[0], bc.t[1]);
     for (int c : rest) (fits(c, bc.t) ? big_cells : giant_cells).push_back(c);
     gc.budget = kBigBudget;
+    // the largest boxes, one workgroup per CU by their LDS: twice the threads per cell (the
+    // same results, see kBig)
+    gc.threads = kBigThreads;
     plan_tile(hd, giant_cells, AS, elem, kBigBudget, gc.t[0], gc.t[1]);
     P.ord = giant_cells;
     P.ord.insert(P.ord.end(), big_cells.begin(), big_cells.end());
@@ -1436,9 +1481,70 @@ struct StreamJoin {
 
 Status finish_stats(SkWork& w, const int* hctl, const double* htot, dd_batch_stats* stats);
 
+template <typename Work>
+std::vector<int32_t> work_order(int n, Work&& work) {
+    std::vector<uint32_t> key(n), key2(n);
+    std::vector<int32_t> ord(n), ord2(n);
+    for (int c = 0; c < n; ++c) {
+        key[c] = 4294967295u - (uint32_t)std::min(work(c), 4294967295.0);
+        ord[c] = c;
+    }
+    for (int shift = 0; shift < 32; shift += 8) {
+        int cnt[257] = {};
+        for (int k = 0; k < n; ++k) ++cnt[((key[k] >> shift) & 255u) + 1];
+        if (cnt[((key[0] >> shift) & 255u) + 1] == n) continue;  // one digit: nothing moves
+        for (int b = 0; b < 256; ++b) cnt[b + 1] += cnt[b];
+        for (int k = 0; k < n; ++k) {
+            const int d = cnt[(key[k] >> shift) & 255u]++;
+            key2[d] = key[k];
+            ord2[d] = ord[k];
+        }
+        key.swap(key2);
+        ord.swap(ord2);
+    }
+    return ord;
+}
+
+// the register-blocked path's part of the pending statistics
+void set_fast_pend(SkWork::Pend& pd, const FastInfo& fi) {
+    pd.terms32 = 0.0;
+    for (int k = 0; k < kClasses; ++k) {
+        pd.n[k] = fi.n[k];
+        pd.lds[k] = fi.lds[k];
+        pd.launches[k] = fi.launches[k];
+        pd.ms[k] = fi.ms[k];
+        pd.terms[k] = fi.terms[k];
+        pd.terms32 += fi.terms[k];
+    }
+}
+
+// Speculative solves (DD_SPEC=0 in the environment switches them off, for A/B timing and
+// the tests that compare both; read on every solve).
+bool spec_enabled() {
+    const char* e = std::getenv("DD_SPEC");
+    return !(e && e[0] == '0');
+}
+
+// float64-finish iterations launched speculatively: 2, or DD_SPEC_FINISH in [0, 8] (0 makes
+// every speculative solve resume its finish: the tests' way to reach that path)
+int spec_finish_launches() {
+    const char* e = std::getenv("DD_SPEC_FINISH");
+    if (!e || !*e) return 2;
+    return std::max(0, std::min(8, std::atoi(e)));
+}
+
+// Between the speculative float32 rounds and the float64 finish: the finish's control block
+// is cleared when the rounds stopped short of the cap, else marked done (-1), so that the
+// finish's launches exit at once and the caller resumes the rounds.
+__global__ void spec_gate_kernel(const int* c32, int* c64, int max_iter) {
+    const int stop = __atomic_load_n(&c32[2], __ATOMIC_RELAXED);
+    const int t = threadIdx.x;
+    if (t < 16) c64[t] = (t == 2 && !(stop > 0 && stop < max_iter)) ? -1 : 0;
+}
+
 Status sk_solve(const SkBatch& p, const dd_sinkhorn_opts& o, hipStream_t caller_st, SkWork& w,
                 dd_batch_stats* stats, int32_t* cell_iters_out, double* cell_err_out,
-                const int32_t* host_dims, bool defer) {
+                const int32_t* host_dims, bool defer, bool spec) {
     Status S;
     w.pend.active = false;
     if (p.ncells < 0 || p.xside < 2 || p.xside > 16 || !(p.kappa > 0.0) || p.max_w1 < 1 ||
@@ -1477,6 +1583,7 @@ Status sk_solve(const SkBatch& p, const dd_sinkhorn_opts& o, hipStream_t caller_
     } else {
         DD_HIP(hipMemcpyAsync(hd.data(), p.dims, hd.size() * 4, hipMemcpyDeviceToHost, st), S);
         DD_HIP(hipStreamSynchronize(st), S);
+        ++w.waits;
     }
     // pinned staging of the launch plans and the statistics (outside no-allocation mode):
     // [order64 | off64 | order | off | fast order], 8-byte aligned
@@ -1518,16 +1625,11 @@ Status sk_solve(const SkBatch& p, const dd_sinkhorn_opts& o, hipStream_t caller_
     auto work = [&](int c) {
         return sk_cell_terms(AS, std::max(hd[2 * c], 0), std::max(hd[2 * c + 1], 0));
     };
-    // cells in order of decreasing LSE work per iteration, ties by index: one sort of packed
-    // integer keys (the work of a cell is an integer below 2^32)
-    std::vector<uint64_t> keys(p.ncells);
-    for (int c = 0; c < p.ncells; ++c) {
-        const double wk = std::min(work(c), 4294967295.0);
-        keys[c] = ((uint64_t)(4294967295u - (uint32_t)wk) << 32) | (uint32_t)c;
-    }
-    std::sort(keys.begin(), keys.end());
-    std::vector<int32_t> ord(p.ncells);
-    for (int k = 0; k < p.ncells; ++k) ord[k] = (int32_t)(keys[k] & 0xffffffffu);
+    // cells in order of decreasing LSE work per iteration, ties by index (the work of a cell
+    // is an integer below 2^32): a stable least-significant-digit radix sort of the inverted
+    // work in four byte passes, from the index order (linear in the cells; a comparison sort
+    // of the four thousand cells of a 512^2 partition was most of the host's planning time)
+    std::vector<int32_t> ord = work_order(p.ncells, work);
     const size_t elem = p.prec == DD_PREC_F64 ? sizeof(double) : sizeof(float);
     // Launch plans, one per precision (the float64 finish has its own tiles).  The two LDS
     // budgets come from the tuner, keyed by block side, precision, stop rule and the size
@@ -1613,13 +1715,27 @@ Status sk_solve(const SkBatch& p, const dd_sinkhorn_opts& o, hipStream_t caller_
         }
     }
     // without the pinned staging the copies read the plans' own vectors: wait for them
-    if (!pinned) DD_HIP(hipStreamSynchronize(st), S);
+    if (!pinned) {
+        DD_HIP(hipStreamSynchronize(st), S);
+        ++w.waits;
+    }
     if (!arena) DD_HIP(hipEventRecord(w.ev0, st), S);
     zero_ints<<<1, 64, 0, st>>>(w.ctrl, 16);
     FastInfo fi;
     int k32 = 0;  // batch rule: the float32 phase's stop iteration
+    // the whole solve enqueued with no host wait (see sk_solve in the header); the float64
+    // finish's first two iterations are then launched with the full max_iter as their limit,
+    // which stops neither of them when the float32 phase has stopped at least two iterations
+    // short of the cap -- what the bound on the speculative rounds' iterations guarantees
+    const int spec_chunk = std::max(1, o.check_every > 0 ? o.check_every : 8);
+    const int spec_first64 = spec_finish_launches();
+    const bool use_spec = spec && defer && pinned && fast && finish &&
+                          o.stop_rule == DD_STOP_BATCH &&
+                          o.max_iter >= fast_spec_max_iters(spec_chunk) + spec_first64 + 2 &&
+                          spec_enabled();
     if (fast)
-        S = fast_solve(p, o, st, w, hd, ord, iters, errs, &fi, !finish, h_ordf, fcls);
+        S = fast_solve(p, o, st, w, hd, ord, iters, errs, &fi, !finish, h_ordf, fcls,
+                       use_spec ? kFastSpec : kFastAll);
     else
         S = p.prec == DD_PREC_F32 ? run_solver<float>(q, P.classes, o, st, w, iters, errs, 0, &k32)
                                   : run_solver<double>(q, P.classes, o, st, w, iters, errs);
@@ -1635,16 +1751,23 @@ Status sk_solve(const SkBatch& p, const dd_sinkhorn_opts& o, hipStream_t caller_
     dd_sinkhorn_opts o64 = o;
     if (o.stop_rule == DD_STOP_BATCH) o64.max_iter = o.max_iter - k32 + (shared ? 1 : 0);
     const bool run64 = finish && o64.max_iter >= 1;
-    if (run64) {
+    if (use_spec) {
+        spec_gate_kernel<<<1, 64, 0, st>>>(w.ctrl, w.ctrl64, o.max_iter);
+        S = run_solver<double>(q64, P64.classes, o64, st, w, w.iters64, errs, spec_first64,
+                               nullptr, w.ctrl64, kRunSpec);
+        if (S.code) return S;
+    } else if (run64) {
         S = run_solver<double>(q64, P64.classes, o64, st, w, w.iters64, errs, 2);
         if (S.code) return S;
     }
+    int* const ctl_stats = use_spec ? w.ctrl64 : w.ctrl;
     // per-cell iterations of both phases, then the statistics over them
     if (run64)
         merge_iters_kernel<<<(p.ncells + kThreads - 1) / kThreads, kThreads, 0, st>>>(
             p.ncells, iters, w.iters64, shared ? 1 : 0);
     sk_stats_kernel<<<1, kThreads, 0, st>>>(p.ncells, iters, run64 ? w.iters64 : nullptr, errs,
-                                            w.cell_mass, o.tol, p.dims, p.xside, w.dtot, w.ctrl);
+                                            w.cell_mass, o.tol, p.dims, p.xside, w.dtot,
+                                            ctl_stats);
     if (!arena) DD_HIP(hipEventRecord(w.ev1, st), S);
     auto& pd = w.pend;
     pd = SkWork::Pend{};
@@ -1660,13 +1783,7 @@ Status sk_solve(const SkBatch& p, const dd_sinkhorn_opts& o, hipStream_t caller_
     pd.key[1] = key.prec;
     pd.key[2] = key.rule;
     pd.key[3] = key.bucket;
-    for (int k = 0; k < kClasses; ++k) {
-        pd.n[k] = fi.n[k];
-        pd.lds[k] = fi.lds[k];
-        pd.launches[k] = fi.launches[k];
-        pd.ms[k] = fi.ms[k];
-        pd.terms[k] = fi.terms[k];
-    }
+    set_fast_pend(pd, fi);
     pd.n_big = P.n_big;
     pd.n_giant = P.n_giant;
     pd.small_tile[0] = P.small_tile[0];
@@ -1680,13 +1797,41 @@ Status sk_solve(const SkBatch& p, const dd_sinkhorn_opts& o, hipStream_t caller_
         for (int k = 0; k < 3; ++k) pd.fkey[k] = fkey[k];
         pd.wave_side = fcls.wave_side;
         pd.big_entries = fcls.big_entries;
-        for (int k = 0; k < kClasses; ++k) pd.terms32 += fi.terms[k];
+    }
+    if (use_spec) {
+        pd.spec = true;
+        pd.spec_slots = fi.spec_slots;
+        for (int k = 0; k < kClasses; ++k) pd.tpi[k] = fi.terms_per_it[k];
+        // what a resumption needs
+        auto& sp = w.spec;
+        sp.need_resume = false;
+        sp.p = p;
+        sp.q64 = q64;
+        sp.o = o;
+        sp.hd = std::move(hd);
+        sp.ord = std::move(ord);
+        sp.cls64.clear();
+        for (const CellClass& c : P64.classes) {
+            const int64_t v[7] = {c.mode, c.lo, c.hi, c.t[0], c.t[1], (int64_t)c.budget,
+                                  c.threads};
+            sp.cls64.insert(sp.cls64.end(), v, v + 7);
+        }
+        sp.wave_side = fcls.wave_side;
+        sp.big_entries = fcls.big_entries;
+        sp.iters = iters;
+        sp.errs = errs;
+        sp.caller = caller_st;
+        sp.first64 = spec_first64;
     }
     if (pinned) {
-        DD_HIP(hipMemcpyAsync(w.h_ctl, w.ctrl, 16 * sizeof(int), hipMemcpyDeviceToHost, st), S);
+        DD_HIP(hipMemcpyAsync(w.h_ctl, ctl_stats, 16 * sizeof(int), hipMemcpyDeviceToHost, st), S);
+        if (use_spec)
+            DD_HIP(hipMemcpyAsync(w.h_ctl32, w.ctrl, 16 * sizeof(int), hipMemcpyDeviceToHost, st),
+                   S);
         DD_HIP(hipMemcpyAsync(w.h_tot, w.dtot, 8 * sizeof(double), hipMemcpyDeviceToHost, st), S);
         if (defer) return S;  // the caller synchronises, then sk_finish
         DD_HIP(hipStreamSynchronize(st), S);
+        ++w.waits;
         return sk_finish(w, stats);
     }
     int hctl[16];
@@ -1694,7 +1839,80 @@ Status sk_solve(const SkBatch& p, const dd_sinkhorn_opts& o, hipStream_t caller_
     DD_HIP(hipMemcpyAsync(hctl, w.ctrl, sizeof hctl, hipMemcpyDeviceToHost, st), S);
     DD_HIP(hipMemcpyAsync(htot, w.dtot, sizeof htot, hipMemcpyDeviceToHost, st), S);
     DD_HIP(hipStreamSynchronize(st), S);
+    ++w.waits;
     return finish_stats(w, hctl, htot, stats);
+}
+
+Status sk_resume(SkWork& w) {
+    Status S;
+    SkWork::Spec& sp = w.spec;
+    SkWork::Pend& pd = w.pend;
+    if (!sp.need_resume || !pd.active || !pd.spec) {
+        S.code = DD_ESTATE;
+        S.msg = "sinkhorn: no speculative solve to resume";
+        return S;
+    }
+    sp.need_resume = false;
+    const StreamJoin join(sp.caller, w.stream, w.evj);
+    const hipStream_t st = w.stream;
+    const dd_sinkhorn_opts& o = sp.o;
+    std::vector<CellClass> cls64(sp.cls64.size() / 7);
+    for (size_t k = 0; k < cls64.size(); ++k) {
+        const int64_t* v = &sp.cls64[7 * k];
+        cls64[k].threads = (int)v[6];
+        cls64[k].mode = (int)v[0];
+        cls64[k].lo = (int)v[1];
+        cls64[k].hi = (int)v[2];
+        cls64[k].t[0] = (int)v[3];
+        cls64[k].t[1] = (int)v[4];
+        cls64[k].budget = (size_t)v[5];
+    }
+    const int stop32 = w.h_ctl32[2];
+    dd_sinkhorn_opts o64 = o;
+    int* ctl_stats = w.ctrl;
+    bool shared = false, run64 = true;
+    if (!(stop32 > 0 && stop32 < o.max_iter)) {
+        // the float32 rounds had not stopped (or stopped at the cap): continue them, then the
+        // float64 finish as a solve without speculation runs it
+        FastInfo fi;
+        FastClasses fcls;
+        fcls.wave_side = sp.wave_side;
+        fcls.big_entries = sp.big_entries;
+        S = fast_solve(sp.p, o, st, w, sp.hd, sp.ord, sp.iters, sp.errs, &fi, false, nullptr,
+                       fcls, kFastResume);
+        if (S.code) return S;
+        DD_HIP(hipEventRecord(w.ev2, st), S);
+        shared = fi.final_done;
+        o64.max_iter = o.max_iter - fi.stop_it + (shared ? 1 : 0);
+        run64 = o64.max_iter >= 1;
+        if (run64) {
+            S = run_solver<double>(sp.q64, cls64, o64, st, w, w.iters64, sp.errs, 2);
+            if (S.code) return S;
+        }
+        set_fast_pend(pd, fi);
+        pd.spec = false;
+    } else {
+        // the float32 phase stopped; the float64 finish had not within its first iterations
+        o64.max_iter = o.max_iter - stop32;
+        S = run_solver<double>(sp.q64, cls64, o64, st, w, w.iters64, sp.errs, sp.first64,
+                               nullptr, w.ctrl64, kRunResume);
+        if (S.code) return S;
+        ctl_stats = w.ctrl64;
+    }
+    pd.run64 = run64;
+    if (run64)
+        merge_iters_kernel<<<(sp.p.ncells + kThreads - 1) / kThreads, kThreads, 0, st>>>(
+            sp.p.ncells, sp.iters, w.iters64, shared ? 1 : 0);
+    sk_stats_kernel<<<1, kThreads, 0, st>>>(sp.p.ncells, sp.iters, run64 ? w.iters64 : nullptr,
+                                            sp.errs, w.cell_mass, o.tol, sp.p.dims, sp.p.xside,
+                                            w.dtot, ctl_stats);
+    DD_HIP(hipEventRecord(w.ev1, st), S);
+    DD_HIP(hipMemcpyAsync(w.h_ctl, ctl_stats, 16 * sizeof(int), hipMemcpyDeviceToHost, st), S);
+    if (pd.spec)
+        DD_HIP(hipMemcpyAsync(w.h_ctl32, w.ctrl, 16 * sizeof(int), hipMemcpyDeviceToHost, st), S);
+    DD_HIP(hipMemcpyAsync(w.h_tot, w.dtot, 8 * sizeof(double), hipMemcpyDeviceToHost, st), S);
+    DD_HIP(hipGetLastError(), S);
+    return S;  // the caller synchronises, then sk_finish
 }
 
 Status finish_stats(SkWork& w, const int* hctl, const double* htot, dd_batch_stats* stats) {
@@ -1780,7 +1998,36 @@ Status finish_stats(SkWork& w, const int* hctl, const double* htot, dd_batch_sta
 Status sk_finish(SkWork& w, dd_batch_stats* stats) {
     // (an empty batch has already reported its statistics)
     if (!w.pend.active) return Status{};
-    return finish_stats(w, w.h_ctl, w.h_tot, stats);
+    SkWork::Pend& pd = w.pend;
+    if (!pd.spec) return finish_stats(w, w.h_ctl, w.h_tot, stats);
+    // a speculative solve: done if the float32 rounds stopped short of the cap and the float64
+    // finish stopped within its first iterations; otherwise the caller resumes it
+    const int* c32 = w.h_ctl32;
+    if (!(c32[2] > 0 && c32[2] < w.spec.o.max_iter && w.h_ctl[2] > 0)) {
+        w.spec.need_resume = true;
+        return Status{};
+    }
+    for (int r = 0; r < pd.spec_slots; ++r)
+        for (int k = 0; k < kClasses; ++k) {
+            float ms = 0.f;
+            if (pd.n[k] && hipEventElapsedTime(&ms, w.kev[k][0][r], w.kev[k][1][r]) == hipSuccess) {
+                pd.ms[k] += ms;
+                pd.launches[k] += 1;
+            }
+        }
+    pd.spec_slots = 0;
+    pd.terms32 = 0.0;
+    for (int k = 0; k < kClasses; ++k) {
+        pd.terms[k] = pd.tpi[k] * c32[10];
+        pd.terms32 += pd.terms[k];
+    }
+    // the statistics and the finish's words from its own block, the float32 phase's fallback
+    // counters and bad-box flag from the rounds' block
+    int hctl[16];
+    std::copy(w.h_ctl, w.h_ctl + 16, hctl);
+    hctl[3] |= c32[3];
+    for (int k = 12; k < 16; ++k) hctl[k] = c32[k];
+    return finish_stats(w, hctl, w.h_tot, stats);
 }
 
 }  // namespace dd

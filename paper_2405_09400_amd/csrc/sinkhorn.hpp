@@ -1,6 +1,8 @@
 // Batched separable log-domain cell Sinkhorn on gfx950 (declarations).
 #pragma once
 
+#include <vector>
+
 #include "common.hpp"
 
 namespace dd {
@@ -37,6 +39,7 @@ struct SkWork {
     int32_t* cell_iters = nullptr;
     int32_t* iters64 = nullptr; // [cap] float64-finish iterations
     int* ctrl = nullptr;        // [16] device control words (queue, ticket, done, flags)
+    int* ctrl64 = nullptr;      // [16] control words of a speculative float64 finish
     double* dtot = nullptr;     // [8] device totals
     void* big = nullptr;        // scratch for Y boxes beyond the LDS tile (g, z in global memory)
     size_t big_bytes = 0;
@@ -70,6 +73,8 @@ struct SkWork {
     char* h_stage = nullptr;
     size_t h_stage_cap = 0;
     int* h_ctl = nullptr;       // [16] control words of the last solve
+    int* h_ctl32 = nullptr;     // [16] a speculative solve's float32-phase control words
+    int64_t waits = 0;          // host waits for the device so far (statistics)
     double* h_tot = nullptr;    // [8] its totals
     // what a solve with deferred statistics leaves for sk_finish
     struct Pend {
@@ -83,7 +88,25 @@ struct SkWork {
         int fchoice = -1, fkey[3] = {0, 0, 0};  // register-blocked path: the tuner's pick
         int wave_side = 0, big_entries = 0;     // and the class thresholds used
         double terms32 = 0.0;                   // LSE terms of the float32 phase
+        bool spec = false;                      // enqueued speculatively (see sk_solve)
+        int spec_slots = 0;                     // its float32 rounds' event slots
+        double tpi[3] = {0.0, 0.0, 0.0};        // and LSE terms per iteration per class
     } pend;
+    // A speculative solve (sk_solve with spec): what its resumption needs, if the rounds and
+    // float64 iterations enqueued without a host wait turn out not to be enough.
+    struct Spec {
+        bool need_resume = false;
+        SkBatch p, q64;
+        dd_sinkhorn_opts o{};
+        std::vector<int32_t> hd, ord;
+        std::vector<int64_t> cls64;  // the float64 finish's classes: mode, lo, hi, t0, t1, budget,
+                                     // threads
+        int wave_side = 0, big_entries = 0;
+        int first64 = 2;  // float64-finish iterations launched speculatively
+        int32_t* iters = nullptr;
+        double* errs = nullptr;
+        hipStream_t caller = nullptr;
+    } spec;
 };
 
 // Carve n elements from the no-allocation arena (256-byte aligned); DD_EINVAL when the arena
@@ -114,10 +137,19 @@ size_t sk_lds_bytes(int xside, int prec);
 // them back.  defer: leave the statistics in w (pinned) and return without waiting for the
 // solve; the caller synchronises its stream and then calls sk_finish, which also reports a
 // stop that missed the tolerance.  Not in no-allocation mode.
+//
+// spec (with defer, on the register-blocked path under the batch rule): enqueue the whole solve
+// without any host wait -- a fixed number of float32 rounds (the rounds after the stop exit
+// at once), a device gate, and the first float64 finish iterations (which exit at once when
+// the float32 phase has not stopped).  sk_finish then sets w.spec.need_resume when that was
+// not enough; sk_resume continues the solve exactly where it stands (the same iterations and
+// results as a solve without spec), after which the caller redoes whatever it enqueued
+// behind the solve and calls sk_finish again.
 Status sk_solve(const SkBatch& p, const dd_sinkhorn_opts& o, hipStream_t st, SkWork& w,
                 dd_batch_stats* stats, int32_t* cell_iters_out, double* cell_err_out,
-                const int32_t* host_dims = nullptr, bool defer = false);
+                const int32_t* host_dims = nullptr, bool defer = false, bool spec = false);
 Status sk_finish(SkWork& w, dd_batch_stats* stats);
+Status sk_resume(SkWork& w);
 
 // iters[c] = ctrl[2] (the batch rule's stop iteration) for every cell
 void launch_done_iters(int ncells, int32_t* iters, const int* ctrl, hipStream_t st);
