@@ -1331,7 +1331,7 @@ bool fast_eligible(const SkBatch& p, const std::vector<int32_t>& hd) {
 Status fast_solve(const SkBatch& p, const dd_sinkhorn_opts& o, hipStream_t st, SkWork& w,
                   const std::vector<int32_t>& hd, const std::vector<int32_t>& order,
                   int32_t* iters, double* errs, FastInfo* info, bool final_pass,
-                  int32_t* h_ord, FastClasses classes, int phase) {
+                  int32_t* h_ord, FastClasses classes, int phase, int spec_rounds) {
     Status S;
     const int n = p.ncells;
     const bool resume = phase == kFastResume;
@@ -1518,9 +1518,10 @@ Status fast_solve(const SkBatch& p, const dd_sinkhorn_opts& o, hipStream_t st, S
         for (int k = 0; k < kClasses; ++k) info->terms_per_it[k] = terms_per_it[k];
     int hctl[16] = {};
     if (phase == kFastSpec) {
-        // `reps` rounds with no host wait: the caller reads the control words after the whole
-        // half-iteration and resumes here if the rule had not stopped by then
-        for (int r = 0; r < reps; ++r) {
+        // `spec_rounds` (at most `reps`) rounds with no host wait: the caller reads the control
+        // words after the whole half-iteration and resumes here if the rule had not stopped
+        const int nspec = std::max(1, std::min(reps, spec_rounds));
+        for (int r = 0; r < nspec; ++r) {
             fork();
             launch(a, kBatch, true, r);
             join();
@@ -1528,7 +1529,7 @@ Status fast_solve(const SkBatch& p, const dd_sinkhorn_opts& o, hipStream_t st, S
         launch_done_iters(n, iters, w.ctrl, st);
         if (info) {
             info->final_done = false;
-            info->spec_slots = reps;
+            info->spec_slots = nspec;
         }
         DD_HIP(hipGetLastError(), S);
         return S;

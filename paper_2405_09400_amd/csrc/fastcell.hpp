@@ -68,10 +68,10 @@ Status fast_solve(const SkBatch& p, const dd_sinkhorn_opts& o, hipStream_t st, S
                   const std::vector<int32_t>& hd, const std::vector<int32_t>& ord,
                   int32_t* iters, double* errs, FastInfo* info, bool final_pass = true,
                   int32_t* h_ord = nullptr, FastClasses cls = FastClasses{},
-                  int phase = kFastAll);
+                  int phase = kFastAll, int spec_rounds = 4);
 // h_ord: pinned host room for n ints (the order is uploaded from there without waiting), or
 // NULL (no-allocation mode: uploaded from a temporary, then waited for).
-// phase kFastSpec (batch rule, not in no-allocation mode): enqueue four rounds and the
+// phase kFastSpec (batch rule, not in no-allocation mode): enqueue spec_rounds (at most four) rounds and the
 // per-cell counts of their stop iteration (0 if none) without a host wait, and return;
 // kFastResume (same arguments, after the caller has waited and copied w.ctrl to w.h_ctl32):
 // continue that solve from where the four rounds left it.

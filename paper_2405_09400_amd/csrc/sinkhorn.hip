@@ -1525,6 +1525,30 @@ bool spec_enabled() {
     return !(e && e[0] == '0');
 }
 
+// float32 rounds a speculative solve of a batch of n cells enqueues: one more than the last
+// such solve needed (from its iteration count: the first two rounds run 4 check_every
+// iterations each), between 2 and the kSpecRounds the bound assumes; 4 for an unseen size
+int spec_rounds_for(const SkWork& w, int n) {
+    for (int k = 0; k < 4; ++k)
+        if (w.spec_n[k] == n) return w.spec_r[k];
+    return 4;
+}
+
+void spec_rounds_learn(SkWork& w, int n, int it32, int chunk, bool resumed) {
+    const int used = resumed ? 4 : it32 <= 4 * chunk ? 1 : it32 <= 8 * chunk ? 2 : 4;
+    const int r = std::min(4, std::max(2, used + 1));
+    int slot = 0;
+    for (int k = 0; k < 4; ++k)
+        if (w.spec_n[k] == n || w.spec_n[k] == 0) {
+            slot = k;
+            break;
+        } else if (k == 3) {
+            slot = (w.spec_next++) & 3;
+        }
+    w.spec_n[slot] = n;
+    w.spec_r[slot] = r;
+}
+
 // float64-finish iterations launched speculatively: 2, or DD_SPEC_FINISH in [0, 8] (0 makes
 // every speculative solve resume its finish: the tests' way to reach that path)
 int spec_finish_launches() {
@@ -1651,9 +1675,7 @@ Status sk_solve(const SkBatch& p, const dd_sinkhorn_opts& o, hipStream_t caller_
     // the general path's plan (not needed when the register-blocked path takes the batch), and
     // the float64 finish's
     const Plan P = fast ? Plan{} : plan_classes(hd, ord, p.ncells, AS, elem, small_budget, big_budget);
-    const Plan P64 = finish ? plan_classes(hd, ord, p.ncells, AS, sizeof(double), kBudgets[1],
-                                           kBudgets[1])
-                            : Plan{};
+    Plan P64;
     auto put = [&](int32_t*& dev_ord, int64_t*& dev_off, int& cap, const Plan& pl,
                    int32_t* h_o, int64_t* h_f) -> Status {
         Status E;
@@ -1692,27 +1714,45 @@ Status sk_solve(const SkBatch& p, const dd_sinkhorn_opts& o, hipStream_t caller_
     q.order = w.order;
     q.scr_off = w.scr_off;
     SkBatch q64 = p;
-    if (finish) {
-        S = put(w.order64, w.scr_off64, w.order64_cap, P64, h_ord64, h_off64);
-        if (S.code) return S;
-        q64.order = w.order64;
-        q64.scr_off = w.scr_off64;
-    }
-    const int64_t scr = std::max(P.scr, P64.scr);
-    if (arena) {
-        double* bigp = nullptr;
-        S = arena_take(w, bigp, (size_t)std::max<int64_t>(scr, 0) + 8);
-        if (S.code) return S;
-        w.big = bigp;
-        w.big_bytes = ((size_t)std::max<int64_t>(scr, 0) + 8) * sizeof(double);
-    } else if (scr > 0) {
-        const size_t need = (size_t)scr * sizeof(double) + 64;
-        if (need > w.big_bytes) {
-            w.mem.put(w.big);
-            w.big = nullptr;
-            DD_HIP(w.mem.get(&w.big, need), S);
-            w.big_bytes = need;
+    // the float64 finish's plan, its upload and the global scratch of both plans; a
+    // speculative solve does this after its float32 rounds are enqueued (the device is busy
+    // with them meanwhile)
+    auto plan_finish = [&]() -> Status {
+        Status E;
+        if (finish) {
+            P64 = plan_classes(hd, ord, p.ncells, AS, sizeof(double), kBudgets[1], kBudgets[1]);
+            E = put(w.order64, w.scr_off64, w.order64_cap, P64, h_ord64, h_off64);
+            if (E.code) return E;
+            q64.order = w.order64;
+            q64.scr_off = w.scr_off64;
         }
+        const int64_t scr = std::max(P.scr, P64.scr);
+        if (arena) {
+            double* bigp = nullptr;
+            E = arena_take(w, bigp, (size_t)std::max<int64_t>(scr, 0) + 8);
+            if (E.code) return E;
+            w.big = bigp;
+            w.big_bytes = ((size_t)std::max<int64_t>(scr, 0) + 8) * sizeof(double);
+        } else if (scr > 0) {
+            const size_t need = (size_t)scr * sizeof(double) + 64;
+            if (need > w.big_bytes) {
+                w.mem.put(w.big);
+                w.big = nullptr;
+                DD_HIP(w.mem.get(&w.big, need), E);
+                w.big_bytes = need;
+            }
+        }
+        return E;
+    };
+    const int spec_chunk = std::max(1, o.check_every > 0 ? o.check_every : 8);
+    const int spec_first64 = spec_finish_launches();
+    const bool use_spec = spec && defer && pinned && fast && finish &&
+                          o.stop_rule == DD_STOP_BATCH &&
+                          o.max_iter >= fast_spec_max_iters(spec_chunk) + spec_first64 + 2 &&
+                          spec_enabled();
+    if (!use_spec) {
+        S = plan_finish();
+        if (S.code) return S;
     }
     // without the pinned staging the copies read the plans' own vectors: wait for them
     if (!pinned) {
@@ -1726,16 +1766,13 @@ Status sk_solve(const SkBatch& p, const dd_sinkhorn_opts& o, hipStream_t caller_
     // the whole solve enqueued with no host wait (see sk_solve in the header); the float64
     // finish's first two iterations are then launched with the full max_iter as their limit,
     // which stops neither of them when the float32 phase has stopped at least two iterations
-    // short of the cap -- what the bound on the speculative rounds' iterations guarantees
-    const int spec_chunk = std::max(1, o.check_every > 0 ? o.check_every : 8);
-    const int spec_first64 = spec_finish_launches();
-    const bool use_spec = spec && defer && pinned && fast && finish &&
-                          o.stop_rule == DD_STOP_BATCH &&
-                          o.max_iter >= fast_spec_max_iters(spec_chunk) + spec_first64 + 2 &&
-                          spec_enabled();
+    // short of the cap -- what the bound on the speculative rounds' iterations guarantees.
+    // The rounds enqueued: one more than the last solve of a batch of this size needed (the
+    // rounds after the stop cost a launch each), at most four
+    const int spec_rounds = use_spec ? spec_rounds_for(w, p.ncells) : 0;
     if (fast)
         S = fast_solve(p, o, st, w, hd, ord, iters, errs, &fi, !finish, h_ordf, fcls,
-                       use_spec ? kFastSpec : kFastAll);
+                       use_spec ? kFastSpec : kFastAll, spec_rounds);
     else
         S = p.prec == DD_PREC_F32 ? run_solver<float>(q, P.classes, o, st, w, iters, errs, 0, &k32)
                                   : run_solver<double>(q, P.classes, o, st, w, iters, errs);
@@ -1752,6 +1789,8 @@ Status sk_solve(const SkBatch& p, const dd_sinkhorn_opts& o, hipStream_t caller_
     if (o.stop_rule == DD_STOP_BATCH) o64.max_iter = o.max_iter - k32 + (shared ? 1 : 0);
     const bool run64 = finish && o64.max_iter >= 1;
     if (use_spec) {
+        S = plan_finish();
+        if (S.code) return S;
         spec_gate_kernel<<<1, 64, 0, st>>>(w.ctrl, w.ctrl64, o.max_iter);
         S = run_solver<double>(q64, P64.classes, o64, st, w, w.iters64, errs, spec_first64,
                                nullptr, w.ctrl64, kRunSpec);
@@ -2003,10 +2042,15 @@ Status sk_finish(SkWork& w, dd_batch_stats* stats) {
     // a speculative solve: done if the float32 rounds stopped short of the cap and the float64
     // finish stopped within its first iterations; otherwise the caller resumes it
     const int* c32 = w.h_ctl32;
+    const int chunk = std::max(1, w.spec.o.check_every > 0 ? w.spec.o.check_every : 8);
     if (!(c32[2] > 0 && c32[2] < w.spec.o.max_iter && w.h_ctl[2] > 0)) {
+        // (a finish that needs more iterations says nothing about the rounds)
+        if (!(c32[2] > 0 && c32[2] < w.spec.o.max_iter))
+            spec_rounds_learn(w, pd.ncells, c32[10], chunk, true);
         w.spec.need_resume = true;
         return Status{};
     }
+    spec_rounds_learn(w, pd.ncells, c32[10], chunk, false);
     for (int r = 0; r < pd.spec_slots; ++r)
         for (int k = 0; k < kClasses; ++k) {
             float ms = 0.f;

@@ -75,6 +75,8 @@ struct SkWork {
     int* h_ctl = nullptr;       // [16] control words of the last solve
     int* h_ctl32 = nullptr;     // [16] a speculative solve's float32-phase control words
     int64_t waits = 0;          // host waits for the device so far (statistics)
+    // float32 rounds a speculative solve enqueues, by batch size (the last four sizes seen)
+    int spec_n[4] = {0, 0, 0, 0}, spec_r[4] = {0, 0, 0, 0}, spec_next = 0;
     double* h_tot = nullptr;    // [8] its totals
     // what a solve with deferred statistics leaves for sk_finish
     struct Pend {
