@@ -356,8 +356,18 @@ typedef struct {
  *   from the previous visit of this partition (alpha kept in energy units across
  *   eps changes), DD_INIT_ZERO starts from zero.
  *   stats (host) may be NULL.  Synchronises the context stream.
+ *   Host waits: in the steady state one, at the end.  The composite boxes come
+ *   from the end of the previous call (any other call that changes the state
+ *   drops them, and the next call reads them back); under the batch rule with
+ *   float32 terms and max_iter >= 4 * 32 * check_every + 4, the float32 rounds
+ *   and the first float64-finish iterations are enqueued without waiting and
+ *   continued after the wait if they were not enough (the same iterations and
+ *   results either way).  DD_SPEC=0 in the environment turns the speculative
+ *   enqueueing off; DD_SPEC_FINISH=n (0..8) sets the float64-finish iterations
+ *   enqueued ahead (default 2).
  * Errors: DD_EINVAL (partition, eps <= 0, opts), DD_ENOMEM (a box outgrew the
- * on-chip limit or memory), DD_ENUMERIC, DD_NOTCONV (warning).
+ * on-chip limit or memory), DD_ENUMERIC, DD_NOTCONV (warning), DD_EDEVICE (a
+ * kernel failed, or the predicted composite boxes differed from the state's).
  */
 dd_status domdec_iterate(dd_ctx* ctx, int32_t partition, double eps,
                          const dd_sinkhorn_opts* opts, dd_iter_stats* stats);
